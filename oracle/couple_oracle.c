@@ -1,0 +1,496 @@
+/*
+ * couple_oracle.c -- plain, slow, FP64 CPU oracle of the dual-grid coupling exchange.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or call
+ * this file; only the test-suite, the smoke check and the CPU-baseline leg of the
+ * benchmark do.  It shares no source, header, table or helper with the GPU path.
+ *
+ * Every function writes out the plain definition of one stage of the per-step
+ * exchange between Lagrangian particles, the coarse ("bulk") grid and the fine
+ * grid of the dual-grid multiscale CFD-DEM coupling (Sec. 2.1, Fig. 1):
+ *
+ *   bin          particle -> containing bulk cell, canonical (cell, id) order;
+ *                the connectivity that must be rebuilt every coupling step (Sec. 2.2)
+ *   deposit      volume-averaged solid fraction and momentum source on the bulk
+ *                grid (Sec. 1 unresolved coupling; porosity in Table 1 and Sec. 2.4;
+ *                momentum source F_fpi of Eq. UFP, Sec. 2.5)
+ *   restrict     fine -> bulk "fluid solution" transfer (Fig. 1, Sec. 2.1, 2.3)
+ *   interp       fluid value at a particle ("cell values or locally interpolated
+ *                values", Sec. 1)
+ *   drag         F = beta (u_f - u_p), Eq. DragLaw (Sec. 2.4), beta by the
+ *                Di Felice voidage correlation
+ *   prolong      bulk -> fine "particle related fields" transfer (Fig. 1)
+ *   advect       explicit Euler update of Eq. DEM_EQUATIONS with drag only
+ *
+ * All arithmetic is FP64, except where a floating-point comparison decides an
+ * integer (the containing-cell index): there the caller chooses the precision
+ * the kernel uses (prec32 = 1 evaluates the index in IEEE binary32).
+ *
+ * Layout: particle vectors are [n][3] (x,y,z); grid fields are [nz][ny][nx] with x
+ * fastest; vector grid fields are three such arrays back to back ([3][nz][ny][nx]).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_PI 3.14159265358979323846
+
+static int64_t lin3(int64_t i, int64_t j, int64_t k, const int n[3])
+{
+    return i + (int64_t)n[0] * (j + (int64_t)n[1] * k);
+}
+
+static int clampi(int64_t v, int n)
+{
+    if (v < 0) return 0;
+    if (v > n - 1) return n - 1;
+    return (int)v;
+}
+
+/* Position clamped into the closed box [0, L]; a NaN coordinate becomes 0
+ * (fmax returns the non-NaN operand).  Returns 1 if the input was outside. */
+static int clamp_pos(const double *p, const double box[3], double out[3])
+{
+    int outside = 0;
+    for (int a = 0; a < 3; ++a) {
+        double x = p[a];
+        if (!(x >= 0.0 && x <= box[a])) outside = 1;
+        out[a] = fmin(fmax(x, 0.0), box[a]);
+    }
+    return outside;
+}
+
+/* Same clamp in binary32 arithmetic (the box length rounded to float). */
+static int clamp_pos32(const double *p, const double box[3], double out[3])
+{
+    int outside = 0;
+    for (int a = 0; a < 3; ++a) {
+        float x = (float)p[a];
+        float L = (float)box[a];
+        if (!(x >= 0.0f && x <= L)) outside = 1;
+        out[a] = (double)fminf(fmaxf(x, 0.0f), L);
+    }
+    return outside;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Bin: containing bulk cell of each particle (connectivity, Sec. 2.2).        */
+/* i_a = floor(x_a * n_a / L_a), clamped to [0, n_a-1]; x = L falls in n-1.   */
+/* Linear key k = i_x + n_x (i_y + n_y i_z).  Returns the number of particles  */
+/* whose position was outside the box (or not finite).                        */
+/* ------------------------------------------------------------------------- */
+int64_t orc_bin(int64_t n, const double *pos, const double box[3], const int nb[3],
+                int prec32, int32_t *cell)
+{
+    int64_t outside = 0;
+    for (int64_t p = 0; p < n; ++p) {
+        double x[3];
+        int idx[3];
+        if (prec32) {
+            outside += clamp_pos32(pos + 3 * p, box, x);
+            for (int a = 0; a < 3; ++a) {
+                float s = (float)((double)nb[a] / box[a]);
+                float c = (float)x[a] * s;
+                idx[a] = clampi((int64_t)floorf(c), nb[a]);
+            }
+        } else {
+            outside += clamp_pos(pos + 3 * p, box, x);
+            for (int a = 0; a < 3; ++a) {
+                double s = (double)nb[a] / box[a];
+                idx[a] = clampi((int64_t)floor(x[a] * s), nb[a]);
+            }
+        }
+        cell[p] = (int32_t)lin3(idx[0], idx[1], idx[2], nb);
+    }
+    return outside;
+}
+
+/* Stable order of particle ids by cell (ties by ascending id), per-cell counts
+ * and the exclusive prefix sum of the counts ("start", length ncell+1).
+ * Written as a counting sort: count, scan, then place ids in ascending order. */
+void orc_sort(int64_t n, const int32_t *cell, int64_t ncell,
+              int32_t *perm, int32_t *count, int32_t *start)
+{
+    memset(count, 0, sizeof(int32_t) * (size_t)ncell);
+    for (int64_t p = 0; p < n; ++p) count[cell[p]] += 1;
+    start[0] = 0;
+    for (int64_t c = 0; c < ncell; ++c) start[c + 1] = start[c] + count[c];
+    int32_t *next = (int32_t *)malloc(sizeof(int32_t) * (size_t)(ncell > 0 ? ncell : 1));
+    for (int64_t c = 0; c < ncell; ++c) next[c] = start[c];
+    for (int64_t p = 0; p < n; ++p) perm[next[cell[p]]++] = (int32_t)p;
+    free(next);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Particle -> bulk-cell weights.                                             */
+/*   NGP: weight 1 on the containing cell.                                    */
+/*   CIC: trilinear weights to the 8 bulk cell centres around the particle;   */
+/*        g = x n / L - 1/2, j = floor(g), t = g - j; corner delta in {0,1}^3 */
+/*        has weight prod_a (delta_a ? t_a : 1 - t_a) on cell clamp(j+delta). */
+/*        Corners folded onto the same cell by the clamp have their weights   */
+/*        added, so the weights always sum to one.                            */
+/* Returns the number of distinct cells written to cells[]/w[].               */
+/* ------------------------------------------------------------------------- */
+static int weights(const double x[3], const double box[3], const int nb[3], int cic,
+                   int prec32, int64_t cells[8], double w[8])
+{
+    if (!cic) {
+        int idx[3];
+        for (int a = 0; a < 3; ++a) {
+            if (prec32) {
+                float s = (float)((double)nb[a] / box[a]);
+                idx[a] = clampi((int64_t)floorf((float)x[a] * s), nb[a]);
+            } else {
+                idx[a] = clampi((int64_t)floor(x[a] * ((double)nb[a] / box[a])), nb[a]);
+            }
+        }
+        cells[0] = lin3(idx[0], idx[1], idx[2], nb);
+        w[0] = 1.0;
+        return 1;
+    }
+    int64_t j[3];
+    double t[3];
+    for (int a = 0; a < 3; ++a) {
+        double g = x[a] * ((double)nb[a] / box[a]) - 0.5;
+        j[a] = (int64_t)floor(g);
+        t[a] = g - (double)j[a];
+    }
+    int m = 0;
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+                int d[3] = {dx, dy, dz};
+                double wt = 1.0;
+                int idx[3];
+                for (int a = 0; a < 3; ++a) {
+                    wt *= d[a] ? t[a] : 1.0 - t[a];
+                    idx[a] = clampi(j[a] + d[a], nb[a]);
+                }
+                int64_t c = lin3(idx[0], idx[1], idx[2], nb);
+                int found = -1;
+                for (int q = 0; q < m; ++q)
+                    if (cells[q] == c) found = q;
+                if (found >= 0) {
+                    w[found] += wt;
+                } else {
+                    cells[m] = c;
+                    w[m] = wt;
+                    ++m;
+                }
+            }
+    return m;
+}
+
+/* Exported for tests: the (cell, weight) list of one particle. */
+int orc_weights(const double *pos, const double box[3], const int nb[3], int cic,
+                int prec32, int64_t *cells, double *w)
+{
+    double x[3];
+    if (prec32) clamp_pos32(pos, box, x); else clamp_pos(pos, box, x);
+    return weights(x, box, nb, cic, prec32, cells, w);
+}
+
+static double particle_volume(double d) { return ORC_PI * d * d * d / 6.0; }
+
+/* ------------------------------------------------------------------------- */
+/* Solid volume fraction of each bulk cell (porosity eps = 1 - phi):          */
+/*   phi_c = sum_p w_pc V_p / V_b,  V_p = pi d^3 / 6, V_b = hx hy hz,          */
+/* accumulated particle by particle in the canonical (cell, id) order.       */
+/* ------------------------------------------------------------------------- */
+void orc_deposit_volume(int64_t n, const double *pos, const double *diam, const int32_t *perm,
+                        const double box[3], const int nb[3], int cic, int prec32, double *phi)
+{
+    int64_t nc = (int64_t)nb[0] * nb[1] * nb[2];
+    double vb = (box[0] / nb[0]) * (box[1] / nb[1]) * (box[2] / nb[2]);
+    for (int64_t c = 0; c < nc; ++c) phi[c] = 0.0;
+    for (int64_t q = 0; q < n; ++q) {
+        int64_t p = perm[q];
+        double x[3];
+        if (prec32) clamp_pos32(pos + 3 * p, box, x); else clamp_pos(pos + 3 * p, box, x);
+        int64_t cells[8];
+        double w[8];
+        int m = weights(x, box, nb, cic, prec32, cells, w);
+        double vp = particle_volume(diam[p]);
+        for (int k = 0; k < m; ++k) phi[cells[k]] += w[k] * vp / vb;
+    }
+}
+
+/* Momentum source on the bulk grid, equal and opposite to the particle drag:
+ *   F_fpi,c = -(1/V_b) sum_p w_pc F_p   (three components, [3][ncell]). */
+void orc_deposit_force(int64_t n, const double *pos, const double *force, const int32_t *perm,
+                       const double box[3], const int nb[3], int cic, int prec32, double *fc)
+{
+    int64_t nc = (int64_t)nb[0] * nb[1] * nb[2];
+    double vb = (box[0] / nb[0]) * (box[1] / nb[1]) * (box[2] / nb[2]);
+    for (int64_t c = 0; c < 3 * nc; ++c) fc[c] = 0.0;
+    for (int64_t q = 0; q < n; ++q) {
+        int64_t p = perm[q];
+        double x[3];
+        if (prec32) clamp_pos32(pos + 3 * p, box, x); else clamp_pos(pos + 3 * p, box, x);
+        int64_t cells[8];
+        double w[8];
+        int m = weights(x, box, nb, cic, prec32, cells, w);
+        for (int k = 0; k < m; ++k)
+            for (int a = 0; a < 3; ++a) fc[a * nc + cells[k]] -= w[k] * force[3 * p + a] / vb;
+    }
+}
+
+/* Void fraction seen by each particle: eps_p = sum_c w_pc (1 - phi_c), with the
+ * same weights as the deposition (the transpose of the deposition operator). */
+void orc_gather_eps(int64_t n, const double *pos, const double *phi, const double box[3],
+                    const int nb[3], int cic, int prec32, double *eps_p)
+{
+    for (int64_t p = 0; p < n; ++p) {
+        double x[3];
+        if (prec32) clamp_pos32(pos + 3 * p, box, x); else clamp_pos(pos + 3 * p, box, x);
+        int64_t cells[8];
+        double w[8];
+        int m = weights(x, box, nb, cic, prec32, cells, w);
+        double e = 0.0;
+        for (int k = 0; k < m; ++k) e += w[k] * (1.0 - phi[cells[k]]);
+        eps_p[p] = e;
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Restriction fine -> bulk: average of the r^3 fine children of each bulk    */
+/* cell (conservative volume average), children visited in raster order.     */
+/* ------------------------------------------------------------------------- */
+void orc_restrict(const double *qf, const int nb[3], int r, double *qb)
+{
+    int nf[3] = {nb[0] * r, nb[1] * r, nb[2] * r};
+    double inv = 1.0 / ((double)r * r * r);
+    for (int k = 0; k < nb[2]; ++k)
+        for (int j = 0; j < nb[1]; ++j)
+            for (int i = 0; i < nb[0]; ++i) {
+                double s = 0.0;
+                for (int c = 0; c < r; ++c)
+                    for (int b = 0; b < r; ++b)
+                        for (int a = 0; a < r; ++a)
+                            s += qf[lin3(i * r + a, j * r + b, k * r + c, nf)];
+                qb[lin3(i, j, k, nb)] = s * inv;
+            }
+}
+
+/* Pressure gradient on the bulk grid: central differences
+ * (P[c+e] - P[c-e]) / (2h), one-sided (P[c+e]-P[c])/h or (P[c]-P[c-e])/h at the
+ * two walls, zero along an axis with a single cell. Output [3][ncell]. */
+void orc_gradient(const double *P, const int nb[3], const double box[3], double *G)
+{
+    int64_t nc = (int64_t)nb[0] * nb[1] * nb[2];
+    for (int k = 0; k < nb[2]; ++k)
+        for (int j = 0; j < nb[1]; ++j)
+            for (int i = 0; i < nb[0]; ++i) {
+                int idx[3] = {i, j, k};
+                int64_t c = lin3(i, j, k, nb);
+                for (int a = 0; a < 3; ++a) {
+                    double h = box[a] / nb[a];
+                    int lo[3] = {i, j, k}, hi[3] = {i, j, k};
+                    double g;
+                    if (nb[a] == 1) {
+                        g = 0.0;
+                    } else if (idx[a] == 0) {
+                        hi[a] = 1;
+                        g = (P[lin3(hi[0], hi[1], hi[2], nb)] - P[c]) / h;
+                    } else if (idx[a] == nb[a] - 1) {
+                        lo[a] = nb[a] - 2;
+                        g = (P[c] - P[lin3(lo[0], lo[1], lo[2], nb)]) / h;
+                    } else {
+                        lo[a] = idx[a] - 1;
+                        hi[a] = idx[a] + 1;
+                        g = (P[lin3(hi[0], hi[1], hi[2], nb)] - P[lin3(lo[0], lo[1], lo[2], nb)]) / (2.0 * h);
+                    }
+                    G[a * nc + c] = g;
+                }
+            }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Trilinear interpolation of a cell-centred field q ([n2][n1][n0] over the   */
+/* box) at points; node indices outside the grid are clamped (zero gradient   */
+/* at the walls).  Used for the fine-grid lookup and for the bulk-grid lookup. */
+/* ------------------------------------------------------------------------- */
+static double trilinear(const double *q, const int n[3], const double box[3], const double x[3])
+{
+    int64_t j[3];
+    double t[3];
+    for (int a = 0; a < 3; ++a) {
+        double g = x[a] * ((double)n[a] / box[a]) - 0.5;
+        j[a] = (int64_t)floor(g);
+        t[a] = g - (double)j[a];
+    }
+    double s = 0.0;
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+                int d[3] = {dx, dy, dz};
+                double wt = 1.0;
+                int idx[3];
+                for (int a = 0; a < 3; ++a) {
+                    wt *= d[a] ? t[a] : 1.0 - t[a];
+                    idx[a] = clampi(j[a] + d[a], n[a]);
+                }
+                s += wt * q[lin3(idx[0], idx[1], idx[2], n)];
+            }
+    return s;
+}
+
+void orc_interp(const double *q, const int n[3], const double box[3], int64_t npts,
+                const double *pos, int prec32, double *out)
+{
+    for (int64_t p = 0; p < npts; ++p) {
+        double x[3];
+        if (prec32) clamp_pos32(pos + 3 * p, box, x); else clamp_pos(pos + 3 * p, box, x);
+        out[p] = trilinear(q, n, box, x);
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Drag, Eq. DragLaw: F = beta (u_f - u_p).  beta after Di Felice:            */
+/*   u_r = u_f - u_p, eps* = max(eps_p, eps_min),                             */
+/*   Re = rho_f eps* d |u_r| / mu_f,  C_D = (0.63 + 4.8 / sqrt(Re))^2,         */
+/*   chi = 3.7 - 0.65 exp(-(1.5 - log10 Re)^2 / 2),                           */
+/*   beta = 1/2 C_D rho_f (pi d^2 / 4) eps*^(2 - chi) |u_r|.                  */
+/* At |u_r| = 0 the force is zero and beta takes its limit                    */
+/*   beta_0 = 1/2 rho_f (pi d^2/4) eps*^(2-3.7) * 4.8^2 mu_f / (rho_f eps* d). */
+/* Returns the number of particles whose void fraction was raised to eps_min.  */
+/* ------------------------------------------------------------------------- */
+int64_t orc_drag(int64_t n, const double *uf, const double *up, const double *diam,
+                 const double *eps_p, double rho_f, double mu_f, double eps_min,
+                 double *force, double *beta)
+{
+    int64_t clamped = 0;
+    for (int64_t p = 0; p < n; ++p) {
+        double ur[3], mag2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            ur[a] = uf[3 * p + a] - up[3 * p + a];
+            mag2 += ur[a] * ur[a];
+        }
+        double mag = sqrt(mag2);
+        double e = eps_p[p];
+        if (e < eps_min) { e = eps_min; ++clamped; }
+        double d = diam[p];
+        double area = ORC_PI * d * d / 4.0;
+        double b;
+        if (mag > 0.0) {
+            double re = rho_f * e * d * mag / mu_f;
+            double cd = 0.63 + 4.8 / sqrt(re);
+            cd = cd * cd;
+            double l = 1.5 - log10(re);
+            double chi = 3.7 - 0.65 * exp(-l * l / 2.0);
+            b = 0.5 * cd * rho_f * area * pow(e, 2.0 - chi) * mag;
+        } else {
+            b = 0.5 * rho_f * area * pow(e, 2.0 - 3.7) * 4.8 * 4.8 * mu_f / (rho_f * e * d);
+        }
+        if (beta) beta[p] = b;
+        for (int a = 0; a < 3; ++a) force[3 * p + a] = b * ur[a];
+    }
+    return clamped;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Prolongation bulk -> fine (conservative trilinear).                        */
+/*   T_f = trilinear interpolation of the bulk field B at the fine centre x_f  */
+/*         (bulk cell-centred nodes, clamped);                                 */
+/*   D_c = B_c - (1/r^3) sum_{f in c} T_f  (defect of the parent cell c);       */
+/*   P(B)_f = T_f + D_c.                                                        */
+/* Restricting P(B) gives back B exactly, and sum_f P(B)_f V_f = sum_c B_c V_b. */
+/* ------------------------------------------------------------------------- */
+static double fine_trilinear(const double *B, const int nb[3], int r, int64_t fi, int64_t fj, int64_t fk)
+{
+    /* fine centre in bulk-index coordinates: g = (f + 1/2)/r - 1/2 */
+    int64_t f[3] = {fi, fj, fk};
+    double box1[3] = {(double)nb[0], (double)nb[1], (double)nb[2]};
+    double x[3];
+    for (int a = 0; a < 3; ++a) x[a] = ((double)f[a] + 0.5) / (double)r;
+    return trilinear(B, nb, box1, x);
+}
+
+static double defect(const double *B, const int nb[3], int r, int i, int j, int k)
+{
+    double s = 0.0;
+    for (int c = 0; c < r; ++c)
+        for (int b = 0; b < r; ++b)
+            for (int a = 0; a < r; ++a)
+                s += fine_trilinear(B, nb, r, (int64_t)i * r + a, (int64_t)j * r + b, (int64_t)k * r + c);
+    return B[lin3(i, j, k, nb)] - s / ((double)r * r * r);
+}
+
+void orc_prolong(const double *B, const int nb[3], int r, int conservative, double *out)
+{
+    int nf[3] = {nb[0] * r, nb[1] * r, nb[2] * r};
+    for (int k = 0; k < nb[2]; ++k)
+        for (int j = 0; j < nb[1]; ++j)
+            for (int i = 0; i < nb[0]; ++i) {
+                double dc = conservative ? defect(B, nb, r, i, j, k) : 0.0;
+                for (int c = 0; c < r; ++c)
+                    for (int b = 0; b < r; ++b)
+                        for (int a = 0; a < r; ++a) {
+                            int64_t fi = (int64_t)i * r + a, fj = (int64_t)j * r + b, fk = (int64_t)k * r + c;
+                            out[lin3(fi, fj, fk, nf)] = fine_trilinear(B, nb, r, fi, fj, fk) + dc;
+                        }
+            }
+}
+
+/* Prolongation at selected flat fine indices only (for sampled comparisons). */
+void orc_prolong_at(const double *B, const int nb[3], int r, int conservative,
+                    int64_t m, const int64_t *fidx, double *out)
+{
+    int nf[3] = {nb[0] * r, nb[1] * r, nb[2] * r};
+    for (int64_t q = 0; q < m; ++q) {
+        int64_t f = fidx[q];
+        int64_t fi = f % nf[0];
+        int64_t fj = (f / nf[0]) % nf[1];
+        int64_t fk = f / ((int64_t)nf[0] * nf[1]);
+        double dc = conservative ? defect(B, nb, r, (int)(fi / r), (int)(fj / r), (int)(fk / r)) : 0.0;
+        out[q] = fine_trilinear(B, nb, r, fi, fj, fk) + dc;
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Explicit Euler step of Eq. DEM_EQUATIONS with the drag as the only force:   */
+/*   x <- x + dt u,  u <- u + dt F / m,  m = rho_p pi d^3 / 6,                */
+/* from the clamped old position; a coordinate that leaves [0, L] is          */
+/* mirrored back (x -> -x, or x -> 2L - x) and that velocity component flips.  */
+/* With prec32 the position/velocity updates are evaluated in binary32 as     */
+/* fused multiply-adds (each result rounded once), the velocity increment      */
+/* dt F / m being formed in FP64 and rounded to binary32 first.               */
+/* ------------------------------------------------------------------------- */
+void orc_advect(int64_t n, double *pos, double *vel, const double *diam, const double *force,
+                double rho_p, double dt, const double box[3], int prec32)
+{
+    for (int64_t p = 0; p < n; ++p) {
+        double x[3];
+        if (prec32) clamp_pos32(pos + 3 * p, box, x); else clamp_pos(pos + 3 * p, box, x);
+        double m = rho_p * particle_volume(diam[p]);
+        for (int a = 0; a < 3; ++a) {
+            double u = vel[3 * p + a];
+            double xn, un;
+            if (prec32) {
+                float acc = (float)(force[3 * p + a] / m);
+                xn = (double)fmaf((float)dt, (float)u, (float)x[a]);
+                un = (double)fmaf((float)dt, acc, (float)u);
+                float L = (float)box[a];
+                if (xn < 0.0) { xn = (double)(-(float)xn); un = -un; }
+                else if (xn > (double)L) { xn = (double)(2.0f * L - (float)xn); un = -un; }
+                xn = (double)fminf(fmaxf((float)xn, 0.0f), L);
+            } else {
+                xn = x[a] + dt * u;
+                un = u + dt * force[3 * p + a] / m;
+                double L = box[a];
+                if (xn < 0.0) { xn = -xn; un = -un; }
+                else if (xn > L) { xn = 2.0 * L - xn; un = -un; }
+                xn = fmin(fmax(xn, 0.0), L);
+            }
+            pos[3 * p + a] = xn;
+            vel[3 * p + a] = un;
+        }
+    }
+}
+
+/* Particle volumes V_p = pi d^3 / 6 (for the conservation diagnostics). */
+void orc_particle_volumes(int64_t n, const double *diam, double *vp)
+{
+    for (int64_t p = 0; p < n; ++p) vp[p] = particle_volume(diam[p]);
+}

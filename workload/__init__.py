@@ -1,0 +1,315 @@
+"""Seeded synthetic inputs for the particle / bulk-grid / fine-grid coupling exchange.
+
+This module only *draws* inputs: particle positions, diameters and velocities, and
+the fine-grid fluid velocity and pressure sampled at fine cell centres.  It holds
+none of the coupling arithmetic (binning, deposition, restriction, interpolation,
+drag, prolongation); both the FP64 oracle and the GPU path receive the arrays it
+returns and nothing else.
+
+Workloads (the paper's own cases need solver runs and case files that are not
+available; these synthetic stand-ins keep their shape, see Sec. 3.3 for the
+10-million-particle layered bed that the largest one imitates):
+
+* ``cube8_ngp_fp64``  unit cube, bulk 8^3, fine 32^3, 10,000 uniform spheres,
+  log-normal diameters, Taylor-Green fluid of amplitude 1, FP64, containing-cell
+  deposition.
+* ``cube64_cic``      unit cube, bulk 64^3, fine 256^3, 2,000,000 uniform spheres,
+  same distributions, cloud-in-cell deposition, 100 explicit-Euler steps of 1e-4.
+* ``bed128_cic``      box 1x1x2, bulk 128x128x256, fine 512x512x1024, 10,000,000
+  spheres: 7,000,000 on a jittered lattice in the bottom quarter (solid fraction
+  ~0.6), 3,000,000 uniform above; bimodal diameters; upflow 0.5 plus a Taylor-Green
+  perturbation of amplitude 0.1.
+* ``bed128_sub2m``    the same grids and fluid with the particles whose id is a
+  multiple of 5 (2,000,000), for the precision study.
+
+Random draws use ``numpy.random.default_rng(seed)`` (PCG64) in the fixed order
+positions, diameters (through class labels for the bed), velocities.  Positions are drawn in FP64 and
+rounded once to the working precision.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# ---------------------------------------------------------------------------
+# Grid description
+# ---------------------------------------------------------------------------
+
+
+@dataclass(frozen=True)
+class Grid:
+    """Uniform, nested bulk/fine grid pair.
+
+    ``box`` is (Lx, Ly, Lz); ``nb`` is bulk cells per axis (x, y, z); the fine grid
+    has ``ratio`` fine cells per bulk cell along every axis.  Arrays are stored
+    z-major, x fastest: a field of the fine grid has shape (nfz, nfy, nfx).
+    """
+
+    box: tuple
+    nb: tuple
+    ratio: int
+
+    @property
+    def nf(self):
+        return tuple(n * self.ratio for n in self.nb)
+
+    @property
+    def n_bulk(self):
+        return self.nb[0] * self.nb[1] * self.nb[2]
+
+    @property
+    def n_fine(self):
+        nf = self.nf
+        return nf[0] * nf[1] * nf[2]
+
+    def fine_centres_1d(self, axis):
+        """Fine cell-centre coordinates along ``axis`` (FP64)."""
+        n = self.nf[axis]
+        h = self.box[axis] / n
+        return (np.arange(n, dtype=np.float64) + 0.5) * h
+
+
+@dataclass
+class Workload:
+    name: str
+    grid: Grid
+    n_particles: int
+    precision: str          # "fp64" | "fp32"
+    deposit: str            # "ngp" | "cic"
+    seed: int
+    particles: str          # "uniform" | "bed"
+    fluid: str              # "tg1" | "upflow"
+    steps: int = 1
+    dt: float = 0.0
+    advect: bool = False
+    rho_f: float = 1000.0
+    mu_f: float = 1.0e-3
+    rho_p: float = 2500.0
+    eps_min: float = 0.3
+    bed_diameters: tuple = (0.002630, 0.005260)
+    subsample_stride: int = 1
+    notes: str = ""
+    extra: dict = field(default_factory=dict)
+
+
+WORKLOADS = {
+    "cube8_ngp_fp64": Workload(
+        name="cube8_ngp_fp64", grid=Grid((1.0, 1.0, 1.0), (8, 8, 8), 4),
+        n_particles=10_000, precision="fp64", deposit="ngp", seed=0,
+        particles="uniform", fluid="tg1"),
+    "cube64_cic": Workload(
+        name="cube64_cic", grid=Grid((1.0, 1.0, 1.0), (64, 64, 64), 4),
+        n_particles=2_000_000, precision="fp32", deposit="cic", seed=1,
+        particles="uniform", fluid="tg1", steps=100, dt=1.0e-4, advect=True),
+    "bed128_cic": Workload(
+        name="bed128_cic", grid=Grid((1.0, 1.0, 2.0), (128, 128, 256), 4),
+        n_particles=10_000_000, precision="fp32", deposit="cic", seed=2,
+        particles="bed", fluid="upflow"),
+    "bed128_sub2m": Workload(
+        name="bed128_sub2m", grid=Grid((1.0, 1.0, 2.0), (128, 128, 256), 4),
+        n_particles=10_000_000, precision="fp32", deposit="cic", seed=2,
+        particles="bed", fluid="upflow", subsample_stride=5),
+}
+
+# ---------------------------------------------------------------------------
+# Particles
+# ---------------------------------------------------------------------------
+
+LOGNORMAL_MEAN = 0.02
+LOGNORMAL_SIGMA = 0.2
+LOGNORMAL_CLIP = (0.01, 0.04)
+VELOCITY_SIGMA = 0.1
+
+
+def lognormal_diameters(rng, n):
+    """d = clip(exp(mu + sigma Z), 0.01, 0.04) with mu chosen so that E[d] = 0.02."""
+    mu = math.log(LOGNORMAL_MEAN) - 0.5 * LOGNORMAL_SIGMA ** 2
+    z = rng.standard_normal(n)
+    return np.clip(np.exp(mu + LOGNORMAL_SIGMA * z), *LOGNORMAL_CLIP)
+
+
+def uniform_particles(rng, n, box):
+    """Positions U[0, L) per axis, log-normal diameters, N(0, 0.1^2) velocities."""
+    pos = rng.random((n, 3)) * np.asarray(box, dtype=np.float64)
+    d = lognormal_diameters(rng, n)
+    vel = rng.normal(0.0, VELOCITY_SIGMA, size=(n, 3))
+    return pos, d, vel
+
+
+BED_LATTICE = (242, 242, 120)      # sites along x, y, z in the bottom quarter
+BED_TOP_Z = 0.5
+BED_PACKED = 7_000_000
+BED_LOOSE = 3_000_000
+
+
+def bed_particles(rng, box, diameters):
+    """Layered packed bed: jittered lattice in z < 0.5, uniform loose particles above.
+
+    The lattice has 242 x 242 x 120 sites with spacing (Lx/242, Ly/242, 0.5/120);
+    each site is jittered uniformly by +-0.25 spacing per axis and a seeded random
+    subset of 7,000,000 sites is kept (in the random order the draw returns).  The
+    remaining 3,000,000 particles are uniform in [0,Lx) x [0,Ly) x [0.5, Lz).
+    Diameters are bimodal, exactly half of each class, assigned by a seeded
+    permutation.
+    """
+    nx, ny, nz = BED_LATTICE
+    sp = np.array([box[0] / nx, box[1] / ny, BED_TOP_Z / nz])
+    nsite = nx * ny * nz
+    # positions: lattice subset, jitter, loose particles
+    pick = rng.permutation(nsite)[:BED_PACKED]
+    iz, rem = np.divmod(pick, nx * ny)
+    iy, ix = np.divmod(rem, nx)
+    lat = np.stack([ix, iy, iz], axis=1).astype(np.float64) + 0.5
+    jitter = rng.uniform(-0.25, 0.25, size=(BED_PACKED, 3))
+    packed = (lat + jitter) * sp
+    lo = np.array([0.0, 0.0, BED_TOP_Z])
+    ext = np.array([box[0], box[1], box[2] - BED_TOP_Z])
+    loose = lo + rng.random((BED_LOOSE, 3)) * ext
+    pos = np.concatenate([packed, loose], axis=0)
+    n = pos.shape[0]
+    cls = rng.permutation(n) < (n // 2)
+    d = np.where(cls, diameters[1], diameters[0]).astype(np.float64)
+    vel = rng.normal(0.0, VELOCITY_SIGMA, size=(n, 3))
+    return pos, d, vel
+
+
+def particles(w: Workload, seed=None, n=None):
+    """Draw the particle set of workload ``w``.
+
+    Returns (pos [n,3], diam [n], vel [n,3]) as float32 (fp32 workloads) or float64.
+    ``n`` overrides the particle count of uniform workloads (small test cases).
+    """
+    rng = np.random.default_rng(w.seed if seed is None else seed)
+    if w.particles == "uniform":
+        pos, d, vel = uniform_particles(rng, w.n_particles if n is None else n, w.grid.box)
+    elif w.particles == "bed":
+        pos, d, vel = bed_particles(rng, w.grid.box, w.bed_diameters)
+    else:
+        raise ValueError(w.particles)
+    if w.subsample_stride > 1:
+        sel = slice(0, None, w.subsample_stride)
+        pos, d, vel = pos[sel], d[sel], vel[sel]
+    dt = np.float64 if w.precision == "fp64" else np.float32
+    return (np.ascontiguousarray(pos.astype(dt)), np.ascontiguousarray(d.astype(dt)),
+            np.ascontiguousarray(vel.astype(dt)))
+
+
+# ---------------------------------------------------------------------------
+# Fluid on the fine grid (point values at fine cell centres)
+# ---------------------------------------------------------------------------
+
+TG_K = 2.0 * math.pi
+
+
+def _tables(grid: Grid, xp):
+    """1-D FP64 tables of the Taylor-Green factors on fine cell centres."""
+    xs = [grid.fine_centres_1d(a) for a in range(3)]
+    t = {}
+    for a, name in enumerate("xyz"):
+        v = TG_K * xs[a]
+        t["s" + name] = np.sin(v)
+        t["c" + name] = np.cos(v)
+        t["c2" + name] = np.cos(2.0 * v)
+    if xp is not np:
+        t = {k: xp.as_tensor(v) for k, v in t.items()}
+    return t
+
+
+def _fields(grid: Grid, fluid: str, rho_f: float, t, sl=None):
+    """Evaluate (u, v, w, p) from the 1-D tables with fixed multiplication order.
+
+    ``t`` holds numpy arrays or torch tensors; the expressions below are evaluated
+    identically by either library (IEEE FP64 products in the same order), so a
+    field generated on the host and on the device is bitwise the same.
+    """
+    if fluid == "tg1":
+        amp, w0 = 1.0, 0.0
+    elif fluid == "upflow":
+        amp, w0 = 0.1, 0.5
+    else:
+        raise ValueError(fluid)
+    sx, cx, c2x = t["sx"][None, None, :], t["cx"][None, None, :], t["c2x"][None, None, :]
+    sy, cy, c2y = t["sy"][None, :, None], t["cy"][None, :, None], t["c2y"][None, :, None]
+    sz, cz, c2z = t["sz"][:, None, None], t["cz"][:, None, None], t["c2z"][:, None, None]
+    if sl is not None:  # restrict the z extent (streaming generation)
+        sz, cz, c2z = sz[sl], cz[sl], c2z[sl]
+    u = ((amp * sx) * cy) * cz
+    v = ((-amp * cx) * sy) * cz
+    pc = rho_f * amp * amp / 16.0
+    p = ((c2x + c2y) * (c2z + 2.0)) * pc
+    w = u * 0.0 + w0
+    return u, v, w, p
+
+
+def fine_fields(w: Workload, dtype=None):
+    """Host (numpy) fine fields u, v, w, p, each (nfz, nfy, nfx), C-contiguous."""
+    dt = dtype or (np.float64 if w.precision == "fp64" else np.float32)
+    t = _tables(w.grid, np)
+    out = []
+    for f in _fields(w.grid, w.fluid, w.rho_f, t):
+        out.append(np.ascontiguousarray(np.broadcast_to(f, (w.grid.nf[2], w.grid.nf[1], w.grid.nf[0])).astype(dt)))
+    return tuple(out)
+
+
+def fine_fields_torch(w: Workload, device, dtype=None):
+    """The same fields built on a torch device (bitwise equal to :func:`fine_fields`)."""
+    import torch
+    dt = dtype or (torch.float64 if w.precision == "fp64" else torch.float32)
+    t = _tables(w.grid, np)
+    t = {k: torch.from_numpy(v).to(device) for k, v in t.items()}
+    nf = w.grid.nf
+    out = []
+    for f in _fields(w.grid, w.fluid, w.rho_f, t):
+        out.append(f.expand(nf[2], nf[1], nf[0]).to(dt).contiguous())
+    return tuple(out)
+
+
+def fine_values_at(w: Workload, fidx, dtype=None):
+    """Fine-field values (u, v, w, p) at flat fine indices ``fidx`` (host, numpy).
+
+    Equal, element by element, to indexing the arrays of :func:`fine_fields`.
+    """
+    dt = dtype or (np.float64 if w.precision == "fp64" else np.float32)
+    nf = w.grid.nf
+    fidx = np.asarray(fidx, dtype=np.int64)
+    iz, rem = np.divmod(fidx, nf[0] * nf[1])
+    iy, ix = np.divmod(rem, nf[0])
+    t = _tables(w.grid, np)
+    tt = {}
+    for k, v in t.items():
+        ax = k[-1]
+        idx = {"x": ix, "y": iy, "z": iz}[ax]
+        tt[k] = v[idx]
+    # evaluate the same expressions on 1-D gathered tables: index [None,None,:] etc.
+    # would broadcast; use a flat evaluation with identical operation order instead.
+    if w.fluid == "tg1":
+        amp, w0 = 1.0, 0.0
+    else:
+        amp, w0 = 0.1, 0.5
+    u = ((amp * tt["sx"]) * tt["cy"]) * tt["cz"]
+    v = ((-amp * tt["cx"]) * tt["sy"]) * tt["cz"]
+    pc = w.rho_f * amp * amp / 16.0
+    p = ((tt["c2x"] + tt["c2y"]) * (tt["c2z"] + 2.0)) * pc
+    ww = u * 0.0 + w0
+    return tuple(a.astype(dt) for a in (u, v, ww, p))
+
+
+def fluid_analytic(w: Workload, x, y, z):
+    """The continuous fluid fields (FP64) at arbitrary points: for error bounds."""
+    amp, w0 = (1.0, 0.0) if w.fluid == "tg1" else (0.1, 0.5)
+    k = TG_K
+    u = amp * np.sin(k * x) * np.cos(k * y) * np.cos(k * z)
+    v = -amp * np.cos(k * x) * np.sin(k * y) * np.cos(k * z)
+    ww = np.zeros_like(u) + w0
+    p = w.rho_f * amp * amp / 16.0 * (np.cos(2 * k * x) + np.cos(2 * k * y)) * (np.cos(2 * k * z) + 2.0)
+    return u, v, ww, p
+
+
+def small_workload(nb=(4, 3, 5), ratio=4, box=(1.0, 0.75, 1.25), n=200, seed=7,
+                   precision="fp64", deposit="cic", fluid="tg1", advect=False, dt=0.0):
+    """A tiny uniform workload for brute-force and edge-case tests."""
+    return Workload(name=f"small_{nb[0]}x{nb[1]}x{nb[2]}_r{ratio}_n{n}", grid=Grid(tuple(box), tuple(nb), ratio),
+                    n_particles=n, precision=precision, deposit=deposit, seed=seed,
+                    particles="uniform", fluid=fluid, advect=advect, dt=dt)
