@@ -1,0 +1,194 @@
+#!/usr/bin/env python3
+"""Throughput of the coupling exchange on one MI355X.
+
+One "step" is one call of couple_step(): bin + sort, volume deposition,
+restriction with the fused fine-grid lookup and drag, momentum-source deposition,
+prolongation and the FP64 conservation sums, for the 10-million-particle packed
+bed (box 1x1x2, bulk 128x128x256, fine 512x512x1024; synthetic inputs resident in
+HBM before timing).  Prints one JSON line with particle-steps/s, the roofline of
+the dominant kernel (timed live with HIP events on the library's stream) and the
+FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import dataclasses
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E, vendor figure
+METRIC = "coupling particle-steps/s, plain vs MLP path at 1e-3 rel err; % HBM peak"
+
+
+def kernel_alg_bytes(name, n, ncell, nfine, fsz):
+    """Algorithmic (compulsory) bytes of one launch of the named kernel.
+
+    restrict_lookup_drag: fine u,v,w,p read once (4 fsz per fine cell); U, P
+        written (4 fsz per bulk cell); per particle position+diameter+velocity
+        read (7 fsz), drag+beta written (4 fsz) and its id read (4 B).
+    prolong: eps and F_fpi written on the fine grid (4 fsz per fine cell);
+        phi and F_fpi read on the bulk grid (4 fsz per bulk cell).
+    """
+    if name == "restrict_lookup_drag":
+        return 4 * fsz * nfine + 4 * fsz * ncell + n * (11 * fsz + 4)
+    if name == "restrict":
+        return 4 * fsz * nfine + 4 * fsz * ncell
+    if name == "prolong":
+        return 4 * fsz * nfine + 4 * fsz * ncell
+    return None
+
+
+def step_alg_bytes(n, ncell, nfine, fsz, sort_passes):
+    """Compulsory HBM bytes of one whole step: fine fields read and written once,
+    particle inputs read and outputs written once, bulk outputs written and read
+    once, plus 16 B per particle per radix pass."""
+    fine = 8 * fsz * nfine
+    particles = n * (7 * fsz + 4 * fsz + 8)          # pos,d,vel in; drag,beta,cell,perm out
+    bulk = ncell * (8 + 11 * fsz * 2)                # count,start; 11 fields written + read
+    sort = 16 * n * sort_passes
+    return fine + particles + bulk + sort
+
+
+def sort_passes(ncell):
+    bits = 1
+    while (1 << bits) < ncell:
+        bits += 1
+    return (bits + 7) // 8
+
+
+def cpu_baseline(w, frac):
+    """Time the FP64 oracle (single-threaded C) on the sub-box x < frac*Lx, y < frac*Ly
+    of the workload (full z extent, same fine spacing), one step."""
+    import numpy as np
+
+    import oracle
+    import workload as W
+    g = w.grid
+    sub = dataclasses.replace(w, grid=W.Grid((g.box[0] * frac, g.box[1] * frac, g.box[2]),
+                                             (int(g.nb[0] * frac), int(g.nb[1] * frac), g.nb[2]), g.ratio))
+    pos, d, vel = W.particles(w)
+    m = (pos[:, 0] < sub.grid.box[0]) & (pos[:, 1] < sub.grid.box[1])
+    pos, d, vel = pos[m], d[m], vel[m]
+    fine = W.fine_fields(sub)
+    oracle.lib()
+    t0 = time.perf_counter()
+    oracle.step(pos, vel, d, fine, sub.grid, rho_f=w.rho_f, mu_f=w.mu_f, rho_p=w.rho_p, eps_min=w.eps_min,
+                cic=True, prec32=True, vel_source="fine")
+    dt = time.perf_counter() - t0
+    cpu = platform.processor() or platform.machine()
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"value": pos.shape[0] / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": (f"one oracle step (FP64, single thread) on the sub-box x<{frac}, y<{frac} of the same "
+                       f"workload: {pos.shape[0]} particles, bulk {sub.grid.nb}, fine {sub.grid.nf}; "
+                       f"{dt:.1f} s; host {cpu}, {os.cpu_count()} logical CPUs")}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="bed128_cic")
+    ap.add_argument("--cpu-frac", type=float, default=0.25, help="x-y fraction of the oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the coupling exchange is built and timed for a single "
+              "MI355X (the multi-GPU sharding is a design in DESIGN.md, not built); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1807_11834_amd as cpl
+    import workload as W
+
+    dev = torch.device("cuda:0")
+    w = W.WORKLOADS[args.workload]
+    g = w.grid
+    pos_np, d_np, vel_np = W.particles(w)
+    n = pos_np.shape[0]
+    fp64 = w.precision == "fp64"
+    dt = torch.float64 if fp64 else torch.float32
+    fsz = 8 if fp64 else 4
+    pos = torch.from_numpy(pos_np).to(dev)
+    vel = torch.from_numpy(vel_np).to(dev)
+    diam = torch.from_numpy(d_np).to(dev)
+    fine = W.fine_fields_torch(w, dev, dt)
+    del pos_np, vel_np, d_np
+    cfg = cpl.Config(box=g.box, nb=g.nb, ratio=g.ratio, rho_f=w.rho_f, mu_f=w.mu_f, rho_p=w.rho_p,
+                     eps_min=w.eps_min, deposit=cpl.COUPLE_CIC if w.deposit == "cic" else cpl.COUPLE_NGP,
+                     precision=cpl.COUPLE_FP64 if fp64 else cpl.COUPLE_FP32_KAHAN,
+                     vel_source=cpl.COUPLE_VEL_FINE, advect=0, max_particles=n)
+    c = cpl.Coupler(cfg)
+    out = cpl.alloc_outputs(cfg, n, device=dev)
+    for _ in range(args.warmup):
+        c.step(pos, vel, diam, fine, out=out)
+    torch.cuda.synchronize()
+    print(f"# warmup done: {args.warmup} steps", file=sys.stderr, flush=True)
+
+    stream = torch.cuda.current_stream()
+    cpl.couple_timing_begin(c.h, args.steps)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        c.step(pos, vel, diam, fine, out=out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    stats = cpl.couple_timing_end(c.h)
+    ms_total = e0.elapsed_time(e1)
+    ms_step = ms_total / args.steps
+    value = n * args.steps / (ms_total / 1e3)
+    print(f"# timed {args.steps} steps: {ms_step:.3f} ms/step", file=sys.stderr, flush=True)
+
+    kernels = {k: {"launches": l, "avg_ms": t / l} for k, (l, t) in stats.items() if l}
+    dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
+    ab = kernel_alg_bytes(dom, n, g.n_bulk, g.n_fine, fsz)
+    roof = None
+    if ab is not None:
+        ach = ab / (kernels[dom]["avg_ms"] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBPS, 4), "traffic": None,
+                "alg_bytes_per_launch": ab, "avg_ms": round(kernels[dom]["avg_ms"], 4)}
+    sb = step_alg_bytes(n, g.n_bulk, g.n_fine, fsz, sort_passes(g.n_bulk))
+    d = cpl.diag_dict(out["diag"])
+    rec = {
+        "metric": METRIC, "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if fp64 else "f32", "data": "synthetic",
+        "config": {"workload": (f"{w.name}: {n} particles, box {g.box}, bulk {g.nb}, fine {g.nf}, "
+                                f"{w.deposit.upper()}, {'FP64' if fp64 else 'FP32 + Kahan, FP64 sums'}, "
+                                "fine-grid velocity lookup"),
+                   "n_particles": n, "bulk": list(g.nb), "fine": list(g.nf)},
+        "roofline": roof,
+        "step_alg_bytes": sb, "step_alg_GBps": round(sb / (ms_step * 1e-3) / 1e9, 1),
+        "step_alg_frac_hbm": round(sb / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+        "kernels_avg_ms": {k: round(v["avg_ms"], 4) for k, v in kernels.items()},
+        "conservation": {"V_dep/V_tot-1": d["V_dep"] / d["V_tot"] - 1 if d["V_tot"] else 0.0,
+                         "S_b+sumF": [d["S_b"][a] + d["sum_Fp"][a] for a in range(3)]},
+    }
+    if not args.no_cpu_baseline:
+        print("# cpu baseline (oracle sample) ...", file=sys.stderr, flush=True)
+        rec["cpu_baseline"] = cpu_baseline(w, args.cpu_frac)
+    else:
+        rec["cpu_baseline"] = None
+    c.close()
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

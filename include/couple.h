@@ -1,0 +1,176 @@
+/*
+ * couple.h -- C ABI of the MI355X (gfx950) dual-grid coupling exchange.
+ *
+ * One call of couple_step() performs the per-timestep exchange between
+ * Lagrangian particles, the coarse "bulk" grid on which the fluid-particle
+ * interaction is resolved and the fine grid on which the fluid equations are
+ * discretised (dual-grid multiscale coupling, Sec. 2.1 and Fig. 1):
+ *
+ *   1. bin      containing bulk cell of every particle and the canonical
+ *               (cell, id) order, rebuilt every coupling step (Sec. 2.2);
+ *   2. deposit  bulk solid fraction phi = sum_p w_pc V_p / V_b; porosity
+ *               eps = 1 - phi (Table 1 and the porosity definition of Sec. 2.4);
+ *   3. restrict fine fluid velocity and pressure averaged over the fine children
+ *               of every bulk cell ("fluid solution" arrow of Fig. 1), plus the
+ *               bulk pressure gradient;
+ *   4. gather   fluid velocity and void fraction at each particle ("cell values
+ *               or locally interpolated values", Sec. 1);
+ *   5. drag     F_p = beta (u_f - u_p), Eq. DragLaw of Sec. 2.4, with beta from
+ *               the Di Felice voidage correlation;
+ *   6. source   momentum source F_fpi,c = -(1/V_b) sum_p w_pc F_p, the counterpart
+ *               of the drag in Eq. UFP (Sec. 2.5);
+ *   7. prolong  eps and F_fpi transferred to the fine grid ("particle related
+ *               fields" arrow of Fig. 1) by a conservative trilinear prolongation;
+ *   8. sums     FP64 conservation diagnostics;
+ *   9. advect   optional explicit Euler step of Eq. DEM_EQUATIONS with the drag
+ *               as the only force.
+ *
+ * Grids: uniform, nested, cell-centred.  The box is [0,Lx]x[0,Ly]x[0,Lz]; the bulk
+ * grid has nb[0] x nb[1] x nb[2] cells; the fine grid has `ratio` fine cells per
+ * bulk cell along each axis.  Every grid array is stored z-major with x fastest
+ * ([nz][ny][nx]); a vector grid field is its three components back to back
+ * ([3][nz][ny][nx]).  Particle vectors are [n][3] (x, y, z interleaved).
+ *
+ * Memory: every pointer in couple_inputs / couple_outputs is a DEVICE pointer
+ * owned by the caller (for example a torch tensor's data_ptr()), C-contiguous and
+ * aligned to at least 16 bytes.  Floating-point arrays are `double` when the
+ * handle's precision is COUPLE_FP64 and `float` otherwise.  The library owns only
+ * its scratch, allocated by couple_init() and released by couple_free().
+ *
+ * Streams: couple_step() enqueues its kernels on the given HIP stream (a
+ * hipStream_t passed as void*; NULL is the null stream) and returns without
+ * synchronising.  Outputs, including diag, are valid once the stream has reached
+ * that point.  It allocates nothing.
+ *
+ * Errors: every function returns a couple_status (0 or negative) and never throws
+ * across the ABI.  Argument and state errors are detected before any launch and
+ * leave all outputs untouched; couple_last_error() then describes the failure.
+ * Particles outside the box (or with a non-finite coordinate) are not an error:
+ * they are clamped into the box and counted in diag[COUPLE_DIAG_N_OUTSIDE].
+ *
+ * Threading: a handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef COUPLE_H
+#define COUPLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct couple_handle couple_handle;
+
+typedef enum {
+    COUPLE_OK = 0,
+    COUPLE_EINVAL = -1,     /* invalid configuration or argument (NULL pointer, n < 0) */
+    COUPLE_ENOMEM = -2,     /* device allocation failed in couple_init                  */
+    COUPLE_EHIP = -3,       /* a HIP runtime call or kernel launch failed               */
+    COUPLE_ECAPACITY = -4,  /* n > max_particles                                        */
+    COUPLE_ESTATE = -6      /* call not valid in the handle's state                     */
+} couple_status;
+
+enum { COUPLE_NGP = 0, COUPLE_CIC = 1 };                  /* deposition weights            */
+enum { COUPLE_FP64 = 0, COUPLE_FP32_KAHAN = 1, COUPLE_FP32_NAIVE = 2 };  /* precision      */
+enum { COUPLE_VEL_FINE = 0, COUPLE_VEL_BULK = 1, COUPLE_VEL_GIVEN = 2 }; /* u_f at particle */
+
+/* Indices into the FP64 diagnostics vector (length COUPLE_DIAG_LEN). */
+enum {
+    COUPLE_DIAG_V_TOT = 0,      /* sum_p V_p, V_p = pi d^3 / 6                              */
+    COUPLE_DIAG_V_DEP = 1,      /* sum_c phi_c V_b (equals V_TOT: volume is conserved)     */
+    COUPLE_DIAG_SUM_FP = 2,     /* [2..4]  sum_p F_p (drag on the particles)               */
+    COUPLE_DIAG_S_B = 5,        /* [5..7]  sum_c F_fpi,c V_b  (equals -sum_p F_p)          */
+    COUPLE_DIAG_S_F = 8,        /* [8..10] sum_f F_f V_f on the fine grid (equals S_B)     */
+    COUPLE_DIAG_E_F = 11,       /* sum_f eps_f V_f, fluid volume on the fine grid          */
+    COUPLE_DIAG_N_CLAMPED = 12, /* particles whose void fraction was raised to eps_min     */
+    COUPLE_DIAG_N_OUTSIDE = 13, /* particles with a coordinate outside [0,L] or not finite */
+    COUPLE_DIAG_MAX_PHI = 14,   /* max_c phi_c                                              */
+    COUPLE_DIAG_N_FALLBACK = 15,/* reserved for callers that substitute u_f (0 here)       */
+    COUPLE_DIAG_LEN = 16
+};
+
+typedef struct couple_config {
+    double  box[3];          /* Lx, Ly, Lz > 0                                              */
+    int32_t nb[3];           /* bulk cells per axis, >= 1, product < 2^31 / ratio^3          */
+    int32_t ratio;           /* fine cells per bulk cell per axis: 1, 2 or 4                  */
+    double  rho_f, mu_f;     /* fluid density and viscosity (> 0)                            */
+    double  rho_p;           /* particle density (> 0), used by the advection                */
+    double  eps_min;         /* drag uses max(eps_p, eps_min), 0 <= eps_min < 1              */
+    double  phi_fp64;        /* particle solid fraction above which the FP32 modes evaluate
+                                eps_p and the voidage factor in FP64 (near close packing)     */
+    int32_t deposit;         /* COUPLE_NGP or COUPLE_CIC                                      */
+    int32_t precision;       /* COUPLE_FP64, COUPLE_FP32_KAHAN or COUPLE_FP32_NAIVE           */
+    int32_t vel_source;      /* COUPLE_VEL_FINE (trilinear on the fine grid), COUPLE_VEL_BULK
+                                (trilinear on the restricted bulk velocity) or
+                                COUPLE_VEL_GIVEN (couple_inputs.uf_given)                     */
+    int32_t advect;          /* 1: explicit Euler update of pos and vel in place              */
+    double  dt;              /* advection time step                                           */
+    int64_t max_particles;   /* capacity of the scratch; n > max_particles is an error        */
+} couple_config;
+
+typedef struct couple_inputs {
+    int64_t     n;           /* number of particles, 0 <= n <= max_particles                  */
+    void       *pos;         /* [n][3] positions; updated in place when advect = 1           */
+    void       *vel;         /* [n][3] velocities; updated in place when advect = 1          */
+    const void *diam;        /* [n] diameters                                                 */
+    const void *fine_u;      /* [nfz][nfy][nfx] fine fluid velocity, x component              */
+    const void *fine_v;      /*   y component                                                 */
+    const void *fine_w;      /*   z component                                                 */
+    const void *fine_p;      /* [nfz][nfy][nfx] fine pressure                                 */
+    const void *uf_given;    /* [n][3] fluid velocity at each particle (VEL_GIVEN only)       */
+} couple_inputs;
+
+typedef struct couple_outputs {
+    void    *drag;           /* [n][3] F_p, drag on each particle (input order)               */
+    void    *beta;           /* [n] drag factor beta, or NULL if not wanted                   */
+    int32_t *cell;           /* [n] containing bulk cell (linear index) per particle          */
+    int32_t *perm;           /* [n] particle ids in ascending (cell, id) order                */
+    int32_t *count;          /* [Nb] particles per bulk cell                                  */
+    int32_t *start;          /* [Nb+1] exclusive prefix sum of count                          */
+    void    *bulk_phi;       /* [Nb] solid volume fraction                                    */
+    void    *bulk_F;         /* [3][Nb] momentum source F_fpi                                 */
+    void    *bulk_U;         /* [3][Nb] restricted fluid velocity                             */
+    void    *bulk_P;         /* [Nb] restricted pressure                                      */
+    void    *bulk_G;         /* [3][Nb] bulk pressure gradient                                */
+    void    *fine_eps;       /* [Nf] porosity prolonged to the fine grid                      */
+    void    *fine_F;         /* [3][Nf] momentum source prolonged to the fine grid            */
+    double  *diag;           /* [COUPLE_DIAG_LEN] FP64 diagnostics (device memory)            */
+} couple_outputs;
+
+/* Validate the configuration and allocate the scratch (about 48 * max_particles
+ * bytes plus a few bytes per bulk cell).  On success *out receives a handle. */
+int couple_init(const couple_config *cfg, couple_handle **out);
+
+/* Enqueue one coupling step (stages 1-9 above) on `stream`.  Every pointer of
+ * `in` and `out` except out->beta (and in->uf_given unless VEL_GIVEN) must be
+ * non-NULL when n > 0; the grid outputs are always required. */
+int couple_step(couple_handle *h, const couple_inputs *in, couple_outputs *out, void *stream);
+
+/* Release the scratch and the handle.  NULL is accepted. */
+int couple_free(couple_handle *h);
+
+/* Text of the last error on this handle (or of the last couple_init failure when
+ * h is NULL).  The pointer stays valid until the next call on the same handle. */
+const char *couple_last_error(const couple_handle *h);
+
+/* ---- per-kernel timing (profiling aid, not part of the coupling method) -----
+ * couple_timing_begin() starts recording: every following couple_step() records
+ * a HIP event on its stream before each kernel launch and after the last one,
+ * for at most `max_steps` steps (the event pool is created here).
+ * couple_timing_end() waits for the recorded events, stops recording and
+ * writes, per kernel name in launch order, the number of launches and the summed
+ * event-to-event milliseconds into stats[0..max_stats); *n_stats receives the
+ * number of names.  Names are static strings owned by the library. */
+typedef struct couple_kernel_stat {
+    const char *name;
+    int64_t     launches;
+    double      total_ms;
+} couple_kernel_stat;
+
+int couple_timing_begin(couple_handle *h, int32_t max_steps);
+int couple_timing_end(couple_handle *h, couple_kernel_stat *stats, int32_t max_stats, int32_t *n_stats);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* COUPLE_H */

@@ -250,6 +250,9 @@ def step(pos, vel, diam, fine, grid, rho_f=1000.0, mu_f=1e-3, rho_p=2500.0, eps_
     P = restrict(fine[3], nb, r)
     G = gradient(P, nb, box)
     out.update(U=U, P=P, G=G)
+    # magnitudes of the averaged values (parity-metric scales, not the method)
+    out["U_mag"] = np.stack([restrict(np.abs(np.asarray(f, dtype=np.float64)), nb, r) for f in fine[:3]])
+    out["P_mag"] = restrict(np.abs(np.asarray(fine[3], dtype=np.float64)), nb, r)
     eps_p = gather_eps(pos, phi, box, nb, cic, prec32)
     if vel_source == "fine":
         uf = np.stack([interp(f, nf, box, pos, prec32) for f in fine[:3]], axis=1)
@@ -263,6 +266,11 @@ def step(pos, vel, diam, fine, grid, rho_f=1000.0, mu_f=1e-3, rho_p=2500.0, eps_
     out.update(eps_p=eps_p, uf=uf, drag=force, beta=beta)
     Fc = deposit_force(pos, force, perm, box, nb, cic, prec32)
     out["F"] = Fc
+    # magnitude of the deposited terms, (1/V_b) sum_p w_pc |F_p|: the scale of
+    # the summation error of F_fpi (used by the parity metric, not by the method)
+    fmag = np.zeros_like(force)
+    fmag[:, 0] = np.sqrt((force ** 2).sum(axis=1))
+    out["F_mag"] = -deposit_force(pos, fmag, perm, box, nb, cic, prec32)[0]
     eps_b = 1.0 - phi
     fields = [eps_b, Fc[0], Fc[1], Fc[2]]
     if fine_out == "full":

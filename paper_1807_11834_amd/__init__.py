@@ -1,0 +1,254 @@
+"""Python binding of the MI355X dual-grid coupling library (``libcouple.so``).
+
+Argument marshalling only: every stage of a coupling step runs in the HIP
+kernels behind the C ABI declared in ``include/couple.h``.  PyTorch provides the
+device memory (tensors are passed as ``data_ptr()``) and the stream.  There is no
+CPU fallback: importing this package without the built library raises.
+
+The functions mirror the C entry points::
+
+    h = couple_init(Config(...))
+    couple_step(h, inputs, outputs, stream=None)
+    couple_free(h)
+    couple_last_error(h)
+
+``Coupler`` wraps a handle with output allocation for convenience.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+
+import torch  # noqa: F401  (loads the HIP runtime the library binds to)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcouple.so")
+
+# ---- constants (include/couple.h) -------------------------------------------
+COUPLE_OK, COUPLE_EINVAL, COUPLE_ENOMEM, COUPLE_EHIP, COUPLE_ECAPACITY, COUPLE_ESTATE = 0, -1, -2, -3, -4, -6
+COUPLE_NGP, COUPLE_CIC = 0, 1
+COUPLE_FP64, COUPLE_FP32_KAHAN, COUPLE_FP32_NAIVE = 0, 1, 2
+COUPLE_VEL_FINE, COUPLE_VEL_BULK, COUPLE_VEL_GIVEN = 0, 1, 2
+DIAG = {"V_tot": 0, "V_dep": 1, "sum_Fp": 2, "S_b": 5, "S_f": 8, "E_f": 11, "n_clamped": 12,
+        "n_outside": 13, "max_phi": 14, "n_fallback": 15}
+DIAG_LEN = 16
+
+
+class CoupleError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class _Config(C.Structure):
+    _fields_ = [("box", C.c_double * 3), ("nb", C.c_int32 * 3), ("ratio", C.c_int32),
+                ("rho_f", C.c_double), ("mu_f", C.c_double), ("rho_p", C.c_double), ("eps_min", C.c_double),
+                ("phi_fp64", C.c_double), ("deposit", C.c_int32), ("precision", C.c_int32),
+                ("vel_source", C.c_int32), ("advect", C.c_int32), ("dt", C.c_double),
+                ("max_particles", C.c_int64)]
+
+
+class _Inputs(C.Structure):
+    _fields_ = [("n", C.c_int64), ("pos", C.c_void_p), ("vel", C.c_void_p), ("diam", C.c_void_p),
+                ("fine_u", C.c_void_p), ("fine_v", C.c_void_p), ("fine_w", C.c_void_p), ("fine_p", C.c_void_p),
+                ("uf_given", C.c_void_p)]
+
+
+class _Outputs(C.Structure):
+    _fields_ = [("drag", C.c_void_p), ("beta", C.c_void_p), ("cell", C.c_void_p), ("perm", C.c_void_p),
+                ("count", C.c_void_p), ("start", C.c_void_p), ("bulk_phi", C.c_void_p), ("bulk_F", C.c_void_p),
+                ("bulk_U", C.c_void_p), ("bulk_P", C.c_void_p), ("bulk_G", C.c_void_p),
+                ("fine_eps", C.c_void_p), ("fine_F", C.c_void_p), ("diag", C.c_void_p)]
+
+
+class _KernelStat(C.Structure):
+    _fields_ = [("name", C.c_char_p), ("launches", C.c_int64), ("total_ms", C.c_double)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                          "(there is no CPU fallback for the coupling step)")
+    L = C.CDLL(LIB_PATH)
+    L.couple_init.argtypes = [C.POINTER(_Config), C.POINTER(C.c_void_p)]
+    L.couple_init.restype = C.c_int
+    L.couple_step.argtypes = [C.c_void_p, C.POINTER(_Inputs), C.POINTER(_Outputs), C.c_void_p]
+    L.couple_step.restype = C.c_int
+    L.couple_free.argtypes = [C.c_void_p]
+    L.couple_free.restype = C.c_int
+    L.couple_last_error.argtypes = [C.c_void_p]
+    L.couple_last_error.restype = C.c_char_p
+    L.couple_timing_begin.argtypes = [C.c_void_p, C.c_int32]
+    L.couple_timing_begin.restype = C.c_int
+    L.couple_timing_end.argtypes = [C.c_void_p, C.POINTER(_KernelStat), C.c_int32, C.POINTER(C.c_int32)]
+    L.couple_timing_end.restype = C.c_int
+    return L
+
+
+_lib = _load()
+
+
+@dataclass
+class Config:
+    """Mirror of ``couple_config``."""
+    box: tuple = (1.0, 1.0, 1.0)
+    nb: tuple = (8, 8, 8)
+    ratio: int = 4
+    rho_f: float = 1000.0
+    mu_f: float = 1.0e-3
+    rho_p: float = 2500.0
+    eps_min: float = 0.3
+    phi_fp64: float = 0.5
+    deposit: int = COUPLE_CIC
+    precision: int = COUPLE_FP32_KAHAN
+    vel_source: int = COUPLE_VEL_FINE
+    advect: int = 0
+    dt: float = 0.0
+    max_particles: int = 0
+
+    def to_c(self):
+        c = _Config()
+        c.box[:] = [float(x) for x in self.box]
+        c.nb[:] = [int(x) for x in self.nb]
+        c.ratio = int(self.ratio)
+        c.rho_f, c.mu_f, c.rho_p = float(self.rho_f), float(self.mu_f), float(self.rho_p)
+        c.eps_min, c.phi_fp64 = float(self.eps_min), float(self.phi_fp64)
+        c.deposit, c.precision, c.vel_source = int(self.deposit), int(self.precision), int(self.vel_source)
+        c.advect, c.dt, c.max_particles = int(self.advect), float(self.dt), int(self.max_particles)
+        return c
+
+    @property
+    def n_bulk(self):
+        return int(self.nb[0]) * int(self.nb[1]) * int(self.nb[2])
+
+    @property
+    def nf(self):
+        return tuple(int(n) * int(self.ratio) for n in self.nb)
+
+    @property
+    def n_fine(self):
+        return self.n_bulk * int(self.ratio) ** 3
+
+    @property
+    def dtype(self):
+        return torch.float64 if self.precision == COUPLE_FP64 else torch.float32
+
+
+def couple_last_error(h):
+    s = _lib.couple_last_error(h)
+    return s.decode() if s else ""
+
+
+def _check(code, h):
+    if code != COUPLE_OK:
+        raise CoupleError(code, couple_last_error(h))
+
+
+def couple_init(cfg: Config):
+    """Validate ``cfg`` and allocate the library scratch; returns the handle."""
+    h = C.c_void_p()
+    c = cfg.to_c()
+    code = _lib.couple_init(C.byref(c), C.byref(h))
+    _check(code, None)
+    return h
+
+
+def couple_free(h):
+    if h is not None:
+        _check(_lib.couple_free(h), None)
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def couple_step(h, inputs: dict, outputs: dict, stream=None):
+    """Enqueue one coupling step.  ``inputs``/``outputs`` map the field names of
+    ``couple_inputs``/``couple_outputs`` to device tensors (or None)."""
+    i = _Inputs()
+    i.n = int(inputs["n"])
+    for k in ("pos", "vel", "diam", "fine_u", "fine_v", "fine_w", "fine_p", "uf_given"):
+        setattr(i, k, _ptr(inputs.get(k)))
+    o = _Outputs()
+    for k, _ in _Outputs._fields_:
+        setattr(o, k, _ptr(outputs.get(k)))
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    elif isinstance(stream, torch.cuda.Stream):
+        stream = stream.cuda_stream
+    _check(_lib.couple_step(h, C.byref(i), C.byref(o), C.c_void_p(stream)), h)
+
+
+def couple_timing_begin(h, max_steps):
+    """Start per-kernel event recording for at most ``max_steps`` steps."""
+    _check(_lib.couple_timing_begin(h, int(max_steps)), h)
+
+
+def couple_timing_end(h):
+    """Stop recording; returns {kernel name: (launches, total milliseconds)}."""
+    stats = (_KernelStat * 64)()
+    n = C.c_int32(0)
+    _check(_lib.couple_timing_end(h, stats, 64, C.byref(n)), h)
+    return {stats[i].name.decode(): (int(stats[i].launches), float(stats[i].total_ms)) for i in range(n.value)}
+
+
+def alloc_outputs(cfg: Config, n: int, device="cuda", beta=True):
+    """Device tensors for every output of a step with ``n`` particles."""
+    dt = cfg.dtype
+    nb, nf = cfg.nb, cfg.nf
+    e = dict(device=device)
+    return {
+        "drag": torch.empty((n, 3), dtype=dt, **e),
+        "beta": torch.empty((n,), dtype=dt, **e) if beta else None,
+        "cell": torch.empty((n,), dtype=torch.int32, **e),
+        "perm": torch.empty((n,), dtype=torch.int32, **e),
+        "count": torch.empty((nb[2], nb[1], nb[0]), dtype=torch.int32, **e),
+        "start": torch.empty((cfg.n_bulk + 1,), dtype=torch.int32, **e),
+        "bulk_phi": torch.empty((nb[2], nb[1], nb[0]), dtype=dt, **e),
+        "bulk_F": torch.empty((3, nb[2], nb[1], nb[0]), dtype=dt, **e),
+        "bulk_U": torch.empty((3, nb[2], nb[1], nb[0]), dtype=dt, **e),
+        "bulk_P": torch.empty((nb[2], nb[1], nb[0]), dtype=dt, **e),
+        "bulk_G": torch.empty((3, nb[2], nb[1], nb[0]), dtype=dt, **e),
+        "fine_eps": torch.empty((nf[2], nf[1], nf[0]), dtype=dt, **e),
+        "fine_F": torch.empty((3, nf[2], nf[1], nf[0]), dtype=dt, **e),
+        "diag": torch.empty((DIAG_LEN,), dtype=torch.float64, **e),
+    }
+
+
+def diag_dict(diag_tensor):
+    d = diag_tensor.detach().cpu().tolist()
+    return {"V_tot": d[0], "V_dep": d[1], "sum_Fp": d[2:5], "S_b": d[5:8], "S_f": d[8:11], "E_f": d[11],
+            "n_clamped": d[12], "n_outside": d[13], "max_phi": d[14], "n_fallback": d[15]}
+
+
+class Coupler:
+    """A handle plus its outputs.  ``step`` takes device tensors of the handle's
+    dtype: pos [n,3], vel [n,3], diam [n], fine fields [nfz,nfy,nfx]."""
+
+    def __init__(self, cfg: Config):
+        self.cfg = cfg
+        self.h = couple_init(cfg)
+        self.out = None
+
+    def step(self, pos, vel, diam, fine, uf_given=None, out=None, beta=True, stream=None):
+        n = pos.shape[0]
+        if out is None:
+            if self.out is None or self.out["drag"].shape[0] != n:
+                self.out = alloc_outputs(self.cfg, n, device=pos.device, beta=beta)
+            out = self.out
+        inputs = {"n": n, "pos": pos, "vel": vel, "diam": diam, "fine_u": fine[0], "fine_v": fine[1],
+                  "fine_w": fine[2], "fine_p": fine[3], "uf_given": uf_given}
+        couple_step(self.h, inputs, out, stream=stream)
+        return out
+
+    def close(self):
+        if self.h is not None:
+            couple_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

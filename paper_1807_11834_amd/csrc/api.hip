@@ -1,0 +1,289 @@
+// api.hip -- C ABI of the coupling library (see include/couple.h).
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "couple.h"
+#include "launch.hpp"
+
+using namespace cpl;
+
+struct couple_handle {
+    couple_config cfg;
+    std::string err;
+    int64_t ncell = 0, nfine = 0;
+    int64_t part_stride = 0;
+    SortScratch sort{};
+    void *sp = nullptr, *sv = nullptr, *sf = nullptr, *plo = nullptr;
+    double *part = nullptr;
+    // per-kernel timing
+    Marker mk;
+    std::vector<hipEvent_t> events;
+    std::vector<const char *> names;
+};
+
+static thread_local std::string g_init_err;
+
+static int fail(couple_handle *h, int code, const std::string &msg) {
+    if (h) h->err = msg;
+    else g_init_err = msg;
+    return code;
+}
+
+static void destroy_events(couple_handle *h) {
+    for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
+    h->events.clear();
+    h->names.clear();
+    h->mk = Marker{};
+}
+
+static void release(couple_handle *h) {
+    destroy_events(h);
+    void *ptrs[] = {h->sort.keys_a, h->sort.keys_b, h->sort.vals_a, h->sort.vals_b, h->sort.hist,
+                    h->sort.totals, h->sp, h->sv, h->sf, h->plo, h->part};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    h->sort = SortScratch{};
+    h->sp = h->sv = h->sf = h->plo = nullptr;
+    h->part = nullptr;
+}
+
+static std::string validate(const couple_config *c) {
+    for (int a = 0; a < 3; ++a) {
+        if (!(std::isfinite(c->box[a]) && c->box[a] > 0.0)) return "box lengths must be finite and > 0";
+        if (c->nb[a] < 1) return "nb must be >= 1 on every axis";
+    }
+    if (!(c->ratio == 1 || c->ratio == 2 || c->ratio == 4)) return "ratio must be 1, 2 or 4";
+    const int64_t ncell = (int64_t)c->nb[0] * c->nb[1] * c->nb[2];
+    if (ncell >= (int64_t(1) << 31) - 1) return "too many bulk cells (must be < 2^31 - 1)";
+    const int64_t r3 = (int64_t)c->ratio * c->ratio * c->ratio;
+    if (ncell * r3 >= (int64_t(1) << 40)) return "too many fine cells";
+    for (int a = 0; a < 3; ++a)
+        if ((int64_t)c->nb[a] * c->ratio >= (int64_t(1) << 30)) return "too many fine cells along an axis";
+    if (!(std::isfinite(c->rho_f) && c->rho_f > 0.0)) return "rho_f must be finite and > 0";
+    if (!(std::isfinite(c->mu_f) && c->mu_f > 0.0)) return "mu_f must be finite and > 0";
+    if (!(std::isfinite(c->rho_p) && c->rho_p > 0.0)) return "rho_p must be finite and > 0";
+    if (!(std::isfinite(c->eps_min) && c->eps_min >= 0.0 && c->eps_min < 1.0)) return "eps_min must be in [0, 1)";
+    if (!std::isfinite(c->phi_fp64)) return "phi_fp64 must be finite";
+    if (!(c->deposit == COUPLE_NGP || c->deposit == COUPLE_CIC)) return "deposit must be COUPLE_NGP or COUPLE_CIC";
+    if (!(c->precision == COUPLE_FP64 || c->precision == COUPLE_FP32_KAHAN || c->precision == COUPLE_FP32_NAIVE))
+        return "unknown precision";
+    if (!(c->vel_source == COUPLE_VEL_FINE || c->vel_source == COUPLE_VEL_BULK || c->vel_source == COUPLE_VEL_GIVEN))
+        return "unknown vel_source";
+    if (!(c->advect == 0 || c->advect == 1)) return "advect must be 0 or 1";
+    if (c->advect && !(std::isfinite(c->dt) && c->dt >= 0.0)) return "dt must be finite and >= 0";
+    if (c->max_particles < 0 || c->max_particles >= (int64_t(1) << 31) - 1)
+        return "max_particles must be in [0, 2^31 - 1)";
+    return "";
+}
+
+template <typename X> static bool dev_alloc(X **p, size_t bytes) {
+    void *q = nullptr;
+    if (bytes == 0) bytes = 256;
+    if (hipMalloc(&q, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return false;
+    }
+    *p = static_cast<X *>(q);
+    return true;
+}
+
+extern "C" int couple_init(const couple_config *cfg, couple_handle **out) {
+    if (!cfg || !out) return fail(nullptr, COUPLE_EINVAL, "couple_init: NULL argument");
+    *out = nullptr;
+    std::string v = validate(cfg);
+    if (!v.empty()) return fail(nullptr, COUPLE_EINVAL, "couple_init: " + v);
+    couple_handle *h = new (std::nothrow) couple_handle();
+    if (!h) return fail(nullptr, COUPLE_ENOMEM, "couple_init: host allocation failed");
+    h->cfg = *cfg;
+    h->ncell = (int64_t)cfg->nb[0] * cfg->nb[1] * cfg->nb[2];
+    h->nfine = h->ncell * cfg->ratio * cfg->ratio * cfg->ratio;
+    const int64_t nmax = cfg->max_particles;
+    const size_t fsz = (cfg->precision == COUPLE_FP64) ? sizeof(double) : sizeof(float);
+    const int64_t ntile = sort_tiles(nmax > 0 ? nmax : 1);
+    const int64_t pblk = (nmax + kBlock - 1) / kBlock, cblk = (h->ncell + kBlock - 1) / kBlock;
+    h->part_stride = (pblk > cblk ? pblk : cblk);
+    if (h->part_stride < ntile) h->part_stride = ntile;
+    if (h->part_stride < 1) h->part_stride = 1;
+    bool ok = dev_alloc(&h->sort.keys_a, sizeof(uint32_t) * nmax) && dev_alloc(&h->sort.keys_b, sizeof(uint32_t) * nmax) &&
+              dev_alloc(&h->sort.vals_a, sizeof(uint32_t) * nmax) && dev_alloc(&h->sort.vals_b, sizeof(uint32_t) * nmax) &&
+              dev_alloc(&h->sort.hist, sizeof(uint32_t) * 256 * ntile) && dev_alloc(&h->sort.totals, sizeof(uint32_t) * 256) &&
+              dev_alloc(&h->sp, 4 * fsz * nmax) && dev_alloc(&h->sv, 4 * fsz * nmax) && dev_alloc(&h->sf, 4 * fsz * nmax) && dev_alloc(&h->plo, fsz * h->ncell) &&
+              dev_alloc(&h->part, sizeof(double) * SL_COUNT * h->part_stride);
+    if (!ok) {
+        release(h);
+        delete h;
+        return fail(nullptr, COUPLE_ENOMEM, "couple_init: device allocation failed");
+    }
+    *out = h;
+    return COUPLE_OK;
+}
+
+extern "C" int couple_free(couple_handle *h) {
+    if (!h) return COUPLE_OK;
+    release(h);
+    delete h;
+    return COUPLE_OK;
+}
+
+extern "C" const char *couple_last_error(const couple_handle *h) {
+    return h ? h->err.c_str() : g_init_err.c_str();
+}
+
+template <typename T> static Geo<T> make_geo(const couple_config &c) {
+    Geo<T> g;
+    for (int a = 0; a < 3; ++a) {
+        g.nb[a] = c.nb[a];
+        g.nf[a] = c.nb[a] * c.ratio;
+        g.L[a] = (T)c.box[a];
+        g.sb[a] = (T)((double)c.nb[a] / c.box[a]);
+        g.sf[a] = (T)((double)g.nf[a] / c.box[a]);
+        g.hb[a] = (T)(c.box[a] / (double)c.nb[a]);
+    }
+    g.ncell = (int64_t)c.nb[0] * c.nb[1] * c.nb[2];
+    g.nfine = g.ncell * c.ratio * c.ratio * c.ratio;
+    g.vb = (c.box[0] / c.nb[0]) * (c.box[1] / c.nb[1]) * (c.box[2] / c.nb[2]);
+    g.vf = g.vb / ((double)c.ratio * c.ratio * c.ratio);
+    g.inv_vb = (T)(1.0 / g.vb);
+    return g;
+}
+
+template <typename T>
+static int step_impl(couple_handle *h, const couple_inputs *in, couple_outputs *out, hipStream_t st) {
+    const couple_config &c = h->cfg;
+    StepArgs<T> a;
+    a.g = make_geo<T>(c);
+    a.n = in->n;
+    a.ratio = c.ratio;
+    a.cic = c.deposit == COUPLE_CIC;
+    a.kahan = c.precision == COUPLE_FP32_KAHAN;
+    a.vel_source = c.vel_source;
+    a.advect = c.advect;
+    a.dt = (T)c.dt;
+    a.rho_f = (T)c.rho_f;
+    a.mu_f = (T)c.mu_f;
+    a.rho_p = (T)c.rho_p;
+    a.eps_min = (T)c.eps_min;
+    a.phi_fp64 = (float)c.phi_fp64;
+    a.pos = (T *)in->pos;
+    a.vel = (T *)in->vel;
+    a.diam = (const T *)in->diam;
+    a.fine[0] = (const T *)in->fine_u;
+    a.fine[1] = (const T *)in->fine_v;
+    a.fine[2] = (const T *)in->fine_w;
+    a.fine[3] = (const T *)in->fine_p;
+    a.uf_given = (const T *)in->uf_given;
+    a.drag = (T *)out->drag;
+    a.beta = (T *)out->beta;
+    a.perm = out->perm;
+    a.start = out->start;
+    a.phi = (T *)out->bulk_phi;
+    a.F = (T *)out->bulk_F;
+    a.U = (T *)out->bulk_U;
+    a.P = (T *)out->bulk_P;
+    a.G = (T *)out->bulk_G;
+    a.fine_eps = (T *)out->fine_eps;
+    a.fine_F = (T *)out->fine_F;
+    a.diag = out->diag;
+    a.sp = (vec4<T> *)h->sp;
+    a.sv = (vec4<T> *)h->sv;
+    a.sf = (vec4<T> *)h->sf;
+    a.Plo = (T *)h->plo;
+    a.part = h->part;
+    a.part_stride = h->part_stride;
+    a.mk = &h->mk;
+
+    (void)hipGetLastError();  // clear a stale error so that it is not reported as ours
+    const uint32_t *skeys = nullptr;
+    hipError_t e = launch_bin_sort<T>(a.pos, a.n, a.g, out->cell, out->perm, out->start, out->count, h->sort,
+                                      h->part + SL_NOUT * h->part_stride, &skeys, &h->mk, st);
+    if (e != hipSuccess) return fail(h, COUPLE_EHIP, std::string("couple_step: sort launch failed: ") + hipGetErrorString(e));
+    e = launch_stages<T>(a, st);
+    if (e != hipSuccess) return fail(h, COUPLE_EHIP, std::string("couple_step: stage launch failed: ") + hipGetErrorString(e));
+    return COUPLE_OK;
+}
+
+extern "C" int couple_step(couple_handle *h, const couple_inputs *in, couple_outputs *out, void *stream) {
+    if (!h) return fail(nullptr, COUPLE_EINVAL, "couple_step: NULL handle");
+    if (!in || !out) return fail(h, COUPLE_EINVAL, "couple_step: NULL inputs or outputs");
+    const couple_config &c = h->cfg;
+    if (in->n < 0) return fail(h, COUPLE_EINVAL, "couple_step: n < 0");
+    if (in->n > c.max_particles) return fail(h, COUPLE_ECAPACITY, "couple_step: n exceeds max_particles");
+    if (!in->fine_u || !in->fine_v || !in->fine_w || !in->fine_p)
+        return fail(h, COUPLE_EINVAL, "couple_step: NULL fine-grid input");
+    if (!out->count || !out->start || !out->bulk_phi || !out->bulk_F || !out->bulk_U || !out->bulk_P ||
+        !out->bulk_G || !out->fine_eps || !out->fine_F || !out->diag)
+        return fail(h, COUPLE_EINVAL, "couple_step: NULL grid output");
+    if (in->n > 0) {
+        if (!in->pos || !in->vel || !in->diam) return fail(h, COUPLE_EINVAL, "couple_step: NULL particle input");
+        if (!out->drag || !out->cell || !out->perm) return fail(h, COUPLE_EINVAL, "couple_step: NULL particle output");
+        if (c.vel_source == COUPLE_VEL_GIVEN && !in->uf_given)
+            return fail(h, COUPLE_EINVAL, "couple_step: vel_source GIVEN needs uf_given");
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (c.precision == COUPLE_FP64) return step_impl<double>(h, in, out, st);
+    return step_impl<float>(h, in, out, st);
+}
+
+extern "C" int couple_timing_begin(couple_handle *h, int32_t max_steps) {
+    if (!h) return fail(nullptr, COUPLE_EINVAL, "couple_timing_begin: NULL handle");
+    if (max_steps < 1 || max_steps > 100000) return fail(h, COUPLE_EINVAL, "couple_timing_begin: max_steps out of range");
+    destroy_events(h);
+    const int per_step = 32;
+    const int cap = max_steps * per_step;
+    h->events.resize(cap);
+    h->names.assign(cap, nullptr);
+    for (int i = 0; i < cap; ++i) {
+        if (hipEventCreate(&h->events[i]) != hipSuccess) {
+            (void)hipGetLastError();
+            h->events.resize(i);
+            destroy_events(h);
+            return fail(h, COUPLE_EHIP, "couple_timing_begin: hipEventCreate failed");
+        }
+    }
+    h->mk.on = true;
+    h->mk.events = h->events.data();
+    h->mk.names = h->names.data();
+    h->mk.cap = cap;
+    h->mk.used = 0;
+    return COUPLE_OK;
+}
+
+extern "C" int couple_timing_end(couple_handle *h, couple_kernel_stat *stats, int32_t max_stats, int32_t *n_stats) {
+    if (!h || !n_stats || (max_stats > 0 && !stats)) return fail(h, COUPLE_EINVAL, "couple_timing_end: NULL argument");
+    if (h->events.empty()) return fail(h, COUPLE_ESTATE, "couple_timing_end: timing was not started");
+    const int used = h->mk.used;
+    h->mk.on = false;
+    int nout = 0;
+    if (used > 0 && hipEventSynchronize(h->events[used - 1]) != hipSuccess) {
+        (void)hipGetLastError();
+        destroy_events(h);
+        return fail(h, COUPLE_EHIP, "couple_timing_end: hipEventSynchronize failed");
+    }
+    for (int i = 0; i + 1 < used; ++i) {
+        const char *nm = h->names[i];
+        if (!nm) continue;  // gap between the end of a step and the next step
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, h->events[i], h->events[i + 1]) != hipSuccess) {
+            (void)hipGetLastError();
+            continue;
+        }
+        int k = 0;
+        while (k < nout && std::strcmp(stats[k].name, nm) != 0) ++k;
+        if (k == nout) {
+            if (nout >= max_stats) continue;
+            stats[k].name = nm;
+            stats[k].launches = 0;
+            stats[k].total_ms = 0.0;
+            ++nout;
+        }
+        stats[k].launches += 1;
+        stats[k].total_ms += ms;
+    }
+    *n_stats = nout;
+    destroy_events(h);
+    return COUPLE_OK;
+}

@@ -1,0 +1,147 @@
+// common.hpp -- device helpers shared by the coupling kernels (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cpl {
+
+constexpr int kBlock = 256;          // threads per workgroup for every kernel
+constexpr int kWave = 64;            // CDNA wavefront width
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr double kPi = 3.14159265358979323846;
+
+// Diagnostic partial-sum slots: each kernel writes one FP64 value per slot per
+// workgroup; the final reduction sums every slot in a fixed order.
+enum Slot {
+    SL_VTOT = 0, SL_PHISUM = 1, SL_FP = 2, SL_FB = 5, SL_FF = 8, SL_EPSF = 11,
+    SL_NCLAMP = 12, SL_NOUT = 13, SL_MAXPHI = 14, SL_NFALL = 15, SL_COUNT = 16
+};
+
+template <typename T> struct V4;
+template <> struct V4<float> { using type = float4; };
+template <> struct V4<double> { using type = double4; };
+template <typename T> using vec4 = typename V4<T>::type;
+
+// Geometry constants of the nested grid pair in the working precision.
+template <typename T> struct Geo {
+    int nb[3];          // bulk cells per axis
+    int nf[3];          // fine cells per axis
+    int64_t ncell;      // bulk cells
+    int64_t nfine;      // fine cells
+    T L[3];             // box lengths
+    T sb[3];            // nb / L (bulk cells per unit length)
+    T sf[3];            // nf / L
+    T hb[3];            // bulk spacing
+    T inv_vb;           // 1 / V_b
+    double vb, vf;      // cell volumes (FP64, for the diagnostics)
+};
+
+// Compensated (Kahan) or plain running sum.
+template <typename T, bool KAHAN> struct Acc {
+    T s = T(0), c = T(0);
+    __device__ __forceinline__ void add(T v) {
+        if constexpr (KAHAN) {
+            T y = v - c;
+            T t = s + y;
+            c = (t - s) - y;
+            s = t;
+        } else {
+            s += v;
+        }
+    }
+};
+
+template <typename T> __device__ __forceinline__ T tmin(T a, T b) { return a < b ? a : b; }
+template <typename T> __device__ __forceinline__ T tmax(T a, T b) { return a > b ? a : b; }
+
+__device__ __forceinline__ float dfloor(float x) { return floorf(x); }
+__device__ __forceinline__ double dfloor(double x) { return floor(x); }
+__device__ __forceinline__ float dsqrt(float x) { return sqrtf(x); }
+__device__ __forceinline__ double dsqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float dexp(float x) { return expf(x); }
+__device__ __forceinline__ double dexp(double x) { return exp(x); }
+__device__ __forceinline__ float dlog10(float x) { return log10f(x); }
+__device__ __forceinline__ double dlog10(double x) { return log10(x); }
+__device__ __forceinline__ float dpow(float x, float y) { return powf(x, y); }
+__device__ __forceinline__ double dpow(double x, double y) { return pow(x, y); }
+__device__ __forceinline__ float dfma(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double dfma(double a, double b, double c) { return fma(a, b, c); }
+
+__device__ __forceinline__ int clampi(int v, int n) { return v < 0 ? 0 : (v > n - 1 ? n - 1 : v); }
+
+// Coordinate clamped into [0, L]; a NaN becomes 0 (fmax returns the other operand).
+template <typename T> __device__ __forceinline__ T clamp_coord(T x, T L, int &outside) {
+    if (!(x >= T(0) && x <= L)) outside = 1;
+    return fmin(fmax(x, T(0)), L);
+}
+
+// One-axis CIC stencil: lower node, fraction, clamped node pair.
+template <typename T> struct Axis {
+    int lo, hi;   // clamped node indices (equal when folded at a wall)
+    T t;          // weight of `hi`; `lo` has 1 - t
+};
+template <typename T> __device__ __forceinline__ Axis<T> cic_axis(T x, T s, int n) {
+    T g = x * s - T(0.5);
+    T jf = dfloor(g);
+    int j = (int)jf;
+    Axis<T> a;
+    a.t = g - jf;
+    a.lo = clampi(j, n);
+    a.hi = clampi(j + 1, n);
+    return a;
+}
+// Weight of axis stencil `a` on node `c` (folded corners add up).
+template <typename T> __device__ __forceinline__ T axis_weight(const Axis<T> &a, int c) {
+    T w = T(0);
+    if (a.lo == c) w += T(1) - a.t;
+    if (a.hi == c) w += a.t;
+    return w;
+}
+
+// Containing-cell index along one axis: floor(x * s), clamped; x = L -> n - 1.
+template <typename T> __device__ __forceinline__ int cell_axis(T x, T s, int n) {
+    return clampi((int)dfloor(x * s), n);
+}
+
+// Workgroup -> logical tile so that consecutive tiles share an XCD (its L2):
+// workgroups are dealt round-robin over the 8 XCDs of the device.
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nblk) {
+    const int64_t nx = 8;
+    int64_t q = nblk / nx, r = nblk % nx;
+    int64_t x = b % nx, k = b / nx;
+    return x * q + (x < r ? x : r) + k;
+}
+
+// ---- wave / block reductions (fixed tree order -> deterministic) -----------
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+    for (int o = kWave / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+// Block-wide sum of one double per thread; every thread receives the total.
+__device__ __forceinline__ double block_sum(double v, double *lds /*[kWavesPerBlock]*/) {
+    v = wave_sum(v);
+    int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    __syncthreads();
+    if (lane == 0) lds[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int i = 0; i < kWavesPerBlock; ++i) t += lds[i];
+    return t;
+}
+__device__ __forceinline__ double block_max(double v, double *lds) {
+    v = wave_max(v);
+    int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    __syncthreads();
+    if (lane == 0) lds[w] = v;
+    __syncthreads();
+    double t = lds[0];
+    for (int i = 1; i < kWavesPerBlock; ++i) t = fmax(t, lds[i]);
+    return t;
+}
+
+}  // namespace cpl

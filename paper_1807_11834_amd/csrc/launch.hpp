@@ -1,0 +1,80 @@
+// launch.hpp -- host-side launchers of the coupling kernels (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace cpl {
+
+// Optional per-kernel event recording (profiling): mark(name) records an event
+// on the stream just before the kernel `name` is launched; mark(nullptr) closes
+// the step.  A no-op when `on` is false or the pool is full.
+struct Marker {
+    bool on = false;
+    hipEvent_t *events = nullptr;
+    const char **names = nullptr;
+    int cap = 0, used = 0;
+    void mark(const char *name, hipStream_t st) {
+        if (!on || used >= cap) return;
+        if (hipEventRecord(events[used], st) != hipSuccess) {
+            (void)hipGetLastError();
+            on = false;
+            return;
+        }
+        names[used++] = name;
+    }
+};
+
+// Scratch of the radix sort, owned by the handle.
+struct SortScratch {
+    uint32_t *keys_a, *keys_b;   // [max_particles]
+    uint32_t *vals_a, *vals_b;   // [max_particles]
+    uint32_t *hist;              // [256 * max_tiles]
+    uint32_t *totals;            // [256]
+};
+
+int sort_tiles(int64_t n);
+
+// Bin particles, sort (cell, id), and build start/count.
+template <typename T>
+hipError_t launch_bin_sort(const T *pos, int64_t n, const Geo<T> &g, int32_t *cell, int32_t *perm, int32_t *start,
+                           int32_t *count, const SortScratch &s, double *part_nout, const uint32_t **sorted_keys,
+                           Marker *mk, hipStream_t st);
+
+// Everything the stage kernels need for one step.
+template <typename T> struct StepArgs {
+    Geo<T> g;
+    int64_t n;
+    int ratio;
+    int cic;           // deposition / gather weights: 1 = CIC, 0 = NGP
+    int kahan;         // compensated per-cell sums (FP32 modes)
+    int vel_source;    // 0 fine, 1 bulk, 2 given
+    int advect;
+    T dt, rho_f, mu_f, rho_p, eps_min;
+    float phi_fp64;    // FP32 modes: FP64 void fraction above this particle solid fraction
+    // inputs
+    T *pos, *vel;
+    const T *diam;
+    const T *fine[4];      // u, v, w, p
+    const T *uf_given;     // [n][3]
+    // outputs
+    T *drag, *beta;
+    const int32_t *perm, *start;
+    T *phi, *F, *U, *P, *G;  // bulk
+    T *fine_eps, *fine_F;    // fine
+    double *diag;
+    // scratch
+    vec4<T> *sp;     // sorted particles (x, y, z, d)
+    vec4<T> *sv;     // sorted velocity
+    vec4<T> *sf;     // sorted drag
+    T *Plo;          // [ncell] low word of the restricted pressure (Kahan compensation)
+    double *part;    // [SL_COUNT][max_blocks]
+    int64_t part_stride;
+    Marker *mk;      // per-kernel event recording (never null)
+};
+
+// Stage launchers (in order of the step).
+template <typename T> hipError_t launch_stages(const StepArgs<T> &a, hipStream_t st);
+
+}  // namespace cpl

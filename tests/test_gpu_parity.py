@@ -1,0 +1,196 @@
+"""GPU parity of one coupling step against the FP64 oracle, through the C ABI.
+
+Integer outputs (cell, perm, count, start) must match bit for bit; FP32 fields
+within e_max <= 1e-4, the FP64 mode within 1e-6, FP64 global sums within rel 1e-6.
+"""
+import numpy as np
+import pytest
+
+import workload as W
+from parity_util import cfg_for, compare_step, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import oracle
+    import paper_1807_11834_amd as cpl
+    return torch, cpl, oracle
+
+
+def _oracle(oracle, cpl, w, cfg, pos, vel, d, fine, fine_out="full", fine_sample=None):
+    return oracle.step(pos, vel, d, fine, w.grid, rho_f=cfg.rho_f, mu_f=cfg.mu_f, rho_p=cfg.rho_p,
+                       eps_min=cfg.eps_min, cic=cfg.deposit == cpl.COUPLE_CIC,
+                       prec32=cfg.precision != cpl.COUPLE_FP64,
+                       vel_source={0: "fine", 1: "bulk"}[cfg.vel_source],
+                       advect_dt=cfg.dt if cfg.advect else None, fine_out=fine_out, fine_sample=fine_sample)
+
+
+def test_cube8_ngp_fp64(env):
+    torch, cpl, oracle = env
+    w = W.WORKLOADS["cube8_ngp_fp64"]
+    pos, d, vel = W.particles(w)
+    fine = W.fine_fields(w)
+    cfg = cfg_for(cpl, w, pos.shape[0])
+    print(f"case cube8_ngp_fp64 n={pos.shape[0]}", flush=True)
+    g = run_gpu(cpl, torch, cfg, pos, vel, d, fine)
+    o = _oracle(oracle, cpl, w, cfg, pos, vel, d, fine)
+    errs = compare_step(g, o, pos.shape[0], w.grid.nb, w.grid.ratio, box=w.grid.box, fp64=True, label="cube8")
+    print("cube8 fp64 e_max:", {k: f"{v:.2e}" for k, v in errs.items()})
+    assert max(errs.values()) < 1e-10
+
+
+SMALL = [
+    # (nb, ratio, box, n, precision, deposit, vel_source)
+    ((5, 3, 4), 4, (1.0, 0.75, 1.25), 777, "fp32k", "cic", "fine"),
+    ((5, 3, 4), 4, (1.0, 0.75, 1.25), 777, "fp64", "cic", "bulk"),
+    ((7, 6, 5), 2, (0.7, 0.6, 0.5), 5000, "fp32n", "cic", "fine"),
+    ((9, 4, 3), 1, (0.9, 0.4, 0.3), 4097, "fp32k", "ngp", "bulk"),
+    ((70, 3, 2), 4, (1.0, 0.05, 0.04), 9001, "fp32k", "cic", "fine"),
+    ((1, 1, 1), 4, (1.0, 1.0, 1.0), 300, "fp64", "cic", "fine"),
+    ((1, 5, 1), 2, (0.3, 1.0, 0.2), 300, "fp32k", "cic", "bulk"),
+    ((130, 1, 3), 4, (2.0, 0.01, 0.05), 12345, "fp32k", "ngp", "fine"),
+    ((33, 17, 9), 4, (1.0, 0.5, 0.25), 70000, "fp32k", "cic", "fine"),
+]
+
+
+@pytest.mark.parametrize("case", SMALL, ids=[f"{c[0]}-r{c[1]}-n{c[3]}-{c[4]}-{c[5]}-{c[6]}" for c in SMALL])
+def test_small_random(env, case):
+    torch, cpl, oracle = env
+    nb, r, box, n, prec, dep, src = case
+    precision = {"fp32k": cpl.COUPLE_FP32_KAHAN, "fp32n": cpl.COUPLE_FP32_NAIVE, "fp64": cpl.COUPLE_FP64}[prec]
+    w = W.small_workload(nb=nb, ratio=r, box=box, n=n, seed=100 + SMALL.index(case),
+                         precision="fp64" if prec == "fp64" else "fp32", deposit=dep)
+    pos, d, vel = W.particles(w)
+    fine = W.fine_fields(w)
+    cfg = cfg_for(cpl, w, n, precision=precision, vel_source={"fine": 0, "bulk": 1}[src])
+    print(f"case small {case}", flush=True)
+    g = run_gpu(cpl, torch, cfg, pos, vel, d, fine)
+    o = _oracle(oracle, cpl, w, cfg, pos, vel, d, fine)
+    errs = compare_step(g, o, n, w.grid.nb, w.grid.ratio, box=w.grid.box, fp64=prec == "fp64", label=str(case), naive=prec == "fp32n")
+    print("e_max:", {k: f"{v:.2e}" for k, v in errs.items()})
+
+
+def test_edge_positions_faces_walls_outside(env):
+    """Particles exactly on bulk faces, on the walls, at x = L, outside the box and
+    non-finite: binning is bit-exact and outside particles are counted."""
+    torch, cpl, oracle = env
+    w = W.small_workload(nb=(4, 3, 5), ratio=4, box=(1.0, 0.75, 1.25), n=64, seed=1, precision="fp32")
+    pos, d, vel = W.particles(w)
+    h = np.array(w.grid.box) / np.array(w.grid.nb)
+    k = 0
+    for a in range(3):
+        for i in range(w.grid.nb[a] + 1):
+            pos[k, a] = np.float32(i * h[a])
+            k += 1
+    pos[k] = [-0.01, 0.2, 0.2]
+    pos[k + 1] = [1.5, 0.2, 5.0]
+    pos[k + 2] = [np.nan, 0.3, 0.3]
+    pos[k + 3] = [0.3, np.inf, 0.3]
+    pos[k + 4] = np.array(w.grid.box, dtype=np.float32)
+    pos[k + 5] = 0.0
+    cfg = cfg_for(cpl, w, pos.shape[0])
+    print("case edge positions", flush=True)
+    g = run_gpu(cpl, torch, cfg, pos, vel, d, W.fine_fields(w))
+    o = _oracle(oracle, cpl, w, cfg, pos, vel, d, W.fine_fields(w))
+    assert o["diag"]["n_outside"] == 4
+    compare_step(g, o, pos.shape[0], w.grid.nb, w.grid.ratio, box=w.grid.box, fp64=False, label="edges")
+
+
+def test_all_particles_in_one_cell_and_empty_cells(env):
+    """A degenerate distribution: 20,000 particles in one bulk cell (one huge
+    segment, every other cell empty)."""
+    torch, cpl, oracle = env
+    w = W.small_workload(nb=(16, 16, 16), ratio=2, box=(1.0, 1.0, 1.0), n=20000, seed=2, precision="fp32")
+    pos, d, vel = W.particles(w)
+    pos = (0.5 + pos / 64.0).astype(np.float32)   # inside cell (8, 8, 8)
+    cfg = cfg_for(cpl, w, pos.shape[0])
+    print("case one cell", flush=True)
+    g = run_gpu(cpl, torch, cfg, pos, vel, d, W.fine_fields(w))
+    o = _oracle(oracle, cpl, w, cfg, pos, vel, d, W.fine_fields(w))
+    compare_step(g, o, pos.shape[0], w.grid.nb, w.grid.ratio, box=w.grid.box, fp64=False, label="one-cell")
+
+
+def test_zero_particles(env):
+    torch, cpl, oracle = env
+    w = W.small_workload(nb=(6, 5, 4), ratio=4, n=0, seed=3, precision="fp32")
+    pos, d, vel = (np.zeros((0, 3), np.float32), np.zeros(0, np.float32), np.zeros((0, 3), np.float32))
+    cfg = cfg_for(cpl, w, 0)
+    print("case zero particles", flush=True)
+    g = run_gpu(cpl, torch, cfg, pos, vel, d, W.fine_fields(w))
+    o = _oracle(oracle, cpl, w, cfg, pos, vel, d, W.fine_fields(w))
+    compare_step(g, o, 0, w.grid.nb, w.grid.ratio, box=w.grid.box, fp64=False, label="zero")
+    assert np.all(g["bulk_phi"] == 0) and np.all(g["fine_F"] == 0)
+    np.testing.assert_allclose(g["fine_eps"], 1.0, atol=1e-7)
+
+
+def test_determinism_bitwise(env):
+    """Two runs of the same step give identical bytes (no float atomics)."""
+    torch, cpl, oracle = env
+    w = W.small_workload(nb=(33, 17, 9), ratio=4, box=(1.0, 0.5, 0.25), n=50000, seed=4, precision="fp32")
+    pos, d, vel = W.particles(w)
+    fine = W.fine_fields(w)
+    cfg = cfg_for(cpl, w, pos.shape[0])
+    print("case determinism", flush=True)
+    a = run_gpu(cpl, torch, cfg, pos, vel, d, fine)
+    b = run_gpu(cpl, torch, cfg, pos, vel, d, fine)
+    for k in ("cell", "perm", "count", "start", "drag", "beta", "bulk_phi", "bulk_F", "bulk_U", "bulk_P",
+              "bulk_G", "fine_eps", "fine_F", "diag"):
+        assert np.array_equal(a[k].view(np.uint8), b[k].view(np.uint8)), k
+
+
+def test_shuffled_input_order(env):
+    """Permuting the input particles permutes the particle outputs and leaves
+    every grid output bit-identical once ids are carried through."""
+    torch, cpl, oracle = env
+    w = W.small_workload(nb=(12, 10, 8), ratio=4, box=(1.2, 1.0, 0.8), n=30000, seed=5, precision="fp32")
+    pos, d, vel = W.particles(w)
+    fine = W.fine_fields(w)
+    cfg = cfg_for(cpl, w, pos.shape[0])
+    print("case shuffled order", flush=True)
+    a = run_gpu(cpl, torch, cfg, pos, vel, d, fine)
+    sh = np.random.default_rng(0).permutation(pos.shape[0])
+    b = run_gpu(cpl, torch, cfg, pos[sh], vel[sh], d[sh], fine)
+    np.testing.assert_array_equal(b["cell"], a["cell"][sh])
+    np.testing.assert_allclose(b["drag"], a["drag"][sh], rtol=1e-5, atol=1e-6 * np.abs(a["drag"]).max())
+    np.testing.assert_array_equal(b["count"], a["count"])
+    # grid sums differ only by the within-cell order of the particles (ids changed)
+    for k in ("bulk_phi", "bulk_F", "fine_eps", "fine_F"):
+        assert np.abs(b[k] - a[k]).max() <= 1e-5 * max(np.abs(a[k]).max(), 1e-30), k
+
+
+def test_capacity_and_null_errors(env):
+    torch, cpl, oracle = env
+    cfg = cpl.Config(nb=(4, 4, 4), ratio=2, max_particles=10)
+    c = cpl.Coupler(cfg)
+    dev = "cuda:0"
+    pos = torch.rand(11, 3, device=dev)
+    fine = [torch.zeros(8, 8, 8, device=dev) for _ in range(4)]
+    with pytest.raises(cpl.CoupleError) as e:
+        c.step(pos, pos.clone(), torch.full((11,), 0.01, device=dev), fine)
+    assert e.value.code == cpl.COUPLE_ECAPACITY
+    out = cpl.alloc_outputs(cfg, 5, device=dev)
+    out["fine_F"] = None
+    with pytest.raises(cpl.CoupleError) as e:
+        cpl.couple_step(c.h, {"n": 5, "pos": pos, "vel": pos, "diam": pos, "fine_u": fine[0], "fine_v": fine[1],
+                              "fine_w": fine[2], "fine_p": fine[3]}, out)
+    assert e.value.code == cpl.COUPLE_EINVAL
+    c.close()
+
+
+def test_cube64_cic_one_step_full(env):
+    """The 2M-particle, 64^3 / 256^3 workload, one step, every output compared."""
+    torch, cpl, oracle = env
+    w = W.WORKLOADS["cube64_cic"]
+    pos, d, vel = W.particles(w)
+    fine = W.fine_fields(w)
+    cfg = cfg_for(cpl, w, pos.shape[0], advect=False)
+    print("case cube64 one step", flush=True)
+    g = run_gpu(cpl, torch, cfg, pos, vel, d, fine)
+    o = _oracle(oracle, cpl, w, cfg, pos, vel, d, fine)
+    errs = compare_step(g, o, pos.shape[0], w.grid.nb, w.grid.ratio, box=w.grid.box, fp64=False, label="cube64")
+    print("cube64 e_max:", {k: f"{v:.2e}" for k, v in errs.items()})
