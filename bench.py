@@ -27,14 +27,16 @@ METRIC = "coupling particle-steps/s, plain vs MLP path at 1e-3 rel err; % HBM pe
 def kernel_alg_bytes(name, n, ncell, nfine, fsz):
     """Algorithmic (compulsory) bytes of one launch of the named kernel.
 
-    restrict_lookup_drag: fine u,v,w,p read once (4 fsz per fine cell); U, P
-        written (4 fsz per bulk cell); per particle position+diameter+velocity
-        read (7 fsz), drag+beta written (4 fsz) and its id read (4 B).
-    prolong: eps and F_fpi written on the fine grid (4 fsz per fine cell);
-        phi and F_fpi read on the bulk grid (4 fsz per bulk cell).
+    restrict_lookup: fine u, v, w, p read once (4 fsz per fine cell); U, P
+        written (4 fsz per bulk cell); per particle the sorted position and
+        diameter read (4 fsz) and the sampled fluid velocity and void fraction
+        written (4 fsz).
+    restrict: the same without the particles.
+    prolong: eps and F_fpi written on the fine grid (4 fsz per fine cell); phi
+        and F_fpi read on the bulk grid (4 fsz per bulk cell).
     """
-    if name == "restrict_lookup_drag":
-        return 4 * fsz * nfine + 4 * fsz * ncell + n * (11 * fsz + 4)
+    if name == "restrict_lookup":
+        return 4 * fsz * nfine + 4 * fsz * ncell + n * 8 * fsz
     if name == "restrict":
         return 4 * fsz * nfine + 4 * fsz * ncell
     if name == "prolong":
@@ -102,6 +104,8 @@ def main():
     ap.add_argument("--workload", default="bed128_cic")
     ap.add_argument("--cpu-frac", type=float, default=0.25, help="x-y fraction of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--vel-source", default="fine", choices=["fine", "bulk"],
+                    help="fluid velocity at the particles: fine-grid lookup (default) or bulk trilinear")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the coupling exchange is built and timed for a single "
@@ -131,7 +135,8 @@ def main():
     cfg = cpl.Config(box=g.box, nb=g.nb, ratio=g.ratio, rho_f=w.rho_f, mu_f=w.mu_f, rho_p=w.rho_p,
                      eps_min=w.eps_min, deposit=cpl.COUPLE_CIC if w.deposit == "cic" else cpl.COUPLE_NGP,
                      precision=cpl.COUPLE_FP64 if fp64 else cpl.COUPLE_FP32_KAHAN,
-                     vel_source=cpl.COUPLE_VEL_FINE, advect=0, max_particles=n)
+                     vel_source=cpl.COUPLE_VEL_FINE if args.vel_source == "fine" else cpl.COUPLE_VEL_BULK,
+                     advect=0, max_particles=n)
     c = cpl.Coupler(cfg)
     out = cpl.alloc_outputs(cfg, n, device=dev)
     for _ in range(args.warmup):
@@ -172,7 +177,7 @@ def main():
         "vs_baseline": None, "dtype": "f64" if fp64 else "f32", "data": "synthetic",
         "config": {"workload": (f"{w.name}: {n} particles, box {g.box}, bulk {g.nb}, fine {g.nf}, "
                                 f"{w.deposit.upper()}, {'FP64' if fp64 else 'FP32 + Kahan, FP64 sums'}, "
-                                "fine-grid velocity lookup"),
+                                f"{args.vel_source}-grid velocity at the particles"),
                    "n_particles": n, "bulk": list(g.nb), "fine": list(g.nf)},
         "roofline": roof,
         "step_alg_bytes": sb, "step_alg_GBps": round(sb / (ms_step * 1e-3) / 1e9, 1),

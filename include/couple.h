@@ -91,7 +91,7 @@ enum {
 
 typedef struct couple_config {
     double  box[3];          /* Lx, Ly, Lz > 0                                              */
-    int32_t nb[3];           /* bulk cells per axis, >= 1, product < 2^31 / ratio^3          */
+    int32_t nb[3];           /* bulk cells per axis, >= 1, nb[0] <= 32767, product < 2^31    */
     int32_t ratio;           /* fine cells per bulk cell per axis: 1, 2 or 4                  */
     double  rho_f, mu_f;     /* fluid density and viscosity (> 0)                            */
     double  rho_p;           /* particle density (> 0), used by the advection                */

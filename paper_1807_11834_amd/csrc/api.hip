@@ -16,7 +16,7 @@ struct couple_handle {
     int64_t ncell = 0, nfine = 0;
     int64_t part_stride = 0;
     SortScratch sort{};
-    void *sp = nullptr, *sv = nullptr, *sf = nullptr, *plo = nullptr;
+    void *sp = nullptr, *uf4 = nullptr, *plo = nullptr, *dep = nullptr;
     double *part = nullptr;
     // per-kernel timing
     Marker mk;
@@ -42,11 +42,11 @@ static void destroy_events(couple_handle *h) {
 static void release(couple_handle *h) {
     destroy_events(h);
     void *ptrs[] = {h->sort.keys_a, h->sort.keys_b, h->sort.vals_a, h->sort.vals_b, h->sort.hist,
-                    h->sort.totals, h->sp, h->sv, h->sf, h->plo, h->part};
+                    h->sort.totals, h->sp, h->uf4, h->plo, h->dep, h->part};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     h->sort = SortScratch{};
-    h->sp = h->sv = h->sf = h->plo = nullptr;
+    h->sp = h->uf4 = h->plo = h->dep = nullptr;
     h->part = nullptr;
 }
 
@@ -56,6 +56,7 @@ static std::string validate(const couple_config *c) {
         if (c->nb[a] < 1) return "nb must be >= 1 on every axis";
     }
     if (!(c->ratio == 1 || c->ratio == 2 || c->ratio == 4)) return "ratio must be 1, 2 or 4";
+    if (c->nb[0] > 32767) return "nb[0] must be <= 32767 (x-stencil nodes are packed in 16 bits)";
     const int64_t ncell = (int64_t)c->nb[0] * c->nb[1] * c->nb[2];
     if (ncell >= (int64_t(1) << 31) - 1) return "too many bulk cells (must be < 2^31 - 1)";
     const int64_t r3 = (int64_t)c->ratio * c->ratio * c->ratio;
@@ -105,13 +106,18 @@ extern "C" int couple_init(const couple_config *cfg, couple_handle **out) {
     const size_t fsz = (cfg->precision == COUPLE_FP64) ? sizeof(double) : sizeof(float);
     const int64_t ntile = sort_tiles(nmax > 0 ? nmax : 1);
     const int64_t pblk = (nmax + kBlock - 1) / kBlock, cblk = (h->ncell + kBlock - 1) / kBlock;
-    h->part_stride = (pblk > cblk ? pblk : cblk);
-    if (h->part_stride < ntile) h->part_stride = ntile;
-    if (h->part_stride < 1) h->part_stride = 1;
+    // one FP64 partial per workgroup and slot: the stride covers the largest
+    // grid of any kernel that writes partials
+    const int64_t dblk = deposit_blocks(cfg->nb, h->ncell, cfg->deposit == COUPLE_CIC);
+    h->part_stride = 1;
+    for (int64_t b : {pblk, cblk, ntile, dblk})
+        if (b > h->part_stride) h->part_stride = b;
     bool ok = dev_alloc(&h->sort.keys_a, sizeof(uint32_t) * nmax) && dev_alloc(&h->sort.keys_b, sizeof(uint32_t) * nmax) &&
               dev_alloc(&h->sort.vals_a, sizeof(uint32_t) * nmax) && dev_alloc(&h->sort.vals_b, sizeof(uint32_t) * nmax) &&
               dev_alloc(&h->sort.hist, sizeof(uint32_t) * 256 * ntile) && dev_alloc(&h->sort.totals, sizeof(uint32_t) * 256) &&
-              dev_alloc(&h->sp, 4 * fsz * nmax) && dev_alloc(&h->sv, 4 * fsz * nmax) && dev_alloc(&h->sf, 4 * fsz * nmax) && dev_alloc(&h->plo, fsz * h->ncell) &&
+              dev_alloc(&h->sp, 4 * fsz * nmax) && dev_alloc(&h->uf4, 4 * fsz * nmax) &&
+              dev_alloc(&h->plo, fsz * h->ncell) &&
+              dev_alloc(&h->dep, (cfg->deposit == COUPLE_CIC ? 27 : 1) * fsz * h->ncell) &&
               dev_alloc(&h->part, sizeof(double) * SL_COUNT * h->part_stride);
     if (!ok) {
         release(h);
@@ -189,9 +195,9 @@ static int step_impl(couple_handle *h, const couple_inputs *in, couple_outputs *
     a.fine_F = (T *)out->fine_F;
     a.diag = out->diag;
     a.sp = (vec4<T> *)h->sp;
-    a.sv = (vec4<T> *)h->sv;
-    a.sf = (vec4<T> *)h->sf;
+    a.uf4 = (vec4<T> *)h->uf4;
     a.Plo = (T *)h->plo;
+    a.dep_partial = (T *)h->dep;
     a.part = h->part;
     a.part_stride = h->part_stride;
     a.mk = &h->mk;

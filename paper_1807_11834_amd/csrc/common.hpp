@@ -103,13 +103,37 @@ template <typename T> __device__ __forceinline__ int cell_axis(T x, T s, int n) 
     return clampi((int)dfloor(x * s), n);
 }
 
-// Workgroup -> logical tile so that consecutive tiles share an XCD (its L2):
-// workgroups are dealt round-robin over the 8 XCDs of the device.
+// Segment bounds read from `start` (a prefix sum over [0, n]) clamped into
+// [0, n]: a no-op for a consistent `start`, it keeps every load in bounds.
+__device__ __forceinline__ int32_t seg_clamp(int32_t v, int64_t n) { return v < 0 ? 0 : (v > n ? (int32_t)n : v); }
+
+__device__ __forceinline__ void decode_cell(int64_t c, const int nb[3], int &cx, int &cy, int &cz) {
+    cx = (int)(c % nb[0]);
+    cy = (int)((c / nb[0]) % nb[1]);
+    cz = (int)(c / ((int64_t)nb[0] * nb[1]));
+}
+
+// LDS written by some lanes of a wave and read by other lanes of the same wave:
+// order the accesses without a workgroup barrier.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Workgroup -> logical tile.  Workgroups are dealt round-robin over the 8 XCDs
+// (each with its own L2).  XCD x takes chunks of kXcdChunk consecutive tiles,
+// and the chunks of the 8 XCDs interleave over the domain: neighbouring tiles
+// share an L2, while a dense region (the packed bed) is spread over all XCDs.
+// The final partial round of chunks keeps the identity mapping (a bijection).
+constexpr int64_t kXcdChunk = 16;
 __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nblk) {
-    const int64_t nx = 8;
-    int64_t q = nblk / nx, r = nblk % nx;
-    int64_t x = b % nx, k = b / nx;
-    return x * q + (x < r ? x : r) + k;
+    const int64_t nx = 8, round = nx * kXcdChunk;
+    const int64_t full = (nblk / round) * round;
+    if (b >= full) return b;
+    const int64_t x = b % nx, k = b / nx;          // k-th workgroup dealt to XCD x
+    const int64_t q = k / kXcdChunk, r = k % kXcdChunk;
+    return (q * nx + x) * kXcdChunk + r;
 }
 
 // ---- wave / block reductions (fixed tree order -> deterministic) -----------

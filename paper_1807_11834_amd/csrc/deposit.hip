@@ -1,0 +1,337 @@
+// deposit.hip -- particle -> bulk-cell deposition of the solid volume fraction
+// and of the momentum source, deterministic and without atomics.
+//
+//   phi_c   = sum_p w_pc V_p / V_b                 (porosity eps = 1 - phi)
+//   F_fpi,c = -(1/V_b) sum_p w_pc F_p              (counterpart of the drag)
+//
+// The particles are in the canonical (cell, id) order with CSR offsets `start`.
+// CIC: two passes through per-row partial sums (see below); every particle is
+// staged once per pass.  NGP: one thread per cell sums its own segment.
+#include <type_traits>
+
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace cpl {
+
+constexpr int kChunk = 256;   // particles staged per wave and chunk
+
+template <typename T> __device__ __forceinline__ T vol_over_vb(T d, T inv_vb) {
+    return (T(kPi / 6.0) * d * d * d) * inv_vb;
+}
+
+// Bulk pressure gradient: central differences, one-sided at the walls, taken in
+// FP64 of the compensated pressure hi + lo (differencing the rounded hi alone
+// would lose ulp(P)/h).
+template <typename T>
+__device__ __forceinline__ void write_gradient(int64_t c, int cx, int cy, int cz, const Geo<T> &g,
+                                               const T *__restrict__ P, const T *__restrict__ Plo,
+                                               T *__restrict__ G) {
+    const int idx[3] = {cx, cy, cz};
+    const int64_t stride[3] = {1, g.nb[0], (int64_t)g.nb[0] * g.nb[1]};
+    auto pv = [&](int64_t k) { return (double)P[k] + (double)Plo[k]; };
+    for (int a = 0; a < 3; ++a) {
+        double gr;
+        const int nax = g.nb[a];
+        const double h = (double)g.hb[a];
+        if (nax == 1) gr = 0.0;
+        else if (idx[a] == 0) gr = (pv(c + stride[a]) - pv(c)) / h;
+        else if (idx[a] == nax - 1) gr = (pv(c) - pv(c - stride[a])) / h;
+        else gr = (pv(c + stride[a]) - pv(c - stride[a])) / (2.0 * h);
+        G[a * g.ncell + c] = (T)gr;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// NGP (containing cell)
+// ---------------------------------------------------------------------------
+template <typename T, bool KAHAN, bool FORCE>
+__global__ __launch_bounds__(kBlock) void k_deposit_ngp(const int32_t *__restrict__ start,
+                                                        const vec4<T> *__restrict__ sp,
+                                                        const int32_t *__restrict__ perm,
+                                                        const T *__restrict__ drag, int64_t n, Geo<T> g,
+                                                        const T *__restrict__ P, const T *__restrict__ Plo,
+                                                        T *__restrict__ out, T *__restrict__ G,
+                                                        double *__restrict__ part, int64_t ps) {
+    __shared__ double red[kWavesPerBlock];
+    const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double v[3] = {0.0, 0.0, 0.0};
+    if (c < g.ncell) {
+        const int32_t s = seg_clamp(start[c], n), e = seg_clamp(start[c + 1], n);
+        if constexpr (!FORCE) {
+            Acc<T, KAHAN> acc;
+            for (int32_t p = s; p < e; ++p) acc.add(vol_over_vb(sp[p].w, g.inv_vb));
+            out[c] = acc.s;
+            v[0] = (double)acc.s;
+        } else {
+            Acc<T, KAHAN> ax, ay, az;
+            for (int32_t p = s; p < e; ++p) {
+                int64_t id = perm[p];
+                if (id < 0 || id >= n) id = 0;
+                ax.add(drag[3 * id + 0]);
+                ay.add(drag[3 * id + 1]);
+                az.add(drag[3 * id + 2]);
+            }
+            const T fx = -ax.s * g.inv_vb, fy = -ay.s * g.inv_vb, fz = -az.s * g.inv_vb;
+            out[c] = fx;
+            out[g.ncell + c] = fy;
+            out[2 * g.ncell + c] = fz;
+            v[0] = fx; v[1] = fy; v[2] = fz;
+            int cx, cy, cz;
+            decode_cell(c, g.nb, cx, cy, cz);
+            write_gradient(c, cx, cy, cz, g, P, Plo, G);
+        }
+    }
+    if constexpr (!FORCE) {
+        const double t = block_sum(v[0], red);
+        const double m = block_max(v[0], red);
+        if (threadIdx.x == 0) {
+            part[SL_PHISUM * ps + blockIdx.x] = t;
+            part[SL_MAXPHI * ps + blockIdx.x] = m;
+        }
+    } else {
+        for (int k = 0; k < 3; ++k) {
+            const double t = block_sum(v[k], red);
+            if (threadIdx.x == 0) part[(SL_FB + k) * ps + blockIdx.x] = t;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// CIC (trilinear to the 8 nearest bulk cell centres, folded at the walls)
+// ---------------------------------------------------------------------------
+// Pass 1, k_deposit_rows: one wave per (source row, 64-cell x segment).  The wave
+// stages the particles of the source cells x0-1 .. x0+64 once (in chunks), with
+// their x-stencil, their weights on the three target y-rows and z-rows around the
+// source row and the deposited value(s).  Lane x then accumulates, over the
+// particles of source cells x-1, x, x+1 in canonical order, the contributions to
+// target cell x of the 3 x 3 target rows, and writes them to the partial slot
+// (source offset) of each target cell.
+// Pass 2, k_deposit_sum: per target cell, the 9 partials of its source rows in
+// ascending row order.
+template <typename T, bool FORCE> struct RowStage {
+    int node[kWavesPerBlock][kChunk];                  // x-stencil nodes lo | hi << 16
+    T tx[kWavesPerBlock][kChunk];                      // weight of hi
+    T wy[3][kWavesPerBlock][kChunk];                   // weight on target rows y'-1, y', y'+1
+    T wz[3][kWavesPerBlock][kChunk];                   // weight on target layers z'-1, z', z'+1
+    T val[FORCE ? 3 : 1][kWavesPerBlock][kChunk];      // V_p / V_b, or F_p
+};
+
+template <typename T>
+__device__ __forceinline__ void row_weights(const Axis<T> &a, int c, T w[3]) {
+    for (int j = 0; j < 3; ++j) {
+        const int t = c - 1 + j;
+        T v = T(0);
+        if (a.lo == t) v += T(1) - a.t;
+        if (a.hi == t) v += a.t;
+        w[j] = v;
+    }
+}
+
+template <typename T, bool KAHAN, bool FORCE>
+__global__ __launch_bounds__(kBlock) void k_deposit_rows(const int32_t *__restrict__ start,
+                                                         const vec4<T> *__restrict__ sp,
+                                                         const int32_t *__restrict__ perm,
+                                                         const T *__restrict__ drag, int64_t n, Geo<T> g,
+                                                         T *__restrict__ partial) {
+    constexpr int NC = FORCE ? 3 : 1;
+    __shared__ RowStage<T, FORCE> st;
+    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int nbx = g.nb[0], nby = g.nb[1], nbz = g.nb[2];
+    const int nseg = (nbx + kWave - 1) / kWave;
+    const int64_t nwave = (int64_t)nby * nbz * nseg;
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t gw = tile * kWavesPerBlock + w;        // (source row, segment)
+    if (gw >= nwave) return;                             // wave-uniform; no block barriers below
+    const int64_t row = gw / nseg;
+    const int x0 = (int)(gw % nseg) * kWave;
+    const int ys = (int)(row % nby), zs = (int)(row / nby);
+    const int x = x0 + lane;
+    const bool active = x < nbx;
+    const int64_t srow = row * nbx;
+    const int xa = x0 > 0 ? x0 - 1 : 0;
+    const int xb = (x0 + kWave < nbx ? x0 + kWave : nbx - 1);
+    const int32_t rs = seg_clamp(start[srow + xa], n), re = seg_clamp(start[srow + xb + 1], n);
+    int32_t ls = 0, le = 0;
+    if (active) {
+        ls = seg_clamp(start[srow + (x > 0 ? x - 1 : 0)], n);
+        le = seg_clamp(start[srow + (x < nbx - 1 ? x + 1 : nbx - 1) + 1], n);
+    }
+    Acc<T, KAHAN> acc[3][3][NC];   // [target z][target y][component]
+    for (int32_t cs = rs; cs < re; cs += kChunk) {       // wave-uniform loop
+        const int32_t ce = (cs + kChunk < re) ? cs + kChunk : re;
+        for (int32_t k = lane; k < ce - cs; k += kWave) {
+            const vec4<T> q = sp[cs + k];
+            const Axis<T> ax = cic_axis(q.x, g.sb[0], nbx);
+            const Axis<T> ay = cic_axis(q.y, g.sb[1], nby);
+            const Axis<T> az = cic_axis(q.z, g.sb[2], nbz);
+            st.node[w][k] = ax.lo | (ax.hi << 16);
+            st.tx[w][k] = ax.t;
+            T wy[3], wz[3];
+            row_weights(ay, ys, wy);
+            row_weights(az, zs, wz);
+            for (int j = 0; j < 3; ++j) {
+                st.wy[j][w][k] = wy[j];
+                st.wz[j][w][k] = wz[j];
+            }
+            if constexpr (FORCE) {
+                int64_t id = perm[cs + k];
+                if (id < 0 || id >= n) id = 0;   // perm is a permutation of [0, n)
+                st.val[0][w][k] = drag[3 * id + 0];
+                st.val[1][w][k] = drag[3 * id + 1];
+                st.val[2][w][k] = drag[3 * id + 2];
+            } else {
+                st.val[0][w][k] = vol_over_vb(q.w, g.inv_vb);
+            }
+        }
+        wave_sync();
+        const int32_t b0 = (ls > cs ? ls : cs) - cs, b1 = (le < ce ? le : ce) - cs;
+        for (int32_t k = b0; k < b1; ++k) {
+            const int nd = st.node[w][k];
+            const T t = st.tx[w][k];
+            T wx = T(0);
+            if ((nd & 0xffff) == x) wx += T(1) - t;
+            if ((nd >> 16) == x) wx += t;
+            if (wx == T(0)) continue;
+            T v[NC];
+            for (int c = 0; c < NC; ++c) v[c] = wx * st.val[c][w][k];
+            T wy[3], wz[3];
+            for (int j = 0; j < 3; ++j) {
+                wy[j] = st.wy[j][w][k];
+                wz[j] = st.wz[j][w][k];
+            }
+#pragma unroll
+            for (int kz = 0; kz < 3; ++kz) {
+                if (wz[kz] == T(0)) continue;
+#pragma unroll
+                for (int jy = 0; jy < 3; ++jy) {
+                    const T wyz = wy[jy] * wz[kz];
+                    if (wyz == T(0)) continue;
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) acc[kz][jy][c].add(wyz * v[c]);
+                }
+            }
+        }
+        wave_sync();
+    }
+    if (!active) return;
+#pragma unroll
+    for (int kz = 0; kz < 3; ++kz) {
+        const int tz = zs - 1 + kz;
+        if (tz < 0 || tz >= nbz) continue;
+#pragma unroll
+        for (int jy = 0; jy < 3; ++jy) {
+            const int ty = ys - 1 + jy;
+            if (ty < 0 || ty >= nby) continue;
+            // slot = source offset from the target: (zs - tz + 1) * 3 + (ys - ty + 1)
+            const int slot = (2 - kz) * 3 + (2 - jy);
+            const int64_t tc = ((int64_t)tz * nby + ty) * nbx + x;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) partial[((int64_t)slot * NC + c) * g.ncell + tc] = acc[kz][jy][c].s;
+        }
+    }
+}
+
+template <typename T, bool KAHAN, bool FORCE>
+__global__ __launch_bounds__(kBlock) void k_deposit_sum(const T *__restrict__ partial, Geo<T> g,
+                                                        const T *__restrict__ P, const T *__restrict__ Plo,
+                                                        T *__restrict__ out, T *__restrict__ G,
+                                                        double *__restrict__ part, int64_t ps) {
+    constexpr int NC = FORCE ? 3 : 1;
+    __shared__ double red[kWavesPerBlock];
+    const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double v[3] = {0.0, 0.0, 0.0};
+    if (c < g.ncell) {
+        int cx, cy, cz;
+        decode_cell(c, g.nb, cx, cy, cz);
+        Acc<T, KAHAN> acc[NC];
+        for (int dz = -1; dz <= 1; ++dz) {
+            if (cz + dz < 0 || cz + dz >= g.nb[2]) continue;
+            for (int dy = -1; dy <= 1; ++dy) {
+                if (cy + dy < 0 || cy + dy >= g.nb[1]) continue;
+                const int slot = (dz + 1) * 3 + (dy + 1);
+                for (int k = 0; k < NC; ++k) acc[k].add(partial[((int64_t)slot * NC + k) * g.ncell + c]);
+            }
+        }
+        if constexpr (FORCE) {
+            const T fx = -acc[0].s * g.inv_vb, fy = -acc[1].s * g.inv_vb, fz = -acc[2].s * g.inv_vb;
+            out[c] = fx;
+            out[g.ncell + c] = fy;
+            out[2 * g.ncell + c] = fz;
+            v[0] = fx; v[1] = fy; v[2] = fz;
+            write_gradient(c, cx, cy, cz, g, P, Plo, G);
+        } else {
+            out[c] = acc[0].s;
+            v[0] = (double)acc[0].s;
+        }
+    }
+    if constexpr (!FORCE) {
+        const double t = block_sum(v[0], red);
+        const double m = block_max(v[0], red);
+        if (threadIdx.x == 0) {
+            part[SL_PHISUM * ps + blockIdx.x] = t;
+            part[SL_MAXPHI * ps + blockIdx.x] = m;
+        }
+    } else {
+        for (int k = 0; k < 3; ++k) {
+            const double t = block_sum(v[k], red);
+            if (threadIdx.x == 0) part[(SL_FB + k) * ps + blockIdx.x] = t;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+int deposit_blocks(const int nb[3], int64_t ncell, int cic) {
+    (void)nb;
+    (void)cic;
+    return (int)((ncell + kBlock - 1) / kBlock);   // NGP kernel and CIC pass 2
+}
+
+static int row_blocks(const int nb[3]) {
+    const int64_t nseg = (nb[0] + kWave - 1) / kWave;
+    const int64_t nwave = (int64_t)nb[1] * nb[2] * nseg;
+    return (int)((nwave + kWavesPerBlock - 1) / kWavesPerBlock);
+}
+
+template <typename T, bool KAHAN> int launch_deposit_phi(const StepArgs<T> &a, hipStream_t st) {
+    const int nblk = deposit_blocks(a.g.nb, a.g.ncell, a.cic);
+    if (a.cic) {
+        hipLaunchKernelGGL((k_deposit_rows<T, KAHAN, false>), dim3(row_blocks(a.g.nb)), dim3(kBlock), 0, st, a.start,
+                           a.sp, a.perm, a.drag, a.n, a.g, a.dep_partial);
+        a.mk->mark("deposit_phi_sum", st);
+        hipLaunchKernelGGL((k_deposit_sum<T, KAHAN, false>), dim3(nblk), dim3(kBlock), 0, st, a.dep_partial, a.g, a.P,
+                           a.Plo, a.phi, a.G, a.part, a.part_stride);
+    } else {
+        hipLaunchKernelGGL((k_deposit_ngp<T, KAHAN, false>), dim3(nblk), dim3(kBlock), 0, st, a.start, a.sp, a.perm,
+                           a.drag, a.n, a.g, a.P, a.Plo, a.phi, a.G, a.part, a.part_stride);
+    }
+    return nblk;
+}
+
+template <typename T, bool KAHAN> int launch_deposit_force(const StepArgs<T> &a, hipStream_t st) {
+    const int nblk = deposit_blocks(a.g.nb, a.g.ncell, a.cic);
+    if (a.cic) {
+        hipLaunchKernelGGL((k_deposit_rows<T, KAHAN, true>), dim3(row_blocks(a.g.nb)), dim3(kBlock), 0, st, a.start,
+                           a.sp, a.perm, a.drag, a.n, a.g, a.dep_partial);
+        a.mk->mark("deposit_force_sum", st);
+        hipLaunchKernelGGL((k_deposit_sum<T, KAHAN, true>), dim3(nblk), dim3(kBlock), 0, st, a.dep_partial, a.g, a.P,
+                           a.Plo, a.F, a.G, a.part, a.part_stride);
+    } else {
+        hipLaunchKernelGGL((k_deposit_ngp<T, KAHAN, true>), dim3(nblk), dim3(kBlock), 0, st, a.start, a.sp, a.perm,
+                           a.drag, a.n, a.g, a.P, a.Plo, a.F, a.G, a.part, a.part_stride);
+    }
+    return nblk;
+}
+
+template int launch_deposit_phi<float, true>(const StepArgs<float> &, hipStream_t);
+template int launch_deposit_phi<float, false>(const StepArgs<float> &, hipStream_t);
+template int launch_deposit_phi<double, true>(const StepArgs<double> &, hipStream_t);
+template int launch_deposit_phi<double, false>(const StepArgs<double> &, hipStream_t);
+template int launch_deposit_force<float, true>(const StepArgs<float> &, hipStream_t);
+template int launch_deposit_force<float, false>(const StepArgs<float> &, hipStream_t);
+template int launch_deposit_force<double, true>(const StepArgs<double> &, hipStream_t);
+template int launch_deposit_force<double, false>(const StepArgs<double> &, hipStream_t);
+
+}  // namespace cpl

@@ -66,9 +66,9 @@ template <typename T> struct StepArgs {
     double *diag;
     // scratch
     vec4<T> *sp;     // sorted particles (x, y, z, d)
-    vec4<T> *sv;     // sorted velocity
-    vec4<T> *sf;     // sorted drag
+    vec4<T> *uf4;    // per particle (input order): fluid velocity and void fraction
     T *Plo;          // [ncell] low word of the restricted pressure (Kahan compensation)
+    T *dep_partial;  // [9][3][ncell] per-source-row partial sums of the CIC deposition
     double *part;    // [SL_COUNT][max_blocks]
     int64_t part_stride;
     Marker *mk;      // per-kernel event recording (never null)
@@ -76,5 +76,11 @@ template <typename T> struct StepArgs {
 
 // Stage launchers (in order of the step).
 template <typename T> hipError_t launch_stages(const StepArgs<T> &a, hipStream_t st);
+
+// Deposition (deposit.hip); each returns the number of workgroups launched
+// (one FP64 partial per workgroup and diagnostic slot).
+template <typename T, bool KAHAN> int launch_deposit_phi(const StepArgs<T> &a, hipStream_t st);
+template <typename T, bool KAHAN> int launch_deposit_force(const StepArgs<T> &a, hipStream_t st);
+int deposit_blocks(const int nb[3], int64_t ncell, int cic);
 
 }  // namespace cpl

@@ -1,23 +1,21 @@
-// stages.hip -- deposition, restriction, particle gather + drag, momentum
-// source, prolongation and the FP64 conservation sums of one coupling step.
+// stages.hip -- restriction, particle sampling, drag, prolongation and the FP64
+// conservation sums of one coupling step (deposition is in deposit.hip).
 //
 // Kernel order on the caller's stream (after binning/sorting, sort.hip):
 //
-//   k_gather       sorted copies of the particle data: sp = (x,y,z,d) clamped
-//                  into the box, sv = velocity; FP64 partial sums of V_p.
-//   k_deposit_phi  one thread per bulk cell gathers the particles of the 27
-//                  (CIC) or 1 (NGP) neighbouring cells from the sorted order, in
-//                  ascending (cell, id), into a compensated FP32 (or FP64) sum:
-//                  phi_c = sum_p w_pc V_p / V_b.  Deterministic, no atomics.
+//   k_gather       sorted copy sp = (x, y, z, d) of the particles, clamped into
+//                  the box.
+//   deposit phi    (deposit.hip)
 //   k_restrict     one thread per bulk cell streams its r^3 fine children of
 //                  u, v, w, p (one 16-byte row load per (z, y) child row for
 //                  r = 4) and writes the compensated averages U, P.  With the
-//                  fine-grid velocity source the same wave then evaluates the
-//                  drag of the particles in its 64 cells while their fine rows
-//                  are still in L2 (the fine lookup costs no extra HBM pass).
-//   k_particles    drag for the bulk-velocity and given-velocity sources.
-//   k_deposit_force F_fpi,c = -(1/V_b) sum_p w_pc F_p (same gather as phi) and
-//                  the bulk pressure gradient.
+//                  fine-grid velocity source the same wave then samples the
+//                  particles of its 64 cells (fine trilinear velocity, void
+//                  fraction) while their fine rows are still in L2: the fine
+//                  lookup costs no extra pass over the fine grid.
+//   k_sample       the same sampling for the bulk and given velocity sources.
+//   k_drag         drag and explicit Euler advection in input order (coalesced).
+//   deposit force  (deposit.hip), with the bulk pressure gradient.
 //   k_prolong      one thread per bulk cell writes its r^3 fine children of
 //                  eps and F_fpi: conservative trilinear T_f + D_c with the
 //                  27-neighbour values held in registers.
@@ -75,12 +73,9 @@ template <typename T, int R> __device__ __forceinline__ void store_row(T *__rest
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_gather(const int32_t *__restrict__ perm, const T *__restrict__ pos,
-                                                   const T *__restrict__ vel, const T *__restrict__ diam,
-                                                   int64_t n, Geo<T> g, vec4<T> *__restrict__ sp,
-                                                   vec4<T> *__restrict__ sv, double *__restrict__ part_vtot) {
-    __shared__ double red[kWavesPerBlock];
-    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    double vp = 0.0;
+                                                   const T *__restrict__ diam, int64_t n, Geo<T> g,
+                                                   vec4<T> *__restrict__ sp) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i < n) {
         int64_t p = perm[i];
         if (p < 0 || p >= n) p = 0;   // perm is a permutation of [0, n); guards the loads
@@ -91,164 +86,6 @@ __global__ __launch_bounds__(kBlock) void k_gather(const int32_t *__restrict__ p
         q.z = clamp_coord(pos[3 * p + 2], g.L[2], o);
         q.w = diam[p];
         sp[i] = q;
-        vec4<T> v;
-        v.x = vel[3 * p + 0];
-        v.y = vel[3 * p + 1];
-        v.z = vel[3 * p + 2];
-        v.w = T(0);
-        sv[i] = v;
-        double d = (double)q.w;
-        vp = kPi * d * d * d / 6.0;
-    }
-    double t = block_sum(vp, red);
-    if (threadIdx.x == 0) part_vtot[blockIdx.x] = t;
-}
-
-// ---------------------------------------------------------------------------
-// Deposition gathers.  The particles that can touch bulk cell c sit in the 27
-// cells c + {-1,0,1}^3 (a CIC particle reaches its containing cell and one
-// neighbour per axis).  For each (dz, dy) the 1-3 cells along x are adjacent in
-// the sorted order, so the thread walks 9 contiguous runs in ascending cell
-// order, each in ascending id: the canonical (cell, id) order.
-// ---------------------------------------------------------------------------
-// Segment bounds read from `start` (a prefix sum over [0, n]) clamped into
-// [0, n]: a no-op for a consistent `start`, it keeps every load in bounds.
-__device__ __forceinline__ int32_t seg_lo(int32_t v, int64_t n) { return v < 0 ? 0 : (v > n ? (int32_t)n : v); }
-__device__ __forceinline__ int32_t seg_hi(int32_t v, int64_t n) { return v < 0 ? 0 : (v > n ? (int32_t)n : v); }
-
-template <typename T>
-__device__ __forceinline__ T cic_weight_to(const vec4<T> &q, const Geo<T> &g, int cx, int cy, int cz) {
-    Axis<T> ax = cic_axis(q.x, g.sb[0], g.nb[0]);
-    Axis<T> ay = cic_axis(q.y, g.sb[1], g.nb[1]);
-    Axis<T> az = cic_axis(q.z, g.sb[2], g.nb[2]);
-    return axis_weight(ax, cx) * axis_weight(ay, cy) * axis_weight(az, cz);
-}
-
-template <typename T> __device__ __forceinline__ T vol_over_vb(T d, T inv_vb) {
-    return (T(kPi / 6.0) * d * d * d) * inv_vb;
-}
-
-__device__ __forceinline__ void decode_cell(int64_t c, const int nb[3], int &cx, int &cy, int &cz) {
-    cx = (int)(c % nb[0]);
-    cy = (int)((c / nb[0]) % nb[1]);
-    cz = (int)(c / ((int64_t)nb[0] * nb[1]));
-}
-
-template <typename T, bool CIC, bool KAHAN>
-__global__ __launch_bounds__(kBlock) void k_deposit_phi(const int32_t *__restrict__ start,
-                                                        const vec4<T> *__restrict__ sp, int64_t n, Geo<T> g,
-                                                        T *__restrict__ phi, double *__restrict__ part,
-                                                        int64_t ps) {
-    __shared__ double red[kWavesPerBlock];
-    int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    double v = 0.0;
-    if (c < g.ncell) {
-        int cx, cy, cz;
-        decode_cell(c, g.nb, cx, cy, cz);
-        Acc<T, KAHAN> acc;
-        if constexpr (!CIC) {
-            const int32_t s = seg_lo(start[c], n), e = seg_hi(start[c + 1], n);
-            for (int32_t p = s; p < e; ++p) acc.add(vol_over_vb(sp[p].w, g.inv_vb));
-        } else {
-            int xl = cx > 0 ? cx - 1 : 0, xh = cx < g.nb[0] - 1 ? cx + 1 : cx;
-            for (int dz = -1; dz <= 1; ++dz) {
-                int z = cz + dz;
-                if (z < 0 || z >= g.nb[2]) continue;
-                for (int dy = -1; dy <= 1; ++dy) {
-                    int y = cy + dy;
-                    if (y < 0 || y >= g.nb[1]) continue;
-                    int64_t row = (int64_t)g.nb[0] * (y + (int64_t)g.nb[1] * z);
-                    int32_t s = seg_lo(start[row + xl], n), e = seg_hi(start[row + xh + 1], n);
-                    for (int32_t p = s; p < e; ++p) {
-                        vec4<T> q = sp[p];
-                        T w = cic_weight_to(q, g, cx, cy, cz);
-                        if (w != T(0)) acc.add(w * vol_over_vb(q.w, g.inv_vb));
-                    }
-                }
-            }
-        }
-        phi[c] = acc.s;
-        v = (double)acc.s;
-    }
-    double t = block_sum(v, red);
-    double m = block_max(v, red);
-    if (threadIdx.x == 0) {
-        part[SL_PHISUM * ps + blockIdx.x] = t;
-        part[SL_MAXPHI * ps + blockIdx.x] = m;
-    }
-}
-
-template <typename T, bool CIC, bool KAHAN>
-__global__ __launch_bounds__(kBlock) void k_deposit_force(const int32_t *__restrict__ start,
-                                                          const vec4<T> *__restrict__ sp,
-                                                          const vec4<T> *__restrict__ sf, int64_t n, Geo<T> g,
-                                                          const T *__restrict__ P, const T *__restrict__ Plo,
-                                                          T *__restrict__ F, T *__restrict__ G,
-                                                          double *__restrict__ part, int64_t ps) {
-    __shared__ double red[kWavesPerBlock];
-    int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    double fb[3] = {0.0, 0.0, 0.0};
-    if (c < g.ncell) {
-        int cx, cy, cz;
-        decode_cell(c, g.nb, cx, cy, cz);
-        Acc<T, KAHAN> ax, ay, az;
-        if constexpr (!CIC) {
-            const int32_t s = seg_lo(start[c], n), e = seg_hi(start[c + 1], n);
-            for (int32_t p = s; p < e; ++p) {
-                vec4<T> f = sf[p];
-                ax.add(f.x);
-                ay.add(f.y);
-                az.add(f.z);
-            }
-        } else {
-            int xl = cx > 0 ? cx - 1 : 0, xh = cx < g.nb[0] - 1 ? cx + 1 : cx;
-            for (int dz = -1; dz <= 1; ++dz) {
-                int z = cz + dz;
-                if (z < 0 || z >= g.nb[2]) continue;
-                for (int dy = -1; dy <= 1; ++dy) {
-                    int y = cy + dy;
-                    if (y < 0 || y >= g.nb[1]) continue;
-                    int64_t row = (int64_t)g.nb[0] * (y + (int64_t)g.nb[1] * z);
-                    int32_t s = seg_lo(start[row + xl], n), e = seg_hi(start[row + xh + 1], n);
-                    for (int32_t p = s; p < e; ++p) {
-                        T w = cic_weight_to(sp[p], g, cx, cy, cz);
-                        if (w != T(0)) {
-                            vec4<T> f = sf[p];
-                            ax.add(w * f.x);
-                            ay.add(w * f.y);
-                            az.add(w * f.z);
-                        }
-                    }
-                }
-            }
-        }
-        T fx = -ax.s * g.inv_vb, fy = -ay.s * g.inv_vb, fz = -az.s * g.inv_vb;
-        F[c] = fx;
-        F[g.ncell + c] = fy;
-        F[2 * g.ncell + c] = fz;
-        fb[0] = fx;
-        fb[1] = fy;
-        fb[2] = fz;
-        // bulk pressure gradient: central differences, one-sided at the walls.
-        // The difference is taken in FP64 of the compensated pressure hi + lo:
-        // differencing the rounded FP32 values alone would lose ulp(P)/h.
-        int idx[3] = {cx, cy, cz};
-        int64_t stride[3] = {1, g.nb[0], (int64_t)g.nb[0] * g.nb[1]};
-        auto pv = [&](int64_t k) { return (double)P[k] + (double)Plo[k]; };
-        for (int a = 0; a < 3; ++a) {
-            double gr;
-            const int nax = g.nb[a];
-            const double h = (double)g.hb[a];
-            if (nax == 1) gr = 0.0;
-            else if (idx[a] == 0) gr = (pv(c + stride[a]) - pv(c)) / h;
-            else if (idx[a] == nax - 1) gr = (pv(c) - pv(c - stride[a])) / h;
-            else gr = (pv(c + stride[a]) - pv(c - stride[a])) / (2.0 * h);
-            G[a * g.ncell + c] = (T)gr;
-        }
-    }
-    for (int a = 0; a < 3; ++a) {
-        double t = block_sum(fb[a], red);
-        if (threadIdx.x == 0) part[(SL_FB + a) * ps + blockIdx.x] = t;
     }
 }
 
@@ -270,166 +107,138 @@ __device__ __forceinline__ T trilin(const T *__restrict__ f, const Axis<T> &ax, 
     return sz * c0 + az.t * c1;
 }
 
-// FP64 re-evaluation of the particle's solid fraction (near close packing).
-template <typename T>
-__device__ __forceinline__ double phi_at_fp64(const T *__restrict__ phi, const vec4<T> &q, const Geo<T> &g, int cic) {
-    if (!cic) {
-        int ix = cell_axis(q.x, g.sb[0], g.nb[0]);
-        int iy = cell_axis(q.y, g.sb[1], g.nb[1]);
-        int iz = cell_axis(q.z, g.sb[2], g.nb[2]);
-        return (double)phi[ix + (int64_t)g.nb[0] * (iy + (int64_t)g.nb[1] * iz)];
-    }
-    double xs[3] = {(double)q.x, (double)q.y, (double)q.z};
-    int lo[3], hi[3];
-    double t[3];
-    for (int a = 0; a < 3; ++a) {
-        double gg = xs[a] * (double)g.sb[a] - 0.5;
-        double jf = floor(gg);
-        t[a] = gg - jf;
-        lo[a] = clampi((int)jf, g.nb[a]);
-        hi[a] = clampi((int)jf + 1, g.nb[a]);
-    }
-    double s = 0.0;
-    for (int dz = 0; dz < 2; ++dz)
-        for (int dy = 0; dy < 2; ++dy)
-            for (int dx = 0; dx < 2; ++dx) {
-                double w = (dx ? t[0] : 1.0 - t[0]) * (dy ? t[1] : 1.0 - t[1]) * (dz ? t[2] : 1.0 - t[2]);
-                int64_t c = (dx ? hi[0] : lo[0]) + (int64_t)g.nb[0] * ((dy ? hi[1] : lo[1]) +
-                                                                        (int64_t)g.nb[1] * (dz ? hi[2] : lo[2]));
-                s += w * (double)phi[c];
-            }
-    return s;
-}
+// Values at x-nodes lo and hi (hi == lo + 1, or hi == lo at a wall) of one row
+// of n >= 2 values, from one 8-byte load of the pair that contains them.
+template <typename T> struct Pair2;
+template <> struct Pair2<float> { typedef float __attribute__((ext_vector_type(2), aligned(4))) type; };
+template <> struct Pair2<double> { typedef double __attribute__((ext_vector_type(2), aligned(8))) type; };
 
 template <typename T>
-__device__ __forceinline__ void particle_step(int64_t i, const StepArgs<T> &a, double acc[4]) {
+__device__ __forceinline__ void load_pair(const T *__restrict__ row, int lo, int hi, T &vlo, T &vhi) {
+    const int base = (hi != lo) ? lo : (lo == 0 ? 0 : lo - 1);
+    const typename Pair2<T>::type v = *reinterpret_cast<const typename Pair2<T>::type *>(row + base);
+    vlo = (lo == base) ? v.x : v.y;
+    vhi = (hi == base) ? v.x : v.y;
+}
+
+// Trilinear value of a cell-centred field from its 4 (y, z) rows of x-pairs.
+template <typename T>
+__device__ __forceinline__ T trilin_pairs(const T *__restrict__ f, const Axis<T> &ax, const Axis<T> &ay,
+                                          const Axis<T> &az, int nx, int64_t nxy) {
+    if (nx == 1) return trilin(f, ax, ay, az, nx, nxy);
+    const int64_t zl = az.lo * nxy, zh = az.hi * nxy, yl = (int64_t)ay.lo * nx, yh = (int64_t)ay.hi * nx;
+    T a0, a1, b0, b1, c0, c1, d0, d1;
+    load_pair(f + zl + yl, ax.lo, ax.hi, a0, a1);
+    load_pair(f + zl + yh, ax.lo, ax.hi, b0, b1);
+    load_pair(f + zh + yl, ax.lo, ax.hi, c0, c1);
+    load_pair(f + zh + yh, ax.lo, ax.hi, d0, d1);
+    const T sx = T(1) - ax.t, sy = T(1) - ay.t, sz = T(1) - az.t;
+    const T e0 = sy * (sx * a0 + ax.t * a1) + ay.t * (sx * b0 + ax.t * b1);
+    const T e1 = sy * (sx * c0 + ax.t * c1) + ay.t * (sx * d0 + ax.t * d1);
+    return sz * e0 + az.t * e1;
+}
+
+// Per particle in the sorted order: the fluid velocity at the particle (fine or
+// bulk trilinear) and the void fraction eps_p = sum_c w_pc (1 - phi_c) (the
+// transpose of the deposition weights), written to uf4[id] = (u, v, w, eps_p)
+// for the input-order drag kernel.  In the FP32 modes, where the particle solid
+// fraction exceeds phi_fp64 (near close packing) phi_p and 1 - phi_p are formed
+// in FP64 from the same eight bulk values.  KB particles per thread are sampled
+// together so that all their gathers are in flight at once.
+template <typename T, int KB>
+__device__ __forceinline__ void sample_particles(const int64_t (&idx)[KB], const StepArgs<T> &a) {
     const Geo<T> &g = a.g;
-    const vec4<T> q = a.sp[i];
-    const vec4<T> v = a.sv[i];
-    int64_t p = a.perm[i];
-    if (p < 0 || p >= a.n) p = 0;   // perm is a permutation of [0, n); guards the stores
-    const T d = q.w;
-
-    // solid fraction at the particle: transpose of the deposition weights
-    T phi_p;
-    if (a.cic) {
-        Axis<T> bx = cic_axis(q.x, g.sb[0], g.nb[0]);
-        Axis<T> by = cic_axis(q.y, g.sb[1], g.nb[1]);
-        Axis<T> bz = cic_axis(q.z, g.sb[2], g.nb[2]);
-        phi_p = trilin(a.phi, bx, by, bz, g.nb[0], (int64_t)g.nb[0] * g.nb[1]);
-    } else {
-        int ix = cell_axis(q.x, g.sb[0], g.nb[0]);
-        int iy = cell_axis(q.y, g.sb[1], g.nb[1]);
-        int iz = cell_axis(q.z, g.sb[2], g.nb[2]);
-        phi_p = a.phi[ix + (int64_t)g.nb[0] * (iy + (int64_t)g.nb[1] * iz)];
+    const vec4<T> *__restrict__ sp = a.sp;
+    const int32_t *__restrict__ perm = a.perm;
+    const T *__restrict__ phi = a.phi;
+    vec4<T> q[KB];
+    int64_t p[KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+        const int64_t i = idx[k] >= 0 ? idx[k] : 0;
+        q[k] = sp[i];
+        p[k] = perm[i];
+        if (p[k] < 0 || p[k] >= a.n) p[k] = 0;   // perm is a permutation of [0, n)
     }
-
-    // fluid velocity at the particle
-    T uf[3];
-    if (a.vel_source == 0) {
-        Axis<T> fx = cic_axis(q.x, g.sf[0], g.nf[0]);
-        Axis<T> fy = cic_axis(q.y, g.sf[1], g.nf[1]);
-        Axis<T> fz = cic_axis(q.z, g.sf[2], g.nf[2]);
-        const int64_t nx = g.nf[0], nxy = (int64_t)g.nf[0] * g.nf[1];
-        for (int k = 0; k < 3; ++k) uf[k] = trilin(a.fine[k], fx, fy, fz, nx, nxy);
-    } else if (a.vel_source == 1) {
-        Axis<T> bx = cic_axis(q.x, g.sb[0], g.nb[0]);
-        Axis<T> by = cic_axis(q.y, g.sb[1], g.nb[1]);
-        Axis<T> bz = cic_axis(q.z, g.sb[2], g.nb[2]);
-        const int64_t nx = g.nb[0], nxy = (int64_t)g.nb[0] * g.nb[1];
-        for (int k = 0; k < 3; ++k) uf[k] = trilin(a.U + k * g.ncell, bx, by, bz, nx, nxy);
-    } else {
-        for (int k = 0; k < 3; ++k) uf[k] = a.uf_given[3 * p + k];
-    }
-
-    // drag: F = beta (u_f - u_p); beta in the form
-    //   1/2 rho_f (pi d^2/4) eps*^(2-chi) (0.63 sqrt|u_r| + 4.8 sqrt(mu_f/(rho_f eps* d)))^2
-    // which equals 1/2 C_D rho_f A eps*^(2-chi) |u_r| with C_D = (0.63 + 4.8/sqrt(Re))^2
-    // and stays finite as |u_r| -> 0.
-    const T ur0 = uf[0] - v.x, ur1 = uf[1] - v.y, ur2 = uf[2] - v.z;
-    const T mag = dsqrt(ur0 * ur0 + ur1 * ur1 + ur2 * ur2);
-    const bool wide = std::is_same<T, float>::value && phi_p > (T)a.phi_fp64;
-    double eps_w = 0.0;
-    T e;
-    int clamped = 0;
-    if (wide) {
-        eps_w = 1.0 - phi_at_fp64(a.phi, q, g, a.cic);
-        if (eps_w < (double)a.eps_min) {
-            eps_w = (double)a.eps_min;
-            clamped = 1;
-        }
-        e = (T)eps_w;
-    } else {
-        e = T(1) - phi_p;
-        if (e < a.eps_min) {
-            e = a.eps_min;
-            clamped = 1;
-        }
-    }
-    T chi = T(3.7);
-    if (mag > T(0)) {
-        T re = a.rho_f * e * d * mag / a.mu_f;
-        T l = T(1.5) - dlog10(re);
-        chi = T(3.7) - T(0.65) * dexp(-l * l * T(0.5));
-    }
-    T vfac = wide ? (T)pow(eps_w, 2.0 - (double)chi) : dpow(e, T(2) - chi);
-    T sq = T(0.63) * dsqrt(mag) + T(4.8) * dsqrt(a.mu_f / (a.rho_f * e * d));
-    T area = T(kPi / 4.0) * d * d;
-    T beta = T(0.5) * a.rho_f * area * vfac * (sq * sq);
-    T F0 = beta * ur0, F1 = beta * ur1, F2 = beta * ur2;
-
-    a.drag[3 * p + 0] = F0;
-    a.drag[3 * p + 1] = F1;
-    a.drag[3 * p + 2] = F2;
-    if (a.beta) a.beta[p] = beta;
-    vec4<T> f;
-    f.x = F0; f.y = F1; f.z = F2; f.w = T(0);
-    a.sf[i] = f;
-    acc[0] += (double)F0;
-    acc[1] += (double)F1;
-    acc[2] += (double)F2;
-    acc[3] += clamped;
-
-    if (a.advect) {
-        // explicit Euler from the old state, specular reflection at the walls
-        const T m = a.rho_p * (T(kPi / 6.0) * d * d * d);
-        const T xs[3] = {q.x, q.y, q.z};
-        const T us[3] = {v.x, v.y, v.z};
-        const T Fs[3] = {F0, F1, F2};
-        for (int k = 0; k < 3; ++k) {
-            T xn = dfma(a.dt, us[k], xs[k]);
-            T un = dfma(a.dt, Fs[k] / m, us[k]);
-            const T L = g.L[k];
-            if (xn < T(0)) {
-                xn = -xn;
-                un = -un;
-            } else if (xn > L) {
-                xn = T(2) * L - xn;
-                un = -un;
+    vec4<T> s[KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+        T eps;
+        if (a.cic) {
+            const Axis<T> bx = cic_axis(q[k].x, g.sb[0], g.nb[0]);
+            const Axis<T> by = cic_axis(q[k].y, g.sb[1], g.nb[1]);
+            const Axis<T> bz = cic_axis(q[k].z, g.sb[2], g.nb[2]);
+            const int nx = g.nb[0];
+            const int64_t nxy = (int64_t)g.nb[0] * g.nb[1];
+            T f000, f001, f010, f011, f100, f101, f110, f111;
+            if (nx >= 2) {
+                const int64_t zl = bz.lo * nxy, zh = bz.hi * nxy, yl = (int64_t)by.lo * nx, yh = (int64_t)by.hi * nx;
+                load_pair(phi + zl + yl, bx.lo, bx.hi, f000, f001);
+                load_pair(phi + zl + yh, bx.lo, bx.hi, f010, f011);
+                load_pair(phi + zh + yl, bx.lo, bx.hi, f100, f101);
+                load_pair(phi + zh + yh, bx.lo, bx.hi, f110, f111);
+            } else {
+                const int64_t zl = bz.lo * nxy, zh = bz.hi * nxy, yl = (int64_t)by.lo * nx, yh = (int64_t)by.hi * nx;
+                f000 = f001 = phi[zl + yl];
+                f010 = f011 = phi[zl + yh];
+                f100 = f101 = phi[zh + yl];
+                f110 = f111 = phi[zh + yh];
             }
-            xn = fmin(fmax(xn, T(0)), L);
-            a.pos[3 * p + k] = xn;
-            a.vel[3 * p + k] = un;
+            const T sx = T(1) - bx.t, sy = T(1) - by.t, sz = T(1) - bz.t;
+            const T phi_p = sz * (sy * (sx * f000 + bx.t * f001) + by.t * (sx * f010 + bx.t * f011)) +
+                            bz.t * (sy * (sx * f100 + bx.t * f101) + by.t * (sx * f110 + bx.t * f111));
+            if (std::is_same<T, float>::value && phi_p > (T)a.phi_fp64) {
+                // FP64 weights from the same positions; the cancellation in 1 - phi is exact
+                const double gx = (double)q[k].x * (double)g.sb[0] - 0.5, gy = (double)q[k].y * (double)g.sb[1] - 0.5,
+                             gz = (double)q[k].z * (double)g.sb[2] - 0.5;
+                const double tx = gx - floor(gx), ty = gy - floor(gy), tz = gz - floor(gz);
+                const double ux = 1.0 - tx, uy = 1.0 - ty, uz = 1.0 - tz;
+                const double ph =
+                    uz * (uy * (ux * (double)f000 + tx * (double)f001) + ty * (ux * (double)f010 + tx * (double)f011)) +
+                    tz * (uy * (ux * (double)f100 + tx * (double)f101) + ty * (ux * (double)f110 + tx * (double)f111));
+                eps = (T)(1.0 - ph);
+            } else {
+                eps = T(1) - phi_p;
+            }
+        } else {
+            const int ix = cell_axis(q[k].x, g.sb[0], g.nb[0]);
+            const int iy = cell_axis(q[k].y, g.sb[1], g.nb[1]);
+            const int iz = cell_axis(q[k].z, g.sb[2], g.nb[2]);
+            eps = T(1) - phi[ix + (int64_t)g.nb[0] * (iy + (int64_t)g.nb[1] * iz)];  // exact for phi in [1/2, 1]
+        }
+        s[k].w = eps;
+        if (a.vel_source == 0) {
+            const Axis<T> fx = cic_axis(q[k].x, g.sf[0], g.nf[0]);
+            const Axis<T> fy = cic_axis(q[k].y, g.sf[1], g.nf[1]);
+            const Axis<T> fz = cic_axis(q[k].z, g.sf[2], g.nf[2]);
+            const int nx = g.nf[0];
+            const int64_t nxy = (int64_t)g.nf[0] * g.nf[1];
+            s[k].x = trilin_pairs(a.fine[0], fx, fy, fz, nx, nxy);
+            s[k].y = trilin_pairs(a.fine[1], fx, fy, fz, nx, nxy);
+            s[k].z = trilin_pairs(a.fine[2], fx, fy, fz, nx, nxy);
+        } else if (a.vel_source == 1) {
+            const Axis<T> bx = cic_axis(q[k].x, g.sb[0], g.nb[0]);
+            const Axis<T> by = cic_axis(q[k].y, g.sb[1], g.nb[1]);
+            const Axis<T> bz = cic_axis(q[k].z, g.sb[2], g.nb[2]);
+            const int nx = g.nb[0];
+            const int64_t nxy = (int64_t)g.nb[0] * g.nb[1];
+            s[k].x = trilin_pairs(a.U, bx, by, bz, nx, nxy);
+            s[k].y = trilin_pairs(a.U + g.ncell, bx, by, bz, nx, nxy);
+            s[k].z = trilin_pairs(a.U + 2 * g.ncell, bx, by, bz, nx, nxy);
+        } else {
+            s[k].x = s[k].y = s[k].z = T(0);   // the drag kernel takes u_f from uf_given
         }
     }
-}
-
-template <typename T>
-__device__ __forceinline__ void write_particle_partials(const double acc[4], double *part, int64_t ps, double *red) {
-    for (int k = 0; k < 3; ++k) {
-        double t = block_sum(acc[k], red);
-        if (threadIdx.x == 0) part[(SL_FP + k) * ps + blockIdx.x] = t;
-    }
-    double t = block_sum(acc[3], red);
-    if (threadIdx.x == 0) part[SL_NCLAMP * ps + blockIdx.x] = t;
+#pragma unroll
+    for (int k = 0; k < KB; ++k)
+        if (idx[k] >= 0) a.uf4[p[k]] = s[k];
 }
 
 // ---------------------------------------------------------------------------
-// Restriction fine -> bulk (+ fused fine lookup and drag)
+// Restriction fine -> bulk (+ fused fine lookup of the particles)
 // ---------------------------------------------------------------------------
-template <typename T, int R, bool KAHAN, bool FUSED>
+template <typename T, int R, bool KAHAN, bool LOOKUP>
 __global__ __launch_bounds__(kBlock) void k_restrict(StepArgs<T> a) {
-    __shared__ double red[kWavesPerBlock];
     const Geo<T> &g = a.g;
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t c = tile * kBlock + threadIdx.x;
@@ -465,26 +274,106 @@ __global__ __launch_bounds__(kBlock) void k_restrict(StepArgs<T> a) {
             }
         }
     }
-    if constexpr (FUSED) {
-        double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-        const int64_t c0 = tile * kBlock + (int64_t)w * kWave;
+    if constexpr (LOOKUP) {
+        // the particles of this workgroup's 256 cells, while their fine rows are
+        // in L2, shared by all its threads, two per thread at a time
+        const int64_t c0 = tile * kBlock;
         if (c0 < g.ncell) {
-            const int64_t c1 = (c0 + kWave < g.ncell) ? c0 + kWave : g.ncell;
-            const int64_t s = seg_lo(a.start[c0], a.n), e = seg_hi(a.start[c1], a.n);
-            for (int64_t i = s + lane; i < e; i += kWave) particle_step(i, a, acc);
+            const int64_t c1 = (c0 + kBlock < g.ncell) ? c0 + kBlock : g.ncell;
+            const int64_t s = seg_clamp(a.start[c0], a.n), e = seg_clamp(a.start[c1], a.n);
+            for (int64_t i = s + threadIdx.x; i < e; i += 2 * kBlock) {
+                const int64_t idx[2] = {i, (i + kBlock < e) ? i + kBlock : -1};
+                sample_particles<T, 2>(idx, a);
+            }
         }
-        write_particle_partials<T>(acc, a.part, a.part_stride, red);
     }
 }
 
+// Sampling for the bulk-velocity and given-velocity sources (sorted order).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_particles(StepArgs<T> a) {
-    __shared__ double red[kWavesPerBlock];
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+__global__ __launch_bounds__(kBlock) void k_sample(StepArgs<T> a) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i < a.n) particle_step(i, a, acc);
-    write_particle_partials<T>(acc, a.part, a.part_stride, red);
+    if (i < a.n) {
+        const int64_t idx[1] = {i};
+        sample_particles<T, 1>(idx, a);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Drag and advection, one thread per particle in input order (coalesced).
+//   F = beta (u_f - u_p), beta written as
+//   1/2 rho_f (pi d^2/4) eps*^(2-chi) (0.63 sqrt|u_r| + 4.8 sqrt(mu_f/(rho_f eps* d)))^2
+// which equals 1/2 C_D rho_f A eps*^(2-chi) |u_r| with C_D = (0.63 + 4.8/sqrt(Re))^2,
+// Re = rho_f eps* d |u_r| / mu_f, chi = 3.7 - 0.65 exp(-(1.5 - log10 Re)^2 / 2), and
+// stays finite as |u_r| -> 0 (where F = 0).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_drag(StepArgs<T> a) {
+    __shared__ double red[kWavesPerBlock];
+    const Geo<T> &g = a.g;
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // sum F (3), clamped, V_p
+    if (p < a.n) {
+        int o = 0;
+        const T xs[3] = {clamp_coord(a.pos[3 * p + 0], g.L[0], o), clamp_coord(a.pos[3 * p + 1], g.L[1], o),
+                         clamp_coord(a.pos[3 * p + 2], g.L[2], o)};
+        const T us[3] = {a.vel[3 * p + 0], a.vel[3 * p + 1], a.vel[3 * p + 2]};
+        const T d = a.diam[p];
+        const vec4<T> s = a.uf4[p];
+        T uf[3] = {s.x, s.y, s.z};
+        if (a.vel_source == 2)
+            for (int k = 0; k < 3; ++k) uf[k] = a.uf_given[3 * p + k];
+        const T ur0 = uf[0] - us[0], ur1 = uf[1] - us[1], ur2 = uf[2] - us[2];
+        const T mag = dsqrt(ur0 * ur0 + ur1 * ur1 + ur2 * ur2);
+        T e = s.w;
+        int clamped = 0;
+        if (e < a.eps_min) {
+            e = a.eps_min;
+            clamped = 1;
+        }
+        T chi = T(3.7);
+        if (mag > T(0)) {
+            const T re = a.rho_f * e * d * mag / a.mu_f;
+            const T l = T(1.5) - dlog10(re);
+            chi = T(3.7) - T(0.65) * dexp(-l * l * T(0.5));
+        }
+        const T vfac = dpow(e, T(2) - chi);
+        const T sq = T(0.63) * dsqrt(mag) + T(4.8) * dsqrt(a.mu_f / (a.rho_f * e * d));
+        const T area = T(kPi / 4.0) * d * d;
+        const T beta = T(0.5) * a.rho_f * area * vfac * (sq * sq);
+        const T Fs[3] = {beta * ur0, beta * ur1, beta * ur2};
+        for (int k = 0; k < 3; ++k) a.drag[3 * p + k] = Fs[k];
+        if (a.beta) a.beta[p] = beta;
+        for (int k = 0; k < 3; ++k) acc[k] = (double)Fs[k];
+        acc[3] = clamped;
+        const double dd = (double)d;
+        acc[4] = kPi * dd * dd * dd / 6.0;
+
+        if (a.advect) {
+            // explicit Euler from the old state, specular reflection at the walls
+            const T m = a.rho_p * (T(kPi / 6.0) * d * d * d);
+            for (int k = 0; k < 3; ++k) {
+                T xn = dfma(a.dt, us[k], xs[k]);
+                T un = dfma(a.dt, Fs[k] / m, us[k]);
+                const T L = g.L[k];
+                if (xn < T(0)) {
+                    xn = -xn;
+                    un = -un;
+                } else if (xn > L) {
+                    xn = T(2) * L - xn;
+                    un = -un;
+                }
+                xn = fmin(fmax(xn, T(0)), L);
+                a.pos[3 * p + k] = xn;
+                a.vel[3 * p + k] = un;
+            }
+        }
+    }
+    const int slots[5] = {SL_FP, SL_FP + 1, SL_FP + 2, SL_NCLAMP, SL_VTOT};
+    for (int k = 0; k < 5; ++k) {
+        const double t = block_sum(acc[k], red);
+        if (threadIdx.x == 0) a.part[slots[k] * a.part_stride + blockIdx.x] = t;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -614,18 +503,26 @@ struct DiagSpec {
 
 __global__ __launch_bounds__(kBlock) void k_diag(const double *__restrict__ part, int64_t ps, DiagSpec spec,
                                                  double *__restrict__ diag) {
+    // one workgroup per slot; thread t sums the partials t + k*kBlock with eight
+    // interleaved accumulators (loads in flight), combined in a fixed order, then
+    // a fixed tree combines the threads: deterministic.
     __shared__ double red[kWavesPerBlock];
-    for (int s = 0; s < SL_COUNT; ++s) {
-        const bool is_max = (s == SL_MAXPHI);
-        double v = 0.0;
-        for (int j = threadIdx.x; j < spec.nblk[s]; j += kBlock) {
-            double x = part[s * ps + j];
-            v = is_max ? fmax(v, x) : v + x;
+    const int s = blockIdx.x;
+    const bool is_max = (s == SL_MAXPHI);
+    const int nb = spec.nblk[s];
+    const double *src = part + s * ps;
+    double v8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int j0 = 0; j0 < nb; j0 += 8 * kBlock) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int j = j0 + u * kBlock + threadIdx.x;
+            if (j < nb) v8[u] = is_max ? fmax(v8[u], src[j]) : v8[u] + src[j];
         }
-        double t = is_max ? block_max(v, red) : block_sum(v, red);
-        if (threadIdx.x == 0) diag[s] = t * spec.scale[s];
-        __syncthreads();
     }
+    double v = v8[0];
+    for (int u = 1; u < 8; ++u) v = is_max ? fmax(v, v8[u]) : v + v8[u];
+    const double t = is_max ? block_max(v, red) : block_sum(v, red);
+    if (threadIdx.x == 0) diag[s] = t * spec.scale[s];
 }
 
 // ---------------------------------------------------------------------------
@@ -635,23 +532,19 @@ template <typename T, int R, bool KAHAN>
 static void launch_grid_stages(const StepArgs<T> &a, hipStream_t st) {
     const int64_t cb = (a.g.ncell + kBlock - 1) / kBlock;
     const int64_t pb = (a.n + kBlock - 1) / kBlock;
-    const bool fused = (a.vel_source == 0);
-    if (fused) {
-        a.mk->mark("restrict_lookup_drag", st);
+    if (a.vel_source == 0) {
+        a.mk->mark("restrict_lookup", st);
         hipLaunchKernelGGL((k_restrict<T, R, KAHAN, true>), dim3(cb), dim3(kBlock), 0, st, a);
     } else {
         a.mk->mark("restrict", st);
         hipLaunchKernelGGL((k_restrict<T, R, KAHAN, false>), dim3(cb), dim3(kBlock), 0, st, a);
-        if (a.n > 0) a.mk->mark("particles", st);
-        if (a.n > 0) hipLaunchKernelGGL(k_particles<T>, dim3(pb), dim3(kBlock), 0, st, a);
+        if (a.n > 0) a.mk->mark("sample", st);
+        if (a.n > 0) hipLaunchKernelGGL(k_sample<T>, dim3(pb), dim3(kBlock), 0, st, a);
     }
+    if (a.n > 0) a.mk->mark("drag", st);
+    if (a.n > 0) hipLaunchKernelGGL(k_drag<T>, dim3(pb), dim3(kBlock), 0, st, a);
     a.mk->mark("deposit_force", st);
-    if (a.cic)
-        hipLaunchKernelGGL((k_deposit_force<T, true, KAHAN>), dim3(cb), dim3(kBlock), 0, st, a.start, a.sp, a.sf,
-                           a.n, a.g, a.P, a.Plo, a.F, a.G, a.part, a.part_stride);
-    else
-        hipLaunchKernelGGL((k_deposit_force<T, false, KAHAN>), dim3(cb), dim3(kBlock), 0, st, a.start, a.sp, a.sf,
-                           a.n, a.g, a.P, a.Plo, a.F, a.G, a.part, a.part_stride);
+    launch_deposit_force<T, KAHAN>(a, st);
     a.mk->mark("prolong", st);
     hipLaunchKernelGGL((k_prolong<T, R>), dim3(cb), dim3(kBlock), 0, st, a);
 }
@@ -668,37 +561,21 @@ template <typename T> hipError_t launch_stages(const StepArgs<T> &a, hipStream_t
     const int64_t cb = (a.g.ncell + kBlock - 1) / kBlock;
     const int64_t pb = (a.n + kBlock - 1) / kBlock;
     const bool kahan = std::is_same<T, float>::value && a.kahan;
-    if (a.n > 0) a.mk->mark("gather", st);
-    if (a.n > 0)
-        hipLaunchKernelGGL(k_gather<T>, dim3(pb), dim3(kBlock), 0, st, a.perm, a.pos, a.vel, a.diam, a.n, a.g, a.sp,
-                           a.sv, a.part + SL_VTOT * a.part_stride);
-    a.mk->mark("deposit_phi", st);
-    if (a.cic) {
-        if (kahan)
-            hipLaunchKernelGGL((k_deposit_phi<T, true, true>), dim3(cb), dim3(kBlock), 0, st, a.start, a.sp, a.n, a.g,
-                               a.phi, a.part, a.part_stride);
-        else
-            hipLaunchKernelGGL((k_deposit_phi<T, true, false>), dim3(cb), dim3(kBlock), 0, st, a.start, a.sp, a.n, a.g,
-                               a.phi, a.part, a.part_stride);
-    } else {
-        if (kahan)
-            hipLaunchKernelGGL((k_deposit_phi<T, false, true>), dim3(cb), dim3(kBlock), 0, st, a.start, a.sp, a.n, a.g,
-                               a.phi, a.part, a.part_stride);
-        else
-            hipLaunchKernelGGL((k_deposit_phi<T, false, false>), dim3(cb), dim3(kBlock), 0, st, a.start, a.sp, a.n, a.g,
-                               a.phi, a.part, a.part_stride);
-    }
-    if (kahan) launch_by_ratio<T, true>(a, st);
-    else launch_by_ratio<T, false>(a, st);
 
+    // workgroups per diagnostic slot (each writes one partial per slot), checked
+    // against the partials' stride before anything is launched
     DiagSpec spec;
     for (int s = 0; s < SL_COUNT; ++s) {
         spec.nblk[s] = (int)cb;
         spec.scale[s] = 1.0;
     }
+    const int db = deposit_blocks(a.g.nb, a.g.ncell, a.cic);
+    spec.nblk[SL_PHISUM] = db;
+    spec.nblk[SL_MAXPHI] = db;
+    for (int k = 0; k < 3; ++k) spec.nblk[SL_FB + k] = db;
     spec.nblk[SL_VTOT] = a.n > 0 ? (int)pb : 0;
     spec.nblk[SL_NOUT] = a.n > 0 ? sort_tiles(a.n) : 0;
-    const int npart = (a.vel_source == 0) ? (int)cb : (a.n > 0 ? (int)pb : 0);
+    const int npart = a.n > 0 ? (int)pb : 0;   // k_drag
     for (int k = 0; k < 3; ++k) spec.nblk[SL_FP + k] = npart;
     spec.nblk[SL_NCLAMP] = npart;
     spec.nblk[SL_NFALL] = 0;
@@ -708,8 +585,19 @@ template <typename T> hipError_t launch_stages(const StepArgs<T> &a, hipStream_t
         spec.scale[SL_FF + k] = a.g.vf;
     }
     spec.scale[SL_EPSF] = a.g.vf;
+    for (int s = 0; s < SL_COUNT; ++s)
+        if (spec.nblk[s] > a.part_stride) return hipErrorInvalidValue;   // partials would not fit
+
+    if (a.n > 0) a.mk->mark("gather", st);
+    if (a.n > 0)
+        hipLaunchKernelGGL(k_gather<T>, dim3(pb), dim3(kBlock), 0, st, a.perm, a.pos, a.diam, a.n, a.g, a.sp);
+    a.mk->mark("deposit_phi", st);
+    if (kahan) launch_deposit_phi<T, true>(a, st);
+    else launch_deposit_phi<T, false>(a, st);
+    if (kahan) launch_by_ratio<T, true>(a, st);
+    else launch_by_ratio<T, false>(a, st);
     a.mk->mark("diag", st);
-    hipLaunchKernelGGL(k_diag, dim3(1), dim3(kBlock), 0, st, a.part, a.part_stride, spec, a.diag);
+    hipLaunchKernelGGL(k_diag, dim3(SL_COUNT), dim3(kBlock), 0, st, a.part, a.part_stride, spec, a.diag);
     a.mk->mark(nullptr, st);
     return hipGetLastError();
 }

@@ -63,7 +63,7 @@ BAD = [
     dict(box=(0.0, 1.0, 1.0)), dict(box=(1.0, float("nan"), 1.0)), dict(nb=(0, 4, 4)), dict(ratio=3),
     dict(rho_f=-1.0), dict(mu_f=0.0), dict(eps_min=1.0), dict(deposit=2), dict(precision=7),
     dict(vel_source=9), dict(advect=2), dict(advect=1, dt=float("inf")), dict(max_particles=-5),
-    dict(nb=(2048, 2048, 1024)),
+    dict(nb=(2048, 2048, 1024)), dict(nb=(40000, 2, 2)),
 ]
 
 
