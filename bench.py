@@ -104,6 +104,7 @@ def main():
     ap.add_argument("--workload", default="bed128_cic")
     ap.add_argument("--cpu-frac", type=float, default=0.25, help="x-y fraction of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-presorted", action="store_true", help="skip the spatially sorted input variant")
     ap.add_argument("--vel-source", default="fine", choices=["fine", "bulk"],
                     help="fluid velocity at the particles: fine-grid lookup (default) or bulk trilinear")
     args = ap.parse_args()
@@ -186,6 +187,23 @@ def main():
         "conservation": {"V_dep/V_tot-1": d["V_dep"] / d["V_tot"] - 1 if d["V_tot"] else 0.0,
                          "S_b+sumF": [d["S_b"][a] + d["sum_Fp"][a] for a in range(3)]},
     }
+    if not args.no_presorted:
+        # The same particles stored in the step's canonical (cell, id) order, as a
+        # DEM code that keeps its arrays spatially sorted would pass them.
+        perm = out["perm"].long()
+        pos_s, vel_s, diam_s = pos[perm].contiguous(), vel[perm].contiguous(), diam[perm].contiguous()
+        for _ in range(args.warmup):
+            c.step(pos_s, vel_s, diam_s, fine, out=out)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.steps):
+            c.step(pos_s, vel_s, diam_s, fine, out=out)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_s = e0.elapsed_time(e1) / args.steps
+        rec["presorted_input"] = {"ms_per_step": ms_s, "value": n / (ms_s * 1e-3),
+                                  "note": "same particles passed in the canonical (cell, id) order"}
+        del pos_s, vel_s, diam_s
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle sample) ...", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(w, args.cpu_frac)

@@ -217,9 +217,20 @@ def fsum_axis(a):
     return math.fsum(np.asarray(a, dtype=np.float64).ravel().tolist())
 
 
+def restrict_all(fine, grid):
+    """Restricted U, P, bulk gradient G and the magnitude scales of one fine field set."""
+    nb, r, box = tuple(grid.nb), int(grid.ratio), tuple(float(b) for b in grid.box)
+    U = np.stack([restrict(f, nb, r) for f in fine[:3]])
+    P = restrict(fine[3], nb, r)
+    G = gradient(P, nb, box)
+    U_mag = np.stack([restrict(np.abs(np.asarray(f, dtype=np.float64)), nb, r) for f in fine[:3]])
+    P_mag = restrict(np.abs(np.asarray(fine[3], dtype=np.float64)), nb, r)
+    return {"U": U, "P": P, "G": G, "U_mag": U_mag, "P_mag": P_mag}
+
+
 def step(pos, vel, diam, fine, grid, rho_f=1000.0, mu_f=1e-3, rho_p=2500.0, eps_min=0.3,
          cic=True, prec32=True, vel_source="fine", advect_dt=None, fine_out="full",
-         fine_sample=None, bulk_velocity=None):
+         fine_sample=None, bulk_velocity=None, restricted=None):
     """One coupling step in FP64.
 
     ``fine`` is (u, v, w, p), each (nfz, nfy, nfx).  ``vel_source`` is "fine"
@@ -227,6 +238,8 @@ def step(pos, vel, diam, fine, grid, rho_f=1000.0, mu_f=1e-3, rho_p=2500.0, eps_
     bulk velocity) or "given" (``bulk_velocity`` is the fluid velocity [n,3] at
     the particles, e.g. a surrogate's prediction).  ``fine_out`` is "full" (all
     fine cells), "sample" (only the flat indices ``fine_sample``) or "none".
+    ``restricted`` reuses the output of :func:`restrict_all` for the same fine
+    fields (the restriction does not depend on the particles).
     Returns a dict of numpy arrays and the diagnostics.
     """
     box = tuple(float(b) for b in grid.box)
@@ -246,13 +259,9 @@ def step(pos, vel, diam, fine, grid, rho_f=1000.0, mu_f=1e-3, rho_p=2500.0, eps_
     out.update(cell=cell, perm=perm, count=count, start=start)
     phi = deposit_volume(pos, diam, perm, box, nb, cic, prec32)
     out["phi"] = phi
-    U = np.stack([restrict(f, nb, r) for f in fine[:3]])
-    P = restrict(fine[3], nb, r)
-    G = gradient(P, nb, box)
-    out.update(U=U, P=P, G=G)
-    # magnitudes of the averaged values (parity-metric scales, not the method)
-    out["U_mag"] = np.stack([restrict(np.abs(np.asarray(f, dtype=np.float64)), nb, r) for f in fine[:3]])
-    out["P_mag"] = restrict(np.abs(np.asarray(fine[3], dtype=np.float64)), nb, r)
+    rr = restricted if restricted is not None else restrict_all(fine, grid)
+    out.update(rr)   # U, P, G and the magnitude scales used by the parity metric
+    U = rr["U"]
     eps_p = gather_eps(pos, phi, box, nb, cic, prec32)
     if vel_source == "fine":
         uf = np.stack([interp(f, nf, box, pos, prec32) for f in fine[:3]], axis=1)

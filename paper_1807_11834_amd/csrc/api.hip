@@ -118,7 +118,7 @@ extern "C" int couple_init(const couple_config *cfg, couple_handle **out) {
               dev_alloc(&h->sp, 4 * fsz * nmax) && dev_alloc(&h->uf4, 4 * fsz * nmax) &&
               dev_alloc(&h->plo, fsz * h->ncell) &&
               dev_alloc(&h->dep, (cfg->deposit == COUPLE_CIC ? 27 : 1) * fsz * h->ncell) &&
-              dev_alloc(&h->part, sizeof(double) * SL_COUNT * h->part_stride);
+              dev_alloc(&h->part, sizeof(double) * (SL_COUNT * h->part_stride + SL_COUNT * 64));
     if (!ok) {
         release(h);
         delete h;

@@ -222,30 +222,53 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t *__rest
     }
 }
 
-// start[c] = lower_bound(sorted keys, c) for c in [0, ncell], count[c] = diff.
+// start[c] = first sorted position with key >= c for c in [0, ncell], and
+// count[c] = start[c+1] - start[c].  A workgroup owns 256 cells; two binary
+// searches bound its key range, which is staged in LDS; every key that differs
+// from its predecessor fills the starts of the cells in between (each entry of
+// the block is written once).  A range longer than the LDS buffer (a very dense
+// block) falls back to one binary search per cell.
+constexpr int kSegCap = 4096;
+
 __global__ __launch_bounds__(kBlock) void k_segments(const uint32_t *__restrict__ skeys, int64_t n, int64_t ncell,
                                                      int32_t *__restrict__ start, int32_t *__restrict__ count) {
     __shared__ int64_t bound[2];
     __shared__ int32_t s_start[kBlock + 1];
+    __shared__ uint32_t kbuf[kSegCap];
     const int64_t c0 = (int64_t)blockIdx.x * kBlock;
     auto lower = [&](int64_t lo, int64_t hi, int64_t c) {   // first i in [lo,hi) with key >= c
         while (lo < hi) {
-            int64_t mid = lo + ((hi - lo) >> 1);
-            if ((int64_t)skeys[mid] < c) lo = mid + 1; else hi = mid;
+            const int64_t mid = lo + ((hi - lo) >> 1);
+            if ((int64_t)skeys[mid] < c) lo = mid + 1;
+            else hi = mid;
         }
         return lo;
     };
     if (threadIdx.x < 2) {
-        int64_t c = threadIdx.x == 0 ? c0 : (c0 + kBlock < ncell ? c0 + kBlock : ncell);
+        const int64_t c = threadIdx.x == 0 ? c0 : (c0 + kBlock < ncell ? c0 + kBlock : ncell);
         bound[threadIdx.x] = lower(0, n, c);
     }
     __syncthreads();
-    for (int t = threadIdx.x; t <= kBlock; t += kBlock) {
-        int64_t c = c0 + t;
-        if (c <= ncell) s_start[t] = (int32_t)lower(bound[0], bound[1], c);
+    const int64_t b0 = bound[0], b1 = bound[1];
+    const int64_t len = b1 - b0;
+    const int cend = (int)((c0 + kBlock < ncell ? c0 + kBlock : ncell) - c0);   // cells of this block
+    if (len <= kSegCap) {
+        for (int64_t i = threadIdx.x; i < len; i += kBlock) kbuf[i] = skeys[b0 + i];
+        __syncthreads();
+        for (int64_t i = threadIdx.x; i < len; i += kBlock) {
+            const int k = (int)((int64_t)kbuf[i] - c0);
+            const int prev = (i == 0) ? -1 : (int)((int64_t)kbuf[i - 1] - c0);
+            for (int c = prev + 1; c <= k; ++c) s_start[c] = (int32_t)(b0 + i);
+        }
+        if (threadIdx.x == 0) {
+            const int last = (len > 0) ? (int)((int64_t)kbuf[len - 1] - c0) : -1;
+            for (int c = last + 1; c <= cend; ++c) s_start[c] = (int32_t)b1;
+        }
+    } else {
+        for (int t = threadIdx.x; t <= cend; t += kBlock) s_start[t] = (int32_t)lower(b0, b1, c0 + t);
     }
     __syncthreads();
-    int64_t c = c0 + threadIdx.x;
+    const int64_t c = c0 + threadIdx.x;
     if (c < ncell) {
         start[c] = s_start[threadIdx.x];
         count[c] = s_start[threadIdx.x + 1] - s_start[threadIdx.x];

@@ -501,28 +501,35 @@ struct DiagSpec {
     double scale[SL_COUNT];
 };
 
-__global__ __launch_bounds__(kBlock) void k_diag(const double *__restrict__ part, int64_t ps, DiagSpec spec,
-                                                 double *__restrict__ diag) {
-    // one workgroup per slot; thread t sums the partials t + k*kBlock with eight
-    // interleaved accumulators (loads in flight), combined in a fixed order, then
-    // a fixed tree combines the threads: deterministic.
+// Stage 1: workgroup (slot, chunk) sums a contiguous chunk of the slot's
+// partials (thread t: elements t, t + kBlock, ... of the chunk, in order), then a
+// fixed tree; stage 2: one workgroup per slot combines the kDiagChunks values in
+// order.  Deterministic.
+constexpr int kDiagChunks = 32;
+
+__global__ __launch_bounds__(kBlock) void k_diag1(const double *__restrict__ part, int64_t ps, DiagSpec spec,
+                                                  double *__restrict__ part2) {
     __shared__ double red[kWavesPerBlock];
-    const int s = blockIdx.x;
+    const int s = blockIdx.x / kDiagChunks, ch = blockIdx.x % kDiagChunks;
     const bool is_max = (s == SL_MAXPHI);
     const int nb = spec.nblk[s];
+    const int per = (nb + kDiagChunks - 1) / kDiagChunks;
+    const int j0 = ch * per, j1 = (j0 + per < nb) ? j0 + per : nb;
     const double *src = part + s * ps;
-    double v8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int j0 = 0; j0 < nb; j0 += 8 * kBlock) {
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int j = j0 + u * kBlock + threadIdx.x;
-            if (j < nb) v8[u] = is_max ? fmax(v8[u], src[j]) : v8[u] + src[j];
-        }
-    }
-    double v = v8[0];
-    for (int u = 1; u < 8; ++u) v = is_max ? fmax(v, v8[u]) : v + v8[u];
+    double v = 0.0;
+    for (int j = j0 + threadIdx.x; j < j1; j += kBlock) v = is_max ? fmax(v, src[j]) : v + src[j];
     const double t = is_max ? block_max(v, red) : block_sum(v, red);
-    if (threadIdx.x == 0) diag[s] = t * spec.scale[s];
+    if (threadIdx.x == 0) part2[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(kWave) void k_diag2(const double *__restrict__ part2, DiagSpec spec,
+                                                 double *__restrict__ diag) {
+    const int s = blockIdx.x;
+    const bool is_max = (s == SL_MAXPHI);
+    double v = 0.0;
+    if (threadIdx.x < kDiagChunks) v = part2[s * kDiagChunks + threadIdx.x];
+    v = is_max ? wave_max(v) : wave_sum(v);
+    if (threadIdx.x == 0) diag[s] = v * spec.scale[s];
 }
 
 // ---------------------------------------------------------------------------
@@ -597,7 +604,9 @@ template <typename T> hipError_t launch_stages(const StepArgs<T> &a, hipStream_t
     if (kahan) launch_by_ratio<T, true>(a, st);
     else launch_by_ratio<T, false>(a, st);
     a.mk->mark("diag", st);
-    hipLaunchKernelGGL(k_diag, dim3(SL_COUNT), dim3(kBlock), 0, st, a.part, a.part_stride, spec, a.diag);
+    double *part2 = a.part + (int64_t)SL_COUNT * a.part_stride;
+    hipLaunchKernelGGL(k_diag1, dim3(SL_COUNT * kDiagChunks), dim3(kBlock), 0, st, a.part, a.part_stride, spec, part2);
+    hipLaunchKernelGGL(k_diag2, dim3(SL_COUNT), dim3(kWave), 0, st, part2, spec, a.diag);
     a.mk->mark(nullptr, st);
     return hipGetLastError();
 }

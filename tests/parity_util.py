@@ -118,8 +118,13 @@ def run_gpu(cpl, torch, cfg, pos, vel, diam, fine, uf_given=None, dev="cuda:0"):
     return res
 
 
-def compare_step(g, o, n, nb, r, fp64, check_fine=True, fine_sample=None, label="", naive=False, box=(1.0, 1.0, 1.0)):
-    """Assert parity of GPU outputs ``g`` with oracle outputs ``o``; returns errors."""
+def compare_step(g, o, n, nb, r, fp64, check_fine=True, fine_sample=None, label="", naive=False, box=(1.0, 1.0, 1.0),
+                 fine_sample_index=None):
+    """Assert parity of GPU outputs ``g`` with oracle outputs ``o``; returns errors.
+
+    ``fine_sample`` indexes the GPU's fine outputs to match the oracle's sampled
+    ones; ``fine_sample_index`` gives the fine cells those samples are (defaults
+    to ``fine_sample``), for the error scale."""
     tol = TOL_FP64_FIELD if fp64 else (TOL_NAIVE if naive else TOL_FP32_FIELD)
     ncell = int(np.prod(nb))
     errs = {}
@@ -141,7 +146,8 @@ def compare_step(g, o, n, nb, r, fp64, check_fine=True, fine_sample=None, label=
         "beta": (g["beta"], o["beta"], None, None),
     }
     if check_fine:
-        Mf = fine_scale_from_bulk(neighbourhood_max(Mb, nb), nb, r, fine_sample)
+        fidx = fine_sample if fine_sample_index is None else fine_sample_index
+        Mf = fine_scale_from_bulk(neighbourhood_max(Mb, nb), nb, r, fidx)
         if fine_sample is None:
             fields["fine_eps"] = (g["fine_eps"].ravel(), o["fine_eps"], None, None)
             fields["fine_F"] = (g["fine_F"].reshape(3, -1), o["fine_F"], Mf, None)
