@@ -16,7 +16,8 @@ d / h_x.  The 26 neighbour cells enter as differences from the centre cell (the
 centre cell as its own values): an invertible linear re-encoding of the same
 stencil that keeps the sub-bulk curvature, a percent of the field values,
 above the BF16 rounding of the standardised inputs.  Each feature is
-standardised with the training-set mean and standard deviation.
+standardised with the training-set mean and standard deviation (floored, see
+norm_stats).
 
 Network: 193 -> 128 -> 128 -> 128 -> 3, tanh-form GELU after the three hidden
 layers, linear output.  The GPU rounds to BF16 (round to nearest even) the
@@ -163,11 +164,26 @@ def standardise(X, mean, std):
     return out
 
 
+STD_REL_FLOOR = 1e-4
+
+
 def norm_stats(X):
-    """Mean and standard deviation per feature; a constant feature gets std 1."""
+    """Mean and population standard deviation per feature, with two floors.
+
+    A neighbour-difference feature's std is raised to at least 1e-4 times the
+    std of the centre cell's value of the same channel: a field that does not
+    vary along some direction (such as a pressure gradient component across the
+    flow) leaves differences that are pure FP32 rounding, which standardisation
+    would otherwise blow up to O(1) inputs.  Then a feature with std below 1e-12
+    gets std 1."""
     X = np.asarray(X, dtype=np.float64)
     mean = X.mean(axis=0)
     std = X.std(axis=0)
+    centre = std[7 * 13:7 * 14].copy()
+    for u in range(27):
+        if u != 13:
+            sl = slice(7 * u, 7 * u + 7)
+            std[sl] = np.maximum(std[sl], STD_REL_FLOOR * centre)
     std[std < 1e-12] = 1.0
     return mean, std
 

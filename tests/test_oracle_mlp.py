@@ -230,3 +230,16 @@ def test_target_scale_floor():
     s = M.target_scale(R)
     assert s[2] == s[1] and s[1] == pytest.approx(2 * s[0])
     np.testing.assert_array_equal(M.target_scale(np.zeros((4, 3))), [1.0, 1.0, 1.0])
+
+
+def test_norm_stats_floors():
+    rng = np.random.default_rng(10)
+    X = rng.standard_normal((500, M.NFEAT))
+    X[:, 7 * 13 + 5] *= 100.0                      # centre value of channel 5, std ~100
+    X[:, 7 * 14 + 5] = rng.standard_normal(500) * 1e-9   # a neighbour difference that is rounding noise
+    X[:, 192] = 0.02                               # constant feature
+    mean, std = M.norm_stats(X)
+    assert std[7 * 14 + 5] == pytest.approx(1e-4 * X[:, 7 * 13 + 5].std())
+    assert std[192] == 1.0
+    np.testing.assert_allclose(std[:7], X[:, :7].std(axis=0))   # unaffected where the spread is real
+    np.testing.assert_allclose(mean, X.mean(axis=0))
