@@ -14,7 +14,8 @@
  *               of every bulk cell ("fluid solution" arrow of Fig. 1), plus the
  *               bulk pressure gradient;
  *   4. gather   fluid velocity and void fraction at each particle ("cell values
- *               or locally interpolated values", Sec. 1);
+ *               or locally interpolated values", Sec. 1), or the learned
+ *               surrogate of that velocity (couple_mlp.h);
  *   5. drag     F_p = beta (u_f - u_p), Eq. DragLaw of Sec. 2.4, with beta from
  *               the Di Felice voidage correlation;
  *   6. source   momentum source F_fpi,c = -(1/V_b) sum_p w_pc F_p, the counterpart
@@ -72,7 +73,7 @@ typedef enum {
 
 enum { COUPLE_NGP = 0, COUPLE_CIC = 1 };                  /* deposition weights            */
 enum { COUPLE_FP64 = 0, COUPLE_FP32_KAHAN = 1, COUPLE_FP32_NAIVE = 2 };  /* precision      */
-enum { COUPLE_VEL_FINE = 0, COUPLE_VEL_BULK = 1, COUPLE_VEL_GIVEN = 2 }; /* u_f at particle */
+enum { COUPLE_VEL_FINE = 0, COUPLE_VEL_BULK = 1, COUPLE_VEL_GIVEN = 2, COUPLE_VEL_MLP = 3 }; /* u_f */
 
 /* Indices into the FP64 diagnostics vector (length COUPLE_DIAG_LEN). */
 enum {
@@ -85,8 +86,11 @@ enum {
     COUPLE_DIAG_N_CLAMPED = 12, /* particles whose void fraction was raised to eps_min     */
     COUPLE_DIAG_N_OUTSIDE = 13, /* particles with a coordinate outside [0,L] or not finite */
     COUPLE_DIAG_MAX_PHI = 14,   /* max_c phi_c                                              */
-    COUPLE_DIAG_N_FALLBACK = 15,/* reserved for callers that substitute u_f (0 here)       */
-    COUPLE_DIAG_LEN = 16
+    COUPLE_DIAG_N_FALLBACK = 15,/* VEL_MLP: particles that took the fine-grid fallback       */
+    COUPLE_DIAG_MLP_ERR2 = 16,  /* VEL_MLP: sum over the checked sample of |u_mlp - u_fine|^2 */
+    COUPLE_DIAG_MLP_REF2 = 17,  /* VEL_MLP: sum over the checked sample of |u_fine|^2         */
+    COUPLE_DIAG_MLP_NSAMP = 18, /* VEL_MLP: particles in the checked sample                   */
+    COUPLE_DIAG_LEN = 19
 };
 
 typedef struct couple_config {
@@ -101,11 +105,17 @@ typedef struct couple_config {
     int32_t deposit;         /* COUPLE_NGP or COUPLE_CIC                                      */
     int32_t precision;       /* COUPLE_FP64, COUPLE_FP32_KAHAN or COUPLE_FP32_NAIVE           */
     int32_t vel_source;      /* COUPLE_VEL_FINE (trilinear on the fine grid), COUPLE_VEL_BULK
-                                (trilinear on the restricted bulk velocity) or
-                                COUPLE_VEL_GIVEN (couple_inputs.uf_given)                     */
+                                (trilinear on the restricted bulk velocity),
+                                COUPLE_VEL_GIVEN (couple_inputs.uf_given) or COUPLE_VEL_MLP
+                                (learned surrogate with fine fallback, FP32 precisions only,
+                                network attached with couple_set_mlp)                         */
     int32_t advect;          /* 1: explicit Euler update of pos and vel in place              */
     double  dt;              /* advection time step                                           */
     int64_t max_particles;   /* capacity of the scratch; n > max_particles is an error        */
+    double  mlp_tol;         /* VEL_MLP: relative L2 error of a brick's checked sample above
+                                which the brick takes the fine lookup (>= 0)                  */
+    int32_t mlp_period;      /* VEL_MLP: one particle in mlp_period is checked (>= 1)          */
+    int32_t reserved;        /* must be 0                                                     */
 } couple_config;
 
 typedef struct couple_inputs {
@@ -118,6 +128,7 @@ typedef struct couple_inputs {
     const void *fine_w;      /*   z component                                                 */
     const void *fine_p;      /* [nfz][nfy][nfx] fine pressure                                 */
     const void *uf_given;    /* [n][3] fluid velocity at each particle (VEL_GIVEN only)       */
+    int64_t     step;        /* caller's step index; VEL_MLP checks ids = step mod mlp_period */
 } couple_inputs;
 
 typedef struct couple_outputs {
@@ -135,15 +146,18 @@ typedef struct couple_outputs {
     void    *fine_eps;       /* [Nf] porosity prolonged to the fine grid                      */
     void    *fine_F;         /* [3][Nf] momentum source prolonged to the fine grid            */
     double  *diag;           /* [COUPLE_DIAG_LEN] FP64 diagnostics (device memory)            */
+    void    *uf;             /* [n][3] fluid velocity used by the drag, or NULL if not wanted */
 } couple_outputs;
 
 /* Validate the configuration and allocate the scratch (about 48 * max_particles
- * bytes plus a few bytes per bulk cell).  On success *out receives a handle. */
+ * bytes plus a few bytes per bulk cell; 32 more bytes per bulk cell for
+ * VEL_MLP).  On success *out receives a handle. */
 int couple_init(const couple_config *cfg, couple_handle **out);
 
 /* Enqueue one coupling step (stages 1-9 above) on `stream`.  Every pointer of
- * `in` and `out` except out->beta (and in->uf_given unless VEL_GIVEN) must be
- * non-NULL when n > 0; the grid outputs are always required. */
+ * `in` and `out` except out->beta and out->uf (and in->uf_given unless
+ * VEL_GIVEN) must be non-NULL when n > 0; the grid outputs are always required.
+ * VEL_MLP without an attached network is COUPLE_ESTATE. */
 int couple_step(couple_handle *h, const couple_inputs *in, couple_outputs *out, void *stream);
 
 /* Release the scratch and the handle.  NULL is accepted. */

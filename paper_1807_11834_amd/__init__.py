@@ -12,7 +12,12 @@ The functions mirror the C entry points::
     couple_free(h)
     couple_last_error(h)
 
-``Coupler`` wraps a handle with output allocation for convenience.
+and those of the learned velocity surrogate (``include/couple_mlp.h``):
+``couple_mlp_init / _free / _set_params / _set_norm / _fit_norm / _get_state /
+_set_state / _forward / _grads / _adam / _train_step / _features`` and
+``couple_set_mlp``.
+
+``Coupler`` wraps a handle with output allocation, ``Mlp`` a network.
 """
 from __future__ import annotations
 
@@ -29,10 +34,12 @@ LIB_PATH = os.path.join(_HERE, "libcouple.so")
 COUPLE_OK, COUPLE_EINVAL, COUPLE_ENOMEM, COUPLE_EHIP, COUPLE_ECAPACITY, COUPLE_ESTATE = 0, -1, -2, -3, -4, -6
 COUPLE_NGP, COUPLE_CIC = 0, 1
 COUPLE_FP64, COUPLE_FP32_KAHAN, COUPLE_FP32_NAIVE = 0, 1, 2
-COUPLE_VEL_FINE, COUPLE_VEL_BULK, COUPLE_VEL_GIVEN = 0, 1, 2
+COUPLE_VEL_FINE, COUPLE_VEL_BULK, COUPLE_VEL_GIVEN, COUPLE_VEL_MLP = 0, 1, 2, 3
 DIAG = {"V_tot": 0, "V_dep": 1, "sum_Fp": 2, "S_b": 5, "S_f": 8, "E_f": 11, "n_clamped": 12,
-        "n_outside": 13, "max_phi": 14, "n_fallback": 15}
-DIAG_LEN = 16
+        "n_outside": 13, "max_phi": 14, "n_fallback": 15, "mlp_err2": 16, "mlp_ref2": 17, "mlp_nsamp": 18}
+DIAG_LEN = 19
+MLP_NFEAT = 193
+MLP_NPARAM = 58243
 
 
 class CoupleError(RuntimeError):
@@ -46,20 +53,26 @@ class _Config(C.Structure):
                 ("rho_f", C.c_double), ("mu_f", C.c_double), ("rho_p", C.c_double), ("eps_min", C.c_double),
                 ("phi_fp64", C.c_double), ("deposit", C.c_int32), ("precision", C.c_int32),
                 ("vel_source", C.c_int32), ("advect", C.c_int32), ("dt", C.c_double),
-                ("max_particles", C.c_int64)]
+                ("max_particles", C.c_int64), ("mlp_tol", C.c_double), ("mlp_period", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class _Inputs(C.Structure):
     _fields_ = [("n", C.c_int64), ("pos", C.c_void_p), ("vel", C.c_void_p), ("diam", C.c_void_p),
                 ("fine_u", C.c_void_p), ("fine_v", C.c_void_p), ("fine_w", C.c_void_p), ("fine_p", C.c_void_p),
-                ("uf_given", C.c_void_p)]
+                ("uf_given", C.c_void_p), ("step", C.c_int64)]
 
 
 class _Outputs(C.Structure):
     _fields_ = [("drag", C.c_void_p), ("beta", C.c_void_p), ("cell", C.c_void_p), ("perm", C.c_void_p),
                 ("count", C.c_void_p), ("start", C.c_void_p), ("bulk_phi", C.c_void_p), ("bulk_F", C.c_void_p),
                 ("bulk_U", C.c_void_p), ("bulk_P", C.c_void_p), ("bulk_G", C.c_void_p),
-                ("fine_eps", C.c_void_p), ("fine_F", C.c_void_p), ("diag", C.c_void_p)]
+                ("fine_eps", C.c_void_p), ("fine_F", C.c_void_p), ("diag", C.c_void_p), ("uf", C.c_void_p)]
+
+
+class _MlpConfig(C.Structure):
+    _fields_ = [("max_batch", C.c_int64), ("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double),
+                ("eps", C.c_double)]
 
 
 class _KernelStat(C.Structure):
@@ -83,6 +96,28 @@ def _load():
     L.couple_timing_begin.restype = C.c_int
     L.couple_timing_end.argtypes = [C.c_void_p, C.POINTER(_KernelStat), C.c_int32, C.POINTER(C.c_int32)]
     L.couple_timing_end.restype = C.c_int
+    P, I64, I = C.c_void_p, C.c_int64, C.c_int
+    sigs = {
+        "couple_mlp_init": [C.POINTER(_MlpConfig), C.POINTER(C.c_void_p)],
+        "couple_mlp_free": [P],
+        "couple_mlp_set_params": [P, P],
+        "couple_mlp_set_norm": [P, P, P, P],
+        "couple_mlp_fit_norm": [P, P, P, I64, P],
+        "couple_mlp_get_state": [P, P, P, P, P, P, P, P],
+        "couple_mlp_set_state": [P, P, P, P, I64, P, P, P],
+        "couple_mlp_forward": [P, P, I64, P, P],
+        "couple_mlp_grads": [P, P, P, I64, P, I64, P, P, P],
+        "couple_mlp_adam": [P, P, P],
+        "couple_mlp_train_step": [P, P, P, I64, P, I64, P, P],
+        "couple_mlp_features": [C.POINTER(_Config), I64, P, P, P, P, P, P, P, I64, P, P, P, P],
+        "couple_set_mlp": [P, P],
+    }
+    for name, args in sigs.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = I
+    L.couple_mlp_last_error.argtypes = [P]
+    L.couple_mlp_last_error.restype = C.c_char_p
     return L
 
 
@@ -106,6 +141,8 @@ class Config:
     advect: int = 0
     dt: float = 0.0
     max_particles: int = 0
+    mlp_tol: float = 1.0e-3
+    mlp_period: int = 100
 
     def to_c(self):
         c = _Config()
@@ -116,6 +153,7 @@ class Config:
         c.eps_min, c.phi_fp64 = float(self.eps_min), float(self.phi_fp64)
         c.deposit, c.precision, c.vel_source = int(self.deposit), int(self.precision), int(self.vel_source)
         c.advect, c.dt, c.max_particles = int(self.advect), float(self.dt), int(self.max_particles)
+        c.mlp_tol, c.mlp_period, c.reserved = float(self.mlp_tol), int(self.mlp_period), 0
         return c
 
     @property
@@ -168,16 +206,21 @@ def couple_step(h, inputs: dict, outputs: dict, stream=None):
     ``couple_inputs``/``couple_outputs`` to device tensors (or None)."""
     i = _Inputs()
     i.n = int(inputs["n"])
+    i.step = int(inputs.get("step", 0))
     for k in ("pos", "vel", "diam", "fine_u", "fine_v", "fine_w", "fine_p", "uf_given"):
         setattr(i, k, _ptr(inputs.get(k)))
     o = _Outputs()
     for k, _ in _Outputs._fields_:
         setattr(o, k, _ptr(outputs.get(k)))
+    _check(_lib.couple_step(h, C.byref(i), C.byref(o), _stream(stream)), h)
+
+
+def _stream(stream):
     if stream is None:
         stream = torch.cuda.current_stream().cuda_stream
     elif isinstance(stream, torch.cuda.Stream):
         stream = stream.cuda_stream
-    _check(_lib.couple_step(h, C.byref(i), C.byref(o), C.c_void_p(stream)), h)
+    return C.c_void_p(stream)
 
 
 def couple_timing_begin(h, max_steps):
@@ -193,8 +236,9 @@ def couple_timing_end(h):
     return {stats[i].name.decode(): (int(stats[i].launches), float(stats[i].total_ms)) for i in range(n.value)}
 
 
-def alloc_outputs(cfg: Config, n: int, device="cuda", beta=True):
-    """Device tensors for every output of a step with ``n`` particles."""
+def alloc_outputs(cfg: Config, n: int, device="cuda", beta=True, uf=False):
+    """Device tensors for every output of a step with ``n`` particles (``uf``:
+    also the fluid velocity used by the drag)."""
     dt = cfg.dtype
     nb, nf = cfg.nb, cfg.nf
     e = dict(device=device)
@@ -213,13 +257,15 @@ def alloc_outputs(cfg: Config, n: int, device="cuda", beta=True):
         "fine_eps": torch.empty((nf[2], nf[1], nf[0]), dtype=dt, **e),
         "fine_F": torch.empty((3, nf[2], nf[1], nf[0]), dtype=dt, **e),
         "diag": torch.empty((DIAG_LEN,), dtype=torch.float64, **e),
+        "uf": torch.empty((n, 3), dtype=dt, **e) if uf else None,
     }
 
 
 def diag_dict(diag_tensor):
     d = diag_tensor.detach().cpu().tolist()
     return {"V_tot": d[0], "V_dep": d[1], "sum_Fp": d[2:5], "S_b": d[5:8], "S_f": d[8:11], "E_f": d[11],
-            "n_clamped": d[12], "n_outside": d[13], "max_phi": d[14], "n_fallback": d[15]}
+            "n_clamped": d[12], "n_outside": d[13], "max_phi": d[14], "n_fallback": d[15],
+            "mlp_err2": d[16], "mlp_ref2": d[17], "mlp_nsamp": d[18]}
 
 
 class Coupler:
@@ -231,14 +277,14 @@ class Coupler:
         self.h = couple_init(cfg)
         self.out = None
 
-    def step(self, pos, vel, diam, fine, uf_given=None, out=None, beta=True, stream=None):
+    def step(self, pos, vel, diam, fine, uf_given=None, out=None, beta=True, stream=None, step=0, uf=False):
         n = pos.shape[0]
         if out is None:
-            if self.out is None or self.out["drag"].shape[0] != n:
-                self.out = alloc_outputs(self.cfg, n, device=pos.device, beta=beta)
+            if (self.out is None or self.out["drag"].shape[0] != n or (uf and self.out["uf"] is None)):
+                self.out = alloc_outputs(self.cfg, n, device=pos.device, beta=beta, uf=uf)
             out = self.out
         inputs = {"n": n, "pos": pos, "vel": vel, "diam": diam, "fine_u": fine[0], "fine_v": fine[1],
-                  "fine_w": fine[2], "fine_p": fine[3], "uf_given": uf_given}
+                  "fine_w": fine[2], "fine_p": fine[3], "uf_given": uf_given, "step": step}
         couple_step(self.h, inputs, out, stream=stream)
         return out
 
@@ -246,6 +292,118 @@ class Coupler:
         if self.h is not None:
             couple_free(self.h)
             self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---- learned velocity surrogate (include/couple_mlp.h) -------------------------
+
+def couple_mlp_last_error(m):
+    s = _lib.couple_mlp_last_error(m)
+    return s.decode() if s else ""
+
+
+def _mcheck(code, m):
+    if code != COUPLE_OK:
+        raise CoupleError(code, couple_mlp_last_error(m))
+
+
+def _host(a, dtype):
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data
+
+
+def couple_mlp_init(max_batch, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    c = _MlpConfig(int(max_batch), float(lr), float(beta1), float(beta2), float(eps))
+    m = C.c_void_p()
+    _mcheck(_lib.couple_mlp_init(C.byref(c), C.byref(m)), None)
+    return m
+
+
+def couple_mlp_free(m):
+    if m is not None:
+        _mcheck(_lib.couple_mlp_free(m), None)
+
+
+def couple_set_mlp(h, m):
+    _check(_lib.couple_set_mlp(h, m), h)
+
+
+def couple_mlp_features(cfg: Config, pos, diam, bulk_phi, bulk_U, bulk_G, feat, u_fine=None, sel=None,
+                        u_bulk=None, resid=None, stream=None):
+    """Raw surrogate features (and optionally bulk velocity and residual) of the
+    particles ``sel`` (all when None) into device tensors."""
+    c = cfg.to_c()
+    n = pos.shape[0]
+    nsel = n if sel is None else sel.shape[0]
+    _mcheck(_lib.couple_mlp_features(C.byref(c), n, _ptr(pos), _ptr(diam), _ptr(bulk_phi), _ptr(bulk_U),
+                                     _ptr(bulk_G), _ptr(u_fine), _ptr(sel), nsel, _ptr(feat), _ptr(u_bulk),
+                                     _ptr(resid), _stream(stream)), None)
+
+
+class Mlp:
+    """A surrogate network handle (device state owned by the library)."""
+
+    def __init__(self, max_batch, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.m = couple_mlp_init(max_batch, lr, beta1, beta2, eps)
+        self.max_batch = int(max_batch)
+
+    def set_params(self, params):
+        a, p = _host(params, "float32")
+        assert a.size == MLP_NPARAM
+        _mcheck(_lib.couple_mlp_set_params(self.m, p), self.m)
+
+    def set_norm(self, mean, std, scale):
+        a, pa = _host(mean, "float64")
+        b, pb = _host(std, "float64")
+        c, pc = _host(scale, "float64")
+        _mcheck(_lib.couple_mlp_set_norm(self.m, pa, pb, pc), self.m)
+
+    def fit_norm(self, feat, resid, stream=None):
+        _mcheck(_lib.couple_mlp_fit_norm(self.m, _ptr(feat), _ptr(resid), feat.shape[0], _stream(stream)), self.m)
+
+    def get_state(self):
+        import numpy as np
+        p = np.empty(MLP_NPARAM, np.float32)
+        mm = np.empty(MLP_NPARAM, np.float32)
+        vv = np.empty(MLP_NPARAM, np.float32)
+        t = C.c_int64(0)
+        mean = np.empty(MLP_NFEAT)
+        std = np.empty(MLP_NFEAT)
+        sc = np.empty(3)
+        _mcheck(_lib.couple_mlp_get_state(self.m, p.ctypes.data, mm.ctypes.data, vv.ctypes.data, C.byref(t),
+                                          mean.ctypes.data, std.ctypes.data, sc.ctypes.data), self.m)
+        return {"params": p, "m": mm, "v": vv, "step": t.value, "mean": mean, "std": std, "scale": sc}
+
+    def set_state(self, st):
+        arrs = [_host(st[k], "float32") for k in ("params", "m", "v")] + \
+               [_host(st[k], "float64") for k in ("mean", "std", "scale")]
+        _mcheck(_lib.couple_mlp_set_state(self.m, arrs[0][1], arrs[1][1], arrs[2][1], int(st["step"]), arrs[3][1],
+                                          arrs[4][1], arrs[5][1]), self.m)
+
+    def forward(self, feat, y, stream=None):
+        _mcheck(_lib.couple_mlp_forward(self.m, _ptr(feat), feat.shape[0], _ptr(y), _stream(stream)), self.m)
+
+    def grads(self, feat, resid, B, grads, idx=None, loss=None, stream=None):
+        _mcheck(_lib.couple_mlp_grads(self.m, _ptr(feat), _ptr(resid), feat.shape[0], _ptr(idx), int(B),
+                                      _ptr(grads), _ptr(loss), _stream(stream)), self.m)
+
+    def adam(self, grads, stream=None):
+        _mcheck(_lib.couple_mlp_adam(self.m, _ptr(grads), _stream(stream)), self.m)
+
+    def train_step(self, feat, resid, B, idx=None, loss=None, stream=None):
+        _mcheck(_lib.couple_mlp_train_step(self.m, _ptr(feat), _ptr(resid), feat.shape[0], _ptr(idx), int(B),
+                                           _ptr(loss), _stream(stream)), self.m)
+
+    def close(self):
+        if self.m is not None:
+            couple_mlp_free(self.m)
+            self.m = None
 
     def __del__(self):
         try:

@@ -6,7 +6,9 @@
 #include <vector>
 
 #include "couple.h"
+#include "couple_mlp.h"
 #include "launch.hpp"
+#include "mlp_state.hpp"
 
 using namespace cpl;
 
@@ -17,6 +19,8 @@ struct couple_handle {
     int64_t part_stride = 0;
     SortScratch sort{};
     void *sp = nullptr, *uf4 = nullptr, *plo = nullptr, *dep = nullptr;
+    float4 *fgrid = nullptr;        // VEL_MLP: packed bulk features
+    const couple_mlp *mlp = nullptr;
     double *part = nullptr;
     // per-kernel timing
     Marker mk;
@@ -42,11 +46,12 @@ static void destroy_events(couple_handle *h) {
 static void release(couple_handle *h) {
     destroy_events(h);
     void *ptrs[] = {h->sort.keys_a, h->sort.keys_b, h->sort.vals_a, h->sort.vals_b, h->sort.hist,
-                    h->sort.totals, h->sp, h->uf4, h->plo, h->dep, h->part};
+                    h->sort.totals, h->sp, h->uf4, h->plo, h->dep, h->part, h->fgrid};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     h->sort = SortScratch{};
     h->sp = h->uf4 = h->plo = h->dep = nullptr;
+    h->fgrid = nullptr;
     h->part = nullptr;
 }
 
@@ -71,8 +76,15 @@ static std::string validate(const couple_config *c) {
     if (!(c->deposit == COUPLE_NGP || c->deposit == COUPLE_CIC)) return "deposit must be COUPLE_NGP or COUPLE_CIC";
     if (!(c->precision == COUPLE_FP64 || c->precision == COUPLE_FP32_KAHAN || c->precision == COUPLE_FP32_NAIVE))
         return "unknown precision";
-    if (!(c->vel_source == COUPLE_VEL_FINE || c->vel_source == COUPLE_VEL_BULK || c->vel_source == COUPLE_VEL_GIVEN))
+    if (!(c->vel_source == COUPLE_VEL_FINE || c->vel_source == COUPLE_VEL_BULK || c->vel_source == COUPLE_VEL_GIVEN ||
+          c->vel_source == COUPLE_VEL_MLP))
         return "unknown vel_source";
+    if (c->vel_source == COUPLE_VEL_MLP) {
+        if (c->precision == COUPLE_FP64) return "vel_source MLP needs an FP32 precision";
+        if (!(std::isfinite(c->mlp_tol) && c->mlp_tol >= 0.0)) return "mlp_tol must be finite and >= 0";
+        if (c->mlp_period < 1) return "mlp_period must be >= 1";
+    }
+    if (c->reserved != 0) return "reserved must be 0";
     if (!(c->advect == 0 || c->advect == 1)) return "advect must be 0 or 1";
     if (c->advect && !(std::isfinite(c->dt) && c->dt >= 0.0)) return "dt must be finite and >= 0";
     if (c->max_particles < 0 || c->max_particles >= (int64_t(1) << 31) - 1)
@@ -110,7 +122,8 @@ extern "C" int couple_init(const couple_config *cfg, couple_handle **out) {
     // grid of any kernel that writes partials
     const int64_t dblk = deposit_blocks(cfg->nb, h->ncell, cfg->deposit == COUPLE_CIC);
     h->part_stride = 1;
-    for (int64_t b : {pblk, cblk, ntile, dblk})
+    const int64_t mblk = mlp_check_blocks(bricks_of(cfg->nb));
+    for (int64_t b : {pblk, cblk, ntile, dblk, mblk})
         if (b > h->part_stride) h->part_stride = b;
     bool ok = dev_alloc(&h->sort.keys_a, sizeof(uint32_t) * nmax) && dev_alloc(&h->sort.keys_b, sizeof(uint32_t) * nmax) &&
               dev_alloc(&h->sort.vals_a, sizeof(uint32_t) * nmax) && dev_alloc(&h->sort.vals_b, sizeof(uint32_t) * nmax) &&
@@ -118,7 +131,8 @@ extern "C" int couple_init(const couple_config *cfg, couple_handle **out) {
               dev_alloc(&h->sp, 4 * fsz * nmax) && dev_alloc(&h->uf4, 4 * fsz * nmax) &&
               dev_alloc(&h->plo, fsz * h->ncell) &&
               dev_alloc(&h->dep, (cfg->deposit == COUPLE_CIC ? 27 : 1) * fsz * h->ncell) &&
-              dev_alloc(&h->part, sizeof(double) * (SL_COUNT * h->part_stride + SL_COUNT * 64));
+              dev_alloc(&h->part, sizeof(double) * (SL_COUNT * h->part_stride + SL_COUNT * 64)) &&
+              (cfg->vel_source != COUPLE_VEL_MLP || dev_alloc(&h->fgrid, sizeof(float4) * 2 * h->ncell));
     if (!ok) {
         release(h);
         delete h;
@@ -201,12 +215,26 @@ static int step_impl(couple_handle *h, const couple_inputs *in, couple_outputs *
     a.part = h->part;
     a.part_stride = h->part_stride;
     a.mk = &h->mk;
+    a.uf_out = (T *)out->uf;
+    a.net = MlpNet{};
+    if (h->mlp) {
+        for (int l = 0; l < 4; ++l) a.net.wt[l] = h->mlp->net.wt[l];
+        a.net.params = h->mlp->net.params;
+        a.net.mean_inv = h->mlp->net.mean_inv;
+        for (int k = 0; k < 3; ++k) a.net.scale[k] = (float)h->mlp->scale[k];
+    }
+    a.fgrid = h->fgrid;
+    a.step = in->step;
+    a.mlp_period = c.mlp_period > 0 ? c.mlp_period : 1;
+    a.mlp_tol = (float)c.mlp_tol;
+    a.n_bricks = bricks_of(c.nb);
 
     (void)hipGetLastError();  // clear a stale error so that it is not reported as ours
     const uint32_t *skeys = nullptr;
     hipError_t e = launch_bin_sort<T>(a.pos, a.n, a.g, out->cell, out->perm, out->start, out->count, h->sort,
                                       h->part + SL_NOUT * h->part_stride, &skeys, &h->mk, st);
     if (e != hipSuccess) return fail(h, COUPLE_EHIP, std::string("couple_step: sort launch failed: ") + hipGetErrorString(e));
+    a.keys = skeys;
     e = launch_stages<T>(a, st);
     if (e != hipSuccess) return fail(h, COUPLE_EHIP, std::string("couple_step: stage launch failed: ") + hipGetErrorString(e));
     return COUPLE_OK;
@@ -229,6 +257,8 @@ extern "C" int couple_step(couple_handle *h, const couple_inputs *in, couple_out
         if (c.vel_source == COUPLE_VEL_GIVEN && !in->uf_given)
             return fail(h, COUPLE_EINVAL, "couple_step: vel_source GIVEN needs uf_given");
     }
+    if (c.vel_source == COUPLE_VEL_MLP && !h->mlp)
+        return fail(h, COUPLE_ESTATE, "couple_step: vel_source MLP needs a network (couple_set_mlp)");
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (c.precision == COUPLE_FP64) return step_impl<double>(h, in, out, st);
     return step_impl<float>(h, in, out, st);
@@ -291,5 +321,11 @@ extern "C" int couple_timing_end(couple_handle *h, couple_kernel_stat *stats, in
     }
     *n_stats = nout;
     destroy_events(h);
+    return COUPLE_OK;
+}
+
+extern "C" int couple_set_mlp(couple_handle *h, const couple_mlp *m) {
+    if (!h) return fail(nullptr, COUPLE_EINVAL, "couple_set_mlp: NULL handle");
+    h->mlp = m;
     return COUPLE_OK;
 }

@@ -14,7 +14,8 @@ constexpr double kPi = 3.14159265358979323846;
 // workgroup; the final reduction sums every slot in a fixed order.
 enum Slot {
     SL_VTOT = 0, SL_PHISUM = 1, SL_FP = 2, SL_FB = 5, SL_FF = 8, SL_EPSF = 11,
-    SL_NCLAMP = 12, SL_NOUT = 13, SL_MAXPHI = 14, SL_NFALL = 15, SL_COUNT = 16
+    SL_NCLAMP = 12, SL_NOUT = 13, SL_MAXPHI = 14, SL_NFALL = 15,
+    SL_MLPERR = 16, SL_MLPREF = 17, SL_MLPSAMP = 18, SL_COUNT = 19
 };
 
 template <typename T> struct V4;
@@ -101,6 +102,27 @@ template <typename T> __device__ __forceinline__ T axis_weight(const Axis<T> &a,
 // Containing-cell index along one axis: floor(x * s), clamped; x = L -> n - 1.
 template <typename T> __device__ __forceinline__ int cell_axis(T x, T s, int n) {
     return clampi((int)dfloor(x * s), n);
+}
+
+// Bulk pressure gradient at cell c: central differences, one-sided at the
+// walls, taken in FP64 of the compensated pressure hi + lo (differencing the
+// rounded hi alone would lose ulp(P)/h).
+template <typename T>
+__device__ __forceinline__ void gradient_at(int64_t c, int cx, int cy, int cz, const int nb[3], const T hb[3],
+                                            const T *__restrict__ P, const T *__restrict__ Plo, T out[3]) {
+    const int idx[3] = {cx, cy, cz};
+    const int64_t stride[3] = {1, nb[0], (int64_t)nb[0] * nb[1]};
+    auto pv = [&](int64_t k) { return (double)P[k] + (double)Plo[k]; };
+    for (int a = 0; a < 3; ++a) {
+        double gr;
+        const int nax = nb[a];
+        const double h = (double)hb[a];
+        if (nax == 1) gr = 0.0;
+        else if (idx[a] == 0) gr = (pv(c + stride[a]) - pv(c)) / h;
+        else if (idx[a] == nax - 1) gr = (pv(c) - pv(c - stride[a])) / h;
+        else gr = (pv(c + stride[a]) - pv(c - stride[a])) / (2.0 * h);
+        out[a] = (T)gr;
+    }
 }
 
 // Segment bounds read from `start` (a prefix sum over [0, n]) clamped into

@@ -20,26 +20,14 @@ template <typename T> __device__ __forceinline__ T vol_over_vb(T d, T inv_vb) {
     return (T(kPi / 6.0) * d * d * d) * inv_vb;
 }
 
-// Bulk pressure gradient: central differences, one-sided at the walls, taken in
-// FP64 of the compensated pressure hi + lo (differencing the rounded hi alone
-// would lose ulp(P)/h).
+// Bulk pressure gradient of cell c written to G ([3][ncell]).
 template <typename T>
 __device__ __forceinline__ void write_gradient(int64_t c, int cx, int cy, int cz, const Geo<T> &g,
                                                const T *__restrict__ P, const T *__restrict__ Plo,
                                                T *__restrict__ G) {
-    const int idx[3] = {cx, cy, cz};
-    const int64_t stride[3] = {1, g.nb[0], (int64_t)g.nb[0] * g.nb[1]};
-    auto pv = [&](int64_t k) { return (double)P[k] + (double)Plo[k]; };
-    for (int a = 0; a < 3; ++a) {
-        double gr;
-        const int nax = g.nb[a];
-        const double h = (double)g.hb[a];
-        if (nax == 1) gr = 0.0;
-        else if (idx[a] == 0) gr = (pv(c + stride[a]) - pv(c)) / h;
-        else if (idx[a] == nax - 1) gr = (pv(c) - pv(c - stride[a])) / h;
-        else gr = (pv(c + stride[a]) - pv(c - stride[a])) / (2.0 * h);
-        G[a * g.ncell + c] = (T)gr;
-    }
+    T gr[3];
+    gradient_at(c, cx, cy, cz, g.nb, g.hb, P, Plo, gr);
+    for (int a = 0; a < 3; ++a) G[a * g.ncell + c] = gr[a];
 }
 
 // ---------------------------------------------------------------------------

@@ -42,6 +42,14 @@ hipError_t launch_bin_sort(const T *pos, int64_t n, const Geo<T> &g, int32_t *ce
                            int32_t *count, const SortScratch &s, double *part_nout, const uint32_t **sorted_keys,
                            Marker *mk, hipStream_t st);
 
+// Device state of the learned surrogate as the step kernels read it.
+struct MlpNet {
+    const uint16_t *wt[4];   // BF16 W^T of each layer, [padded fan-out][padded fan-in]
+    const float *params;     // FP32 master parameters (biases are read from here)
+    const float *mean_inv;   // [2][224] feature mean, then 1/std (0 in the padding)
+    float scale[3];          // per-component scale of the residual
+};
+
 // Everything the stage kernels need for one step.
 template <typename T> struct StepArgs {
     Geo<T> g;
@@ -49,7 +57,7 @@ template <typename T> struct StepArgs {
     int ratio;
     int cic;           // deposition / gather weights: 1 = CIC, 0 = NGP
     int kahan;         // compensated per-cell sums (FP32 modes)
-    int vel_source;    // 0 fine, 1 bulk, 2 given
+    int vel_source;    // 0 fine, 1 bulk, 2 given, 3 learned surrogate (+ fine fallback)
     int advect;
     T dt, rho_f, mu_f, rho_p, eps_min;
     float phi_fp64;    // FP32 modes: FP64 void fraction above this particle solid fraction
@@ -72,10 +80,29 @@ template <typename T> struct StepArgs {
     double *part;    // [SL_COUNT][max_blocks]
     int64_t part_stride;
     Marker *mk;      // per-kernel event recording (never null)
+    // optional output: fluid velocity used by the drag, [n][3] (input order)
+    T *uf_out;
+    // learned surrogate (vel_source 3)
+    const uint32_t *keys;        // containing cell of each particle in the sorted order
+    MlpNet net;                  // device state of the network
+    float4 *fgrid;               // [ncell][2] packed bulk features (eps, U, G)
+    int64_t step;                // caller's step index: selects the checked sample
+    int mlp_period;              // one particle in mlp_period is checked (id mod period)
+    float mlp_tol;               // brick falls back to the fine lookup above this error
+    int64_t n_bricks;            // 8x8x8-cell bricks of the bulk grid
 };
 
 // Stage launchers (in order of the step).
 template <typename T> hipError_t launch_stages(const StepArgs<T> &a, hipStream_t st);
+
+// Learned-surrogate stages of the step (mlp.hip): packed features and pressure
+// gradient, inference, sampled check with fine fallback.  Each check workgroup
+// writes one partial per MLP diagnostic slot; mlp_check_blocks() is their number.
+void launch_mlp_pack(const StepArgs<float> &a, hipStream_t st);
+void launch_mlp_infer(const StepArgs<float> &a, hipStream_t st);
+void launch_mlp_check(const StepArgs<float> &a, hipStream_t st);
+int64_t mlp_check_blocks(int64_t n_bricks);
+int64_t bricks_of(const int nb[3]);
 
 // Deposition (deposit.hip); each returns the number of workgroups launched
 // (one FP64 partial per workgroup and diagnostic slot).

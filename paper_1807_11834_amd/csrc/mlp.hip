@@ -1,0 +1,828 @@
+// mlp.hip -- the learned velocity surrogate on the gfx950 matrix cores.
+//
+// The surrogate predicts the sub-bulk part of the fluid velocity at a particle
+// (fine-grid lookup minus bulk trilinear interpolation) from the 3x3x3 bulk
+// stencil around its cell, its in-cell offset and its diameter.  All products
+// are v_mfma_f32_16x16x32_bf16: BF16 operands (rounded to nearest even), FP32
+// accumulation.
+//
+// Operand layout of one 16x16x32 product on a 64-lane wave (lane l, n = l % 16,
+// g = l / 16): the A operand lane holds row n and eight contraction slots of
+// group g, the B operand lane holds column n and the same eight slots, and the
+// result lane holds column n, rows 4g .. 4g+3.  Which contraction index a slot
+// stands for is a labelling shared by A and B: any permutation works as long as
+// both operands use it.
+//
+// Products are written "transposed": weights are the A operand (rows = output
+// neurons), activations the B operand (columns = particles).  The result of one
+// layer (column = particle, rows = neurons 4g..4g+3 of a 16-row block) is then
+// already the B operand of the next layer once two row blocks are paired into
+// one 32-wide slot group: slots 0-3 <- rows 32q+4g+j, slots 4-7 <- rows
+// 32q+16+4g+j.  The in-step inference kernel chains the four layers this way in
+// registers, with the weights pre-permuted into that slot order in LDS.
+//
+// Training runs layer by layer over a batch in HBM (natural slot order, rows
+// k = 32q + 8g + i) with transposed copies for the weight-gradient products,
+// whose contraction runs over the batch.  Every reduction has a fixed order.
+#include <type_traits>
+
+#include "common.hpp"
+#include "launch.hpp"
+#include "mlp.hpp"
+#include "sample.hpp"
+
+namespace cpl {
+namespace mlp {
+
+typedef __bf16 bf16x8 __attribute__((__vector_size__(16)));
+typedef float f32x4 __attribute__((__vector_size__(16)));
+
+// float -> bfloat16 bits, round to nearest even (NaN stays NaN).
+__device__ __forceinline__ uint32_t bf16_bits(float x) {
+    uint32_t u = __float_as_uint(x);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+__device__ __forceinline__ uint32_t pack2(float lo, float hi) { return bf16_bits(lo) | (bf16_bits(hi) << 16); }
+__device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
+__device__ __forceinline__ bf16x8 load8(const uint16_t *p) { return as_bf16x8(*reinterpret_cast<const uint4 *>(p)); }
+__device__ __forceinline__ bf16x8 zero8() { return as_bf16x8(make_uint4(0u, 0u, 0u, 0u)); }
+__device__ __forceinline__ f32x4 mma(bf16x8 a, bf16x8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// tanh-form GELU 0.5 z (1 + tanh(sqrt(2/pi) (z + 0.044715 z^3))) and its derivative
+constexpr float kGc = 0.7978845608028654f, kGa = 0.044715f;
+__device__ __forceinline__ float tanh_e(float u) { return 1.f - __fdividef(2.f, __expf(2.f * u) + 1.f); }
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.f + tanh_e(kGc * z * (1.f + kGa * z * z))); }
+__device__ __forceinline__ float gelu_grad(float z) {
+    const float z2 = z * z;
+    const float t = tanh_e(kGc * z * (1.f + kGa * z2));
+    return 0.5f * (1.f + t) + 0.5f * z * (1.f - t * t) * kGc * (1.f + 3.f * kGa * z2);
+}
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+
+// ---------------------------------------------------------------------------
+// Parameter bookkeeping
+// ---------------------------------------------------------------------------
+// Flat parameter index -> (layer, is_weight, k, m).
+__device__ __forceinline__ void decode_param(int64_t i, int &l, bool &w, int &k, int &m) {
+    l = 0;
+    while (l < 3 && i >= off_w(l + 1)) ++l;
+    const int64_t r = i - off_w(l);
+    const int64_t nw = (int64_t)fan_in(l) * fan_out(l);
+    w = r < nw;
+    if (w) {
+        k = (int)(r / fan_out(l));
+        m = (int)(r % fan_out(l));
+    } else {
+        k = 0;
+        m = (int)(r - nw);
+    }
+}
+
+struct WPtrs {
+    uint16_t *wt[4], *wn[4];
+};
+
+__device__ __forceinline__ void write_bf16_copies(const WPtrs &w, int l, int k, int m, float p) {
+    const uint16_t b = (uint16_t)bf16_bits(p);
+    w.wt[l][(int64_t)m * kpad(l) + k] = b;
+    if (l > 0) w.wn[l][(int64_t)k * cpad(l) + m] = b;
+}
+
+__global__ __launch_bounds__(kBlock) void k_cast(const float *__restrict__ params, WPtrs w) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= kNParam) return;
+    int l, k, m;
+    bool isw;
+    decode_param(i, l, isw, k, m);
+    if (isw) write_bf16_copies(w, l, k, m, params[i]);
+}
+
+// Adam (bias-corrected) on the FP32 master parameters, then the BF16 copies.
+__global__ __launch_bounds__(kBlock) void k_adam(const float *__restrict__ grads, float *__restrict__ params,
+                                                 float *__restrict__ mom1, float *__restrict__ mom2, WPtrs w,
+                                                 float lr, float b1, float omb1, float b2, float omb2, float eps,
+                                                 float c1, float c2) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= kNParam) return;
+    const float g = grads[i];
+    const float m = b1 * mom1[i] + omb1 * g;
+    const float v = b2 * mom2[i] + omb2 * g * g;
+    const float p = params[i] - lr * (m / c1) / (sqrtf(v / c2) + eps);
+    mom1[i] = m;
+    mom2[i] = v;
+    params[i] = p;
+    int l, k, mm;
+    bool isw;
+    decode_param(i, l, isw, k, mm);
+    if (isw) write_bf16_copies(w, l, k, mm, p);
+}
+
+// ---------------------------------------------------------------------------
+// Batch kernels (training and inference on given features)
+// ---------------------------------------------------------------------------
+// X0[b][k] = bf16((feat[row][k] - mean[k]) / std[k]) for k < 193, 0 up to 224;
+// row = idx[b] (or b).  T[b] = resid[row] / scale (optional).
+__global__ __launch_bounds__(kBlock) void k_standardise(const float *__restrict__ feat, const float *__restrict__ resid,
+                                                        const int32_t *__restrict__ idx, int64_t nrows, int64_t B,
+                                                        const float *__restrict__ mean_inv, float is0, float is1,
+                                                        float is2, uint16_t *__restrict__ x0, float *__restrict__ T) {
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= B * kK1) return;
+    const int64_t b = e / kK1;
+    const int k = (int)(e % kK1);
+    int64_t row = idx ? (int64_t)idx[b] : b;
+    if (row < 0 || row >= nrows) row = 0;   // documented: indices must be in range; keeps loads in bounds
+    float v = 0.f;
+    if (k < kFeat) v = (feat[row * kFeat + k] - mean_inv[k]) * mean_inv[kK1 + k];
+    x0[e] = (uint16_t)bf16_bits(v);
+    if (T && k < 4) {
+        const float is[3] = {is0, is1, is2};
+        T[b * 4 + k] = (k < 3) ? resid[row * 3 + k] * is[k] : 0.f;
+    }
+}
+
+// One dense layer for 16-row tiles, one wave per tile:
+//   Z = X W + b (X [B][32 KB] BF16, W^T [16 MB][32 KB] BF16), then
+//   hidden: Z -> z (FP32), gelu(Z) -> h (BF16), both [B][16 MB];
+//   output (MB = 1): Z -> y [B][16]; with targets T [B][4] also the loss partial
+//   of the tile and dY = (Y - T) / B as FP32 [B][16] and BF16 [B][32].
+template <int KB, int MB, bool OUT>
+__global__ __launch_bounds__(kBlock) void k_dense(const uint16_t *__restrict__ X, const uint16_t *__restrict__ WT,
+                                                  const float *__restrict__ bias, int M, int64_t B,
+                                                  float *__restrict__ Z, uint16_t *__restrict__ H,
+                                                  const float *__restrict__ T, float inv_b, float *__restrict__ dzf,
+                                                  uint16_t *__restrict__ dz, double *__restrict__ loss_part) {
+    constexpr int KP = 32 * KB, MP = 16 * MB;
+    const int lane = lane_id(), n = lane & 15, g = lane >> 4;
+    const int64_t ntile = (B + 15) / 16;
+    const int64_t tile = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    if (tile >= ntile) return;   // whole wave
+    const int64_t b = tile * 16 + n;
+    const bool valid = b < B;
+    bf16x8 xb[KB];
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) xb[kb] = valid ? load8(X + b * KP + 32 * kb + 8 * g) : zero8();
+    double lp = 0.0;
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) acc = mma(load8(WT + (int64_t)(16 * mb + n) * KP + 32 * kb + 8 * g), xb[kb], acc);
+        const int m0 = 16 * mb + 4 * g;
+        float z[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) z[j] = acc[j] + ((m0 + j < M) ? bias[m0 + j] : 0.f);
+        if constexpr (!OUT) {
+            if (valid) {
+                *reinterpret_cast<float4 *>(Z + b * MP + m0) = make_float4(z[0], z[1], z[2], z[3]);
+                *reinterpret_cast<uint2 *>(H + b * MP + m0) =
+                    make_uint2(pack2(gelu(z[0]), gelu(z[1])), pack2(gelu(z[2]), gelu(z[3])));
+            }
+        } else {
+            if (valid) *reinterpret_cast<float4 *>(Z + b * MP + m0) = make_float4(z[0], z[1], z[2], z[3]);
+            if (T) {
+                float d[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const float dd = (valid && m0 + j < M) ? z[j] - T[b * 4 + m0 + j] : 0.f;
+                    lp += 0.5 * (double)dd * (double)dd;
+                    d[j] = dd * inv_b;
+                }
+                if (valid) {
+                    *reinterpret_cast<float4 *>(dzf + b * MP + m0) = make_float4(d[0], d[1], d[2], d[3]);
+                    *reinterpret_cast<uint2 *>(dz + b * 32 + m0) = make_uint2(pack2(d[0], d[1]), pack2(d[2], d[3]));
+                }
+            }
+        }
+    }
+    if constexpr (OUT) {
+        if (T) {
+            lp = wave_sum(lp);
+            if (lane == 0) loss_part[tile] = lp * (double)inv_b;
+        }
+    }
+}
+
+// Input gradient of a layer times gelu' of the previous pre-activation:
+//   dZp = (dZ W^T) .* gelu'(Zp),  dZ [B][32 KC] BF16, W [16 NB][32 KC] BF16,
+//   Zp [B][16 NB] FP32 -> dZp as FP32 and BF16 [B][16 NB].
+template <int KC, int NB>
+__global__ __launch_bounds__(kBlock) void k_dense_bwd(const uint16_t *__restrict__ dZ, const uint16_t *__restrict__ W,
+                                                      const float *__restrict__ Zp, int64_t B,
+                                                      float *__restrict__ dzpf, uint16_t *__restrict__ dzp) {
+    constexpr int MC = 32 * KC, KI = 16 * NB;
+    const int lane = lane_id(), n = lane & 15, g = lane >> 4;
+    const int64_t ntile = (B + 15) / 16;
+    const int64_t tile = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    if (tile >= ntile) return;
+    const int64_t b = tile * 16 + n;
+    const bool valid = b < B;
+    bf16x8 db[KC];
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc) db[kc] = valid ? load8(dZ + b * MC + 32 * kc + 8 * g) : zero8();
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc) acc = mma(load8(W + (int64_t)(16 * nb + n) * MC + 32 * kc + 8 * g), db[kc], acc);
+        const int k0 = 16 * nb + 4 * g;
+        if (valid) {
+            const float4 zp = *reinterpret_cast<const float4 *>(Zp + b * KI + k0);
+            const float d0 = acc[0] * gelu_grad(zp.x), d1 = acc[1] * gelu_grad(zp.y);
+            const float d2 = acc[2] * gelu_grad(zp.z), d3 = acc[3] * gelu_grad(zp.w);
+            *reinterpret_cast<float4 *>(dzpf + b * KI + k0) = make_float4(d0, d1, d2, d3);
+            *reinterpret_cast<uint2 *>(dzp + b * KI + k0) = make_uint2(pack2(d0, d1), pack2(d2, d3));
+        }
+    }
+}
+
+// BF16 transpose src [R][C] -> dst [C][R] through LDS (64 x 64 tiles).
+__global__ __launch_bounds__(kBlock) void k_transpose(const uint16_t *__restrict__ src, int64_t R, int64_t C,
+                                                      uint16_t *__restrict__ dst) {
+    __shared__ uint16_t t[64][66];
+    const int64_t r0 = (int64_t)blockIdx.x * 64, c0 = (int64_t)blockIdx.y * 64;
+    for (int i = threadIdx.x; i < 64 * 64; i += kBlock) {
+        const int rr = i / 64, cc = i % 64;
+        t[rr][cc] = (r0 + rr < R && c0 + cc < C) ? src[(r0 + rr) * C + c0 + cc] : (uint16_t)0;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 64 * 64; i += kBlock) {
+        const int cc = i / 64, rr = i % 64;
+        if (c0 + cc < C && r0 + rr < R) dst[(c0 + cc) * R + r0 + rr] = t[rr][cc];
+    }
+}
+
+// Weight and bias gradients of one layer over a chunk of rows:
+//   part_w[c][m][k] = sum_{b in chunk} dZ[b][m] H[b][k]   (BF16 x BF16, FP32 accumulate)
+//   part_b[c][m]    = sum_{b in chunk} dZf[b][m]          (FP32 values, FP64 sum)
+// from the transposed copies dZT [16 MT][B] and HT [16 KT][B].  Rows in chunks
+// of kChunk; B is a multiple of 32.
+template <int MT, int KT>
+__global__ __launch_bounds__(kBlock) void k_wgrad(const uint16_t *__restrict__ dZT, const uint16_t *__restrict__ HT,
+                                                  const float *__restrict__ dzf, int64_t B,
+                                                  float *__restrict__ part_w, double *__restrict__ part_b) {
+    constexpr int MP = 16 * MT, KP = 16 * KT;
+    const int lane = lane_id(), n = lane & 15, g = lane >> 4, wave = threadIdx.x >> 6;
+    const int64_t c = blockIdx.x;
+    const int64_t b0 = c * kChunk, b1 = (b0 + kChunk < B) ? b0 + kChunk : B;
+    for (int tt = wave; tt < MT * KT; tt += kWavesPerBlock) {
+        const int mt = tt / KT, kt = tt % KT;
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        const uint16_t *pa = dZT + (int64_t)(16 * mt + n) * B + 8 * g;
+        const uint16_t *pb = HT + (int64_t)(16 * kt + n) * B + 8 * g;
+        for (int64_t bb = b0; bb < b1; bb += 32) acc = mma(load8(pa + bb), load8(pb + bb), acc);
+        float *o = part_w + (c * MP + 16 * mt + 4 * g) * KP + 16 * kt + n;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) o[(int64_t)j * KP] = acc[j];
+    }
+    for (int m = threadIdx.x; m < MP; m += kBlock) {
+        double s = 0.0;
+        for (int64_t b = b0; b < b1; ++b) s += (double)dzf[b * MP + m];
+        part_b[c * MP + m] = s;
+    }
+}
+
+struct GradParts {
+    const float *w[4];
+    const double *b[4];
+};
+
+// Flat gradient vector from the per-chunk partials (chunks summed in order).
+__global__ __launch_bounds__(kBlock) void k_reduce_grads(GradParts parts, int64_t nchunk, float *__restrict__ grads) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= kNParam) return;
+    int l, k, m;
+    bool isw;
+    decode_param(i, l, isw, k, m);
+    double s = 0.0;
+    if (isw) {
+        const int MP = mpad(l), KP = kpad(l);
+        for (int64_t c = 0; c < nchunk; ++c) s += (double)parts.w[l][(c * MP + m) * KP + k];
+    } else {
+        const int MP = mpad(l);
+        for (int64_t c = 0; c < nchunk; ++c) s += parts.b[l][c * MP + m];
+    }
+    grads[i] = (float)s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_sum_loss(const double *__restrict__ part, int64_t n, float *__restrict__ out) {
+    __shared__ double red[kWavesPerBlock];
+    double v = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += kBlock) v += part[i];
+    v = block_sum(v, red);
+    if (threadIdx.x == 0) out[0] = (float)v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_output(const float *__restrict__ y16, int64_t B, float *__restrict__ y) {
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e < B * 3) y[e] = y16[(e / 3) * 16 + e % 3];
+}
+
+// Column statistics: pass 0 sums x, pass 1 sums (x - mean)^2, per chunk of rows.
+__global__ __launch_bounds__(kBlock) void k_colsum(const float *__restrict__ x, int64_t n, int cols, int64_t rows_per,
+                                                   const double *__restrict__ mean, double *__restrict__ part) {
+    const int c = threadIdx.x;
+    if (c >= cols) return;
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per, r1 = (r0 + rows_per < n) ? r0 + rows_per : n;
+    const double mu = mean ? mean[c] : 0.0;
+    double s = 0.0;
+    for (int64_t r = r0; r < r1; ++r) {
+        const double v = (double)x[r * cols + c] - mu;
+        s += mean ? v * v : v;
+    }
+    part[(int64_t)blockIdx.x * cols + c] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_colfinish(const double *__restrict__ part, int64_t nchunk, int cols,
+                                                      int64_t n, int sq, double *__restrict__ out) {
+    const int c = threadIdx.x;
+    if (c >= cols) return;
+    double s = 0.0;
+    for (int64_t k = 0; k < nchunk; ++k) s += part[k * cols + c];
+    out[c] = sq ? sqrt(s / (double)n) : s / (double)n;
+}
+
+// ---------------------------------------------------------------------------
+// Features of given particles from the bulk fields (training pairs)
+// ---------------------------------------------------------------------------
+// feat[j] = the 193 raw features of particle i = sel[j] (or j): per stencil cell
+// (dz, dy, dx in -1..1, dx fastest, clamped at the walls) eps = 1 - phi, U, G,
+// neighbours minus the centre cell; offsets x * n / L - i; d * n_x / L_x.
+// u_bulk[j] = bulk trilinear velocity; resid[j] = u_fine[i] - u_bulk[j].
+__global__ __launch_bounds__(kBlock) void k_features(Geo<float> g, int64_t n, const float *__restrict__ pos,
+                                                     const float *__restrict__ diam, const float *__restrict__ phi,
+                                                     const float *__restrict__ U, const float *__restrict__ G,
+                                                     const float *__restrict__ u_fine, const int32_t *__restrict__ sel,
+                                                     int64_t nsel, float *__restrict__ feat,
+                                                     float *__restrict__ u_bulk, float *__restrict__ resid) {
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j >= nsel) return;
+    int64_t i = sel ? (int64_t)sel[j] : j;
+    if (i < 0 || i >= n) i = 0;   // documented: entries must be in range; keeps loads in bounds
+    int o = 0;
+    const float x = clamp_coord(pos[3 * i + 0], g.L[0], o), y = clamp_coord(pos[3 * i + 1], g.L[1], o),
+                z = clamp_coord(pos[3 * i + 2], g.L[2], o);
+    const int ix = cell_axis(x, g.sb[0], g.nb[0]), iy = cell_axis(y, g.sb[1], g.nb[1]),
+              iz = cell_axis(z, g.sb[2], g.nb[2]);
+    const int64_t nx = g.nb[0], nxy = (int64_t)g.nb[0] * g.nb[1], nc = g.ncell;
+    const int64_t c0 = ix + nx * iy + nxy * iz;
+    float cen[7] = {1.f - phi[c0], U[c0], U[nc + c0], U[2 * nc + c0], G[c0], G[nc + c0], G[2 * nc + c0]};
+    float *out = feat + j * kFeat;
+    int col = 0;
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int cx = clampi(ix + dx, g.nb[0]), cy = clampi(iy + dy, g.nb[1]), cz = clampi(iz + dz, g.nb[2]);
+                const int64_t c = cx + nx * cy + nxy * cz;
+                const float v[7] = {1.f - phi[c], U[c], U[nc + c], U[2 * nc + c], G[c], G[nc + c], G[2 * nc + c]};
+                const bool centre = (dx == 0 && dy == 0 && dz == 0);
+                for (int k = 0; k < 7; ++k) out[col++] = centre ? cen[k] : v[k] - cen[k];
+            }
+    out[col++] = x * g.sb[0] - (float)ix;
+    out[col++] = y * g.sb[1] - (float)iy;
+    out[col++] = z * g.sb[2] - (float)iz;
+    out[col++] = diam[i] * g.sb[0];
+    if (u_bulk || resid) {
+        const Axis<float> bx = cic_axis(x, g.sb[0], g.nb[0]);
+        const Axis<float> by = cic_axis(y, g.sb[1], g.nb[1]);
+        const Axis<float> bz = cic_axis(z, g.sb[2], g.nb[2]);
+        const int inx = g.nb[0];
+        float ub[3];
+        for (int a = 0; a < 3; ++a) ub[a] = trilin_pairs(U + a * nc, bx, by, bz, inx, nxy);
+        if (u_bulk)
+            for (int a = 0; a < 3; ++a) u_bulk[3 * j + a] = ub[a];
+        if (resid && u_fine)
+            for (int a = 0; a < 3; ++a) resid[3 * j + a] = u_fine[3 * i + a] - ub[a];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// In-step inference: packed bulk features, fused gather + four-layer chain,
+// sampled check with fine fallback
+// ---------------------------------------------------------------------------
+// fgrid[2c] = (1 - phi, U_x, U_y, U_z), fgrid[2c+1] = (G_x, G_y, G_z, 0); G is
+// also written to the bulk gradient output (same values as the source stage).
+__global__ __launch_bounds__(kBlock) void k_pack(StepArgs<float> a) {
+    const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (c >= a.g.ncell) return;
+    int cx, cy, cz;
+    decode_cell(c, a.g.nb, cx, cy, cz);
+    float gr[3];
+    gradient_at(c, cx, cy, cz, a.g.nb, a.g.hb, a.P, a.Plo, gr);
+    const int64_t nc = a.g.ncell;
+    for (int k = 0; k < 3; ++k) a.G[k * nc + c] = gr[k];
+    a.fgrid[2 * c] = make_float4(1.f - a.phi[c], a.U[c], a.U[nc + c], a.U[2 * nc + c]);
+    a.fgrid[2 * c + 1] = make_float4(gr[0], gr[1], gr[2], 0.f);
+}
+
+constexpr int kInfWaves = 4;                    // waves per workgroup
+constexpr int kInfRows = 64;                    // particles per wave and round (4 tiles of 16)
+constexpr int kFrag1 = 8 * 7, kFragH = 8 * 4;   // operand fragments per layer
+constexpr int kFrags = kFrag1 + 2 * kFragH + 4;
+
+struct InferLds {
+    uint4 frag[kFrags][kWave];    // weight fragments in slot order, 16 B per lane
+    float bias[3 * kHid + 16];    // b1, b2, b3, b4 (padded)
+    float mean[kFeat], inv[kFeat];
+};
+
+// Layer-1 slot (kb, g, i) -> feature index: unit u = 4 kb + g is stencil cell u
+// (its 7 channels in slots 0-6) or, for u = 27, the offsets and diameter.
+__device__ __forceinline__ int slot_feature(int kb, int g, int i) {
+    const int u = 4 * kb + g;
+    if (u < 27) return i < 7 ? 7 * u + i : -1;
+    return i < 4 ? 189 + i : -1;
+}
+// Hidden-layer slot (kb, g, i) -> input neuron (result-layout pairing).
+__device__ __forceinline__ int slot_hidden(int kb, int g, int i) {
+    return 32 * kb + (i < 4 ? 4 * g + i : 16 + 4 * g + (i - 4));
+}
+
+// One layer of the chain for 4 tiles: in[t][kb] (KB slot groups) -> 8 row
+// blocks -> gelu -> out[t][4] in the paired slot order.
+template <int KB>
+__device__ __forceinline__ void chain_layer(const InferLds &L, int frag0, const float *bias, const uint4 (&in)[4][KB],
+                                            uint4 (&out)[4][4], int lane, int g) {
+#pragma unroll
+    for (int mb = 0; mb < 8; ++mb) {
+        f32x4 acc[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) {
+            const bf16x8 w = as_bf16x8(L.frag[frag0 + mb * KB + kb][lane]);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) acc[t] = mma(w, as_bf16x8(in[t][kb]), acc[t]);
+        }
+        const int m0 = 16 * mb + 4 * g;
+        const float b0 = bias[m0], b1 = bias[m0 + 1], b2 = bias[m0 + 2], b3 = bias[m0 + 3];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const uint32_t lo = pack2(gelu(acc[t][0] + b0), gelu(acc[t][1] + b1));
+            const uint32_t hi = pack2(gelu(acc[t][2] + b2), gelu(acc[t][3] + b3));
+            if (mb & 1) {
+                out[t][mb >> 1].z = lo;
+                out[t][mb >> 1].w = hi;
+            } else {
+                out[t][mb >> 1].x = lo;
+                out[t][mb >> 1].y = hi;
+            }
+        }
+    }
+}
+
+// Persistent: each workgroup takes one contiguous range of the sorted particles
+// (neighbouring cells: the stencil loads hit L1/L2), each wave 64 particles per
+// round.  Lane (n, g) gathers, for tile t and slot group kb, unit 4 kb + g of
+// particle 16 t + n; it then finishes particle 16 g + n: u = u_bulk + s * y and
+// eps_p, written to uf4[id].
+__global__ __launch_bounds__(kBlock) void k_infer(StepArgs<float> a) {
+    __shared__ InferLds L;
+    const int lane = lane_id(), n = lane & 15, g = lane >> 4, wave = threadIdx.x >> 6;
+    const MlpNet &net = a.net;
+    // weights into LDS in slot order
+    for (int e = threadIdx.x; e < kFrags * kWave * 8; e += kBlock) {
+        const int f = e >> 9, ln = (e >> 3) & 63, i = e & 7;
+        const int r = ln & 15, gg = ln >> 4;
+        uint16_t v = 0;
+        if (f < kFrag1) {
+            const int mb = f / 7, kb = f % 7;
+            const int k = slot_feature(kb, gg, i);
+            if (k >= 0) v = net.wt[0][(16 * mb + r) * kpad(0) + k];
+        } else if (f < kFrag1 + 2 * kFragH) {
+            const int l = (f < kFrag1 + kFragH) ? 1 : 2;
+            const int ff = f - kFrag1 - (l - 1) * kFragH;
+            const int mb = ff / 4, kb = ff % 4;
+            v = net.wt[l][(16 * mb + r) * kpad(l) + slot_hidden(kb, gg, i)];
+        } else {
+            const int kb = f - kFrag1 - 2 * kFragH;
+            v = net.wt[3][r * kpad(3) + slot_hidden(kb, gg, i)];
+        }
+        reinterpret_cast<uint16_t *>(&L.frag[f][ln])[i] = v;
+    }
+    for (int e = threadIdx.x; e < 3 * kHid + 16; e += kBlock) {
+        const int l = e / kHid, m = e % kHid;
+        L.bias[e] = (l < 3) ? net.params[off_b(l) + m] : (m < kOut ? net.params[off_b(3) + m] : 0.f);
+    }
+    for (int e = threadIdx.x; e < kFeat; e += kBlock) {
+        L.mean[e] = net.mean_inv[e];
+        L.inv[e] = net.mean_inv[kK1 + e];
+    }
+    __syncthreads();
+
+    const Geo<float> &geo = a.g;
+    const int64_t per = ((a.n + gridDim.x - 1) / gridDim.x + kInfRows - 1) / kInfRows * kInfRows;
+    const int64_t s_begin = (int64_t)blockIdx.x * per;
+    const int64_t s_end = (s_begin + per < a.n) ? s_begin + per : a.n;
+    const int64_t nx = geo.nb[0], nxy = (int64_t)geo.nb[0] * geo.nb[1];
+    for (int64_t base = s_begin + (int64_t)wave * kInfRows; base < s_end; base += kInfWaves * kInfRows) {
+        uint4 x[4][7];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int64_t s = base + 16 * t + n;
+            const bool valid = s < s_end;
+            const int64_t sc = valid ? s : s_begin;
+            const float4 q = a.sp[sc];
+            int64_t c0 = a.keys[sc];
+            if (c0 < 0 || c0 >= geo.ncell) c0 = 0;
+            int ix, iy, iz;
+            decode_cell(c0, geo.nb, ix, iy, iz);
+            const float4 A0 = a.fgrid[2 * c0], A1 = a.fgrid[2 * c0 + 1];
+#pragma unroll
+            for (int kb = 0; kb < 7; ++kb) {
+                const int u = 4 * kb + g;
+                float v[8];
+                int f0;
+                if (u < 27) {
+                    const int dx = u % 3 - 1, dy = (u / 3) % 3 - 1, dz = u / 9 - 1;
+                    const int64_t c = clampi(ix + dx, geo.nb[0]) + nx * clampi(iy + dy, geo.nb[1]) +
+                                      nxy * clampi(iz + dz, geo.nb[2]);
+                    const float4 B0 = a.fgrid[2 * c], B1 = a.fgrid[2 * c + 1];
+                    if (u == 13) {
+                        v[0] = A0.x; v[1] = A0.y; v[2] = A0.z; v[3] = A0.w;
+                        v[4] = A1.x; v[5] = A1.y; v[6] = A1.z;
+                    } else {
+                        v[0] = B0.x - A0.x; v[1] = B0.y - A0.y; v[2] = B0.z - A0.z; v[3] = B0.w - A0.w;
+                        v[4] = B1.x - A1.x; v[5] = B1.y - A1.y; v[6] = B1.z - A1.z;
+                    }
+                    v[7] = 0.f;
+                    f0 = 7 * u;
+                } else {
+                    v[0] = q.x * geo.sb[0] - (float)ix;
+                    v[1] = q.y * geo.sb[1] - (float)iy;
+                    v[2] = q.z * geo.sb[2] - (float)iz;
+                    v[3] = q.w * geo.sb[0];
+                    v[4] = v[5] = v[6] = v[7] = 0.f;
+                    f0 = 189;
+                }
+                const int nv = (u < 27) ? 7 : 4;
+                float xs[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) xs[i] = (i < nv && valid) ? (v[i] - L.mean[f0 + i]) * L.inv[f0 + i] : 0.f;
+                x[t][kb] = make_uint4(pack2(xs[0], xs[1]), pack2(xs[2], xs[3]), pack2(xs[4], xs[5]), pack2(xs[6], xs[7]));
+            }
+        }
+        uint4 h1[4][4], h2[4][4];
+        chain_layer<7>(L, 0, L.bias, x, h1, lane, g);
+        chain_layer<4>(L, kFrag1, L.bias + kHid, h1, h2, lane, g);
+        chain_layer<4>(L, kFrag1 + kFragH, L.bias + 2 * kHid, h2, h1, lane, g);
+        f32x4 y[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) y[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) {
+            const bf16x8 w = as_bf16x8(L.frag[kFrag1 + 2 * kFragH + kb][lane]);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) y[t] = mma(w, as_bf16x8(h1[t][kb]), y[t]);
+        }
+        // lane (n, 0) holds the 3 outputs of particle 16 t + n in y[t]; lane (n, g)
+        // finishes particle 16 g + n
+        float yo[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const float v = __shfl(y[t][j], n, kWave);
+                if (t == g) yo[j] = v;
+            }
+        const int64_t s = base + 16 * g + n;
+        if (s < s_end) {
+            const float4 q = a.sp[s];
+            int64_t p = a.perm[s];
+            if (p < 0 || p >= a.n) p = 0;
+            float4 r = sample_one(q, a, 1);
+            r.x += net.scale[0] * (yo[0] + L.bias[3 * kHid + 0]);
+            r.y += net.scale[1] * (yo[1] + L.bias[3 * kHid + 1]);
+            r.z += net.scale[2] * (yo[2] + L.bias[3 * kHid + 2]);
+            a.uf4[p] = r;
+        }
+    }
+}
+
+// Bricks of 8x8x8 bulk cells, one wave each.  The checked sample is every
+// particle with id mod period = step mod period; where its relative L2 error
+// against the fine lookup exceeds tol, every particle of the brick takes the
+// fine lookup.  Per workgroup: fallback count, sampled squared error and
+// reference, sample count (FP64 partials, fixed order).
+constexpr int kBrick = 8;
+
+__global__ __launch_bounds__(kBlock) void k_check(StepArgs<float> a) {
+    __shared__ double red[kWavesPerBlock];
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    const int64_t brick = (int64_t)blockIdx.x * kWavesPerBlock + wave;
+    const Geo<float> &geo = a.g;
+    double err = 0.0, ref = 0.0, ns = 0.0, nfall = 0.0;
+    if (brick < a.n_bricks && a.n > 0) {
+        const int bx = (geo.nb[0] + kBrick - 1) / kBrick, by = (geo.nb[1] + kBrick - 1) / kBrick;
+        const int ox = (int)(brick % bx) * kBrick, oy = (int)((brick / bx) % by) * kBrick,
+                  oz = (int)(brick / ((int64_t)bx * by)) * kBrick;
+        const int wx = (ox + kBrick < geo.nb[0]) ? kBrick : geo.nb[0] - ox;
+        const int64_t period = a.mlp_period, phase = ((a.step % period) + period) % period;
+        for (int dz = 0; dz < kBrick && oz + dz < geo.nb[2]; ++dz)
+            for (int dy = 0; dy < kBrick && oy + dy < geo.nb[1]; ++dy) {
+                const int64_t c0 = ox + (int64_t)geo.nb[0] * ((oy + dy) + (int64_t)geo.nb[1] * (oz + dz));
+                const int64_t s0 = seg_clamp(a.start[c0], a.n), s1 = seg_clamp(a.start[c0 + wx], a.n);
+                for (int64_t s = s0 + lane; s < s1; s += kWave) {
+                    int64_t p = a.perm[s];
+                    if (p < 0 || p >= a.n) p = 0;
+                    if (p % period != phase) continue;
+                    float ux, uy, uz;
+                    fine_velocity(a.sp[s], a, ux, uy, uz);
+                    const float4 m = a.uf4[p];
+                    const double ex = (double)m.x - ux, ey = (double)m.y - uy, ez = (double)m.z - uz;
+                    err += ex * ex + ey * ey + ez * ez;
+                    ref += (double)ux * ux + (double)uy * uy + (double)uz * uz;
+                    ns += 1.0;
+                }
+            }
+        const double terr = wave_sum(err), tref = wave_sum(ref), tns = wave_sum(ns);
+        const double tol = (double)a.mlp_tol;
+        if (tns > 0.0 && terr > tol * tol * tref) {
+            for (int dz = 0; dz < kBrick && oz + dz < geo.nb[2]; ++dz)
+                for (int dy = 0; dy < kBrick && oy + dy < geo.nb[1]; ++dy) {
+                    const int64_t c0 = ox + (int64_t)geo.nb[0] * ((oy + dy) + (int64_t)geo.nb[1] * (oz + dz));
+                    const int64_t s0 = seg_clamp(a.start[c0], a.n), s1 = seg_clamp(a.start[c0 + wx], a.n);
+                    for (int64_t s = s0 + lane; s < s1; s += kWave) {
+                        int64_t p = a.perm[s];
+                        if (p < 0 || p >= a.n) p = 0;
+                        float4 m = a.uf4[p];
+                        fine_velocity(a.sp[s], a, m.x, m.y, m.z);
+                        a.uf4[p] = m;
+                        nfall += 1.0;
+                    }
+                }
+        }
+    }
+    const double vals[4] = {nfall, err, ref, ns};
+    const int slots[4] = {SL_NFALL, SL_MLPERR, SL_MLPREF, SL_MLPSAMP};
+    for (int k = 0; k < 4; ++k) {
+        const double t = block_sum(vals[k], red);
+        if (threadIdx.x == 0) a.part[slots[k] * a.part_stride + blockIdx.x] = t;
+    }
+}
+
+}  // namespace mlp
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+int64_t bricks_of(const int nb[3]) {
+    int64_t b = 1;
+    for (int a = 0; a < 3; ++a) b *= (nb[a] + mlp::kBrick - 1) / mlp::kBrick;
+    return b;
+}
+int64_t mlp_check_blocks(int64_t n_bricks) { return (n_bricks + kWavesPerBlock - 1) / kWavesPerBlock; }
+
+void launch_mlp_pack(const StepArgs<float> &a, hipStream_t st) {
+    hipLaunchKernelGGL(mlp::k_pack, dim3((unsigned)((a.g.ncell + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, a);
+}
+
+void launch_mlp_infer(const StepArgs<float> &a, hipStream_t st) {
+    if (a.n <= 0) return;
+    int dev = 0, ncu = 256;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (ncu < 1) ncu = 1;
+    // one workgroup per compute unit, or fewer for small inputs
+    const int64_t rounds = (a.n + mlp::kInfRows - 1) / mlp::kInfRows;
+    int64_t grid = ncu;
+    if (grid * mlp::kInfWaves > rounds) grid = (rounds + mlp::kInfWaves - 1) / mlp::kInfWaves;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(mlp::k_infer, dim3((unsigned)grid), dim3(kBlock), 0, st, a);
+}
+
+void launch_mlp_check(const StepArgs<float> &a, hipStream_t st) {
+    hipLaunchKernelGGL(mlp::k_check, dim3((unsigned)mlp_check_blocks(a.n_bricks)), dim3(kBlock), 0, st, a);
+}
+
+namespace mlp {
+
+static WPtrs wptrs(const NetBufs &net) {
+    WPtrs w;
+    for (int l = 0; l < 4; ++l) {
+        w.wt[l] = net.wt[l];
+        w.wn[l] = net.wn[l];
+    }
+    return w;
+}
+
+static unsigned blocks(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+hipError_t launch_cast(const NetBufs &net, hipStream_t st) {
+    hipLaunchKernelGGL(k_cast, dim3(blocks(kNParam)), dim3(kBlock), 0, st, net.params, wptrs(net));
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(const NetBufs &net, const float *grads, float lr, float b1, float omb1, float b2, float omb2,
+                       float eps, float c1, float c2, hipStream_t st) {
+    hipLaunchKernelGGL(k_adam, dim3(blocks(kNParam)), dim3(kBlock), 0, st, grads, net.params, net.m, net.v, wptrs(net),
+                       lr, b1, omb1, b2, omb2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t launch_standardise(const float *feat, const float *resid, const int32_t *idx, int64_t nrows, int64_t B,
+                              const float *mean_inv, const float inv_scale[3], uint16_t *x0, float *t,
+                              hipStream_t st) {
+    if (B <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_standardise, dim3(blocks(B * kK1)), dim3(kBlock), 0, st, feat, resid, idx, nrows, B, mean_inv,
+                       inv_scale[0], inv_scale[1], inv_scale[2], x0, t);
+    return hipGetLastError();
+}
+
+static unsigned tile_blocks(int64_t B) { return (unsigned)(((B + 15) / 16 + kWavesPerBlock - 1) / kWavesPerBlock); }
+
+hipError_t launch_forward(const NetBufs &net, const TrainBufs &tb, int64_t B, bool with_loss, hipStream_t st) {
+    if (B <= 0) return hipSuccess;
+    const dim3 gr(tile_blocks(B)), bl(kBlock);
+    const float *p = net.params;
+    hipLaunchKernelGGL((k_dense<7, 8, false>), gr, bl, 0, st, tb.x0, net.wt[0], p + off_b(0), kHid, B, tb.z[0], tb.h[0],
+                       nullptr, 0.f, nullptr, nullptr, nullptr);
+    hipLaunchKernelGGL((k_dense<4, 8, false>), gr, bl, 0, st, tb.h[0], net.wt[1], p + off_b(1), kHid, B, tb.z[1], tb.h[1],
+                       nullptr, 0.f, nullptr, nullptr, nullptr);
+    hipLaunchKernelGGL((k_dense<4, 8, false>), gr, bl, 0, st, tb.h[1], net.wt[2], p + off_b(2), kHid, B, tb.z[2], tb.h[2],
+                       nullptr, 0.f, nullptr, nullptr, nullptr);
+    hipLaunchKernelGGL((k_dense<4, 1, true>), gr, bl, 0, st, tb.h[2], net.wt[3], p + off_b(3), kOut, B, tb.y, nullptr,
+                       with_loss ? tb.t : nullptr, (float)(1.0 / (double)B), tb.dzf[3], tb.dz[3], tb.loss_part);
+    return hipGetLastError();
+}
+
+static void transpose(const uint16_t *src, int64_t R, int64_t C, uint16_t *dst, hipStream_t st) {
+    hipLaunchKernelGGL(k_transpose, dim3((unsigned)((R + 63) / 64), (unsigned)((C + 63) / 64)), dim3(kBlock), 0, st, src,
+                       R, C, dst);
+}
+
+hipError_t launch_backward(const NetBufs &net, const TrainBufs &tb, int64_t B, float *grads, float *loss,
+                           hipStream_t st) {
+    const dim3 gr(tile_blocks(B)), bl(kBlock);
+    // input gradients of layers 4, 3, 2 (each times gelu' of the layer below)
+    hipLaunchKernelGGL((k_dense_bwd<1, 8>), gr, bl, 0, st, tb.dz[3], net.wn[3], tb.z[2], B, tb.dzf[2], tb.dz[2]);
+    hipLaunchKernelGGL((k_dense_bwd<4, 8>), gr, bl, 0, st, tb.dz[2], net.wn[2], tb.z[1], B, tb.dzf[1], tb.dz[1]);
+    hipLaunchKernelGGL((k_dense_bwd<4, 8>), gr, bl, 0, st, tb.dz[1], net.wn[1], tb.z[0], B, tb.dzf[0], tb.dz[0]);
+    // transposed copies for the products over the batch
+    transpose(tb.x0, B, kK1, tb.x0t, st);
+    for (int l = 0; l < 3; ++l) {
+        transpose(tb.h[l], B, kHid, tb.ht[l], st);
+        transpose(tb.dz[l], B, kHid, tb.dzt[l], st);
+    }
+    transpose(tb.dz[3], B, 32, tb.dzt[3], st);
+    const unsigned nc = (unsigned)n_chunks(B);
+    hipLaunchKernelGGL((k_wgrad<8, 14>), dim3(nc), bl, 0, st, tb.dzt[0], tb.x0t, tb.dzf[0], B, tb.part_w[0], tb.part_b[0]);
+    hipLaunchKernelGGL((k_wgrad<8, 8>), dim3(nc), bl, 0, st, tb.dzt[1], tb.ht[0], tb.dzf[1], B, tb.part_w[1], tb.part_b[1]);
+    hipLaunchKernelGGL((k_wgrad<8, 8>), dim3(nc), bl, 0, st, tb.dzt[2], tb.ht[1], tb.dzf[2], B, tb.part_w[2], tb.part_b[2]);
+    hipLaunchKernelGGL((k_wgrad<1, 8>), dim3(nc), bl, 0, st, tb.dzt[3], tb.ht[2], tb.dzf[3], B, tb.part_w[3], tb.part_b[3]);
+    GradParts parts;
+    for (int l = 0; l < 4; ++l) {
+        parts.w[l] = tb.part_w[l];
+        parts.b[l] = tb.part_b[l];
+    }
+    hipLaunchKernelGGL(k_reduce_grads, dim3(blocks(kNParam)), bl, 0, st, parts, (int64_t)nc, grads);
+    if (loss) hipLaunchKernelGGL(k_sum_loss, dim3(1), bl, 0, st, tb.loss_part, (B + 15) / 16, loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_output(const TrainBufs &tb, int64_t B, float *y, hipStream_t st) {
+    if (B <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_output, dim3(blocks(B * 3)), dim3(kBlock), 0, st, tb.y, B, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_column_stats(const float *x, int64_t n, int cols, double *part, int64_t nchunk, double *mean,
+                               double *std, hipStream_t st) {
+    const int64_t rows_per = (n + nchunk - 1) / nchunk;
+    hipLaunchKernelGGL(k_colsum, dim3((unsigned)nchunk), dim3(kBlock), 0, st, x, n, cols, rows_per, nullptr, part);
+    hipLaunchKernelGGL(k_colfinish, dim3(1), dim3(kBlock), 0, st, part, nchunk, cols, n, 0, mean);
+    hipLaunchKernelGGL(k_colsum, dim3((unsigned)nchunk), dim3(kBlock), 0, st, x, n, cols, rows_per, mean, part);
+    hipLaunchKernelGGL(k_colfinish, dim3(1), dim3(kBlock), 0, st, part, nchunk, cols, n, 1, std);
+    return hipGetLastError();
+}
+
+hipError_t launch_features(const int nb[3], const double box[3], int64_t n, const float *pos, const float *diam,
+                           const float *phi, const float *U, const float *G, const float *u_fine,
+                           const int32_t *sel, int64_t nsel, float *feat, float *u_bulk, float *resid,
+                           hipStream_t st) {
+    if (nsel <= 0) return hipSuccess;
+    Geo<float> g;
+    for (int a = 0; a < 3; ++a) {
+        g.nb[a] = nb[a];
+        g.nf[a] = nb[a];
+        g.L[a] = (float)box[a];
+        g.sb[a] = (float)((double)nb[a] / box[a]);
+        g.sf[a] = g.sb[a];
+        g.hb[a] = (float)(box[a] / (double)nb[a]);
+    }
+    g.ncell = (int64_t)nb[0] * nb[1] * nb[2];
+    g.nfine = g.ncell;
+    g.vb = (box[0] / nb[0]) * (box[1] / nb[1]) * (box[2] / nb[2]);
+    g.vf = g.vb;
+    g.inv_vb = (float)(1.0 / g.vb);
+    hipLaunchKernelGGL(k_features, dim3(blocks(nsel)), dim3(kBlock), 0, st, g, n, pos, diam, phi, U, G, u_fine, sel, nsel,
+                       feat, u_bulk, resid);
+    return hipGetLastError();
+}
+
+}  // namespace mlp
+}  // namespace cpl

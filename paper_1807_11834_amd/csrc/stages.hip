@@ -24,6 +24,7 @@
 
 #include "common.hpp"
 #include "launch.hpp"
+#include "sample.hpp"
 
 namespace cpl {
 
@@ -93,64 +94,14 @@ __global__ __launch_bounds__(kBlock) void k_gather(const int32_t *__restrict__ p
 // Particle stage: void fraction and fluid velocity at the particle, drag
 // (Eq. DragLaw with the Di Felice voidage function), optional Euler advection.
 // ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ T trilin(const T *__restrict__ f, const Axis<T> &ax, const Axis<T> &ay,
-                                    const Axis<T> &az, int64_t nx, int64_t nxy) {
-    const int64_t zl = az.lo * nxy, zh = az.hi * nxy, yl = ay.lo * nx, yh = ay.hi * nx;
-    const T sx = T(1) - ax.t, sy = T(1) - ay.t, sz = T(1) - az.t;
-    T c00 = sx * f[zl + yl + ax.lo] + ax.t * f[zl + yl + ax.hi];
-    T c01 = sx * f[zl + yh + ax.lo] + ax.t * f[zl + yh + ax.hi];
-    T c10 = sx * f[zh + yl + ax.lo] + ax.t * f[zh + yl + ax.hi];
-    T c11 = sx * f[zh + yh + ax.lo] + ax.t * f[zh + yh + ax.hi];
-    T c0 = sy * c00 + ay.t * c01;
-    T c1 = sy * c10 + ay.t * c11;
-    return sz * c0 + az.t * c1;
-}
-
-// Values at x-nodes lo and hi (hi == lo + 1, or hi == lo at a wall) of one row
-// of n >= 2 values, from one 8-byte load of the pair that contains them.
-template <typename T> struct Pair2;
-template <> struct Pair2<float> { typedef float __attribute__((ext_vector_type(2), aligned(4))) type; };
-template <> struct Pair2<double> { typedef double __attribute__((ext_vector_type(2), aligned(8))) type; };
-
-template <typename T>
-__device__ __forceinline__ void load_pair(const T *__restrict__ row, int lo, int hi, T &vlo, T &vhi) {
-    const int base = (hi != lo) ? lo : (lo == 0 ? 0 : lo - 1);
-    const typename Pair2<T>::type v = *reinterpret_cast<const typename Pair2<T>::type *>(row + base);
-    vlo = (lo == base) ? v.x : v.y;
-    vhi = (hi == base) ? v.x : v.y;
-}
-
-// Trilinear value of a cell-centred field from its 4 (y, z) rows of x-pairs.
-template <typename T>
-__device__ __forceinline__ T trilin_pairs(const T *__restrict__ f, const Axis<T> &ax, const Axis<T> &ay,
-                                          const Axis<T> &az, int nx, int64_t nxy) {
-    if (nx == 1) return trilin(f, ax, ay, az, nx, nxy);
-    const int64_t zl = az.lo * nxy, zh = az.hi * nxy, yl = (int64_t)ay.lo * nx, yh = (int64_t)ay.hi * nx;
-    T a0, a1, b0, b1, c0, c1, d0, d1;
-    load_pair(f + zl + yl, ax.lo, ax.hi, a0, a1);
-    load_pair(f + zl + yh, ax.lo, ax.hi, b0, b1);
-    load_pair(f + zh + yl, ax.lo, ax.hi, c0, c1);
-    load_pair(f + zh + yh, ax.lo, ax.hi, d0, d1);
-    const T sx = T(1) - ax.t, sy = T(1) - ay.t, sz = T(1) - az.t;
-    const T e0 = sy * (sx * a0 + ax.t * a1) + ay.t * (sx * b0 + ax.t * b1);
-    const T e1 = sy * (sx * c0 + ax.t * c1) + ay.t * (sx * d0 + ax.t * d1);
-    return sz * e0 + az.t * e1;
-}
-
-// Per particle in the sorted order: the fluid velocity at the particle (fine or
-// bulk trilinear) and the void fraction eps_p = sum_c w_pc (1 - phi_c) (the
-// transpose of the deposition weights), written to uf4[id] = (u, v, w, eps_p)
-// for the input-order drag kernel.  In the FP32 modes, where the particle solid
-// fraction exceeds phi_fp64 (near close packing) phi_p and 1 - phi_p are formed
-// in FP64 from the same eight bulk values.  KB particles per thread are sampled
-// together so that all their gathers are in flight at once.
+// Per particle in the sorted order: sample_one() with the handle's velocity
+// source, written to uf4[id] = (u, v, w, eps_p) for the input-order drag kernel.
+// KB particles per thread are sampled together so that all their gathers are in
+// flight at once.
 template <typename T, int KB>
 __device__ __forceinline__ void sample_particles(const int64_t (&idx)[KB], const StepArgs<T> &a) {
-    const Geo<T> &g = a.g;
     const vec4<T> *__restrict__ sp = a.sp;
     const int32_t *__restrict__ perm = a.perm;
-    const T *__restrict__ phi = a.phi;
     vec4<T> q[KB];
     int64_t p[KB];
 #pragma unroll
@@ -162,73 +113,7 @@ __device__ __forceinline__ void sample_particles(const int64_t (&idx)[KB], const
     }
     vec4<T> s[KB];
 #pragma unroll
-    for (int k = 0; k < KB; ++k) {
-        T eps;
-        if (a.cic) {
-            const Axis<T> bx = cic_axis(q[k].x, g.sb[0], g.nb[0]);
-            const Axis<T> by = cic_axis(q[k].y, g.sb[1], g.nb[1]);
-            const Axis<T> bz = cic_axis(q[k].z, g.sb[2], g.nb[2]);
-            const int nx = g.nb[0];
-            const int64_t nxy = (int64_t)g.nb[0] * g.nb[1];
-            T f000, f001, f010, f011, f100, f101, f110, f111;
-            if (nx >= 2) {
-                const int64_t zl = bz.lo * nxy, zh = bz.hi * nxy, yl = (int64_t)by.lo * nx, yh = (int64_t)by.hi * nx;
-                load_pair(phi + zl + yl, bx.lo, bx.hi, f000, f001);
-                load_pair(phi + zl + yh, bx.lo, bx.hi, f010, f011);
-                load_pair(phi + zh + yl, bx.lo, bx.hi, f100, f101);
-                load_pair(phi + zh + yh, bx.lo, bx.hi, f110, f111);
-            } else {
-                const int64_t zl = bz.lo * nxy, zh = bz.hi * nxy, yl = (int64_t)by.lo * nx, yh = (int64_t)by.hi * nx;
-                f000 = f001 = phi[zl + yl];
-                f010 = f011 = phi[zl + yh];
-                f100 = f101 = phi[zh + yl];
-                f110 = f111 = phi[zh + yh];
-            }
-            const T sx = T(1) - bx.t, sy = T(1) - by.t, sz = T(1) - bz.t;
-            const T phi_p = sz * (sy * (sx * f000 + bx.t * f001) + by.t * (sx * f010 + bx.t * f011)) +
-                            bz.t * (sy * (sx * f100 + bx.t * f101) + by.t * (sx * f110 + bx.t * f111));
-            if (std::is_same<T, float>::value && phi_p > (T)a.phi_fp64) {
-                // FP64 weights from the same positions; the cancellation in 1 - phi is exact
-                const double gx = (double)q[k].x * (double)g.sb[0] - 0.5, gy = (double)q[k].y * (double)g.sb[1] - 0.5,
-                             gz = (double)q[k].z * (double)g.sb[2] - 0.5;
-                const double tx = gx - floor(gx), ty = gy - floor(gy), tz = gz - floor(gz);
-                const double ux = 1.0 - tx, uy = 1.0 - ty, uz = 1.0 - tz;
-                const double ph =
-                    uz * (uy * (ux * (double)f000 + tx * (double)f001) + ty * (ux * (double)f010 + tx * (double)f011)) +
-                    tz * (uy * (ux * (double)f100 + tx * (double)f101) + ty * (ux * (double)f110 + tx * (double)f111));
-                eps = (T)(1.0 - ph);
-            } else {
-                eps = T(1) - phi_p;
-            }
-        } else {
-            const int ix = cell_axis(q[k].x, g.sb[0], g.nb[0]);
-            const int iy = cell_axis(q[k].y, g.sb[1], g.nb[1]);
-            const int iz = cell_axis(q[k].z, g.sb[2], g.nb[2]);
-            eps = T(1) - phi[ix + (int64_t)g.nb[0] * (iy + (int64_t)g.nb[1] * iz)];  // exact for phi in [1/2, 1]
-        }
-        s[k].w = eps;
-        if (a.vel_source == 0) {
-            const Axis<T> fx = cic_axis(q[k].x, g.sf[0], g.nf[0]);
-            const Axis<T> fy = cic_axis(q[k].y, g.sf[1], g.nf[1]);
-            const Axis<T> fz = cic_axis(q[k].z, g.sf[2], g.nf[2]);
-            const int nx = g.nf[0];
-            const int64_t nxy = (int64_t)g.nf[0] * g.nf[1];
-            s[k].x = trilin_pairs(a.fine[0], fx, fy, fz, nx, nxy);
-            s[k].y = trilin_pairs(a.fine[1], fx, fy, fz, nx, nxy);
-            s[k].z = trilin_pairs(a.fine[2], fx, fy, fz, nx, nxy);
-        } else if (a.vel_source == 1) {
-            const Axis<T> bx = cic_axis(q[k].x, g.sb[0], g.nb[0]);
-            const Axis<T> by = cic_axis(q[k].y, g.sb[1], g.nb[1]);
-            const Axis<T> bz = cic_axis(q[k].z, g.sb[2], g.nb[2]);
-            const int nx = g.nb[0];
-            const int64_t nxy = (int64_t)g.nb[0] * g.nb[1];
-            s[k].x = trilin_pairs(a.U, bx, by, bz, nx, nxy);
-            s[k].y = trilin_pairs(a.U + g.ncell, bx, by, bz, nx, nxy);
-            s[k].z = trilin_pairs(a.U + 2 * g.ncell, bx, by, bz, nx, nxy);
-        } else {
-            s[k].x = s[k].y = s[k].z = T(0);   // the drag kernel takes u_f from uf_given
-        }
-    }
+    for (int k = 0; k < KB; ++k) s[k] = sample_one(q[k], a, a.vel_source);
 #pragma unroll
     for (int k = 0; k < KB; ++k)
         if (idx[k] >= 0) a.uf4[p[k]] = s[k];
@@ -323,6 +208,8 @@ __global__ __launch_bounds__(kBlock) void k_drag(StepArgs<T> a) {
         T uf[3] = {s.x, s.y, s.z};
         if (a.vel_source == 2)
             for (int k = 0; k < 3; ++k) uf[k] = a.uf_given[3 * p + k];
+        if (a.uf_out)
+            for (int k = 0; k < 3; ++k) a.uf_out[3 * p + k] = uf[k];
         const T ur0 = uf[0] - us[0], ur1 = uf[1] - us[1], ur2 = uf[2] - us[2];
         const T mag = dsqrt(ur0 * ur0 + ur1 * ur1 + ur2 * ur2);
         T e = s.w;
@@ -542,6 +429,19 @@ static void launch_grid_stages(const StepArgs<T> &a, hipStream_t st) {
     if (a.vel_source == 0) {
         a.mk->mark("restrict_lookup", st);
         hipLaunchKernelGGL((k_restrict<T, R, KAHAN, true>), dim3(cb), dim3(kBlock), 0, st, a);
+    } else if (a.vel_source == 3) {
+        if constexpr (std::is_same<T, float>::value) {
+            a.mk->mark("restrict", st);
+            hipLaunchKernelGGL((k_restrict<T, R, KAHAN, false>), dim3(cb), dim3(kBlock), 0, st, a);
+            a.mk->mark("mlp_pack", st);
+            launch_mlp_pack(a, st);
+            if (a.n > 0) {
+                a.mk->mark("mlp_infer", st);
+                launch_mlp_infer(a, st);
+                a.mk->mark("mlp_check", st);
+                launch_mlp_check(a, st);
+            }
+        }
     } else {
         a.mk->mark("restrict", st);
         hipLaunchKernelGGL((k_restrict<T, R, KAHAN, false>), dim3(cb), dim3(kBlock), 0, st, a);
@@ -585,7 +485,11 @@ template <typename T> hipError_t launch_stages(const StepArgs<T> &a, hipStream_t
     const int npart = a.n > 0 ? (int)pb : 0;   // k_drag
     for (int k = 0; k < 3; ++k) spec.nblk[SL_FP + k] = npart;
     spec.nblk[SL_NCLAMP] = npart;
-    spec.nblk[SL_NFALL] = 0;
+    const int nmlp = (a.vel_source == 3 && a.n > 0) ? (int)mlp_check_blocks(a.n_bricks) : 0;
+    spec.nblk[SL_NFALL] = nmlp;
+    spec.nblk[SL_MLPERR] = nmlp;
+    spec.nblk[SL_MLPREF] = nmlp;
+    spec.nblk[SL_MLPSAMP] = nmlp;
     spec.scale[SL_PHISUM] = a.g.vb;
     for (int k = 0; k < 3; ++k) {
         spec.scale[SL_FB + k] = a.g.vb;

@@ -1,6 +1,7 @@
 """CPU checks of the C ABI: the library loads, exports every entry point that
-include/couple.h declares, its structs have the header's layout, and argument
-validation rejects bad calls before any device work."""
+include/couple.h and include/couple_mlp.h declare, its structs have the
+headers' layout, and argument validation rejects bad calls before any device
+work."""
 import os
 import re
 import subprocess
@@ -8,19 +9,23 @@ import subprocess
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "couple.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("couple.h", "couple_mlp.h")]
 LIB = os.path.join(ROOT, "paper_1807_11834_amd", "libcouple.so")
 
 
 def declared_functions():
-    text = open(HEADER).read()
+    text = "".join(open(h).read() for h in HEADERS)
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(couple_[a-z_]+)\s*\(", text)))
 
 
 def test_header_declares_the_entry_points():
-    assert declared_functions() == ["couple_free", "couple_init", "couple_last_error", "couple_step",
-                                    "couple_timing_begin", "couple_timing_end"]
+    assert declared_functions() == sorted([
+        "couple_free", "couple_init", "couple_last_error", "couple_step", "couple_timing_begin", "couple_timing_end",
+        "couple_mlp_init", "couple_mlp_free", "couple_mlp_last_error", "couple_mlp_set_params",
+        "couple_mlp_set_norm", "couple_mlp_fit_norm", "couple_mlp_get_state", "couple_mlp_set_state",
+        "couple_mlp_forward", "couple_mlp_grads", "couple_mlp_adam", "couple_mlp_train_step",
+        "couple_mlp_features", "couple_set_mlp"])
 
 
 def test_library_exports_every_declared_symbol():
@@ -39,24 +44,32 @@ def test_struct_layout_matches_header(tmp_path):
     src.write_text("""
 #include <stdio.h>
 #include <stddef.h>
-#include "couple.h"
+#include "couple_mlp.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu\\n", sizeof(couple_config), offsetof(couple_config, rho_f),
-         offsetof(couple_config, deposit), offsetof(couple_config, dt), offsetof(couple_config, max_particles));
-  printf("%zu %zu\\n", sizeof(couple_inputs), offsetof(couple_inputs, uf_given));
-  printf("%zu %zu\\n", sizeof(couple_outputs), offsetof(couple_outputs, diag));
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(couple_config), offsetof(couple_config, rho_f),
+         offsetof(couple_config, deposit), offsetof(couple_config, dt), offsetof(couple_config, max_particles),
+         offsetof(couple_config, mlp_tol), offsetof(couple_config, mlp_period), offsetof(couple_config, reserved));
+  printf("%zu %zu %zu\\n", sizeof(couple_inputs), offsetof(couple_inputs, uf_given), offsetof(couple_inputs, step));
+  printf("%zu %zu %zu\\n", sizeof(couple_outputs), offsetof(couple_outputs, diag), offsetof(couple_outputs, uf));
+  printf("%zu %zu %zu\\n", sizeof(couple_mlp_config), offsetof(couple_mlp_config, lr), offsetof(couple_mlp_config, eps));
+  printf("%d %d %d %d\\n", COUPLE_DIAG_LEN, COUPLE_VEL_MLP, COUPLE_MLP_NFEAT, COUPLE_MLP_NPARAM);
   return 0; }
 """)
     exe = tmp_path / "layout"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     lines = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
     a = [int(x) for x in lines[0].split()]
-    assert a == [C.sizeof(cpl._Config), cpl._Config.rho_f.offset, cpl._Config.deposit.offset,
-                 cpl._Config.dt.offset, cpl._Config.max_particles.offset]
+    K = cpl._Config
+    assert a == [C.sizeof(K), K.rho_f.offset, K.deposit.offset, K.dt.offset, K.max_particles.offset,
+                 K.mlp_tol.offset, K.mlp_period.offset, K.reserved.offset]
     b = [int(x) for x in lines[1].split()]
-    assert b == [C.sizeof(cpl._Inputs), cpl._Inputs.uf_given.offset]
+    assert b == [C.sizeof(cpl._Inputs), cpl._Inputs.uf_given.offset, cpl._Inputs.step.offset]
     c = [int(x) for x in lines[2].split()]
-    assert c == [C.sizeof(cpl._Outputs), cpl._Outputs.diag.offset]
+    assert c == [C.sizeof(cpl._Outputs), cpl._Outputs.diag.offset, cpl._Outputs.uf.offset]
+    d = [int(x) for x in lines[3].split()]
+    assert d == [C.sizeof(cpl._MlpConfig), cpl._MlpConfig.lr.offset, cpl._MlpConfig.eps.offset]
+    e = [int(x) for x in lines[4].split()]
+    assert e == [cpl.DIAG_LEN, cpl.COUPLE_VEL_MLP, cpl.MLP_NFEAT, cpl.MLP_NPARAM]
 
 
 BAD = [
@@ -64,6 +77,8 @@ BAD = [
     dict(rho_f=-1.0), dict(mu_f=0.0), dict(eps_min=1.0), dict(deposit=2), dict(precision=7),
     dict(vel_source=9), dict(advect=2), dict(advect=1, dt=float("inf")), dict(max_particles=-5),
     dict(nb=(2048, 2048, 1024)), dict(nb=(40000, 2, 2)),
+    dict(vel_source=3, precision=0), dict(vel_source=3, mlp_period=0), dict(vel_source=3, mlp_tol=-1.0),
+    dict(vel_source=3, mlp_tol=float("nan")),
 ]
 
 
@@ -83,3 +98,26 @@ def test_null_handle_and_free_null():
     assert cpl._lib.couple_free(None) == cpl.COUPLE_OK
     i, o = cpl._Inputs(), cpl._Outputs()
     assert cpl._lib.couple_step(None, C.byref(i), C.byref(o), None) == cpl.COUPLE_EINVAL
+
+
+@pytest.mark.parametrize("kw", [dict(max_batch=16), dict(max_batch=1 << 26), dict(lr=0.0), dict(beta1=1.0),
+                                dict(beta2=-0.1), dict(eps=0.0)])
+def test_mlp_init_rejects_invalid_config(kw):
+    import paper_1807_11834_amd as cpl
+    args = {"max_batch": 1024, **kw}
+    with pytest.raises(cpl.CoupleError) as ei:
+        cpl.couple_mlp_init(**args)
+    assert ei.value.code == cpl.COUPLE_EINVAL
+    assert "couple_mlp_init" in str(ei.value)
+
+
+def test_mlp_null_handles():
+    import paper_1807_11834_amd as cpl
+    L = cpl._lib
+    assert L.couple_mlp_free(None) == cpl.COUPLE_OK
+    assert L.couple_mlp_set_params(None, None) == cpl.COUPLE_EINVAL
+    assert L.couple_mlp_forward(None, None, 0, None, None) == cpl.COUPLE_EINVAL
+    assert L.couple_mlp_train_step(None, None, None, 0, None, 0, None, None) == cpl.COUPLE_EINVAL
+    assert L.couple_set_mlp(None, None) == cpl.COUPLE_EINVAL
+    assert L.couple_mlp_features(None, 0, None, None, None, None, None, None, None, 0, None, None, None,
+                                 None) == cpl.COUPLE_EINVAL
