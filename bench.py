@@ -17,10 +17,14 @@ import platform
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E, vendor figure
+MFMA_BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix-core peak, vendor figure
+MLP_FLOP_PER_PARTICLE = 2 * (193 * 128 + 128 * 128 + 128 * 128 + 128 * 3)   # 115,712: one forward pass
 METRIC = "coupling particle-steps/s, plain vs MLP path at 1e-3 rel err; % HBM peak"
 
 
@@ -96,6 +100,123 @@ def cpu_baseline(w, frac):
                        f"{dt:.1f} s; host {cpu}, {os.cpu_count()} logical CPUs")}
 
 
+def _rel(a, b):
+    import torch
+    return float(torch.linalg.vector_norm((a - b).double()) / torch.linalg.vector_norm(b.double()))
+
+
+def mlp_leg(args, w, cfg, pos, vel, diam, fine, plain_ms, plain_kernels, dev):
+    """The learned-surrogate path on the same workload: training pairs from the
+    64^3/256^3 Taylor-Green workload (20,000 particles from each of its 100
+    advected steps) and from this workload's first step (2,000,000 particles),
+    training on the GPU (batch 65,536, Adam lr 1e-3), then the timed step with
+    vel_source MLP and the 1 % sampled check with fine fallback at 1e-3."""
+    import dataclasses as dc
+
+    import torch
+
+    import paper_1807_11834_amd as cpl
+    import workload as W
+    from paper_1807_11834_amd import surrogate as S
+    t0 = time.perf_counter()
+    w1 = W.WORKLOADS["cube64_cic"]
+    p1, d1, v1 = W.particles(w1)
+    g1 = w1.grid
+    cfg1 = cpl.Config(box=g1.box, nb=g1.nb, ratio=g1.ratio, rho_f=w1.rho_f, mu_f=w1.mu_f, rho_p=w1.rho_p,
+                      eps_min=w1.eps_min, advect=1, dt=w1.dt, max_particles=p1.shape[0])
+    pool = S.PairPool(w1.steps * 20000 + 2_000_000)
+    P1, V1, D1 = (torch.from_numpy(a).to(dev) for a in (p1, v1, d1))
+    fine1 = W.fine_fields_torch(w1, dev, torch.float32)
+    S.collect(pool, cfg1, P1, V1, D1, fine1, steps=w1.steps, per_step=20000, seed=3)
+    del P1, V1, D1, fine1
+    cfgf = dc.replace(cfg, vel_source=cpl.COUPLE_VEL_FINE, advect=0)
+    S.collect(pool, cfgf, pos, vel, diam, fine, steps=1, per_step=2_000_000, seed=4)
+    t_pairs = time.perf_counter() - t0
+    mlp = cpl.Mlp(65536)
+    mlp.set_params(S.he_uniform(0))
+    feat, resid = pool.view()
+    mlp.fit_norm(feat, resid)
+    t0 = time.perf_counter()
+    hist = S.train(mlp, feat, resid, steps=args.mlp_steps, batch=65536, seed=3, log_every=max(1, args.mlp_steps // 4),
+                   log=lambda m: print("# surrogate " + m, file=sys.stderr, flush=True))
+    t_train = time.perf_counter() - t0
+    del pool, feat, resid
+    torch.cuda.empty_cache()
+
+    n = pos.shape[0]
+
+    def velocities(source, tol=1e30):
+        c = cpl.Coupler(dc.replace(cfg, vel_source=source, advect=0, mlp_tol=tol))
+        if source == cpl.COUPLE_VEL_MLP:
+            cpl.couple_set_mlp(c.h, mlp.m)
+        o = c.step(pos, vel, diam, fine, uf=True)
+        torch.cuda.synchronize()
+        u = o["uf"].clone()
+        d = cpl.diag_dict(o["diag"])
+        c.close()
+        return u, d
+
+    uF, _ = velocities(cpl.COUPLE_VEL_FINE)
+    uB, _ = velocities(cpl.COUPLE_VEL_BULK)
+    uM, dm = velocities(cpl.COUPLE_VEL_MLP)
+    uMF, dmf = velocities(cpl.COUPLE_VEL_MLP, tol=1e-3)
+    upflow = torch.tensor([0.0, 0.0, 0.5 if w.fluid == "upflow" else 0.0], device=dev)
+    acc = {
+        "rel_err_mlp": _rel(uM, uF), "rel_err_mlp_with_fallback": _rel(uMF, uF), "rel_err_bulk": _rel(uB, uF),
+        "rel_err_mlp_perturbation": float(torch.linalg.vector_norm((uM - uF).double()) /
+                                          torch.linalg.vector_norm((uF - upflow).double())),
+        "rel_err_bulk_perturbation": float(torch.linalg.vector_norm((uB - uF).double()) /
+                                           torch.linalg.vector_norm((uF - upflow).double())),
+        "sampled_rel_err_in_step": float(np.sqrt(dmf["mlp_err2"] / dmf["mlp_ref2"])) if dmf["mlp_ref2"] else None,
+        "fallback_fraction": dmf["n_fallback"] / n,
+    }
+    del uF, uB, uM, uMF
+
+    cm = cpl.Coupler(dc.replace(cfg, vel_source=cpl.COUPLE_VEL_MLP, advect=0, mlp_tol=1e-3))
+    cpl.couple_set_mlp(cm.h, mlp.m)
+    out = cpl.alloc_outputs(cm.cfg, n, device=dev)
+    for k in range(args.warmup):
+        cm.step(pos, vel, diam, fine, out=out, step=k)
+    torch.cuda.synchronize()
+    cpl.couple_timing_begin(cm.h, args.steps)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for k in range(args.steps):
+        cm.step(pos, vel, diam, fine, out=out, step=k)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    stats = cpl.couple_timing_end(cm.h)
+    ms = e0.elapsed_time(e1) / args.steps
+    dfin = cpl.diag_dict(out["diag"])
+    cm.close()
+    mlp.close()
+    kern = {k: {"launches": l, "avg_ms": t / l} for k, (l, t) in stats.items() if l}
+    t_inf = kern["mlp_infer"]["avg_ms"]
+    flop = n * MLP_FLOP_PER_PARTICLE
+    ach = flop / (t_inf * 1e-3) / 1e12
+    vel_mlp = sum(kern[k]["avg_ms"] for k in ("restrict", "mlp_pack", "mlp_infer", "mlp_check") if k in kern)
+    vel_plain = plain_kernels.get("restrict_lookup", {}).get("avg_ms")
+    return {
+        "ms_per_step": ms, "value": n / (ms * 1e-3), "unit": "particle-steps/s",
+        "speedup_vs_plain_step": plain_ms / ms,
+        "velocity_stage_ms": {"plain (restrict + fine lookup)": vel_plain,
+                              "mlp (restrict + pack + infer + check/fallback)": round(vel_mlp, 4)},
+        "speedup_vs_plain_velocity_stage": (vel_plain / vel_mlp) if vel_plain else None,
+        "accuracy_vs_fine_lookup": acc,
+        "last_timed_step": {"sampled_rel_err": float(np.sqrt(dfin["mlp_err2"] / dfin["mlp_ref2"]))
+                            if dfin["mlp_ref2"] else None, "fallback_particles": dfin["n_fallback"]},
+        "roofline": {"bound": "mfma", "kernel": "mlp_infer", "achieved": round(ach, 1),
+                     "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(ach / MFMA_BF16_PEAK_TFLOPS, 4),
+                     "traffic": None, "flop_per_launch": flop, "avg_ms": round(t_inf, 4)},
+        "kernels_avg_ms": {k: round(v["avg_ms"], 4) for k, v in kern.items()},
+        "train": {"steps": args.mlp_steps, "batch": 65536, "seconds": round(t_train, 1),
+                  "pairs_seconds": round(t_pairs, 1), "loss_first_last": [hist[0][1], hist[-1][1]],
+                  "pairs": "20,000 per step x 100 advected steps of cube64_cic + 2,000,000 of this workload's "
+                           "first step"},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,6 +228,8 @@ def main():
     ap.add_argument("--no-presorted", action="store_true", help="skip the spatially sorted input variant")
     ap.add_argument("--vel-source", default="fine", choices=["fine", "bulk"],
                     help="fluid velocity at the particles: fine-grid lookup (default) or bulk trilinear")
+    ap.add_argument("--no-mlp", action="store_true", help="skip the learned-surrogate path")
+    ap.add_argument("--mlp-steps", type=int, default=20000, help="surrogate training steps (batch 65,536)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the coupling exchange is built and timed for a single "
@@ -114,7 +237,6 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_1807_11834_amd as cpl
@@ -204,6 +326,9 @@ def main():
         rec["presorted_input"] = {"ms_per_step": ms_s, "value": n / (ms_s * 1e-3),
                                   "note": "same particles passed in the canonical (cell, id) order"}
         del pos_s, vel_s, diam_s
+    if not args.no_mlp:
+        print("# surrogate: pairs, training, timing ...", file=sys.stderr, flush=True)
+        rec["mlp_path"] = mlp_leg(args, w, cfg, pos, vel, diam, fine, ms_step, kernels, dev)
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle sample) ...", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(w, args.cpu_frac)

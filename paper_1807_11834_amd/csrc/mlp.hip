@@ -37,14 +37,13 @@ namespace mlp {
 typedef __bf16 bf16x8 __attribute__((__vector_size__(16)));
 typedef float f32x4 __attribute__((__vector_size__(16)));
 
-// float -> bfloat16 bits, round to nearest even (NaN stays NaN).
-__device__ __forceinline__ uint32_t bf16_bits(float x) {
-    uint32_t u = __float_as_uint(x);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return u >> 16;
+// float -> bfloat16, round to nearest even (v_cvt_pk_bf16_f32 on gfx950).
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pack2(float lo, float hi) {
+    const bf16x2 v = {(__bf16)lo, (__bf16)hi};
+    return __builtin_bit_cast(uint32_t, v);
 }
-__device__ __forceinline__ uint32_t pack2(float lo, float hi) { return bf16_bits(lo) | (bf16_bits(hi) << 16); }
+__device__ __forceinline__ uint32_t bf16_bits(float x) { return pack2(x, 0.f) & 0xffffu; }
 __device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
 __device__ __forceinline__ bf16x8 load8(const uint16_t *p) { return as_bf16x8(*reinterpret_cast<const uint4 *>(p)); }
 __device__ __forceinline__ bf16x8 zero8() { return as_bf16x8(make_uint4(0u, 0u, 0u, 0u)); }
@@ -52,14 +51,21 @@ __device__ __forceinline__ f32x4 mma(bf16x8 a, bf16x8 b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-// tanh-form GELU 0.5 z (1 + tanh(sqrt(2/pi) (z + 0.044715 z^3))) and its derivative
+// tanh-form GELU 0.5 z (1 + tanh(u)), u = sqrt(2/pi) (z + 0.044715 z^3), written
+// as z * sigma(2u) with sigma(2u) = 1 / (1 + 2^(-2u log2 e)): one exp2 and one
+// reciprocal (hardware, ~1 ulp).  For z -> -inf, 2^(...) -> inf and the result
+// -> -0; for z -> +inf it -> z.  Derivative: with s = sigma(2u),
+//   gelu'(z) = s + 2 z s (1 - s) du/dz,  du/dz = sqrt(2/pi) (1 + 3 * 0.044715 z^2).
 constexpr float kGc = 0.7978845608028654f, kGa = 0.044715f;
-__device__ __forceinline__ float tanh_e(float u) { return 1.f - __fdividef(2.f, __expf(2.f * u) + 1.f); }
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.f + tanh_e(kGc * z * (1.f + kGa * z * z))); }
+constexpr float kGk = 2.3022081983914574f;   // 2 sqrt(2/pi) log2(e)
+__device__ __forceinline__ float sig2u(float z) {
+    const float t = fmaf(-kGk * kGa, z * z, -kGk);   // -2u log2(e) / z
+    return __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_exp2f(z * t));
+}
+__device__ __forceinline__ float gelu(float z) { return z * sig2u(z); }
 __device__ __forceinline__ float gelu_grad(float z) {
-    const float z2 = z * z;
-    const float t = tanh_e(kGc * z * (1.f + kGa * z2));
-    return 0.5f * (1.f + t) + 0.5f * z * (1.f - t * t) * kGc * (1.f + 3.f * kGa * z2);
+    const float s = sig2u(z);
+    return s + 2.f * z * s * (1.f - s) * (kGc * fmaf(3.f * kGa, z * z, 1.f));
 }
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
@@ -420,15 +426,16 @@ __global__ __launch_bounds__(kBlock) void k_pack(StepArgs<float> a) {
     a.fgrid[2 * c + 1] = make_float4(gr[0], gr[1], gr[2], 0.f);
 }
 
-constexpr int kInfWaves = 4;                    // waves per workgroup
-constexpr int kInfRows = 64;                    // particles per wave and round (4 tiles of 16)
+constexpr int kInfWaves = 8;                    // waves per workgroup (two per SIMD)
+constexpr int kInfTiles = 2;                    // 16-particle tiles per wave and round
+constexpr int kInfRows = 16 * kInfTiles;        // particles per wave and round
 constexpr int kFrag1 = 8 * 7, kFragH = 8 * 4;   // operand fragments per layer
 constexpr int kFrags = kFrag1 + 2 * kFragH + 4;
 
 struct InferLds {
     uint4 frag[kFrags][kWave];    // weight fragments in slot order, 16 B per lane
     float bias[3 * kHid + 16];    // b1, b2, b3, b4 (padded)
-    float mean[kFeat], inv[kFeat];
+    float mean[kK1], inv[kK1];    // standardisation per feature (0 in the padding)
 };
 
 // Layer-1 slot (kb, g, i) -> feature index: unit u = 4 kb + g is stencil cell u
@@ -443,28 +450,29 @@ __device__ __forceinline__ int slot_hidden(int kb, int g, int i) {
     return 32 * kb + (i < 4 ? 4 * g + i : 16 + 4 * g + (i - 4));
 }
 
-// One layer of the chain for 4 tiles: in[t][kb] (KB slot groups) -> 8 row
-// blocks -> gelu -> out[t][4] in the paired slot order.
-template <int KB>
-__device__ __forceinline__ void chain_layer(const InferLds &L, int frag0, const float *bias, const uint4 (&in)[4][KB],
-                                            uint4 (&out)[4][4], int lane, int g) {
+// One layer of the chain for NT tiles: in[t][kb] (KB slot groups) -> 8 row
+// blocks (accumulators start at the bias) -> gelu -> out[t][4] in the paired
+// slot order.  Each weight fragment read from LDS feeds NT products.
+template <int NT, int KB>
+__device__ __forceinline__ void chain_layer(const InferLds &L, int frag0, const float *bias,
+                                            const uint4 (&in)[NT][KB], uint4 (&out)[NT][4], int lane, int g) {
 #pragma unroll
     for (int mb = 0; mb < 8; ++mb) {
-        f32x4 acc[4];
+        const int m0 = 16 * mb + 4 * g;
+        const f32x4 b = {bias[m0], bias[m0 + 1], bias[m0 + 2], bias[m0 + 3]};
+        f32x4 acc[NT];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int t = 0; t < NT; ++t) acc[t] = b;
 #pragma unroll
         for (int kb = 0; kb < KB; ++kb) {
             const bf16x8 w = as_bf16x8(L.frag[frag0 + mb * KB + kb][lane]);
 #pragma unroll
-            for (int t = 0; t < 4; ++t) acc[t] = mma(w, as_bf16x8(in[t][kb]), acc[t]);
+            for (int t = 0; t < NT; ++t) acc[t] = mma(w, as_bf16x8(in[t][kb]), acc[t]);
         }
-        const int m0 = 16 * mb + 4 * g;
-        const float b0 = bias[m0], b1 = bias[m0 + 1], b2 = bias[m0 + 2], b3 = bias[m0 + 3];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const uint32_t lo = pack2(gelu(acc[t][0] + b0), gelu(acc[t][1] + b1));
-            const uint32_t hi = pack2(gelu(acc[t][2] + b2), gelu(acc[t][3] + b3));
+        for (int t = 0; t < NT; ++t) {
+            const uint32_t lo = pack2(gelu(acc[t][0]), gelu(acc[t][1]));
+            const uint32_t hi = pack2(gelu(acc[t][2]), gelu(acc[t][3]));
             if (mb & 1) {
                 out[t][mb >> 1].z = lo;
                 out[t][mb >> 1].w = hi;
@@ -476,17 +484,74 @@ __device__ __forceinline__ void chain_layer(const InferLds &L, int frag0, const 
     }
 }
 
+// Standardised layer-1 inputs of one particle (sorted index s, valid or not)
+// for lane group g: x[kb] holds unit 4 kb + g.
+__device__ __forceinline__ void gather_features(const StepArgs<float> &a, const InferLds &L, int64_t s, bool valid,
+                                                int g, uint4 (&x)[7]) {
+    const Geo<float> &geo = a.g;
+    const int64_t nx = geo.nb[0], nxy = (int64_t)geo.nb[0] * geo.nb[1];
+    const float4 q = a.sp[s];
+    int64_t c0 = a.keys[s];
+    if (c0 < 0 || c0 >= geo.ncell) c0 = 0;
+    int ix, iy, iz;
+    decode_cell(c0, geo.nb, ix, iy, iz);
+    // all stencil loads first (one cell per slot group), then the arithmetic
+    float4 B0[7], B1[7];
+#pragma unroll
+    for (int kb = 0; kb < 7; ++kb) {
+        const int u = 4 * kb + g;
+        const int uu = u < 27 ? u : 13;
+        const int dx = uu % 3 - 1, dy = (uu / 3) % 3 - 1, dz = uu / 9 - 1;
+        const int64_t c = clampi(ix + dx, geo.nb[0]) + nx * clampi(iy + dy, geo.nb[1]) + nxy * clampi(iz + dz, geo.nb[2]);
+        B0[kb] = a.fgrid[2 * c];
+        B1[kb] = a.fgrid[2 * c + 1];
+    }
+    const float4 A0 = a.fgrid[2 * c0], A1 = a.fgrid[2 * c0 + 1];
+#pragma unroll
+    for (int kb = 0; kb < 7; ++kb) {
+        const int u = 4 * kb + g;
+        float v[8];
+        int f0, nv;
+        if (u < 27) {
+            const bool centre = (u == 13);
+            v[0] = centre ? A0.x : B0[kb].x - A0.x;
+            v[1] = centre ? A0.y : B0[kb].y - A0.y;
+            v[2] = centre ? A0.z : B0[kb].z - A0.z;
+            v[3] = centre ? A0.w : B0[kb].w - A0.w;
+            v[4] = centre ? A1.x : B1[kb].x - A1.x;
+            v[5] = centre ? A1.y : B1[kb].y - A1.y;
+            v[6] = centre ? A1.z : B1[kb].z - A1.z;
+            v[7] = 0.f;
+            f0 = 7 * u;
+            nv = 7;
+        } else {
+            v[0] = q.x * geo.sb[0] - (float)ix;
+            v[1] = q.y * geo.sb[1] - (float)iy;
+            v[2] = q.z * geo.sb[2] - (float)iz;
+            v[3] = q.w * geo.sb[0];
+            v[4] = v[5] = v[6] = v[7] = 0.f;
+            f0 = 189;
+            nv = 4;
+        }
+        float xs[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) xs[i] = (i < nv && valid) ? (v[i] - L.mean[f0 + i]) * L.inv[f0 + i] : 0.f;
+        x[kb] = make_uint4(pack2(xs[0], xs[1]), pack2(xs[2], xs[3]), pack2(xs[4], xs[5]), pack2(xs[6], xs[7]));
+    }
+}
+
 // Persistent: each workgroup takes one contiguous range of the sorted particles
-// (neighbouring cells: the stencil loads hit L1/L2), each wave 64 particles per
-// round.  Lane (n, g) gathers, for tile t and slot group kb, unit 4 kb + g of
-// particle 16 t + n; it then finishes particle 16 g + n: u = u_bulk + s * y and
-// eps_p, written to uf4[id].
-__global__ __launch_bounds__(kBlock) void k_infer(StepArgs<float> a) {
+// (neighbouring cells: the stencil loads hit L1/L2), each wave kInfRows particles
+// per round.  Lane (n, g) gathers, for tile t and slot group kb, unit 4 kb + g of
+// particle 16 t + n; lanes with g < kInfTiles then finish particle 16 g + n:
+// u = u_bulk + s * y and eps_p, written to uf4[id].
+__global__ __launch_bounds__(kInfWaves * kWave) void k_infer(StepArgs<float> a) {
     __shared__ InferLds L;
+    constexpr int NT = kInfTiles;
     const int lane = lane_id(), n = lane & 15, g = lane >> 4, wave = threadIdx.x >> 6;
     const MlpNet &net = a.net;
     // weights into LDS in slot order
-    for (int e = threadIdx.x; e < kFrags * kWave * 8; e += kBlock) {
+    for (int e = threadIdx.x; e < kFrags * kWave * 8; e += kInfWaves * kWave) {
         const int f = e >> 9, ln = (e >> 3) & 63, i = e & 7;
         const int r = ln & 15, gg = ln >> 4;
         uint16_t v = 0;
@@ -505,100 +570,65 @@ __global__ __launch_bounds__(kBlock) void k_infer(StepArgs<float> a) {
         }
         reinterpret_cast<uint16_t *>(&L.frag[f][ln])[i] = v;
     }
-    for (int e = threadIdx.x; e < 3 * kHid + 16; e += kBlock) {
+    for (int e = threadIdx.x; e < 3 * kHid + 16; e += kInfWaves * kWave) {
         const int l = e / kHid, m = e % kHid;
         L.bias[e] = (l < 3) ? net.params[off_b(l) + m] : (m < kOut ? net.params[off_b(3) + m] : 0.f);
     }
-    for (int e = threadIdx.x; e < kFeat; e += kBlock) {
+    for (int e = threadIdx.x; e < kK1; e += kInfWaves * kWave) {
         L.mean[e] = net.mean_inv[e];
         L.inv[e] = net.mean_inv[kK1 + e];
     }
     __syncthreads();
 
-    const Geo<float> &geo = a.g;
     const int64_t per = ((a.n + gridDim.x - 1) / gridDim.x + kInfRows - 1) / kInfRows * kInfRows;
     const int64_t s_begin = (int64_t)blockIdx.x * per;
     const int64_t s_end = (s_begin + per < a.n) ? s_begin + per : a.n;
-    const int64_t nx = geo.nb[0], nxy = (int64_t)geo.nb[0] * geo.nb[1];
     for (int64_t base = s_begin + (int64_t)wave * kInfRows; base < s_end; base += kInfWaves * kInfRows) {
-        uint4 x[4][7];
+        // the particle this lane finishes: its bulk velocity, void fraction and id
+        // are fetched first so that their loads overlap the chain
+        const int64_t so = base + 16 * g + n;
+        const bool own = (g < NT) && so < s_end;
+        float4 r = make_float4(0.f, 0.f, 0.f, 0.f);
+        int64_t p = 0;
+        if (own) {
+            r = sample_one(a.sp[so], a, 1);
+            p = a.perm[so];
+            if (p < 0 || p >= a.n) p = 0;
+        }
+        uint4 x[NT][7];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
+        for (int t = 0; t < NT; ++t) {
             const int64_t s = base + 16 * t + n;
             const bool valid = s < s_end;
-            const int64_t sc = valid ? s : s_begin;
-            const float4 q = a.sp[sc];
-            int64_t c0 = a.keys[sc];
-            if (c0 < 0 || c0 >= geo.ncell) c0 = 0;
-            int ix, iy, iz;
-            decode_cell(c0, geo.nb, ix, iy, iz);
-            const float4 A0 = a.fgrid[2 * c0], A1 = a.fgrid[2 * c0 + 1];
-#pragma unroll
-            for (int kb = 0; kb < 7; ++kb) {
-                const int u = 4 * kb + g;
-                float v[8];
-                int f0;
-                if (u < 27) {
-                    const int dx = u % 3 - 1, dy = (u / 3) % 3 - 1, dz = u / 9 - 1;
-                    const int64_t c = clampi(ix + dx, geo.nb[0]) + nx * clampi(iy + dy, geo.nb[1]) +
-                                      nxy * clampi(iz + dz, geo.nb[2]);
-                    const float4 B0 = a.fgrid[2 * c], B1 = a.fgrid[2 * c + 1];
-                    if (u == 13) {
-                        v[0] = A0.x; v[1] = A0.y; v[2] = A0.z; v[3] = A0.w;
-                        v[4] = A1.x; v[5] = A1.y; v[6] = A1.z;
-                    } else {
-                        v[0] = B0.x - A0.x; v[1] = B0.y - A0.y; v[2] = B0.z - A0.z; v[3] = B0.w - A0.w;
-                        v[4] = B1.x - A1.x; v[5] = B1.y - A1.y; v[6] = B1.z - A1.z;
-                    }
-                    v[7] = 0.f;
-                    f0 = 7 * u;
-                } else {
-                    v[0] = q.x * geo.sb[0] - (float)ix;
-                    v[1] = q.y * geo.sb[1] - (float)iy;
-                    v[2] = q.z * geo.sb[2] - (float)iz;
-                    v[3] = q.w * geo.sb[0];
-                    v[4] = v[5] = v[6] = v[7] = 0.f;
-                    f0 = 189;
-                }
-                const int nv = (u < 27) ? 7 : 4;
-                float xs[8];
-#pragma unroll
-                for (int i = 0; i < 8; ++i) xs[i] = (i < nv && valid) ? (v[i] - L.mean[f0 + i]) * L.inv[f0 + i] : 0.f;
-                x[t][kb] = make_uint4(pack2(xs[0], xs[1]), pack2(xs[2], xs[3]), pack2(xs[4], xs[5]), pack2(xs[6], xs[7]));
-            }
+            gather_features(a, L, valid ? s : base, valid, g, x[t]);
         }
-        uint4 h1[4][4], h2[4][4];
-        chain_layer<7>(L, 0, L.bias, x, h1, lane, g);
-        chain_layer<4>(L, kFrag1, L.bias + kHid, h1, h2, lane, g);
-        chain_layer<4>(L, kFrag1 + kFragH, L.bias + 2 * kHid, h2, h1, lane, g);
-        f32x4 y[4];
+        uint4 h1[NT][4], h2[NT][4];
+        chain_layer<NT, 7>(L, 0, L.bias, x, h1, lane, g);
+        chain_layer<NT, 4>(L, kFrag1, L.bias + kHid, h1, h2, lane, g);
+        chain_layer<NT, 4>(L, kFrag1 + kFragH, L.bias + 2 * kHid, h2, h1, lane, g);
+        f32x4 y[NT];
+        const f32x4 b4 = {L.bias[3 * kHid], L.bias[3 * kHid + 1], L.bias[3 * kHid + 2], 0.f};
 #pragma unroll
-        for (int t = 0; t < 4; ++t) y[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int t = 0; t < NT; ++t) y[t] = b4;
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb) {
             const bf16x8 w = as_bf16x8(L.frag[kFrag1 + 2 * kFragH + kb][lane]);
 #pragma unroll
-            for (int t = 0; t < 4; ++t) y[t] = mma(w, as_bf16x8(h1[t][kb]), y[t]);
+            for (int t = 0; t < NT; ++t) y[t] = mma(w, as_bf16x8(h1[t][kb]), y[t]);
         }
-        // lane (n, 0) holds the 3 outputs of particle 16 t + n in y[t]; lane (n, g)
-        // finishes particle 16 g + n
+        // lane (n, 0) holds the 3 outputs of particle 16 t + n in y[t]
         float yo[3] = {0.f, 0.f, 0.f};
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
+        for (int t = 0; t < NT; ++t)
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
                 const float v = __shfl(y[t][j], n, kWave);
                 if (t == g) yo[j] = v;
             }
-        const int64_t s = base + 16 * g + n;
-        if (s < s_end) {
-            const float4 q = a.sp[s];
-            int64_t p = a.perm[s];
-            if (p < 0 || p >= a.n) p = 0;
-            float4 r = sample_one(q, a, 1);
-            r.x += net.scale[0] * (yo[0] + L.bias[3 * kHid + 0]);
-            r.y += net.scale[1] * (yo[1] + L.bias[3 * kHid + 1]);
-            r.z += net.scale[2] * (yo[2] + L.bias[3 * kHid + 2]);
+        if (own) {
+            r.x += net.scale[0] * yo[0];
+            r.y += net.scale[1] * yo[1];
+            r.z += net.scale[2] * yo[2];
             a.uf4[p] = r;
         }
     }
@@ -692,7 +722,7 @@ void launch_mlp_infer(const StepArgs<float> &a, hipStream_t st) {
     int64_t grid = ncu;
     if (grid * mlp::kInfWaves > rounds) grid = (rounds + mlp::kInfWaves - 1) / mlp::kInfWaves;
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(mlp::k_infer, dim3((unsigned)grid), dim3(kBlock), 0, st, a);
+    hipLaunchKernelGGL(mlp::k_infer, dim3((unsigned)grid), dim3(mlp::kInfWaves * kWave), 0, st, a);
 }
 
 void launch_mlp_check(const StepArgs<float> &a, hipStream_t st) {
