@@ -229,6 +229,9 @@ def main():
     ap.add_argument("--vel-source", default="fine", choices=["fine", "bulk"],
                     help="fluid velocity at the particles: fine-grid lookup (default) or bulk trilinear")
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned-surrogate path")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain copy kernel of known size (1 GiB read, 1 GiB written, 3 times): "
+                         "the reference that scales the FETCH_SIZE / WRITE_SIZE counters to bytes")
     ap.add_argument("--mlp-steps", type=int, default=20000, help="surrogate training steps (batch 65,536)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -238,6 +241,17 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration": {"kernel": "elementwise multiply by 1.0 (torch)", "launches": 3,
+                                               "bytes_read_per_launch": 1 << 30,
+                                               "bytes_written_per_launch": 1 << 30}}), flush=True)
+        return
 
     import paper_1807_11834_amd as cpl
     import workload as W

@@ -452,27 +452,34 @@ __device__ __forceinline__ int slot_hidden(int kb, int g, int i) {
 
 // One layer of the chain for NT tiles: in[t][kb] (KB slot groups) -> 8 row
 // blocks (accumulators start at the bias) -> gelu -> out[t][4] in the paired
-// slot order.  Each weight fragment read from LDS feeds NT products.
+// slot order.  The slot-group loop is outermost so that the 8 NT accumulators
+// form independent MFMA chains (a dependent MFMA waits for its predecessor);
+// each weight fragment read from LDS feeds NT products.
 template <int NT, int KB>
 __device__ __forceinline__ void chain_layer(const InferLds &L, int frag0, const float *bias,
                                             const uint4 (&in)[NT][KB], uint4 (&out)[NT][4], int lane, int g) {
+    f32x4 acc[8][NT];
 #pragma unroll
     for (int mb = 0; mb < 8; ++mb) {
         const int m0 = 16 * mb + 4 * g;
         const f32x4 b = {bias[m0], bias[m0 + 1], bias[m0 + 2], bias[m0 + 3]};
-        f32x4 acc[NT];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) acc[t] = b;
+        for (int t = 0; t < NT; ++t) acc[mb][t] = b;
+    }
 #pragma unroll
-        for (int kb = 0; kb < KB; ++kb) {
+    for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+        for (int mb = 0; mb < 8; ++mb) {
             const bf16x8 w = as_bf16x8(L.frag[frag0 + mb * KB + kb][lane]);
 #pragma unroll
-            for (int t = 0; t < NT; ++t) acc[t] = mma(w, as_bf16x8(in[t][kb]), acc[t]);
+            for (int t = 0; t < NT; ++t) acc[mb][t] = mma(w, as_bf16x8(in[t][kb]), acc[mb][t]);
         }
 #pragma unroll
+    for (int mb = 0; mb < 8; ++mb)
+#pragma unroll
         for (int t = 0; t < NT; ++t) {
-            const uint32_t lo = pack2(gelu(acc[t][0]), gelu(acc[t][1]));
-            const uint32_t hi = pack2(gelu(acc[t][2]), gelu(acc[t][3]));
+            const uint32_t lo = pack2(gelu(acc[mb][t][0]), gelu(acc[mb][t][1]));
+            const uint32_t hi = pack2(gelu(acc[mb][t][2]), gelu(acc[mb][t][3]));
             if (mb & 1) {
                 out[t][mb >> 1].z = lo;
                 out[t][mb >> 1].w = hi;
@@ -481,17 +488,62 @@ __device__ __forceinline__ void chain_layer(const InferLds &L, int frag0, const 
                 out[t][mb >> 1].y = hi;
             }
         }
-    }
 }
 
-// Standardised layer-1 inputs of one particle (sorted index s, valid or not)
-// for lane group g: x[kb] holds unit 4 kb + g.
-__device__ __forceinline__ void gather_features(const StepArgs<float> &a, const InferLds &L, int64_t s, bool valid,
-                                                int g, uint4 (&x)[7]) {
+// Bulk trilinear velocity and void fraction at a particle from the packed
+// features (fgrid[2c] = (eps_c, U_c)): u_bulk = sum_c w_pc U_c and
+// eps_p = sum_c w_pc eps_c with the deposition weights (CIC or NGP).  Where the
+// particle solid fraction exceeds phi_fp64 the sum is taken in FP64 (eps_c =
+// 1 - phi_c is exact for phi_c >= 1/2, where it matters).
+__device__ __forceinline__ float4 bulk_sample_packed(const StepArgs<float> &a, const float4 &q) {
+    const Geo<float> &g = a.g;
+    const Axis<float> bx = cic_axis(q.x, g.sb[0], g.nb[0]);
+    const Axis<float> by = cic_axis(q.y, g.sb[1], g.nb[1]);
+    const Axis<float> bz = cic_axis(q.z, g.sb[2], g.nb[2]);
+    const int64_t nx = g.nb[0], nxy = (int64_t)g.nb[0] * g.nb[1];
+    const int64_t zl = bz.lo * nxy, zh = bz.hi * nxy, yl = by.lo * nx, yh = by.hi * nx;
+    const float4 c000 = a.fgrid[2 * (zl + yl + bx.lo)], c001 = a.fgrid[2 * (zl + yl + bx.hi)];
+    const float4 c010 = a.fgrid[2 * (zl + yh + bx.lo)], c011 = a.fgrid[2 * (zl + yh + bx.hi)];
+    const float4 c100 = a.fgrid[2 * (zh + yl + bx.lo)], c101 = a.fgrid[2 * (zh + yl + bx.hi)];
+    const float4 c110 = a.fgrid[2 * (zh + yh + bx.lo)], c111 = a.fgrid[2 * (zh + yh + bx.hi)];
+    const float sx = 1.f - bx.t, sy = 1.f - by.t, sz = 1.f - bz.t;
+    auto tri = [&](float v000, float v001, float v010, float v011, float v100, float v101, float v110, float v111) {
+        return sz * (sy * (sx * v000 + bx.t * v001) + by.t * (sx * v010 + bx.t * v011)) +
+               bz.t * (sy * (sx * v100 + bx.t * v101) + by.t * (sx * v110 + bx.t * v111));
+    };
+    float4 r;
+    r.x = tri(c000.y, c001.y, c010.y, c011.y, c100.y, c101.y, c110.y, c111.y);
+    r.y = tri(c000.z, c001.z, c010.z, c011.z, c100.z, c101.z, c110.z, c111.z);
+    r.z = tri(c000.w, c001.w, c010.w, c011.w, c100.w, c101.w, c110.w, c111.w);
+    if (a.cic) {
+        const float e = tri(c000.x, c001.x, c010.x, c011.x, c100.x, c101.x, c110.x, c111.x);
+        if (1.f - e > a.phi_fp64) {
+            const double gx = (double)q.x * (double)g.sb[0] - 0.5, gy = (double)q.y * (double)g.sb[1] - 0.5,
+                         gz = (double)q.z * (double)g.sb[2] - 0.5;
+            const double tx = gx - floor(gx), ty = gy - floor(gy), tz = gz - floor(gz);
+            const double ux = 1.0 - tx, uy = 1.0 - ty, uz = 1.0 - tz;
+            r.w = (float)(uz * (uy * (ux * (double)c000.x + tx * (double)c001.x) +
+                                ty * (ux * (double)c010.x + tx * (double)c011.x)) +
+                          tz * (uy * (ux * (double)c100.x + tx * (double)c101.x) +
+                                ty * (ux * (double)c110.x + tx * (double)c111.x)));
+        } else {
+            r.w = e;
+        }
+    } else {
+        const int ix = cell_axis(q.x, g.sb[0], g.nb[0]), iy = cell_axis(q.y, g.sb[1], g.nb[1]),
+                  iz = cell_axis(q.z, g.sb[2], g.nb[2]);
+        r.w = a.fgrid[2 * (ix + nx * iy + nxy * iz)].x;
+    }
+    return r;
+}
+
+// Standardised layer-1 inputs of one particle (clamped position and diameter q,
+// containing cell c0; zero when not valid) for lane group g: x[kb] holds unit
+// 4 kb + g.
+__device__ __forceinline__ void gather_features(const StepArgs<float> &a, const InferLds &L, const float4 &q,
+                                                int64_t c0, bool valid, int g, uint4 (&x)[7]) {
     const Geo<float> &geo = a.g;
     const int64_t nx = geo.nb[0], nxy = (int64_t)geo.nb[0] * geo.nb[1];
-    const float4 q = a.sp[s];
-    int64_t c0 = a.keys[s];
     if (c0 < 0 || c0 >= geo.ncell) c0 = 0;
     int ix, iy, iz;
     decode_cell(c0, geo.nb, ix, iy, iz);
@@ -544,7 +596,8 @@ __device__ __forceinline__ void gather_features(const StepArgs<float> &a, const 
 // (neighbouring cells: the stencil loads hit L1/L2), each wave kInfRows particles
 // per round.  Lane (n, g) gathers, for tile t and slot group kb, unit 4 kb + g of
 // particle 16 t + n; lanes with g < kInfTiles then finish particle 16 g + n:
-// u = u_bulk + s * y and eps_p, written to uf4[id].
+// u = u_bulk + s * y and eps_p (both from the packed features), written to
+// uf4[id].
 __global__ __launch_bounds__(kInfWaves * kWave) void k_infer(StepArgs<float> a) {
     __shared__ InferLds L;
     constexpr int NT = kInfTiles;
@@ -584,24 +637,33 @@ __global__ __launch_bounds__(kInfWaves * kWave) void k_infer(StepArgs<float> a) 
     const int64_t s_begin = (int64_t)blockIdx.x * per;
     const int64_t s_end = (s_begin + per < a.n) ? s_begin + per : a.n;
     for (int64_t base = s_begin + (int64_t)wave * kInfRows; base < s_end; base += kInfWaves * kInfRows) {
-        // the particle this lane finishes: its bulk velocity, void fraction and id
-        // are fetched first so that their loads overlap the chain
+        float4 q[NT];
+        int64_t c[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            int64_t s = base + 16 * t + n;
+            s = s < s_end ? s : base;
+            q[t] = a.sp[s];
+            c[t] = a.keys[s];
+        }
+        // the particle this lane finishes (tile g): its bulk velocity, void
+        // fraction and id are fetched first so that their loads overlap the chain
         const int64_t so = base + 16 * g + n;
         const bool own = (g < NT) && so < s_end;
         float4 r = make_float4(0.f, 0.f, 0.f, 0.f);
         int64_t p = 0;
         if (own) {
-            r = sample_one(a.sp[so], a, 1);
+            float4 qo = q[0];
+#pragma unroll
+            for (int t = 1; t < NT; ++t)
+                if (g == t) qo = q[t];
+            r = bulk_sample_packed(a, qo);
             p = a.perm[so];
             if (p < 0 || p >= a.n) p = 0;
         }
         uint4 x[NT][7];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const int64_t s = base + 16 * t + n;
-            const bool valid = s < s_end;
-            gather_features(a, L, valid ? s : base, valid, g, x[t]);
-        }
+        for (int t = 0; t < NT; ++t) gather_features(a, L, q[t], c[t], base + 16 * t + n < s_end, g, x[t]);
         uint4 h1[NT][4], h2[NT][4];
         chain_layer<NT, 7>(L, 0, L.bias, x, h1, lane, g);
         chain_layer<NT, 4>(L, kFrag1, L.bias + kHid, h1, h2, lane, g);

@@ -66,17 +66,13 @@ __device__ __forceinline__ void fine_velocity(const vec4<T> &q, const StepArgs<T
     uz = trilin_pairs(a.fine[2], fx, fy, fz, nx, nxy);
 }
 
-// Void fraction and fluid velocity at one particle (clamped position q.xyz):
-// eps_p = sum_c w_pc (1 - phi_c) (the transpose of the deposition weights) and
-// u_f by source src (0: trilinear on the fine grid, 1: trilinear on the
-// restricted bulk velocity, otherwise 0).  In the FP32 modes, where the particle
-// solid fraction exceeds phi_fp64 (near close packing), phi_p and 1 - phi_p are
-// formed in FP64 from the same eight bulk values.
-template <typename T>
-__device__ __forceinline__ vec4<T> sample_one(const vec4<T> &q, const StepArgs<T> &a, int src) {
+// Void fraction at one particle (clamped position q.xyz): eps_p = sum_c w_pc
+// (1 - phi_c), the transpose of the deposition weights.  In the FP32 modes,
+// where the particle solid fraction exceeds phi_fp64 (near close packing), phi_p
+// and 1 - phi_p are formed in FP64 from the same eight bulk values.
+template <typename T> __device__ __forceinline__ T eps_at(const vec4<T> &q, const StepArgs<T> &a) {
     const Geo<T> &g = a.g;
     const T *__restrict__ phi = a.phi;
-    vec4<T> s;
     T eps;
     if (a.cic) {
         const Axis<T> bx = cic_axis(q.x, g.sb[0], g.nb[0]);
@@ -120,7 +116,17 @@ __device__ __forceinline__ vec4<T> sample_one(const vec4<T> &q, const StepArgs<T
         const int iz = cell_axis(q.z, g.sb[2], g.nb[2]);
         eps = T(1) - phi[ix + (int64_t)g.nb[0] * (iy + (int64_t)g.nb[1] * iz)];  // exact for phi in [1/2, 1]
     }
-    s.w = eps;
+    return eps;
+}
+
+// Void fraction and fluid velocity at one particle: eps_at() and u_f by source
+// src (0: trilinear on the fine grid, 1: trilinear on the restricted bulk
+// velocity, otherwise 0).
+template <typename T>
+__device__ __forceinline__ vec4<T> sample_one(const vec4<T> &q, const StepArgs<T> &a, int src) {
+    const Geo<T> &g = a.g;
+    vec4<T> s;
+    s.w = eps_at(q, a);
     if (src == 0) {
         fine_velocity(q, a, s.x, s.y, s.z);
     } else if (src == 1) {

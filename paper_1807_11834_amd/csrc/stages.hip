@@ -8,11 +8,12 @@
 //   deposit phi    (deposit.hip)
 //   k_restrict     one thread per bulk cell streams its r^3 fine children of
 //                  u, v, w, p (one 16-byte row load per (z, y) child row for
-//                  r = 4) and writes the compensated averages U, P.  With the
-//                  fine-grid velocity source the same wave then samples the
-//                  particles of its 64 cells (fine trilinear velocity, void
-//                  fraction) while their fine rows are still in L2: the fine
-//                  lookup costs no extra pass over the fine grid.
+//                  r = 4) and writes the compensated averages U, P.
+//   k_restrict_brick  the same restriction tiled in 8x4x2-cell bricks with the
+//                  fine-grid lookup fused: the brick's fine u, v, w stay in LDS
+//                  and its particles are sampled from there (fine trilinear
+//                  velocity, void fraction from a haloed copy of phi), so the
+//                  fine lookup costs no extra pass over the fine grid.
 //   k_sample       the same sampling for the bulk and given velocity sources.
 //   k_drag         drag and explicit Euler advection in input order (coalesced).
 //   deposit force  (deposit.hip), with the bulk pressure gradient.
@@ -120,9 +121,9 @@ __device__ __forceinline__ void sample_particles(const int64_t (&idx)[KB], const
 }
 
 // ---------------------------------------------------------------------------
-// Restriction fine -> bulk (+ fused fine lookup of the particles)
+// Restriction fine -> bulk
 // ---------------------------------------------------------------------------
-template <typename T, int R, bool KAHAN, bool LOOKUP>
+template <typename T, int R, bool KAHAN>
 __global__ __launch_bounds__(kBlock) void k_restrict(StepArgs<T> a) {
     const Geo<T> &g = a.g;
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -159,19 +160,186 @@ __global__ __launch_bounds__(kBlock) void k_restrict(StepArgs<T> a) {
             }
         }
     }
-    if constexpr (LOOKUP) {
-        // the particles of this workgroup's 256 cells, while their fine rows are
-        // in L2, shared by all its threads, two per thread at a time
-        const int64_t c0 = tile * kBlock;
-        if (c0 < g.ncell) {
-            const int64_t c1 = (c0 + kBlock < g.ncell) ? c0 + kBlock : g.ncell;
-            const int64_t s = seg_clamp(a.start[c0], a.n), e = seg_clamp(a.start[c1], a.n);
-            for (int64_t i = s + threadIdx.x; i < e; i += 2 * kBlock) {
-                const int64_t idx[2] = {i, (i + kBlock < e) ? i + kBlock : -1};
-                sample_particles<T, 2>(idx, a);
+}
+
+// Restriction with the fine-grid lookup, tiled in bricks of 8 x 4 x 2 bulk
+// cells, one wave per brick (lane = cell).  Each lane restricts its cell's r^3
+// children of u, v, w, p and also keeps u, v, w in LDS; the brick's particles
+// (8 rows of up to 8 cells, contiguous in the sorted order) then take their
+// trilinear fine velocity from LDS when all eight fine nodes lie in the brick,
+// from global memory otherwise (a stencil that crosses the brick's faces).
+// The brick is 8R fine cells wide along x (one 128-byte line per row for r = 4
+// in FP32), so its loads are whole lines.
+constexpr int kBrickX = 8, kBrickY = 4, kBrickZ = 2;
+
+template <typename T, int R, bool KAHAN>
+__global__ __launch_bounds__(kWave) void k_restrict_brick(StepArgs<T> a) {
+    constexpr int FX = kBrickX * R, FY = kBrickY * R, FZ = kBrickZ * R;
+    constexpr int HX = kBrickX + 2, HY = kBrickY + 2, HZ = kBrickZ + 2;   // bulk cells with a one-cell halo
+    constexpr int NROW = kBrickY * kBrickZ;
+    __shared__ T sv[3][FZ][FY][FX];
+    __shared__ T sphi[HZ][HY][HX];
+    __shared__ int32_t srow[NROW + 1];   // particle-segment prefix over the brick's rows
+    __shared__ int32_t sbeg[NROW];
+    const Geo<T> &g = a.g;
+    const int bnx = (g.nb[0] + kBrickX - 1) / kBrickX, bny = (g.nb[1] + kBrickY - 1) / kBrickY;
+    const int64_t brick = xcd_tile(blockIdx.x, gridDim.x);
+    const int ox = (int)(brick % bnx) * kBrickX, oy = (int)((brick / bnx) % bny) * kBrickY,
+              oz = (int)(brick / ((int64_t)bnx * bny)) * kBrickZ;
+    const int lane = threadIdx.x;
+    const int lx = lane % kBrickX, ly = (lane / kBrickX) % kBrickY, lz = lane / (kBrickX * kBrickY);
+    const int cx = ox + lx, cy = oy + ly, cz = oz + lz;
+    const int64_t nx = g.nb[0], nxy = (int64_t)g.nb[0] * g.nb[1];
+    const int64_t nfx = g.nf[0], nfxy = (int64_t)g.nf[0] * g.nf[1];
+    // the brick's particle rows and phi with its halo (indices clamped at the walls)
+    const int wx = (ox + kBrickX < g.nb[0]) ? kBrickX : g.nb[0] - ox;
+    if (lane < NROW) {
+        const int ry = oy + lane % kBrickY, rz = oz + lane / kBrickY;
+        int32_t b0 = 0, cnt = 0;
+        if (ry < g.nb[1] && rz < g.nb[2]) {
+            const int64_t c0 = ox + nx * ry + nxy * rz;
+            b0 = seg_clamp(a.start[c0], a.n);
+            cnt = seg_clamp(a.start[c0 + wx], a.n) - b0;
+        }
+        sbeg[lane] = b0;
+        srow[lane + 1] = cnt;
+    }
+    for (int e = lane; e < HX * HY * HZ; e += kWave) {
+        const int hx = e % HX, hy = (e / HX) % HY, hz = e / (HX * HY);
+        const int gx = clampi(ox - 1 + hx, g.nb[0]), gy = clampi(oy - 1 + hy, g.nb[1]), gz = clampi(oz - 1 + hz, g.nb[2]);
+        sphi[hz][hy][hx] = a.phi[gx + nx * gy + nxy * gz];
+    }
+    if (cx < g.nb[0] && cy < g.nb[1] && cz < g.nb[2]) {
+        const int64_t c = cx + nx * cy + nxy * cz;
+        const int64_t base = (int64_t)R * cz * nfxy + (int64_t)R * cy * nfx + (int64_t)R * cx;
+        const T inv = T(1) / T(R * R * R);
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            const T *__restrict__ q = a.fine[f] + base;
+            Row<T, R> rows[R][R];
+#pragma unroll
+            for (int rz = 0; rz < R; ++rz)
+#pragma unroll
+                for (int ry = 0; ry < R; ++ry) rows[rz][ry] = load_row<T, R>(q + rz * nfxy + ry * nfx);
+            Acc<T, KAHAN> acc;
+#pragma unroll
+            for (int rz = 0; rz < R; ++rz)
+#pragma unroll
+                for (int ry = 0; ry < R; ++ry)
+#pragma unroll
+                    for (int rx = 0; rx < R; ++rx) acc.add(rows[rz][ry].v[rx]);
+            const T val = acc.s * inv;   // 1/R^3 is a power of two: the scaling is exact
+            if (f < 3) {
+                a.U[f * g.ncell + c] = val;
+#pragma unroll
+                for (int rz = 0; rz < R; ++rz)
+#pragma unroll
+                    for (int ry = 0; ry < R; ++ry)
+#pragma unroll
+                        for (int rx = 0; rx < R; ++rx) sv[f][lz * R + rz][ly * R + ry][lx * R + rx] = rows[rz][ry].v[rx];
+            } else {
+                a.P[c] = val;
+                // the compensated sum is s - c: keep -c/R^3 so that the pressure
+                // gradient can difference (hi + lo) instead of the rounded hi
+                a.Plo[c] = -acc.c * inv;
             }
         }
     }
+    __syncthreads();
+    if (lane == 0) {
+        srow[0] = 0;
+        for (int r = 0; r < NROW; ++r) srow[r + 1] += srow[r];
+    }
+    __syncthreads();
+    const int total = srow[NROW];
+    const int fx0 = ox * R, fy0 = oy * R, fz0 = oz * R;
+    // up to kPB particles per lane at a time: their loads are issued together
+    constexpr int kPB = 4;
+    for (int j0 = lane; j0 < total; j0 += kPB * kWave) {
+        vec4<T> qs[kPB];
+        int64_t ps[kPB];
+#pragma unroll
+        for (int k = 0; k < kPB; ++k) {
+            const int j = j0 + k * kWave;
+            int64_t i = sbeg[0];
+            if (j < total) {
+                int r = 0;
+                while (r + 1 < NROW && srow[r + 1] <= j) ++r;
+                i = sbeg[r] + (j - srow[r]);
+            }
+            qs[k] = a.sp[i];
+            ps[k] = a.perm[i];
+        }
+#pragma unroll
+        for (int k = 0; k < kPB; ++k) {
+        if (j0 + k * kWave >= total) break;
+        const vec4<T> q = qs[k];
+        int64_t p = ps[k];
+        if (p < 0 || p >= a.n) p = 0;   // perm is a permutation of [0, n)
+        vec4<T> s;
+        // fine trilinear velocity: from LDS when the eight nodes lie in the brick
+        const Axis<T> ax = cic_axis(q.x, g.sf[0], g.nf[0]);
+        const Axis<T> ay = cic_axis(q.y, g.sf[1], g.nf[1]);
+        const Axis<T> az = cic_axis(q.z, g.sf[2], g.nf[2]);
+        const int xl = ax.lo - fx0, xh = ax.hi - fx0, yl = ay.lo - fy0, yh = ay.hi - fy0, zl = az.lo - fz0,
+                  zh = az.hi - fz0;
+        if (xl >= 0 && xh < FX && yl >= 0 && yh < FY && zl >= 0 && zh < FZ) {
+            const T sx = T(1) - ax.t, sy = T(1) - ay.t, sz = T(1) - az.t;
+            T u[3];
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                const T e0 = sy * (sx * sv[f][zl][yl][xl] + ax.t * sv[f][zl][yl][xh]) +
+                             ay.t * (sx * sv[f][zl][yh][xl] + ax.t * sv[f][zl][yh][xh]);
+                const T e1 = sy * (sx * sv[f][zh][yl][xl] + ax.t * sv[f][zh][yl][xh]) +
+                             ay.t * (sx * sv[f][zh][yh][xl] + ax.t * sv[f][zh][yh][xh]);
+                u[f] = sz * e0 + az.t * e1;
+            }
+            s.x = u[0];
+            s.y = u[1];
+            s.z = u[2];
+        } else {
+            fine_velocity(q, a, s.x, s.y, s.z);
+        }
+        // void fraction at the particle from the haloed phi (its stencil is the
+        // containing cell and a neighbour, always inside the halo)
+        if (a.cic) {
+            const Axis<T> bx = cic_axis(q.x, g.sb[0], g.nb[0]);
+            const Axis<T> by = cic_axis(q.y, g.sb[1], g.nb[1]);
+            const Axis<T> bz = cic_axis(q.z, g.sb[2], g.nb[2]);
+            const int hxl = bx.lo - ox + 1, hxh = bx.hi - ox + 1, hyl = by.lo - oy + 1, hyh = by.hi - oy + 1,
+                      hzl = bz.lo - oz + 1, hzh = bz.hi - oz + 1;
+            const T f000 = sphi[hzl][hyl][hxl], f001 = sphi[hzl][hyl][hxh], f010 = sphi[hzl][hyh][hxl],
+                    f011 = sphi[hzl][hyh][hxh], f100 = sphi[hzh][hyl][hxl], f101 = sphi[hzh][hyl][hxh],
+                    f110 = sphi[hzh][hyh][hxl], f111 = sphi[hzh][hyh][hxh];
+            const T sx = T(1) - bx.t, sy = T(1) - by.t, sz = T(1) - bz.t;
+            const T phi_p = sz * (sy * (sx * f000 + bx.t * f001) + by.t * (sx * f010 + bx.t * f011)) +
+                            bz.t * (sy * (sx * f100 + bx.t * f101) + by.t * (sx * f110 + bx.t * f111));
+            if (std::is_same<T, float>::value && phi_p > (T)a.phi_fp64) {
+                // FP64 weights from the same positions; the cancellation in 1 - phi is exact
+                const double gx = (double)q.x * (double)g.sb[0] - 0.5, gy = (double)q.y * (double)g.sb[1] - 0.5,
+                             gz = (double)q.z * (double)g.sb[2] - 0.5;
+                const double tx = gx - floor(gx), ty = gy - floor(gy), tz = gz - floor(gz);
+                const double ux = 1.0 - tx, uy = 1.0 - ty, uz = 1.0 - tz;
+                const double ph =
+                    uz * (uy * (ux * (double)f000 + tx * (double)f001) + ty * (ux * (double)f010 + tx * (double)f011)) +
+                    tz * (uy * (ux * (double)f100 + tx * (double)f101) + ty * (ux * (double)f110 + tx * (double)f111));
+                s.w = (T)(1.0 - ph);
+            } else {
+                s.w = T(1) - phi_p;
+            }
+        } else {
+            const int ix = cell_axis(q.x, g.sb[0], g.nb[0]), iy = cell_axis(q.y, g.sb[1], g.nb[1]),
+                      iz = cell_axis(q.z, g.sb[2], g.nb[2]);
+            s.w = T(1) - sphi[iz - oz + 1][iy - oy + 1][ix - ox + 1];
+        }
+        a.uf4[p] = s;
+        }
+    }
+}
+
+template <typename T, int R> int64_t brick_blocks(const Geo<T> &g) {
+    return (int64_t)((g.nb[0] + kBrickX - 1) / kBrickX) * ((g.nb[1] + kBrickY - 1) / kBrickY) *
+           ((g.nb[2] + kBrickZ - 1) / kBrickZ);
 }
 
 // Sampling for the bulk-velocity and given-velocity sources (sorted order).
@@ -428,11 +596,12 @@ static void launch_grid_stages(const StepArgs<T> &a, hipStream_t st) {
     const int64_t pb = (a.n + kBlock - 1) / kBlock;
     if (a.vel_source == 0) {
         a.mk->mark("restrict_lookup", st);
-        hipLaunchKernelGGL((k_restrict<T, R, KAHAN, true>), dim3(cb), dim3(kBlock), 0, st, a);
+        hipLaunchKernelGGL((k_restrict_brick<T, R, KAHAN>), dim3((unsigned)brick_blocks<T, R>(a.g)), dim3(kWave), 0,
+                           st, a);
     } else if (a.vel_source == 3) {
         if constexpr (std::is_same<T, float>::value) {
             a.mk->mark("restrict", st);
-            hipLaunchKernelGGL((k_restrict<T, R, KAHAN, false>), dim3(cb), dim3(kBlock), 0, st, a);
+            hipLaunchKernelGGL((k_restrict<T, R, KAHAN>), dim3(cb), dim3(kBlock), 0, st, a);
             a.mk->mark("mlp_pack", st);
             launch_mlp_pack(a, st);
             if (a.n > 0) {
@@ -444,7 +613,7 @@ static void launch_grid_stages(const StepArgs<T> &a, hipStream_t st) {
         }
     } else {
         a.mk->mark("restrict", st);
-        hipLaunchKernelGGL((k_restrict<T, R, KAHAN, false>), dim3(cb), dim3(kBlock), 0, st, a);
+        hipLaunchKernelGGL((k_restrict<T, R, KAHAN>), dim3(cb), dim3(kBlock), 0, st, a);
         if (a.n > 0) a.mk->mark("sample", st);
         if (a.n > 0) hipLaunchKernelGGL(k_sample<T>, dim3(pb), dim3(kBlock), 0, st, a);
     }

@@ -283,8 +283,8 @@ def _bricks_with_sample(cell, nb, period, phase):
 
 def test_fallback_on_bad_network(env):
     """An untrained network fails the sampled check: every brick that holds a
-    checked particle falls back to the fine lookup (bitwise the plain path's
-    velocity), the others keep the network's; counts match."""
+    checked particle falls back to the fine lookup (the plain path's velocity),
+    the others keep the network's; counts match."""
     torch, cpl, oracle = env
     case = _small_case(torch, cpl, nb=(20, 18, 17), n=30000)
     feat, ub, res = _features(torch, cpl, case)
@@ -298,7 +298,11 @@ def test_fallback_on_bad_network(env):
     d = g["diag_d"]
     assert d["n_fallback"] == fell.sum() and 0 < fell.sum() < fell.size
     assert d["mlp_nsamp"] == np.sum(np.arange(fell.size) % period == step % period)
-    np.testing.assert_array_equal(g["uf"][fell], case["host"]["uf"][fell])
+    # the fallback is the plain path's trilinear lookup of the same fine values
+    # (read from global memory there, from LDS in the plain kernel): equal to
+    # FP32 rounding
+    ulp = 2.0 ** -23 * np.abs(case["host"]["uf"]).max()
+    np.testing.assert_allclose(g["uf"][fell], case["host"]["uf"][fell], rtol=0, atol=2 * ulp)
     assert np.all(np.any(g["uf"][~fell] != case["host"]["uf"][~fell], axis=1))
     # the sampled error the step reports is that of the network before fallback
     ids = np.arange(fell.size) % period == step % period
@@ -307,7 +311,9 @@ def test_fallback_on_bad_network(env):
     fine_u = case["host"]["uf"][ids].astype(np.float64)
     e2 = np.sum((pre[ids] - fine_u) ** 2)
     r2 = np.sum(fine_u ** 2)
-    assert abs(d["mlp_err2"] - e2) <= 1e-9 * e2 and abs(d["mlp_ref2"] - r2) <= 1e-9 * r2
+    # (the check looks the fine velocity up itself; it agrees with the plain
+    # path to FP32 rounding)
+    assert abs(d["mlp_err2"] - e2) <= 1e-6 * e2 and abs(d["mlp_ref2"] - r2) <= 1e-6 * r2
     net.close()
 
 
@@ -321,7 +327,8 @@ def test_fallback_everywhere_with_zero_tolerance(env):
     g = _mlp_step(torch, cpl, case, net, tol=0.0, period=1)
     assert g["diag_d"]["n_fallback"] == case["pos"].shape[0]
     assert g["diag_d"]["mlp_nsamp"] == case["pos"].shape[0]
-    np.testing.assert_array_equal(g["uf"], case["host"]["uf"])
+    ulp = 2.0 ** -23 * np.abs(case["host"]["uf"]).max()
+    np.testing.assert_allclose(g["uf"], case["host"]["uf"], rtol=0, atol=2 * ulp)
     # the void fraction at the particle comes from another kernel (the compiler
     # may contract its products differently): equal to FP32 rounding
     np.testing.assert_allclose(g["drag"], case["host"]["drag"], rtol=1e-5, atol=1e-6 * np.abs(g["drag"]).max())
