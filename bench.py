@@ -59,6 +59,108 @@ def step_alg_bytes(n, ncell, nfine, fsz, sort_passes):
     return fine + particles + bulk + sort
 
 
+# Marks of the library's kernel timing -> the kernel names rocprofv3 reports.
+PROFILE_NAMES = {
+    "restrict_lookup": "cpl::k_restrict_brick<float, 4, true>",
+    "restrict": "cpl::k_restrict<float, 4, true>",
+    "prolong": "cpl::k_prolong<float, 4>",
+    "mlp_infer": "cpl::mlp::k_infer",
+}
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_bed128.json")
+
+
+def csrc_sha256():
+    """Hash of the HIP sources: profiled counters apply only to this build."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1807_11834_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp")):
+            h.update(f.encode())
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def profiled_traffic(mark):
+    """HBM bytes per launch of the kernel behind ``mark`` from the committed
+    counter profile, or None when there is none or the sources have changed."""
+    try:
+        with open(TRAFFIC_PROFILE) as f:
+            prof = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if prof.get("csrc_sha256") != csrc_sha256():
+        return None
+    k = prof.get("kernels", {}).get(PROFILE_NAMES.get(mark, mark))
+    return None if k is None else k["traffic_bytes_per_launch"]
+
+
+def _pmc_means(path):
+    """Mean counter value per kernel (KiB per dispatch) from a rocprofv3 csv."""
+    import csv
+    import glob
+    import re
+    vals = {}
+    for fn in glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True):
+        with open(fn) as f:
+            for r in csv.DictReader(f):
+                k = re.sub(r"\(.*", "", r["Kernel_Name"]).replace("void ", "").strip()
+                vals.setdefault(k, []).append(float(r["Counter_Value"]))
+    return {k: (sum(v) / len(v), len(v)) for k, v in vals.items()}
+
+
+def traffic_summary(d):
+    """JSON summary of the FETCH_SIZE / WRITE_SIZE runs under directory ``d``,
+    each counter scaled by what it reads for the 1 GiB copy of --copy-calibration:
+    subdirectories fetch, write (the plain path, --no-mlp), fetch_mlp, write_mlp
+    (with the surrogate: only its in-step kernels are taken from these, the
+    others also ran on the training workload), cal_fetch, cal_write."""
+    fetch, write = _pmc_means(os.path.join(d, "fetch")), _pmc_means(os.path.join(d, "write"))
+    fm, wm = _pmc_means(os.path.join(d, "fetch_mlp")), _pmc_means(os.path.join(d, "write_mlp"))
+    for k in ("cpl::mlp::k_pack", "cpl::mlp::k_infer", "cpl::mlp::k_check"):
+        if k in fm and k in wm:
+            fetch[k], write[k] = fm[k], wm[k]
+    cf, cw = _pmc_means(os.path.join(d, "cal_fetch")), _pmc_means(os.path.join(d, "cal_write"))
+    copy = [k for k in cf if "AUnaryFunctor" in k or "MulFunctor" in k]
+    if not copy:
+        raise SystemExit("no copy kernel in the calibration runs")
+    gib_kib = float(1 << 20)
+    f_fetch, f_write = gib_kib / cf[copy[0]][0], gib_kib / cw[copy[0]][0]
+    kernels = {}
+    for k in sorted(set(fetch) & set(write)):
+        if not k.startswith("cpl::"):
+            continue
+        fk, fn = fetch[k]
+        wk, _ = write[k]
+        kernels[k] = {"dispatches": fn, "fetch_kib": round(fk, 1), "write_kib": round(wk, 1),
+                      "traffic_bytes_per_launch": int(round((fk * f_fetch + wk * f_write) * 1024))}
+    return {
+        "workload": "bed128_cic: 10,000,000 particles, bulk 128x128x256, fine 512x512x1024, FP32",
+        "csrc_sha256": csrc_sha256(),
+        "calibration": {"kernel": copy[0], "bytes_read": 1 << 30, "bytes_written": 1 << 30,
+                        "fetch_kib": cf[copy[0]][0], "write_kib": cw[copy[0]][0],
+                        "fetch_factor": round(f_fetch, 4), "write_factor": round(f_write, 4)},
+        "kernels": kernels,
+    }
+
+
+def trace_summary(csv_path):
+    """Markdown table of a rocprofv3 --stats kernel summary (library kernels)."""
+    import csv
+    import re
+    with open(csv_path) as f:
+        rows = list(csv.DictReader(f))
+    lines = ["| kernel | calls | avg us | min us | max us | share of traced GPU time |", "|---|---|---|---|---|---|"]
+    for r in rows:
+        n = re.sub(r"\(.*", "", r["Name"]).replace("void ", "").strip()
+        if not n.startswith("cpl::"):
+            continue
+        lines.append(f"| `{n}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
+                     f"{float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.1f}% |")
+    return "\n".join(lines)
+
+
 def sort_passes(ncell):
     bits = 1
     while (1 << bits) < ncell:
@@ -208,7 +310,7 @@ def mlp_leg(args, w, cfg, pos, vel, diam, fine, plain_ms, plain_kernels, dev):
                             if dfin["mlp_ref2"] else None, "fallback_particles": dfin["n_fallback"]},
         "roofline": {"bound": "mfma", "kernel": "mlp_infer", "achieved": round(ach, 1),
                      "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(ach / MFMA_BF16_PEAK_TFLOPS, 4),
-                     "traffic": None, "flop_per_launch": flop, "avg_ms": round(t_inf, 4)},
+                     "traffic": profiled_traffic("mlp_infer"), "flop_per_launch": flop, "avg_ms": round(t_inf, 4)},
         "kernels_avg_ms": {k: round(v["avg_ms"], 4) for k, v in kern.items()},
         "train": {"steps": args.mlp_steps, "batch": 65536, "seconds": round(t_train, 1),
                   "pairs_seconds": round(t_pairs, 1), "loss_first_last": [hist[0][1], hist[-1][1]],
@@ -229,11 +331,21 @@ def main():
     ap.add_argument("--vel-source", default="fine", choices=["fine", "bulk"],
                     help="fluid velocity at the particles: fine-grid lookup (default) or bulk trilinear")
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned-surrogate path")
+    ap.add_argument("--traffic-summary", metavar="DIR",
+                    help="print the JSON summary of the FETCH_SIZE/WRITE_SIZE runs under DIR and exit")
+    ap.add_argument("--trace-summary", metavar="CSV",
+                    help="print a markdown table of a rocprofv3 kernel_stats.csv and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain copy kernel of known size (1 GiB read, 1 GiB written, 3 times): "
                          "the reference that scales the FETCH_SIZE / WRITE_SIZE counters to bytes")
     ap.add_argument("--mlp-steps", type=int, default=20000, help="surrogate training steps (batch 65,536)")
     args = ap.parse_args()
+    if args.traffic_summary:
+        print(json.dumps(traffic_summary(args.traffic_summary), indent=1))
+        return
+    if args.trace_summary:
+        print(trace_summary(args.trace_summary))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the coupling exchange is built and timed for a single "
               "MI355X (the multi-GPU sharding is a design in DESIGN.md, not built); run with --gpus 1",
@@ -304,7 +416,7 @@ def main():
     if ab is not None:
         ach = ab / (kernels[dom]["avg_ms"] * 1e-3) / 1e9
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBPS, 4), "traffic": None,
+                "frac": round(ach / HBM_PEAK_GBPS, 4), "traffic": profiled_traffic(dom),
                 "alg_bytes_per_launch": ab, "avg_ms": round(kernels[dom]["avg_ms"], 4)}
     sb = step_alg_bytes(n, g.n_bulk, g.n_fine, fsz, sort_passes(g.n_bulk))
     d = cpl.diag_dict(out["diag"])
