@@ -172,3 +172,63 @@ def test_precision_study_bed128_sub2m(env, tmp_path):
     assert max(report["fp64"]["e_max"].values()) <= TOL_FP64_FIELD
     assert max(report["fp32_kahan"]["e_max"].values()) <= TOL_FP32_FIELD
     assert max(report["fp32_naive"]["e_max"].values()) <= TOL_NAIVE
+
+
+def test_bed128_surrogate_full_size_sampled(env):
+    """The surrogate step on the 10M-particle bed in the benchmark's launch
+    configuration (vel_source MLP, no fallback): on 20,000 sampled particles the
+    network part of the velocity matches the BF16-emulating oracle network fed
+    with the features of the GPU's own bulk fields; the bulk fields equal the
+    plain step's."""
+    torch, cpl, oracle = env
+    from oracle import mlp as M
+    w = W.WORKLOADS["bed128_cic"]
+    pos, d, vel = W.particles(w)
+    n = pos.shape[0]
+    dev = "cuda:0"
+    P, V, D = to_dev(pos, torch, dev), to_dev(vel, torch, dev), to_dev(d, torch, dev)
+    Fd = W.fine_fields_torch(w, dev, torch.float32)
+    cfg = cfg_for(cpl, w, n)
+    print("case bed128 surrogate: plain step", flush=True)
+    c = cpl.Coupler(cfg)
+    out = c.step(P, V, D, Fd, uf=True)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(13)
+
+    def feats(ids):
+        S = torch.from_numpy(ids.astype(np.int32)).to(dev)
+        f = torch.empty((ids.size, 193), dtype=torch.float32, device=dev)
+        ub = torch.empty((ids.size, 3), dtype=torch.float32, device=dev)
+        r = torch.empty((ids.size, 3), dtype=torch.float32, device=dev)
+        cpl.couple_mlp_features(cfg, P, D, out["bulk_phi"], out["bulk_U"], out["bulk_G"], f, u_fine=out["uf"],
+                                sel=S, u_bulk=ub, resid=r)
+        torch.cuda.synchronize()
+        return f.cpu().numpy().astype(np.float64), ub.cpu().numpy().astype(np.float64), r.cpu().numpy()
+
+    X, _, R = feats(rng.choice(n, 200_000, replace=False))
+    mean, std = M.norm_stats(X)
+    scale = M.target_scale(R)
+    rp = np.random.default_rng(1013)
+    params = [(Wl, rp.standard_normal(b.shape) * 0.2) for Wl, b in M.init_params(13)]
+    net = cpl.Mlp(1024)
+    net.set_params(M.flatten(params))
+    net.set_norm(mean, std, scale)
+    cm = cpl.Config(**{**cfg.__dict__, "vel_source": cpl.COUPLE_VEL_MLP, "mlp_tol": 1e30})
+    h = cpl.Coupler(cm)
+    cpl.couple_set_mlp(h.h, net.m)
+    print("case bed128 surrogate: surrogate step", flush=True)
+    om = h.step(P, V, D, Fd, uf=True, step=3)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(om["bulk_U"].cpu().numpy(), out["bulk_U"].cpu().numpy())
+    np.testing.assert_array_equal(om["bulk_phi"].cpu().numpy(), out["bulk_phi"].cpu().numpy())
+    assert cpl.diag_dict(om["diag"])["n_fallback"] == 0
+    ids = rng.choice(n, 20_000, replace=False)
+    Xs, ubs, _ = feats(ids)
+    Y, _ = M.forward(params, M.standardise(Xs, mean, std), emulate=True)
+    g = om["uf"].cpu().numpy()[ids].astype(np.float64)
+    e = float(np.linalg.norm(g - ubs - Y * scale) / np.linalg.norm(Y * scale))
+    print(f"bed128 surrogate, network part on 20,000 samples: rel {e:.2e}", flush=True)
+    h.close()
+    c.close()
+    net.close()
+    assert e <= 1e-3
