@@ -142,13 +142,19 @@ __global__ __launch_bounds__(kBlock) void k_restrict(StepArgs<T> a) {
             for (int lz = 0; lz < R; ++lz)
 #pragma unroll
                 for (int ly = 0; ly < R; ++ly) rows[lz][ly] = load_row<T, R>(q + lz * nfxy + ly * nfx);
+            // per fine child plane, then the planes in order (s_0, -c_0, s_1, ...):
+            // the same sums as the brick-tiled kernel
             Acc<T, KAHAN> acc;
 #pragma unroll
-            for (int lz = 0; lz < R; ++lz)
+            for (int lz = 0; lz < R; ++lz) {
+                Acc<T, KAHAN> plane;
 #pragma unroll
                 for (int ly = 0; ly < R; ++ly)
 #pragma unroll
-                    for (int lx = 0; lx < R; ++lx) acc.add(rows[lz][ly].v[lx]);
+                    for (int lx = 0; lx < R; ++lx) plane.add(rows[lz][ly].v[lx]);
+                acc.add(plane.s);
+                if constexpr (KAHAN) acc.add(-plane.c);
+            }
             T val = acc.s * inv;   // 1/R^3 is a power of two: the scaling is exact
             if (f < 3) {
                 a.U[f * g.ncell + c] = val;
@@ -163,80 +169,98 @@ __global__ __launch_bounds__(kBlock) void k_restrict(StepArgs<T> a) {
 }
 
 // Restriction with the fine-grid lookup, tiled in bricks of 8 x 4 x 2 bulk
-// cells, one wave per brick (lane = cell).  Each lane restricts its cell's r^3
-// children of u, v, w, p and also keeps u, v, w in LDS; the brick's particles
-// (8 rows of up to 8 cells, contiguous in the sorted order) then take their
-// trilinear fine velocity from LDS when all eight fine nodes lie in the brick,
-// from global memory otherwise (a stencil that crosses the brick's faces).
-// The brick is 8R fine cells wide along x (one 128-byte line per row for r = 4
-// in FP32), so its loads are whole lines.
+// cells, one 256-thread workgroup per brick: four neighbouring threads share a
+// cell, one per fine child plane (z).  Each thread loads its plane's r x r rows
+// of u, v, w, p, keeps u, v, w in LDS and sums its plane (compensated); the
+// four plane sums are combined in order through cross-lane reads.  The brick's
+// particles (8 rows of up to 8 cells, contiguous in the sorted order, flattened
+// over the workgroup) take their trilinear fine velocity from LDS when all
+// eight fine nodes lie in the brick (from global memory when the stencil
+// crosses a brick face) and their void fraction from a haloed copy of phi in
+// LDS.  The brick is 8r fine cells wide along x (one 128-byte line per row for
+// r = 4 in FP32).
 constexpr int kBrickX = 8, kBrickY = 4, kBrickZ = 2;
+constexpr int kBrickThreads = 4 * kBrickX * kBrickY * kBrickZ;
 
 template <typename T, int R, bool KAHAN>
-__global__ __launch_bounds__(kWave) void k_restrict_brick(StepArgs<T> a) {
+__global__ __launch_bounds__(kBrickThreads) void k_restrict_brick(StepArgs<T> a) {
     constexpr int FX = kBrickX * R, FY = kBrickY * R, FZ = kBrickZ * R;
     constexpr int HX = kBrickX + 2, HY = kBrickY + 2, HZ = kBrickZ + 2;   // bulk cells with a one-cell halo
     constexpr int NROW = kBrickY * kBrickZ;
+    constexpr int NT = kBrickThreads;
+    static_assert(R <= 4, "one thread per fine child plane");
     __shared__ T sv[3][FZ][FY][FX];
     __shared__ T sphi[HZ][HY][HX];
-    __shared__ int32_t srow[NROW + 1];   // particle-segment prefix over the brick's rows
+    __shared__ int32_t srow[NROW + 1];    // particle-segment prefix over the brick's rows
     __shared__ int32_t sbeg[NROW];
     const Geo<T> &g = a.g;
     const int bnx = (g.nb[0] + kBrickX - 1) / kBrickX, bny = (g.nb[1] + kBrickY - 1) / kBrickY;
     const int64_t brick = xcd_tile(blockIdx.x, gridDim.x);
     const int ox = (int)(brick % bnx) * kBrickX, oy = (int)((brick / bnx) % bny) * kBrickY,
               oz = (int)(brick / ((int64_t)bnx * bny)) * kBrickZ;
-    const int lane = threadIdx.x;
-    const int lx = lane % kBrickX, ly = (lane / kBrickX) % kBrickY, lz = lane / (kBrickX * kBrickY);
+    const int tid = threadIdx.x, lane = tid % kWave;
+    const int cl = tid >> 2, rz = tid & 3;   // cell of the brick, fine child plane
+    const int lx = cl % kBrickX, ly = (cl / kBrickX) % kBrickY, lz = cl / (kBrickX * kBrickY);
     const int cx = ox + lx, cy = oy + ly, cz = oz + lz;
+    const bool inside = cx < g.nb[0] && cy < g.nb[1] && cz < g.nb[2];
     const int64_t nx = g.nb[0], nxy = (int64_t)g.nb[0] * g.nb[1];
     const int64_t nfx = g.nf[0], nfxy = (int64_t)g.nf[0] * g.nf[1];
     // the brick's particle rows and phi with its halo (indices clamped at the walls)
     const int wx = (ox + kBrickX < g.nb[0]) ? kBrickX : g.nb[0] - ox;
-    if (lane < NROW) {
-        const int ry = oy + lane % kBrickY, rz = oz + lane / kBrickY;
+    if (tid < NROW) {
+        const int ry = oy + tid % kBrickY, rzz = oz + tid / kBrickY;
         int32_t b0 = 0, cnt = 0;
-        if (ry < g.nb[1] && rz < g.nb[2]) {
-            const int64_t c0 = ox + nx * ry + nxy * rz;
+        if (ry < g.nb[1] && rzz < g.nb[2]) {
+            const int64_t c0 = ox + nx * ry + nxy * rzz;
             b0 = seg_clamp(a.start[c0], a.n);
             cnt = seg_clamp(a.start[c0 + wx], a.n) - b0;
         }
-        sbeg[lane] = b0;
-        srow[lane + 1] = cnt;
+        sbeg[tid] = b0;
+        srow[tid + 1] = cnt;
     }
-    for (int e = lane; e < HX * HY * HZ; e += kWave) {
+    for (int e = tid; e < HX * HY * HZ; e += NT) {
         const int hx = e % HX, hy = (e / HX) % HY, hz = e / (HX * HY);
         const int gx = clampi(ox - 1 + hx, g.nb[0]), gy = clampi(oy - 1 + hy, g.nb[1]), gz = clampi(oz - 1 + hz, g.nb[2]);
         sphi[hz][hy][hx] = a.phi[gx + nx * gy + nxy * gz];
     }
-    if (cx < g.nb[0] && cy < g.nb[1] && cz < g.nb[2]) {
-        const int64_t c = cx + nx * cy + nxy * cz;
-        const int64_t base = (int64_t)R * cz * nfxy + (int64_t)R * cy * nfx + (int64_t)R * cx;
-        const T inv = T(1) / T(R * R * R);
+    const bool work = inside && rz < R;
+    const int64_t base = ((int64_t)R * cz + rz) * nfxy + (int64_t)R * cy * nfx + (int64_t)R * cx;
+    const T inv = T(1) / T(R * R * R);
 #pragma unroll
-        for (int f = 0; f < 4; ++f) {
+    for (int f = 0; f < 4; ++f) {
+        Acc<T, KAHAN> plane;
+        if (work) {
             const T *__restrict__ q = a.fine[f] + base;
-            Row<T, R> rows[R][R];
+            Row<T, R> rows[R];
 #pragma unroll
-            for (int rz = 0; rz < R; ++rz)
+            for (int ry = 0; ry < R; ++ry) rows[ry] = load_row<T, R>(q + ry * nfx);
 #pragma unroll
-                for (int ry = 0; ry < R; ++ry) rows[rz][ry] = load_row<T, R>(q + rz * nfxy + ry * nfx);
-            Acc<T, KAHAN> acc;
+            for (int ry = 0; ry < R; ++ry)
 #pragma unroll
-            for (int rz = 0; rz < R; ++rz)
+                for (int rx = 0; rx < R; ++rx) plane.add(rows[ry].v[rx]);
+            if (f < 3) {
 #pragma unroll
                 for (int ry = 0; ry < R; ++ry)
 #pragma unroll
-                    for (int rx = 0; rx < R; ++rx) acc.add(rows[rz][ry].v[rx]);
+                    for (int rx = 0; rx < R; ++rx) sv[f][lz * R + rz][ly * R + ry][lx * R + rx] = rows[ry].v[rx];
+            }
+        }
+        // the planes of this cell in order (s_0, -c_0, s_1, ...), read from the
+        // cell's four lanes; the plane-0 lane writes the average
+        Acc<T, KAHAN> acc;
+        const int l0 = lane & ~3;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const T sk = __shfl(plane.s, l0 + k, kWave);
+            const T ck = __shfl(plane.c, l0 + k, kWave);
+            acc.add(sk);
+            if constexpr (KAHAN) acc.add(-ck);
+        }
+        if (inside && rz == 0) {
+            const int64_t c = cx + nx * cy + nxy * cz;
             const T val = acc.s * inv;   // 1/R^3 is a power of two: the scaling is exact
             if (f < 3) {
                 a.U[f * g.ncell + c] = val;
-#pragma unroll
-                for (int rz = 0; rz < R; ++rz)
-#pragma unroll
-                    for (int ry = 0; ry < R; ++ry)
-#pragma unroll
-                        for (int rx = 0; rx < R; ++rx) sv[f][lz * R + rz][ly * R + ry][lx * R + rx] = rows[rz][ry].v[rx];
             } else {
                 a.P[c] = val;
                 // the compensated sum is s - c: keep -c/R^3 so that the pressure
@@ -246,21 +270,21 @@ __global__ __launch_bounds__(kWave) void k_restrict_brick(StepArgs<T> a) {
         }
     }
     __syncthreads();
-    if (lane == 0) {
+    if (tid == 0) {
         srow[0] = 0;
         for (int r = 0; r < NROW; ++r) srow[r + 1] += srow[r];
     }
     __syncthreads();
     const int total = srow[NROW];
     const int fx0 = ox * R, fy0 = oy * R, fz0 = oz * R;
-    // up to kPB particles per lane at a time: their loads are issued together
-    constexpr int kPB = 4;
-    for (int j0 = lane; j0 < total; j0 += kPB * kWave) {
+    // up to kPB particles per thread at a time: their loads are issued together
+    constexpr int kPB = 2;
+    for (int j0 = tid; j0 < total; j0 += kPB * NT) {
         vec4<T> qs[kPB];
         int64_t ps[kPB];
 #pragma unroll
         for (int k = 0; k < kPB; ++k) {
-            const int j = j0 + k * kWave;
+            const int j = j0 + k * NT;
             int64_t i = sbeg[0];
             if (j < total) {
                 int r = 0;
@@ -272,7 +296,7 @@ __global__ __launch_bounds__(kWave) void k_restrict_brick(StepArgs<T> a) {
         }
 #pragma unroll
         for (int k = 0; k < kPB; ++k) {
-        if (j0 + k * kWave >= total) break;
+        if (j0 + k * NT >= total) break;
         const vec4<T> q = qs[k];
         int64_t p = ps[k];
         if (p < 0 || p >= a.n) p = 0;   // perm is a permutation of [0, n)
@@ -596,8 +620,8 @@ static void launch_grid_stages(const StepArgs<T> &a, hipStream_t st) {
     const int64_t pb = (a.n + kBlock - 1) / kBlock;
     if (a.vel_source == 0) {
         a.mk->mark("restrict_lookup", st);
-        hipLaunchKernelGGL((k_restrict_brick<T, R, KAHAN>), dim3((unsigned)brick_blocks<T, R>(a.g)), dim3(kWave), 0,
-                           st, a);
+        hipLaunchKernelGGL((k_restrict_brick<T, R, KAHAN>), dim3((unsigned)brick_blocks<T, R>(a.g)),
+                           dim3(kBrickThreads), 0, st, a);
     } else if (a.vel_source == 3) {
         if constexpr (std::is_same<T, float>::value) {
             a.mk->mark("restrict", st);
