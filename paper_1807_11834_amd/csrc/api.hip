@@ -231,8 +231,8 @@ static int step_impl(couple_handle *h, const couple_inputs *in, couple_outputs *
 
     (void)hipGetLastError();  // clear a stale error so that it is not reported as ours
     const uint32_t *skeys = nullptr;
-    hipError_t e = launch_bin_sort<T>(a.pos, a.n, a.g, out->cell, out->perm, out->start, out->count, h->sort,
-                                      h->part + SL_NOUT * h->part_stride, &skeys, &h->mk, st);
+    hipError_t e = launch_bin_sort<T>(a.pos, a.diam, a.n, a.g, out->cell, a.uf4, out->perm, out->start,
+                                      out->count, h->sort, h->part + SL_NOUT * h->part_stride, &skeys, &h->mk, st);
     if (e != hipSuccess) return fail(h, COUPLE_EHIP, std::string("couple_step: sort launch failed: ") + hipGetErrorString(e));
     a.keys = skeys;
     e = launch_stages<T>(a, st);

@@ -38,9 +38,9 @@ int sort_tiles(int64_t n);
 
 // Bin particles, sort (cell, id), and build start/count.
 template <typename T>
-hipError_t launch_bin_sort(const T *pos, int64_t n, const Geo<T> &g, int32_t *cell, int32_t *perm, int32_t *start,
-                           int32_t *count, const SortScratch &s, double *part_nout, const uint32_t **sorted_keys,
-                           Marker *mk, hipStream_t st);
+hipError_t launch_bin_sort(const T *pos, const T *diam, int64_t n, const Geo<T> &g, int32_t *cell, vec4<T> *pk,
+                           int32_t *perm, int32_t *start, int32_t *count, const SortScratch &s, double *part_nout,
+                           const uint32_t **sorted_keys, Marker *mk, hipStream_t st);
 
 // Device state of the learned surrogate as the step kernels read it.
 struct MlpNet {
@@ -74,7 +74,8 @@ template <typename T> struct StepArgs {
     double *diag;
     // scratch
     vec4<T> *sp;     // sorted particles (x, y, z, d)
-    vec4<T> *uf4;    // per particle (input order): fluid velocity and void fraction
+    vec4<T> *uf4;    // per particle (input order): packed (x, y, z, d) from binning until the
+                     // gather has read it, then fluid velocity and void fraction
     T *Plo;          // [ncell] low word of the restricted pressure (Kahan compensation)
     T *dep_partial;  // [9][3][ncell] per-source-row partial sums of the CIC deposition
     double *part;    // [SL_COUNT][max_blocks]

@@ -4,8 +4,10 @@
 // The particle -> cell connectivity changes with every coupling step because
 // the particles move (Sec. 2.2); it is rebuilt here from scratch each step:
 //
-//   k_bin          containing cell per particle (output `cell`) and the digit
-//                  histogram of the first radix pass, per tile;
+//   k_bin          containing cell per particle (output `cell`), the packed
+//                  input-order copy pk = (x, y, z, d) with the position clamped
+//                  into the box, and the digit histogram of the first radix
+//                  pass, per tile;
 //   k_radix_hist   digit histogram per tile for later passes;
 //   k_radix_prefix exclusive prefix over tiles of every digit, digit totals;
 //   k_radix_scatter stable ranking inside a tile (wave ballots, LDS staging) and
@@ -27,8 +29,9 @@ constexpr int kWaveSpan = kWave * kItems;          // keys handled by one wave
 constexpr int kMaxDigits = 256;                    // radix <= 8 bits per pass
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_bin(const T *__restrict__ pos, int64_t n, Geo<T> g,
-                                                int32_t *__restrict__ cell, uint32_t *__restrict__ hist,
+__global__ __launch_bounds__(kBlock) void k_bin(const T *__restrict__ pos, const T *__restrict__ diam, int64_t n,
+                                                Geo<T> g, int32_t *__restrict__ cell, vec4<T> *__restrict__ pk,
+                                                uint32_t *__restrict__ hist,
                                                 int ntile, int bits0, double *__restrict__ part_nout) {
     __shared__ uint32_t h[kMaxDigits];
     __shared__ double red[kWavesPerBlock];
@@ -49,6 +52,12 @@ __global__ __launch_bounds__(kBlock) void k_bin(const T *__restrict__ pos, int64
             int iz = cell_axis(z, g.sb[2], g.nb[2]);
             int32_t c = ix + g.nb[0] * (iy + g.nb[1] * iz);
             cell[p] = c;
+            vec4<T> q;
+            q.x = x;
+            q.y = y;
+            q.z = z;
+            q.w = diam[p];
+            pk[p] = q;
             atomicAdd(&h[(uint32_t)c & (ndig - 1)], 1u);
             nout += outside;
         }
@@ -292,16 +301,16 @@ void sort_plan(int64_t ncell, int *npass, int widths[4]) {
 }
 
 template <typename T>
-hipError_t launch_bin_sort(const T *pos, int64_t n, const Geo<T> &g, int32_t *cell, int32_t *perm, int32_t *start,
-                           int32_t *count, const SortScratch &s, double *part_nout,
+hipError_t launch_bin_sort(const T *pos, const T *diam, int64_t n, const Geo<T> &g, int32_t *cell, vec4<T> *pk,
+                           int32_t *perm, int32_t *start, int32_t *count, const SortScratch &s, double *part_nout,
                            const uint32_t **sorted_keys, Marker *mk, hipStream_t st) {
     int npass, widths[4];
     sort_plan(g.ncell, &npass, widths);
     const int ntile = sort_tiles(n);
     if (n > 0) {
         mk->mark("bin", st);
-        hipLaunchKernelGGL(k_bin<T>, dim3(ntile), dim3(kBlock), 0, st, pos, n, g, cell, s.hist, ntile, widths[0],
-                           part_nout);
+        hipLaunchKernelGGL(k_bin<T>, dim3(ntile), dim3(kBlock), 0, st, pos, diam, n, g, cell, pk, s.hist, ntile,
+                           widths[0], part_nout);
         int shift = 0;
         const uint32_t *kin = (const uint32_t *)cell;
         const uint32_t *vin = nullptr;
@@ -336,11 +345,11 @@ hipError_t launch_bin_sort(const T *pos, int64_t n, const Geo<T> &g, int32_t *ce
     return hipGetLastError();
 }
 
-template hipError_t launch_bin_sort<float>(const float *, int64_t, const Geo<float> &, int32_t *, int32_t *,
-                                           int32_t *, int32_t *, const SortScratch &, double *, const uint32_t **,
-                                           Marker *, hipStream_t);
-template hipError_t launch_bin_sort<double>(const double *, int64_t, const Geo<double> &, int32_t *, int32_t *,
-                                            int32_t *, int32_t *, const SortScratch &, double *, const uint32_t **,
-                                            Marker *, hipStream_t);
+template hipError_t launch_bin_sort<float>(const float *, const float *, int64_t, const Geo<float> &, int32_t *,
+                                           vec4<float> *, int32_t *, int32_t *, int32_t *, const SortScratch &,
+                                           double *, const uint32_t **, Marker *, hipStream_t);
+template hipError_t launch_bin_sort<double>(const double *, const double *, int64_t, const Geo<double> &, int32_t *,
+                                            vec4<double> *, int32_t *, int32_t *, int32_t *, const SortScratch &,
+                                            double *, const uint32_t **, Marker *, hipStream_t);
 
 }  // namespace cpl

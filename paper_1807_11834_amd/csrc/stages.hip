@@ -3,8 +3,9 @@
 //
 // Kernel order on the caller's stream (after binning/sorting, sort.hip):
 //
-//   k_gather       sorted copy sp = (x, y, z, d) of the particles, clamped into
-//                  the box.
+//   k_gather       sorted copy sp = (x, y, z, d) of the particles: the packed
+//                  input-order copy that binning wrote (clamped into the box),
+//                  permuted, one 16-byte (FP32) read per particle.
 //   deposit phi    (deposit.hip)
 //   k_restrict     one thread per bulk cell streams its r^3 fine children of
 //                  u, v, w, p (one 16-byte row load per (z, y) child row for
@@ -74,20 +75,13 @@ template <typename T, int R> __device__ __forceinline__ void store_row(T *__rest
 // k_gather: sorted particle copies
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_gather(const int32_t *__restrict__ perm, const T *__restrict__ pos,
-                                                   const T *__restrict__ diam, int64_t n, Geo<T> g,
-                                                   vec4<T> *__restrict__ sp) {
+__global__ __launch_bounds__(kBlock) void k_gather(const int32_t *__restrict__ perm, const vec4<T> *__restrict__ pk,
+                                                   int64_t n, vec4<T> *__restrict__ sp) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i < n) {
         int64_t p = perm[i];
-        if (p < 0 || p >= n) p = 0;   // perm is a permutation of [0, n); guards the loads
-        int o = 0;
-        vec4<T> q;
-        q.x = clamp_coord(pos[3 * p + 0], g.L[0], o);
-        q.y = clamp_coord(pos[3 * p + 1], g.L[1], o);
-        q.z = clamp_coord(pos[3 * p + 2], g.L[2], o);
-        q.w = diam[p];
-        sp[i] = q;
+        if (p < 0 || p >= n) p = 0;   // perm is a permutation of [0, n); guards the load
+        sp[i] = pk[p];
     }
 }
 
@@ -694,7 +688,7 @@ template <typename T> hipError_t launch_stages(const StepArgs<T> &a, hipStream_t
 
     if (a.n > 0) a.mk->mark("gather", st);
     if (a.n > 0)
-        hipLaunchKernelGGL(k_gather<T>, dim3(pb), dim3(kBlock), 0, st, a.perm, a.pos, a.diam, a.n, a.g, a.sp);
+        hipLaunchKernelGGL(k_gather<T>, dim3(pb), dim3(kBlock), 0, st, a.perm, a.uf4, a.n, a.sp);
     a.mk->mark("deposit_phi", st);
     if (kahan) launch_deposit_phi<T, true>(a, st);
     else launch_deposit_phi<T, false>(a, st);
