@@ -10,8 +10,8 @@ The per-stage definitions live in ``couple_oracle.c`` (plain C, FP64), built int
 stages in the order of one coupling step (Fig. 1, Sec. 2.1-2.2):
 
     bin -> volume deposition -> restriction (+ pressure gradient) -> fluid value
-    at particles -> drag -> momentum-source deposition -> prolongation ->
-    conservation sums (-> explicit Euler advection)
+    at particles -> drag -> momentum-source deposition (+ optional semi-implicit
+    split K, KU) -> prolongation -> conservation sums (-> explicit Euler advection)
 
 The learned surrogate's oracle is in :mod:`oracle.mlp`.
 
@@ -61,6 +61,7 @@ def lib():
         L.orc_weights.restype = I
         L.orc_deposit_volume.argtypes = [I64, P, P, P, P, P, I, I, P]
         L.orc_deposit_force.argtypes = [I64, P, P, P, P, P, I, I, P]
+        L.orc_deposit_semi.argtypes = [I64, P, P, P, P, P, P, I, I, P, P]
         L.orc_gather_eps.argtypes = [I64, P, P, P, P, I, I, P]
         L.orc_restrict.argtypes = [P, P, I, P]
         L.orc_gradient.argtypes = [P, P, P, P]
@@ -71,7 +72,7 @@ def lib():
         L.orc_prolong_at.argtypes = [P, P, I, I, I64, P, P]
         L.orc_advect.argtypes = [I64, P, P, P, P, D, D, P, I]
         L.orc_particle_volumes.argtypes = [I64, P, P]
-        for name in ("orc_deposit_volume", "orc_deposit_force", "orc_gather_eps", "orc_restrict",
+        for name in ("orc_deposit_volume", "orc_deposit_force", "orc_deposit_semi", "orc_gather_eps", "orc_restrict",
                      "orc_gradient", "orc_interp", "orc_prolong", "orc_prolong_at", "orc_advect",
                      "orc_particle_volumes"):
             getattr(L, name).restype = None
@@ -138,6 +139,18 @@ def deposit_force(pos, force, perm, box, nb, cic, prec32=False):
                             _p(np.ascontiguousarray(perm, np.int32)), _p(_f64(box)), _p(_i32x3(nb)),
                             int(cic), int(prec32), _p(fc))
     return fc.reshape(3, -1)
+
+
+def deposit_semi(pos, beta, vel, perm, box, nb, cic, prec32=False):
+    """Semi-implicit source fields: (K [ncell], KU [3, ncell])."""
+    pos = _f64(pos).reshape(-1, 3)
+    nc = int(np.prod(nb))
+    K = np.empty(nc, dtype=np.float64)
+    KU = np.empty(3 * nc, dtype=np.float64)
+    lib().orc_deposit_semi(pos.shape[0], _p(pos), _p(_f64(beta)), _p(_f64(vel).reshape(-1, 3)),
+                           _p(np.ascontiguousarray(perm, np.int32)), _p(_f64(box)), _p(_i32x3(nb)),
+                           int(cic), int(prec32), _p(K), _p(KU))
+    return K, KU.reshape(3, -1)
 
 
 def gather_eps(pos, phi, box, nb, cic, prec32=False):
@@ -230,7 +243,7 @@ def restrict_all(fine, grid):
 
 def step(pos, vel, diam, fine, grid, rho_f=1000.0, mu_f=1e-3, rho_p=2500.0, eps_min=0.3,
          cic=True, prec32=True, vel_source="fine", advect_dt=None, fine_out="full",
-         fine_sample=None, bulk_velocity=None, restricted=None):
+         fine_sample=None, bulk_velocity=None, restricted=None, semi_implicit=False):
     """One coupling step in FP64.
 
     ``fine`` is (u, v, w, p), each (nfz, nfy, nfx).  ``vel_source`` is "fine"
@@ -239,7 +252,8 @@ def step(pos, vel, diam, fine, grid, rho_f=1000.0, mu_f=1e-3, rho_p=2500.0, eps_
     the particles, e.g. a surrogate's prediction).  ``fine_out`` is "full" (all
     fine cells), "sample" (only the flat indices ``fine_sample``) or "none".
     ``restricted`` reuses the output of :func:`restrict_all` for the same fine
-    fields (the restriction does not depend on the particles).
+    fields (the restriction does not depend on the particles).  ``semi_implicit``
+    adds the semi-implicit source fields K, KU (bulk and prolonged) and their sums.
     Returns a dict of numpy arrays and the diagnostics.
     """
     box = tuple(float(b) for b in grid.box)
@@ -288,6 +302,19 @@ def step(pos, vel, diam, fine, grid, rho_f=1000.0, mu_f=1e-3, rho_p=2500.0, eps_
     elif fine_out == "sample":
         fo = [prolong_at(B, nb, r, fine_sample, True) for B in fields]
         out["fine_eps"], out["fine_F"] = fo[0], np.stack(fo[1:])
+    if semi_implicit:
+        K, KU = deposit_semi(pos, beta, vel, perm, box, nb, cic, prec32)
+        out["K"], out["KU"] = K, KU
+        # (1/V_b) sum_p w_pc beta_p |u_p|: the scale of the summation error of KU
+        out["KU_mag"] = deposit_semi(pos, beta * np.sqrt((vel ** 2).sum(axis=1)), np.ones_like(vel), perm,
+                                     box, nb, cic, prec32)[1][0]
+        sf = [K, KU[0], KU[1], KU[2]]
+        if fine_out == "full":
+            fo = [prolong(B, nb, r, True) for B in sf]
+            out["fine_K"], out["fine_KU"] = fo[0], np.stack(fo[1:])
+        elif fine_out == "sample":
+            fo = [prolong_at(B, nb, r, fine_sample, True) for B in sf]
+            out["fine_K"], out["fine_KU"] = fo[0], np.stack(fo[1:])
     vp = particle_volumes(diam)
     diag = {
         "V_tot": fsum_axis(vp),
@@ -301,6 +328,14 @@ def step(pos, vel, diam, fine, grid, rho_f=1000.0, mu_f=1e-3, rho_p=2500.0, eps_
     if fine_out == "full":
         diag["S_f"] = [fsum_axis(out["fine_F"][a]) * vf for a in range(3)]
         diag["E_f"] = fsum_axis(out["fine_eps"]) * vf
+    if semi_implicit:
+        diag["K_p"] = fsum_axis(beta)
+        diag["KU_p"] = [fsum_axis(beta * vel[:, a]) for a in range(3)]
+        diag["K_b"] = fsum_axis(out["K"]) * vb
+        diag["KU_b"] = [fsum_axis(out["KU"][a]) * vb for a in range(3)]
+        if fine_out == "full":
+            diag["K_f"] = fsum_axis(out["fine_K"]) * vf
+            diag["KU_f"] = [fsum_axis(out["fine_KU"][a]) * vf for a in range(3)]
     out["diag"] = diag
     if advect_dt is not None:
         out["pos_new"], out["vel_new"] = advect(pos, vel, diam, force, rho_p, advect_dt, box, prec32)

@@ -19,6 +19,8 @@
  *                values", Sec. 1)
  *   drag         F = beta (u_f - u_p), Eq. DragLaw (Sec. 2.4), beta by the
  *                Di Felice voidage correlation
+ *   semi         deposited drag coefficient and beta-weighted particle velocity,
+ *                the semi-implicit form of the momentum source (Sec. 2.5)
  *   prolong      bulk -> fine "particle related fields" transfer (Fig. 1)
  *   advect       explicit Euler update of Eq. DEM_EQUATIONS with drag only
  *
@@ -233,6 +235,34 @@ void orc_deposit_force(int64_t n, const double *pos, const double *force, const 
         int m = weights(x, box, nb, cic, prec32, cells, w);
         for (int k = 0; k < m; ++k)
             for (int a = 0; a < 3; ++a) fc[a * nc + cells[k]] -= w[k] * force[3 * p + a] / vb;
+    }
+}
+
+/* Semi-implicit split of the momentum source (the drag counterpart of Eq. UFP
+ * is treated semi-implicitly in the fluid solve, Sec. 2.5).  With
+ * F_p = beta_p (u_f - u_p) the source is -K_c u_f + KU_c wherever the fluid
+ * velocity is uniform over the deposition stencil, where
+ *   K_c  = (1/V_b) sum_p w_pc beta_p          (implicit coefficient, [ncell])
+ *   KU_c = (1/V_b) sum_p w_pc beta_p u_p      (explicit part, [3][ncell]).
+ * Same weights and canonical (cell, id) order as the other depositions. */
+void orc_deposit_semi(int64_t n, const double *pos, const double *beta, const double *vel, const int32_t *perm,
+                      const double box[3], const int nb[3], int cic, int prec32, double *K, double *KU)
+{
+    int64_t nc = (int64_t)nb[0] * nb[1] * nb[2];
+    double vb = (box[0] / nb[0]) * (box[1] / nb[1]) * (box[2] / nb[2]);
+    for (int64_t c = 0; c < nc; ++c) K[c] = 0.0;
+    for (int64_t c = 0; c < 3 * nc; ++c) KU[c] = 0.0;
+    for (int64_t q = 0; q < n; ++q) {
+        int64_t p = perm[q];
+        double x[3];
+        if (prec32) clamp_pos32(pos + 3 * p, box, x); else clamp_pos(pos + 3 * p, box, x);
+        int64_t cells[8];
+        double w[8];
+        int m = weights(x, box, nb, cic, prec32, cells, w);
+        for (int k = 0; k < m; ++k) {
+            K[cells[k]] += w[k] * beta[p] / vb;
+            for (int a = 0; a < 3; ++a) KU[a * nc + cells[k]] += w[k] * beta[p] * vel[3 * p + a] / vb;
+        }
     }
 }
 
