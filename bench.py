@@ -38,12 +38,13 @@ def kernel_alg_bytes(name, n, ncell, nfine, fsz):
     restrict: the same without the particles.
     prolong: eps and F_fpi written on the fine grid (4 fsz per fine cell); phi
         and F_fpi read on the bulk grid (4 fsz per bulk cell).
+    prolong_semi: the same for K and KU (semi-implicit split).
     """
     if name == "restrict_lookup":
         return 4 * fsz * nfine + 4 * fsz * ncell + n * 8 * fsz
     if name == "restrict":
         return 4 * fsz * nfine + 4 * fsz * ncell
-    if name == "prolong":
+    if name in ("prolong", "prolong_semi"):
         return 4 * fsz * nfine + 4 * fsz * ncell
     return None
 
@@ -319,6 +320,47 @@ def mlp_leg(args, w, cfg, pos, vel, diam, fine, plain_ms, plain_kernels, dev):
     }
 
 
+def semi_leg(args, cfg, pos, vel, diam, fine, plain_ms, n, g, fsz, dev):
+    """The same step with the semi-implicit split on (K, KU deposited and
+    prolonged in addition): time per step, the extra kernels and the prolongation
+    roofline of K, KU, and the conservation of their sums."""
+    import torch
+    import paper_1807_11834_amd as cpl
+    cfg_s = dataclasses.replace(cfg, semi_implicit=1)
+    c = cpl.Coupler(cfg_s)
+    out = cpl.alloc_outputs(cfg_s, n, device=dev)
+    try:
+        for _ in range(args.warmup):
+            c.step(pos, vel, diam, fine, out=out)
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        cpl.couple_timing_begin(c.h, args.steps)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            c.step(pos, vel, diam, fine, out=out)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        stats = cpl.couple_timing_end(c.h)
+        ms = e0.elapsed_time(e1) / args.steps
+        d = cpl.diag_dict(out["diag"])
+    finally:
+        c.close()
+    kern = {k: t / l for k, (l, t) in stats.items() if l and k in ("deposit_semi", "deposit_semi_sum", "prolong_semi")}
+    ab = kernel_alg_bytes("prolong_semi", n, g.n_bulk, g.n_fine, fsz)
+    pr = kern.get("prolong_semi")
+    del out
+    torch.cuda.empty_cache()
+    print(f"# semi-implicit split: {ms:.3f} ms/step", file=sys.stderr, flush=True)
+    return {"ms_per_step": ms, "value": n / (ms * 1e-3), "extra_ms_vs_plain": ms - plain_ms,
+            "kernels_avg_ms": {k: round(v, 4) for k, v in kern.items()},
+            "prolong_semi_GBps": round(ab / (pr * 1e-3) / 1e9, 1) if pr else None,
+            "prolong_semi_frac_hbm": round(ab / (pr * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4) if pr else None,
+            "conservation": {"K_b/K_p-1": d["K_b"] / d["K_p"] - 1 if d["K_p"] else 0.0,
+                             "K_f/K_b-1": d["K_f"] / d["K_b"] - 1 if d["K_b"] else 0.0}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -331,6 +373,7 @@ def main():
     ap.add_argument("--vel-source", default="fine", choices=["fine", "bulk"],
                     help="fluid velocity at the particles: fine-grid lookup (default) or bulk trilinear")
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned-surrogate path")
+    ap.add_argument("--no-semi", action="store_true", help="skip the semi-implicit split variant")
     ap.add_argument("--traffic-summary", metavar="DIR",
                     help="print the JSON summary of the FETCH_SIZE/WRITE_SIZE runs under DIR and exit")
     ap.add_argument("--trace-summary", metavar="CSV",
@@ -452,6 +495,8 @@ def main():
         rec["presorted_input"] = {"ms_per_step": ms_s, "value": n / (ms_s * 1e-3),
                                   "note": "same particles passed in the canonical (cell, id) order"}
         del pos_s, vel_s, diam_s
+    if not args.no_semi:
+        rec["semi_implicit"] = semi_leg(args, cfg, pos, vel, diam, fine, ms_step, n, g, fsz, dev)
     if not args.no_mlp:
         print("# surrogate: pairs, training, timing ...", file=sys.stderr, flush=True)
         rec["mlp_path"] = mlp_leg(args, w, cfg, pos, vel, diam, fine, ms_step, kernels, dev)

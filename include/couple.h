@@ -19,9 +19,16 @@
  *   5. drag     F_p = beta (u_f - u_p), Eq. DragLaw of Sec. 2.4, with beta from
  *               the Di Felice voidage correlation;
  *   6. source   momentum source F_fpi,c = -(1/V_b) sum_p w_pc F_p, the counterpart
- *               of the drag in Eq. UFP (Sec. 2.5);
- *   7. prolong  eps and F_fpi transferred to the fine grid ("particle related
- *               fields" arrow of Fig. 1) by a conservative trilinear prolongation;
+ *               of the drag in Eq. UFP (Sec. 2.5); with semi_implicit = 1 also its
+ *               semi-implicit split (the drag term of Eq. UFP is treated
+ *               semi-implicitly in the fluid solve, Sec. 2.5):
+ *                 K_c  = (1/V_b) sum_p w_pc beta_p        implicit coefficient,
+ *                 KU_c = (1/V_b) sum_p w_pc beta_p u_p    explicit part,
+ *               so that F_fpi = -K u_f + KU wherever u_f is uniform over the
+ *               deposition stencil (u_p: the velocity before advection);
+ *   7. prolong  eps and F_fpi (and K, KU) transferred to the fine grid ("particle
+ *               related fields" arrow of Fig. 1) by a conservative trilinear
+ *               prolongation;
  *   8. sums     FP64 conservation diagnostics;
  *   9. advect   optional explicit Euler step of Eq. DEM_EQUATIONS with the drag
  *               as the only force.
@@ -90,7 +97,13 @@ enum {
     COUPLE_DIAG_MLP_ERR2 = 16,  /* VEL_MLP: sum over the checked sample of |u_mlp - u_fine|^2 */
     COUPLE_DIAG_MLP_REF2 = 17,  /* VEL_MLP: sum over the checked sample of |u_fine|^2         */
     COUPLE_DIAG_MLP_NSAMP = 18, /* VEL_MLP: particles in the checked sample                   */
-    COUPLE_DIAG_LEN = 19
+    COUPLE_DIAG_K_P = 19,       /* semi_implicit: sum_p beta_p                                */
+    COUPLE_DIAG_KU_P = 20,      /* [20..22] semi_implicit: sum_p beta_p u_p                   */
+    COUPLE_DIAG_K_B = 23,       /* sum_c K_c V_b (equals K_P)                                 */
+    COUPLE_DIAG_KU_B = 24,      /* [24..26] sum_c KU_c V_b (equals KU_P)                      */
+    COUPLE_DIAG_K_F = 27,       /* sum_f K_f V_f on the fine grid (equals K_B)                */
+    COUPLE_DIAG_KU_F = 28,      /* [28..30] sum_f KU_f V_f (equals KU_B)                      */
+    COUPLE_DIAG_LEN = 31
 };
 
 typedef struct couple_config {
@@ -115,7 +128,7 @@ typedef struct couple_config {
     double  mlp_tol;         /* VEL_MLP: relative L2 error of a brick's checked sample above
                                 which the brick takes the fine lookup (>= 0)                  */
     int32_t mlp_period;      /* VEL_MLP: one particle in mlp_period is checked (>= 1)          */
-    int32_t reserved;        /* must be 0                                                     */
+    int32_t semi_implicit;   /* 1: also deposit and prolong K and KU (step 6); 0 or 1          */
 } couple_config;
 
 typedef struct couple_inputs {
@@ -147,16 +160,22 @@ typedef struct couple_outputs {
     void    *fine_F;         /* [3][Nf] momentum source prolonged to the fine grid            */
     double  *diag;           /* [COUPLE_DIAG_LEN] FP64 diagnostics (device memory)            */
     void    *uf;             /* [n][3] fluid velocity used by the drag, or NULL if not wanted */
+    void    *bulk_K;         /* [Nb] semi-implicit drag coefficient K (semi_implicit only)    */
+    void    *bulk_KU;        /* [3][Nb] semi-implicit explicit part KU (semi_implicit only)   */
+    void    *fine_K;         /* [Nf] K prolonged to the fine grid (semi_implicit only)        */
+    void    *fine_KU;        /* [3][Nf] KU prolonged to the fine grid (semi_implicit only)    */
 } couple_outputs;
 
 /* Validate the configuration and allocate the scratch (about 48 * max_particles
  * bytes plus a few bytes per bulk cell; 32 more bytes per bulk cell for
- * VEL_MLP).  On success *out receives a handle. */
+ * VEL_MLP, 9 more values per bulk cell for semi_implicit with CIC).  On success
+ * *out receives a handle. */
 int couple_init(const couple_config *cfg, couple_handle **out);
 
 /* Enqueue one coupling step (stages 1-9 above) on `stream`.  Every pointer of
  * `in` and `out` except out->beta and out->uf (and in->uf_given unless
- * VEL_GIVEN) must be non-NULL when n > 0; the grid outputs are always required.
+ * VEL_GIVEN) must be non-NULL when n > 0; the grid outputs are always required,
+ * the four K/KU outputs when semi_implicit = 1 (ignored otherwise).
  * VEL_MLP without an attached network is COUPLE_ESTATE. */
 int couple_step(couple_handle *h, const couple_inputs *in, couple_outputs *out, void *stream);
 

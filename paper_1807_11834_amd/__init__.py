@@ -36,8 +36,9 @@ COUPLE_NGP, COUPLE_CIC = 0, 1
 COUPLE_FP64, COUPLE_FP32_KAHAN, COUPLE_FP32_NAIVE = 0, 1, 2
 COUPLE_VEL_FINE, COUPLE_VEL_BULK, COUPLE_VEL_GIVEN, COUPLE_VEL_MLP = 0, 1, 2, 3
 DIAG = {"V_tot": 0, "V_dep": 1, "sum_Fp": 2, "S_b": 5, "S_f": 8, "E_f": 11, "n_clamped": 12,
-        "n_outside": 13, "max_phi": 14, "n_fallback": 15, "mlp_err2": 16, "mlp_ref2": 17, "mlp_nsamp": 18}
-DIAG_LEN = 19
+        "n_outside": 13, "max_phi": 14, "n_fallback": 15, "mlp_err2": 16, "mlp_ref2": 17, "mlp_nsamp": 18,
+        "K_p": 19, "KU_p": 20, "K_b": 23, "KU_b": 24, "K_f": 27, "KU_f": 28}
+DIAG_LEN = 31
 MLP_NFEAT = 193
 MLP_NPARAM = 58243
 
@@ -54,7 +55,7 @@ class _Config(C.Structure):
                 ("phi_fp64", C.c_double), ("deposit", C.c_int32), ("precision", C.c_int32),
                 ("vel_source", C.c_int32), ("advect", C.c_int32), ("dt", C.c_double),
                 ("max_particles", C.c_int64), ("mlp_tol", C.c_double), ("mlp_period", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("semi_implicit", C.c_int32)]
 
 
 class _Inputs(C.Structure):
@@ -67,7 +68,8 @@ class _Outputs(C.Structure):
     _fields_ = [("drag", C.c_void_p), ("beta", C.c_void_p), ("cell", C.c_void_p), ("perm", C.c_void_p),
                 ("count", C.c_void_p), ("start", C.c_void_p), ("bulk_phi", C.c_void_p), ("bulk_F", C.c_void_p),
                 ("bulk_U", C.c_void_p), ("bulk_P", C.c_void_p), ("bulk_G", C.c_void_p),
-                ("fine_eps", C.c_void_p), ("fine_F", C.c_void_p), ("diag", C.c_void_p), ("uf", C.c_void_p)]
+                ("fine_eps", C.c_void_p), ("fine_F", C.c_void_p), ("diag", C.c_void_p), ("uf", C.c_void_p),
+                ("bulk_K", C.c_void_p), ("bulk_KU", C.c_void_p), ("fine_K", C.c_void_p), ("fine_KU", C.c_void_p)]
 
 
 class _MlpConfig(C.Structure):
@@ -143,6 +145,7 @@ class Config:
     max_particles: int = 0
     mlp_tol: float = 1.0e-3
     mlp_period: int = 100
+    semi_implicit: int = 0
 
     def to_c(self):
         c = _Config()
@@ -153,7 +156,8 @@ class Config:
         c.eps_min, c.phi_fp64 = float(self.eps_min), float(self.phi_fp64)
         c.deposit, c.precision, c.vel_source = int(self.deposit), int(self.precision), int(self.vel_source)
         c.advect, c.dt, c.max_particles = int(self.advect), float(self.dt), int(self.max_particles)
-        c.mlp_tol, c.mlp_period, c.reserved = float(self.mlp_tol), int(self.mlp_period), 0
+        c.mlp_tol, c.mlp_period = float(self.mlp_tol), int(self.mlp_period)
+        c.semi_implicit = int(self.semi_implicit)
         return c
 
     @property
@@ -238,10 +242,12 @@ def couple_timing_end(h):
 
 def alloc_outputs(cfg: Config, n: int, device="cuda", beta=True, uf=False):
     """Device tensors for every output of a step with ``n`` particles (``uf``:
-    also the fluid velocity used by the drag)."""
+    also the fluid velocity used by the drag; the K/KU fields when the
+    configuration asks for the semi-implicit split)."""
     dt = cfg.dtype
     nb, nf = cfg.nb, cfg.nf
     e = dict(device=device)
+    semi = bool(cfg.semi_implicit)
     return {
         "drag": torch.empty((n, 3), dtype=dt, **e),
         "beta": torch.empty((n,), dtype=dt, **e) if beta else None,
@@ -258,6 +264,10 @@ def alloc_outputs(cfg: Config, n: int, device="cuda", beta=True, uf=False):
         "fine_F": torch.empty((3, nf[2], nf[1], nf[0]), dtype=dt, **e),
         "diag": torch.empty((DIAG_LEN,), dtype=torch.float64, **e),
         "uf": torch.empty((n, 3), dtype=dt, **e) if uf else None,
+        "bulk_K": torch.empty((nb[2], nb[1], nb[0]), dtype=dt, **e) if semi else None,
+        "bulk_KU": torch.empty((3, nb[2], nb[1], nb[0]), dtype=dt, **e) if semi else None,
+        "fine_K": torch.empty((nf[2], nf[1], nf[0]), dtype=dt, **e) if semi else None,
+        "fine_KU": torch.empty((3, nf[2], nf[1], nf[0]), dtype=dt, **e) if semi else None,
     }
 
 
@@ -265,7 +275,8 @@ def diag_dict(diag_tensor):
     d = diag_tensor.detach().cpu().tolist()
     return {"V_tot": d[0], "V_dep": d[1], "sum_Fp": d[2:5], "S_b": d[5:8], "S_f": d[8:11], "E_f": d[11],
             "n_clamped": d[12], "n_outside": d[13], "max_phi": d[14], "n_fallback": d[15],
-            "mlp_err2": d[16], "mlp_ref2": d[17], "mlp_nsamp": d[18]}
+            "mlp_err2": d[16], "mlp_ref2": d[17], "mlp_nsamp": d[18], "K_p": d[19], "KU_p": d[20:23],
+            "K_b": d[23], "KU_b": d[24:27], "K_f": d[27], "KU_f": d[28:31]}
 
 
 class Coupler:

@@ -84,7 +84,7 @@ static std::string validate(const couple_config *c) {
         if (!(std::isfinite(c->mlp_tol) && c->mlp_tol >= 0.0)) return "mlp_tol must be finite and >= 0";
         if (c->mlp_period < 1) return "mlp_period must be >= 1";
     }
-    if (c->reserved != 0) return "reserved must be 0";
+    if (!(c->semi_implicit == 0 || c->semi_implicit == 1)) return "semi_implicit must be 0 or 1";
     if (!(c->advect == 0 || c->advect == 1)) return "advect must be 0 or 1";
     if (c->advect && !(std::isfinite(c->dt) && c->dt >= 0.0)) return "dt must be finite and >= 0";
     if (c->max_particles < 0 || c->max_particles >= (int64_t(1) << 31) - 1)
@@ -130,7 +130,7 @@ extern "C" int couple_init(const couple_config *cfg, couple_handle **out) {
               dev_alloc(&h->sort.hist, sizeof(uint32_t) * 256 * ntile) && dev_alloc(&h->sort.totals, sizeof(uint32_t) * 256) &&
               dev_alloc(&h->sp, 4 * fsz * nmax) && dev_alloc(&h->uf4, 4 * fsz * nmax) &&
               dev_alloc(&h->plo, fsz * h->ncell) &&
-              dev_alloc(&h->dep, (cfg->deposit == COUPLE_CIC ? 27 : 1) * fsz * h->ncell) &&
+              dev_alloc(&h->dep, (cfg->deposit == COUPLE_CIC ? (cfg->semi_implicit ? 36 : 27) : 1) * fsz * h->ncell) &&
               dev_alloc(&h->part, sizeof(double) * (SL_COUNT * h->part_stride + SL_COUNT * 64)) &&
               (cfg->vel_source != COUPLE_VEL_MLP || dev_alloc(&h->fgrid, sizeof(float4) * 2 * h->ncell));
     if (!ok) {
@@ -182,6 +182,7 @@ static int step_impl(couple_handle *h, const couple_inputs *in, couple_outputs *
     a.kahan = c.precision == COUPLE_FP32_KAHAN;
     a.vel_source = c.vel_source;
     a.advect = c.advect;
+    a.semi = c.semi_implicit;
     a.dt = (T)c.dt;
     a.rho_f = (T)c.rho_f;
     a.mu_f = (T)c.mu_f;
@@ -207,6 +208,10 @@ static int step_impl(couple_handle *h, const couple_inputs *in, couple_outputs *
     a.G = (T *)out->bulk_G;
     a.fine_eps = (T *)out->fine_eps;
     a.fine_F = (T *)out->fine_F;
+    a.K = (T *)out->bulk_K;
+    a.KU = (T *)out->bulk_KU;
+    a.fine_K = (T *)out->fine_K;
+    a.fine_KU = (T *)out->fine_KU;
     a.diag = out->diag;
     a.sp = (vec4<T> *)h->sp;
     a.uf4 = (vec4<T> *)h->uf4;
@@ -251,6 +256,8 @@ extern "C" int couple_step(couple_handle *h, const couple_inputs *in, couple_out
     if (!out->count || !out->start || !out->bulk_phi || !out->bulk_F || !out->bulk_U || !out->bulk_P ||
         !out->bulk_G || !out->fine_eps || !out->fine_F || !out->diag)
         return fail(h, COUPLE_EINVAL, "couple_step: NULL grid output");
+    if (c.semi_implicit && (!out->bulk_K || !out->bulk_KU || !out->fine_K || !out->fine_KU))
+        return fail(h, COUPLE_EINVAL, "couple_step: semi_implicit needs bulk_K, bulk_KU, fine_K and fine_KU");
     if (in->n > 0) {
         if (!in->pos || !in->vel || !in->diam) return fail(h, COUPLE_EINVAL, "couple_step: NULL particle input");
         if (!out->drag || !out->cell || !out->perm) return fail(h, COUPLE_EINVAL, "couple_step: NULL particle output");

@@ -15,7 +15,8 @@ constexpr double kPi = 3.14159265358979323846;
 enum Slot {
     SL_VTOT = 0, SL_PHISUM = 1, SL_FP = 2, SL_FB = 5, SL_FF = 8, SL_EPSF = 11,
     SL_NCLAMP = 12, SL_NOUT = 13, SL_MAXPHI = 14, SL_NFALL = 15,
-    SL_MLPERR = 16, SL_MLPREF = 17, SL_MLPSAMP = 18, SL_COUNT = 19
+    SL_MLPERR = 16, SL_MLPREF = 17, SL_MLPSAMP = 18,
+    SL_KP = 19, SL_KUP = 20, SL_KB = 23, SL_KUB = 24, SL_KF = 27, SL_KUF = 28, SL_COUNT = 31
 };
 
 template <typename T> struct V4;

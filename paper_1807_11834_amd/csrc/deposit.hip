@@ -3,6 +3,8 @@
 //
 //   phi_c   = sum_p w_pc V_p / V_b                 (porosity eps = 1 - phi)
 //   F_fpi,c = -(1/V_b) sum_p w_pc F_p              (counterpart of the drag)
+//   K_c     = (1/V_b) sum_p w_pc beta_p            (semi-implicit split of F_fpi:
+//   KU_c    = (1/V_b) sum_p w_pc beta_p u_p         F_fpi = -K u_f + KU in uniform flow)
 //
 // The particles are in the canonical (cell, id) order with CSR offsets `start`.
 // CIC: two passes through per-row partial sums (see below); every particle is
@@ -15,6 +17,11 @@
 namespace cpl {
 
 constexpr int kChunk = 256;   // particles staged per wave and chunk
+
+// What a deposition pass sums: V_p / V_b (phi), the drag F_p (source) or
+// (beta_p, beta_p u_p) (semi-implicit split).
+enum DepMode { kPhi = 0, kForce = 1, kSemi = 2 };
+template <int MODE> struct DepNc { static constexpr int value = MODE == kPhi ? 1 : (MODE == kForce ? 3 : 4); };
 
 template <typename T> __device__ __forceinline__ T vol_over_vb(T d, T inv_vb) {
     return (T(kPi / 6.0) * d * d * d) * inv_vb;
@@ -33,20 +40,35 @@ __device__ __forceinline__ void write_gradient(int64_t c, int cx, int cy, int cz
 // ---------------------------------------------------------------------------
 // NGP (containing cell)
 // ---------------------------------------------------------------------------
-template <typename T, bool KAHAN, bool FORCE>
+template <typename T, bool KAHAN, int MODE>
 __global__ __launch_bounds__(kBlock) void k_deposit_ngp(const int32_t *__restrict__ start,
                                                         const vec4<T> *__restrict__ sp,
                                                         const int32_t *__restrict__ perm,
-                                                        const T *__restrict__ drag, int64_t n, Geo<T> g,
+                                                        const T *__restrict__ drag,
+                                                        const vec4<T> *__restrict__ src4, int64_t n, Geo<T> g,
                                                         const T *__restrict__ P, const T *__restrict__ Plo,
-                                                        T *__restrict__ out, T *__restrict__ G,
+                                                        T *__restrict__ out, T *__restrict__ out2, T *__restrict__ G,
                                                         double *__restrict__ part, int64_t ps) {
     __shared__ double red[kWavesPerBlock];
     const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    double v[3] = {0.0, 0.0, 0.0};
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
     if (c < g.ncell) {
         const int32_t s = seg_clamp(start[c], n), e = seg_clamp(start[c + 1], n);
-        if constexpr (!FORCE) {
+        if constexpr (MODE == kSemi) {
+            Acc<T, KAHAN> acc[4];
+            for (int32_t p = s; p < e; ++p) {
+                int64_t id = perm[p];
+                if (id < 0 || id >= n) id = 0;
+                const vec4<T> b = src4[id];
+                acc[0].add(b.x);
+                acc[1].add(b.y);
+                acc[2].add(b.z);
+                acc[3].add(b.w);
+            }
+            out[c] = acc[0].s * g.inv_vb;
+            for (int k = 0; k < 3; ++k) out2[k * g.ncell + c] = acc[k + 1].s * g.inv_vb;
+            for (int k = 0; k < 4; ++k) v[k] = (double)(acc[k].s * g.inv_vb);
+        } else if constexpr (MODE == kPhi) {
             Acc<T, KAHAN> acc;
             for (int32_t p = s; p < e; ++p) acc.add(vol_over_vb(sp[p].w, g.inv_vb));
             out[c] = acc.s;
@@ -70,17 +92,23 @@ __global__ __launch_bounds__(kBlock) void k_deposit_ngp(const int32_t *__restric
             write_gradient(c, cx, cy, cz, g, P, Plo, G);
         }
     }
-    if constexpr (!FORCE) {
+    if constexpr (MODE == kPhi) {
         const double t = block_sum(v[0], red);
         const double m = block_max(v[0], red);
         if (threadIdx.x == 0) {
             part[SL_PHISUM * ps + blockIdx.x] = t;
             part[SL_MAXPHI * ps + blockIdx.x] = m;
         }
-    } else {
+    } else if constexpr (MODE == kForce) {
         for (int k = 0; k < 3; ++k) {
             const double t = block_sum(v[k], red);
             if (threadIdx.x == 0) part[(SL_FB + k) * ps + blockIdx.x] = t;
+        }
+    } else {
+        const int slots[4] = {SL_KB, SL_KUB, SL_KUB + 1, SL_KUB + 2};
+        for (int k = 0; k < 4; ++k) {
+            const double t = block_sum(v[k], red);
+            if (threadIdx.x == 0) part[slots[k] * ps + blockIdx.x] = t;
         }
     }
 }
@@ -97,12 +125,12 @@ __global__ __launch_bounds__(kBlock) void k_deposit_ngp(const int32_t *__restric
 // (source offset) of each target cell.
 // Pass 2, k_deposit_sum: per target cell, the 9 partials of its source rows in
 // ascending row order.
-template <typename T, bool FORCE> struct RowStage {
+template <typename T, int MODE> struct RowStage {
     int node[kWavesPerBlock][kChunk];                  // x-stencil nodes lo | hi << 16
     T tx[kWavesPerBlock][kChunk];                      // weight of hi
     T wy[3][kWavesPerBlock][kChunk];                   // weight on target rows y'-1, y', y'+1
     T wz[3][kWavesPerBlock][kChunk];                   // weight on target layers z'-1, z', z'+1
-    T val[FORCE ? 3 : 1][kWavesPerBlock][kChunk];      // V_p / V_b, or F_p
+    T val[DepNc<MODE>::value][kWavesPerBlock][kChunk]; // V_p / V_b, F_p, or (beta_p, beta_p u_p)
 };
 
 template <typename T>
@@ -116,14 +144,15 @@ __device__ __forceinline__ void row_weights(const Axis<T> &a, int c, T w[3]) {
     }
 }
 
-template <typename T, bool KAHAN, bool FORCE>
+template <typename T, bool KAHAN, int MODE>
 __global__ __launch_bounds__(kBlock) void k_deposit_rows(const int32_t *__restrict__ start,
                                                          const vec4<T> *__restrict__ sp,
                                                          const int32_t *__restrict__ perm,
-                                                         const T *__restrict__ drag, int64_t n, Geo<T> g,
+                                                         const T *__restrict__ drag,
+                                                         const vec4<T> *__restrict__ src4, int64_t n, Geo<T> g,
                                                          T *__restrict__ partial) {
-    constexpr int NC = FORCE ? 3 : 1;
-    __shared__ RowStage<T, FORCE> st;
+    constexpr int NC = DepNc<MODE>::value;
+    __shared__ RowStage<T, MODE> st;
     const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int nbx = g.nb[0], nby = g.nb[1], nbz = g.nb[2];
     const int nseg = (nbx + kWave - 1) / kWave;
@@ -162,12 +191,20 @@ __global__ __launch_bounds__(kBlock) void k_deposit_rows(const int32_t *__restri
                 st.wy[j][w][k] = wy[j];
                 st.wz[j][w][k] = wz[j];
             }
-            if constexpr (FORCE) {
+            if constexpr (MODE == kForce) {
                 int64_t id = perm[cs + k];
                 if (id < 0 || id >= n) id = 0;   // perm is a permutation of [0, n)
                 st.val[0][w][k] = drag[3 * id + 0];
                 st.val[1][w][k] = drag[3 * id + 1];
                 st.val[2][w][k] = drag[3 * id + 2];
+            } else if constexpr (MODE == kSemi) {
+                int64_t id = perm[cs + k];
+                if (id < 0 || id >= n) id = 0;
+                const vec4<T> b = src4[id];
+                st.val[0][w][k] = b.x;
+                st.val[1][w][k] = b.y;
+                st.val[2][w][k] = b.z;
+                st.val[3][w][k] = b.w;
             } else {
                 st.val[0][w][k] = vol_over_vb(q.w, g.inv_vb);
             }
@@ -220,15 +257,15 @@ __global__ __launch_bounds__(kBlock) void k_deposit_rows(const int32_t *__restri
     }
 }
 
-template <typename T, bool KAHAN, bool FORCE>
+template <typename T, bool KAHAN, int MODE>
 __global__ __launch_bounds__(kBlock) void k_deposit_sum(const T *__restrict__ partial, Geo<T> g,
                                                         const T *__restrict__ P, const T *__restrict__ Plo,
-                                                        T *__restrict__ out, T *__restrict__ G,
+                                                        T *__restrict__ out, T *__restrict__ out2, T *__restrict__ G,
                                                         double *__restrict__ part, int64_t ps) {
-    constexpr int NC = FORCE ? 3 : 1;
+    constexpr int NC = DepNc<MODE>::value;
     __shared__ double red[kWavesPerBlock];
     const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    double v[3] = {0.0, 0.0, 0.0};
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
     if (c < g.ncell) {
         int cx, cy, cz;
         decode_cell(c, g.nb, cx, cy, cz);
@@ -241,29 +278,39 @@ __global__ __launch_bounds__(kBlock) void k_deposit_sum(const T *__restrict__ pa
                 for (int k = 0; k < NC; ++k) acc[k].add(partial[((int64_t)slot * NC + k) * g.ncell + c]);
             }
         }
-        if constexpr (FORCE) {
+        if constexpr (MODE == kForce) {
             const T fx = -acc[0].s * g.inv_vb, fy = -acc[1].s * g.inv_vb, fz = -acc[2].s * g.inv_vb;
             out[c] = fx;
             out[g.ncell + c] = fy;
             out[2 * g.ncell + c] = fz;
             v[0] = fx; v[1] = fy; v[2] = fz;
             write_gradient(c, cx, cy, cz, g, P, Plo, G);
+        } else if constexpr (MODE == kSemi) {
+            out[c] = acc[0].s * g.inv_vb;
+            for (int k = 0; k < 3; ++k) out2[k * g.ncell + c] = acc[k + 1].s * g.inv_vb;
+            for (int k = 0; k < 4; ++k) v[k] = (double)(acc[k].s * g.inv_vb);
         } else {
             out[c] = acc[0].s;
             v[0] = (double)acc[0].s;
         }
     }
-    if constexpr (!FORCE) {
+    if constexpr (MODE == kPhi) {
         const double t = block_sum(v[0], red);
         const double m = block_max(v[0], red);
         if (threadIdx.x == 0) {
             part[SL_PHISUM * ps + blockIdx.x] = t;
             part[SL_MAXPHI * ps + blockIdx.x] = m;
         }
-    } else {
+    } else if constexpr (MODE == kForce) {
         for (int k = 0; k < 3; ++k) {
             const double t = block_sum(v[k], red);
             if (threadIdx.x == 0) part[(SL_FB + k) * ps + blockIdx.x] = t;
+        }
+    } else {
+        const int slots[4] = {SL_KB, SL_KUB, SL_KUB + 1, SL_KUB + 2};
+        for (int k = 0; k < 4; ++k) {
+            const double t = block_sum(v[k], red);
+            if (threadIdx.x == 0) part[slots[k] * ps + blockIdx.x] = t;
         }
     }
 }
@@ -283,34 +330,33 @@ static int row_blocks(const int nb[3]) {
     return (int)((nwave + kWavesPerBlock - 1) / kWavesPerBlock);
 }
 
-template <typename T, bool KAHAN> int launch_deposit_phi(const StepArgs<T> &a, hipStream_t st) {
+template <typename T, bool KAHAN, int MODE>
+static int launch_deposit(const StepArgs<T> &a, T *out, T *out2, hipStream_t st, const char *sum_mark) {
     const int nblk = deposit_blocks(a.g.nb, a.g.ncell, a.cic);
+    const vec4<T> *src4 = a.uf4;   // (beta, beta u_p) per particle once the drag has run
     if (a.cic) {
-        hipLaunchKernelGGL((k_deposit_rows<T, KAHAN, false>), dim3(row_blocks(a.g.nb)), dim3(kBlock), 0, st, a.start,
-                           a.sp, a.perm, a.drag, a.n, a.g, a.dep_partial);
-        a.mk->mark("deposit_phi_sum", st);
-        hipLaunchKernelGGL((k_deposit_sum<T, KAHAN, false>), dim3(nblk), dim3(kBlock), 0, st, a.dep_partial, a.g, a.P,
-                           a.Plo, a.phi, a.G, a.part, a.part_stride);
+        hipLaunchKernelGGL((k_deposit_rows<T, KAHAN, MODE>), dim3(row_blocks(a.g.nb)), dim3(kBlock), 0, st, a.start,
+                           a.sp, a.perm, a.drag, src4, a.n, a.g, a.dep_partial);
+        a.mk->mark(sum_mark, st);
+        hipLaunchKernelGGL((k_deposit_sum<T, KAHAN, MODE>), dim3(nblk), dim3(kBlock), 0, st, a.dep_partial, a.g, a.P,
+                           a.Plo, out, out2, a.G, a.part, a.part_stride);
     } else {
-        hipLaunchKernelGGL((k_deposit_ngp<T, KAHAN, false>), dim3(nblk), dim3(kBlock), 0, st, a.start, a.sp, a.perm,
-                           a.drag, a.n, a.g, a.P, a.Plo, a.phi, a.G, a.part, a.part_stride);
+        hipLaunchKernelGGL((k_deposit_ngp<T, KAHAN, MODE>), dim3(nblk), dim3(kBlock), 0, st, a.start, a.sp, a.perm,
+                           a.drag, src4, a.n, a.g, a.P, a.Plo, out, out2, a.G, a.part, a.part_stride);
     }
     return nblk;
 }
 
+template <typename T, bool KAHAN> int launch_deposit_phi(const StepArgs<T> &a, hipStream_t st) {
+    return launch_deposit<T, KAHAN, kPhi>(a, a.phi, nullptr, st, "deposit_phi_sum");
+}
+
 template <typename T, bool KAHAN> int launch_deposit_force(const StepArgs<T> &a, hipStream_t st) {
-    const int nblk = deposit_blocks(a.g.nb, a.g.ncell, a.cic);
-    if (a.cic) {
-        hipLaunchKernelGGL((k_deposit_rows<T, KAHAN, true>), dim3(row_blocks(a.g.nb)), dim3(kBlock), 0, st, a.start,
-                           a.sp, a.perm, a.drag, a.n, a.g, a.dep_partial);
-        a.mk->mark("deposit_force_sum", st);
-        hipLaunchKernelGGL((k_deposit_sum<T, KAHAN, true>), dim3(nblk), dim3(kBlock), 0, st, a.dep_partial, a.g, a.P,
-                           a.Plo, a.F, a.G, a.part, a.part_stride);
-    } else {
-        hipLaunchKernelGGL((k_deposit_ngp<T, KAHAN, true>), dim3(nblk), dim3(kBlock), 0, st, a.start, a.sp, a.perm,
-                           a.drag, a.n, a.g, a.P, a.Plo, a.F, a.G, a.part, a.part_stride);
-    }
-    return nblk;
+    return launch_deposit<T, KAHAN, kForce>(a, a.F, nullptr, st, "deposit_force_sum");
+}
+
+template <typename T, bool KAHAN> int launch_deposit_semi(const StepArgs<T> &a, hipStream_t st) {
+    return launch_deposit<T, KAHAN, kSemi>(a, a.K, a.KU, st, "deposit_semi_sum");
 }
 
 template int launch_deposit_phi<float, true>(const StepArgs<float> &, hipStream_t);
@@ -321,5 +367,9 @@ template int launch_deposit_force<float, true>(const StepArgs<float> &, hipStrea
 template int launch_deposit_force<float, false>(const StepArgs<float> &, hipStream_t);
 template int launch_deposit_force<double, true>(const StepArgs<double> &, hipStream_t);
 template int launch_deposit_force<double, false>(const StepArgs<double> &, hipStream_t);
+template int launch_deposit_semi<float, true>(const StepArgs<float> &, hipStream_t);
+template int launch_deposit_semi<float, false>(const StepArgs<float> &, hipStream_t);
+template int launch_deposit_semi<double, true>(const StepArgs<double> &, hipStream_t);
+template int launch_deposit_semi<double, false>(const StepArgs<double> &, hipStream_t);
 
 }  // namespace cpl

@@ -59,6 +59,7 @@ template <typename T> struct StepArgs {
     int kahan;         // compensated per-cell sums (FP32 modes)
     int vel_source;    // 0 fine, 1 bulk, 2 given, 3 learned surrogate (+ fine fallback)
     int advect;
+    int semi;          // semi-implicit source fields K, KU
     T dt, rho_f, mu_f, rho_p, eps_min;
     float phi_fp64;    // FP32 modes: FP64 void fraction above this particle solid fraction
     // inputs
@@ -71,13 +72,16 @@ template <typename T> struct StepArgs {
     const int32_t *perm, *start;
     T *phi, *F, *U, *P, *G;  // bulk
     T *fine_eps, *fine_F;    // fine
+    T *K, *KU;               // bulk semi-implicit coefficient [ncell] and beta u_p source [3][ncell]
+    T *fine_K, *fine_KU;     // the same prolonged to the fine grid
     double *diag;
     // scratch
     vec4<T> *sp;     // sorted particles (x, y, z, d)
     vec4<T> *uf4;    // per particle (input order): packed (x, y, z, d) from binning until the
-                     // gather has read it, then fluid velocity and void fraction
+                     // gather has read it, then fluid velocity and void fraction until the
+                     // drag has read it, then (beta, beta u_p) when semi
     T *Plo;          // [ncell] low word of the restricted pressure (Kahan compensation)
-    T *dep_partial;  // [9][3][ncell] per-source-row partial sums of the CIC deposition
+    T *dep_partial;  // [9][nc][ncell] per-source-row partial sums of the CIC deposition (nc <= 4)
     double *part;    // [SL_COUNT][max_blocks]
     int64_t part_stride;
     Marker *mk;      // per-kernel event recording (never null)
@@ -109,6 +113,7 @@ int64_t bricks_of(const int nb[3]);
 // (one FP64 partial per workgroup and diagnostic slot).
 template <typename T, bool KAHAN> int launch_deposit_phi(const StepArgs<T> &a, hipStream_t st);
 template <typename T, bool KAHAN> int launch_deposit_force(const StepArgs<T> &a, hipStream_t st);
+template <typename T, bool KAHAN> int launch_deposit_semi(const StepArgs<T> &a, hipStream_t st);
 int deposit_blocks(const int nb[3], int64_t ncell, int cic);
 
 }  // namespace cpl

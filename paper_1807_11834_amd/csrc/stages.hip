@@ -16,11 +16,13 @@
 //                  velocity, void fraction from a haloed copy of phi), so the
 //                  fine lookup costs no extra pass over the fine grid.
 //   k_sample       the same sampling for the bulk and given velocity sources.
-//   k_drag         drag and explicit Euler advection in input order (coalesced).
-//   deposit force  (deposit.hip), with the bulk pressure gradient.
+//   k_drag         drag and explicit Euler advection in input order (coalesced);
+//                  with the semi-implicit split also (beta, beta u_p).
+//   deposit force  (deposit.hip), with the bulk pressure gradient; then the
+//                  semi-implicit K, KU when requested.
 //   k_prolong      one thread per bulk cell writes its r^3 fine children of
-//                  eps and F_fpi: conservative trilinear T_f + D_c with the
-//                  27-neighbour values held in registers.
+//                  eps and F_fpi (a second launch: K and KU): conservative
+//                  trilinear T_f + D_c with the 27-neighbour values in registers.
 //   k_diag         fixed-order reduction of the per-workgroup FP64 partials.
 #include <type_traits>
 
@@ -383,7 +385,7 @@ __global__ __launch_bounds__(kBlock) void k_drag(StepArgs<T> a) {
     __shared__ double red[kWavesPerBlock];
     const Geo<T> &g = a.g;
     const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // sum F (3), clamped, V_p
+    double acc[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // sum F (3), clamped, V_p, beta, beta u_p (3)
     if (p < a.n) {
         int o = 0;
         const T xs[3] = {clamp_coord(a.pos[3 * p + 0], g.L[0], o), clamp_coord(a.pos[3 * p + 1], g.L[1], o),
@@ -421,6 +423,20 @@ __global__ __launch_bounds__(kBlock) void k_drag(StepArgs<T> a) {
         acc[3] = clamped;
         const double dd = (double)d;
         acc[4] = kPi * dd * dd * dd / 6.0;
+        if (a.semi) {
+            // (beta, beta u_p) with the velocity the drag used, for the
+            // semi-implicit deposition (this thread has read uf4[p] already)
+            vec4<T> b;
+            b.x = beta;
+            b.y = beta * us[0];
+            b.z = beta * us[1];
+            b.w = beta * us[2];
+            a.uf4[p] = b;
+            acc[5] = (double)beta;
+            acc[6] = (double)b.y;
+            acc[7] = (double)b.z;
+            acc[8] = (double)b.w;
+        }
 
         if (a.advect) {
             // explicit Euler from the old state, specular reflection at the walls
@@ -442,8 +458,9 @@ __global__ __launch_bounds__(kBlock) void k_drag(StepArgs<T> a) {
             }
         }
     }
-    const int slots[5] = {SL_FP, SL_FP + 1, SL_FP + 2, SL_NCLAMP, SL_VTOT};
-    for (int k = 0; k < 5; ++k) {
+    const int slots[9] = {SL_FP, SL_FP + 1, SL_FP + 2, SL_NCLAMP, SL_VTOT, SL_KP, SL_KUP, SL_KUP + 1, SL_KUP + 2};
+    const int nsl = a.semi ? 9 : 5;   // uniform over the launch
+    for (int k = 0; k < nsl; ++k) {
         const double t = block_sum(acc[k], red);
         if (threadIdx.x == 0) a.part[slots[k] * a.part_stride + blockIdx.x] = t;
     }
@@ -477,8 +494,18 @@ __device__ __forceinline__ T wsum3(int l, T a0, T a1, T a2) {
     return s;
 }
 
+// The four bulk fields a prolongation launch transfers, their fine outputs and
+// the diagnostic slots of their fine sums; field 0 is optionally complemented
+// (the solid fraction phi is prolonged as the porosity 1 - phi).
+template <typename T> struct ProlongSet {
+    const T *B[4];
+    T *out[4];
+    int slot[4];
+    int complement0;
+};
+
 template <typename T, int R>
-__global__ __launch_bounds__(kBlock) void k_prolong(StepArgs<T> a) {
+__global__ __launch_bounds__(kBlock) void k_prolong(StepArgs<T> a, ProlongSet<T> fs) {
     __shared__ double red[kWavesPerBlock];
     const Geo<T> &g = a.g;
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -495,8 +522,8 @@ __global__ __launch_bounds__(kBlock) void k_prolong(StepArgs<T> a) {
         const int64_t fbase = (int64_t)R * cz * nfxy + (int64_t)R * cy * nfx + (int64_t)R * cx;
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
-            const T *__restrict__ B = (f == 0) ? a.phi : a.F + (int64_t)(f - 1) * g.ncell;
-            T *__restrict__ out = (f == 0) ? a.fine_eps : a.fine_F + (int64_t)(f - 1) * g.nfine;
+            const T *__restrict__ B = fs.B[f];
+            T *__restrict__ out = fs.out[f];
             T b[3][3][3];
 #pragma unroll
             for (int k = 0; k < 3; ++k)
@@ -505,7 +532,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong(StepArgs<T> a) {
 #pragma unroll
                     for (int i = 0; i < 3; ++i) {
                         T v = B[oz[k] + oy[j] + ox[i]];
-                        b[k][j][i] = (f == 0) ? T(1) - v : v;
+                        b[k][j][i] = (f == 0 && fs.complement0) ? T(1) - v : v;
                     }
             // defect of the parent: B_c - (1/R^3) sum of the trilinear children
             T D = T(0);
@@ -556,13 +583,9 @@ __global__ __launch_bounds__(kBlock) void k_prolong(StepArgs<T> a) {
             sums[f] = s;
         }
     }
-    {
-        double t = block_sum(sums[0], red);
-        if (threadIdx.x == 0) a.part[SL_EPSF * a.part_stride + blockIdx.x] = t;
-    }
-    for (int k = 0; k < 3; ++k) {
-        double t = block_sum(sums[k + 1], red);
-        if (threadIdx.x == 0) a.part[(SL_FF + k) * a.part_stride + blockIdx.x] = t;
+    for (int k = 0; k < 4; ++k) {
+        double t = block_sum(sums[k], red);
+        if (threadIdx.x == 0) a.part[fs.slot[k] * a.part_stride + blockIdx.x] = t;
     }
 }
 
@@ -639,8 +662,25 @@ static void launch_grid_stages(const StepArgs<T> &a, hipStream_t st) {
     if (a.n > 0) hipLaunchKernelGGL(k_drag<T>, dim3(pb), dim3(kBlock), 0, st, a);
     a.mk->mark("deposit_force", st);
     launch_deposit_force<T, KAHAN>(a, st);
+    if (a.semi) {
+        a.mk->mark("deposit_semi", st);
+        launch_deposit_semi<T, KAHAN>(a, st);
+    }
+    const int64_t nc = a.g.ncell, nf = a.g.nfine;
+    const ProlongSet<T> src{{a.phi, a.F, a.F + nc, a.F + 2 * nc},
+                            {a.fine_eps, a.fine_F, a.fine_F + nf, a.fine_F + 2 * nf},
+                            {SL_EPSF, SL_FF, SL_FF + 1, SL_FF + 2},
+                            1};
     a.mk->mark("prolong", st);
-    hipLaunchKernelGGL((k_prolong<T, R>), dim3(cb), dim3(kBlock), 0, st, a);
+    hipLaunchKernelGGL((k_prolong<T, R>), dim3(cb), dim3(kBlock), 0, st, a, src);
+    if (a.semi) {
+        const ProlongSet<T> semi{{a.K, a.KU, a.KU + nc, a.KU + 2 * nc},
+                                 {a.fine_K, a.fine_KU, a.fine_KU + nf, a.fine_KU + 2 * nf},
+                                 {SL_KF, SL_KUF, SL_KUF + 1, SL_KUF + 2},
+                                 0};
+        a.mk->mark("prolong_semi", st);
+        hipLaunchKernelGGL((k_prolong<T, R>), dim3(cb), dim3(kBlock), 0, st, a, semi);
+    }
 }
 
 template <typename T, bool KAHAN> static void launch_by_ratio(const StepArgs<T> &a, hipStream_t st) {
@@ -677,6 +717,13 @@ template <typename T> hipError_t launch_stages(const StepArgs<T> &a, hipStream_t
     spec.nblk[SL_MLPERR] = nmlp;
     spec.nblk[SL_MLPREF] = nmlp;
     spec.nblk[SL_MLPSAMP] = nmlp;
+    for (int k = 0; k < 4; ++k) {
+        spec.nblk[SL_KP + k] = a.semi ? npart : 0;   // k_drag
+        spec.nblk[SL_KB + k] = a.semi ? db : 0;      // deposition
+        spec.nblk[SL_KF + k] = a.semi ? (int)cb : 0; // prolongation
+        spec.scale[SL_KB + k] = a.g.vb;
+        spec.scale[SL_KF + k] = a.g.vf;
+    }
     spec.scale[SL_PHISUM] = a.g.vb;
     for (int k = 0; k < 3; ++k) {
         spec.scale[SL_FB + k] = a.g.vb;

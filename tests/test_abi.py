@@ -48,9 +48,10 @@ def test_struct_layout_matches_header(tmp_path):
 int main(void) {
   printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(couple_config), offsetof(couple_config, rho_f),
          offsetof(couple_config, deposit), offsetof(couple_config, dt), offsetof(couple_config, max_particles),
-         offsetof(couple_config, mlp_tol), offsetof(couple_config, mlp_period), offsetof(couple_config, reserved));
+         offsetof(couple_config, mlp_tol), offsetof(couple_config, mlp_period), offsetof(couple_config, semi_implicit));
   printf("%zu %zu %zu\\n", sizeof(couple_inputs), offsetof(couple_inputs, uf_given), offsetof(couple_inputs, step));
-  printf("%zu %zu %zu\\n", sizeof(couple_outputs), offsetof(couple_outputs, diag), offsetof(couple_outputs, uf));
+  printf("%zu %zu %zu %zu\\n", sizeof(couple_outputs), offsetof(couple_outputs, diag), offsetof(couple_outputs, uf),
+         offsetof(couple_outputs, fine_KU));
   printf("%zu %zu %zu\\n", sizeof(couple_mlp_config), offsetof(couple_mlp_config, lr), offsetof(couple_mlp_config, eps));
   printf("%d %d %d %d\\n", COUPLE_DIAG_LEN, COUPLE_VEL_MLP, COUPLE_MLP_NFEAT, COUPLE_MLP_NPARAM);
   return 0; }
@@ -61,11 +62,12 @@ int main(void) {
     a = [int(x) for x in lines[0].split()]
     K = cpl._Config
     assert a == [C.sizeof(K), K.rho_f.offset, K.deposit.offset, K.dt.offset, K.max_particles.offset,
-                 K.mlp_tol.offset, K.mlp_period.offset, K.reserved.offset]
+                 K.mlp_tol.offset, K.mlp_period.offset, K.semi_implicit.offset]
     b = [int(x) for x in lines[1].split()]
     assert b == [C.sizeof(cpl._Inputs), cpl._Inputs.uf_given.offset, cpl._Inputs.step.offset]
     c = [int(x) for x in lines[2].split()]
-    assert c == [C.sizeof(cpl._Outputs), cpl._Outputs.diag.offset, cpl._Outputs.uf.offset]
+    assert c == [C.sizeof(cpl._Outputs), cpl._Outputs.diag.offset, cpl._Outputs.uf.offset,
+                 cpl._Outputs.fine_KU.offset]
     d = [int(x) for x in lines[3].split()]
     assert d == [C.sizeof(cpl._MlpConfig), cpl._MlpConfig.lr.offset, cpl._MlpConfig.eps.offset]
     e = [int(x) for x in lines[4].split()]
@@ -78,7 +80,7 @@ BAD = [
     dict(vel_source=9), dict(advect=2), dict(advect=1, dt=float("inf")), dict(max_particles=-5),
     dict(nb=(2048, 2048, 1024)), dict(nb=(40000, 2, 2)),
     dict(vel_source=3, precision=0), dict(vel_source=3, mlp_period=0), dict(vel_source=3, mlp_tol=-1.0),
-    dict(vel_source=3, mlp_tol=float("nan")),
+    dict(vel_source=3, mlp_tol=float("nan")), dict(semi_implicit=2), dict(semi_implicit=-1),
 ]
 
 
