@@ -68,6 +68,8 @@ def lib():
         L.orc_interp.argtypes = [P, P, P, I64, P, I, P]
         L.orc_drag.argtypes = [I64, P, P, P, P, D, D, D, P, P]
         L.orc_drag.restype = I64
+        L.orc_drag_vof.argtypes = [I64, P, P, P, P, P, D, D, D, D, D, P, P]
+        L.orc_drag_vof.restype = I64
         L.orc_prolong.argtypes = [P, P, I, I, P]
         L.orc_prolong_at.argtypes = [P, P, I, I, I64, P, P]
         L.orc_advect.argtypes = [I64, P, P, P, P, D, D, P, I]
@@ -192,6 +194,19 @@ def drag(uf, up, diam, eps_p, rho_f, mu_f, eps_min):
     return force, beta, int(nc)
 
 
+def drag_vof(uf, up, diam, eps_p, alpha_p, rho1, mu1, rho2, mu2, eps_min):
+    """Two-fluid drag: (force [n,3], beta [n], n_clamped) with the density and
+    viscosity at each particle mixed by its liquid fraction alpha_p."""
+    uf = _f64(uf).reshape(-1, 3)
+    n = uf.shape[0]
+    force = np.empty((n, 3), dtype=np.float64)
+    beta = np.empty(n, dtype=np.float64)
+    nc = lib().orc_drag_vof(n, _p(uf), _p(_f64(up).reshape(-1, 3)), _p(_f64(diam)), _p(_f64(eps_p)),
+                            _p(_f64(alpha_p)), float(rho1), float(mu1), float(rho2), float(mu2), float(eps_min),
+                            _p(force), _p(beta))
+    return force, beta, int(nc)
+
+
 def prolong(B, nb, r, conservative=True):
     out = np.empty(int(np.prod(nb)) * r ** 3, dtype=np.float64)
     lib().orc_prolong(_p(_f64(B)), _p(_i32x3(nb)), int(r), int(conservative), _p(out))
@@ -243,7 +258,8 @@ def restrict_all(fine, grid):
 
 def step(pos, vel, diam, fine, grid, rho_f=1000.0, mu_f=1e-3, rho_p=2500.0, eps_min=0.3,
          cic=True, prec32=True, vel_source="fine", advect_dt=None, fine_out="full",
-         fine_sample=None, bulk_velocity=None, restricted=None, semi_implicit=False):
+         fine_sample=None, bulk_velocity=None, restricted=None, semi_implicit=False, alpha=None, rho2=None,
+         mu2=None):
     """One coupling step in FP64.
 
     ``fine`` is (u, v, w, p), each (nfz, nfy, nfx).  ``vel_source`` is "fine"
@@ -254,6 +270,9 @@ def step(pos, vel, diam, fine, grid, rho_f=1000.0, mu_f=1e-3, rho_p=2500.0, eps_
     ``restricted`` reuses the output of :func:`restrict_all` for the same fine
     fields (the restriction does not depend on the particles).  ``semi_implicit``
     adds the semi-implicit source fields K, KU (bulk and prolonged) and their sums.
+    ``alpha`` (fine liquid volume fraction, (nfz, nfy, nfx)) turns on the
+    two-fluid drag: alpha is restricted to the bulk grid, interpolated
+    trilinearly to each particle, and mixes (rho_f, mu_f) with (rho2, mu2).
     Returns a dict of numpy arrays and the diagnostics.
     """
     box = tuple(float(b) for b in grid.box)
@@ -285,7 +304,13 @@ def step(pos, vel, diam, fine, grid, rho_f=1000.0, mu_f=1e-3, rho_p=2500.0, eps_
         uf = _f64(bulk_velocity).reshape(-1, 3)
     else:
         raise ValueError(vel_source)
-    force, beta, nclamp = drag(uf, vel, diam, eps_p, rho_f, mu_f, eps_min)
+    if alpha is None:
+        force, beta, nclamp = drag(uf, vel, diam, eps_p, rho_f, mu_f, eps_min)
+    else:
+        alpha_b = restrict(alpha, nb, r)
+        alpha_p = interp(alpha_b, nb, box, pos, prec32)
+        force, beta, nclamp = drag_vof(uf, vel, diam, eps_p, alpha_p, rho_f, mu_f, rho2, mu2, eps_min)
+        out.update(alpha=alpha_b, alpha_p=alpha_p)
     out.update(eps_p=eps_p, uf=uf, drag=force, beta=beta)
     Fc = deposit_force(pos, force, perm, box, nb, cic, prec32)
     out["F"] = Fc

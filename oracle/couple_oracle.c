@@ -18,7 +18,8 @@
  *   interp       fluid value at a particle ("cell values or locally interpolated
  *                values", Sec. 1)
  *   drag         F = beta (u_f - u_p), Eq. DragLaw (Sec. 2.4), beta by the
- *                Di Felice voidage correlation
+ *                Di Felice voidage correlation; optionally with the two-fluid
+ *                (VOF) density and viscosity at the particle (Sec. 2.5)
  *   semi         deposited drag coefficient and beta-weighted particle velocity,
  *                the semi-implicit form of the momentum source (Sec. 2.5)
  *   prolong      bulk -> fine "particle related fields" transfer (Fig. 1)
@@ -386,9 +387,28 @@ void orc_interp(const double *q, const int n[3], const double box[3], int64_t np
 /*   beta_0 = 1/2 rho_f (pi d^2/4) eps*^(2-3.7) * 4.8^2 mu_f / (rho_f eps* d). */
 /* Returns the number of particles whose void fraction was raised to eps_min.  */
 /* ------------------------------------------------------------------------- */
-int64_t orc_drag(int64_t n, const double *uf, const double *up, const double *diam,
-                 const double *eps_p, double rho_f, double mu_f, double eps_min,
-                 double *force, double *beta)
+/* beta of one particle (Di Felice, as above) for relative speed |u_r| = mag,
+ * void fraction e (already raised to eps_min), diameter d and the fluid's
+ * density and viscosity at the particle. */
+static double drag_beta(double mag, double e, double d, double rho_f, double mu_f)
+{
+    double area = ORC_PI * d * d / 4.0;
+    if (mag > 0.0) {
+        double re = rho_f * e * d * mag / mu_f;
+        double cd = 0.63 + 4.8 / sqrt(re);
+        cd = cd * cd;
+        double l = 1.5 - log10(re);
+        double chi = 3.7 - 0.65 * exp(-l * l / 2.0);
+        return 0.5 * cd * rho_f * area * pow(e, 2.0 - chi) * mag;
+    }
+    return 0.5 * rho_f * area * pow(e, 2.0 - 3.7) * 4.8 * 4.8 * mu_f / (rho_f * e * d);
+}
+
+/* Drag of particles p in [0, n) with the fluid density and viscosity rho_f[p],
+ * mu_f[p] at each particle; returns the number of clamped void fractions. */
+static int64_t drag_var(int64_t n, const double *uf, const double *up, const double *diam,
+                        const double *eps_p, const double *rho_f, const double *mu_f, double eps_min,
+                        double *force, double *beta)
 {
     int64_t clamped = 0;
     for (int64_t p = 0; p < n; ++p) {
@@ -397,26 +417,46 @@ int64_t orc_drag(int64_t n, const double *uf, const double *up, const double *di
             ur[a] = uf[3 * p + a] - up[3 * p + a];
             mag2 += ur[a] * ur[a];
         }
-        double mag = sqrt(mag2);
         double e = eps_p[p];
         if (e < eps_min) { e = eps_min; ++clamped; }
-        double d = diam[p];
-        double area = ORC_PI * d * d / 4.0;
-        double b;
-        if (mag > 0.0) {
-            double re = rho_f * e * d * mag / mu_f;
-            double cd = 0.63 + 4.8 / sqrt(re);
-            cd = cd * cd;
-            double l = 1.5 - log10(re);
-            double chi = 3.7 - 0.65 * exp(-l * l / 2.0);
-            b = 0.5 * cd * rho_f * area * pow(e, 2.0 - chi) * mag;
-        } else {
-            b = 0.5 * rho_f * area * pow(e, 2.0 - 3.7) * 4.8 * 4.8 * mu_f / (rho_f * e * d);
-        }
+        double b = drag_beta(sqrt(mag2), e, diam[p], rho_f[p], mu_f[p]);
         if (beta) beta[p] = b;
         for (int a = 0; a < 3; ++a) force[3 * p + a] = b * ur[a];
     }
     return clamped;
+}
+
+int64_t orc_drag(int64_t n, const double *uf, const double *up, const double *diam,
+                 const double *eps_p, double rho_f, double mu_f, double eps_min,
+                 double *force, double *beta)
+{
+    double *rv = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *mv = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    for (int64_t p = 0; p < n; ++p) { rv[p] = rho_f; mv[p] = mu_f; }
+    int64_t c = drag_var(n, uf, up, diam, eps_p, rv, mv, eps_min, force, beta);
+    free(rv);
+    free(mv);
+    return c;
+}
+
+/* Two-fluid (VOF) drag: the fluid density and viscosity at the particle follow
+ * the liquid volume fraction alpha_p there (the local-property mixture of the
+ * VOF fluid, Sec. 2.5):
+ *   rho_f = rho_1 alpha + rho_2 (1 - alpha),   mu_f = mu_1 alpha + mu_2 (1 - alpha). */
+int64_t orc_drag_vof(int64_t n, const double *uf, const double *up, const double *diam,
+                     const double *eps_p, const double *alpha_p, double rho1, double mu1, double rho2,
+                     double mu2, double eps_min, double *force, double *beta)
+{
+    double *rv = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *mv = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    for (int64_t p = 0; p < n; ++p) {
+        rv[p] = rho1 * alpha_p[p] + rho2 * (1.0 - alpha_p[p]);
+        mv[p] = mu1 * alpha_p[p] + mu2 * (1.0 - alpha_p[p]);
+    }
+    int64_t c = drag_var(n, uf, up, diam, eps_p, rv, mv, eps_min, force, beta);
+    free(rv);
+    free(mv);
+    return c;
 }
 
 /* ------------------------------------------------------------------------- */
