@@ -320,18 +320,16 @@ def mlp_leg(args, w, cfg, pos, vel, diam, fine, plain_ms, plain_kernels, dev):
     }
 
 
-def semi_leg(args, cfg, pos, vel, diam, fine, plain_ms, n, g, fsz, dev):
-    """The same step with the semi-implicit split on (K, KU deposited and
-    prolonged in addition): time per step, the extra kernels and the prolongation
-    roofline of K, KU, and the conservation of their sums."""
+def _time_variant(args, cfg_v, pos, vel, diam, fine, n, dev, alpha=None):
+    """Warm up, then time ``args.steps`` steps of a configuration variant with
+    per-kernel events; returns (ms per step, {kernel: avg ms}, diagnostics)."""
     import torch
     import paper_1807_11834_amd as cpl
-    cfg_s = dataclasses.replace(cfg, semi_implicit=1)
-    c = cpl.Coupler(cfg_s)
-    out = cpl.alloc_outputs(cfg_s, n, device=dev)
+    c = cpl.Coupler(cfg_v)
+    out = cpl.alloc_outputs(cfg_v, n, device=dev)
     try:
         for _ in range(args.warmup):
-            c.step(pos, vel, diam, fine, out=out)
+            c.step(pos, vel, diam, fine, out=out, alpha=alpha)
         torch.cuda.synchronize()
         stream = torch.cuda.current_stream()
         cpl.couple_timing_begin(c.h, args.steps)
@@ -339,7 +337,7 @@ def semi_leg(args, cfg, pos, vel, diam, fine, plain_ms, n, g, fsz, dev):
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         for _ in range(args.steps):
-            c.step(pos, vel, diam, fine, out=out)
+            c.step(pos, vel, diam, fine, out=out, alpha=alpha)
         e1.record(stream)
         torch.cuda.synchronize()
         stats = cpl.couple_timing_end(c.h)
@@ -347,11 +345,19 @@ def semi_leg(args, cfg, pos, vel, diam, fine, plain_ms, n, g, fsz, dev):
         d = cpl.diag_dict(out["diag"])
     finally:
         c.close()
-    kern = {k: t / l for k, (l, t) in stats.items() if l and k in ("deposit_semi", "deposit_semi_sum", "prolong_semi")}
-    ab = kernel_alg_bytes("prolong_semi", n, g.n_bulk, g.n_fine, fsz)
-    pr = kern.get("prolong_semi")
     del out
     torch.cuda.empty_cache()
+    return ms, {k: t / l for k, (l, t) in stats.items() if l}, d
+
+
+def semi_leg(args, cfg, pos, vel, diam, fine, plain_ms, n, g, fsz, dev):
+    """The same step with the semi-implicit split on (K, KU deposited and
+    prolonged in addition): time per step, the extra kernels and the prolongation
+    roofline of K, KU, and the conservation of their sums."""
+    ms, kt, d = _time_variant(args, dataclasses.replace(cfg, semi_implicit=1), pos, vel, diam, fine, n, dev)
+    kern = {k: v for k, v in kt.items() if k in ("deposit_semi", "deposit_semi_sum", "prolong_semi")}
+    ab = kernel_alg_bytes("prolong_semi", n, g.n_bulk, g.n_fine, fsz)
+    pr = kern.get("prolong_semi")
     print(f"# semi-implicit split: {ms:.3f} ms/step", file=sys.stderr, flush=True)
     return {"ms_per_step": ms, "value": n / (ms * 1e-3), "extra_ms_vs_plain": ms - plain_ms,
             "kernels_avg_ms": {k: round(v, 4) for k, v in kern.items()},
@@ -359,6 +365,26 @@ def semi_leg(args, cfg, pos, vel, diam, fine, plain_ms, n, g, fsz, dev):
             "prolong_semi_frac_hbm": round(ab / (pr * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4) if pr else None,
             "conservation": {"K_b/K_p-1": d["K_b"] / d["K_p"] - 1 if d["K_p"] else 0.0,
                              "K_f/K_b-1": d["K_f"] / d["K_b"] - 1 if d["K_b"] else 0.0}}
+
+
+def vof_leg(args, w, cfg, pos, vel, diam, fine, plain_ms, n, g, fsz, dev):
+    """The same step with the two-fluid drag (water below a tilted free surface
+    at z ~ 0.6 L_z, air above: the drag's density and viscosity follow the liquid
+    fraction at each particle): time per step, the alpha restriction kernel and
+    its roofline."""
+    import workload as W
+    alpha = W.fine_alpha_torch(w, dev, fine[0].dtype)
+    cfg_v = dataclasses.replace(cfg, vof=1, rho_f2=1.2, mu_f2=1.8e-5)
+    ms, kt, _ = _time_variant(args, cfg_v, pos, vel, diam, fine, n, dev, alpha=alpha)
+    del alpha
+    ra = kt.get("restrict_alpha")
+    ab = fsz * g.n_fine + fsz * g.n_bulk
+    print(f"# two-fluid drag: {ms:.3f} ms/step", file=sys.stderr, flush=True)
+    return {"ms_per_step": ms, "value": n / (ms * 1e-3), "extra_ms_vs_plain": ms - plain_ms,
+            "fluid_2": {"rho": cfg_v.rho_f2, "mu": cfg_v.mu_f2},
+            "kernels_avg_ms": {k: round(v, 4) for k, v in kt.items() if k in ("restrict_alpha", "drag")},
+            "restrict_alpha_GBps": round(ab / (ra * 1e-3) / 1e9, 1) if ra else None,
+            "restrict_alpha_frac_hbm": round(ab / (ra * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4) if ra else None}
 
 
 def main():
@@ -374,6 +400,7 @@ def main():
                     help="fluid velocity at the particles: fine-grid lookup (default) or bulk trilinear")
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned-surrogate path")
     ap.add_argument("--no-semi", action="store_true", help="skip the semi-implicit split variant")
+    ap.add_argument("--no-vof", action="store_true", help="skip the two-fluid drag variant")
     ap.add_argument("--traffic-summary", metavar="DIR",
                     help="print the JSON summary of the FETCH_SIZE/WRITE_SIZE runs under DIR and exit")
     ap.add_argument("--trace-summary", metavar="CSV",
@@ -497,6 +524,8 @@ def main():
         del pos_s, vel_s, diam_s
     if not args.no_semi:
         rec["semi_implicit"] = semi_leg(args, cfg, pos, vel, diam, fine, ms_step, n, g, fsz, dev)
+    if not args.no_vof:
+        rec["two_fluid_drag"] = vof_leg(args, w, cfg, pos, vel, diam, fine, ms_step, n, g, fsz, dev)
     if not args.no_mlp:
         print("# surrogate: pairs, training, timing ...", file=sys.stderr, flush=True)
         rec["mlp_path"] = mlp_leg(args, w, cfg, pos, vel, diam, fine, ms_step, kernels, dev)

@@ -17,7 +17,12 @@
  *               or locally interpolated values", Sec. 1), or the learned
  *               surrogate of that velocity (couple_mlp.h);
  *   5. drag     F_p = beta (u_f - u_p), Eq. DragLaw of Sec. 2.4, with beta from
- *               the Di Felice voidage correlation;
+ *               the Di Felice voidage correlation; with vof = 1 the fluid density
+ *               and viscosity at the particle are those of the two-fluid (VOF)
+ *               mixture, rho_f = rho_1 alpha + rho_2 (1 - alpha) and likewise mu_f
+ *               (Sec. 2.5), alpha being the liquid volume fraction restricted to
+ *               the bulk grid (its volume average) and interpolated trilinearly
+ *               to the particle;
  *   6. source   momentum source F_fpi,c = -(1/V_b) sum_p w_pc F_p, the counterpart
  *               of the drag in Eq. UFP (Sec. 2.5); with semi_implicit = 1 also its
  *               semi-implicit split (the drag term of Eq. UFP is treated
@@ -129,6 +134,8 @@ typedef struct couple_config {
                                 which the brick takes the fine lookup (>= 0)                  */
     int32_t mlp_period;      /* VEL_MLP: one particle in mlp_period is checked (>= 1)          */
     int32_t semi_implicit;   /* 1: also deposit and prolong K and KU (step 6); 0 or 1          */
+    int32_t vof;             /* 1: two-fluid drag (step 5); rho_f, mu_f are fluid 1's; 0 or 1 */
+    double  rho_f2, mu_f2;   /* vof: density and viscosity of fluid 2 (> 0)                   */
 } couple_config;
 
 typedef struct couple_inputs {
@@ -142,6 +149,7 @@ typedef struct couple_inputs {
     const void *fine_p;      /* [nfz][nfy][nfx] fine pressure                                 */
     const void *uf_given;    /* [n][3] fluid velocity at each particle (VEL_GIVEN only)       */
     int64_t     step;        /* caller's step index; VEL_MLP checks ids = step mod mlp_period */
+    const void *fine_alpha;  /* [nfz][nfy][nfx] liquid volume fraction in [0, 1] (vof only)     */
 } couple_inputs;
 
 typedef struct couple_outputs {
@@ -164,6 +172,7 @@ typedef struct couple_outputs {
     void    *bulk_KU;        /* [3][Nb] semi-implicit explicit part KU (semi_implicit only)   */
     void    *fine_K;         /* [Nf] K prolonged to the fine grid (semi_implicit only)        */
     void    *fine_KU;        /* [3][Nf] KU prolonged to the fine grid (semi_implicit only)    */
+    void    *bulk_alpha;     /* [Nb] restricted liquid volume fraction (vof only)             */
 } couple_outputs;
 
 /* Validate the configuration and allocate the scratch (about 48 * max_particles
@@ -175,7 +184,8 @@ int couple_init(const couple_config *cfg, couple_handle **out);
 /* Enqueue one coupling step (stages 1-9 above) on `stream`.  Every pointer of
  * `in` and `out` except out->beta and out->uf (and in->uf_given unless
  * VEL_GIVEN) must be non-NULL when n > 0; the grid outputs are always required,
- * the four K/KU outputs when semi_implicit = 1 (ignored otherwise).
+ * the four K/KU outputs when semi_implicit = 1 (ignored otherwise), in->fine_alpha
+ * and out->bulk_alpha when vof = 1 (ignored otherwise).
  * VEL_MLP without an attached network is COUPLE_ESTATE. */
 int couple_step(couple_handle *h, const couple_inputs *in, couple_outputs *out, void *stream);
 

@@ -55,13 +55,13 @@ class _Config(C.Structure):
                 ("phi_fp64", C.c_double), ("deposit", C.c_int32), ("precision", C.c_int32),
                 ("vel_source", C.c_int32), ("advect", C.c_int32), ("dt", C.c_double),
                 ("max_particles", C.c_int64), ("mlp_tol", C.c_double), ("mlp_period", C.c_int32),
-                ("semi_implicit", C.c_int32)]
+                ("semi_implicit", C.c_int32), ("vof", C.c_int32), ("rho_f2", C.c_double), ("mu_f2", C.c_double)]
 
 
 class _Inputs(C.Structure):
     _fields_ = [("n", C.c_int64), ("pos", C.c_void_p), ("vel", C.c_void_p), ("diam", C.c_void_p),
                 ("fine_u", C.c_void_p), ("fine_v", C.c_void_p), ("fine_w", C.c_void_p), ("fine_p", C.c_void_p),
-                ("uf_given", C.c_void_p), ("step", C.c_int64)]
+                ("uf_given", C.c_void_p), ("step", C.c_int64), ("fine_alpha", C.c_void_p)]
 
 
 class _Outputs(C.Structure):
@@ -69,7 +69,8 @@ class _Outputs(C.Structure):
                 ("count", C.c_void_p), ("start", C.c_void_p), ("bulk_phi", C.c_void_p), ("bulk_F", C.c_void_p),
                 ("bulk_U", C.c_void_p), ("bulk_P", C.c_void_p), ("bulk_G", C.c_void_p),
                 ("fine_eps", C.c_void_p), ("fine_F", C.c_void_p), ("diag", C.c_void_p), ("uf", C.c_void_p),
-                ("bulk_K", C.c_void_p), ("bulk_KU", C.c_void_p), ("fine_K", C.c_void_p), ("fine_KU", C.c_void_p)]
+                ("bulk_K", C.c_void_p), ("bulk_KU", C.c_void_p), ("fine_K", C.c_void_p), ("fine_KU", C.c_void_p),
+                ("bulk_alpha", C.c_void_p)]
 
 
 class _MlpConfig(C.Structure):
@@ -146,6 +147,9 @@ class Config:
     mlp_tol: float = 1.0e-3
     mlp_period: int = 100
     semi_implicit: int = 0
+    vof: int = 0
+    rho_f2: float = 1.2
+    mu_f2: float = 1.8e-5
 
     def to_c(self):
         c = _Config()
@@ -158,6 +162,7 @@ class Config:
         c.advect, c.dt, c.max_particles = int(self.advect), float(self.dt), int(self.max_particles)
         c.mlp_tol, c.mlp_period = float(self.mlp_tol), int(self.mlp_period)
         c.semi_implicit = int(self.semi_implicit)
+        c.vof, c.rho_f2, c.mu_f2 = int(self.vof), float(self.rho_f2), float(self.mu_f2)
         return c
 
     @property
@@ -211,7 +216,7 @@ def couple_step(h, inputs: dict, outputs: dict, stream=None):
     i = _Inputs()
     i.n = int(inputs["n"])
     i.step = int(inputs.get("step", 0))
-    for k in ("pos", "vel", "diam", "fine_u", "fine_v", "fine_w", "fine_p", "uf_given"):
+    for k in ("pos", "vel", "diam", "fine_u", "fine_v", "fine_w", "fine_p", "uf_given", "fine_alpha"):
         setattr(i, k, _ptr(inputs.get(k)))
     o = _Outputs()
     for k, _ in _Outputs._fields_:
@@ -268,6 +273,7 @@ def alloc_outputs(cfg: Config, n: int, device="cuda", beta=True, uf=False):
         "bulk_KU": torch.empty((3, nb[2], nb[1], nb[0]), dtype=dt, **e) if semi else None,
         "fine_K": torch.empty((nf[2], nf[1], nf[0]), dtype=dt, **e) if semi else None,
         "fine_KU": torch.empty((3, nf[2], nf[1], nf[0]), dtype=dt, **e) if semi else None,
+        "bulk_alpha": torch.empty((nb[2], nb[1], nb[0]), dtype=dt, **e) if cfg.vof else None,
     }
 
 
@@ -281,21 +287,23 @@ def diag_dict(diag_tensor):
 
 class Coupler:
     """A handle plus its outputs.  ``step`` takes device tensors of the handle's
-    dtype: pos [n,3], vel [n,3], diam [n], fine fields [nfz,nfy,nfx]."""
+    dtype: pos [n,3], vel [n,3], diam [n], fine fields [nfz,nfy,nfx] (and the
+    fine liquid fraction ``alpha`` when the configuration has ``vof``)."""
 
     def __init__(self, cfg: Config):
         self.cfg = cfg
         self.h = couple_init(cfg)
         self.out = None
 
-    def step(self, pos, vel, diam, fine, uf_given=None, out=None, beta=True, stream=None, step=0, uf=False):
+    def step(self, pos, vel, diam, fine, uf_given=None, out=None, beta=True, stream=None, step=0, uf=False,
+             alpha=None):
         n = pos.shape[0]
         if out is None:
             if (self.out is None or self.out["drag"].shape[0] != n or (uf and self.out["uf"] is None)):
                 self.out = alloc_outputs(self.cfg, n, device=pos.device, beta=beta, uf=uf)
             out = self.out
         inputs = {"n": n, "pos": pos, "vel": vel, "diam": diam, "fine_u": fine[0], "fine_v": fine[1],
-                  "fine_w": fine[2], "fine_p": fine[3], "uf_given": uf_given, "step": step}
+                  "fine_w": fine[2], "fine_p": fine[3], "uf_given": uf_given, "step": step, "fine_alpha": alpha}
         couple_step(self.h, inputs, out, stream=stream)
         return out
 

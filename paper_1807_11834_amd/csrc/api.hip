@@ -85,6 +85,9 @@ static std::string validate(const couple_config *c) {
         if (c->mlp_period < 1) return "mlp_period must be >= 1";
     }
     if (!(c->semi_implicit == 0 || c->semi_implicit == 1)) return "semi_implicit must be 0 or 1";
+    if (!(c->vof == 0 || c->vof == 1)) return "vof must be 0 or 1";
+    if (c->vof && !(std::isfinite(c->rho_f2) && c->rho_f2 > 0.0)) return "rho_f2 must be finite and > 0";
+    if (c->vof && !(std::isfinite(c->mu_f2) && c->mu_f2 > 0.0)) return "mu_f2 must be finite and > 0";
     if (!(c->advect == 0 || c->advect == 1)) return "advect must be 0 or 1";
     if (c->advect && !(std::isfinite(c->dt) && c->dt >= 0.0)) return "dt must be finite and >= 0";
     if (c->max_particles < 0 || c->max_particles >= (int64_t(1) << 31) - 1)
@@ -183,6 +186,11 @@ static int step_impl(couple_handle *h, const couple_inputs *in, couple_outputs *
     a.vel_source = c.vel_source;
     a.advect = c.advect;
     a.semi = c.semi_implicit;
+    a.vof = c.vof;
+    a.rho_f2 = (T)c.rho_f2;
+    a.mu_f2 = (T)c.mu_f2;
+    a.fine_alpha = (const T *)in->fine_alpha;
+    a.alpha = (T *)out->bulk_alpha;
     a.dt = (T)c.dt;
     a.rho_f = (T)c.rho_f;
     a.mu_f = (T)c.mu_f;
@@ -258,6 +266,8 @@ extern "C" int couple_step(couple_handle *h, const couple_inputs *in, couple_out
         return fail(h, COUPLE_EINVAL, "couple_step: NULL grid output");
     if (c.semi_implicit && (!out->bulk_K || !out->bulk_KU || !out->fine_K || !out->fine_KU))
         return fail(h, COUPLE_EINVAL, "couple_step: semi_implicit needs bulk_K, bulk_KU, fine_K and fine_KU");
+    if (c.vof && (!in->fine_alpha || !out->bulk_alpha))
+        return fail(h, COUPLE_EINVAL, "couple_step: vof needs fine_alpha and bulk_alpha");
     if (in->n > 0) {
         if (!in->pos || !in->vel || !in->diam) return fail(h, COUPLE_EINVAL, "couple_step: NULL particle input");
         if (!out->drag || !out->cell || !out->perm) return fail(h, COUPLE_EINVAL, "couple_step: NULL particle output");

@@ -60,19 +60,23 @@ template <typename T> struct StepArgs {
     int vel_source;    // 0 fine, 1 bulk, 2 given, 3 learned surrogate (+ fine fallback)
     int advect;
     int semi;          // semi-implicit source fields K, KU
+    int vof;           // two-fluid drag: (rho_f, mu_f) mixed with (rho_f2, mu_f2) by alpha
     T dt, rho_f, mu_f, rho_p, eps_min;
+    T rho_f2, mu_f2;
     float phi_fp64;    // FP32 modes: FP64 void fraction above this particle solid fraction
     // inputs
     T *pos, *vel;
     const T *diam;
     const T *fine[4];      // u, v, w, p
     const T *uf_given;     // [n][3]
+    const T *fine_alpha;   // [nfine] liquid volume fraction (vof)
     // outputs
     T *drag, *beta;
     const int32_t *perm, *start;
     T *phi, *F, *U, *P, *G;  // bulk
     T *fine_eps, *fine_F;    // fine
     T *K, *KU;               // bulk semi-implicit coefficient [ncell] and beta u_p source [3][ncell]
+    T *alpha;                // bulk liquid volume fraction [ncell] (vof)
     T *fine_K, *fine_KU;     // the same prolonged to the fine grid
     double *diag;
     // scratch

@@ -16,6 +16,8 @@
 //                  velocity, void fraction from a haloed copy of phi), so the
 //                  fine lookup costs no extra pass over the fine grid.
 //   k_sample       the same sampling for the bulk and given velocity sources.
+//   k_restrict_alpha  two-fluid drag: bulk liquid fraction, average of the fine
+//                  children.
 //   k_drag         drag and explicit Euler advection in input order (coalesced);
 //                  with the semi-implicit split also (beta, beta u_p).
 //   deposit force  (deposit.hip), with the bulk pressure gradient; then the
@@ -162,6 +164,38 @@ __global__ __launch_bounds__(kBlock) void k_restrict(StepArgs<T> a) {
             }
         }
     }
+}
+
+// Restriction of the liquid volume fraction (two-fluid drag): the bulk alpha is
+// the average of the r^3 fine children (the volume average that defines alpha),
+// summed per fine child plane and then the planes in order, as for U and P.
+template <typename T, int R, bool KAHAN>
+__global__ __launch_bounds__(kBlock) void k_restrict_alpha(StepArgs<T> a) {
+    const Geo<T> &g = a.g;
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t c = tile * kBlock + threadIdx.x;
+    if (c >= g.ncell) return;
+    int cx, cy, cz;
+    decode_cell(c, g.nb, cx, cy, cz);
+    const int64_t nfx = g.nf[0], nfxy = (int64_t)g.nf[0] * g.nf[1];
+    const T *__restrict__ q = a.fine_alpha + (int64_t)R * cz * nfxy + (int64_t)R * cy * nfx + (int64_t)R * cx;
+    Row<T, R> rows[R][R];
+#pragma unroll
+    for (int lz = 0; lz < R; ++lz)
+#pragma unroll
+        for (int ly = 0; ly < R; ++ly) rows[lz][ly] = load_row<T, R>(q + lz * nfxy + ly * nfx);
+    Acc<T, KAHAN> acc;
+#pragma unroll
+    for (int lz = 0; lz < R; ++lz) {
+        Acc<T, KAHAN> plane;
+#pragma unroll
+        for (int ly = 0; ly < R; ++ly)
+#pragma unroll
+            for (int lx = 0; lx < R; ++lx) plane.add(rows[lz][ly].v[lx]);
+        acc.add(plane.s);
+        if constexpr (KAHAN) acc.add(-plane.c);
+    }
+    a.alpha[c] = acc.s * (T(1) / T(R * R * R));
 }
 
 // Restriction with the fine-grid lookup, tiled in bricks of 8 x 4 x 2 bulk
@@ -406,16 +440,28 @@ __global__ __launch_bounds__(kBlock) void k_drag(StepArgs<T> a) {
             e = a.eps_min;
             clamped = 1;
         }
+        // fluid density and viscosity at the particle: fluid 1's, or with the
+        // two-fluid drag the mixture by the liquid fraction interpolated from
+        // the restricted alpha
+        T rho = a.rho_f, mu = a.mu_f;
+        if (a.vof) {
+            const Axis<T> bx = cic_axis(xs[0], g.sb[0], g.nb[0]);
+            const Axis<T> by = cic_axis(xs[1], g.sb[1], g.nb[1]);
+            const Axis<T> bz = cic_axis(xs[2], g.sb[2], g.nb[2]);
+            const T al = trilin(a.alpha, bx, by, bz, g.nb[0], (int64_t)g.nb[0] * g.nb[1]);
+            rho = a.rho_f * al + a.rho_f2 * (T(1) - al);
+            mu = a.mu_f * al + a.mu_f2 * (T(1) - al);
+        }
         T chi = T(3.7);
         if (mag > T(0)) {
-            const T re = a.rho_f * e * d * mag / a.mu_f;
+            const T re = rho * e * d * mag / mu;
             const T l = T(1.5) - dlog10(re);
             chi = T(3.7) - T(0.65) * dexp(-l * l * T(0.5));
         }
         const T vfac = dpow(e, T(2) - chi);
-        const T sq = T(0.63) * dsqrt(mag) + T(4.8) * dsqrt(a.mu_f / (a.rho_f * e * d));
+        const T sq = T(0.63) * dsqrt(mag) + T(4.8) * dsqrt(mu / (rho * e * d));
         const T area = T(kPi / 4.0) * d * d;
-        const T beta = T(0.5) * a.rho_f * area * vfac * (sq * sq);
+        const T beta = T(0.5) * rho * area * vfac * (sq * sq);
         const T Fs[3] = {beta * ur0, beta * ur1, beta * ur2};
         for (int k = 0; k < 3; ++k) a.drag[3 * p + k] = Fs[k];
         if (a.beta) a.beta[p] = beta;
@@ -657,6 +703,10 @@ static void launch_grid_stages(const StepArgs<T> &a, hipStream_t st) {
         hipLaunchKernelGGL((k_restrict<T, R, KAHAN>), dim3(cb), dim3(kBlock), 0, st, a);
         if (a.n > 0) a.mk->mark("sample", st);
         if (a.n > 0) hipLaunchKernelGGL(k_sample<T>, dim3(pb), dim3(kBlock), 0, st, a);
+    }
+    if (a.vof) {
+        a.mk->mark("restrict_alpha", st);
+        hipLaunchKernelGGL((k_restrict_alpha<T, R, KAHAN>), dim3(cb), dim3(kBlock), 0, st, a);
     }
     if (a.n > 0) a.mk->mark("drag", st);
     if (a.n > 0) hipLaunchKernelGGL(k_drag<T>, dim3(pb), dim3(kBlock), 0, st, a);

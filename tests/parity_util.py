@@ -99,7 +99,7 @@ def to_dev(a, torch, dev, dtype=None):
     return t.to(dev)
 
 
-def run_gpu(cpl, torch, cfg, pos, vel, diam, fine, uf_given=None, dev="cuda:0"):
+def run_gpu(cpl, torch, cfg, pos, vel, diam, fine, uf_given=None, dev="cuda:0", alpha=None):
     """One step on the GPU; returns numpy copies of every output (+ advected state)."""
     dt = cfg.dtype
     P = to_dev(pos, torch, dev, dt)
@@ -107,8 +107,9 @@ def run_gpu(cpl, torch, cfg, pos, vel, diam, fine, uf_given=None, dev="cuda:0"):
     D = to_dev(diam, torch, dev, dt)
     Fn = [to_dev(f, torch, dev, dt) for f in fine]
     UG = None if uf_given is None else to_dev(uf_given, torch, dev, dt)
+    AL = None if alpha is None else to_dev(alpha, torch, dev, dt)
     c = cpl.Coupler(cfg)
-    out = c.step(P, V, D, Fn, uf_given=UG)
+    out = c.step(P, V, D, Fn, uf_given=UG, alpha=AL)
     torch.cuda.synchronize()
     res = {k: (v.cpu().numpy() if v is not None else None) for k, v in out.items()}
     res["diag_d"] = cpl.diag_dict(out["diag"])

@@ -49,9 +49,10 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(couple_config), offsetof(couple_config, rho_f),
          offsetof(couple_config, deposit), offsetof(couple_config, dt), offsetof(couple_config, max_particles),
          offsetof(couple_config, mlp_tol), offsetof(couple_config, mlp_period), offsetof(couple_config, semi_implicit));
-  printf("%zu %zu %zu\\n", sizeof(couple_inputs), offsetof(couple_inputs, uf_given), offsetof(couple_inputs, step));
-  printf("%zu %zu %zu %zu\\n", sizeof(couple_outputs), offsetof(couple_outputs, diag), offsetof(couple_outputs, uf),
-         offsetof(couple_outputs, fine_KU));
+  printf("%zu %zu %zu %zu %zu\\n", sizeof(couple_inputs), offsetof(couple_inputs, uf_given), offsetof(couple_inputs, step),
+         offsetof(couple_inputs, fine_alpha), offsetof(couple_config, mu_f2));
+  printf("%zu %zu %zu %zu %zu\\n", sizeof(couple_outputs), offsetof(couple_outputs, diag), offsetof(couple_outputs, uf),
+         offsetof(couple_outputs, fine_KU), offsetof(couple_outputs, bulk_alpha));
   printf("%zu %zu %zu\\n", sizeof(couple_mlp_config), offsetof(couple_mlp_config, lr), offsetof(couple_mlp_config, eps));
   printf("%d %d %d %d\\n", COUPLE_DIAG_LEN, COUPLE_VEL_MLP, COUPLE_MLP_NFEAT, COUPLE_MLP_NPARAM);
   return 0; }
@@ -64,10 +65,11 @@ int main(void) {
     assert a == [C.sizeof(K), K.rho_f.offset, K.deposit.offset, K.dt.offset, K.max_particles.offset,
                  K.mlp_tol.offset, K.mlp_period.offset, K.semi_implicit.offset]
     b = [int(x) for x in lines[1].split()]
-    assert b == [C.sizeof(cpl._Inputs), cpl._Inputs.uf_given.offset, cpl._Inputs.step.offset]
+    assert b == [C.sizeof(cpl._Inputs), cpl._Inputs.uf_given.offset, cpl._Inputs.step.offset,
+                 cpl._Inputs.fine_alpha.offset, cpl._Config.mu_f2.offset]
     c = [int(x) for x in lines[2].split()]
     assert c == [C.sizeof(cpl._Outputs), cpl._Outputs.diag.offset, cpl._Outputs.uf.offset,
-                 cpl._Outputs.fine_KU.offset]
+                 cpl._Outputs.fine_KU.offset, cpl._Outputs.bulk_alpha.offset]
     d = [int(x) for x in lines[3].split()]
     assert d == [C.sizeof(cpl._MlpConfig), cpl._MlpConfig.lr.offset, cpl._MlpConfig.eps.offset]
     e = [int(x) for x in lines[4].split()]
@@ -81,6 +83,7 @@ BAD = [
     dict(nb=(2048, 2048, 1024)), dict(nb=(40000, 2, 2)),
     dict(vel_source=3, precision=0), dict(vel_source=3, mlp_period=0), dict(vel_source=3, mlp_tol=-1.0),
     dict(vel_source=3, mlp_tol=float("nan")), dict(semi_implicit=2), dict(semi_implicit=-1),
+    dict(vof=2), dict(vof=1, rho_f2=0.0), dict(vof=1, mu_f2=float("inf")),
 ]
 
 

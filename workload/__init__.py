@@ -266,6 +266,38 @@ def fine_fields_torch(w: Workload, device, dtype=None):
     return tuple(out)
 
 
+def _alpha(grid: Grid, xp, x, y, z):
+    """Liquid volume fraction of a smooth, tilted free surface: liquid below
+    z_s(x, y) = L_z (0.6 + 0.1 x / L_x - 0.05 y / L_y), a tanh profile two fine
+    cells thick: alpha = (1 - tanh((z - z_s) / (2 h_z))) / 2."""
+    L = grid.box
+    zs = L[2] * (0.6 + 0.1 * x / L[0] - 0.05 * y / L[1])
+    delta = 2.0 * L[2] / grid.nf[2]
+    return 0.5 * (1.0 - xp.tanh((z - zs) / delta))
+
+
+def fine_alpha(w: Workload, dtype=None):
+    """Host (numpy) fine liquid fraction (nfz, nfy, nfx), for the two-fluid drag."""
+    dt = dtype or (np.float64 if w.precision == "fp64" else np.float32)
+    g = w.grid
+    xs = [g.fine_centres_1d(a) for a in range(3)]
+    a = _alpha(g, np, xs[0][None, None, :], xs[1][None, :, None], xs[2][:, None, None])
+    return np.ascontiguousarray(a.astype(dt))
+
+
+def fine_alpha_torch(w: Workload, device, dtype=None):
+    """The same field built on a torch device (FP64 there, then cast; equal to
+    :func:`fine_alpha` up to the last bit of tanh)."""
+    import torch
+    dt = dtype or (torch.float64 if w.precision == "fp64" else torch.float32)
+    g = w.grid
+    xs = [torch.from_numpy(g.fine_centres_1d(a)).to(device) for a in range(3)]
+    out = torch.empty((g.nf[2], g.nf[1], g.nf[0]), dtype=dt, device=device)
+    for k in range(g.nf[2]):   # one z-plane at a time: bounded FP64 temporaries
+        out[k] = _alpha(g, torch, xs[0][None, :], xs[1][:, None], xs[2][k]).to(dt)
+    return out
+
+
 def fine_values_at(w: Workload, fidx, dtype=None):
     """Fine-field values (u, v, w, p) at flat fine indices ``fidx`` (host, numpy).
 
