@@ -74,9 +74,10 @@ def lib():
         L.orc_prolong_at.argtypes = [P, P, I, I, I64, P, P]
         L.orc_advect.argtypes = [I64, P, P, P, P, D, D, P, I]
         L.orc_particle_volumes.argtypes = [I64, P, P]
+        L.orc_remap.argtypes = [P, P, P, P, P, P]
         for name in ("orc_deposit_volume", "orc_deposit_force", "orc_deposit_semi", "orc_gather_eps", "orc_restrict",
                      "orc_gradient", "orc_interp", "orc_prolong", "orc_prolong_at", "orc_advect",
-                     "orc_particle_volumes"):
+                     "orc_particle_volumes", "orc_remap"):
             getattr(L, name).restype = None
         _lib = L
     return _lib
@@ -227,6 +228,22 @@ def advect(pos, vel, diam, force, rho_p, dt, box, prec32=False):
     lib().orc_advect(pos.shape[0], _p(pos), _p(vel), _p(_f64(diam)), _p(_f64(force).reshape(-1, 3)),
                      float(rho_p), float(dt), _p(_f64(box)), int(prec32))
     return pos, vel
+
+
+def remap(src, src_nodes, dst_nodes):
+    """Volume-weighted transfer of a cell field between two rectilinear grids over
+    the same box.  ``src_nodes`` / ``dst_nodes`` are three 1-D arrays of node
+    coordinates (x, y, z); ``src`` is (nz, ny, nx) of the sender grid.  Returns
+    the receiver field (nz, ny, nx)."""
+    ns = np.array([len(a) - 1 for a in src_nodes], dtype=np.int32)
+    nd = np.array([len(a) - 1 for a in dst_nodes], dtype=np.int32)
+    sn = np.concatenate([_f64(a) for a in src_nodes])
+    dn = np.concatenate([_f64(a) for a in dst_nodes])
+    src = _f64(src).reshape(-1)
+    assert src.shape[0] == int(np.prod(ns))
+    out = np.empty(int(np.prod(nd)), dtype=np.float64)
+    lib().orc_remap(_p(ns), _p(sn), _p(nd), _p(dn), _p(src), _p(out))
+    return out.reshape(nd[2], nd[1], nd[0])
 
 
 def particle_volumes(diam):

@@ -23,6 +23,8 @@
  *   semi         deposited drag coefficient and beta-weighted particle velocity,
  *                the semi-implicit form of the momentum source (Sec. 2.5)
  *   prolong      bulk -> fine "particle related fields" transfer (Fig. 1)
+ *   remap        volume-weighted transfer between two grids that need not be
+ *                nested (the sender -> receiver interpolation of Sec. 2.3)
  *   advect       explicit Euler update of Eq. DEM_EQUATIONS with drag only
  *
  * All arithmetic is FP64, except where a floating-point comparison decides an
@@ -557,6 +559,49 @@ void orc_advect(int64_t n, double *pos, double *vel, const double *diam, const d
             vel[3 * p + a] = un;
         }
     }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Grid-to-grid interpolation between two grids that need not be nested      */
+/* (the sender -> receiver map of Sec. 2.3, static for non-deforming grids).  */
+/* Both grids are rectilinear and cell-centred over the same box; axis a of a */
+/* grid has n[a] cells between nodes x_a[0] < ... < x_a[n[a]]; the nodes of  */
+/* the three axes are stored one after the other.  The receiver value is the  */
+/* volume-weighted average of the sender cells it overlaps:                   */
+/*   dst_c = (sum_f |f intersect c| src_f) / |c|.                             */
+/* ------------------------------------------------------------------------- */
+static double overlap1(double a0, double a1, double b0, double b1)
+{
+    double lo = a0 > b0 ? a0 : b0, hi = a1 < b1 ? a1 : b1;
+    return hi > lo ? hi - lo : 0.0;
+}
+
+void orc_remap(const int ns[3], const double *src_nodes, const int nd[3], const double *dst_nodes,
+               const double *src, double *dst)
+{
+    const double *xs[3], *xd[3];
+    xs[0] = src_nodes; xs[1] = xs[0] + ns[0] + 1; xs[2] = xs[1] + ns[1] + 1;
+    xd[0] = dst_nodes; xd[1] = xd[0] + nd[0] + 1; xd[2] = xd[1] + nd[1] + 1;
+    for (int k = 0; k < nd[2]; ++k)
+        for (int j = 0; j < nd[1]; ++j)
+            for (int i = 0; i < nd[0]; ++i) {
+                double acc = 0.0;
+                for (int fk = 0; fk < ns[2]; ++fk) {
+                    double oz = overlap1(xd[2][k], xd[2][k + 1], xs[2][fk], xs[2][fk + 1]);
+                    if (oz == 0.0) continue;
+                    for (int fj = 0; fj < ns[1]; ++fj) {
+                        double oy = overlap1(xd[1][j], xd[1][j + 1], xs[1][fj], xs[1][fj + 1]);
+                        if (oy == 0.0) continue;
+                        for (int fi = 0; fi < ns[0]; ++fi) {
+                            double ox = overlap1(xd[0][i], xd[0][i + 1], xs[0][fi], xs[0][fi + 1]);
+                            if (ox == 0.0) continue;
+                            acc += ox * oy * oz * src[lin3(fi, fj, fk, ns)];
+                        }
+                    }
+                }
+                double vol = (xd[0][i + 1] - xd[0][i]) * (xd[1][j + 1] - xd[1][j]) * (xd[2][k + 1] - xd[2][k]);
+                dst[lin3(i, j, k, nd)] = acc / vol;
+            }
 }
 
 /* Particle volumes V_p = pi d^3 / 6 (for the conservation diagnostics). */
