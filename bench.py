@@ -387,6 +387,52 @@ def vof_leg(args, w, cfg, pos, vel, diam, fine, plain_ms, n, g, fsz, dev):
             "restrict_alpha_frac_hbm": round(ab / (ra * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4) if ra else None}
 
 
+def remap_leg(args, g, fine, fsz, dev):
+    """Grid-to-grid transfer between non-nested grids at the bed's size: the four
+    fine fields (u, v, w, p; 512 x 512 x 1024 over 1 x 1 x 2) to a 192 x 192 x 384
+    grid (ratio 8/3, sender cells straddle receiver faces) and the four coarse
+    fields back.  Per direction: average time of one four-field transfer and the
+    algorithmic bandwidth (sender fields read once + receiver fields written
+    once) against the HBM peak."""
+    import torch
+    import paper_1807_11834_amd as cpl
+    box = g.box
+    nc = (192, 192, 384)
+    nodes = lambda n: [np.linspace(0.0, box[a], n[a] + 1) for a in range(3)]
+    prec = cpl.COUPLE_FP64 if fsz == 8 else cpl.COUPLE_FP32_KAHAN
+    down, up = cpl.Remap(nodes(g.nf), nodes(nc), prec), cpl.Remap(nodes(nc), nodes(g.nf), prec)
+    try:
+        src = torch.stack(fine)
+        coarse = torch.empty((4, nc[2], nc[1], nc[0]), dtype=src.dtype, device=dev)
+        back = torch.empty_like(src)
+        res = {}
+        for name, r, a, b, nsrc, ndst in (("fine_to_nonnested", down, src, coarse, g.n_fine, int(np.prod(nc))),
+                                          ("nonnested_to_fine", up, coarse, back, int(np.prod(nc)), g.n_fine)):
+            for _ in range(max(args.warmup, 1)):
+                r.apply(a, b)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(args.steps):
+                r.apply(a, b)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.steps
+            ab = 4 * fsz * (nsrc + ndst)
+            res[name] = {"ms_per_4_fields": round(ms, 4), "alg_GBps": round(ab / (ms * 1e-3) / 1e9, 1),
+                         "frac_hbm": round(ab / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
+        res["receiver_grid"] = list(nc)
+        res["map_nnz_3d"] = down.info()[1]
+        del src, coarse, back
+    finally:
+        down.close()
+        up.close()
+    torch.cuda.empty_cache()
+    print(f"# non-nested transfer: {res}", file=sys.stderr, flush=True)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -401,6 +447,7 @@ def main():
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned-surrogate path")
     ap.add_argument("--no-semi", action="store_true", help="skip the semi-implicit split variant")
     ap.add_argument("--no-vof", action="store_true", help="skip the two-fluid drag variant")
+    ap.add_argument("--no-remap", action="store_true", help="skip the non-nested grid transfer")
     ap.add_argument("--traffic-summary", metavar="DIR",
                     help="print the JSON summary of the FETCH_SIZE/WRITE_SIZE runs under DIR and exit")
     ap.add_argument("--trace-summary", metavar="CSV",
@@ -526,6 +573,8 @@ def main():
         rec["semi_implicit"] = semi_leg(args, cfg, pos, vel, diam, fine, ms_step, n, g, fsz, dev)
     if not args.no_vof:
         rec["two_fluid_drag"] = vof_leg(args, w, cfg, pos, vel, diam, fine, ms_step, n, g, fsz, dev)
+    if not args.no_remap:
+        rec["nonnested_transfer"] = remap_leg(args, g, fine, fsz, dev)
     if not args.no_mlp:
         print("# surrogate: pairs, training, timing ...", file=sys.stderr, flush=True)
         rec["mlp_path"] = mlp_leg(args, w, cfg, pos, vel, diam, fine, ms_step, kernels, dev)

@@ -114,11 +114,17 @@ def _load():
         "couple_mlp_train_step": [P, P, P, I64, P, I64, P, P],
         "couple_mlp_features": [C.POINTER(_Config), I64, P, P, P, P, P, P, P, I64, P, P, P, P],
         "couple_set_mlp": [P, P],
+        "couple_remap_init": [P, P, P, P, C.c_int32, C.POINTER(C.c_void_p)],
+        "couple_remap_apply": [P, P, P, C.c_int32, P],
+        "couple_remap_info": [P, P, P],
+        "couple_remap_free": [P],
     }
     for name, args in sigs.items():
         f = getattr(L, name)
         f.argtypes = args
         f.restype = I
+    L.couple_remap_last_error.argtypes = [P]
+    L.couple_remap_last_error.restype = C.c_char_p
     L.couple_mlp_last_error.argtypes = [P]
     L.couple_mlp_last_error.restype = C.c_char_p
     return L
@@ -423,6 +429,66 @@ class Mlp:
         if self.m is not None:
             couple_mlp_free(self.m)
             self.m = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---- grid-to-grid transfer between non-nested grids (include/couple_remap.h) ----
+
+def _rcheck(code, r):
+    if code != COUPLE_OK:
+        s = _lib.couple_remap_last_error(r)
+        raise CoupleError(code, s.decode() if s else "")
+
+
+class Remap:
+    """Volume-weighted transfer from a sender grid to a receiver grid over the
+    same box.  ``src_nodes`` / ``dst_nodes``: three 1-D arrays of node
+    coordinates (x, y, z) of rectilinear cell-centred grids."""
+
+    def __init__(self, src_nodes, dst_nodes, precision=COUPLE_FP32_KAHAN):
+        import numpy as np
+        self.ns = [len(a) - 1 for a in src_nodes]
+        self.nd = [len(a) - 1 for a in dst_nodes]
+        self.precision = int(precision)
+        ns, pns = _host(self.ns, "int32")
+        nd, pnd = _host(self.nd, "int32")
+        sn, psn = _host(np.concatenate([np.asarray(a, np.float64) for a in src_nodes]), "float64")
+        dn, pdn = _host(np.concatenate([np.asarray(a, np.float64) for a in dst_nodes]), "float64")
+        r = C.c_void_p()
+        _rcheck(_lib.couple_remap_init(pns, psn, pnd, pdn, self.precision, C.byref(r)), None)
+        self.r = r
+
+    @property
+    def dtype(self):
+        return torch.float64 if self.precision == COUPLE_FP64 else torch.float32
+
+    def apply(self, src, dst=None, stream=None):
+        """src: device tensor [..., nz, ny, nx] of the sender grid (leading dims =
+        fields); returns dst [..., nz', ny', nx'] of the receiver grid."""
+        nsrc = self.ns[0] * self.ns[1] * self.ns[2]
+        assert src.is_contiguous() and src.dtype == self.dtype and src.numel() % nsrc == 0
+        nf = src.numel() // nsrc
+        lead = tuple(src.shape[:-3]) if src.dim() > 3 else ()
+        if dst is None:
+            dst = torch.empty(lead + (self.nd[2], self.nd[1], self.nd[0]), dtype=self.dtype, device=src.device)
+        _rcheck(_lib.couple_remap_apply(self.r, _ptr(src), _ptr(dst), nf, _stream(stream)), self.r)
+        return dst
+
+    def info(self):
+        ax = (C.c_int64 * 3)()
+        tot = C.c_int64(0)
+        _rcheck(_lib.couple_remap_info(self.r, ax, C.byref(tot)), self.r)
+        return list(ax), int(tot.value)
+
+    def close(self):
+        if getattr(self, "r", None) is not None:
+            _lib.couple_remap_free(self.r)
+            self.r = None
 
     def __del__(self):
         try:

@@ -1,0 +1,266 @@
+// remap.hip -- volume-weighted transfer between two rectilinear grids that need
+// not be nested (see include/couple_remap.h).
+//
+// The overlap map |f intersect c| / |c| factors over the axes, so it is kept as
+// three 1-D factors: for receiver index i along axis a, the overlapping sender
+// indices are the contiguous range first_a[i] .. first_a[i] + cnt_a[i] - 1 with
+// weights w_a[off_a[i] + k] = overlap length / receiver cell length.  Built on
+// the host in FP64 once per grid pair; applied on the device with one thread per
+// receiver cell (x fastest, so a wave reads neighbouring sender rows), summing
+// the sender cells in raster order (z, then y, then x), compensated in the FP32
+// Kahan mode.  Storing the 3-D map as CSR would read more bytes of indices and
+// weights than of field values; the factors are a few KB and stay in cache.
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "couple_remap.h"
+
+using namespace cpl;
+
+namespace {
+
+struct Axis1D {
+    int32_t *first = nullptr;   // [nd] first overlapping sender index
+    int32_t *cnt = nullptr;     // [nd] number of overlapping sender cells
+    int32_t *off = nullptr;     // [nd] offset of the weights
+    void *w = nullptr;          // [nnz] T weights
+    int64_t nnz = 0;
+};
+
+template <typename T> struct RemapArgs {
+    const int32_t *first[3], *cnt[3], *off[3];
+    const T *w[3];
+    int ns[3], nd[3];
+    int64_t nsrc, ndst;
+};
+
+template <typename T, bool KAHAN>
+__global__ __launch_bounds__(kBlock) void k_remap(RemapArgs<T> r, const T *__restrict__ src, T *__restrict__ dst) {
+    const int64_t nblk = gridDim.x;
+    const int64_t c = xcd_tile(blockIdx.x, nblk) * kBlock + threadIdx.x;
+    if (c >= r.ndst) return;
+    const T *__restrict__ s = src + (int64_t)blockIdx.y * r.nsrc;
+    const int i = (int)(c % r.nd[0]), j = (int)((c / r.nd[0]) % r.nd[1]),
+              k = (int)(c / ((int64_t)r.nd[0] * r.nd[1]));
+    const int fx = r.first[0][i], nx = r.cnt[0][i], ox = r.off[0][i];
+    const int fy = r.first[1][j], ny = r.cnt[1][j], oy = r.off[1][j];
+    const int fz = r.first[2][k], nz = r.cnt[2][k], oz = r.off[2][k];
+    const int64_t sx = r.ns[0], sxy = (int64_t)r.ns[0] * r.ns[1];
+    Acc<T, KAHAN> acc;
+    for (int kz = 0; kz < nz; ++kz) {
+        const T wz = r.w[2][oz + kz];
+        for (int ky = 0; ky < ny; ++ky) {
+            const T wyz = wz * r.w[1][oy + ky];
+            const T *__restrict__ row = s + (int64_t)(fz + kz) * sxy + (int64_t)(fy + ky) * sx + fx;
+            for (int kx = 0; kx < nx; ++kx) acc.add((wyz * r.w[0][ox + kx]) * row[kx]);
+        }
+    }
+    dst[(int64_t)blockIdx.y * r.ndst + c] = acc.s;
+}
+
+}  // namespace
+
+struct couple_remap {
+    int32_t ns[3], nd[3];
+    int32_t precision;
+    Axis1D ax[3];
+    std::string err;
+};
+
+static thread_local std::string g_remap_init_err;
+
+static int rfail(couple_remap *r, int code, const std::string &msg) {
+    if (r) r->err = msg;
+    else g_remap_init_err = msg;
+    return code;
+}
+
+static void remap_release(couple_remap *r) {
+    for (int a = 0; a < 3; ++a) {
+        void *p[] = {r->ax[a].first, r->ax[a].cnt, r->ax[a].off, r->ax[a].w};
+        for (void *q : p)
+            if (q) (void)hipFree(q);
+        r->ax[a] = Axis1D{};
+    }
+}
+
+static std::string check_grid(const int32_t n[3], const double *nodes, const char *name) {
+    int64_t cells = 1;
+    const double *x = nodes;
+    for (int a = 0; a < 3; ++a) {
+        if (n[a] < 1) return std::string(name) + ": cells per axis must be >= 1";
+        cells *= n[a];
+        if (cells >= (int64_t(1) << 31)) return std::string(name) + ": too many cells (must be < 2^31)";
+        for (int i = 0; i <= n[a]; ++i)
+            if (!std::isfinite(x[i])) return std::string(name) + ": node coordinates must be finite";
+        for (int i = 0; i < n[a]; ++i)
+            if (!(x[i + 1] > x[i])) return std::string(name) + ": node coordinates must increase strictly";
+        x += n[a] + 1;
+    }
+    return "";
+}
+
+// 1-D factor along one axis: receiver cells [xd_i, xd_{i+1}] against sender
+// cells [xs_j, xs_{j+1}], weights = overlap length / receiver length.
+static void build_axis(const double *xs, int ns, const double *xd, int nd, std::vector<int32_t> &first,
+                       std::vector<int32_t> &cnt, std::vector<int32_t> &off, std::vector<double> &w) {
+    first.assign(nd, 0);
+    cnt.assign(nd, 0);
+    off.assign(nd, 0);
+    w.clear();
+    int j = 0;
+    for (int i = 0; i < nd; ++i) {
+        const double lo = xd[i], hi = xd[i + 1], len = hi - lo;
+        while (j < ns - 1 && xs[j + 1] <= lo) ++j;   // first sender cell ending after lo
+        off[i] = (int32_t)w.size();
+        first[i] = j;
+        int c = 0;
+        for (int jj = j; jj < ns && xs[jj] < hi; ++jj) {
+            const double ov = std::fmin(hi, xs[jj + 1]) - std::fmax(lo, xs[jj]);
+            if (ov <= 0.0) {
+                if (c == 0) first[i] = jj + 1;   // touches only: not part of the range
+                continue;
+            }
+            w.push_back(ov / len);
+            ++c;
+        }
+        cnt[i] = c;
+    }
+}
+
+template <typename X> static bool dalloc_copy(X **p, const void *host, size_t bytes) {
+    void *q = nullptr;
+    if (hipMalloc(&q, bytes ? bytes : 16) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return false;
+    }
+    if (bytes && hipMemcpy(q, host, bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(q);
+        *p = nullptr;
+        return false;
+    }
+    *p = static_cast<X *>(q);
+    return true;
+}
+
+extern "C" int couple_remap_init(const int32_t src_n[3], const double *src_nodes, const int32_t dst_n[3],
+                                 const double *dst_nodes, int32_t precision, couple_remap **out) {
+    if (!out) return rfail(nullptr, COUPLE_EINVAL, "couple_remap_init: NULL output");
+    *out = nullptr;
+    if (!src_n || !src_nodes || !dst_n || !dst_nodes) return rfail(nullptr, COUPLE_EINVAL, "couple_remap_init: NULL grid");
+    if (!(precision == COUPLE_FP64 || precision == COUPLE_FP32_KAHAN || precision == COUPLE_FP32_NAIVE))
+        return rfail(nullptr, COUPLE_EINVAL, "couple_remap_init: unknown precision");
+    std::string e = check_grid(src_n, src_nodes, "sender grid");
+    if (e.empty()) e = check_grid(dst_n, dst_nodes, "receiver grid");
+    if (!e.empty()) return rfail(nullptr, COUPLE_EINVAL, "couple_remap_init: " + e);
+    const double *xs = src_nodes, *xd = dst_nodes;
+    for (int a = 0; a < 3; ++a) {
+        const double L = xs[src_n[a]] - xs[0], tol = 1e-12 * L;
+        if (std::fabs(xs[0] - xd[0]) > tol || std::fabs(xs[src_n[a]] - xd[dst_n[a]]) > tol)
+            return rfail(nullptr, COUPLE_EINVAL, "couple_remap_init: the grids must span the same box");
+        xs += src_n[a] + 1;
+        xd += dst_n[a] + 1;
+    }
+    couple_remap *r = new (std::nothrow) couple_remap();
+    if (!r) return rfail(nullptr, COUPLE_ENOMEM, "couple_remap_init: host allocation failed");
+    for (int a = 0; a < 3; ++a) {
+        r->ns[a] = src_n[a];
+        r->nd[a] = dst_n[a];
+    }
+    r->precision = precision;
+    xs = src_nodes;
+    xd = dst_nodes;
+    bool ok = true;
+    for (int a = 0; a < 3 && ok; ++a) {
+        std::vector<int32_t> first, cnt, off;
+        std::vector<double> w;
+        build_axis(xs, src_n[a], xd, dst_n[a], first, cnt, off, w);
+        r->ax[a].nnz = (int64_t)w.size();
+        const size_t nd = (size_t)dst_n[a];
+        ok = dalloc_copy(&r->ax[a].first, first.data(), nd * 4) && dalloc_copy(&r->ax[a].cnt, cnt.data(), nd * 4) &&
+             dalloc_copy(&r->ax[a].off, off.data(), nd * 4);
+        if (ok) {
+            if (precision == COUPLE_FP64) {
+                ok = dalloc_copy(&r->ax[a].w, w.data(), w.size() * sizeof(double));
+            } else {
+                std::vector<float> wf(w.begin(), w.end());
+                ok = dalloc_copy(&r->ax[a].w, wf.data(), wf.size() * sizeof(float));
+            }
+        }
+        xs += src_n[a] + 1;
+        xd += dst_n[a] + 1;
+    }
+    if (!ok) {
+        remap_release(r);
+        delete r;
+        return rfail(nullptr, COUPLE_ENOMEM, "couple_remap_init: device allocation failed");
+    }
+    *out = r;
+    return COUPLE_OK;
+}
+
+template <typename T, bool KAHAN>
+static hipError_t launch_remap(const couple_remap *r, const void *src, void *dst, int nfields, hipStream_t st) {
+    RemapArgs<T> a;
+    a.nsrc = a.ndst = 1;
+    for (int k = 0; k < 3; ++k) {
+        a.first[k] = r->ax[k].first;
+        a.cnt[k] = r->ax[k].cnt;
+        a.off[k] = r->ax[k].off;
+        a.w[k] = static_cast<const T *>(r->ax[k].w);
+        a.ns[k] = r->ns[k];
+        a.nd[k] = r->nd[k];
+        a.nsrc *= r->ns[k];
+        a.ndst *= r->nd[k];
+    }
+    const int64_t nblk = (a.ndst + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL((k_remap<T, KAHAN>), dim3((unsigned)nblk, (unsigned)nfields), dim3(kBlock), 0, st, a,
+                       static_cast<const T *>(src), static_cast<T *>(dst));
+    return hipGetLastError();
+}
+
+extern "C" int couple_remap_apply(couple_remap *r, const void *src, void *dst, int32_t nfields, void *stream) {
+    if (!r) return rfail(nullptr, COUPLE_EINVAL, "couple_remap_apply: NULL map");
+    if (!src || !dst) return rfail(r, COUPLE_EINVAL, "couple_remap_apply: NULL field");
+    if (nfields < 1 || nfields > 64) return rfail(r, COUPLE_EINVAL, "couple_remap_apply: nfields must be in [1, 64]");
+    const size_t fsz = r->precision == COUPLE_FP64 ? 8 : 4;
+    const size_t bs = fsz * (size_t)nfields * (size_t)r->ns[0] * r->ns[1] * r->ns[2];
+    const size_t bd = fsz * (size_t)nfields * (size_t)r->nd[0] * r->nd[1] * r->nd[2];
+    const char *ps = static_cast<const char *>(src), *pd = static_cast<const char *>(dst);
+    if (ps < pd + bd && pd < ps + bs) return rfail(r, COUPLE_EINVAL, "couple_remap_apply: src and dst overlap");
+    (void)hipGetLastError();
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e;
+    if (r->precision == COUPLE_FP64) e = launch_remap<double, false>(r, src, dst, nfields, st);
+    else if (r->precision == COUPLE_FP32_KAHAN) e = launch_remap<float, true>(r, src, dst, nfields, st);
+    else e = launch_remap<float, false>(r, src, dst, nfields, st);
+    if (e != hipSuccess) return rfail(r, COUPLE_EHIP, std::string("couple_remap_apply: launch failed: ") + hipGetErrorString(e));
+    return COUPLE_OK;
+}
+
+extern "C" int couple_remap_info(const couple_remap *r, int64_t nnz_axis[3], int64_t *nnz_total) {
+    if (!r) return COUPLE_EINVAL;
+    if (nnz_axis)
+        for (int a = 0; a < 3; ++a) nnz_axis[a] = r->ax[a].nnz;
+    if (nnz_total) {
+        // the 3-D map has, per receiver cell, the product of its three ranges
+        *nnz_total = r->ax[0].nnz * r->ax[1].nnz * r->ax[2].nnz;
+    }
+    return COUPLE_OK;
+}
+
+extern "C" int couple_remap_free(couple_remap *r) {
+    if (!r) return COUPLE_OK;
+    remap_release(r);
+    delete r;
+    return COUPLE_OK;
+}
+
+extern "C" const char *couple_remap_last_error(const couple_remap *r) {
+    return r ? r->err.c_str() : g_remap_init_err.c_str();
+}

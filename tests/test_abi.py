@@ -1,5 +1,5 @@
 """CPU checks of the C ABI: the library loads, exports every entry point that
-include/couple.h and include/couple_mlp.h declare, its structs have the
+include/couple.h, include/couple_mlp.h and include/couple_remap.h declare, its structs have the
 headers' layout, and argument validation rejects bad calls before any device
 work."""
 import os
@@ -9,7 +9,7 @@ import subprocess
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADERS = [os.path.join(ROOT, "include", h) for h in ("couple.h", "couple_mlp.h")]
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("couple.h", "couple_mlp.h", "couple_remap.h")]
 LIB = os.path.join(ROOT, "paper_1807_11834_amd", "libcouple.so")
 
 
@@ -25,7 +25,8 @@ def test_header_declares_the_entry_points():
         "couple_mlp_init", "couple_mlp_free", "couple_mlp_last_error", "couple_mlp_set_params",
         "couple_mlp_set_norm", "couple_mlp_fit_norm", "couple_mlp_get_state", "couple_mlp_set_state",
         "couple_mlp_forward", "couple_mlp_grads", "couple_mlp_adam", "couple_mlp_train_step",
-        "couple_mlp_features", "couple_set_mlp"])
+        "couple_mlp_features", "couple_set_mlp",
+        "couple_remap_init", "couple_remap_apply", "couple_remap_info", "couple_remap_free", "couple_remap_last_error"])
 
 
 def test_library_exports_every_declared_symbol():
@@ -126,3 +127,37 @@ def test_mlp_null_handles():
     assert L.couple_set_mlp(None, None) == cpl.COUPLE_EINVAL
     assert L.couple_mlp_features(None, 0, None, None, None, None, None, None, None, 0, None, None, None,
                                  None) == cpl.COUPLE_EINVAL
+
+
+def _nodes(n, box=(1.0, 1.0, 1.0)):
+    import numpy as np
+    return [np.linspace(0.0, box[a], n[a] + 1) for a in range(3)]
+
+
+@pytest.mark.parametrize("case", ["zero_cells", "not_increasing", "nan", "box_mismatch", "precision"])
+def test_remap_init_rejects_invalid_grids(case):
+    import numpy as np
+    import paper_1807_11834_amd as cpl
+    src, dst, prec = _nodes((4, 3, 2)), _nodes((2, 2, 2)), cpl.COUPLE_FP32_KAHAN
+    if case == "zero_cells":
+        dst[1] = np.array([0.0])
+    elif case == "not_increasing":
+        src[0] = np.array([0.0, 0.5, 0.5, 0.75, 1.0])
+    elif case == "nan":
+        src[2] = np.array([0.0, float("nan"), 1.0])
+    elif case == "box_mismatch":
+        dst[2] = np.array([0.0, 0.5, 1.1])
+    else:
+        prec = 9
+    with pytest.raises(cpl.CoupleError) as ei:
+        cpl.Remap(src, dst, precision=prec)
+    assert ei.value.code == cpl.COUPLE_EINVAL
+    assert "couple_remap_init" in str(ei.value)
+
+
+def test_remap_null_handles():
+    import paper_1807_11834_amd as cpl
+    L = cpl._lib
+    assert L.couple_remap_free(None) == cpl.COUPLE_OK
+    assert L.couple_remap_apply(None, None, None, 1, None) == cpl.COUPLE_EINVAL
+    assert L.couple_remap_info(None, None, None) == cpl.COUPLE_EINVAL
