@@ -5,11 +5,16 @@
 // three 1-D factors: for receiver index i along axis a, the overlapping sender
 // indices are the contiguous range first_a[i] .. first_a[i] + cnt_a[i] - 1 with
 // weights w_a[off_a[i] + k] = overlap length / receiver cell length.  Built on
-// the host in FP64 once per grid pair; applied on the device with one thread per
-// receiver cell (x fastest, so a wave reads neighbouring sender rows), summing
-// the sender cells in raster order (z, then y, then x), compensated in the FP32
-// Kahan mode.  Storing the 3-D map as CSR would read more bytes of indices and
-// weights than of field values; the factors are a few KB and stay in cache.
+// the host in FP64 once per grid pair.  Applied on the device by one of three
+// kernels: for a receiver finer than the sender in y and z, tiles of receiver
+// rows over an LDS-staged sender slab (k_remap_tile); otherwise receiver rows
+// per workgroup (k_remap_rows: the y, z part of the sum over whole sender rows
+// with coalesced loads, then the x part from LDS); for sender rows too long for
+// LDS, one thread per receiver cell (k_remap: raster order z, y, x).
+// Sums are compensated in the FP32 Kahan mode.  Storing the 3-D map as CSR
+// would read more bytes of indices and weights than of field values; the
+// factors are a few KB and stay in cache.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -61,11 +66,141 @@ __global__ __launch_bounds__(kBlock) void k_remap(RemapArgs<T> r, const T *__res
     dst[(int64_t)blockIdx.y * r.ndst + c] = acc.s;
 }
 
+// Receiver rows (y, z) of one field per workgroup, grid-strided over the rows.
+// A row's y and z factors are the same for the whole workgroup: the (z, y)
+// sender rows it overlaps and their weights wz * wy are tabulated in LDS (up to
+// kMaxQ at a time), then every sender x of the slab is summed over those rows
+// -- each thread issues its kMaxQ loads together -- giving r(x_s) in LDS; then
+// each receiver x sums its overlapping r values with the x weights.  Sum
+// order: (z, y) in raster order, then x.
+constexpr int kMaxQ = 16;
+
+template <typename T, bool KAHAN>
+__global__ __launch_bounds__(kBlock) void k_remap_rows(RemapArgs<T> r, const T *__restrict__ src,
+                                                       T *__restrict__ dst) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    T *row = reinterpret_cast<T *>(lds_raw);
+    __shared__ int64_t qoff[kMaxQ];
+    __shared__ T qw[kMaxQ];
+    const int64_t nrow = (int64_t)r.nd[1] * r.nd[2];
+    const T *__restrict__ s = src + (int64_t)blockIdx.y * r.nsrc;
+    const int nsx = r.ns[0];
+    const int64_t sxy = (int64_t)r.ns[0] * r.ns[1];
+    const int64_t first_row = xcd_tile(blockIdx.x, gridDim.x);
+    for (int64_t rr = first_row; rr < nrow; rr += gridDim.x) {    // uniform over the workgroup
+        const int j = (int)(rr % r.nd[1]), k = (int)(rr / r.nd[1]);
+        const int fy = r.first[1][j], ny = r.cnt[1][j], oy = r.off[1][j];
+        const int fz = r.first[2][k], nz = r.cnt[2][k], oz = r.off[2][k];
+        const int nq = ny * nz;
+        for (int q0 = 0; q0 < nq; q0 += kMaxQ) {
+            const int mq = nq - q0 < kMaxQ ? nq - q0 : kMaxQ;
+            if (threadIdx.x < mq) {
+                const int q = q0 + threadIdx.x, kz = q / ny, ky = q % ny;
+                qoff[threadIdx.x] = (int64_t)(fz + kz) * sxy + (int64_t)(fy + ky) * nsx;
+                qw[threadIdx.x] = r.w[2][oz + kz] * r.w[1][oy + ky];
+            }
+            __syncthreads();
+            for (int xs = threadIdx.x; xs < nsx; xs += kBlock) {
+                T v[kMaxQ];
+#pragma unroll
+                for (int q = 0; q < kMaxQ; ++q) v[q] = q < mq ? s[qoff[q] + xs] : T(0);
+                Acc<T, KAHAN> acc;
+                if (q0 > 0) acc.s = row[xs];   // continue the partial sum of earlier rows
+#pragma unroll
+                for (int q = 0; q < kMaxQ; ++q)
+                    if (q < mq) acc.add(qw[q] * v[q]);
+                row[xs] = acc.s;
+            }
+            __syncthreads();
+        }
+        T *__restrict__ out = dst + (int64_t)blockIdx.y * r.ndst + rr * r.nd[0];
+        for (int xd = threadIdx.x; xd < r.nd[0]; xd += kBlock) {
+            const int fx = r.first[0][xd], nx = r.cnt[0][xd], ox = r.off[0][xd];
+            Acc<T, KAHAN> acc;
+            for (int kx = 0; kx < nx; ++kx) acc.add(r.w[0][ox + kx] * row[fx + kx]);
+            out[xd] = acc.s;
+        }
+        __syncthreads();   // the row buffer is reused by the next row
+    }
+}
+
+// A tile of kTileJ x kTileK receiver rows (y, z) of one field per workgroup,
+// for receivers finer than the sender in y and z: the sender slab under the tile
+// (its overlapping y and z rows, whole x extent) is staged in LDS once with
+// coalesced loads, and every receiver cell of the tile sums its (z, y, x)
+// overlaps from LDS in raster order.
+constexpr int kTileJ = 8, kTileK = 8;
+constexpr int kMaxX = 4;   // x factors held in registers (longer ranges read them in the loop)
+
+template <typename T, bool KAHAN>
+__global__ __launch_bounds__(kBlock) void k_remap_tile(RemapArgs<T> r, const T *__restrict__ src,
+                                                       T *__restrict__ dst) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    T *slab = reinterpret_cast<T *>(lds_raw);
+    const int tny = (r.nd[1] + kTileJ - 1) / kTileJ;
+    const int64_t t = xcd_tile(blockIdx.x, gridDim.x);
+    const int j0 = (int)(t % tny) * kTileJ, k0 = (int)(t / tny) * kTileK;
+    const int j1 = j0 + kTileJ < r.nd[1] ? j0 + kTileJ : r.nd[1];
+    const int k1 = k0 + kTileK < r.nd[2] ? k0 + kTileK : r.nd[2];
+    const int ys0 = r.first[1][j0], ys1 = r.first[1][j1 - 1] + r.cnt[1][j1 - 1];
+    const int zs0 = r.first[2][k0], zs1 = r.first[2][k1 - 1] + r.cnt[2][k1 - 1];
+    const int Ys = ys1 - ys0, nsx = r.ns[0];
+    const int64_t sxy = (int64_t)r.ns[0] * r.ns[1];
+    const T *__restrict__ s = src + (int64_t)blockIdx.y * r.nsrc;
+    const int nslab = (zs1 - zs0) * Ys * nsx;
+    for (int e = threadIdx.x; e < nslab; e += kBlock) {
+        const int x = e % nsx, yy = (e / nsx) % Ys, zz = e / (nsx * Ys);
+        slab[e] = s[(int64_t)(zs0 + zz) * sxy + (int64_t)(ys0 + yy) * nsx + x];
+    }
+    __syncthreads();
+    // each thread keeps the x factor of its receiver columns in registers and
+    // walks the tile's rows, whose y and z factors are uniform
+    const int ndx = r.nd[0];
+    T *__restrict__ out = dst + (int64_t)blockIdx.y * r.ndst;
+    for (int xd = threadIdx.x; xd < ndx; xd += kBlock) {
+        const int fx = r.first[0][xd], nx = r.cnt[0][xd], ox = r.off[0][xd];
+        T wx[kMaxX];
+#pragma unroll
+        for (int q = 0; q < kMaxX; ++q) wx[q] = q < nx ? r.w[0][ox + q] : T(0);
+        for (int k = k0; k < k1; ++k) {
+            const int fz = r.first[2][k], nz = r.cnt[2][k], oz = r.off[2][k];
+            for (int j = j0; j < j1; ++j) {
+                const int fy = r.first[1][j], ny = r.cnt[1][j], oy = r.off[1][j];
+                Acc<T, KAHAN> acc;
+                for (int kz = 0; kz < nz; ++kz) {
+                    const T wz = r.w[2][oz + kz];
+                    for (int ky = 0; ky < ny; ++ky) {
+                        const T wyz = wz * r.w[1][oy + ky];
+                        const T *row = slab + ((fz + kz - zs0) * Ys + (fy + ky - ys0)) * nsx + fx;
+                        if (nx <= kMaxX) {
+#pragma unroll
+                            for (int q = 0; q < kMaxX; ++q)
+                                if (q < nx) acc.add((wyz * wx[q]) * row[q]);
+                        } else {
+                            for (int kx = 0; kx < nx; ++kx) acc.add((wyz * r.w[0][ox + kx]) * row[kx]);
+                        }
+                    }
+                }
+                out[((int64_t)k * r.nd[1] + j) * ndx + xd] = acc.s;
+            }
+        }
+    }
+}
+
+// Sender slabs under a receiver tile up to this many bytes take k_remap_tile
+// when the receiver is finer than the sender in both y and z.
+constexpr size_t kTileLdsBytes = 48 * 1024;
+
+// Sender rows up to this many bytes are staged whole in LDS by k_remap_rows;
+// longer rows take k_remap.
+constexpr size_t kRowLdsBytes = 60 * 1024;
+
 }  // namespace
 
 struct couple_remap {
     int32_t ns[3], nd[3];
     int32_t precision;
+    size_t tile_slab_rows;   // most sender (y, z) rows under one receiver tile (0: tile kernel not used)
     Axis1D ax[3];
     std::string err;
 };
@@ -176,10 +311,18 @@ extern "C" int couple_remap_init(const int32_t src_n[3], const double *src_nodes
     xs = src_nodes;
     xd = dst_nodes;
     bool ok = true;
+    size_t span[3] = {0, 0, 0};   // most sender indices under kTileJ (y) / kTileK (z) receiver indices
+    bool finer[3] = {true, true, true};
     for (int a = 0; a < 3 && ok; ++a) {
         std::vector<int32_t> first, cnt, off;
         std::vector<double> w;
         build_axis(xs, src_n[a], xd, dst_n[a], first, cnt, off, w);
+        const int tile = a == 2 ? kTileK : kTileJ;
+        for (int i0 = 0; i0 < dst_n[a]; i0 += tile) {
+            const int i1 = std::min(i0 + tile, dst_n[a]);
+            span[a] = std::max(span[a], (size_t)(first[i1 - 1] + cnt[i1 - 1] - first[i0]));
+        }
+        finer[a] = dst_n[a] > src_n[a];
         r->ax[a].nnz = (int64_t)w.size();
         const size_t nd = (size_t)dst_n[a];
         ok = dalloc_copy(&r->ax[a].first, first.data(), nd * 4) && dalloc_copy(&r->ax[a].cnt, cnt.data(), nd * 4) &&
@@ -195,6 +338,7 @@ extern "C" int couple_remap_init(const int32_t src_n[3], const double *src_nodes
         xs += src_n[a] + 1;
         xd += dst_n[a] + 1;
     }
+    r->tile_slab_rows = (finer[1] && finer[2]) ? span[1] * span[2] : 0;
     if (!ok) {
         remap_release(r);
         delete r;
@@ -218,9 +362,24 @@ static hipError_t launch_remap(const couple_remap *r, const void *src, void *dst
         a.nsrc *= r->ns[k];
         a.ndst *= r->nd[k];
     }
-    const int64_t nblk = (a.ndst + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL((k_remap<T, KAHAN>), dim3((unsigned)nblk, (unsigned)nfields), dim3(kBlock), 0, st, a,
-                       static_cast<const T *>(src), static_cast<T *>(dst));
+    const size_t lds = sizeof(T) * (size_t)r->ns[0];
+    const size_t tile_lds = lds * r->tile_slab_rows;
+    if (r->tile_slab_rows > 0 && tile_lds <= kTileLdsBytes) {
+        const int64_t ntile = (int64_t)((r->nd[1] + kTileJ - 1) / kTileJ) * ((r->nd[2] + kTileK - 1) / kTileK);
+        hipLaunchKernelGGL((k_remap_tile<T, KAHAN>), dim3((unsigned)ntile, (unsigned)nfields), dim3(kBlock), tile_lds,
+                           st, a, static_cast<const T *>(src), static_cast<T *>(dst));
+    } else if (lds <= kRowLdsBytes) {
+        // enough workgroups to fill the chip several times over, each looping
+        // over rows (a row is a small amount of work when the receiver is finer)
+        const int64_t nrow = (int64_t)r->nd[1] * r->nd[2];
+        const int64_t per_field = std::max<int64_t>(1, std::min<int64_t>(nrow, 8192 / nfields + 1));
+        hipLaunchKernelGGL((k_remap_rows<T, KAHAN>), dim3((unsigned)per_field, (unsigned)nfields), dim3(kBlock), lds,
+                           st, a, static_cast<const T *>(src), static_cast<T *>(dst));
+    } else {
+        const int64_t nblk = (a.ndst + kBlock - 1) / kBlock;
+        hipLaunchKernelGGL((k_remap<T, KAHAN>), dim3((unsigned)nblk, (unsigned)nfields), dim3(kBlock), 0, st, a,
+                           static_cast<const T *>(src), static_cast<T *>(dst));
+    }
     return hipGetLastError();
 }
 

@@ -3,6 +3,8 @@ receiver interpolation of Sec. 2.3) against the FP64 oracle, through the C ABI.
 
 e_max of a receiver cell: |g - o| / max(M_c, 1e-3 max M), with M the transfer of
 |src| (the size of the terms the cell sums).  FP32 within 1e-4, FP64 within 1e-6.
+Both kernels are covered: receiver rows from LDS-staged sender rows, and one
+thread per receiver cell for sender rows longer than the LDS buffer.
 At the packed bed's full fine-grid size the transfer is compared on sampled
 receiver cells (each one an oracle call on the sender cells it overlaps) and
 checked for constants and the conserved integral.
@@ -52,6 +54,9 @@ CASES = [
     ((32, 24, 20), (8, 6, 5), (1.0, 0.75, 0.625), "uniform", "fp32n", 1),
     ((1, 30, 2), (1, 7, 5), (0.1, 1.0, 0.3), "random", "fp32k", 1),
     ((61, 3, 47), (29, 5, 13), (1.0, 0.1, 0.8), "random", "fp32k", 1),
+    # sender rows longer than the LDS row buffer: the per-cell kernel
+    ((20000, 2, 1), (7, 3, 2), (1.0, 0.2, 0.1), "random", "fp32k", 1),
+    ((9000, 1, 2), (13, 1, 1), (1.0, 0.1, 0.1), "uniform", "fp64", 1),
 ]
 
 
