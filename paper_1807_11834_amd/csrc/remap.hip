@@ -154,7 +154,8 @@ __global__ __launch_bounds__(kBlock) void k_remap_tile(RemapArgs<T> r, const T *
     }
     __syncthreads();
     // each thread keeps the x factor of its receiver columns in registers and
-    // walks the tile's rows, whose y and z factors are uniform
+    // walks the tile's rows, whose y and z factors are uniform; the (large,
+    // write-once) receiver field is stored non-temporally
     const int ndx = r.nd[0];
     T *__restrict__ out = dst + (int64_t)blockIdx.y * r.ndst;
     for (int xd = threadIdx.x; xd < ndx; xd += kBlock) {
@@ -181,7 +182,7 @@ __global__ __launch_bounds__(kBlock) void k_remap_tile(RemapArgs<T> r, const T *
                         }
                     }
                 }
-                out[((int64_t)k * r.nd[1] + j) * ndx + xd] = acc.s;
+                __builtin_nontemporal_store(acc.s, &out[((int64_t)k * r.nd[1] + j) * ndx + xd]);
             }
         }
     }

@@ -60,18 +60,27 @@ template <typename T, int R> __device__ __forceinline__ Row<T, R> load_row(const
     return r;
 }
 
+// Fine-grid rows written once and not read again in the step: non-temporal
+// stores, so that the 4 GB written per prolongation do not sit dirty in the
+// caches and slow the next kernels while they are written back.
+template <typename T, int N> using NtVec = T __attribute__((ext_vector_type(N)));
+
 template <typename T, int R> __device__ __forceinline__ void store_row(T *__restrict__ p, const T *v) {
     if constexpr (std::is_same<T, float>::value && R == 4) {
-        *reinterpret_cast<float4 *>(p) = make_float4(v[0], v[1], v[2], v[3]);
+        const NtVec<float, 4> q = {v[0], v[1], v[2], v[3]};
+        __builtin_nontemporal_store(q, reinterpret_cast<NtVec<float, 4> *>(p));
     } else if constexpr (std::is_same<T, float>::value && R == 2) {
-        *reinterpret_cast<float2 *>(p) = make_float2(v[0], v[1]);
+        const NtVec<float, 2> q = {v[0], v[1]};
+        __builtin_nontemporal_store(q, reinterpret_cast<NtVec<float, 2> *>(p));
     } else if constexpr (std::is_same<T, double>::value && R == 4) {
-        reinterpret_cast<double2 *>(p)[0] = make_double2(v[0], v[1]);
-        reinterpret_cast<double2 *>(p)[1] = make_double2(v[2], v[3]);
+        const NtVec<double, 2> q0 = {v[0], v[1]}, q1 = {v[2], v[3]};
+        __builtin_nontemporal_store(q0, reinterpret_cast<NtVec<double, 2> *>(p));
+        __builtin_nontemporal_store(q1, reinterpret_cast<NtVec<double, 2> *>(p) + 1);
     } else if constexpr (std::is_same<T, double>::value && R == 2) {
-        *reinterpret_cast<double2 *>(p) = make_double2(v[0], v[1]);
+        const NtVec<double, 2> q = {v[0], v[1]};
+        __builtin_nontemporal_store(q, reinterpret_cast<NtVec<double, 2> *>(p));
     } else {
-        for (int k = 0; k < R; ++k) p[k] = v[k];
+        for (int k = 0; k < R; ++k) __builtin_nontemporal_store(v[k], p + k);
     }
 }
 
