@@ -267,7 +267,10 @@ __global__ __launch_bounds__(kBlock) void k_transpose(const uint16_t *__restrict
 //   part_w[c][m][k] = sum_{b in chunk} dZ[b][m] H[b][k]   (BF16 x BF16, FP32 accumulate)
 //   part_b[c][m]    = sum_{b in chunk} dZf[b][m]          (FP32 values, FP64 sum)
 // from the transposed copies dZT [16 MT][B] and HT [16 KT][B].  Rows in chunks
-// of kChunk; B is a multiple of 32.
+// of kChunk; B is a multiple of 32.  Each wave owns output column blocks kt and
+// keeps all MT row blocks in registers: per 32 rows it loads one HT fragment and
+// the MT dZT fragments and issues MT independent products.  The bias sums run
+// four interleaved FP64 partial sums (rows b mod 4) combined in a fixed order.
 template <int MT, int KT>
 __global__ __launch_bounds__(kBlock) void k_wgrad(const uint16_t *__restrict__ dZT, const uint16_t *__restrict__ HT,
                                                   const float *__restrict__ dzf, int64_t B,
@@ -276,20 +279,34 @@ __global__ __launch_bounds__(kBlock) void k_wgrad(const uint16_t *__restrict__ d
     const int lane = lane_id(), n = lane & 15, g = lane >> 4, wave = threadIdx.x >> 6;
     const int64_t c = blockIdx.x;
     const int64_t b0 = c * kChunk, b1 = (b0 + kChunk < B) ? b0 + kChunk : B;
-    for (int tt = wave; tt < MT * KT; tt += kWavesPerBlock) {
-        const int mt = tt / KT, kt = tt % KT;
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-        const uint16_t *pa = dZT + (int64_t)(16 * mt + n) * B + 8 * g;
-        const uint16_t *pb = HT + (int64_t)(16 * kt + n) * B + 8 * g;
-        for (int64_t bb = b0; bb < b1; bb += 32) acc = mma(load8(pa + bb), load8(pb + bb), acc);
-        float *o = part_w + (c * MP + 16 * mt + 4 * g) * KP + 16 * kt + n;
+    for (int kt = wave; kt < KT; kt += kWavesPerBlock) {
+        f32x4 acc[MT];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) o[(int64_t)j * KP] = acc[j];
+        for (int mt = 0; mt < MT; ++mt) acc[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        const uint16_t *pb = HT + (int64_t)(16 * kt + n) * B + 8 * g;
+        const uint16_t *pa = dZT + (int64_t)n * B + 8 * g;
+        for (int64_t bb = b0; bb < b1; bb += 32) {
+            const bf16x8 bv = load8(pb + bb);
+            bf16x8 av[MT];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) av[mt] = load8(pa + (int64_t)16 * mt * B + bb);
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) acc[mt] = mma(av[mt], bv, acc[mt]);
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            float *o = part_w + (c * MP + 16 * mt + 4 * g) * KP + 16 * kt + n;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) o[(int64_t)j * KP] = acc[mt][j];
+        }
     }
     for (int m = threadIdx.x; m < MP; m += kBlock) {
-        double s = 0.0;
-        for (int64_t b = b0; b < b1; ++b) s += (double)dzf[b * MP + m];
-        part_b[c * MP + m] = s;
+        double s[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int64_t b = b0; b < b1; b += 4) {   // chunks are multiples of 32 rows
+#pragma unroll
+            for (int q = 0; q < 4; ++q) s[q] += (double)dzf[(b + q) * MP + m];
+        }
+        part_b[c * MP + m] = (s[0] + s[1]) + (s[2] + s[3]);
     }
 }
 
@@ -305,15 +322,18 @@ __global__ __launch_bounds__(kBlock) void k_reduce_grads(GradParts parts, int64_
     int l, k, m;
     bool isw;
     decode_param(i, l, isw, k, m);
-    double s = 0.0;
+    // four interleaved partial sums over the chunks (c mod 4), combined in a
+    // fixed order: deterministic, and four independent dependency chains
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
     if (isw) {
         const int MP = mpad(l), KP = kpad(l);
-        for (int64_t c = 0; c < nchunk; ++c) s += (double)parts.w[l][(c * MP + m) * KP + k];
+        const float *w = parts.w[l] + (int64_t)m * KP + k;
+        for (int64_t c = 0; c < nchunk; ++c) s[c & 3] += (double)w[c * MP * KP];
     } else {
         const int MP = mpad(l);
-        for (int64_t c = 0; c < nchunk; ++c) s += parts.b[l][c * MP + m];
+        for (int64_t c = 0; c < nchunk; ++c) s[c & 3] += parts.b[l][c * MP + m];
     }
-    grads[i] = (float)s;
+    grads[i] = (float)((s[0] + s[1]) + (s[2] + s[3]));
 }
 
 __global__ __launch_bounds__(kBlock) void k_sum_loss(const double *__restrict__ part, int64_t n, float *__restrict__ out) {

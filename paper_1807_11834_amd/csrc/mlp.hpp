@@ -49,7 +49,7 @@ struct TrainBufs {
     float *grads = nullptr;                        // [kNParam]
 };
 
-constexpr int64_t kChunk = 512;   // rows per workgroup in the weight-gradient products
+constexpr int64_t kChunk = 256;   // rows per workgroup in the weight-gradient products
 inline int64_t n_chunks(int64_t B) { return (B + kChunk - 1) / kChunk; }
 
 // Device state of one network (owned by the couple_mlp handle).
