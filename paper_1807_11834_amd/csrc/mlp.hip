@@ -315,25 +315,61 @@ struct GradParts {
     const double *b[4];
 };
 
-// Flat gradient vector from the per-chunk partials (chunks summed in order).
+// Flat gradient vector from the per-chunk partials.  Work entries follow the
+// partials' layout (per layer the padded [m][k] weight slots, k fastest, then
+// the m bias slots), so that the loads of a wave are contiguous; each entry is
+// summed by kRedGroups threads over interleaved chunks (c mod kRedGroups, two
+// partial sums each) whose results are combined in a fixed order.
+constexpr int kRedGroups = 8;
+constexpr int kRedEntries = kBlock / kRedGroups;   // entries per workgroup
+
+__host__ __device__ constexpr int64_t red_w_begin(int l) {
+    return l == 0 ? 0 : red_w_begin(l - 1) + (int64_t)mpad(l - 1) * kpad(l - 1) + mpad(l - 1);
+}
+constexpr int64_t kRedTotal = red_w_begin(3) + (int64_t)mpad(3) * kpad(3) + mpad(3);
+
 __global__ __launch_bounds__(kBlock) void k_reduce_grads(GradParts parts, int64_t nchunk, float *__restrict__ grads) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= kNParam) return;
-    int l, k, m;
-    bool isw;
-    decode_param(i, l, isw, k, m);
-    // four interleaved partial sums over the chunks (c mod 4), combined in a
-    // fixed order: deterministic, and four independent dependency chains
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
-    if (isw) {
-        const int MP = mpad(l), KP = kpad(l);
-        const float *w = parts.w[l] + (int64_t)m * KP + k;
-        for (int64_t c = 0; c < nchunk; ++c) s[c & 3] += (double)w[c * MP * KP];
-    } else {
-        const int MP = mpad(l);
-        for (int64_t c = 0; c < nchunk; ++c) s[c & 3] += parts.b[l][c * MP + m];
+    __shared__ double red[kRedGroups][kRedEntries];
+    const int le = threadIdx.x % kRedEntries, grp = threadIdx.x / kRedEntries;
+    const int64_t e = (int64_t)blockIdx.x * kRedEntries + le;
+    int l = 0;
+    while (l < 3 && e >= red_w_begin(l + 1)) ++l;
+    const int64_t r = e - red_w_begin(l);
+    const int MP = mpad(l), KP = kpad(l);
+    const bool isw = r < (int64_t)MP * KP;
+    const int m = isw ? (int)(r / KP) : (int)(r - (int64_t)MP * KP), k = isw ? (int)(r % KP) : 0;
+    double s0 = 0.0, s1 = 0.0;
+    if (e < kRedTotal) {
+        if (isw) {
+            const float *w = parts.w[l] + (int64_t)m * KP + k;
+            const int64_t stride = (int64_t)MP * KP;
+            int64_t c = grp;
+            for (; c + kRedGroups < nchunk; c += 2 * kRedGroups) {
+                s0 += (double)w[c * stride];
+                s1 += (double)w[(c + kRedGroups) * stride];
+            }
+            if (c < nchunk) s0 += (double)w[c * stride];
+        } else {
+            int64_t c = grp;
+            for (; c + kRedGroups < nchunk; c += 2 * kRedGroups) {
+                s0 += parts.b[l][c * MP + m];
+                s1 += parts.b[l][(c + kRedGroups) * MP + m];
+            }
+            if (c < nchunk) s0 += parts.b[l][c * MP + m];
+        }
     }
-    grads[i] = (float)((s[0] + s[1]) + (s[2] + s[3]));
+    red[grp][le] = s0 + s1;
+    __syncthreads();
+    if (grp == 0 && e < kRedTotal) {
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < kRedGroups; ++q) t += red[q][le];
+        if (isw) {
+            if (k < fan_in(l) && m < fan_out(l)) grads[off_w(l) + (int64_t)k * fan_out(l) + m] = (float)t;
+        } else if (m < fan_out(l)) {
+            grads[off_b(l) + m] = (float)t;
+        }
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_sum_loss(const double *__restrict__ part, int64_t n, float *__restrict__ out) {
@@ -891,7 +927,8 @@ hipError_t launch_backward(const NetBufs &net, const TrainBufs &tb, int64_t B, f
         parts.w[l] = tb.part_w[l];
         parts.b[l] = tb.part_b[l];
     }
-    hipLaunchKernelGGL(k_reduce_grads, dim3(blocks(kNParam)), bl, 0, st, parts, (int64_t)nc, grads);
+    hipLaunchKernelGGL(k_reduce_grads, dim3((unsigned)((kRedTotal + kRedEntries - 1) / kRedEntries)), bl, 0, st, parts,
+                       (int64_t)nc, grads);
     if (loss) hipLaunchKernelGGL(k_sum_loss, dim3(1), bl, 0, st, tb.loss_part, (B + 15) / 16, loss);
     return hipGetLastError();
 }
