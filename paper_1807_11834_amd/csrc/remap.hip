@@ -296,6 +296,10 @@ extern "C" int couple_remap_init(const int32_t src_n[3], const double *src_nodes
     if (!e.empty()) return rfail(nullptr, COUPLE_EINVAL, "couple_remap_init: " + e);
     const double *xs = src_nodes, *xd = dst_nodes;
     for (int a = 0; a < 3; ++a) {
+        // a 1-D factor has at most src_n + dst_n - 1 entries (one per interval
+        // of the merged node sequence); its offsets are 32-bit
+        if ((int64_t)src_n[a] + dst_n[a] >= (int64_t(1) << 31))
+            return rfail(nullptr, COUPLE_EINVAL, "couple_remap_init: too many cells along an axis");
         const double L = xs[src_n[a]] - xs[0], tol = 1e-12 * L;
         if (std::fabs(xs[0] - xd[0]) > tol || std::fabs(xs[src_n[a]] - xd[dst_n[a]]) > tol)
             return rfail(nullptr, COUPLE_EINVAL, "couple_remap_init: the grids must span the same box");
