@@ -755,55 +755,83 @@ __global__ __launch_bounds__(kInfWaves * kWave) void k_infer(StepArgs<float> a) 
 // Bricks of 8x8x8 bulk cells, one wave each.  The checked sample is every
 // particle with id mod period = step mod period; where its relative L2 error
 // against the fine lookup exceeds tol, every particle of the brick takes the
-// fine lookup.  Per workgroup: fallback count, sampled squared error and
-// reference, sample count (FP64 partials, fixed order).
+// fine lookup.  The brick's 64 (z, y) rows are one lane each: their sorted
+// ranges are loaded at once and prefix-summed across the wave, and the brick's
+// particles are then processed 64 at a time in that flattened order.  Per
+// workgroup: fallback count, sampled squared error and reference, sample count
+// (FP64 partials, fixed order).
 constexpr int kBrick = 8;
 
 __global__ __launch_bounds__(kBlock) void k_check(StepArgs<float> a) {
+    static_assert(kBrick * kBrick == kWave, "one lane per (z, y) row of a brick");
     __shared__ double red[kWavesPerBlock];
+    __shared__ int32_t pre[kWavesPerBlock][kWave + 1];   // particles before each row (exclusive prefix)
+    __shared__ int64_t row0[kWavesPerBlock][kWave];      // first sorted position of each row
     const int lane = lane_id(), wave = threadIdx.x >> 6;
     const int64_t brick = (int64_t)blockIdx.x * kWavesPerBlock + wave;
     const Geo<float> &geo = a.g;
     double err = 0.0, ref = 0.0, ns = 0.0, nfall = 0.0;
-    if (brick < a.n_bricks && a.n > 0) {
+    if (brick < a.n_bricks && a.n > 0) {   // uniform over the wave
         const int bx = (geo.nb[0] + kBrick - 1) / kBrick, by = (geo.nb[1] + kBrick - 1) / kBrick;
         const int ox = (int)(brick % bx) * kBrick, oy = (int)((brick / bx) % by) * kBrick,
                   oz = (int)(brick / ((int64_t)bx * by)) * kBrick;
         const int wx = (ox + kBrick < geo.nb[0]) ? kBrick : geo.nb[0] - ox;
-        const int64_t period = a.mlp_period, phase = ((a.step % period) + period) % period;
-        for (int dz = 0; dz < kBrick && oz + dz < geo.nb[2]; ++dz)
-            for (int dy = 0; dy < kBrick && oy + dy < geo.nb[1]; ++dy) {
-                const int64_t c0 = ox + (int64_t)geo.nb[0] * ((oy + dy) + (int64_t)geo.nb[1] * (oz + dz));
-                const int64_t s0 = seg_clamp(a.start[c0], a.n), s1 = seg_clamp(a.start[c0 + wx], a.n);
-                for (int64_t s = s0 + lane; s < s1; s += kWave) {
-                    int64_t p = a.perm[s];
-                    if (p < 0 || p >= a.n) p = 0;
-                    if (p % period != phase) continue;
-                    float ux, uy, uz;
-                    fine_velocity(a.sp[s], a, ux, uy, uz);
-                    const float4 m = a.uf4[p];
-                    const double ex = (double)m.x - ux, ey = (double)m.y - uy, ez = (double)m.z - uz;
-                    err += ex * ex + ey * ey + ez * ez;
-                    ref += (double)ux * ux + (double)uy * uy + (double)uz * uz;
-                    ns += 1.0;
-                }
+        // lane r owns row (dz, dy) = (r / 8, r % 8): its particles are the
+        // contiguous sorted range of cells ox .. ox + wx - 1 of that row
+        const int dz = lane / kBrick, dy = lane % kBrick;
+        int64_t s0 = 0, s1 = 0;
+        if (oz + dz < geo.nb[2] && oy + dy < geo.nb[1]) {
+            const int64_t c0 = ox + (int64_t)geo.nb[0] * ((oy + dy) + (int64_t)geo.nb[1] * (oz + dz));
+            s0 = seg_clamp(a.start[c0], a.n);
+            s1 = seg_clamp(a.start[c0 + wx], a.n);
+        }
+        int32_t incl = (int32_t)(s1 - s0);   // inclusive prefix over the lanes (rows in order)
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const int32_t v = __shfl_up(incl, o, kWave);
+            if (lane >= o) incl += v;
+        }
+        pre[wave][lane + 1] = incl;
+        if (lane == 0) pre[wave][0] = 0;
+        row0[wave][lane] = s0;
+        wave_sync();
+        const int32_t total = pre[wave][kWave];
+        // flattened index j -> row (last r with pre[r] <= j) -> sorted position
+        auto position = [&](int32_t j) {
+            int lo = 0, hi = kWave;   // pre[lo] <= j < pre[hi]
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (pre[wave][mid] <= j) lo = mid;
+                else hi = mid;
             }
+            return row0[wave][lo] + (j - pre[wave][lo]);
+        };
+        const int64_t period = a.mlp_period, phase = ((a.step % period) + period) % period;
+        for (int32_t j = lane; j < total; j += kWave) {
+            const int64_t s = position(j);
+            int64_t p = a.perm[s];
+            if (p < 0 || p >= a.n) p = 0;
+            if (p % period != phase) continue;
+            float ux, uy, uz;
+            fine_velocity(a.sp[s], a, ux, uy, uz);
+            const float4 m = a.uf4[p];
+            const double ex = (double)m.x - ux, ey = (double)m.y - uy, ez = (double)m.z - uz;
+            err += ex * ex + ey * ey + ez * ez;
+            ref += (double)ux * ux + (double)uy * uy + (double)uz * uz;
+            ns += 1.0;
+        }
         const double terr = wave_sum(err), tref = wave_sum(ref), tns = wave_sum(ns);
         const double tol = (double)a.mlp_tol;
         if (tns > 0.0 && terr > tol * tol * tref) {
-            for (int dz = 0; dz < kBrick && oz + dz < geo.nb[2]; ++dz)
-                for (int dy = 0; dy < kBrick && oy + dy < geo.nb[1]; ++dy) {
-                    const int64_t c0 = ox + (int64_t)geo.nb[0] * ((oy + dy) + (int64_t)geo.nb[1] * (oz + dz));
-                    const int64_t s0 = seg_clamp(a.start[c0], a.n), s1 = seg_clamp(a.start[c0 + wx], a.n);
-                    for (int64_t s = s0 + lane; s < s1; s += kWave) {
-                        int64_t p = a.perm[s];
-                        if (p < 0 || p >= a.n) p = 0;
-                        float4 m = a.uf4[p];
-                        fine_velocity(a.sp[s], a, m.x, m.y, m.z);
-                        a.uf4[p] = m;
-                        nfall += 1.0;
-                    }
-                }
+            for (int32_t j = lane; j < total; j += kWave) {
+                const int64_t s = position(j);
+                int64_t p = a.perm[s];
+                if (p < 0 || p >= a.n) p = 0;
+                float4 m = a.uf4[p];
+                fine_velocity(a.sp[s], a, m.x, m.y, m.z);
+                a.uf4[p] = m;
+                nfall += 1.0;
+            }
         }
     }
     const double vals[4] = {nfall, err, ref, ns};
