@@ -271,6 +271,53 @@ def test_step_inference_matches_oracle(env):
     net.close()
 
 
+def test_step_with_semi_implicit_and_two_fluid_drag(env):
+    """The options compose with the surrogate velocity: vel_source MLP with the
+    semi-implicit split and the two-fluid drag on.  Everything after the
+    velocity (drag with the mixed density and viscosity, sources, K and KU,
+    prolongation, sums) matches the oracle run with the GPU's velocity."""
+    torch, cpl, oracle = env
+    case = _small_case(torch, cpl, seed=23)
+    feat, ub, res = _features(torch, cpl, case)
+    X = feat.cpu().numpy().astype(np.float64)
+    R = res.cpu().numpy().astype(np.float64)
+    mean, std = M.norm_stats(X)
+    net = _net(torch, cpl, _params(6, bias_scale=0.2), mean, std, M.target_scale(R))
+    w = case["w"]
+    alpha = W.fine_alpha(w)
+    cfg = cfg_for(cpl, w, case["pos"].shape[0], vel_source=cpl.COUPLE_VEL_MLP)
+    cfg.mlp_tol, cfg.semi_implicit, cfg.vof, cfg.rho_f2, cfg.mu_f2 = 1e30, 1, 1, 1.2, 1.8e-5
+    print("case mlp + semi-implicit + two-fluid", flush=True)
+    c = cpl.Coupler(cfg)
+    try:
+        cpl.couple_set_mlp(c.h, net.m)
+        out = c.step(case["P"], case["V"], case["D"], case["Fd"], uf=True, alpha=to_dev(alpha, torch, "cuda:0"))
+        torch.cuda.synchronize()
+        g = {k: v.cpu().numpy() for k, v in out.items() if v is not None}
+        g["diag_d"] = cpl.diag_dict(out["diag"])
+    finally:
+        c.close()
+    o = oracle.step(case["pos"], case["vel"], case["d"], case["fine"], w.grid, rho_f=w.rho_f, mu_f=w.mu_f,
+                    rho_p=w.rho_p, eps_min=w.eps_min, cic=True, prec32=True, vel_source="given",
+                    bulk_velocity=g["uf"], semi_implicit=True, alpha=alpha, rho2=1.2, mu2=1.8e-5)
+    nb, r = w.grid.nb, w.grid.ratio
+    compare_step(g, o, case["pos"].shape[0], nb, r, fp64=False, box=w.grid.box, label="mlp+semi+vof")
+    nc = int(np.prod(nb))
+    from parity_util import emax, fine_scale_from_bulk, neighbourhood_max
+    errs = {
+        "alpha": emax(g["bulk_alpha"].ravel(), o["alpha"], field_scale=1.0),
+        "K": emax(g["bulk_K"].ravel(), o["K"]),
+        "KU": emax(g["bulk_KU"].reshape(3, nc), o["KU"], o["KU_mag"]),
+        "fine_K": emax(g["fine_K"].ravel(), o["fine_K"],
+                       fine_scale_from_bulk(neighbourhood_max(np.abs(o["K"]), nb), nb, r)),
+        "fine_KU": emax(g["fine_KU"].reshape(3, -1), o["fine_KU"],
+                        fine_scale_from_bulk(neighbourhood_max(o["KU_mag"], nb), nb, r)),
+    }
+    print("mlp + semi + vof e_max:", {k: f"{v:.2e}" for k, v in errs.items()})
+    assert max(errs.values()) <= TOL_FP32_FIELD
+    net.close()
+
+
 def _bricks_with_sample(cell, nb, period, phase):
     ids = np.arange(cell.size)
     c = cell.astype(np.int64)
