@@ -118,6 +118,62 @@ def test_bed128_full_size_sampled(env):
     print("bed128 e_max:", {k: f"{v:.2e}" for k, v in errs.items()})
 
 
+def test_bed128_semi_implicit_two_fluid_full_size_sampled(env):
+    """The 10M-particle bed at full size with the semi-implicit split and the
+    two-fluid drag on (the benchmark's variant legs, both at once): every bulk
+    and particle output, K, KU and the restricted alpha against the oracle; the
+    fine-grid outputs (eps, F, K, KU) on 200,000 sampled fine cells."""
+    torch, cpl, oracle = env
+    from parity_util import emax, fine_scale_from_bulk, neighbourhood_max
+    w = W.WORKLOADS["bed128_cic"]
+    pos, d, vel, fine = _bed_inputs(w)
+    alpha = W.fine_alpha(w)
+    n = pos.shape[0]
+    cfg = cfg_for(cpl, w, n)
+    cfg.semi_implicit, cfg.vof, cfg.rho_f2, cfg.mu_f2 = 1, 1, 1.2, 1.8e-5
+    print(f"case bed128 semi-implicit + two-fluid n={n}", flush=True)
+    dev = "cuda:0"
+    P, V, D = to_dev(pos, torch, dev), to_dev(vel, torch, dev), to_dev(d, torch, dev)
+    Fd = [to_dev(f, torch, dev) for f in fine]
+    A = to_dev(alpha, torch, dev)
+    c = cpl.Coupler(cfg)
+    out = c.step(P, V, D, Fd, alpha=A)
+    torch.cuda.synchronize()
+    sample = np.random.default_rng(12).integers(0, w.grid.n_fine, 200_000)
+    si = torch.from_numpy(sample).to(dev)
+    g = {k: (v.cpu().numpy() if v is not None and not k.startswith("fine") else None) for k, v in out.items()}
+    g["fine_eps"] = out["fine_eps"].reshape(-1)[si].cpu().numpy()
+    g["fine_F"] = out["fine_F"].reshape(3, -1)[:, si].cpu().numpy()
+    g["fine_K"] = out["fine_K"].reshape(-1)[si].cpu().numpy()
+    g["fine_KU"] = out["fine_KU"].reshape(3, -1)[:, si].cpu().numpy()
+    g["diag_d"] = cpl.diag_dict(out["diag"])
+    c.close()
+    del P, V, D, Fd, A, out
+    torch.cuda.empty_cache()
+    o = oracle.step(pos, vel, d, fine, w.grid, rho_f=w.rho_f, mu_f=w.mu_f, rho_p=w.rho_p, eps_min=w.eps_min,
+                    cic=True, prec32=True, vel_source="fine", fine_out="sample", fine_sample=sample,
+                    semi_implicit=True, alpha=alpha, rho2=1.2, mu2=1.8e-5)
+    nb, r = w.grid.nb, w.grid.ratio
+    errs = compare_step(g, o, n, nb, r, box=w.grid.box, fp64=False, fine_sample=np.arange(sample.size),
+                        label="bed128 semi+vof", fine_sample_index=sample)
+    nc = int(np.prod(nb))
+    errs.update({
+        "alpha": emax(g["bulk_alpha"].ravel(), o["alpha"], field_scale=1.0),
+        "K": emax(g["bulk_K"].ravel(), o["K"]),
+        "KU": emax(g["bulk_KU"].reshape(3, nc), o["KU"], o["KU_mag"]),
+        "fine_K": emax(g["fine_K"], o["fine_K"],
+                       fine_scale_from_bulk(neighbourhood_max(np.abs(o["K"]), nb), nb, r, sample)),
+        "fine_KU": emax(g["fine_KU"], o["fine_KU"],
+                        fine_scale_from_bulk(neighbourhood_max(o["KU_mag"], nb), nb, r, sample)),
+    })
+    print("bed128 semi+vof e_max:", {k: f"{v:.2e}" for k, v in errs.items()})
+    assert max(errs.values()) <= TOL_FP32_FIELD
+    dg, od = g["diag_d"], o["diag"]
+    assert abs(dg["K_p"] - od["K_p"]) <= 1e-6 * od["K_p"]
+    assert abs(dg["K_b"] - dg["K_p"]) <= 1e-6 * od["K_p"]
+    assert abs(dg["K_f"] - dg["K_b"]) <= 1e-6 * od["K_p"]
+
+
 def test_precision_study_bed128_sub2m(env, tmp_path):
     """Compensated FP32 vs naive FP32 vs FP64 on the GPU, each against the FP64
     oracle, on the 2M-particle subsample of the bed (same grids): per-field max
