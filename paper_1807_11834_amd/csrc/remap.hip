@@ -125,10 +125,12 @@ __global__ __launch_bounds__(kBlock) void k_remap_rows(RemapArgs<T> r, const T *
 }
 
 // A tile of kTileJ x kTileK receiver rows (y, z) of one field per workgroup,
-// for receivers finer than the sender in y and z: the sender slab under the tile
-// (its overlapping y and z rows, whole x extent) is staged in LDS once with
-// coalesced loads, and every receiver cell of the tile sums its (z, y, x)
-// overlaps from LDS in raster order.
+// for receivers finer than the sender in y and z.  The sender slab under the
+// tile (its overlapping y and z rows, whole x extent) is staged in LDS with
+// coalesced loads; every slab row is then transferred along x into a second LDS
+// buffer (rx, receiver x resolution); finally each receiver cell sums its
+// (z, y) overlaps of rx.  Sum order: x within each sender row, then (z, y) in
+// raster order.
 constexpr int kTileJ = 8, kTileK = 8;
 constexpr int kMaxX = 4;   // x factors held in registers (longer ranges read them in the loop)
 
@@ -136,7 +138,6 @@ template <typename T, bool KAHAN>
 __global__ __launch_bounds__(kBlock) void k_remap_tile(RemapArgs<T> r, const T *__restrict__ src,
                                                        T *__restrict__ dst) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    T *slab = reinterpret_cast<T *>(lds_raw);
     const int tny = (r.nd[1] + kTileJ - 1) / kTileJ;
     const int64_t t = xcd_tile(blockIdx.x, gridDim.x);
     const int j0 = (int)(t % tny) * kTileJ, k0 = (int)(t / tny) * kTileK;
@@ -144,43 +145,52 @@ __global__ __launch_bounds__(kBlock) void k_remap_tile(RemapArgs<T> r, const T *
     const int k1 = k0 + kTileK < r.nd[2] ? k0 + kTileK : r.nd[2];
     const int ys0 = r.first[1][j0], ys1 = r.first[1][j1 - 1] + r.cnt[1][j1 - 1];
     const int zs0 = r.first[2][k0], zs1 = r.first[2][k1 - 1] + r.cnt[2][k1 - 1];
-    const int Ys = ys1 - ys0, nsx = r.ns[0];
+    const int Ys = ys1 - ys0, nsx = r.ns[0], ndx = r.nd[0];
+    const int nrows = (zs1 - zs0) * Ys;   // sender rows of the slab
+    T *slab = reinterpret_cast<T *>(lds_raw);
+    T *rx = slab + (size_t)nrows * nsx;
     const int64_t sxy = (int64_t)r.ns[0] * r.ns[1];
     const T *__restrict__ s = src + (int64_t)blockIdx.y * r.nsrc;
-    const int nslab = (zs1 - zs0) * Ys * nsx;
+    const int nslab = nrows * nsx;
     for (int e = threadIdx.x; e < nslab; e += kBlock) {
         const int x = e % nsx, yy = (e / nsx) % Ys, zz = e / (nsx * Ys);
         slab[e] = s[(int64_t)(zs0 + zz) * sxy + (int64_t)(ys0 + yy) * nsx + x];
     }
     __syncthreads();
-    // each thread keeps the x factor of its receiver columns in registers and
-    // walks the tile's rows, whose y and z factors are uniform; the (large,
-    // write-once) receiver field is stored non-temporally
-    const int ndx = r.nd[0];
-    T *__restrict__ out = dst + (int64_t)blockIdx.y * r.ndst;
+    // x transfer of every slab row; each thread keeps the x factor of its
+    // receiver columns in registers
     for (int xd = threadIdx.x; xd < ndx; xd += kBlock) {
         const int fx = r.first[0][xd], nx = r.cnt[0][xd], ox = r.off[0][xd];
         T wx[kMaxX];
 #pragma unroll
         for (int q = 0; q < kMaxX; ++q) wx[q] = q < nx ? r.w[0][ox + q] : T(0);
-        for (int k = k0; k < k1; ++k) {
-            const int fz = r.first[2][k], nz = r.cnt[2][k], oz = r.off[2][k];
-            for (int j = j0; j < j1; ++j) {
-                const int fy = r.first[1][j], ny = r.cnt[1][j], oy = r.off[1][j];
+        for (int row = 0; row < nrows; ++row) {
+            const T *sr = slab + (size_t)row * nsx + fx;
+            Acc<T, KAHAN> acc;
+            if (nx <= kMaxX) {
+#pragma unroll
+                for (int q = 0; q < kMaxX; ++q)
+                    if (q < nx) acc.add(wx[q] * sr[q]);
+            } else {
+                for (int kx = 0; kx < nx; ++kx) acc.add(r.w[0][ox + kx] * sr[kx]);
+            }
+            rx[(size_t)row * ndx + xd] = acc.s;
+        }
+    }
+    __syncthreads();
+    // (z, y) overlaps of each receiver cell; the row factors are uniform, the
+    // (large, write-once) receiver field is stored non-temporally
+    T *__restrict__ out = dst + (int64_t)blockIdx.y * r.ndst;
+    for (int k = k0; k < k1; ++k) {
+        const int fz = r.first[2][k], nz = r.cnt[2][k], oz = r.off[2][k];
+        for (int j = j0; j < j1; ++j) {
+            const int fy = r.first[1][j], ny = r.cnt[1][j], oy = r.off[1][j];
+            for (int xd = threadIdx.x; xd < ndx; xd += kBlock) {
                 Acc<T, KAHAN> acc;
                 for (int kz = 0; kz < nz; ++kz) {
                     const T wz = r.w[2][oz + kz];
-                    for (int ky = 0; ky < ny; ++ky) {
-                        const T wyz = wz * r.w[1][oy + ky];
-                        const T *row = slab + ((fz + kz - zs0) * Ys + (fy + ky - ys0)) * nsx + fx;
-                        if (nx <= kMaxX) {
-#pragma unroll
-                            for (int q = 0; q < kMaxX; ++q)
-                                if (q < nx) acc.add((wyz * wx[q]) * row[q]);
-                        } else {
-                            for (int kx = 0; kx < nx; ++kx) acc.add((wyz * r.w[0][ox + kx]) * row[kx]);
-                        }
-                    }
+                    const T *rr = rx + ((size_t)(fz + kz - zs0) * Ys + (fy - ys0)) * ndx + xd;
+                    for (int ky = 0; ky < ny; ++ky) acc.add((wz * r.w[1][oy + ky]) * rr[(size_t)ky * ndx]);
                 }
                 __builtin_nontemporal_store(acc.s, &out[((int64_t)k * r.nd[1] + j) * ndx + xd]);
             }
@@ -188,9 +198,9 @@ __global__ __launch_bounds__(kBlock) void k_remap_tile(RemapArgs<T> r, const T *
     }
 }
 
-// Sender slabs under a receiver tile up to this many bytes take k_remap_tile
-// when the receiver is finer than the sender in both y and z.
-constexpr size_t kTileLdsBytes = 48 * 1024;
+// Tiles whose sender slab and x-transferred rows take up to this many bytes of
+// LDS use k_remap_tile when the receiver is finer than the sender in y and z.
+constexpr size_t kTileLdsBytes = 96 * 1024;
 
 // Sender rows up to this many bytes are staged whole in LDS by k_remap_rows;
 // longer rows take k_remap.
@@ -368,8 +378,15 @@ static hipError_t launch_remap(const couple_remap *r, const void *src, void *dst
         a.ndst *= r->nd[k];
     }
     const size_t lds = sizeof(T) * (size_t)r->ns[0];
-    const size_t tile_lds = lds * r->tile_slab_rows;
-    if (r->tile_slab_rows > 0 && tile_lds <= kTileLdsBytes) {
+    const size_t tile_lds = sizeof(T) * r->tile_slab_rows * ((size_t)r->ns[0] + r->nd[0]);   // slab + rx
+    bool tile_ok = r->tile_slab_rows > 0 && tile_lds <= kTileLdsBytes;
+    if (tile_ok && tile_lds > 64 * 1024) {
+        // more than 64 KB of dynamic LDS per workgroup must be allowed explicitly
+        tile_ok = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_remap_tile<T, KAHAN>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)tile_lds) == hipSuccess;
+        if (!tile_ok) (void)hipGetLastError();
+    }
+    if (tile_ok) {
         const int64_t ntile = (int64_t)((r->nd[1] + kTileJ - 1) / kTileJ) * ((r->nd[2] + kTileK - 1) / kTileK);
         hipLaunchKernelGGL((k_remap_tile<T, KAHAN>), dim3((unsigned)ntile, (unsigned)nfields), dim3(kBlock), tile_lds,
                            st, a, static_cast<const T *>(src), static_cast<T *>(dst));
