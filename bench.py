@@ -75,17 +75,26 @@ TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_bed128.json")
 UNPROFILED_SOURCES = ("remap.hip",)
 
 
+def _code_only(text):
+    """Source text without comments, trailing blanks and blank lines (none of
+    which changes the build)."""
+    import re
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(l.rstrip() for l in text.splitlines() if l.strip())
+
+
 def csrc_sha256():
-    """Hash of the HIP sources of the coupling step and the surrogate: profiled
-    counters apply only to this build."""
+    """Hash of the HIP sources (code only) of the coupling step and the
+    surrogate: profiled counters apply only to this build."""
     import hashlib
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1807_11834_amd", "csrc")
     for f in sorted(os.listdir(d)):
         if f.endswith((".hip", ".hpp")) and f not in UNPROFILED_SOURCES:
             h.update(f.encode())
-            with open(os.path.join(d, f), "rb") as fh:
-                h.update(fh.read())
+            with open(os.path.join(d, f), encoding="utf-8") as fh:
+                h.update(_code_only(fh.read()).encode())
     return h.hexdigest()
 
 

@@ -482,7 +482,7 @@ __global__ __launch_bounds__(kBlock) void k_pack(StepArgs<float> a) {
     a.fgrid[2 * c + 1] = make_float4(gr[0], gr[1], gr[2], 0.f);
 }
 
-constexpr int kInfWaves = 8;                    // waves per workgroup (two per SIMD)
+constexpr int kInfWaves = 8;                    // waves per workgroup (two per SIMD: the LDS and 256 VGPRs per wave)
 constexpr int kInfTiles = 2;                    // 16-particle tiles per wave and round
 constexpr int kInfRows = 16 * kInfTiles;        // particles per wave and round
 constexpr int kFrag1 = 8 * 7, kFragH = 8 * 4;   // operand fragments per layer

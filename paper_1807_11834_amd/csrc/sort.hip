@@ -12,8 +12,9 @@
 //   k_radix_prefix exclusive prefix over tiles of every digit, digit totals;
 //   k_radix_scatter stable ranking inside a tile (wave ballots, LDS staging) and
 //                  coalesced scatter to the digit's output run;
-//   k_segments     start[c] = first sorted position with cell >= c (binary
-//                  search), count[c] = start[c+1] - start[c].
+//   k_segments     start[c] = first sorted position with cell >= c (the key
+//                  changes within a 256-cell block, located by two binary
+//                  searches and staged in LDS), count[c] = start[c+1] - start[c].
 //
 // Keys are cell indices < ncell; ids are the input order, so a stable LSD sort
 // starting from the identity order gives ascending (cell, id).  Integer atomics
