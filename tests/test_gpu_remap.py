@@ -54,6 +54,10 @@ CASES = [
     ((32, 24, 20), (8, 6, 5), (1.0, 0.75, 0.625), "uniform", "fp32n", 1),
     ((1, 30, 2), (1, 7, 5), (0.1, 1.0, 0.3), "random", "fp32k", 1),
     ((61, 3, 47), (29, 5, 13), (1.0, 0.1, 0.8), "random", "fp32k", 1),
+    # single cells
+    ((1, 1, 1), (1, 1, 1), (0.5, 0.25, 2.0), "uniform", "fp32k", 2),
+    ((1, 1, 1), (3, 2, 5), (0.5, 0.25, 2.0), "random", "fp64", 1),
+    ((4, 7, 3), (1, 1, 1), (0.5, 0.25, 2.0), "random", "fp32k", 1),
     # sender rows longer than the LDS row buffer: the per-cell kernel
     ((20000, 2, 1), (7, 3, 2), (1.0, 0.2, 0.1), "random", "fp32k", 1),
     ((9000, 1, 2), (13, 1, 1), (1.0, 0.1, 0.1), "uniform", "fp64", 1),

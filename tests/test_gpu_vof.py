@@ -99,3 +99,24 @@ def test_vof_needs_alpha(env):
         assert ei.value.code == cpl.COUPLE_EINVAL and "vof" in str(ei.value)
     finally:
         c.close()
+
+
+def test_zero_particles_with_semi_implicit_and_two_fluid(env):
+    """No particles, both options on: alpha is still restricted (against the
+    oracle), K, KU and their prolongations are zero, every sum is zero."""
+    torch, cpl, oracle = env
+    w = W.small_workload(nb=(6, 5, 4), ratio=4, n=0, seed=3, precision="fp32")
+    pos, d, vel = (np.zeros((0, 3), np.float32), np.zeros(0, np.float32), np.zeros((0, 3), np.float32))
+    alpha = W.fine_alpha(w)
+    cfg = cfg_for(cpl, w, 0)
+    cfg.vof, cfg.rho_f2, cfg.mu_f2, cfg.semi_implicit = 1, RHO2, MU2, 1
+    print("case zero particles semi + vof", flush=True)
+    g = run_gpu(cpl, torch, cfg, pos, vel, d, W.fine_fields(w), alpha=alpha)
+    a_ref = oracle.restrict(alpha, w.grid.nb, w.grid.ratio)
+    assert emax(g["bulk_alpha"].ravel(), a_ref, field_scale=1.0) <= TOL_FP32_FIELD
+    for k in ("bulk_K", "bulk_KU", "fine_K", "fine_KU", "bulk_phi", "bulk_F", "fine_F"):
+        assert np.all(g[k] == 0), k
+    for k in ("K_p", "K_b", "K_f"):
+        assert g["diag_d"][k] == 0.0
+    assert all(v == 0.0 for v in g["diag_d"]["KU_f"])
+
