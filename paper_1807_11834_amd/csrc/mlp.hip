@@ -157,12 +157,15 @@ __global__ __launch_bounds__(kBlock) void k_standardise(const float *__restrict_
 //   hidden: Z -> z (FP32), gelu(Z) -> h (BF16), both [B][16 MB];
 //   output (MB = 1): Z -> y [B][16]; with targets T [B][4] also the loss partial
 //   of the tile and dY = (Y - T) / B as FP32 [B][16] and BF16 [B][32].
+// HT (may be NULL): the BF16 result (h, or dY for the output layer) also
+// written transposed, [16 MB][B], for the weight-gradient products.
 template <int KB, int MB, bool OUT>
 __global__ __launch_bounds__(kBlock) void k_dense(const uint16_t *__restrict__ X, const uint16_t *__restrict__ WT,
                                                   const float *__restrict__ bias, int M, int64_t B,
                                                   float *__restrict__ Z, uint16_t *__restrict__ H,
                                                   const float *__restrict__ T, float inv_b, float *__restrict__ dzf,
-                                                  uint16_t *__restrict__ dz, double *__restrict__ loss_part) {
+                                                  uint16_t *__restrict__ dz, double *__restrict__ loss_part,
+                                                  uint16_t *__restrict__ HT) {
     constexpr int KP = 32 * KB, MP = 16 * MB;
     const int lane = lane_id(), n = lane & 15, g = lane >> 4;
     const int64_t ntile = (B + 15) / 16;
@@ -186,8 +189,14 @@ __global__ __launch_bounds__(kBlock) void k_dense(const uint16_t *__restrict__ X
         if constexpr (!OUT) {
             if (valid) {
                 *reinterpret_cast<float4 *>(Z + b * MP + m0) = make_float4(z[0], z[1], z[2], z[3]);
-                *reinterpret_cast<uint2 *>(H + b * MP + m0) =
-                    make_uint2(pack2(gelu(z[0]), gelu(z[1])), pack2(gelu(z[2]), gelu(z[3])));
+                const uint2 hv = make_uint2(pack2(gelu(z[0]), gelu(z[1])), pack2(gelu(z[2]), gelu(z[3])));
+                *reinterpret_cast<uint2 *>(H + b * MP + m0) = hv;
+                if (HT) {
+                    HT[(int64_t)(m0 + 0) * B + b] = (uint16_t)(hv.x & 0xffffu);
+                    HT[(int64_t)(m0 + 1) * B + b] = (uint16_t)(hv.x >> 16);
+                    HT[(int64_t)(m0 + 2) * B + b] = (uint16_t)(hv.y & 0xffffu);
+                    HT[(int64_t)(m0 + 3) * B + b] = (uint16_t)(hv.y >> 16);
+                }
             }
         } else {
             if (valid) *reinterpret_cast<float4 *>(Z + b * MP + m0) = make_float4(z[0], z[1], z[2], z[3]);
@@ -201,7 +210,14 @@ __global__ __launch_bounds__(kBlock) void k_dense(const uint16_t *__restrict__ X
                 }
                 if (valid) {
                     *reinterpret_cast<float4 *>(dzf + b * MP + m0) = make_float4(d[0], d[1], d[2], d[3]);
-                    *reinterpret_cast<uint2 *>(dz + b * 32 + m0) = make_uint2(pack2(d[0], d[1]), pack2(d[2], d[3]));
+                    const uint2 dv = make_uint2(pack2(d[0], d[1]), pack2(d[2], d[3]));
+                    *reinterpret_cast<uint2 *>(dz + b * 32 + m0) = dv;
+                    if (HT) {
+                        HT[(int64_t)(m0 + 0) * B + b] = (uint16_t)(dv.x & 0xffffu);
+                        HT[(int64_t)(m0 + 1) * B + b] = (uint16_t)(dv.x >> 16);
+                        HT[(int64_t)(m0 + 2) * B + b] = (uint16_t)(dv.y & 0xffffu);
+                        HT[(int64_t)(m0 + 3) * B + b] = (uint16_t)(dv.y >> 16);
+                    }
                 }
             }
         }
@@ -216,11 +232,13 @@ __global__ __launch_bounds__(kBlock) void k_dense(const uint16_t *__restrict__ X
 
 // Input gradient of a layer times gelu' of the previous pre-activation:
 //   dZp = (dZ W^T) .* gelu'(Zp),  dZ [B][32 KC] BF16, W [16 NB][32 KC] BF16,
-//   Zp [B][16 NB] FP32 -> dZp as FP32 and BF16 [B][16 NB].
+//   Zp [B][16 NB] FP32 -> dZp as FP32 and BF16 [B][16 NB], and the BF16 values
+//   transposed, dzpT [16 NB][B], for the weight-gradient products.
 template <int KC, int NB>
 __global__ __launch_bounds__(kBlock) void k_dense_bwd(const uint16_t *__restrict__ dZ, const uint16_t *__restrict__ W,
                                                       const float *__restrict__ Zp, int64_t B,
-                                                      float *__restrict__ dzpf, uint16_t *__restrict__ dzp) {
+                                                      float *__restrict__ dzpf, uint16_t *__restrict__ dzp,
+                                                      uint16_t *__restrict__ dzpT) {
     constexpr int MC = 32 * KC, KI = 16 * NB;
     const int lane = lane_id(), n = lane & 15, g = lane >> 4;
     const int64_t ntile = (B + 15) / 16;
@@ -242,7 +260,12 @@ __global__ __launch_bounds__(kBlock) void k_dense_bwd(const uint16_t *__restrict
             const float d0 = acc[0] * gelu_grad(zp.x), d1 = acc[1] * gelu_grad(zp.y);
             const float d2 = acc[2] * gelu_grad(zp.z), d3 = acc[3] * gelu_grad(zp.w);
             *reinterpret_cast<float4 *>(dzpf + b * KI + k0) = make_float4(d0, d1, d2, d3);
-            *reinterpret_cast<uint2 *>(dzp + b * KI + k0) = make_uint2(pack2(d0, d1), pack2(d2, d3));
+            const uint2 dv = make_uint2(pack2(d0, d1), pack2(d2, d3));
+            *reinterpret_cast<uint2 *>(dzp + b * KI + k0) = dv;
+            dzpT[(int64_t)(k0 + 0) * B + b] = (uint16_t)(dv.x & 0xffffu);
+            dzpT[(int64_t)(k0 + 1) * B + b] = (uint16_t)(dv.x >> 16);
+            dzpT[(int64_t)(k0 + 2) * B + b] = (uint16_t)(dv.y & 0xffffu);
+            dzpT[(int64_t)(k0 + 3) * B + b] = (uint16_t)(dv.y >> 16);
         }
     }
 }
@@ -915,14 +938,18 @@ hipError_t launch_forward(const NetBufs &net, const TrainBufs &tb, int64_t B, bo
     if (B <= 0) return hipSuccess;
     const dim3 gr(tile_blocks(B)), bl(kBlock);
     const float *p = net.params;
+    // a training pass (with_loss) also writes the transposed copies that the
+    // weight-gradient products read
+    auto T = [&](uint16_t *q) { return with_loss ? q : nullptr; };
     hipLaunchKernelGGL((k_dense<7, 8, false>), gr, bl, 0, st, tb.x0, net.wt[0], p + off_b(0), kHid, B, tb.z[0], tb.h[0],
-                       nullptr, 0.f, nullptr, nullptr, nullptr);
+                       nullptr, 0.f, nullptr, nullptr, nullptr, T(tb.ht[0]));
     hipLaunchKernelGGL((k_dense<4, 8, false>), gr, bl, 0, st, tb.h[0], net.wt[1], p + off_b(1), kHid, B, tb.z[1], tb.h[1],
-                       nullptr, 0.f, nullptr, nullptr, nullptr);
+                       nullptr, 0.f, nullptr, nullptr, nullptr, T(tb.ht[1]));
     hipLaunchKernelGGL((k_dense<4, 8, false>), gr, bl, 0, st, tb.h[1], net.wt[2], p + off_b(2), kHid, B, tb.z[2], tb.h[2],
-                       nullptr, 0.f, nullptr, nullptr, nullptr);
+                       nullptr, 0.f, nullptr, nullptr, nullptr, T(tb.ht[2]));
     hipLaunchKernelGGL((k_dense<4, 1, true>), gr, bl, 0, st, tb.h[2], net.wt[3], p + off_b(3), kOut, B, tb.y, nullptr,
-                       with_loss ? tb.t : nullptr, (float)(1.0 / (double)B), tb.dzf[3], tb.dz[3], tb.loss_part);
+                       with_loss ? tb.t : nullptr, (float)(1.0 / (double)B), tb.dzf[3], tb.dz[3], tb.loss_part,
+                       T(tb.dzt[3]));
     return hipGetLastError();
 }
 
@@ -935,16 +962,15 @@ hipError_t launch_backward(const NetBufs &net, const TrainBufs &tb, int64_t B, f
                            hipStream_t st) {
     const dim3 gr(tile_blocks(B)), bl(kBlock);
     // input gradients of layers 4, 3, 2 (each times gelu' of the layer below)
-    hipLaunchKernelGGL((k_dense_bwd<1, 8>), gr, bl, 0, st, tb.dz[3], net.wn[3], tb.z[2], B, tb.dzf[2], tb.dz[2]);
-    hipLaunchKernelGGL((k_dense_bwd<4, 8>), gr, bl, 0, st, tb.dz[2], net.wn[2], tb.z[1], B, tb.dzf[1], tb.dz[1]);
-    hipLaunchKernelGGL((k_dense_bwd<4, 8>), gr, bl, 0, st, tb.dz[1], net.wn[1], tb.z[0], B, tb.dzf[0], tb.dz[0]);
-    // transposed copies for the products over the batch
+    hipLaunchKernelGGL((k_dense_bwd<1, 8>), gr, bl, 0, st, tb.dz[3], net.wn[3], tb.z[2], B, tb.dzf[2], tb.dz[2],
+                       tb.dzt[2]);
+    hipLaunchKernelGGL((k_dense_bwd<4, 8>), gr, bl, 0, st, tb.dz[2], net.wn[2], tb.z[1], B, tb.dzf[1], tb.dz[1],
+                       tb.dzt[1]);
+    hipLaunchKernelGGL((k_dense_bwd<4, 8>), gr, bl, 0, st, tb.dz[1], net.wn[1], tb.z[0], B, tb.dzf[0], tb.dz[0],
+                       tb.dzt[0]);
+    // the transposed layer input for the first layer's products over the batch
+    // (the other transposed copies were written by their producing kernels)
     transpose(tb.x0, B, kK1, tb.x0t, st);
-    for (int l = 0; l < 3; ++l) {
-        transpose(tb.h[l], B, kHid, tb.ht[l], st);
-        transpose(tb.dz[l], B, kHid, tb.dzt[l], st);
-    }
-    transpose(tb.dz[3], B, 32, tb.dzt[3], st);
     const unsigned nc = (unsigned)n_chunks(B);
     hipLaunchKernelGGL((k_wgrad<8, 14>), dim3(nc), bl, 0, st, tb.dzt[0], tb.x0t, tb.dzf[0], B, tb.part_w[0], tb.part_b[0]);
     hipLaunchKernelGGL((k_wgrad<8, 8>), dim3(nc), bl, 0, st, tb.dzt[1], tb.ht[0], tb.dzf[1], B, tb.part_w[1], tb.part_b[1]);
