@@ -365,6 +365,30 @@ def _time_variant(args, cfg_v, pos, vel, diam, fine, n, dev, alpha=None):
     return ms, {k: t / l for k, (l, t) in stats.items() if l}, d
 
 
+def stream_copy(dev, steps=20):
+    """Achievable HBM bandwidth on this device: a plain 1 GiB device-to-device
+    copy (torch), read + write bytes over its average time."""
+    import torch
+    src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    gbps = 2 * (1 << 30) / (ms * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"kernel": "torch copy_ of 1 GiB (device to device)", "GBps": round(gbps, 1),
+            "frac_of_peak": round(gbps / HBM_PEAK_GBPS, 4)}
+
+
 def semi_leg(args, cfg, pos, vel, diam, fine, plain_ms, n, g, fsz, dev):
     """The same step with the semi-implicit split on (K, KU deposited and
     prolonged in addition): time per step, the extra kernels and the prolongation
@@ -551,6 +575,7 @@ def main():
                 "frac": round(ach / HBM_PEAK_GBPS, 4), "traffic": profiled_traffic(dom),
                 "alg_bytes_per_launch": ab, "avg_ms": round(kernels[dom]["avg_ms"], 4)}
     sb = step_alg_bytes(n, g.n_bulk, g.n_fine, fsz, sort_passes(g.n_bulk))
+    copy_bw = stream_copy(dev)
     d = cpl.diag_dict(out["diag"])
     rec = {
         "metric": METRIC, "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
@@ -563,6 +588,7 @@ def main():
         "roofline": roof,
         "step_alg_bytes": sb, "step_alg_GBps": round(sb / (ms_step * 1e-3) / 1e9, 1),
         "step_alg_frac_hbm": round(sb / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+        "hbm_stream_copy": copy_bw,
         "kernels_avg_ms": {k: round(v["avg_ms"], 4) for k, v in kernels.items()},
         "conservation": {"V_dep/V_tot-1": d["V_dep"] / d["V_tot"] - 1 if d["V_tot"] else 0.0,
                          "S_b+sumF": [d["S_b"][a] + d["sum_Fp"][a] for a in range(3)]},
