@@ -133,7 +133,7 @@ extern "C" int couple_init(const couple_config *cfg, couple_handle **out) {
               dev_alloc(&h->sort.hist, sizeof(uint32_t) * 256 * ntile) && dev_alloc(&h->sort.totals, sizeof(uint32_t) * 256) &&
               dev_alloc(&h->sp, 4 * fsz * nmax) && dev_alloc(&h->uf4, 4 * fsz * nmax) &&
               dev_alloc(&h->plo, fsz * h->ncell) &&
-              dev_alloc(&h->dep, (cfg->deposit == COUPLE_CIC ? (cfg->semi_implicit ? 36 : 27) : 1) * fsz * h->ncell) &&
+              dev_alloc(&h->dep, (cfg->deposit == COUPLE_CIC ? (cfg->semi_implicit ? 16 : 12) : 1) * fsz * h->ncell) &&
               dev_alloc(&h->part, sizeof(double) * (SL_COUNT * h->part_stride + SL_COUNT * 64)) &&
               (cfg->vel_source != COUPLE_VEL_MLP || dev_alloc(&h->fgrid, sizeof(float4) * 2 * h->ncell));
     if (!ok) {

@@ -17,6 +17,7 @@
 namespace cpl {
 
 constexpr int kChunk = 256;   // particles staged per wave and chunk
+static_assert(kChunk % kWave == 0, "a chunk is staged in whole waves");
 
 // What a deposition pass sums: V_p / V_b (phi), the drag F_p (source) or
 // (beta_p, beta_p u_p) (semi-implicit split).
@@ -116,21 +117,39 @@ __global__ __launch_bounds__(kBlock) void k_deposit_ngp(const int32_t *__restric
 // ---------------------------------------------------------------------------
 // CIC (trilinear to the 8 nearest bulk cell centres, folded at the walls)
 // ---------------------------------------------------------------------------
-// Pass 1, k_deposit_rows: one wave per (source row, 64-cell x segment).  The wave
-// stages the particles of the source cells x0-1 .. x0+64 once (in chunks), with
-// their x-stencil, their weights on the three target y-rows and z-rows around the
+// Pass 1, k_deposit_rows: one wave per (2 x 2 group of source rows in y and z,
+// 64-cell x segment).  For each source row of its group the wave stages the
+// particles of the source cells x0-1 .. x0+64 once (in chunks), with their
+// x-stencil, their weights on the three target y-rows and z-rows around the
 // source row and the deposited value(s).  Lane x then accumulates, over the
 // particles of source cells x-1, x, x+1 in canonical order, the contributions to
-// target cell x of the 3 x 3 target rows, and writes them to the partial slot
-// (source offset) of each target cell.
-// Pass 2, k_deposit_sum: per target cell, the 9 partials of its source rows in
-// ascending row order.
+// target cell x of the 4 x 4 target rows the group reaches (y-rows 2gy-1 ..
+// 2gy+2, z-layers 2gz-1 .. 2gz+2), and writes each to the partial slot of its
+// (z-group, y-group) offset from the target.
+// Pass 2, k_deposit_sum: per target cell, the <= 4 partials of the source groups
+// it receives from, in ascending (z-group, y-group) order.
+// A target row receives from 2 x 2 groups rather than from 3 x 3 source rows:
+// the partial sums written and read back are 4/9 of one slot per source row.
 template <typename T, int MODE> struct RowStage {
     int node[kWavesPerBlock][kChunk];                  // x-stencil nodes lo | hi << 16
     T tx[kWavesPerBlock][kChunk];                      // weight of hi
     T wy[3][kWavesPerBlock][kChunk];                   // weight on target rows y'-1, y', y'+1
     T wz[3][kWavesPerBlock][kChunk];                   // weight on target layers z'-1, z', z'+1
     T val[DepNc<MODE>::value][kWavesPerBlock][kChunk]; // V_p / V_b, F_p, or (beta_p, beta_p u_p)
+};
+
+// Row-pass sums s += w v.  Where the mode compensates its sums, the weights and
+// values are widened to FP64 and summed there with one FMA per term.  In the
+// FP32 mode both products are exact in FP64, so every term is rounded once at
+// FP64 precision: at least as accurate as a Kahan-compensated FP32 sum, for one
+// instruction per term instead of five (FP64 FMAs issue at the rate of unpacked
+// FP32 ones on this chip).  In the FP64 mode the at most ~100 terms of a partial
+// sum carry a relative error below 1e-14 of their magnitudes.  The naive FP32
+// mode sums with plain FP32 FMAs.
+template <typename T, bool KAHAN> struct RowSum {
+    using W = typename std::conditional<KAHAN, double, T>::type;
+    W s = W(0);
+    __device__ __forceinline__ void add(W w, W v) { s = fma(w, v, s); }
 };
 
 template <typename T>
@@ -141,6 +160,121 @@ __device__ __forceinline__ void row_weights(const Axis<T> &a, int c, T w[3]) {
         if (a.lo == t) v += T(1) - a.t;
         if (a.hi == t) v += a.t;
         w[j] = v;
+    }
+}
+
+// Lowest source group (of 2 rows) that reaches target row t: floor((t - 1) / 2).
+__device__ __forceinline__ int group_lo(int t) { return ((t + 1) >> 1) - 1; }
+
+// One source row (ys, zs) of the wave's group: row JY, layer KZ of the group.
+// Its contributions go to the accumulators [KZ + 0..2][JY + 0..2].
+template <typename T, bool KAHAN, int MODE, int JY, int KZ>
+__device__ __forceinline__ void deposit_source_row(RowSum<T, KAHAN> (&acc)[4][4][DepNc<MODE>::value],
+                                                   RowStage<T, MODE> &st, int w, int lane, int x0, int ys, int zs,
+                                                   const int32_t *__restrict__ start, const vec4<T> *__restrict__ sp,
+                                                   const int32_t *__restrict__ perm, const T *__restrict__ drag,
+                                                   const vec4<T> *__restrict__ src4, int64_t n, const Geo<T> &g) {
+    constexpr int NC = DepNc<MODE>::value;
+    using W = typename RowSum<T, KAHAN>::W;
+    const int nbx = g.nb[0], nby = g.nb[1], nbz = g.nb[2];
+    const int x = x0 + lane;
+    const int64_t srow = ((int64_t)zs * nby + ys) * nbx;
+    const int xa = x0 > 0 ? x0 - 1 : 0;
+    const int xb = (x0 + kWave < nbx ? x0 + kWave : nbx - 1);
+    const int32_t rs = seg_clamp(start[srow + xa], n), re = seg_clamp(start[srow + xb + 1], n);
+    int32_t ls = 0, le = 0;
+    if (x < nbx) {
+        ls = seg_clamp(start[srow + (x > 0 ? x - 1 : 0)], n);
+        le = seg_clamp(start[srow + (x < nbx - 1 ? x + 1 : nbx - 1) + 1], n);
+    }
+    for (int32_t cs = rs; cs < re; cs += kChunk) {       // wave-uniform loop
+        const int32_t m = ((cs + kChunk < re) ? cs + kChunk : re) - cs;
+        const int32_t ce = cs + m;
+        // Staging: every load of the chunk is issued before any is used, so the
+        // random-access value gather through perm costs one round trip per
+        // chunk rather than one per 64 particles.
+        constexpr int KS = kChunk / kWave;
+        vec4<T> q[KS];
+        int64_t id[KS];
+#pragma unroll
+        for (int u = 0; u < KS; ++u) {
+            const int k = lane + u * kWave;
+            id[u] = 0;
+            if (k < m) {
+                q[u] = sp[cs + k];
+                if constexpr (MODE != kPhi) {
+                    const int64_t i = perm[cs + k];
+                    id[u] = (i < 0 || i >= n) ? 0 : i;   // perm is a permutation of [0, n)
+                }
+            }
+        }
+        T val[KS][NC];
+#pragma unroll
+        for (int u = 0; u < KS; ++u) {
+            if (lane + u * kWave < m) {
+                if constexpr (MODE == kForce) {
+                    for (int c = 0; c < 3; ++c) val[u][c] = drag[3 * id[u] + c];
+                } else if constexpr (MODE == kSemi) {
+                    const vec4<T> b = src4[id[u]];
+                    val[u][0] = b.x;
+                    val[u][1] = b.y;
+                    val[u][2] = b.z;
+                    val[u][3] = b.w;
+                } else {
+                    val[u][0] = vol_over_vb(q[u].w, g.inv_vb);
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < KS; ++u) {
+            const int k = lane + u * kWave;
+            if (k < m) {
+                const Axis<T> ax = cic_axis(q[u].x, g.sb[0], nbx);
+                const Axis<T> ay = cic_axis(q[u].y, g.sb[1], nby);
+                const Axis<T> az = cic_axis(q[u].z, g.sb[2], nbz);
+                st.node[w][k] = ax.lo | (ax.hi << 16);
+                st.tx[w][k] = ax.t;
+                T wy[3], wz[3];
+                row_weights(ay, ys, wy);
+                row_weights(az, zs, wz);
+                for (int j = 0; j < 3; ++j) {
+                    st.wy[j][w][k] = wy[j];
+                    st.wz[j][w][k] = wz[j];
+                }
+                for (int c = 0; c < NC; ++c) st.val[c][w][k] = val[u][c];
+            }
+        }
+        wave_sync();
+        const int32_t b0 = (ls > cs ? ls : cs) - cs, b1 = (le < ce ? le : ce) - cs;
+        // Branch-free: the lanes of a wave hold different particles, so a skip
+        // of the zero weights (5 of the 9 target rows, a third of the x
+        // visits) would diverge and save nothing; their terms add zeros.
+        for (int32_t k = b0; k < b1; ++k) {
+            const int nd = st.node[w][k];
+            const T t = st.tx[w][k];
+            T wx = T(0);
+            if ((nd & 0xffff) == x) wx += T(1) - t;
+            if ((nd >> 16) == x) wx += t;
+            W v[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) v[c] = W(wx) * W(st.val[c][w][k]);
+            W wy[3], wz[3];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                wy[j] = W(st.wy[j][w][k]);
+                wz[j] = W(st.wz[j][w][k]);
+            }
+#pragma unroll
+            for (int kz = 0; kz < 3; ++kz) {
+#pragma unroll
+                for (int jy = 0; jy < 3; ++jy) {
+                    const W wyz = wy[jy] * wz[kz];
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) acc[KZ + kz][JY + jy][c].add(wyz, v[c]);
+                }
+            }
+        }
+        wave_sync();
     }
 }
 
@@ -156,103 +290,40 @@ __global__ __launch_bounds__(kBlock) void k_deposit_rows(const int32_t *__restri
     const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int nbx = g.nb[0], nby = g.nb[1], nbz = g.nb[2];
     const int nseg = (nbx + kWave - 1) / kWave;
-    const int64_t nwave = (int64_t)nby * nbz * nseg;
+    const int ngy = (nby + 1) >> 1, ngz = (nbz + 1) >> 1;
+    const int64_t nwave = (int64_t)ngy * ngz * nseg;
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int64_t gw = tile * kWavesPerBlock + w;        // (source row, segment)
+    const int64_t gw = tile * kWavesPerBlock + w;        // (source group, segment)
     if (gw >= nwave) return;                             // wave-uniform; no block barriers below
-    const int64_t row = gw / nseg;
+    const int64_t grp = gw / nseg;
     const int x0 = (int)(gw % nseg) * kWave;
-    const int ys = (int)(row % nby), zs = (int)(row / nby);
+    const int gy = (int)(grp % ngy), gz = (int)(grp / ngy);
     const int x = x0 + lane;
-    const bool active = x < nbx;
-    const int64_t srow = row * nbx;
-    const int xa = x0 > 0 ? x0 - 1 : 0;
-    const int xb = (x0 + kWave < nbx ? x0 + kWave : nbx - 1);
-    const int32_t rs = seg_clamp(start[srow + xa], n), re = seg_clamp(start[srow + xb + 1], n);
-    int32_t ls = 0, le = 0;
-    if (active) {
-        ls = seg_clamp(start[srow + (x > 0 ? x - 1 : 0)], n);
-        le = seg_clamp(start[srow + (x < nbx - 1 ? x + 1 : nbx - 1) + 1], n);
+    const int y0 = 2 * gy, z0 = 2 * gz;
+    RowSum<T, KAHAN> acc[4][4][NC];   // [target z - (z0 - 1)][target y - (y0 - 1)][component]
+    deposit_source_row<T, KAHAN, MODE, 0, 0>(acc, st, w, lane, x0, y0, z0, start, sp, perm, drag, src4, n, g);
+    if (y0 + 1 < nby)
+        deposit_source_row<T, KAHAN, MODE, 1, 0>(acc, st, w, lane, x0, y0 + 1, z0, start, sp, perm, drag, src4, n, g);
+    if (z0 + 1 < nbz) {
+        deposit_source_row<T, KAHAN, MODE, 0, 1>(acc, st, w, lane, x0, y0, z0 + 1, start, sp, perm, drag, src4, n, g);
+        if (y0 + 1 < nby)
+            deposit_source_row<T, KAHAN, MODE, 1, 1>(acc, st, w, lane, x0, y0 + 1, z0 + 1, start, sp, perm, drag,
+                                                     src4, n, g);
     }
-    Acc<T, KAHAN> acc[3][3][NC];   // [target z][target y][component]
-    for (int32_t cs = rs; cs < re; cs += kChunk) {       // wave-uniform loop
-        const int32_t ce = (cs + kChunk < re) ? cs + kChunk : re;
-        for (int32_t k = lane; k < ce - cs; k += kWave) {
-            const vec4<T> q = sp[cs + k];
-            const Axis<T> ax = cic_axis(q.x, g.sb[0], nbx);
-            const Axis<T> ay = cic_axis(q.y, g.sb[1], nby);
-            const Axis<T> az = cic_axis(q.z, g.sb[2], nbz);
-            st.node[w][k] = ax.lo | (ax.hi << 16);
-            st.tx[w][k] = ax.t;
-            T wy[3], wz[3];
-            row_weights(ay, ys, wy);
-            row_weights(az, zs, wz);
-            for (int j = 0; j < 3; ++j) {
-                st.wy[j][w][k] = wy[j];
-                st.wz[j][w][k] = wz[j];
-            }
-            if constexpr (MODE == kForce) {
-                int64_t id = perm[cs + k];
-                if (id < 0 || id >= n) id = 0;   // perm is a permutation of [0, n)
-                st.val[0][w][k] = drag[3 * id + 0];
-                st.val[1][w][k] = drag[3 * id + 1];
-                st.val[2][w][k] = drag[3 * id + 2];
-            } else if constexpr (MODE == kSemi) {
-                int64_t id = perm[cs + k];
-                if (id < 0 || id >= n) id = 0;
-                const vec4<T> b = src4[id];
-                st.val[0][w][k] = b.x;
-                st.val[1][w][k] = b.y;
-                st.val[2][w][k] = b.z;
-                st.val[3][w][k] = b.w;
-            } else {
-                st.val[0][w][k] = vol_over_vb(q.w, g.inv_vb);
-            }
-        }
-        wave_sync();
-        const int32_t b0 = (ls > cs ? ls : cs) - cs, b1 = (le < ce ? le : ce) - cs;
-        for (int32_t k = b0; k < b1; ++k) {
-            const int nd = st.node[w][k];
-            const T t = st.tx[w][k];
-            T wx = T(0);
-            if ((nd & 0xffff) == x) wx += T(1) - t;
-            if ((nd >> 16) == x) wx += t;
-            if (wx == T(0)) continue;
-            T v[NC];
-            for (int c = 0; c < NC; ++c) v[c] = wx * st.val[c][w][k];
-            T wy[3], wz[3];
-            for (int j = 0; j < 3; ++j) {
-                wy[j] = st.wy[j][w][k];
-                wz[j] = st.wz[j][w][k];
-            }
+    if (x >= nbx) return;
 #pragma unroll
-            for (int kz = 0; kz < 3; ++kz) {
-                if (wz[kz] == T(0)) continue;
-#pragma unroll
-                for (int jy = 0; jy < 3; ++jy) {
-                    const T wyz = wy[jy] * wz[kz];
-                    if (wyz == T(0)) continue;
-#pragma unroll
-                    for (int c = 0; c < NC; ++c) acc[kz][jy][c].add(wyz * v[c]);
-                }
-            }
-        }
-        wave_sync();
-    }
-    if (!active) return;
-#pragma unroll
-    for (int kz = 0; kz < 3; ++kz) {
-        const int tz = zs - 1 + kz;
+    for (int kz = 0; kz < 4; ++kz) {
+        const int tz = z0 - 1 + kz;
         if (tz < 0 || tz >= nbz) continue;
+        const int sz = gz - group_lo(tz);                // 0 or 1
 #pragma unroll
-        for (int jy = 0; jy < 3; ++jy) {
-            const int ty = ys - 1 + jy;
+        for (int jy = 0; jy < 4; ++jy) {
+            const int ty = y0 - 1 + jy;
             if (ty < 0 || ty >= nby) continue;
-            // slot = source offset from the target: (zs - tz + 1) * 3 + (ys - ty + 1)
-            const int slot = (2 - kz) * 3 + (2 - jy);
+            const int slot = sz * 2 + (gy - group_lo(ty));
             const int64_t tc = ((int64_t)tz * nby + ty) * nbx + x;
 #pragma unroll
-            for (int c = 0; c < NC; ++c) partial[((int64_t)slot * NC + c) * g.ncell + tc] = acc[kz][jy][c].s;
+            for (int c = 0; c < NC; ++c) partial[((int64_t)slot * NC + c) * g.ncell + tc] = T(acc[kz][jy][c].s);
         }
     }
 }
@@ -270,11 +341,13 @@ __global__ __launch_bounds__(kBlock) void k_deposit_sum(const T *__restrict__ pa
         int cx, cy, cz;
         decode_cell(c, g.nb, cx, cy, cz);
         Acc<T, KAHAN> acc[NC];
-        for (int dz = -1; dz <= 1; ++dz) {
-            if (cz + dz < 0 || cz + dz >= g.nb[2]) continue;
-            for (int dy = -1; dy <= 1; ++dy) {
-                if (cy + dy < 0 || cy + dy >= g.nb[1]) continue;
-                const int slot = (dz + 1) * 3 + (dy + 1);
+        const int gzl = group_lo(cz), gyl = group_lo(cy);
+        const int ngy = (g.nb[1] + 1) >> 1, ngz = (g.nb[2] + 1) >> 1;
+        for (int sz = 0; sz < 2; ++sz) {
+            if (gzl + sz < 0 || gzl + sz >= ngz) continue;
+            for (int sy = 0; sy < 2; ++sy) {
+                if (gyl + sy < 0 || gyl + sy >= ngy) continue;
+                const int slot = sz * 2 + sy;
                 for (int k = 0; k < NC; ++k) acc[k].add(partial[((int64_t)slot * NC + k) * g.ncell + c]);
             }
         }
@@ -326,7 +399,7 @@ int deposit_blocks(const int nb[3], int64_t ncell, int cic) {
 
 static int row_blocks(const int nb[3]) {
     const int64_t nseg = (nb[0] + kWave - 1) / kWave;
-    const int64_t nwave = (int64_t)nb[1] * nb[2] * nseg;
+    const int64_t nwave = (int64_t)((nb[1] + 1) / 2) * ((nb[2] + 1) / 2) * nseg;
     return (int)((nwave + kWavesPerBlock - 1) / kWavesPerBlock);
 }
 

@@ -85,7 +85,7 @@ template <typename T> struct StepArgs {
                      // gather has read it, then fluid velocity and void fraction until the
                      // drag has read it, then (beta, beta u_p) when semi
     T *Plo;          // [ncell] low word of the restricted pressure (Kahan compensation)
-    T *dep_partial;  // [9][nc][ncell] per-source-row partial sums of the CIC deposition (nc <= 4)
+    T *dep_partial;  // [4][nc][ncell] per-source-group partial sums of the CIC deposition (nc <= 4)
     double *part;    // [SL_COUNT][max_blocks]
     int64_t part_stride;
     Marker *mk;      // per-kernel event recording (never null)
