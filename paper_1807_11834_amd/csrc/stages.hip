@@ -130,6 +130,35 @@ __device__ __forceinline__ void sample_particles(const int64_t (&idx)[KB], const
 // ---------------------------------------------------------------------------
 // Restriction fine -> bulk
 // ---------------------------------------------------------------------------
+// Sums of the r^3 fine children, per fine child plane and then the planes in
+// order.  The compensated FP32 mode widens the FP32 children to FP64 and sums
+// them there: with at most 64 terms the sum is within 64 FP64 roundings of
+// exact, so its FP32 rounding is the correctly rounded average in all but rare
+// ties, and the FP32 residue lo = S - hi carries the rest of the pressure for
+// the gradient (a per-plane Kahan sum recombined over the planes keeps only
+// part of it); one convert and one FP64 add per child instead of Kahan's four
+// instructions.  The FP64 mode compensates in FP64 (Kahan), naive FP32 sums
+// plainly.
+template <typename T, bool KAHAN> struct ChildSum {
+    static constexpr bool kWide = std::is_same<T, float>::value && KAHAN;
+    using W = typename std::conditional<kWide, double, T>::type;
+    static constexpr bool kComp = KAHAN && !kWide;   // Kahan in T
+    Acc<W, kComp> acc;
+    __device__ __forceinline__ void add(T v) { acc.add(W(v)); }
+    // a plane's sum (s, with its compensation c) added to the cell's
+    __device__ __forceinline__ void add_plane(W ps, W pc) {
+        acc.add(ps);
+        if constexpr (kComp) acc.add(-pc);
+    }
+    // the average, and what its rounding leaves out (the scale 1/r^3 is a power
+    // of two, so the scaling is exact)
+    __device__ __forceinline__ T hi(T inv) const { return T(acc.s * W(inv)); }
+    __device__ __forceinline__ T lo(T inv) const {
+        if constexpr (kWide) return T(acc.s * W(inv) - W(hi(inv)));
+        else return -acc.c * inv;
+    }
+};
+
 template <typename T, int R, bool KAHAN>
 __global__ __launch_bounds__(kBlock) void k_restrict(StepArgs<T> a) {
     const Geo<T> &g = a.g;
@@ -151,25 +180,24 @@ __global__ __launch_bounds__(kBlock) void k_restrict(StepArgs<T> a) {
                 for (int ly = 0; ly < R; ++ly) rows[lz][ly] = load_row<T, R>(q + lz * nfxy + ly * nfx);
             // per fine child plane, then the planes in order (s_0, -c_0, s_1, ...):
             // the same sums as the brick-tiled kernel
-            Acc<T, KAHAN> acc;
+            ChildSum<T, KAHAN> acc;
 #pragma unroll
             for (int lz = 0; lz < R; ++lz) {
-                Acc<T, KAHAN> plane;
+                ChildSum<T, KAHAN> plane;
 #pragma unroll
                 for (int ly = 0; ly < R; ++ly)
 #pragma unroll
                     for (int lx = 0; lx < R; ++lx) plane.add(rows[lz][ly].v[lx]);
-                acc.add(plane.s);
-                if constexpr (KAHAN) acc.add(-plane.c);
+                acc.add_plane(plane.acc.s, plane.acc.c);
             }
-            T val = acc.s * inv;   // 1/R^3 is a power of two: the scaling is exact
+            const T val = acc.hi(inv);
             if (f < 3) {
                 a.U[f * g.ncell + c] = val;
             } else {
                 a.P[c] = val;
-                // the compensated sum is s - c: keep -c/R^3 so that the pressure
-                // gradient can difference (hi + lo) instead of the rounded hi
-                a.Plo[c] = -acc.c * inv;
+                // keep the rest of the average so that the pressure gradient can
+                // difference (hi + lo) instead of the rounded hi
+                a.Plo[c] = acc.lo(inv);
             }
         }
     }
@@ -193,18 +221,17 @@ __global__ __launch_bounds__(kBlock) void k_restrict_alpha(StepArgs<T> a) {
     for (int lz = 0; lz < R; ++lz)
 #pragma unroll
         for (int ly = 0; ly < R; ++ly) rows[lz][ly] = load_row<T, R>(q + lz * nfxy + ly * nfx);
-    Acc<T, KAHAN> acc;
+    ChildSum<T, KAHAN> acc;
 #pragma unroll
     for (int lz = 0; lz < R; ++lz) {
-        Acc<T, KAHAN> plane;
+        ChildSum<T, KAHAN> plane;
 #pragma unroll
         for (int ly = 0; ly < R; ++ly)
 #pragma unroll
             for (int lx = 0; lx < R; ++lx) plane.add(rows[lz][ly].v[lx]);
-        acc.add(plane.s);
-        if constexpr (KAHAN) acc.add(-plane.c);
+        acc.add_plane(plane.acc.s, plane.acc.c);
     }
-    a.alpha[c] = acc.s * (T(1) / T(R * R * R));
+    a.alpha[c] = acc.hi(T(1) / T(R * R * R));
 }
 
 // Restriction with the fine-grid lookup, tiled in bricks of 8 x 4 x 2 bulk
@@ -267,7 +294,7 @@ __global__ __launch_bounds__(kBrickThreads) void k_restrict_brick(StepArgs<T> a)
     const T inv = T(1) / T(R * R * R);
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
-        Acc<T, KAHAN> plane;
+        ChildSum<T, KAHAN> plane;
         if (work) {
             const T *__restrict__ q = a.fine[f] + base;
             Row<T, R> rows[R];
@@ -286,25 +313,24 @@ __global__ __launch_bounds__(kBrickThreads) void k_restrict_brick(StepArgs<T> a)
         }
         // the planes of this cell in order (s_0, -c_0, s_1, ...), read from the
         // cell's four lanes; the plane-0 lane writes the average
-        Acc<T, KAHAN> acc;
+        ChildSum<T, KAHAN> acc;
         const int l0 = lane & ~3;
 #pragma unroll
         for (int k = 0; k < R; ++k) {
-            const T sk = __shfl(plane.s, l0 + k, kWave);
-            const T ck = __shfl(plane.c, l0 + k, kWave);
-            acc.add(sk);
-            if constexpr (KAHAN) acc.add(-ck);
+            const auto sk = __shfl(plane.acc.s, l0 + k, kWave);
+            const auto ck = ChildSum<T, KAHAN>::kComp ? __shfl(plane.acc.c, l0 + k, kWave) : plane.acc.c;
+            acc.add_plane(sk, ck);
         }
         if (inside && rz == 0) {
             const int64_t c = cx + nx * cy + nxy * cz;
-            const T val = acc.s * inv;   // 1/R^3 is a power of two: the scaling is exact
+            const T val = acc.hi(inv);
             if (f < 3) {
                 a.U[f * g.ncell + c] = val;
             } else {
                 a.P[c] = val;
-                // the compensated sum is s - c: keep -c/R^3 so that the pressure
-                // gradient can difference (hi + lo) instead of the rounded hi
-                a.Plo[c] = -acc.c * inv;
+                // keep the rest of the average so that the pressure gradient can
+                // difference (hi + lo) instead of the rounded hi
+                a.Plo[c] = acc.lo(inv);
             }
         }
     }
