@@ -12,9 +12,9 @@
 //   k_radix_prefix exclusive prefix over tiles of every digit, digit totals;
 //   k_radix_scatter stable ranking inside a tile (wave ballots, LDS staging) and
 //                  coalesced scatter to the digit's output run;
-//   k_segments     start[c] = first sorted position with cell >= c (the key
-//                  changes within a 256-cell block, located by two binary
-//                  searches and staged in LDS), count[c] = start[c+1] - start[c].
+//   k_segment_starts  start[c] = first sorted position with cell >= c, set by
+//                  the sorted positions where the key changes;
+//   k_segment_counts  count[c] = start[c+1] - start[c].
 //
 // Keys are cell indices < ncell; ids are the input order, so a stable LSD sort
 // starting from the identity order gives ascending (cell, id).  Integer atomics
@@ -232,58 +232,41 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t *__rest
     }
 }
 
-// start[c] = first sorted position with key >= c for c in [0, ncell], and
-// count[c] = start[c+1] - start[c].  A workgroup owns 256 cells; two binary
-// searches bound its key range, which is staged in LDS; every key that differs
-// from its predecessor fills the starts of the cells in between (each entry of
-// the block is written once).  A range longer than the LDS buffer (a very dense
-// block) falls back to one binary search per cell.
-constexpr int kSegCap = 4096;
+// start[c] = first sorted position with key >= c, for c in [0, ncell].  Every
+// sorted position i whose key differs from its predecessor's (with key[-1] = -1
+// and key[n] = ncell) sets start[c] = i for the cells c in (key[i-1], key[i]],
+// so every entry is written exactly once and the keys are read once, coalesced,
+// without searches.  A gap of more than kGapLane cells (a run of empty cells)
+// is filled by the whole wave together.
+constexpr int kGapLane = 32;
 
-__global__ __launch_bounds__(kBlock) void k_segments(const uint32_t *__restrict__ skeys, int64_t n, int64_t ncell,
-                                                     int32_t *__restrict__ start, int32_t *__restrict__ count) {
-    __shared__ int64_t bound[2];
-    __shared__ int32_t s_start[kBlock + 1];
-    __shared__ uint32_t kbuf[kSegCap];
-    const int64_t c0 = (int64_t)blockIdx.x * kBlock;
-    auto lower = [&](int64_t lo, int64_t hi, int64_t c) {   // first i in [lo,hi) with key >= c
-        while (lo < hi) {
-            const int64_t mid = lo + ((hi - lo) >> 1);
-            if ((int64_t)skeys[mid] < c) lo = mid + 1;
-            else hi = mid;
-        }
-        return lo;
-    };
-    if (threadIdx.x < 2) {
-        const int64_t c = threadIdx.x == 0 ? c0 : (c0 + kBlock < ncell ? c0 + kBlock : ncell);
-        bound[threadIdx.x] = lower(0, n, c);
+__global__ __launch_bounds__(kBlock) void k_segment_starts(const uint32_t *__restrict__ skeys, int64_t n,
+                                                           int64_t ncell, int32_t *__restrict__ start) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;   // sorted position, 0 .. n
+    const int lane = threadIdx.x % kWave;
+    int32_t lo = 0, hi = -1;   // the cells set to i
+    if (i <= n) {
+        // keys are cells < ncell; the clamp only keeps the stores in bounds
+        auto key = [&](int64_t k) { const int64_t v = skeys[k]; return (int32_t)(v < ncell ? v : ncell - 1); };
+        lo = (i == 0 ? -1 : key(i - 1)) + 1;
+        hi = i == n ? (int32_t)ncell : key(i);
     }
-    __syncthreads();
-    const int64_t b0 = bound[0], b1 = bound[1];
-    const int64_t len = b1 - b0;
-    const int cend = (int)((c0 + kBlock < ncell ? c0 + kBlock : ncell) - c0);   // cells of this block
-    if (len <= kSegCap) {
-        for (int64_t i = threadIdx.x; i < len; i += kBlock) kbuf[i] = skeys[b0 + i];
-        __syncthreads();
-        for (int64_t i = threadIdx.x; i < len; i += kBlock) {
-            const int k = (int)((int64_t)kbuf[i] - c0);
-            const int prev = (i == 0) ? -1 : (int)((int64_t)kbuf[i - 1] - c0);
-            for (int c = prev + 1; c <= k; ++c) s_start[c] = (int32_t)(b0 + i);
-        }
-        if (threadIdx.x == 0) {
-            const int last = (len > 0) ? (int)((int64_t)kbuf[len - 1] - c0) : -1;
-            for (int c = last + 1; c <= cend; ++c) s_start[c] = (int32_t)b1;
-        }
-    } else {
-        for (int t = threadIdx.x; t <= cend; t += kBlock) s_start[t] = (int32_t)lower(b0, b1, c0 + t);
+    const int32_t len = hi - lo + 1;
+    if (len > 0 && len <= kGapLane)
+        for (int32_t c = lo; c <= hi; ++c) start[c] = (int32_t)i;
+    uint64_t m = __ballot(len > kGapLane);   // wave-uniform
+    while (m) {
+        const int l = __ffsll((unsigned long long)m) - 1;
+        m &= m - 1;
+        const int32_t glo = __shfl(lo, l, kWave), ghi = __shfl(hi, l, kWave), gi = __shfl((int32_t)i, l, kWave);
+        for (int32_t c = glo + lane; c <= ghi; c += kWave) start[c] = gi;
     }
-    __syncthreads();
-    const int64_t c = c0 + threadIdx.x;
-    if (c < ncell) {
-        start[c] = s_start[threadIdx.x];
-        count[c] = s_start[threadIdx.x + 1] - s_start[threadIdx.x];
-    }
-    if (c0 + kBlock >= ncell && threadIdx.x == 0) start[ncell] = (int32_t)n;
+}
+
+__global__ __launch_bounds__(kBlock) void k_segment_counts(const int32_t *__restrict__ start, int64_t ncell,
+                                                           int32_t *__restrict__ count) {
+    const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (c < ncell) count[c] = start[c + 1] - start[c];
 }
 
 // ---------------------------------------------------------------------------
@@ -340,9 +323,10 @@ hipError_t launch_bin_sort(const T *pos, const T *diam, int64_t n, const Geo<T> 
     } else {
         *sorted_keys = s.keys_a;
     }
-    const int nblk = (int)((g.ncell + kBlock - 1) / kBlock);
+    const int sblk = (int)((n + 1 + kBlock - 1) / kBlock), cblk = (int)((g.ncell + kBlock - 1) / kBlock);
     mk->mark("segments", st);
-    hipLaunchKernelGGL(k_segments, dim3(nblk), dim3(kBlock), 0, st, *sorted_keys, n, g.ncell, start, count);
+    hipLaunchKernelGGL(k_segment_starts, dim3(sblk), dim3(kBlock), 0, st, *sorted_keys, n, g.ncell, start);
+    hipLaunchKernelGGL(k_segment_counts, dim3(cblk), dim3(kBlock), 0, st, start, g.ncell, count);
     return hipGetLastError();
 }
 
