@@ -84,6 +84,11 @@ typedef enum {
 } couple_status;
 
 enum { COUPLE_NGP = 0, COUPLE_CIC = 1 };                  /* deposition weights            */
+/* Precision.  COUPLE_FP64: FP64 data and sums.  COUPLE_FP32_KAHAN: FP32 data with
+ * error-compensated sums (the restriction and the deposition's first pass sum
+ * the FP32 terms in FP64 registers, other per-cell sums are Kahan-compensated
+ * in FP32; the pressure keeps a low word for its gradient).  COUPLE_FP32_NAIVE:
+ * FP32 data, plain FP32 sums (the uncompensated baseline). */
 enum { COUPLE_FP64 = 0, COUPLE_FP32_KAHAN = 1, COUPLE_FP32_NAIVE = 2 };  /* precision      */
 enum { COUPLE_VEL_FINE = 0, COUPLE_VEL_BULK = 1, COUPLE_VEL_GIVEN = 2, COUPLE_VEL_MLP = 3 }; /* u_f */
 
