@@ -421,7 +421,7 @@ def vof_leg(args, w, cfg, pos, vel, diam, fine, plain_ms, n, g, fsz, dev):
     print(f"# two-fluid drag: {ms:.3f} ms/step", file=sys.stderr, flush=True)
     return {"ms_per_step": ms, "value": n / (ms * 1e-3), "extra_ms_vs_plain": ms - plain_ms,
             "fluid_2": {"rho": cfg_v.rho_f2, "mu": cfg_v.mu_f2},
-            "kernels_avg_ms": {k: round(v, 4) for k, v in kt.items() if k in ("restrict_alpha", "drag")},
+            "kernels_avg_ms": {k: round(v, 4) for k, v in kt.items() if k in ("restrict_alpha", "pack_alpha", "drag")},
             "restrict_alpha_GBps": round(ab / (ra * 1e-3) / 1e9, 1) if ra else None,
             "restrict_alpha_frac_hbm": round(ab / (ra * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4) if ra else None}
 

@@ -19,6 +19,7 @@ struct couple_handle {
     int64_t part_stride = 0;
     SortScratch sort{};
     void *sp = nullptr, *uf4 = nullptr, *plo = nullptr, *dep = nullptr;
+    void *alpha8 = nullptr;         // vof: packed stencil records of the bulk alpha
     float4 *fgrid = nullptr;        // VEL_MLP: packed bulk features
     const couple_mlp *mlp = nullptr;
     double *part = nullptr;
@@ -46,11 +47,11 @@ static void destroy_events(couple_handle *h) {
 static void release(couple_handle *h) {
     destroy_events(h);
     void *ptrs[] = {h->sort.keys_a, h->sort.keys_b, h->sort.vals_a, h->sort.vals_b, h->sort.hist,
-                    h->sort.totals, h->sp, h->uf4, h->plo, h->dep, h->part, h->fgrid};
+                    h->sort.totals, h->sp, h->uf4, h->plo, h->dep, h->part, h->fgrid, h->alpha8};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     h->sort = SortScratch{};
-    h->sp = h->uf4 = h->plo = h->dep = nullptr;
+    h->sp = h->uf4 = h->plo = h->dep = h->alpha8 = nullptr;
     h->fgrid = nullptr;
     h->part = nullptr;
 }
@@ -135,7 +136,8 @@ extern "C" int couple_init(const couple_config *cfg, couple_handle **out) {
               dev_alloc(&h->plo, fsz * h->ncell) &&
               dev_alloc(&h->dep, (cfg->deposit == COUPLE_CIC ? (cfg->semi_implicit ? 16 : 12) : 1) * fsz * h->ncell) &&
               dev_alloc(&h->part, sizeof(double) * (SL_COUNT * h->part_stride + SL_COUNT * 64)) &&
-              (cfg->vel_source != COUPLE_VEL_MLP || dev_alloc(&h->fgrid, sizeof(float4) * 2 * h->ncell));
+              (cfg->vel_source != COUPLE_VEL_MLP || dev_alloc(&h->fgrid, sizeof(float4) * 2 * h->ncell)) &&
+              (!cfg->vof || dev_alloc(&h->alpha8, 8 * fsz * h->ncell));
     if (!ok) {
         release(h);
         delete h;
@@ -191,6 +193,7 @@ static int step_impl(couple_handle *h, const couple_inputs *in, couple_outputs *
     a.mu_f2 = (T)c.mu_f2;
     a.fine_alpha = (const T *)in->fine_alpha;
     a.alpha = (T *)out->bulk_alpha;
+    a.alpha8 = (T *)h->alpha8;
     a.dt = (T)c.dt;
     a.rho_f = (T)c.rho_f;
     a.mu_f = (T)c.mu_f;

@@ -77,6 +77,7 @@ template <typename T> struct StepArgs {
     T *fine_eps, *fine_F;    // fine
     T *K, *KU;               // bulk semi-implicit coefficient [ncell] and beta u_p source [3][ncell]
     T *alpha;                // bulk liquid volume fraction [ncell] (vof)
+    T *alpha8;               // [ncell][8] bulk alpha at cell + {0,1}^3 (clamped): one stencil record per cell (vof)
     T *fine_K, *fine_KU;     // the same prolonged to the fine grid
     double *diag;
     // scratch

@@ -17,7 +17,8 @@
 //                  fine lookup costs no extra pass over the fine grid.
 //   k_sample       the same sampling for the bulk and given velocity sources.
 //   k_restrict_alpha  two-fluid drag: bulk liquid fraction, average of the fine
-//                  children.
+//                  children; k_pack_alpha8 then stores each cell's 2x2x2
+//                  stencil corners as one record for the drag's lookups.
 //   k_drag         drag and explicit Euler advection in input order (coalesced);
 //                  with the semi-implicit split also (beta, beta u_p).
 //   deposit force  (deposit.hip), with the bulk pressure gradient; then the
@@ -232,6 +233,58 @@ __global__ __launch_bounds__(kBlock) void k_restrict_alpha(StepArgs<T> a) {
         acc.add_plane(plane.acc.s, plane.acc.c);
     }
     a.alpha[c] = acc.hi(T(1) / T(R * R * R));
+}
+
+// The bulk alpha at the eight cells cell + {0,1}^3 (clamped into the grid), as
+// one 8-value record per cell: the drag kernel runs in input order, and a
+// particle's trilinear stencil (whose lower corner is the record's cell) is
+// then one 32-byte read instead of reads from four rows of the bulk grid.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_pack_alpha8(StepArgs<T> a) {
+    const Geo<T> &g = a.g;
+    const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (c >= g.ncell) return;
+    int cx, cy, cz;
+    decode_cell(c, g.nb, cx, cy, cz);
+    const int64_t nx = g.nb[0], nxy = nx * g.nb[1];
+    const int64_t xs[2] = {cx, cx + 1 < g.nb[0] ? cx + 1 : cx};
+    const int64_t ys[2] = {cy * nx, (cy + 1 < g.nb[1] ? cy + 1 : cy) * nx};
+    const int64_t zs[2] = {cz * nxy, (cz + 1 < g.nb[2] ? cz + 1 : cz) * nxy};
+    vec4<T> r[2];
+    for (int dz = 0; dz < 2; ++dz) {
+        r[dz].x = a.alpha[zs[dz] + ys[0] + xs[0]];
+        r[dz].y = a.alpha[zs[dz] + ys[0] + xs[1]];
+        r[dz].z = a.alpha[zs[dz] + ys[1] + xs[0]];
+        r[dz].w = a.alpha[zs[dz] + ys[1] + xs[1]];
+    }
+    vec4<T> *out = reinterpret_cast<vec4<T> *>(a.alpha8) + 2 * c;
+    out[0] = r[0];
+    out[1] = r[1];
+}
+
+// Trilinear alpha at a particle from its stencil record, in the arithmetic
+// order of trilin() (the same value bit for bit).
+template <typename T>
+__device__ __forceinline__ T trilin_alpha8(const T *__restrict__ alpha8, const Axis<T> &ax, const Axis<T> &ay,
+                                           const Axis<T> &az, const int nb[3]) {
+    const vec4<T> *r = reinterpret_cast<const vec4<T> *>(alpha8) +
+                       2 * (((int64_t)az.lo * nb[1] + ay.lo) * nb[0] + ax.lo);
+    const vec4<T> lo = r[0];
+    const vec4<T> hi = az.hi != az.lo ? r[1] : lo;
+    const bool ox = ax.hi != ax.lo, oy = ay.hi != ay.lo;
+    // corner [z][y][x] of the stencil: x, y offsets 0 at a folded wall
+    const T z0y0x0 = lo.x, z0y0x1 = ox ? lo.y : lo.x, z0y1x0 = oy ? lo.z : lo.x,
+            z0y1x1 = oy ? (ox ? lo.w : lo.z) : (ox ? lo.y : lo.x);
+    const T z1y0x0 = hi.x, z1y0x1 = ox ? hi.y : hi.x, z1y1x0 = oy ? hi.z : hi.x,
+            z1y1x1 = oy ? (ox ? hi.w : hi.z) : (ox ? hi.y : hi.x);
+    const T sx = T(1) - ax.t, sy = T(1) - ay.t, sz = T(1) - az.t;
+    const T c00 = sx * z0y0x0 + ax.t * z0y0x1;
+    const T c01 = sx * z0y1x0 + ax.t * z0y1x1;
+    const T c10 = sx * z1y0x0 + ax.t * z1y0x1;
+    const T c11 = sx * z1y1x0 + ax.t * z1y1x1;
+    const T c0 = sy * c00 + ay.t * c01;
+    const T c1 = sy * c10 + ay.t * c11;
+    return sz * c0 + az.t * c1;
 }
 
 // Restriction with the fine-grid lookup, tiled in bricks of 8 x 4 x 2 bulk
@@ -483,7 +536,7 @@ __global__ __launch_bounds__(kBlock) void k_drag(StepArgs<T> a) {
             const Axis<T> bx = cic_axis(xs[0], g.sb[0], g.nb[0]);
             const Axis<T> by = cic_axis(xs[1], g.sb[1], g.nb[1]);
             const Axis<T> bz = cic_axis(xs[2], g.sb[2], g.nb[2]);
-            const T al = trilin(a.alpha, bx, by, bz, g.nb[0], (int64_t)g.nb[0] * g.nb[1]);
+            const T al = trilin_alpha8(a.alpha8, bx, by, bz, g.nb);
             rho = a.rho_f * al + a.rho_f2 * (T(1) - al);
             mu = a.mu_f * al + a.mu_f2 * (T(1) - al);
         }
@@ -742,6 +795,8 @@ static void launch_grid_stages(const StepArgs<T> &a, hipStream_t st) {
     if (a.vof) {
         a.mk->mark("restrict_alpha", st);
         hipLaunchKernelGGL((k_restrict_alpha<T, R, KAHAN>), dim3(cb), dim3(kBlock), 0, st, a);
+        if (a.n > 0) a.mk->mark("pack_alpha", st);
+        if (a.n > 0) hipLaunchKernelGGL(k_pack_alpha8<T>, dim3(cb), dim3(kBlock), 0, st, a);
     }
     if (a.n > 0) a.mk->mark("drag", st);
     if (a.n > 0) hipLaunchKernelGGL(k_drag<T>, dim3(pb), dim3(kBlock), 0, st, a);
