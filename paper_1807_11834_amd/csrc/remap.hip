@@ -11,10 +11,16 @@
 // per workgroup (k_remap_rows: the y, z part of the sum over whole sender rows
 // with coalesced loads, then the x part from LDS); for sender rows too long for
 // LDS, one thread per receiver cell (k_remap: raster order z, y, x).
-// Sums are compensated in the FP32 Kahan mode.  Storing the 3-D map as CSR
+// In the compensated FP32 mode the tile and per-cell kernels sum in FP64
+// registers (each weight x value product of FP32 operands is exact there; one
+// FMA per term); the row kernel keeps Kahan-compensated FP32 sums (an FP64
+// variant of it, with its partial sums in LDS, measured slower).
+// Storing the 3-D map as CSR
 // would read more bytes of indices and weights than of field values; the
 // factors are a few KB and stay in cache.
 #include <algorithm>
+#include <type_traits>
+#include <cstdint>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -42,6 +48,9 @@ template <typename T> struct RemapArgs {
     int64_t nsrc, ndst;
 };
 
+// Accumulator type: FP64 in the compensated FP32 mode, T otherwise.
+template <typename T, bool KAHAN> using SumT = typename std::conditional<KAHAN, double, T>::type;
+
 template <typename T, bool KAHAN>
 __global__ __launch_bounds__(kBlock) void k_remap(RemapArgs<T> r, const T *__restrict__ src, T *__restrict__ dst) {
     const int64_t nblk = gridDim.x;
@@ -54,16 +63,17 @@ __global__ __launch_bounds__(kBlock) void k_remap(RemapArgs<T> r, const T *__res
     const int fy = r.first[1][j], ny = r.cnt[1][j], oy = r.off[1][j];
     const int fz = r.first[2][k], nz = r.cnt[2][k], oz = r.off[2][k];
     const int64_t sx = r.ns[0], sxy = (int64_t)r.ns[0] * r.ns[1];
-    Acc<T, KAHAN> acc;
+    using W = SumT<T, KAHAN>;
+    W acc = W(0);
     for (int kz = 0; kz < nz; ++kz) {
         const T wz = r.w[2][oz + kz];
         for (int ky = 0; ky < ny; ++ky) {
             const T wyz = wz * r.w[1][oy + ky];
             const T *__restrict__ row = s + (int64_t)(fz + kz) * sxy + (int64_t)(fy + ky) * sx + fx;
-            for (int kx = 0; kx < nx; ++kx) acc.add((wyz * r.w[0][ox + kx]) * row[kx]);
+            for (int kx = 0; kx < nx; ++kx) acc = fma(W(wyz * r.w[0][ox + kx]), W(row[kx]), acc);
         }
     }
-    dst[(int64_t)blockIdx.y * r.ndst + c] = acc.s;
+    dst[(int64_t)blockIdx.y * r.ndst + c] = T(acc);
 }
 
 // Receiver rows (y, z) of one field per workgroup, grid-strided over the rows.
@@ -129,72 +139,154 @@ __global__ __launch_bounds__(kBlock) void k_remap_rows(RemapArgs<T> r, const T *
 // tile (its overlapping y and z rows, whole x extent) is staged in LDS with
 // coalesced loads; every slab row is then transferred along x into a second LDS
 // buffer (rx, receiver x resolution); finally each receiver cell sums its
-// (z, y) overlaps of rx.  Sum order: x within each sender row, then (z, y) in
-// raster order.
+// (z, y) overlaps of rx, whose offsets and weights are tabulated per receiver
+// row of the tile.  Sum order: x within each sender row, then (z, y) in raster
+// order.  Loop positions advance incrementally: no integer divisions per
+// element.
 constexpr int kTileJ = 8, kTileK = 8;
-constexpr int kMaxX = 4;   // x factors held in registers (longer ranges read them in the loop)
+constexpr int kTileRows = kTileJ * kTileK;
+constexpr int kMaxX = 4;       // x factors held in registers (longer ranges read them in the loop)
+constexpr int kMaxTerms = 4;   // (z, y) terms of a receiver row in the table: a receiver cell no
+                               // larger than the sender cells it meets overlaps at most 2 x 2
+                               // sender rows; rows with more terms read the factors directly
+
+template <typename T> using Vec4NT = T __attribute__((ext_vector_type(4)));
 
 template <typename T, bool KAHAN>
 __global__ __launch_bounds__(kBlock) void k_remap_tile(RemapArgs<T> r, const T *__restrict__ src,
-                                                       T *__restrict__ dst) {
+                                                       T *__restrict__ dst, bool vec4) {
+    using W = SumT<T, KAHAN>;
     extern __shared__ __align__(16) unsigned char lds_raw[];
+    __shared__ int32_t toff[kTileRows][kMaxTerms];   // rx offset of each term of a receiver row
+    __shared__ W tw[kTileRows][kMaxTerms];           // its weight wz * wy
+    __shared__ int32_t tn[kTileRows];                // number of terms
+    __shared__ int32_t tjk[kTileRows][2];            // the row's receiver (j, k)
+    __shared__ int64_t orow[kTileRows];              // the row's offset in the receiver field
     const int tny = (r.nd[1] + kTileJ - 1) / kTileJ;
     const int64_t t = xcd_tile(blockIdx.x, gridDim.x);
     const int j0 = (int)(t % tny) * kTileJ, k0 = (int)(t / tny) * kTileK;
     const int j1 = j0 + kTileJ < r.nd[1] ? j0 + kTileJ : r.nd[1];
     const int k1 = k0 + kTileK < r.nd[2] ? k0 + kTileK : r.nd[2];
+    const int nj = j1 - j0, nk = k1 - k0;
     const int ys0 = r.first[1][j0], ys1 = r.first[1][j1 - 1] + r.cnt[1][j1 - 1];
     const int zs0 = r.first[2][k0], zs1 = r.first[2][k1 - 1] + r.cnt[2][k1 - 1];
     const int Ys = ys1 - ys0, nsx = r.ns[0], ndx = r.nd[0];
     const int nrows = (zs1 - zs0) * Ys;   // sender rows of the slab
     T *slab = reinterpret_cast<T *>(lds_raw);
-    T *rx = slab + (size_t)nrows * nsx;
+    T *rx = slab + (((size_t)nrows * nsx + 3) & ~(size_t)3);   // 16-byte aligned
     const int64_t sxy = (int64_t)r.ns[0] * r.ns[1];
     const T *__restrict__ s = src + (int64_t)blockIdx.y * r.nsrc;
-    const int nslab = nrows * nsx;
-    for (int e = threadIdx.x; e < nslab; e += kBlock) {
-        const int x = e % nsx, yy = (e / nsx) % Ys, zz = e / (nsx * Ys);
-        slab[e] = s[(int64_t)(zs0 + zz) * sxy + (int64_t)(ys0 + yy) * nsx + x];
+    // the term table, one thread per receiver row of the tile (row = kk * nj + jj)
+    if (threadIdx.x < nj * nk) {
+        const int jj = threadIdx.x % nj, kk = threadIdx.x / nj;
+        const int j = j0 + jj, k = k0 + kk;
+        const int fz = r.first[2][k], nz = r.cnt[2][k], oz = r.off[2][k];
+        const int fy = r.first[1][j], ny = r.cnt[1][j], oy = r.off[1][j];
+        tn[threadIdx.x] = nz * ny;
+        tjk[threadIdx.x][0] = j;
+        tjk[threadIdx.x][1] = k;
+        orow[threadIdx.x] = ((int64_t)k * r.nd[1] + j) * ndx;
+        if (nz * ny <= kMaxTerms) {
+            int q = 0;
+            for (int kz = 0; kz < nz; ++kz)
+                for (int ky = 0; ky < ny; ++ky, ++q) {
+                    toff[threadIdx.x][q] = ((fz + kz - zs0) * Ys + (fy + ky - ys0)) * ndx;
+                    tw[threadIdx.x][q] = W(r.w[2][oz + kz] * r.w[1][oy + ky]);
+                }
+        }
+    }
+    // stage the slab, x fastest, then slab rows (y fastest, then z)
+    {
+        int x = threadIdx.x % nsx, row = threadIdx.x / nsx;
+        int yy = row % Ys, zz = row / Ys;
+        const int dx = kBlock % nsx, drow = kBlock / nsx;
+        while (row < nrows) {
+            slab[(size_t)row * nsx + x] = s[(int64_t)(zs0 + zz) * sxy + (int64_t)(ys0 + yy) * nsx + x];
+            x += dx;
+            int d = drow;
+            if (x >= nsx) {
+                x -= nsx;
+                ++d;
+            }
+            row += d;
+            yy += d;
+            if (yy >= Ys) {
+                zz += yy / Ys;
+                yy %= Ys;
+            }
+        }
     }
     __syncthreads();
     // x transfer of every slab row; each thread keeps the x factor of its
     // receiver columns in registers
     for (int xd = threadIdx.x; xd < ndx; xd += kBlock) {
         const int fx = r.first[0][xd], nx = r.cnt[0][xd], ox = r.off[0][xd];
-        T wx[kMaxX];
+        W wx[kMaxX];
 #pragma unroll
-        for (int q = 0; q < kMaxX; ++q) wx[q] = q < nx ? r.w[0][ox + q] : T(0);
+        for (int q = 0; q < kMaxX; ++q) wx[q] = q < nx ? W(r.w[0][ox + q]) : W(0);
         for (int row = 0; row < nrows; ++row) {
             const T *sr = slab + (size_t)row * nsx + fx;
-            Acc<T, KAHAN> acc;
+            W acc = W(0);
             if (nx <= kMaxX) {
 #pragma unroll
                 for (int q = 0; q < kMaxX; ++q)
-                    if (q < nx) acc.add(wx[q] * sr[q]);
+                    if (q < nx) acc = fma(wx[q], W(sr[q]), acc);
             } else {
-                for (int kx = 0; kx < nx; ++kx) acc.add(r.w[0][ox + kx] * sr[kx]);
+                for (int kx = 0; kx < nx; ++kx) acc = fma(W(r.w[0][ox + kx]), W(sr[kx]), acc);
             }
-            rx[(size_t)row * ndx + xd] = acc.s;
+            rx[(size_t)row * ndx + xd] = T(acc);
         }
     }
     __syncthreads();
-    // (z, y) overlaps of each receiver cell; the row factors are uniform, the
-    // (large, write-once) receiver field is stored non-temporally
+    // (z, y) overlaps of each receiver cell; the (large, write-once) receiver
+    // field is stored non-temporally.  With vec4 set (receiver rows a multiple
+    // of 4 long, 16-byte aligned output) a thread forms 4 neighbouring cells of
+    // a row and stores them with one vector store.  Work items run over
+    // (tile row, x / width).
     T *__restrict__ out = dst + (int64_t)blockIdx.y * r.ndst;
-    for (int k = k0; k < k1; ++k) {
-        const int fz = r.first[2][k], nz = r.cnt[2][k], oz = r.off[2][k];
-        for (int j = j0; j < j1; ++j) {
-            const int fy = r.first[1][j], ny = r.cnt[1][j], oy = r.off[1][j];
-            for (int xd = threadIdx.x; xd < ndx; xd += kBlock) {
-                Acc<T, KAHAN> acc;
-                for (int kz = 0; kz < nz; ++kz) {
-                    const T wz = r.w[2][oz + kz];
-                    const T *rr = rx + ((size_t)(fz + kz - zs0) * Ys + (fy - ys0)) * ndx + xd;
-                    for (int ky = 0; ky < ny; ++ky) acc.add((wz * r.w[1][oy + ky]) * rr[(size_t)ky * ndx]);
-                }
-                __builtin_nontemporal_store(acc.s, &out[((int64_t)k * r.nd[1] + j) * ndx + xd]);
+    const int Wd = vec4 ? 4 : 1, nxw = ndx / Wd;
+    const int ntr = nj * nk;
+    int xw = threadIdx.x % nxw, tr = threadIdx.x / nxw;
+    const int dxw = kBlock % nxw, dtr = kBlock / nxw;
+    while (tr < ntr) {
+        const int xd = xw * Wd;
+        const int n = tn[tr];
+        W acc[4] = {W(0), W(0), W(0), W(0)};
+        auto term = [&](W w, const T *p) {
+            if (vec4) {
+                const Vec4NT<T> v = *reinterpret_cast<const Vec4NT<T> *>(p);
+                acc[0] = fma(w, W(v.x), acc[0]);
+                acc[1] = fma(w, W(v.y), acc[1]);
+                acc[2] = fma(w, W(v.z), acc[2]);
+                acc[3] = fma(w, W(v.w), acc[3]);
+            } else {
+                acc[0] = fma(w, W(p[0]), acc[0]);
             }
+        };
+        if (n <= kMaxTerms) {
+            for (int q = 0; q < n; ++q) term(tw[tr][q], rx + toff[tr][q] + xd);
+        } else {
+            const int j = tjk[tr][0], k = tjk[tr][1];
+            const int fz = r.first[2][k], nz = r.cnt[2][k], oz = r.off[2][k];
+            const int fy = r.first[1][j], ny = r.cnt[1][j], oy = r.off[1][j];
+            for (int kz = 0; kz < nz; ++kz)
+                for (int ky = 0; ky < ny; ++ky)
+                    term(W(r.w[2][oz + kz] * r.w[1][oy + ky]), rx + ((fz + kz - zs0) * Ys + (fy + ky - ys0)) * ndx + xd);
         }
+        T *o = out + orow[tr] + xd;
+        if (vec4) {
+            const Vec4NT<T> v = {T(acc[0]), T(acc[1]), T(acc[2]), T(acc[3])};
+            __builtin_nontemporal_store(v, reinterpret_cast<Vec4NT<T> *>(o));
+        } else {
+            __builtin_nontemporal_store(T(acc[0]), o);
+        }
+        xw += dxw;
+        int d = dtr;
+        if (xw >= nxw) {
+            xw -= nxw;
+            ++d;
+        }
+        tr += d;
     }
 }
 
@@ -378,7 +470,8 @@ static hipError_t launch_remap(const couple_remap *r, const void *src, void *dst
         a.ndst *= r->nd[k];
     }
     const size_t lds = sizeof(T) * (size_t)r->ns[0];
-    const size_t tile_lds = sizeof(T) * r->tile_slab_rows * ((size_t)r->ns[0] + r->nd[0]);   // slab + rx
+    const size_t tile_lds =
+        sizeof(T) * (((r->tile_slab_rows * (size_t)r->ns[0] + 3) & ~(size_t)3) + r->tile_slab_rows * r->nd[0]);   // slab + rx
     bool tile_ok = r->tile_slab_rows > 0 && tile_lds <= kTileLdsBytes;
     if (tile_ok && tile_lds > 64 * 1024) {
         // more than 64 KB of dynamic LDS per workgroup must be allowed explicitly
@@ -388,9 +481,12 @@ static hipError_t launch_remap(const couple_remap *r, const void *src, void *dst
     }
     if (tile_ok) {
         const int64_t ntile = (int64_t)((r->nd[1] + kTileJ - 1) / kTileJ) * ((r->nd[2] + kTileK - 1) / kTileK);
+        const bool vec4 = r->nd[0] % 4 == 0 && reinterpret_cast<uintptr_t>(dst) % (4 * sizeof(T)) == 0;
         hipLaunchKernelGGL((k_remap_tile<T, KAHAN>), dim3((unsigned)ntile, (unsigned)nfields), dim3(kBlock), tile_lds,
-                           st, a, static_cast<const T *>(src), static_cast<T *>(dst));
+                           st, a, static_cast<const T *>(src), static_cast<T *>(dst), vec4);
     } else if (lds <= kRowLdsBytes) {
+        // enough workgroups to fill the chip several times over, each looping
+        // over rows (a row is a small amount of work when the receiver is finer)
         // enough workgroups to fill the chip several times over, each looping
         // over rows (a row is a small amount of work when the receiver is finer)
         const int64_t nrow = (int64_t)r->nd[1] * r->nd[2];
