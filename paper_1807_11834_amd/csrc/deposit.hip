@@ -143,9 +143,9 @@ template <typename T, int MODE> struct RowStage {
 // FP32 mode both products are exact in FP64, so every term is rounded once at
 // FP64 precision: at least as accurate as a Kahan-compensated FP32 sum, for one
 // instruction per term instead of five (FP64 FMAs issue at the rate of unpacked
-// FP32 ones on this chip).  In the FP64 mode the at most ~100 terms of a partial
-// sum carry a relative error below 1e-14 of their magnitudes.  The naive FP32
-// mode sums with plain FP32 FMAs.
+// FP32 ones on this chip).  The FP64 mode sums with plain FP64 FMAs (the at most
+// ~100 terms of a partial sum carry an error below 1e-14 of their magnitudes),
+// the naive FP32 mode with plain FP32 FMAs.
 template <typename T, bool KAHAN> struct RowSum {
     using W = typename std::conditional<KAHAN, double, T>::type;
     W s = W(0);

@@ -138,8 +138,7 @@ __device__ __forceinline__ void sample_particles(const int64_t (&idx)[KB], const
 // ties, and the FP32 residue lo = S - hi carries the rest of the pressure for
 // the gradient (a per-plane Kahan sum recombined over the planes keeps only
 // part of it); one convert and one FP64 add per child instead of Kahan's four
-// instructions.  The FP64 mode compensates in FP64 (Kahan), naive FP32 sums
-// plainly.
+// instructions.  The FP64 and naive FP32 modes sum plainly in their own type.
 template <typename T, bool KAHAN> struct ChildSum {
     static constexpr bool kWide = std::is_same<T, float>::value && KAHAN;
     using W = typename std::conditional<kWide, double, T>::type;
@@ -179,8 +178,8 @@ __global__ __launch_bounds__(kBlock) void k_restrict(StepArgs<T> a) {
             for (int lz = 0; lz < R; ++lz)
 #pragma unroll
                 for (int ly = 0; ly < R; ++ly) rows[lz][ly] = load_row<T, R>(q + lz * nfxy + ly * nfx);
-            // per fine child plane, then the planes in order (s_0, -c_0, s_1, ...):
-            // the same sums as the brick-tiled kernel
+            // per fine child plane, then the planes in order (with a Kahan sum,
+            // s_0, -c_0, s_1, ...): the same sums as the brick-tiled kernel
             ChildSum<T, KAHAN> acc;
 #pragma unroll
             for (int lz = 0; lz < R; ++lz) {
@@ -364,8 +363,9 @@ __global__ __launch_bounds__(kBrickThreads) void k_restrict_brick(StepArgs<T> a)
                     for (int rx = 0; rx < R; ++rx) sv[f][lz * R + rz][ly * R + ry][lx * R + rx] = rows[ry].v[rx];
             }
         }
-        // the planes of this cell in order (s_0, -c_0, s_1, ...), read from the
-        // cell's four lanes; the plane-0 lane writes the average
+        // the planes of this cell in order (with a Kahan sum, s_0, -c_0, s_1,
+        // ...), read from the cell's four lanes; the plane-0 lane writes the
+        // average
         ChildSum<T, KAHAN> acc;
         const int l0 = lane & ~3;
 #pragma unroll
