@@ -3,8 +3,9 @@ receiver interpolation of Sec. 2.3) against the FP64 oracle, through the C ABI.
 
 e_max of a receiver cell: |g - o| / max(M_c, 1e-3 max M), with M the transfer of
 |src| (the size of the terms the cell sums).  FP32 within 1e-4, FP64 within 1e-6.
-Both kernels are covered: receiver rows from LDS-staged sender rows, and one
-thread per receiver cell for sender rows longer than the LDS buffer.
+All three kernels are covered: receiver rows from LDS-staged sender rows, tiles
+of receiver rows finer than the sender (with and without four-cell stores),
+and one thread per receiver cell for sender rows longer than the LDS buffer.
 At the packed bed's full fine-grid size the transfer is compared on sampled
 receiver cells (each one an oracle call on the sender cells it overlaps) and
 checked for constants and the conserved integral.
@@ -54,6 +55,11 @@ CASES = [
     ((32, 24, 20), (8, 6, 5), (1.0, 0.75, 0.625), "uniform", "fp32n", 1),
     ((1, 30, 2), (1, 7, 5), (0.1, 1.0, 0.3), "random", "fp32k", 1),
     ((61, 3, 47), (29, 5, 13), (1.0, 0.1, 0.8), "random", "fp32k", 1),
+    # receiver finer in y and z with rows a multiple of 4 long: the tile kernel's
+    # four-cell stores; with random spacing some receiver rows overlap more
+    # than 2 x 2 sender rows (the table's overflow path)
+    ((6, 9, 8), (16, 11, 10), (1.0, 0.8, 0.6), "random", "fp32k", 2),
+    ((5, 4, 3), (12, 8, 8), (1.0, 1.0, 1.0), "uniform", "fp64", 1),
     # single cells
     ((1, 1, 1), (1, 1, 1), (0.5, 0.25, 2.0), "uniform", "fp32k", 2),
     ((1, 1, 1), (3, 2, 5), (0.5, 0.25, 2.0), "random", "fp64", 1),
