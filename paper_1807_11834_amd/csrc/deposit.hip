@@ -7,8 +7,9 @@
 //   KU_c    = (1/V_b) sum_p w_pc beta_p u_p         F_fpi = -K u_f + KU in uniform flow)
 //
 // The particles are in the canonical (cell, id) order with CSR offsets `start`.
-// CIC: two passes through per-row partial sums (see below); every particle is
-// staged once per pass.  NGP: one thread per cell sums its own segment.
+// CIC: two passes through partial sums per group of source rows (see below);
+// every particle is staged once per pass.  NGP: one thread per cell sums its
+// own segment.
 #include <type_traits>
 
 #include "common.hpp"
