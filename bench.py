@@ -478,7 +478,8 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="bed128_cic")
-    ap.add_argument("--cpu-frac", type=float, default=0.25, help="x-y fraction of the oracle sample")
+    ap.add_argument("--cpu-frac", type=float, default=0.3125,
+                    help="x-y fraction of the oracle sample (40 of the bed's 128 bulk cells per axis)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-presorted", action="store_true", help="skip the spatially sorted input variant")
     ap.add_argument("--vel-source", default="fine", choices=["fine", "bulk"],
