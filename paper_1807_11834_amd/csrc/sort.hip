@@ -259,7 +259,7 @@ __global__ __launch_bounds__(kBlock) void k_segment_starts(const uint32_t *__res
         const int l = __ffsll((unsigned long long)m) - 1;
         m &= m - 1;
         const int32_t glo = __shfl(lo, l, kWave), ghi = __shfl(hi, l, kWave), gi = __shfl((int32_t)i, l, kWave);
-        for (int32_t c = glo + lane; c <= ghi; c += kWave) start[c] = gi;
+        for (int64_t c = (int64_t)glo + lane; c <= ghi; c += kWave) start[c] = gi;   // 64-bit: no wrap near 2^31
     }
 }
 
