@@ -16,6 +16,8 @@ of the element and S the size of the field's inputs, as the arithmetic sees them
     of its terms M_c = (1/V_b) sum_p w_pc |F_p|;
   * prolonged F_fpi: m_i = max of M over the 27 bulk cells that feed the parent.
 """
+import os
+
 import numpy as np
 
 # Tolerances of the parity contract.
@@ -179,3 +181,10 @@ def compare_step(g, o, n, nb, r, fp64, check_fine=True, fine_sample=None, label=
     if check_fine and fine_sample is None and "E_f" in od:
         assert rel(d["E_f"], od["E_f"], od["E_f"]) <= TOL_REDUCTION
     return errs
+
+
+def results_dir():
+    """Where GPU tests write their reports (JSON): $COUPLE_RESULTS_DIR, else
+    results/ at the repository root."""
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    return os.environ.get("COUPLE_RESULTS_DIR") or os.path.join(root, "results")

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import workload as W
-from parity_util import cfg_for, to_dev
+from parity_util import cfg_for, to_dev, results_dir
 
 pytestmark = pytest.mark.gpu
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -89,8 +89,8 @@ def test_training_gain_cube64(env):
            "rel_err_mlp_with_fallback": e_mlp_fb, "sampled_rel_err": sampled,
            "fallback_particles": dmf["n_fallback"], "n": int(pv.shape[0])}
     print(json.dumps(rec), flush=True)
-    os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
-    with open(os.path.join(ROOT, "gpurun_out", "surrogate_gain_cube64.json"), "w") as f:
+    os.makedirs(results_dir(), exist_ok=True)
+    with open(os.path.join(results_dir(), "surrogate_gain_cube64.json"), "w") as f:
         json.dump(rec, f, indent=1)
     mlp.close()
     assert hist[-1][1] < hist[0][1] / 20

@@ -8,8 +8,8 @@ import numpy as np
 import pytest
 
 import workload as W
-from parity_util import (TOL_FP32_FIELD, TOL_FP64_FIELD, TOL_NAIVE, cfg_for, compare_step, emax, rms_rel,
-                         run_gpu, to_dev)
+from parity_util import (TOL_FP32_FIELD, TOL_FP64_FIELD, TOL_NAIVE, cfg_for, compare_step, emax, results_dir,
+                         rms_rel, run_gpu, to_dev)
 
 pytestmark = pytest.mark.gpu
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -221,8 +221,8 @@ def test_precision_study_bed128_sub2m(env, tmp_path):
             "(S_b + sum F_p) / sum|F_p|": [(dg["S_b"][a] + dg["sum_Fp"][a]) / sabs[a] for a in range(3)],
             "(S_f - S_b) / sum|F_p|": [(dg["S_f"][a] - dg["S_b"][a]) / sabs[a] for a in range(3)],
         }
-    os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
-    with open(os.path.join(ROOT, "gpurun_out", "precision_study_bed128_sub2m.json"), "w") as f:
+    os.makedirs(results_dir(), exist_ok=True)
+    with open(os.path.join(results_dir(), "precision_study_bed128_sub2m.json"), "w") as f:
         json.dump(report, f, indent=1)
     print(json.dumps(report, indent=1))
     assert max(report["fp64"]["e_max"].values()) <= TOL_FP64_FIELD
