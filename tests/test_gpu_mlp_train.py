@@ -1,5 +1,5 @@
 """The surrogate trained on the GPU by the library's own kernels, and what it
-gains over the method without it (bulk trilinear interpolation), judged against
+gains over the method without it (bulk trilinear interpolation), measured against
 the fine-grid lookup on held-out particles."""
 import json
 import os
