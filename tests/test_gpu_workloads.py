@@ -236,6 +236,9 @@ def test_precision_study_bed128_sub2m(env, tmp_path):
     k = report["fp32_kahan"]["e_max"]
     assert k["U"] <= 1.2e-7 and k["P"] <= 1.2e-7, k
     assert k["G"] <= 3e-7, k
+    # The deposited fields are limited by the FP32 positions, diameters and drag
+    # (a few roundings of each term), not by the sums: measured 2e-7 to 6e-7.
+    assert k["phi"] <= 1e-6 and k["F"] <= 2e-6 and k["fine_eps"] <= 1e-6 and k["fine_F"] <= 2e-6, k
 
 
 def test_bed128_surrogate_full_size_sampled(env):
