@@ -199,10 +199,19 @@ def cpu_baseline(w, frac):
     pos, d, vel = pos[m], d[m], vel[m]
     fine = W.fine_fields(sub)
     oracle.lib()
-    t0 = time.perf_counter()
-    oracle.step(pos, vel, d, fine, sub.grid, rho_f=w.rho_f, mu_f=w.mu_f, rho_p=w.rho_p, eps_min=w.eps_min,
-                cic=True, prec32=True, vel_source="fine")
-    dt = time.perf_counter() - t0
+
+    def one_step(threads):
+        prev = oracle.set_threads(threads)
+        t0 = time.perf_counter()
+        oracle.step(pos, vel, d, fine, sub.grid, rho_f=w.rho_f, mu_f=w.mu_f, rho_p=w.rho_p, eps_min=w.eps_min,
+                    cic=True, prec32=True, vel_source="fine")
+        dt = time.perf_counter() - t0
+        oracle.set_threads(prev)
+        return dt
+
+    dt = one_step(1)
+    ncores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    dt_all = one_step(ncores)
     cpu = platform.processor() or platform.machine()
     try:
         with open("/proc/cpuinfo") as f:
@@ -215,7 +224,10 @@ def cpu_baseline(w, frac):
     return {"value": pos.shape[0] / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
             "sample": (f"one oracle step (FP64, single thread) on the sub-box x<{frac}, y<{frac} of the same "
                        f"workload: {pos.shape[0]} particles, bulk {sub.grid.nb}, fine {sub.grid.nf}; "
-                       f"{dt:.1f} s; host {cpu}, {os.cpu_count()} logical CPUs")}
+                       f"{dt:.1f} s; host {cpu}, {os.cpu_count()} logical CPUs"),
+            "all_cores": {"value": pos.shape[0] / dt_all, "cores": ncores, "seconds": round(dt_all, 2),
+                          "note": "same sample; OpenMP over the oracle's independent per-particle / per-cell "
+                                  "loops, the canonical-order deposition sums and the sort stay serial"}}
 
 
 def _rel(a, b):
@@ -295,18 +307,16 @@ def mlp_leg(args, w, cfg, pos, vel, diam, fine, plain_ms, plain_kernels, dev):
     out = cpl.alloc_outputs(cm.cfg, n, device=dev)
     for k in range(args.warmup):
         cm.step(pos, vel, diam, fine, out=out, step=k)
-    torch.cuda.synchronize()
-    cpl.couple_timing_begin(cm.h, args.steps)
     stream = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for k in range(args.steps):
+    total, per = timed_steps(lambda k: cm.step(pos, vel, diam, fine, out=out, step=k), args.steps, stream)
+    ms = total / args.steps
+    dfin = cpl.diag_dict(out["diag"])
+    nk = min(args.steps, 20)
+    cpl.couple_timing_begin(cm.h, nk)
+    for k in range(nk):
         cm.step(pos, vel, diam, fine, out=out, step=k)
-    e1.record(stream)
     torch.cuda.synchronize()
     stats = cpl.couple_timing_end(cm.h)
-    ms = e0.elapsed_time(e1) / args.steps
-    dfin = cpl.diag_dict(out["diag"])
     cm.close()
     mlp.close()
     kern = {k: {"launches": l, "avg_ms": t / l} for k, (l, t) in stats.items() if l}
@@ -316,7 +326,7 @@ def mlp_leg(args, w, cfg, pos, vel, diam, fine, plain_ms, plain_kernels, dev):
     vel_mlp = sum(kern[k]["avg_ms"] for k in ("restrict", "mlp_pack", "mlp_infer", "mlp_check") if k in kern)
     vel_plain = plain_kernels.get("restrict_lookup", {}).get("avg_ms")
     return {
-        "ms_per_step": ms, "value": n / (ms * 1e-3), "unit": "particle-steps/s",
+        "ms_per_step": ms, "value": n / (ms * 1e-3), "unit": "particle-steps/s", "per_step": step_stats(per),
         "speedup_vs_plain_step": plain_ms / ms,
         "velocity_stage_ms": {"plain (restrict + fine lookup)": vel_plain,
                               "mlp (restrict + pack + infer + check/fallback)": round(vel_mlp, 4)},
@@ -335,9 +345,72 @@ def mlp_leg(args, w, cfg, pos, vel, diam, fine, plain_ms, plain_kernels, dev):
     }
 
 
+def timed_steps(step_fn, k, stream):
+    """Run ``step_fn`` k times on ``stream`` with one HIP event between
+    consecutive steps (no per-kernel markers); returns (total ms, per-step ms)."""
+    import torch
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(k + 1)]
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    for i in range(k):
+        step_fn(i)
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    return ev[0].elapsed_time(ev[k]), [ev[i].elapsed_time(ev[i + 1]) for i in range(k)]
+
+
+def step_stats(per):
+    a = np.asarray(per, dtype=np.float64)
+    return {"steps": int(a.size), "median_ms": round(float(np.median(a)), 4), "mean_ms": round(float(a.mean()), 4),
+            "sd_ms": round(float(a.std(ddof=1)) if a.size > 1 else 0.0, 4), "min_ms": round(float(a.min()), 4),
+            "max_ms": round(float(a.max()), 4)}
+
+
+def advected_leg(args, dev):
+    """The 64^3 / 256^3 Taylor-Green cube with 2,000,000 particles advanced by
+    its 100 explicit-Euler steps (dt = 1e-4, drag the only force, re-binned every
+    step), timed whole from the initial state after a warm-up on a copy."""
+    import torch
+    import paper_1807_11834_amd as cpl
+    import workload as W
+    w = W.WORKLOADS["cube64_cic"]
+    g = w.grid
+    p0, d0, v0 = W.particles(w)
+    n = p0.shape[0]
+    fine = W.fine_fields_torch(w, dev, torch.float32)
+    diam = torch.from_numpy(d0).to(dev)
+    cfg = cpl.Config(box=g.box, nb=g.nb, ratio=g.ratio, rho_f=w.rho_f, mu_f=w.mu_f, rho_p=w.rho_p,
+                     eps_min=w.eps_min, advect=1, dt=w.dt, max_particles=n)
+    c = cpl.Coupler(cfg)
+    out = cpl.alloc_outputs(cfg, n, device=dev)
+    try:
+        pos, vel = torch.from_numpy(p0).to(dev), torch.from_numpy(v0).to(dev)
+        for _ in range(max(args.warmup, 1)):
+            c.step(pos, vel, diam, fine, out=out)
+        pos, vel = torch.from_numpy(p0).to(dev), torch.from_numpy(v0).to(dev)
+        stream = torch.cuda.current_stream()
+        total, per = timed_steps(lambda i: c.step(pos, vel, diam, fine, out=out, step=i), w.steps, stream)
+        dg = cpl.diag_dict(out["diag"])
+    finally:
+        c.close()
+    ms = total / w.steps
+    sb = step_alg_bytes(n, g.n_bulk, g.n_fine, 4, sort_passes(g.n_bulk)) + 24 * n   # + advected pos, vel
+    print(f"# advected cube: {ms:.3f} ms/step", file=sys.stderr, flush=True)
+    del fine, out
+    torch.cuda.empty_cache()
+    return {"workload": f"{w.name}: {n} particles, bulk {g.nb}, fine {g.nf}, CIC, FP32, {w.steps} explicit-Euler "
+                        f"steps of dt = {w.dt} timed whole",
+            "ms_per_step": ms, "value": n * w.steps / (total * 1e-3), "unit": "particle-steps/s",
+            "per_step": step_stats(per), "step_alg_bytes": sb,
+            "step_alg_GBps": round(sb / (ms * 1e-3) / 1e9, 1),
+            "step_alg_frac_hbm": round(sb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+            "n_outside_last_step": dg["n_outside"]}
+
+
 def _time_variant(args, cfg_v, pos, vel, diam, fine, n, dev, alpha=None):
-    """Warm up, then time ``args.steps`` steps of a configuration variant with
-    per-kernel events; returns (ms per step, {kernel: avg ms}, diagnostics)."""
+    """Warm up, then time ``args.steps`` steps of a configuration variant (no
+    markers), then up to 20 steps with per-kernel events; returns (ms per step,
+    {kernel: avg ms}, diagnostics)."""
     import torch
     import paper_1807_11834_amd as cpl
     c = cpl.Coupler(cfg_v)
@@ -345,19 +418,16 @@ def _time_variant(args, cfg_v, pos, vel, diam, fine, n, dev, alpha=None):
     try:
         for _ in range(args.warmup):
             c.step(pos, vel, diam, fine, out=out, alpha=alpha)
-        torch.cuda.synchronize()
         stream = torch.cuda.current_stream()
-        cpl.couple_timing_begin(c.h, args.steps)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(args.steps):
+        ms = timed_steps(lambda i: c.step(pos, vel, diam, fine, out=out, alpha=alpha), args.steps, stream)[0] \
+            / args.steps
+        d = cpl.diag_dict(out["diag"])
+        nk = min(args.steps, 20)
+        cpl.couple_timing_begin(c.h, nk)
+        for _ in range(nk):
             c.step(pos, vel, diam, fine, out=out, alpha=alpha)
-        e1.record(stream)
         torch.cuda.synchronize()
         stats = cpl.couple_timing_end(c.h)
-        ms = e0.elapsed_time(e1) / args.steps
-        d = cpl.diag_dict(out["diag"])
     finally:
         c.close()
     del out
@@ -475,7 +545,7 @@ def remap_leg(args, g, fine, fsz, dev):
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="bed128_cic")
     ap.add_argument("--cpu-frac", type=float, default=0.3125,
@@ -488,6 +558,7 @@ def main():
     ap.add_argument("--no-semi", action="store_true", help="skip the semi-implicit split variant")
     ap.add_argument("--no-vof", action="store_true", help="skip the two-fluid drag variant")
     ap.add_argument("--no-remap", action="store_true", help="skip the non-nested grid transfer")
+    ap.add_argument("--no-advected", action="store_true", help="skip the 100-step advected 64^3 cube")
     ap.add_argument("--traffic-summary", metavar="DIR",
                     help="print the JSON summary of the FETCH_SIZE/WRITE_SIZE runs under DIR and exit")
     ap.add_argument("--trace-summary", metavar="CSV",
@@ -551,20 +622,22 @@ def main():
     print(f"# warmup done: {args.warmup} steps", file=sys.stderr, flush=True)
 
     stream = torch.cuda.current_stream()
-    cpl.couple_timing_begin(c.h, args.steps)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(args.steps):
-        c.step(pos, vel, diam, fine, out=out)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    stats = cpl.couple_timing_end(c.h)
-    ms_total = e0.elapsed_time(e1)
+    # headline: exactly --steps steps, one event between consecutive steps, no
+    # per-kernel markers inside the timed loop
+    step_fn = lambda i: c.step(pos, vel, diam, fine, out=out)
+    ms_total, per = timed_steps(step_fn, args.steps, stream)
     ms_step = ms_total / args.steps
     value = n * args.steps / (ms_total / 1e3)
     print(f"# timed {args.steps} steps: {ms_step:.3f} ms/step", file=sys.stderr, flush=True)
+    # the median over at least 100 steps (a second loop when --steps is smaller)
+    per100 = per if args.steps >= 100 else timed_steps(step_fn, 100, stream)[1]
+    # per-kernel HIP events in a separate loop
+    nk = min(args.steps, 20)
+    cpl.couple_timing_begin(c.h, nk)
+    for _ in range(nk):
+        c.step(pos, vel, diam, fine, out=out)
+    torch.cuda.synchronize()
+    stats = cpl.couple_timing_end(c.h)
 
     kernels = {k: {"launches": l, "avg_ms": t / l} for k, (l, t) in stats.items() if l}
     dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
@@ -586,6 +659,8 @@ def main():
                                 f"{w.deposit.upper()}, {'FP64' if fp64 else 'FP32 + Kahan, FP64 sums'}, "
                                 f"{args.vel_source}-grid velocity at the particles"),
                    "n_particles": n, "bulk": list(g.nb), "fine": list(g.nf)},
+        "per_step": step_stats(per),
+        "median_of_100": step_stats(per100),
         "roofline": roof,
         "step_alg_bytes": sb, "step_alg_GBps": round(sb / (ms_step * 1e-3) / 1e9, 1),
         "step_alg_frac_hbm": round(sb / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
@@ -601,16 +676,12 @@ def main():
         pos_s, vel_s, diam_s = pos[perm].contiguous(), vel[perm].contiguous(), diam[perm].contiguous()
         for _ in range(args.warmup):
             c.step(pos_s, vel_s, diam_s, fine, out=out)
-        torch.cuda.synchronize()
-        e0.record(stream)
-        for _ in range(args.steps):
-            c.step(pos_s, vel_s, diam_s, fine, out=out)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms_s = e0.elapsed_time(e1) / args.steps
+        ms_s = timed_steps(lambda i: c.step(pos_s, vel_s, diam_s, fine, out=out), args.steps, stream)[0] / args.steps
         rec["presorted_input"] = {"ms_per_step": ms_s, "value": n / (ms_s * 1e-3),
                                   "note": "same particles passed in the canonical (cell, id) order"}
         del pos_s, vel_s, diam_s
+    if not args.no_advected:
+        rec["advected_cube64"] = advected_leg(args, dev)
     if not args.no_semi:
         rec["semi_implicit"] = semi_leg(args, cfg, pos, vel, diam, fine, ms_step, n, g, fsz, dev)
     if not args.no_vof:

@@ -35,7 +35,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 def build(force=True):
     """Compile the C oracle with gcc (plain FP64, no fast-math, no contraction)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
                                "-fPIC", "-shared", "-o", _LIB + ".tmp", _SRC, "-lm"])
         os.replace(_LIB + ".tmp", _LIB)
 
@@ -75,12 +75,26 @@ def lib():
         L.orc_advect.argtypes = [I64, P, P, P, P, D, D, P, I]
         L.orc_particle_volumes.argtypes = [I64, P, P]
         L.orc_remap.argtypes = [P, P, P, P, P, P]
+        L.orc_set_threads.argtypes = [I]
+        L.orc_set_threads.restype = None
+        L.orc_get_threads.argtypes = []
+        L.orc_get_threads.restype = I
         for name in ("orc_deposit_volume", "orc_deposit_force", "orc_deposit_semi", "orc_gather_eps", "orc_restrict",
                      "orc_gradient", "orc_interp", "orc_prolong", "orc_prolong_at", "orc_advect",
                      "orc_particle_volumes", "orc_remap"):
             getattr(L, name).restype = None
+        L.orc_set_threads(1)    # one thread unless asked (set_threads)
         _lib = L
     return _lib
+
+
+def set_threads(k):
+    """Threads of the oracle's independent-iteration loops (the canonical-order
+    sums are always serial; results do not depend on k).  Returns the previous
+    setting."""
+    prev = lib().orc_get_threads()
+    lib().orc_set_threads(int(k))
+    return prev
 
 
 def _p(a):

@@ -33,13 +33,24 @@
  *
  * Layout: particle vectors are [n][3] (x,y,z); grid fields are [nz][ny][nx] with x
  * fastest; vector grid fields are three such arrays back to back ([3][nz][ny][nx]).
+ *
+ * Threads: loops whose iterations are independent (one particle, one cell or one
+ * point each, no shared sum) may run on several OpenMP threads (orc_set_threads;
+ * one thread unless asked).  Every sum whose order is the canonical one (the
+ * depositions in (cell, id) order, the sort) stays serial, so the results do not
+ * depend on the number of threads.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
 #define ORC_PI 3.14159265358979323846
+
+/* Threads of the independent-iteration loops (see the header comment). */
+void orc_set_threads(int k) { omp_set_num_threads(k > 0 ? k : 1); }
+int orc_get_threads(void) { return omp_get_max_threads(); }
 
 static int64_t lin3(int64_t i, int64_t j, int64_t k, const int n[3])
 {
@@ -89,6 +100,7 @@ int64_t orc_bin(int64_t n, const double *pos, const double box[3], const int nb[
                 int prec32, int32_t *cell)
 {
     int64_t outside = 0;
+#pragma omp parallel for schedule(static) reduction(+ : outside)
     for (int64_t p = 0; p < n; ++p) {
         double x[3];
         int idx[3];
@@ -274,6 +286,7 @@ void orc_deposit_semi(int64_t n, const double *pos, const double *beta, const do
 void orc_gather_eps(int64_t n, const double *pos, const double *phi, const double box[3],
                     const int nb[3], int cic, int prec32, double *eps_p)
 {
+#pragma omp parallel for schedule(static)
     for (int64_t p = 0; p < n; ++p) {
         double x[3];
         if (prec32) clamp_pos32(pos + 3 * p, box, x); else clamp_pos(pos + 3 * p, box, x);
@@ -294,6 +307,7 @@ void orc_restrict(const double *qf, const int nb[3], int r, double *qb)
 {
     int nf[3] = {nb[0] * r, nb[1] * r, nb[2] * r};
     double inv = 1.0 / ((double)r * r * r);
+#pragma omp parallel for schedule(static) collapse(2)
     for (int k = 0; k < nb[2]; ++k)
         for (int j = 0; j < nb[1]; ++j)
             for (int i = 0; i < nb[0]; ++i) {
@@ -312,6 +326,7 @@ void orc_restrict(const double *qf, const int nb[3], int r, double *qb)
 void orc_gradient(const double *P, const int nb[3], const double box[3], double *G)
 {
     int64_t nc = (int64_t)nb[0] * nb[1] * nb[2];
+#pragma omp parallel for schedule(static) collapse(2)
     for (int k = 0; k < nb[2]; ++k)
         for (int j = 0; j < nb[1]; ++j)
             for (int i = 0; i < nb[0]; ++i) {
@@ -372,6 +387,7 @@ static double trilinear(const double *q, const int n[3], const double box[3], co
 void orc_interp(const double *q, const int n[3], const double box[3], int64_t npts,
                 const double *pos, int prec32, double *out)
 {
+#pragma omp parallel for schedule(static)
     for (int64_t p = 0; p < npts; ++p) {
         double x[3];
         if (prec32) clamp_pos32(pos + 3 * p, box, x); else clamp_pos(pos + 3 * p, box, x);
@@ -413,6 +429,7 @@ static int64_t drag_var(int64_t n, const double *uf, const double *up, const dou
                         double *force, double *beta)
 {
     int64_t clamped = 0;
+#pragma omp parallel for schedule(static) reduction(+ : clamped)
     for (int64_t p = 0; p < n; ++p) {
         double ur[3], mag2 = 0.0;
         for (int a = 0; a < 3; ++a) {
@@ -492,6 +509,7 @@ static double defect(const double *B, const int nb[3], int r, int i, int j, int 
 void orc_prolong(const double *B, const int nb[3], int r, int conservative, double *out)
 {
     int nf[3] = {nb[0] * r, nb[1] * r, nb[2] * r};
+#pragma omp parallel for schedule(static) collapse(2)
     for (int k = 0; k < nb[2]; ++k)
         for (int j = 0; j < nb[1]; ++j)
             for (int i = 0; i < nb[0]; ++i) {
@@ -510,6 +528,7 @@ void orc_prolong_at(const double *B, const int nb[3], int r, int conservative,
                     int64_t m, const int64_t *fidx, double *out)
 {
     int nf[3] = {nb[0] * r, nb[1] * r, nb[2] * r};
+#pragma omp parallel for schedule(static)
     for (int64_t q = 0; q < m; ++q) {
         int64_t f = fidx[q];
         int64_t fi = f % nf[0];
@@ -525,36 +544,38 @@ void orc_prolong_at(const double *B, const int nb[3], int r, int conservative,
 /*   x <- x + dt u,  u <- u + dt F / m,  m = rho_p pi d^3 / 6,                */
 /* from the clamped old position; a coordinate that leaves [0, L] is          */
 /* mirrored back (x -> -x, or x -> 2L - x) and that velocity component flips.  */
-/* With prec32 the position/velocity updates are evaluated in binary32 as     */
-/* fused multiply-adds (each result rounded once), the velocity increment      */
-/* dt F / m being formed in FP64 and rounded to binary32 first.               */
+/* The new position and velocity are computed in FP64 in both modes.          */
+/* Whether a wall was crossed is a discrete decision taken on floating-point  */
+/* values: with prec32 it is taken in binary32, the precision of the state    */
+/* the FP32 modes advance, on the candidate position x + dt u rounded once to */
+/* binary32 (fmaf: the exact product and sum, one rounding; x, u, dt and L    */
+/* being binary32 values there).  Without prec32 the FP64 candidate decides.  */
 /* ------------------------------------------------------------------------- */
 void orc_advect(int64_t n, double *pos, double *vel, const double *diam, const double *force,
                 double rho_p, double dt, const double box[3], int prec32)
 {
+#pragma omp parallel for schedule(static)
     for (int64_t p = 0; p < n; ++p) {
         double x[3];
         if (prec32) clamp_pos32(pos + 3 * p, box, x); else clamp_pos(pos + 3 * p, box, x);
         double m = rho_p * particle_volume(diam[p]);
         for (int a = 0; a < 3; ++a) {
             double u = vel[3 * p + a];
-            double xn, un;
+            double L = box[a];
+            double xn = x[a] + dt * u;
+            double un = u + dt * force[3 * p + a] / m;
+            int below, above;
             if (prec32) {
-                float acc = (float)(force[3 * p + a] / m);
-                xn = (double)fmaf((float)dt, (float)u, (float)x[a]);
-                un = (double)fmaf((float)dt, acc, (float)u);
-                float L = (float)box[a];
-                if (xn < 0.0) { xn = (double)(-(float)xn); un = -un; }
-                else if (xn > (double)L) { xn = (double)(2.0f * L - (float)xn); un = -un; }
-                xn = (double)fminf(fmaxf((float)xn, 0.0f), L);
+                float c = fmaf((float)dt, (float)u, (float)x[a]);
+                below = c < 0.0f;
+                above = c > (float)L;
             } else {
-                xn = x[a] + dt * u;
-                un = u + dt * force[3 * p + a] / m;
-                double L = box[a];
-                if (xn < 0.0) { xn = -xn; un = -un; }
-                else if (xn > L) { xn = 2.0 * L - xn; un = -un; }
-                xn = fmin(fmax(xn, 0.0), L);
+                below = xn < 0.0;
+                above = xn > L;
             }
+            if (below) { xn = -xn; un = -un; }
+            else if (above) { xn = 2.0 * L - xn; un = -un; }
+            xn = fmin(fmax(xn, 0.0), L);
             pos[3 * p + a] = xn;
             vel[3 * p + a] = un;
         }
@@ -582,6 +603,7 @@ void orc_remap(const int ns[3], const double *src_nodes, const int nd[3], const 
     const double *xs[3], *xd[3];
     xs[0] = src_nodes; xs[1] = xs[0] + ns[0] + 1; xs[2] = xs[1] + ns[1] + 1;
     xd[0] = dst_nodes; xd[1] = xd[0] + nd[0] + 1; xd[2] = xd[1] + nd[1] + 1;
+#pragma omp parallel for schedule(static) collapse(2)
     for (int k = 0; k < nd[2]; ++k)
         for (int j = 0; j < nd[1]; ++j)
             for (int i = 0; i < nd[0]; ++i) {

@@ -49,6 +49,14 @@ class CoupleError(RuntimeError):
         self.code = code
 
 
+class ArgumentError(CoupleError, ValueError):
+    """An argument rejected by the binding's checks before the library is
+    called (the code is the one the library would return, where it checks)."""
+
+    def __init__(self, msg, code=COUPLE_EINVAL):
+        super().__init__(code, msg)
+
+
 class _Config(C.Structure):
     _fields_ = [("box", C.c_double * 3), ("nb", C.c_int32 * 3), ("ratio", C.c_int32),
                 ("rho_f", C.c_double), ("mu_f", C.c_double), ("rho_p", C.c_double), ("eps_min", C.c_double),
@@ -198,17 +206,22 @@ def _check(code, h):
         raise CoupleError(code, couple_last_error(h))
 
 
+_HANDLE_CFG = {}   # handle address -> its Config (for the argument checks)
+
+
 def couple_init(cfg: Config):
     """Validate ``cfg`` and allocate the library scratch; returns the handle."""
     h = C.c_void_p()
     c = cfg.to_c()
     code = _lib.couple_init(C.byref(c), C.byref(h))
     _check(code, None)
+    _HANDLE_CFG[h.value] = Config(**cfg.__dict__)
     return h
 
 
 def couple_free(h):
     if h is not None:
+        _HANDLE_CFG.pop(h.value, None)
         _check(_lib.couple_free(h), None)
 
 
@@ -216,9 +229,93 @@ def _ptr(t):
     return None if t is None else t.data_ptr()
 
 
+# ---- argument checks ------------------------------------------------------------
+# The kernels index every array by sizes taken from the configuration, so a
+# tensor of the wrong size, type, device or layout would be read or written out of
+# bounds (or reinterpreted).  Every tensor is checked before the library sees its
+# address; a failure raises ArgumentError (a ValueError) and nothing is launched.
+
+def check_tensor(name, t, dtype, numel, device=None, optional=False, require_gpu=True, align=16, why=""):
+    """Check one argument: a torch tensor on ``device`` (a GPU unless
+    ``require_gpu`` is False) of ``dtype`` with ``numel`` elements, C-contiguous
+    and ``align``-byte aligned.  ``None`` is accepted when ``optional``; ``why``
+    says what makes a missing argument required."""
+    if t is None:
+        if optional:
+            return
+        raise ArgumentError(f"{name}: required{' ' + why if why else ''}, got None")
+    if not isinstance(t, torch.Tensor):
+        raise ArgumentError(f"{name}: expected a torch.Tensor, got {type(t).__name__}")
+    if require_gpu and t.device.type != "cuda":
+        raise ArgumentError(f"{name}: must be on a GPU, is on {t.device}")
+    if device is not None and t.device != device:
+        raise ArgumentError(f"{name}: on {t.device}, the other arguments are on {device}")
+    if t.dtype != dtype:
+        raise ArgumentError(f"{name}: dtype {t.dtype}, expected {dtype}")
+    if t.numel() != numel:
+        raise ArgumentError(f"{name}: {t.numel()} elements (shape {tuple(t.shape)}), expected {numel}")
+    if not t.is_contiguous():
+        raise ArgumentError(f"{name}: not contiguous (a strided view); pass .contiguous()")
+    if numel and align and t.data_ptr() % align:
+        raise ArgumentError(f"{name}: data is not {align}-byte aligned (an offset view?)")
+
+
+def validate_step(cfg, inputs, outputs, require_gpu=True):
+    """Check the tensors of one couple_step call against the configuration
+    (sizes, dtypes, devices, layout); raises ValueError."""
+    n = inputs.get("n")
+    if not isinstance(n, int) or n < 0:
+        raise ArgumentError(f"n: expected an int >= 0, got {n!r}")
+    if n > int(cfg.max_particles):
+        raise ArgumentError(f"n = {n} exceeds max_particles = {cfg.max_particles}", COUPLE_ECAPACITY)
+    ft, it = cfg.dtype, torch.int32
+    nb, nf = cfg.n_bulk, cfg.n_fine
+    dev = None
+    for k in ("pos", "fine_u"):
+        t = inputs.get(k)
+        if isinstance(t, torch.Tensor):
+            dev = t.device
+            break
+    kw = dict(device=dev, require_gpu=require_gpu)
+    has_n = n > 0
+    check_tensor("pos", inputs.get("pos"), ft, 3 * n, optional=not has_n, **kw)
+    check_tensor("vel", inputs.get("vel"), ft, 3 * n, optional=not has_n, **kw)
+    check_tensor("diam", inputs.get("diam"), ft, n, optional=not has_n, **kw)
+    for k in ("fine_u", "fine_v", "fine_w", "fine_p"):
+        check_tensor(k, inputs.get(k), ft, nf, **kw)
+    check_tensor("uf_given", inputs.get("uf_given"), ft, 3 * n,
+                 optional=not (has_n and cfg.vel_source == COUPLE_VEL_GIVEN), why="with vel_source GIVEN", **kw)
+    check_tensor("fine_alpha", inputs.get("fine_alpha"), ft, nf, optional=not cfg.vof, why="with vof = 1", **kw)
+    o = outputs
+    check_tensor("drag", o.get("drag"), ft, 3 * n, optional=not has_n, **kw)
+    check_tensor("beta", o.get("beta"), ft, n, optional=True, **kw)
+    check_tensor("cell", o.get("cell"), it, n, optional=not has_n, **kw)
+    check_tensor("perm", o.get("perm"), it, n, optional=not has_n, **kw)
+    check_tensor("count", o.get("count"), it, nb, **kw)
+    check_tensor("start", o.get("start"), it, nb + 1, **kw)
+    for k, m in (("bulk_phi", 1), ("bulk_F", 3), ("bulk_U", 3), ("bulk_P", 1), ("bulk_G", 3)):
+        check_tensor(k, o.get(k), ft, m * nb, **kw)
+    check_tensor("fine_eps", o.get("fine_eps"), ft, nf, **kw)
+    check_tensor("fine_F", o.get("fine_F"), ft, 3 * nf, **kw)
+    check_tensor("diag", o.get("diag"), torch.float64, DIAG_LEN, **kw)
+    check_tensor("uf", o.get("uf"), ft, 3 * n, optional=True, **kw)
+    semi = bool(cfg.semi_implicit)
+    ws = "with semi_implicit = 1"
+    check_tensor("bulk_K", o.get("bulk_K"), ft, nb, optional=not semi, why=ws, **kw)
+    check_tensor("bulk_KU", o.get("bulk_KU"), ft, 3 * nb, optional=not semi, why=ws, **kw)
+    check_tensor("fine_K", o.get("fine_K"), ft, nf, optional=not semi, why=ws, **kw)
+    check_tensor("fine_KU", o.get("fine_KU"), ft, 3 * nf, optional=not semi, why=ws, **kw)
+    check_tensor("bulk_alpha", o.get("bulk_alpha"), ft, nb, optional=not cfg.vof, why="with vof = 1", **kw)
+
+
 def couple_step(h, inputs: dict, outputs: dict, stream=None):
     """Enqueue one coupling step.  ``inputs``/``outputs`` map the field names of
-    ``couple_inputs``/``couple_outputs`` to device tensors (or None)."""
+    ``couple_inputs``/``couple_outputs`` to device tensors (or None).  Every
+    tensor is checked against the handle's configuration first (ValueError)."""
+    cfg = _HANDLE_CFG.get(getattr(h, "value", None))
+    if cfg is None:
+        raise ArgumentError("couple_step: not a live handle of couple_init")
+    validate_step(cfg, inputs, outputs)
     i = _Inputs()
     i.n = int(inputs["n"])
     i.step = int(inputs.get("step", 0))
@@ -364,8 +461,22 @@ def couple_mlp_features(cfg: Config, pos, diam, bulk_phi, bulk_U, bulk_G, feat, 
     """Raw surrogate features (and optionally bulk velocity and residual) of the
     particles ``sel`` (all when None) into device tensors."""
     c = cfg.to_c()
+    if not isinstance(pos, torch.Tensor) or pos.dim() != 2:
+        raise ArgumentError("pos: expected a [n, 3] tensor")
     n = pos.shape[0]
-    nsel = n if sel is None else sel.shape[0]
+    nsel = n if sel is None else sel.numel()
+    f32, nb = torch.float32, cfg.n_bulk
+    kw = dict(device=pos.device, align=4)   # element-wise accesses: any 4-byte offset will do
+    check_tensor("pos", pos, f32, 3 * n, **kw)
+    check_tensor("diam", diam, f32, n, **kw)
+    check_tensor("bulk_phi", bulk_phi, f32, nb, **kw)
+    check_tensor("bulk_U", bulk_U, f32, 3 * nb, **kw)
+    check_tensor("bulk_G", bulk_G, f32, 3 * nb, **kw)
+    check_tensor("feat", feat, f32, MLP_NFEAT * nsel, **kw)
+    check_tensor("u_fine", u_fine, f32, 3 * n, optional=resid is None, **kw)
+    check_tensor("sel", sel, torch.int32, nsel, optional=True, **kw)
+    check_tensor("u_bulk", u_bulk, f32, 3 * nsel, optional=True, **kw)
+    check_tensor("resid", resid, f32, 3 * nsel, optional=True, **kw)
     _mcheck(_lib.couple_mlp_features(C.byref(c), n, _ptr(pos), _ptr(diam), _ptr(bulk_phi), _ptr(bulk_U),
                                      _ptr(bulk_G), _ptr(u_fine), _ptr(sel), nsel, _ptr(feat), _ptr(u_bulk),
                                      _ptr(resid), _stream(stream)), None)
@@ -380,7 +491,8 @@ class Mlp:
 
     def set_params(self, params):
         a, p = _host(params, "float32")
-        assert a.size == MLP_NPARAM
+        if a.size != MLP_NPARAM:
+            raise ArgumentError(f"params: {a.size} values, expected {MLP_NPARAM}")
         _mcheck(_lib.couple_mlp_set_params(self.m, p), self.m)
 
     def set_norm(self, mean, std, scale):
@@ -389,7 +501,21 @@ class Mlp:
         c, pc = _host(scale, "float64")
         _mcheck(_lib.couple_mlp_set_norm(self.m, pa, pb, pc), self.m)
 
+    def _rows(self, feat, resid=None, limit=True):
+        if not isinstance(feat, torch.Tensor) or feat.dim() != 2:
+            raise ArgumentError("feat: expected a [rows, 193] tensor")
+        n = feat.shape[0]
+        if limit and n > self.max_batch:
+            raise ArgumentError(f"feat: {n} rows exceed max_batch = {self.max_batch}")
+        # rows are read element by element: any 4-byte offset (a slice of a pool) will do
+        check_tensor("feat", feat, torch.float32, MLP_NFEAT * n, align=4)
+        check_tensor("resid", resid, torch.float32, 3 * n, device=feat.device, optional=True, align=4)
+        return n
+
     def fit_norm(self, feat, resid, stream=None):
+        self._rows(feat, resid, limit=False)
+        if resid is None:
+            raise ArgumentError("resid: required")
         _mcheck(_lib.couple_mlp_fit_norm(self.m, _ptr(feat), _ptr(resid), feat.shape[0], _stream(stream)), self.m)
 
     def get_state(self):
@@ -412,16 +538,32 @@ class Mlp:
                                           arrs[4][1], arrs[5][1]), self.m)
 
     def forward(self, feat, y, stream=None):
+        n = self._rows(feat)
+        check_tensor("y", y, torch.float32, 3 * n, device=feat.device, align=4)
         _mcheck(_lib.couple_mlp_forward(self.m, _ptr(feat), feat.shape[0], _ptr(y), _stream(stream)), self.m)
 
+    def _batch(self, feat, resid, B, idx):
+        n = self._rows(feat, resid, limit=False)
+        if resid is None:
+            raise ArgumentError("resid: required")
+        if idx is None and int(B) > n:
+            raise ArgumentError(f"B = {B} exceeds the {n} rows")
+        check_tensor("idx", idx, torch.int32, int(B), device=feat.device, optional=True, align=4)
+
     def grads(self, feat, resid, B, grads, idx=None, loss=None, stream=None):
+        self._batch(feat, resid, B, idx)
+        check_tensor("grads", grads, torch.float32, MLP_NPARAM, device=feat.device)
+        check_tensor("loss", loss, torch.float32, 1, device=feat.device, optional=True)
         _mcheck(_lib.couple_mlp_grads(self.m, _ptr(feat), _ptr(resid), feat.shape[0], _ptr(idx), int(B),
                                       _ptr(grads), _ptr(loss), _stream(stream)), self.m)
 
     def adam(self, grads, stream=None):
+        check_tensor("grads", grads, torch.float32, MLP_NPARAM)
         _mcheck(_lib.couple_mlp_adam(self.m, _ptr(grads), _stream(stream)), self.m)
 
     def train_step(self, feat, resid, B, idx=None, loss=None, stream=None):
+        self._batch(feat, resid, B, idx)
+        check_tensor("loss", loss, torch.float32, 1, device=feat.device, optional=True)
         _mcheck(_lib.couple_mlp_train_step(self.m, _ptr(feat), _ptr(resid), feat.shape[0], _ptr(idx), int(B),
                                            _ptr(loss), _stream(stream)), self.m)
 
@@ -471,11 +613,15 @@ class Remap:
         """src: device tensor [..., nz, ny, nx] of the sender grid (leading dims =
         fields); returns dst [..., nz', ny', nx'] of the receiver grid."""
         nsrc = self.ns[0] * self.ns[1] * self.ns[2]
-        assert src.is_contiguous() and src.dtype == self.dtype and src.numel() % nsrc == 0
+        ndst = self.nd[0] * self.nd[1] * self.nd[2]
+        if not isinstance(src, torch.Tensor) or src.numel() == 0 or src.numel() % nsrc:
+            raise ArgumentError(f"src: expected a whole number (>= 1) of sender fields of {nsrc} cells")
         nf = src.numel() // nsrc
+        check_tensor("src", src, self.dtype, nf * nsrc)
         lead = tuple(src.shape[:-3]) if src.dim() > 3 else ()
         if dst is None:
             dst = torch.empty(lead + (self.nd[2], self.nd[1], self.nd[0]), dtype=self.dtype, device=src.device)
+        check_tensor("dst", dst, self.dtype, nf * ndst, device=src.device)
         _rcheck(_lib.couple_remap_apply(self.r, _ptr(src), _ptr(dst), nf, _stream(stream)), self.r)
         return dst
 

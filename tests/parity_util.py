@@ -148,6 +148,10 @@ def compare_step(g, o, n, nb, r, fp64, check_fine=True, fine_sample=None, label=
         "drag": (g["drag"].T, o["drag"].T, None, None),
         "beta": (g["beta"], o["beta"], None, None),
     }
+    if o.get("pos_new") is not None and g.get("pos_new") is not None:
+        # explicit Euler advection: the state after the step, per particle
+        fields["pos_new"] = (np.asarray(g["pos_new"]).reshape(-1, 3).T, o["pos_new"].T, None, None)
+        fields["vel_new"] = (np.asarray(g["vel_new"]).reshape(-1, 3).T, o["vel_new"].T, None, None)
     if check_fine:
         fidx = fine_sample if fine_sample_index is None else fine_sample_index
         Mf = fine_scale_from_bulk(neighbourhood_max(Mb, nb), nb, r, fidx)
@@ -181,6 +185,23 @@ def compare_step(g, o, n, nb, r, fp64, check_fine=True, fine_sample=None, label=
     if check_fine and fine_sample is None and "E_f" in od:
         assert rel(d["E_f"], od["E_f"], od["E_f"]) <= TOL_REDUCTION
     return errs
+
+
+def raw_step(cpl, h, inputs, outputs, stream=None):
+    """Call the C entry point directly, without the binding's argument checks
+    (to test the library's own checks); returns the status code."""
+    import ctypes as C
+    i = cpl._Inputs()
+    i.n = int(inputs["n"])
+    for k, _ in cpl._Inputs._fields_:
+        if k not in ("n", "step"):
+            t = inputs.get(k)
+            setattr(i, k, None if t is None else t.data_ptr())
+    o = cpl._Outputs()
+    for k, _ in cpl._Outputs._fields_:
+        t = outputs.get(k)
+        setattr(o, k, None if t is None else t.data_ptr())
+    return cpl._lib.couple_step(h, C.byref(i), C.byref(o), cpl._stream(stream))
 
 
 def results_dir():

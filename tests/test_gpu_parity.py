@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import workload as W
-from parity_util import cfg_for, compare_step, run_gpu
+from parity_util import cfg_for, compare_step, raw_step, run_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -170,15 +170,24 @@ def test_capacity_and_null_errors(env):
     dev = "cuda:0"
     pos = torch.rand(11, 3, device=dev)
     fine = [torch.zeros(8, 8, 8, device=dev) for _ in range(4)]
+    # the binding rejects them before the library sees them ...
     with pytest.raises(cpl.CoupleError) as e:
         c.step(pos, pos.clone(), torch.full((11,), 0.01, device=dev), fine)
     assert e.value.code == cpl.COUPLE_ECAPACITY
     out = cpl.alloc_outputs(cfg, 5, device=dev)
     out["fine_F"] = None
+    p5 = pos[:5].contiguous()
+    args = {"n": 5, "pos": p5, "vel": p5, "diam": torch.full((5,), 0.01, device=dev), "fine_u": fine[0],
+            "fine_v": fine[1], "fine_w": fine[2], "fine_p": fine[3]}
     with pytest.raises(cpl.CoupleError) as e:
-        cpl.couple_step(c.h, {"n": 5, "pos": pos, "vel": pos, "diam": pos, "fine_u": fine[0], "fine_v": fine[1],
-                              "fine_w": fine[2], "fine_p": fine[3]}, out)
-    assert e.value.code == cpl.COUPLE_EINVAL
+        cpl.couple_step(c.h, args, out)
+    assert e.value.code == cpl.COUPLE_EINVAL and isinstance(e.value, ValueError)
+    # ... and the library's own checks return the same codes, launching nothing
+    big = cpl.alloc_outputs(cfg, 11, device=dev)
+    assert raw_step(cpl, c.h, {**args, "n": 11, "pos": pos, "vel": pos,
+                               "diam": torch.full((11,), 0.01, device=dev)}, big) == cpl.COUPLE_ECAPACITY
+    assert raw_step(cpl, c.h, args, out) == cpl.COUPLE_EINVAL
+    assert "NULL grid output" in cpl.couple_last_error(c.h)
     c.close()
 
 
