@@ -20,6 +20,15 @@ TOL_MLP = 1e-3   # norm-wise relative error of network outputs and gradients
 # with several such flips, and catches a wrong or misplaced row (an error of
 # order one).
 TOL_ROW = 1e-2
+# In the step the network's inputs are gathered and standardised by the inference
+# kernel in FP32, while the reference features are standardised in FP64: an input
+# within one FP32 rounding of a BF16 rounding boundary then rounds to the other
+# BF16 neighbour on the two sides (one input in ~2^16), changing that input by one
+# BF16 step (2^-8 of a standardised value of at most a few units) and the row's
+# output by a few 1e-3 of the output scale.  The in-step rows are therefore held
+# to TOL_ROW relative to max(|y|, rms/2): a row whose network part is wrong or
+# misplaced, or off by 10 % of a typical row, still fails.
+ROW_FLOOR_INSTEP = 0.5
 
 
 @pytest.fixture(scope="module")
@@ -38,12 +47,13 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def _assert_rows(got, ref, label, tol=TOL_ROW):
-    """Per-row bound above, on [n, k] outputs; returns the worst row's error."""
+def _assert_rows(got, ref, label, tol=TOL_ROW, floor_frac=1e-2):
+    """Per-row bound above, on [n, k] outputs: |g - o| <= tol * max(|o|,
+    floor_frac * rms |o|); returns the worst row's error."""
     g = np.asarray(got, np.float64).reshape(len(ref), -1)
     o = np.asarray(ref, np.float64).reshape(len(ref), -1)
     rn = np.linalg.norm(o, axis=1)
-    floor = 1e-2 * np.sqrt(np.mean(rn ** 2)) if rn.size else 0.0
+    floor = floor_frac * np.sqrt(np.mean(rn ** 2)) if rn.size else 0.0
     err = np.linalg.norm(g - o, axis=1) / np.maximum(np.maximum(rn, floor), 1e-300)
     worst = float(err.max()) if err.size else 0.0
     assert worst <= tol, f"{label}: row {int(err.argmax())} error {worst:.3e} > {tol}"
@@ -283,7 +293,7 @@ def test_step_inference_matches_oracle(env):
     Xo = M.features(case["pos"], case["d"], 1.0 - o["phi"], o["U"], o["G"], w.grid.box, w.grid.nb)
     u_o = M.predict(params, Xo, mean, std, scale, o["uf"])
     e2 = _rel(g["uf"] - o["uf"], u_o - o["uf"])
-    r1 = _assert_rows(g["uf"] - ubg, Yg * scale, "in-step network part")
+    r1 = _assert_rows(g["uf"] - ubg, Yg * scale, "in-step network part", floor_frac=ROW_FLOOR_INSTEP)
     # against the whole oracle pipeline the BF16-rounded inputs themselves can
     # differ by a step (reported, bounded norm-wise)
     g2 = np.asarray(g["uf"] - o["uf"], np.float64)

@@ -306,10 +306,12 @@ def test_bed128_surrogate_full_size_sampled(env):
     Y, _ = M.forward(params, M.standardise(Xs, mean, std), emulate=True)
     g = om["uf"].cpu().numpy()[ids].astype(np.float64)
     e = float(np.linalg.norm(g - ubs - Y * scale) / np.linalg.norm(Y * scale))
-    # per particle as well (a wrong or misplaced row would hide in the norm)
+    # per particle as well (a wrong or misplaced row would hide in the norm): the
+    # in-step bound of tests/test_gpu_mlp.py, |d| <= 1e-2 max(|y|, rms/2) (its
+    # inputs are standardised in FP32 in the step, in FP64 here)
     part, ref = g - ubs, Y * scale
     rn = np.linalg.norm(ref, axis=1)
-    er = np.linalg.norm(part - ref, axis=1) / np.maximum(rn, 1e-2 * np.sqrt(np.mean(rn ** 2)))
+    er = np.linalg.norm(part - ref, axis=1) / np.maximum(rn, 0.5 * np.sqrt(np.mean(rn ** 2)))
     print(f"bed128 surrogate, network part on 20,000 samples: rel {e:.2e}, worst row {er.max():.2e}", flush=True)
     assert er.max() <= 1e-2, (int(er.argmax()), float(er.max()))
     h.close()
