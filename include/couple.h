@@ -197,8 +197,9 @@ int couple_step(couple_handle *h, const couple_inputs *in, couple_outputs *out, 
 /* Release the scratch and the handle.  NULL is accepted. */
 int couple_free(couple_handle *h);
 
-/* Text of the last error on this handle (or of the last couple_init failure when
- * h is NULL).  The pointer stays valid until the next call on the same handle. */
+/* Text of the last error on this handle (or, when h is NULL, of the calling
+ * thread's last couple_init or couple_step_noalloc failure).  The pointer stays
+ * valid until the next call on the same handle (or thread). */
 const char *couple_last_error(const couple_handle *h);
 
 /* ---- per-kernel timing (profiling aid, not part of the coupling method) -----
@@ -217,6 +218,29 @@ typedef struct couple_kernel_stat {
 
 int couple_timing_begin(couple_handle *h, int32_t max_steps);
 int couple_timing_end(couple_handle *h, couple_kernel_stat *stats, int32_t max_stats, int32_t *n_stats);
+
+/* ---- the step without allocation ----------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  couple_step_noalloc()
+ * runs the same kernels as couple_step() (same results, bit for bit) without a
+ * handle: it validates *cfg as couple_init() does and takes its scratch from a
+ * static device array of COUPLE_NOALLOC_SCRATCH_BYTES, one per device (each
+ * device that loads the library holds it until the process ends).  It calls no
+ * hipMalloc/hipFree and no allocating routine.
+ *   Capacity: the scratch a call needs grows with n and the bulk cell count
+ *   (about 48 bytes per particle plus 52 per bulk cell in FP32 with CIC); a call
+ *   that needs more than the array holds returns COUPLE_ECAPACITY before any
+ *   launch.  cfg->max_particles is not used (the capacity is the array).
+ *   Not supported: vel_source = COUPLE_VEL_MLP (the network lives in a handle);
+ *   COUPLE_EINVAL.
+ *   Concurrency: every call on a device uses that device's one array, which
+ *   keeps the last call's contents; calls that overlap on one device (other
+ *   streams or threads) race and give wrong results.  Calls in order on one
+ *   stream are safe.
+ * Errors as couple_step(); couple_last_error(NULL) describes the last failure of
+ * the calling thread. */
+#define COUPLE_NOALLOC_SCRATCH_BYTES (64ll << 20)
+int couple_step_noalloc(const couple_config *cfg, const couple_inputs *in, couple_outputs *out, void *stream);
 
 #ifdef __cplusplus
 }

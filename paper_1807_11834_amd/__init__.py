@@ -103,6 +103,8 @@ def _load():
     L.couple_free.restype = C.c_int
     L.couple_last_error.argtypes = [C.c_void_p]
     L.couple_last_error.restype = C.c_char_p
+    L.couple_step_noalloc.argtypes = [C.POINTER(_Config), C.POINTER(_Inputs), C.POINTER(_Outputs), C.c_void_p]
+    L.couple_step_noalloc.restype = C.c_int
     L.couple_timing_begin.argtypes = [C.c_void_p, C.c_int32]
     L.couple_timing_begin.restype = C.c_int
     L.couple_timing_end.argtypes = [C.c_void_p, C.POINTER(_KernelStat), C.c_int32, C.POINTER(C.c_int32)]
@@ -325,6 +327,28 @@ def couple_step(h, inputs: dict, outputs: dict, stream=None):
     for k, _ in _Outputs._fields_:
         setattr(o, k, _ptr(outputs.get(k)))
     _check(_lib.couple_step(h, C.byref(i), C.byref(o), _stream(stream)), h)
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20   # COUPLE_NOALLOC_SCRATCH_BYTES
+
+
+def couple_step_noalloc(cfg: Config, inputs: dict, outputs: dict, stream=None):
+    """The coupling step without a handle and without allocation (the library's
+    static scratch; see couple_step_noalloc in include/couple.h).  Tensors are
+    checked as for couple_step, with no particle capacity other than the
+    scratch's."""
+    chk = Config(**{**cfg.__dict__, "max_particles": max(int(inputs.get("n", 0)), int(cfg.max_particles))})
+    validate_step(chk, inputs, outputs)
+    c = cfg.to_c()
+    i = _Inputs()
+    i.n = int(inputs["n"])
+    i.step = int(inputs.get("step", 0))
+    for k in ("pos", "vel", "diam", "fine_u", "fine_v", "fine_w", "fine_p", "uf_given", "fine_alpha"):
+        setattr(i, k, _ptr(inputs.get(k)))
+    o = _Outputs()
+    for k, _ in _Outputs._fields_:
+        setattr(o, k, _ptr(outputs.get(k)))
+    _check(_lib.couple_step_noalloc(C.byref(c), C.byref(i), C.byref(o), _stream(stream)), None)
 
 
 def _stream(stream):

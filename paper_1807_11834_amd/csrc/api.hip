@@ -2,6 +2,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -29,11 +30,15 @@ struct couple_handle {
     std::vector<const char *> names;
 };
 
-static thread_local std::string g_init_err;
+// Text of the last error reported without a handle (couple_init, the no-alloc
+// step): a fixed per-thread buffer, so that reporting allocates nothing.
+static thread_local char g_err[512];
+
+static void set_global_err(const char *a, const char *b = "") { snprintf(g_err, sizeof(g_err), "%s%s", a, b); }
 
 static int fail(couple_handle *h, int code, const std::string &msg) {
     if (h) h->err = msg;
-    else g_init_err = msg;
+    else set_global_err(msg.c_str());
     return code;
 }
 
@@ -56,7 +61,9 @@ static void release(couple_handle *h) {
     h->part = nullptr;
 }
 
-static std::string validate(const couple_config *c) {
+// Configuration check shared by couple_init and couple_step_noalloc; returns
+// nullptr when valid, else a static message (allocates nothing).
+static const char *validate(const couple_config *c) {
     for (int a = 0; a < 3; ++a) {
         if (!(std::isfinite(c->box[a]) && c->box[a] > 0.0)) return "box lengths must be finite and > 0";
         if (c->nb[a] < 1) return "nb must be >= 1 on every axis";
@@ -93,7 +100,62 @@ static std::string validate(const couple_config *c) {
     if (c->advect && !(std::isfinite(c->dt) && c->dt >= 0.0)) return "dt must be finite and >= 0";
     if (c->max_particles < 0 || c->max_particles >= (int64_t(1) << 31) - 1)
         return "max_particles must be in [0, 2^31 - 1)";
-    return "";
+    return nullptr;
+}
+
+// The library scratch of a configuration for up to nmax particles: one buffer
+// per entry of Buf, sized here for both couple_init (separate allocations) and
+// couple_step_noalloc (carved from the static array).
+enum Buf { B_KEYS_A, B_KEYS_B, B_VALS_A, B_VALS_B, B_HIST, B_TOTALS, B_SP, B_UF4, B_PLO, B_DEP, B_PART, B_FGRID,
+           B_ALPHA8, B_COUNT };
+
+struct ScratchPlan {
+    size_t bytes[B_COUNT];
+    int64_t part_stride;
+};
+
+static ScratchPlan scratch_plan(const couple_config &c, int64_t nmax) {
+    ScratchPlan p{};
+    const int64_t ncell = (int64_t)c.nb[0] * c.nb[1] * c.nb[2];
+    const size_t fsz = (c.precision == COUPLE_FP64) ? sizeof(double) : sizeof(float);
+    const int64_t ntile = sort_tiles(nmax > 0 ? nmax : 1);
+    const int64_t pblk = (nmax + kBlock - 1) / kBlock, cblk = (ncell + kBlock - 1) / kBlock;
+    // one FP64 partial per workgroup and slot: the stride covers the largest
+    // grid of any kernel that writes partials
+    const int64_t dblk = deposit_blocks(c.nb, ncell, c.deposit == COUPLE_CIC);
+    const int64_t mblk = mlp_check_blocks(bricks_of(c.nb));
+    p.part_stride = 1;
+    for (int64_t b : {pblk, cblk, ntile, dblk, mblk})
+        if (b > p.part_stride) p.part_stride = b;
+    p.bytes[B_KEYS_A] = p.bytes[B_KEYS_B] = p.bytes[B_VALS_A] = p.bytes[B_VALS_B] = sizeof(uint32_t) * nmax;
+    p.bytes[B_HIST] = sizeof(uint32_t) * 256 * ntile;
+    p.bytes[B_TOTALS] = sizeof(uint32_t) * 256;
+    p.bytes[B_SP] = p.bytes[B_UF4] = 4 * fsz * nmax;
+    p.bytes[B_PLO] = fsz * ncell;
+    p.bytes[B_DEP] = (c.deposit == COUPLE_CIC ? (c.semi_implicit ? 16 : 12) : 1) * fsz * ncell;
+    p.bytes[B_PART] = sizeof(double) * (SL_COUNT * p.part_stride + SL_COUNT * 64);
+    p.bytes[B_FGRID] = c.vel_source == COUPLE_VEL_MLP ? sizeof(float4) * 2 * ncell : 0;
+    p.bytes[B_ALPHA8] = c.vof ? 8 * fsz * ncell : 0;
+    return p;
+}
+
+// Buffer pointers of a plan in the handle.
+static void **buf_slot(couple_handle *h, int b) {
+    switch (b) {
+    case B_KEYS_A: return (void **)&h->sort.keys_a;
+    case B_KEYS_B: return (void **)&h->sort.keys_b;
+    case B_VALS_A: return (void **)&h->sort.vals_a;
+    case B_VALS_B: return (void **)&h->sort.vals_b;
+    case B_HIST: return (void **)&h->sort.hist;
+    case B_TOTALS: return (void **)&h->sort.totals;
+    case B_SP: return &h->sp;
+    case B_UF4: return &h->uf4;
+    case B_PLO: return &h->plo;
+    case B_DEP: return &h->dep;
+    case B_PART: return (void **)&h->part;
+    case B_FGRID: return (void **)&h->fgrid;
+    default: return &h->alpha8;
+    }
 }
 
 template <typename X> static bool dev_alloc(X **p, size_t bytes) {
@@ -111,33 +173,20 @@ template <typename X> static bool dev_alloc(X **p, size_t bytes) {
 extern "C" int couple_init(const couple_config *cfg, couple_handle **out) {
     if (!cfg || !out) return fail(nullptr, COUPLE_EINVAL, "couple_init: NULL argument");
     *out = nullptr;
-    std::string v = validate(cfg);
-    if (!v.empty()) return fail(nullptr, COUPLE_EINVAL, "couple_init: " + v);
+    if (const char *v = validate(cfg)) {
+        set_global_err("couple_init: ", v);
+        return COUPLE_EINVAL;
+    }
     couple_handle *h = new (std::nothrow) couple_handle();
     if (!h) return fail(nullptr, COUPLE_ENOMEM, "couple_init: host allocation failed");
     h->cfg = *cfg;
     h->ncell = (int64_t)cfg->nb[0] * cfg->nb[1] * cfg->nb[2];
     h->nfine = h->ncell * cfg->ratio * cfg->ratio * cfg->ratio;
-    const int64_t nmax = cfg->max_particles;
-    const size_t fsz = (cfg->precision == COUPLE_FP64) ? sizeof(double) : sizeof(float);
-    const int64_t ntile = sort_tiles(nmax > 0 ? nmax : 1);
-    const int64_t pblk = (nmax + kBlock - 1) / kBlock, cblk = (h->ncell + kBlock - 1) / kBlock;
-    // one FP64 partial per workgroup and slot: the stride covers the largest
-    // grid of any kernel that writes partials
-    const int64_t dblk = deposit_blocks(cfg->nb, h->ncell, cfg->deposit == COUPLE_CIC);
-    h->part_stride = 1;
-    const int64_t mblk = mlp_check_blocks(bricks_of(cfg->nb));
-    for (int64_t b : {pblk, cblk, ntile, dblk, mblk})
-        if (b > h->part_stride) h->part_stride = b;
-    bool ok = dev_alloc(&h->sort.keys_a, sizeof(uint32_t) * nmax) && dev_alloc(&h->sort.keys_b, sizeof(uint32_t) * nmax) &&
-              dev_alloc(&h->sort.vals_a, sizeof(uint32_t) * nmax) && dev_alloc(&h->sort.vals_b, sizeof(uint32_t) * nmax) &&
-              dev_alloc(&h->sort.hist, sizeof(uint32_t) * 256 * ntile) && dev_alloc(&h->sort.totals, sizeof(uint32_t) * 256) &&
-              dev_alloc(&h->sp, 4 * fsz * nmax) && dev_alloc(&h->uf4, 4 * fsz * nmax) &&
-              dev_alloc(&h->plo, fsz * h->ncell) &&
-              dev_alloc(&h->dep, (cfg->deposit == COUPLE_CIC ? (cfg->semi_implicit ? 16 : 12) : 1) * fsz * h->ncell) &&
-              dev_alloc(&h->part, sizeof(double) * (SL_COUNT * h->part_stride + SL_COUNT * 64)) &&
-              (cfg->vel_source != COUPLE_VEL_MLP || dev_alloc(&h->fgrid, sizeof(float4) * 2 * h->ncell)) &&
-              (!cfg->vof || dev_alloc(&h->alpha8, 8 * fsz * h->ncell));
+    const ScratchPlan plan = scratch_plan(*cfg, cfg->max_particles);
+    h->part_stride = plan.part_stride;
+    bool ok = true;
+    for (int b = 0; b < B_COUNT && ok; ++b)
+        if (plan.bytes[b] > 0 || b < B_FGRID) ok = dev_alloc(buf_slot(h, b), plan.bytes[b]);
     if (!ok) {
         release(h);
         delete h;
@@ -155,7 +204,7 @@ extern "C" int couple_free(couple_handle *h) {
 }
 
 extern "C" const char *couple_last_error(const couple_handle *h) {
-    return h ? h->err.c_str() : g_init_err.c_str();
+    return h ? h->err.c_str() : g_err;
 }
 
 template <typename T> static Geo<T> make_geo(const couple_config &c) {
@@ -176,8 +225,13 @@ template <typename T> static Geo<T> make_geo(const couple_config &c) {
     return g;
 }
 
+// Enqueue the step's kernels with the scratch of `h` (a handle of couple_init, or
+// the stack-built view of the static scratch of couple_step_noalloc).  On a launch
+// failure returns COUPLE_EHIP with a static description in *what and the HIP
+// error in *herr; allocates nothing.
 template <typename T>
-static int step_impl(couple_handle *h, const couple_inputs *in, couple_outputs *out, hipStream_t st) {
+static int step_impl(couple_handle *h, const couple_inputs *in, couple_outputs *out, hipStream_t st,
+                     const char **what, hipError_t *herr) {
     const couple_config &c = h->cfg;
     StepArgs<T> a;
     a.g = make_geo<T>(c);
@@ -249,39 +303,147 @@ static int step_impl(couple_handle *h, const couple_inputs *in, couple_outputs *
     const uint32_t *skeys = nullptr;
     hipError_t e = launch_bin_sort<T>(a.pos, a.diam, a.n, a.g, out->cell, a.uf4, out->perm, out->start,
                                       out->count, h->sort, h->part + SL_NOUT * h->part_stride, &skeys, &h->mk, st);
-    if (e != hipSuccess) return fail(h, COUPLE_EHIP, std::string("couple_step: sort launch failed: ") + hipGetErrorString(e));
+    if (e != hipSuccess) {
+        *what = "sort launch failed: ";
+        *herr = e;
+        return COUPLE_EHIP;
+    }
     a.keys = skeys;
     e = launch_stages<T>(a, st);
-    if (e != hipSuccess) return fail(h, COUPLE_EHIP, std::string("couple_step: stage launch failed: ") + hipGetErrorString(e));
+    if (e != hipSuccess) {
+        *what = "stage launch failed: ";
+        *herr = e;
+        return COUPLE_EHIP;
+    }
     return COUPLE_OK;
+}
+
+// Argument checks of a step (no allocation); nullptr when the call is valid.
+static const char *check_step(const couple_config &c, const couple_inputs *in, const couple_outputs *out) {
+    if (in->n < 0) return "n < 0";
+    if (!in->fine_u || !in->fine_v || !in->fine_w || !in->fine_p) return "NULL fine-grid input";
+    if (!out->count || !out->start || !out->bulk_phi || !out->bulk_F || !out->bulk_U || !out->bulk_P ||
+        !out->bulk_G || !out->fine_eps || !out->fine_F || !out->diag)
+        return "NULL grid output";
+    if (c.semi_implicit && (!out->bulk_K || !out->bulk_KU || !out->fine_K || !out->fine_KU))
+        return "semi_implicit needs bulk_K, bulk_KU, fine_K and fine_KU";
+    if (c.vof && (!in->fine_alpha || !out->bulk_alpha)) return "vof needs fine_alpha and bulk_alpha";
+    if (in->n > 0) {
+        if (!in->pos || !in->vel || !in->diam) return "NULL particle input";
+        if (!out->drag || !out->cell || !out->perm) return "NULL particle output";
+        if (c.vel_source == COUPLE_VEL_GIVEN && !in->uf_given) return "vel_source GIVEN needs uf_given";
+    }
+    return nullptr;
 }
 
 extern "C" int couple_step(couple_handle *h, const couple_inputs *in, couple_outputs *out, void *stream) {
     if (!h) return fail(nullptr, COUPLE_EINVAL, "couple_step: NULL handle");
     if (!in || !out) return fail(h, COUPLE_EINVAL, "couple_step: NULL inputs or outputs");
     const couple_config &c = h->cfg;
-    if (in->n < 0) return fail(h, COUPLE_EINVAL, "couple_step: n < 0");
-    if (in->n > c.max_particles) return fail(h, COUPLE_ECAPACITY, "couple_step: n exceeds max_particles");
-    if (!in->fine_u || !in->fine_v || !in->fine_w || !in->fine_p)
-        return fail(h, COUPLE_EINVAL, "couple_step: NULL fine-grid input");
-    if (!out->count || !out->start || !out->bulk_phi || !out->bulk_F || !out->bulk_U || !out->bulk_P ||
-        !out->bulk_G || !out->fine_eps || !out->fine_F || !out->diag)
-        return fail(h, COUPLE_EINVAL, "couple_step: NULL grid output");
-    if (c.semi_implicit && (!out->bulk_K || !out->bulk_KU || !out->fine_K || !out->fine_KU))
-        return fail(h, COUPLE_EINVAL, "couple_step: semi_implicit needs bulk_K, bulk_KU, fine_K and fine_KU");
-    if (c.vof && (!in->fine_alpha || !out->bulk_alpha))
-        return fail(h, COUPLE_EINVAL, "couple_step: vof needs fine_alpha and bulk_alpha");
-    if (in->n > 0) {
-        if (!in->pos || !in->vel || !in->diam) return fail(h, COUPLE_EINVAL, "couple_step: NULL particle input");
-        if (!out->drag || !out->cell || !out->perm) return fail(h, COUPLE_EINVAL, "couple_step: NULL particle output");
-        if (c.vel_source == COUPLE_VEL_GIVEN && !in->uf_given)
-            return fail(h, COUPLE_EINVAL, "couple_step: vel_source GIVEN needs uf_given");
-    }
+    if (in->n > c.max_particles && in->n >= 0)
+        return fail(h, COUPLE_ECAPACITY, "couple_step: n exceeds max_particles");
+    if (const char *why = check_step(c, in, out)) return fail(h, COUPLE_EINVAL, std::string("couple_step: ") + why);
     if (c.vel_source == COUPLE_VEL_MLP && !h->mlp)
         return fail(h, COUPLE_ESTATE, "couple_step: vel_source MLP needs a network (couple_set_mlp)");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if (c.precision == COUPLE_FP64) return step_impl<double>(h, in, out, st);
-    return step_impl<float>(h, in, out, st);
+    const char *what = nullptr;
+    hipError_t herr = hipSuccess;
+    const int rc = c.precision == COUPLE_FP64 ? step_impl<double>(h, in, out, st, &what, &herr)
+                                              : step_impl<float>(h, in, out, st, &what, &herr);
+    if (rc != COUPLE_OK) return fail(h, rc, std::string("couple_step: ") + what + hipGetErrorString(herr));
+    return COUPLE_OK;
+}
+
+// ---- the step without allocation ---------------------------------------------
+// The scratch of couple_step_noalloc: one array per device (each device that
+// loads the library holds its own copy until the process ends).  Its device
+// address is taken once per device with hipGetSymbolAddress; in host code the
+// array's name is not a device address and is never passed to a kernel or copy.
+static __device__ __align__(256) unsigned char scratch[COUPLE_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static void *g_scratch_ptr[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+// Device address of this device's scratch array (nullptr on failure).
+static void *scratch_on_device(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
+extern "C" int couple_step_noalloc(const couple_config *cfg, const couple_inputs *in, couple_outputs *out,
+                                   void *stream) {
+    if (!cfg || !in || !out) {
+        set_global_err("couple_step_noalloc: NULL argument");
+        return COUPLE_EINVAL;
+    }
+    if (const char *v = validate(cfg)) {
+        set_global_err("couple_step_noalloc: ", v);
+        return COUPLE_EINVAL;
+    }
+    if (cfg->vel_source == COUPLE_VEL_MLP) {
+        set_global_err("couple_step_noalloc: vel_source MLP needs a network handle (use couple_step)");
+        return COUPLE_EINVAL;
+    }
+    if (const char *why = check_step(*cfg, in, out)) {
+        set_global_err("couple_step_noalloc: ", why);
+        return COUPLE_EINVAL;
+    }
+    // scratch for exactly these n particles, carved in 256-byte aligned pieces
+    const ScratchPlan plan = scratch_plan(*cfg, in->n);
+    size_t total = 0;
+    for (int b = 0; b < B_COUNT; ++b) total += (plan.bytes[b] + 255) / 256 * 256;
+    if (total > (size_t)COUPLE_NOALLOC_SCRATCH_BYTES) {
+        snprintf(g_err, sizeof(g_err),
+                 "couple_step_noalloc: this step needs %zu bytes of scratch, more than the %lld of the static "
+                 "array (fewer particles or bulk cells, or couple_init + couple_step)",
+                 total, (long long)COUPLE_NOALLOC_SCRATCH_BYTES);
+        return COUPLE_ECAPACITY;
+    }
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        set_global_err("couple_step_noalloc: hipGetDevice failed");
+        return COUPLE_EHIP;
+    }
+    unsigned char *base = static_cast<unsigned char *>(scratch_on_device(dev));
+    if (!base) {
+        set_global_err("couple_step_noalloc: hipGetSymbolAddress of the scratch array failed");
+        return COUPLE_EHIP;
+    }
+    // a stack view of a handle over the static scratch (no events, no network)
+    couple_handle h;
+    h.cfg = *cfg;
+    h.cfg.max_particles = in->n;
+    h.ncell = (int64_t)cfg->nb[0] * cfg->nb[1] * cfg->nb[2];
+    h.nfine = h.ncell * cfg->ratio * cfg->ratio * cfg->ratio;
+    h.part_stride = plan.part_stride;
+    size_t off = 0;
+    for (int b = 0; b < B_COUNT; ++b) {
+        *buf_slot(&h, b) = plan.bytes[b] ? base + off : nullptr;
+        off += (plan.bytes[b] + 255) / 256 * 256;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const char *what = nullptr;
+    hipError_t herr = hipSuccess;
+    const int rc = cfg->precision == COUPLE_FP64 ? step_impl<double>(&h, in, out, st, &what, &herr)
+                                                 : step_impl<float>(&h, in, out, st, &what, &herr);
+    // the view owns nothing: release() must not free the static array
+    for (int b = 0; b < B_COUNT; ++b) *buf_slot(&h, b) = nullptr;
+    if (rc != COUPLE_OK) {
+        snprintf(g_err, sizeof(g_err), "couple_step_noalloc: %s%s", what, hipGetErrorString(herr));
+        return rc;
+    }
+    return COUPLE_OK;
 }
 
 extern "C" int couple_timing_begin(couple_handle *h, int32_t max_steps) {

@@ -22,6 +22,7 @@ def declared_functions():
 def test_header_declares_the_entry_points():
     assert declared_functions() == sorted([
         "couple_free", "couple_init", "couple_last_error", "couple_step", "couple_timing_begin", "couple_timing_end",
+        "couple_step_noalloc",
         "couple_mlp_init", "couple_mlp_free", "couple_mlp_last_error", "couple_mlp_set_params",
         "couple_mlp_set_norm", "couple_mlp_fit_norm", "couple_mlp_get_state", "couple_mlp_set_state",
         "couple_mlp_forward", "couple_mlp_grads", "couple_mlp_adam", "couple_mlp_train_step",
@@ -56,6 +57,7 @@ int main(void) {
          offsetof(couple_outputs, fine_KU), offsetof(couple_outputs, bulk_alpha));
   printf("%zu %zu %zu\\n", sizeof(couple_mlp_config), offsetof(couple_mlp_config, lr), offsetof(couple_mlp_config, eps));
   printf("%d %d %d %d\\n", COUPLE_DIAG_LEN, COUPLE_VEL_MLP, COUPLE_MLP_NFEAT, COUPLE_MLP_NPARAM);
+  printf("%lld\\n", (long long)COUPLE_NOALLOC_SCRATCH_BYTES);
   return 0; }
 """)
     exe = tmp_path / "layout"
@@ -75,6 +77,18 @@ int main(void) {
     assert d == [C.sizeof(cpl._MlpConfig), cpl._MlpConfig.lr.offset, cpl._MlpConfig.eps.offset]
     e = [int(x) for x in lines[4].split()]
     assert e == [cpl.DIAG_LEN, cpl.COUPLE_VEL_MLP, cpl.MLP_NFEAT, cpl.MLP_NPARAM]
+    assert int(lines[5]) == cpl.NOALLOC_SCRATCH_BYTES
+
+
+def test_noalloc_rejects_invalid_config_without_a_gpu():
+    """The no-alloc step validates its configuration before touching the device."""
+    import ctypes as C
+    import paper_1807_11834_amd as cpl
+    c = cpl.Config(ratio=3).to_c()
+    i, o = cpl._Inputs(), cpl._Outputs()
+    assert cpl._lib.couple_step_noalloc(C.byref(c), C.byref(i), C.byref(o), None) == cpl.COUPLE_EINVAL
+    assert "couple_step_noalloc: ratio" in cpl.couple_last_error(None)
+    assert cpl._lib.couple_step_noalloc(None, C.byref(i), C.byref(o), None) == cpl.COUPLE_EINVAL
 
 
 BAD = [
