@@ -75,6 +75,8 @@ def lib():
         L.orc_advect.argtypes = [I64, P, P, P, P, D, D, P, I]
         L.orc_particle_volumes.argtypes = [I64, P, P]
         L.orc_remap.argtypes = [P, P, P, P, P, P]
+        L.orc_box_remap.argtypes = [I64, P, I64, P, P, P]
+        L.orc_box_remap.restype = None
         L.orc_set_threads.argtypes = [I]
         L.orc_set_threads.restype = None
         L.orc_get_threads.argtypes = []
@@ -258,6 +260,19 @@ def remap(src, src_nodes, dst_nodes):
     out = np.empty(int(np.prod(nd)), dtype=np.float64)
     lib().orc_remap(_p(ns), _p(sn), _p(nd), _p(dn), _p(src), _p(out))
     return out.reshape(nd[2], nd[1], nd[0])
+
+
+def box_remap(src, sender_boxes, receiver_boxes):
+    """Volume-weighted transfer between two grids of axis-aligned cells (each
+    grid an [n, 6] array of boxes x0, x1, y0, y1, z0, z1): receiver value =
+    sum over overlapping sender cells of |overlap| * value / |receiver cell|."""
+    sb = _f64(sender_boxes).reshape(-1, 6)
+    rb = _f64(receiver_boxes).reshape(-1, 6)
+    src = _f64(src).reshape(-1)
+    assert src.shape[0] == sb.shape[0]
+    out = np.empty(rb.shape[0], dtype=np.float64)
+    lib().orc_box_remap(sb.shape[0], _p(sb), rb.shape[0], _p(rb), _p(src), _p(out))
+    return out
 
 
 def particle_volumes(diam):

@@ -626,6 +626,38 @@ void orc_remap(const int ns[3], const double *src_nodes, const int nd[3], const 
             }
 }
 
+/* ------------------------------------------------------------------------- */
+/* Grid-to-grid transfer between two grids made of arbitrary axis-aligned    */
+/* cells (boxes), e.g. locally refined grids that are not nested in each      */
+/* other (Sec. 2.1: the fine grid may be non-uniform and locally refined;    */
+/* Sec. 2.3: a static sender -> receiver map).  Cell c of a grid is the box   */
+/* [b[6c], b[6c+1]] x [b[6c+2], b[6c+3]] x [b[6c+4], b[6c+5]].  The receiver */
+/* value is the volume-weighted average of the sender cells it overlaps,     */
+/*   dst_r = (sum_s |r intersect s| src_s) / |r|,                            */
+/* computed here by brute force over every (receiver, sender) pair.          */
+/* ------------------------------------------------------------------------- */
+void orc_box_remap(int64_t ns, const double *sbox, int64_t nr, const double *rbox, const double *src,
+                   double *dst)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < nr; ++r) {
+        const double *R = rbox + 6 * r;
+        double acc = 0.0;
+        for (int64_t c = 0; c < ns; ++c) {
+            const double *S = sbox + 6 * c;
+            double ox = overlap1(R[0], R[1], S[0], S[1]);
+            if (ox == 0.0) continue;
+            double oy = overlap1(R[2], R[3], S[2], S[3]);
+            if (oy == 0.0) continue;
+            double oz = overlap1(R[4], R[5], S[4], S[5]);
+            if (oz == 0.0) continue;
+            acc += ox * oy * oz * src[c];
+        }
+        double vol = (R[1] - R[0]) * (R[3] - R[2]) * (R[5] - R[4]);
+        dst[r] = acc / vol;
+    }
+}
+
 /* Particle volumes V_p = pi d^3 / 6 (for the conservation diagnostics). */
 void orc_particle_volumes(int64_t n, const double *diam, double *vp)
 {

@@ -345,3 +345,68 @@ def small_workload(nb=(4, 3, 5), ratio=4, box=(1.0, 0.75, 1.25), n=200, seed=7,
     return Workload(name=f"small_{nb[0]}x{nb[1]}x{nb[2]}_r{ratio}_n{n}", grid=Grid(tuple(box), tuple(nb), ratio),
                     n_particles=n, precision=precision, deposit=deposit, seed=seed,
                     particles="uniform", fluid=fluid, advect=advect, dt=dt)
+
+
+# ---------------------------------------------------------------------------
+# Grids made of axis-aligned cells (boxes): uniform and locally refined
+# ---------------------------------------------------------------------------
+
+def box_grid(box, n):
+    """Cells of a uniform grid of n = (nx, ny, nz) cells over box, as an [N, 6]
+    array of boxes (x0, x1, y0, y1, z0, z1) in raster order (x fastest)."""
+    e = [np.linspace(0.0, box[a], n[a] + 1) for a in range(3)]
+    z0, y0, x0 = np.meshgrid(e[2][:-1], e[1][:-1], e[0][:-1], indexing="ij")
+    z1, y1, x1 = np.meshgrid(e[2][1:], e[1][1:], e[0][1:], indexing="ij")
+    return np.stack([x0.ravel(), x1.ravel(), y0.ravel(), y1.ravel(), z0.ravel(), z1.ravel()], axis=1)
+
+
+def refined_box_grid(box, n, region, split=2):
+    """A locally refined grid: the uniform base grid of n cells over box, with
+    every base cell whose centre lies inside region = (x0, x1, y0, y1, z0, z1)
+    split into split^3 children.  Cells are listed in the base raster order, a
+    split cell replaced in place by its children (raster order within it), so
+    that neighbouring cells stay close in memory.  Returns [N, 6] boxes."""
+    base = box_grid(box, n)
+    cx, cy, cz = (base[:, 0] + base[:, 1]) / 2, (base[:, 2] + base[:, 3]) / 2, (base[:, 4] + base[:, 5]) / 2
+    inside = ((cx > region[0]) & (cx < region[1]) & (cy > region[2]) & (cy < region[3]) &
+              (cz > region[4]) & (cz < region[5]))
+    t = (np.arange(split + 1, dtype=np.float64) / split)
+    out = []
+    for b, ref in zip(base, inside):
+        if not ref:
+            out.append(b[None, :])
+            continue
+        ex = b[0] + (b[1] - b[0]) * t
+        ey = b[2] + (b[3] - b[2]) * t
+        ez = b[4] + (b[5] - b[4]) * t
+        k, j, i = np.meshgrid(np.arange(split), np.arange(split), np.arange(split), indexing="ij")
+        k, j, i = k.ravel(), j.ravel(), i.ravel()
+        out.append(np.stack([ex[i], ex[i + 1], ey[j], ey[j + 1], ez[k], ez[k + 1]], axis=1))
+    return np.concatenate(out, axis=0)
+
+
+def refined_box_grid_fast(box, n, region, split=2):
+    """refined_box_grid for large grids (vectorised; the same cells in the same
+    order)."""
+    base = box_grid(box, n)
+    c = np.stack([(base[:, 0] + base[:, 1]) / 2, (base[:, 2] + base[:, 3]) / 2, (base[:, 4] + base[:, 5]) / 2], 1)
+    inside = ((c[:, 0] > region[0]) & (c[:, 0] < region[1]) & (c[:, 1] > region[2]) & (c[:, 1] < region[3]) &
+              (c[:, 2] > region[4]) & (c[:, 2] < region[5]))
+    s3 = split ** 3
+    counts = np.where(inside, s3, 1)
+    first = np.concatenate([[0], np.cumsum(counts)[:-1]])
+    out = np.empty((int(counts.sum()), 6), dtype=np.float64)
+    out[first[~inside]] = base[~inside]
+    rb = base[inside]
+    k, j, i = np.meshgrid(np.arange(split), np.arange(split), np.arange(split), indexing="ij")
+    k, j, i = k.ravel(), j.ravel(), i.ravel()
+    for q in range(s3):
+        lo = np.stack([i[q], j[q], k[q]]) / split
+        hi = (np.stack([i[q], j[q], k[q]]) + 1) / split
+        child = np.empty_like(rb)
+        for a in range(3):
+            w = rb[:, 2 * a + 1] - rb[:, 2 * a]
+            child[:, 2 * a] = rb[:, 2 * a] + w * lo[a]
+            child[:, 2 * a + 1] = rb[:, 2 * a] + w * hi[a]
+        out[first[inside] + q] = child
+    return out
