@@ -133,6 +133,14 @@ def _load():
         f = getattr(L, name)
         f.argtypes = args
         f.restype = I
+    for name, args in {"couple_boxmap_init": [I64, P, I64, P, C.c_int32, C.POINTER(C.c_void_p)],
+                       "couple_boxmap_apply": [P, P, P, C.c_int32, P],
+                       "couple_boxmap_info": [P, P, P], "couple_boxmap_free": [P]}.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = I
+    L.couple_boxmap_last_error.argtypes = [P]
+    L.couple_boxmap_last_error.restype = C.c_char_p
     L.couple_remap_last_error.argtypes = [P]
     L.couple_remap_last_error.restype = C.c_char_p
     L.couple_mlp_last_error.argtypes = [P]
@@ -659,6 +667,63 @@ class Remap:
         if getattr(self, "r", None) is not None:
             _lib.couple_remap_free(self.r)
             self.r = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---- transfer between grids of arbitrary axis-aligned cells (include/couple_boxmap.h) ----
+
+class BoxMap:
+    """Volume-weighted transfer from a sender grid to a receiver grid, each an
+    [n, 6] array of axis-aligned cells (x0, x1, y0, y1, z0, z1), through a CSR
+    overlap map built once (host, FP64) and applied on the device."""
+
+    def __init__(self, sender_boxes, receiver_boxes, precision=COUPLE_FP32_KAHAN):
+        import numpy as np
+        sb, psb = _host(np.asarray(sender_boxes, np.float64).reshape(-1, 6), "float64")
+        rb, prb = _host(np.asarray(receiver_boxes, np.float64).reshape(-1, 6), "float64")
+        self.ns, self.nr = sb.shape[0], rb.shape[0]
+        self.precision = int(precision)
+        m = C.c_void_p()
+        code = _lib.couple_boxmap_init(self.ns, psb, self.nr, prb, self.precision, C.byref(m))
+        if code != COUPLE_OK:
+            s = _lib.couple_boxmap_last_error(None)
+            raise CoupleError(code, s.decode() if s else "")
+        self.m = m
+
+    @property
+    def dtype(self):
+        return torch.float64 if self.precision == COUPLE_FP64 else torch.float32
+
+    def apply(self, src, dst=None, stream=None):
+        """src: device tensor [nfields, ns] (or [ns]); returns dst [nfields, nr]
+        (or [nr])."""
+        if not isinstance(src, torch.Tensor) or src.numel() == 0 or src.numel() % self.ns:
+            raise ArgumentError(f"src: expected a whole number (>= 1) of sender fields of {self.ns} cells")
+        nf = src.numel() // self.ns
+        check_tensor("src", src, self.dtype, nf * self.ns)
+        if dst is None:
+            dst = torch.empty((nf, self.nr) if src.dim() > 1 else (self.nr,), dtype=self.dtype, device=src.device)
+        check_tensor("dst", dst, self.dtype, nf * self.nr, device=src.device)
+        code = _lib.couple_boxmap_apply(self.m, _ptr(src), _ptr(dst), nf, _stream(stream))
+        if code != COUPLE_OK:
+            s = _lib.couple_boxmap_last_error(self.m)
+            raise CoupleError(code, s.decode() if s else "")
+        return dst
+
+    def info(self):
+        nnz, mr = C.c_int64(0), C.c_int64(0)
+        _lib.couple_boxmap_info(self.m, C.byref(nnz), C.byref(mr))
+        return int(nnz.value), int(mr.value)
+
+    def close(self):
+        if getattr(self, "m", None) is not None:
+            _lib.couple_boxmap_free(self.m)
+            self.m = None
 
     def __del__(self):
         try:

@@ -9,7 +9,8 @@ import subprocess
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADERS = [os.path.join(ROOT, "include", h) for h in ("couple.h", "couple_mlp.h", "couple_remap.h")]
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("couple.h", "couple_mlp.h", "couple_remap.h",
+                                                       "couple_boxmap.h")]
 LIB = os.path.join(ROOT, "paper_1807_11834_amd", "libcouple.so")
 
 
@@ -27,7 +28,9 @@ def test_header_declares_the_entry_points():
         "couple_mlp_set_norm", "couple_mlp_fit_norm", "couple_mlp_get_state", "couple_mlp_set_state",
         "couple_mlp_forward", "couple_mlp_grads", "couple_mlp_adam", "couple_mlp_train_step",
         "couple_mlp_features", "couple_set_mlp",
-        "couple_remap_init", "couple_remap_apply", "couple_remap_info", "couple_remap_free", "couple_remap_last_error"])
+        "couple_remap_init", "couple_remap_apply", "couple_remap_info", "couple_remap_free", "couple_remap_last_error",
+        "couple_boxmap_init", "couple_boxmap_apply", "couple_boxmap_info", "couple_boxmap_free",
+        "couple_boxmap_last_error"])
 
 
 def test_library_exports_every_declared_symbol():
@@ -175,3 +178,35 @@ def test_remap_null_handles():
     assert L.couple_remap_free(None) == cpl.COUPLE_OK
     assert L.couple_remap_apply(None, None, None, 1, None) == cpl.COUPLE_EINVAL
     assert L.couple_remap_info(None, None, None) == cpl.COUPLE_EINVAL
+
+
+@pytest.mark.parametrize("case", ["ns0", "nan", "inverted", "precision", "null"])
+def test_boxmap_init_rejects_invalid_grids(case):
+    import numpy as np
+    import paper_1807_11834_amd as cpl
+    good = np.array([[0.0, 1.0, 0.0, 1.0, 0.0, 1.0]])
+    s, r, prec = good.copy(), good.copy(), cpl.COUPLE_FP32_KAHAN
+    if case == "ns0":
+        s = np.zeros((0, 6))
+    elif case == "nan":
+        r[0, 3] = float("nan")
+    elif case == "inverted":
+        s[0, 4], s[0, 5] = 1.0, 0.5
+    elif case == "precision":
+        prec = 7
+    if case == "null":
+        import ctypes as C
+        h = C.c_void_p()
+        assert cpl._lib.couple_boxmap_init(1, None, 1, None, 1, C.byref(h)) == cpl.COUPLE_EINVAL
+        return
+    with pytest.raises(cpl.CoupleError) as ei:
+        cpl.BoxMap(s, r, precision=prec)
+    assert ei.value.code == cpl.COUPLE_EINVAL
+    assert "couple_boxmap_init" in str(ei.value)
+
+
+def test_boxmap_null_handles():
+    import paper_1807_11834_amd as cpl
+    L = cpl._lib
+    assert L.couple_boxmap_free(None) == cpl.COUPLE_OK
+    assert L.couple_boxmap_apply(None, None, None, 1, None) == cpl.COUPLE_EINVAL
