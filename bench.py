@@ -31,20 +31,25 @@ METRIC = "coupling particle-steps/s, plain vs MLP path at 1e-3 rel err; % HBM pe
 def kernel_alg_bytes(name, n, ncell, nfine, fsz):
     """Algorithmic (compulsory) bytes of one launch of the named kernel.
 
-    restrict_lookup: fine u, v, w, p read once (4 fsz per fine cell); U, P
-        written (4 fsz per bulk cell); per particle the sorted position and
-        diameter read (4 fsz) and the sampled fluid velocity and void fraction
-        written (4 fsz).
-    restrict: the same without the particles.
-    prolong: eps and F_fpi written on the fine grid (4 fsz per fine cell); phi
-        and F_fpi read on the bulk grid (4 fsz per bulk cell).
-    prolong_semi: the same for K and KU (semi-implicit split).
+    restrict_lookup: fine u, v, w read once (3 fsz per fine cell); U written
+        (3 fsz per bulk cell); per particle the sorted position and diameter
+        read (4 fsz) and the sampled fluid velocity and void fraction written
+        (4 fsz).
+    restrict: u, v, w, p read, U, P written (the other velocity sources).
+    restrict_p: the pressure alone (beside the fused kernel).
+    prolong: F_fpi written on the fine grid (3 fsz per fine cell) and read on
+        the bulk grid (3 fsz per bulk cell); prolong_eps: the porosity
+        (1 + 1); prolong_semi: K and KU (4 + 4).
     """
     if name == "restrict_lookup":
-        return 4 * fsz * nfine + 4 * fsz * ncell + n * 8 * fsz
+        return 3 * fsz * nfine + 3 * fsz * ncell + n * 8 * fsz
     if name == "restrict":
         return 4 * fsz * nfine + 4 * fsz * ncell
-    if name in ("prolong", "prolong_semi"):
+    if name in ("restrict_p", "prolong_eps"):
+        return fsz * nfine + fsz * ncell
+    if name == "prolong":
+        return 3 * fsz * nfine + 3 * fsz * ncell
+    if name == "prolong_semi":
         return 4 * fsz * nfine + 4 * fsz * ncell
     return None
 
@@ -496,6 +501,69 @@ def vof_leg(args, w, cfg, pos, vel, diam, fine, plain_ms, n, g, fsz, dev):
             "restrict_alpha_frac_hbm": round(ab / (ra * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4) if ra else None}
 
 
+def precision_leg(args, cfg, pos, vel, diam, fine, plain_ms, n, dev):
+    """The same step in the other FP32 precision modes: Kahan-compensated FP32
+    per-cell sums and plain FP32 sums (the headline runs FP64-register per-cell
+    sums); time per step and the time of the restriction, deposition and
+    transfer kernels whose sums the mode changes."""
+    import paper_1807_11834_amd as cpl
+    res = {}
+    keys = ("restrict_p", "restrict_lookup", "deposit_phi", "deposit_phi_sum", "deposit_force", "deposit_force_sum")
+    for name, prec in (("fp32_kahan", cpl.COUPLE_FP32_KAHAN), ("fp32_naive", cpl.COUPLE_FP32_NAIVE)):
+        ms, kt, _ = _time_variant(args, dataclasses.replace(cfg, precision=prec), pos, vel, diam, fine, n, dev)
+        res[name] = {"ms_per_step": ms, "value": n / (ms * 1e-3), "vs_fp64_register_sums": ms / plain_ms,
+                     "kernels_avg_ms": {k: round(v, 4) for k, v in kt.items() if k in keys}}
+        print(f"# precision {name}: {ms:.3f} ms/step", file=sys.stderr, flush=True)
+    return res
+
+
+def part_leg(args, cfg, pos, vel, diam, fine, plain_ms, n, dev):
+    """The partitioned step (co-located z-slabs with one-layer halos, Sec. 2.2)
+    on this workload for K = 2, 4, 8 slabs and both exchange strategies
+    (distributed and gather-scatter, Sec. 2.3): time per step against the
+    monolithic step, the static communication matrix's bytes per step, and the
+    agreement with the monolithic step at full size (cell, perm, count bit for
+    bit; the largest deviation of phi and of the prolonged source relative to
+    their largest magnitude)."""
+    import torch
+    import paper_1807_11834_amd as cpl
+    ref = cpl.alloc_outputs(cfg, n, device=dev)
+    c = cpl.Coupler(cfg)
+    try:
+        c.step(pos, vel, diam, fine, out=ref)
+    finally:
+        c.close()
+    out = cpl.alloc_outputs(cfg, n, device=dev)
+    stream = torch.cuda.current_stream()
+    res = {}
+    for K in (2, 4, 8):
+        p = cpl.Part(cfg, K)
+        try:
+            comm = p.comm_matrix()
+            for name, ex in (("distributed", cpl.COUPLE_EXCHANGE_DISTRIBUTED),
+                             ("gather_scatter", cpl.COUPLE_EXCHANGE_GATHER_SCATTER)):
+                for _ in range(max(args.warmup, 1)):
+                    p.step(pos, vel, diam, fine, out=out, exchange=ex)
+                k = min(args.steps, 20)
+                total, per = timed_steps(lambda i: p.step(pos, vel, diam, fine, out=out, exchange=ex), k, stream)
+                ms = total / k
+                same = {key: bool(torch.equal(out[key], ref[key])) for key in ("cell", "perm", "count", "start")}
+                dev_phi = float((out["bulk_phi"] - ref["bulk_phi"]).abs().max() / ref["bulk_phi"].abs().max())
+                dev_ff = float((out["fine_F"] - ref["fine_F"]).abs().max() / ref["fine_F"].abs().max())
+                res[f"K{K}_{name}"] = {"ms_per_step": ms, "value": n / (ms * 1e-3), "per_step": step_stats(per),
+                                       "overhead_vs_monolithic": ms / plain_ms - 1.0,
+                                       "integers_equal_monolithic": same,
+                                       "max_dev_phi": dev_phi, "max_dev_fine_F": dev_ff}
+                print(f"# partitioned K={K} {name}: {ms:.3f} ms/step", file=sys.stderr, flush=True)
+            res[f"K{K}_comm_bytes_per_step"] = int(comm.sum())
+            res[f"K{K}_comm_nonzero_blocks"] = int((comm > 0).sum())
+        finally:
+            p.close()
+    del out, ref
+    torch.cuda.empty_cache()
+    return res
+
+
 def remap_leg(args, g, fine, fsz, dev):
     """Grid-to-grid transfer between non-nested grids at the bed's size: the four
     fine fields (u, v, w, p; 512 x 512 x 1024 over 1 x 1 x 2) to a 192 x 192 x 384
@@ -508,7 +576,7 @@ def remap_leg(args, g, fine, fsz, dev):
     box = g.box
     nc = (192, 192, 384)
     nodes = lambda n: [np.linspace(0.0, box[a], n[a] + 1) for a in range(3)]
-    prec = cpl.COUPLE_FP64 if fsz == 8 else cpl.COUPLE_FP32_KAHAN
+    prec = cpl.COUPLE_FP64 if fsz == 8 else cpl.COUPLE_FP32_WIDE
     down, up = cpl.Remap(nodes(g.nf), nodes(nc), prec), cpl.Remap(nodes(nc), nodes(g.nf), prec)
     try:
         src = torch.stack(fine)
@@ -559,6 +627,8 @@ def main():
     ap.add_argument("--no-vof", action="store_true", help="skip the two-fluid drag variant")
     ap.add_argument("--no-remap", action="store_true", help="skip the non-nested grid transfer")
     ap.add_argument("--no-advected", action="store_true", help="skip the 100-step advected 64^3 cube")
+    ap.add_argument("--no-part", action="store_true", help="skip the partitioned (z-slab) step")
+    ap.add_argument("--no-precision", action="store_true", help="skip the Kahan and naive FP32 variants")
     ap.add_argument("--traffic-summary", metavar="DIR",
                     help="print the JSON summary of the FETCH_SIZE/WRITE_SIZE runs under DIR and exit")
     ap.add_argument("--trace-summary", metavar="CSV",
@@ -611,7 +681,7 @@ def main():
     del pos_np, vel_np, d_np
     cfg = cpl.Config(box=g.box, nb=g.nb, ratio=g.ratio, rho_f=w.rho_f, mu_f=w.mu_f, rho_p=w.rho_p,
                      eps_min=w.eps_min, deposit=cpl.COUPLE_CIC if w.deposit == "cic" else cpl.COUPLE_NGP,
-                     precision=cpl.COUPLE_FP64 if fp64 else cpl.COUPLE_FP32_KAHAN,
+                     precision=cpl.COUPLE_FP64 if fp64 else cpl.COUPLE_FP32_WIDE,
                      vel_source=cpl.COUPLE_VEL_FINE if args.vel_source == "fine" else cpl.COUPLE_VEL_BULK,
                      advect=0, max_particles=n)
     c = cpl.Coupler(cfg)
@@ -656,7 +726,7 @@ def main():
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64" if fp64 else "f32", "data": "synthetic",
         "config": {"workload": (f"{w.name}: {n} particles, box {g.box}, bulk {g.nb}, fine {g.nf}, "
-                                f"{w.deposit.upper()}, {'FP64' if fp64 else 'FP32 + Kahan, FP64 sums'}, "
+                                f"{w.deposit.upper()}, {'FP64' if fp64 else 'FP32 data, FP64-register per-cell sums, FP64 global sums'}, "
                                 f"{args.vel_source}-grid velocity at the particles"),
                    "n_particles": n, "bulk": list(g.nb), "fine": list(g.nf)},
         "per_step": step_stats(per),
@@ -682,6 +752,10 @@ def main():
         del pos_s, vel_s, diam_s
     if not args.no_advected:
         rec["advected_cube64"] = advected_leg(args, dev)
+    if not args.no_precision and not fp64:
+        rec["precision_modes"] = precision_leg(args, cfg, pos, vel, diam, fine, ms_step, n, dev)
+    if not args.no_part:
+        rec["partitioned"] = part_leg(args, cfg, pos, vel, diam, fine, ms_step, n, dev)
     if not args.no_semi:
         rec["semi_implicit"] = semi_leg(args, cfg, pos, vel, diam, fine, ms_step, n, g, fsz, dev)
     if not args.no_vof:

@@ -84,12 +84,17 @@ typedef enum {
 } couple_status;
 
 enum { COUPLE_NGP = 0, COUPLE_CIC = 1 };                  /* deposition weights            */
-/* Precision.  COUPLE_FP64: FP64 data and sums.  COUPLE_FP32_KAHAN: FP32 data with
- * error-compensated sums (the restriction and the deposition's first pass sum
- * the FP32 terms in FP64 registers, other per-cell sums are Kahan-compensated
- * in FP32; the pressure keeps a low word for its gradient).  COUPLE_FP32_NAIVE:
- * FP32 data, plain FP32 sums (the uncompensated baseline). */
-enum { COUPLE_FP64 = 0, COUPLE_FP32_KAHAN = 1, COUPLE_FP32_NAIVE = 2 };  /* precision      */
+/* Precision: the data type and how per-cell sums (restriction children,
+ * deposition terms, transfer overlaps) accumulate; the global diagnostics are
+ * FP64 sums in every mode.
+ *   COUPLE_FP64        FP64 data, plain FP64 sums.
+ *   COUPLE_FP32_WIDE   FP32 data; per-cell sums accumulated in FP64 registers and
+ *                      rounded to FP32 once per cell (the pressure keeps an FP32
+ *                      low word for its gradient).  The default FP32 mode.
+ *   COUPLE_FP32_NAIVE  FP32 data, plain FP32 sums (the uncompensated baseline).
+ *   COUPLE_FP32_KAHAN  FP32 data, Kahan-compensated FP32 per-cell sums (the
+ *                      pressure's low word is the negated compensation). */
+enum { COUPLE_FP64 = 0, COUPLE_FP32_WIDE = 1, COUPLE_FP32_NAIVE = 2, COUPLE_FP32_KAHAN = 3 };  /* precision */
 enum { COUPLE_VEL_FINE = 0, COUPLE_VEL_BULK = 1, COUPLE_VEL_GIVEN = 2, COUPLE_VEL_MLP = 3 }; /* u_f */
 
 /* Indices into the FP64 diagnostics vector (length COUPLE_DIAG_LEN). */
@@ -126,7 +131,7 @@ typedef struct couple_config {
     double  phi_fp64;        /* particle solid fraction above which the FP32 modes evaluate
                                 eps_p and the voidage factor in FP64 (near close packing)     */
     int32_t deposit;         /* COUPLE_NGP or COUPLE_CIC                                      */
-    int32_t precision;       /* COUPLE_FP64, COUPLE_FP32_KAHAN or COUPLE_FP32_NAIVE           */
+    int32_t precision;       /* COUPLE_FP64, COUPLE_FP32_WIDE, _NAIVE or _KAHAN               */
     int32_t vel_source;      /* COUPLE_VEL_FINE (trilinear on the fine grid), COUPLE_VEL_BULK
                                 (trilinear on the restricted bulk velocity),
                                 COUPLE_VEL_GIVEN (couple_inputs.uf_given) or COUPLE_VEL_MLP
@@ -218,6 +223,49 @@ typedef struct couple_kernel_stat {
 
 int couple_timing_begin(couple_handle *h, int32_t max_steps);
 int couple_timing_end(couple_handle *h, couple_kernel_stat *stats, int32_t max_stats, int32_t *n_stats);
+
+/* ---- partitioned step (partition-equivalence emulation on one device) ---------
+ * The paper runs the coupling on many processes: each owns a partition of the
+ * bulk grid together with the particles whose containing bulk cell it owns and
+ * the fine cells nested in it (co-located partitions, Sec. 2.2), and the
+ * partitions exchange the data their neighbours need through a static, sparse
+ * process-to-process communication matrix, executed either through a master
+ * process ("gather-scatter") or directly between neighbours ("distributed",
+ * Sec. 2.3); the partitioned run must give the results of the sequential one
+ * (Sec. 3.1).  couple_part_step() does this on one device with nparts z-slabs:
+ * slab k owns bulk layers [z_k, z_{k+1}) (as equal as possible) and keeps, in
+ * buffers of its own, the particles binned there, its fine slab and one ghost
+ * bulk layer towards each neighbour.  Per step it exchanges (i) the fine cells of
+ * the boundary bulk layer (for the lookups and the pressure gradient next to the
+ * slab face), (ii) the ghost-layer partial sums of the volume deposition, added
+ * into the owner (reverse halo add), then the completed boundary layer back into
+ * the ghost layer, (iii) the same for the momentum source (and K, KU).  Only
+ * neighbouring slabs communicate: the matrix has the nonzero blocks (k, k +- 1).
+ *   exchange = COUPLE_EXCHANGE_DISTRIBUTED: each block is copied (or added)
+ *   directly from the sender's buffer into the receiver's;
+ *   COUPLE_EXCHANGE_GATHER_SCATTER: every block goes to a root buffer first and
+ *   from there to its receiver (two transfers).
+ * Results: cell, perm, count and start equal couple_step()'s bit for bit; the
+ * fields differ from it by the order of the summations split across owners
+ * (rounding only); the FP64 sums are the partitions' sums added in order.
+ * Scope: velocity source FINE or BULK; no two-fluid drag; the bulk spacing
+ * L_z / nb[2] must be a power of two (so that shifting positions into a slab's
+ * frame is exact); with advection, particles are assumed to move less than one
+ * bulk layer per step (the halo is one layer deep).  The call synchronises the
+ * stream once (to read the partition sizes).  Outputs and inputs as couple_step. */
+enum { COUPLE_EXCHANGE_DISTRIBUTED = 0, COUPLE_EXCHANGE_GATHER_SCATTER = 1 };
+typedef struct couple_part couple_part;
+
+/* nparts in [1, min(64, nb[2])]; allocates each slab's scratch and buffers
+ * (about nparts handles of couple_init, plus one copy of the fine inputs and
+ * outputs). */
+int couple_part_init(const couple_config *cfg, int32_t nparts, couple_part **out);
+int couple_part_step(couple_part *p, const couple_inputs *in, couple_outputs *out, int32_t exchange, void *stream);
+/* bytes[i * nparts + j]: bytes slab j sends to slab i in one step (the static
+ * communication matrix; zero unless |i - j| = 1). */
+int couple_part_comm_matrix(const couple_part *p, int64_t *bytes);
+int couple_part_free(couple_part *p);                     /* NULL is accepted */
+const char *couple_part_last_error(const couple_part *p);
 
 /* ---- the step without allocation ----------------------------------------------
  * For callers that cannot allocate device memory: code under HIP graph capture,

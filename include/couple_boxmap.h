@@ -52,7 +52,8 @@ typedef struct couple_boxmap couple_boxmap;
  * receiver grid (nr cells, receiver_boxes [nr][6]) for fields of the given
  * precision (COUPLE_FP64: double fields and weights, FP64 sums; the FP32
  * precisions: float fields and weights, FP64 register sums for
- * COUPLE_FP32_KAHAN, plain FP32 sums for COUPLE_FP32_NAIVE).  1 <= ns, nr <
+ * COUPLE_FP32_WIDE, Kahan-compensated FP32 sums for COUPLE_FP32_KAHAN, plain
+ * FP32 sums for COUPLE_FP32_NAIVE).  1 <= ns, nr <
  * 2^31; the map may hold at most 2^31 - 1 nonzeros.  Synchronous. */
 int couple_boxmap_init(int64_t ns, const double *sender_boxes, int64_t nr, const double *receiver_boxes,
                        int32_t precision, couple_boxmap **out);

@@ -48,8 +48,8 @@ typedef struct couple_remap couple_remap;
 
 /* Build the map from the sender grid (src_n, src_nodes) to the receiver grid
  * (dst_n, dst_nodes) for fields of the given precision (COUPLE_FP64: double
- * fields and weights; COUPLE_FP32_KAHAN / COUPLE_FP32_NAIVE: float fields,
- * compensated or plain sums).  Each grid: cells per axis >= 1, fewer than 2^31
+ * fields and weights; COUPLE_FP32_WIDE / COUPLE_FP32_KAHAN / COUPLE_FP32_NAIVE:
+ * float fields, sums in FP64 registers, Kahan-compensated in FP32, or plain).  Each grid: cells per axis >= 1, fewer than 2^31
  * cells in all.  On success *out receives the map (a few device arrays of the
  * size of the receiver's axes). */
 int couple_remap_init(const int32_t src_n[3], const double *src_nodes, const int32_t dst_n[3],

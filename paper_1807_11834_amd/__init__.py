@@ -33,8 +33,9 @@ LIB_PATH = os.path.join(_HERE, "libcouple.so")
 # ---- constants (include/couple.h) -------------------------------------------
 COUPLE_OK, COUPLE_EINVAL, COUPLE_ENOMEM, COUPLE_EHIP, COUPLE_ECAPACITY, COUPLE_ESTATE = 0, -1, -2, -3, -4, -6
 COUPLE_NGP, COUPLE_CIC = 0, 1
-COUPLE_FP64, COUPLE_FP32_KAHAN, COUPLE_FP32_NAIVE = 0, 1, 2
+COUPLE_FP64, COUPLE_FP32_WIDE, COUPLE_FP32_NAIVE, COUPLE_FP32_KAHAN = 0, 1, 2, 3
 COUPLE_VEL_FINE, COUPLE_VEL_BULK, COUPLE_VEL_GIVEN, COUPLE_VEL_MLP = 0, 1, 2, 3
+COUPLE_EXCHANGE_DISTRIBUTED, COUPLE_EXCHANGE_GATHER_SCATTER = 0, 1
 DIAG = {"V_tot": 0, "V_dep": 1, "sum_Fp": 2, "S_b": 5, "S_f": 8, "E_f": 11, "n_clamped": 12,
         "n_outside": 13, "max_phi": 14, "n_fallback": 15, "mlp_err2": 16, "mlp_ref2": 17, "mlp_nsamp": 18,
         "K_p": 19, "KU_p": 20, "K_b": 23, "KU_b": 24, "K_f": 27, "KU_f": 28}
@@ -141,6 +142,14 @@ def _load():
         f.restype = I
     L.couple_boxmap_last_error.argtypes = [P]
     L.couple_boxmap_last_error.restype = C.c_char_p
+    for name, args in {"couple_part_init": [C.POINTER(_Config), C.c_int32, C.POINTER(C.c_void_p)],
+                       "couple_part_step": [P, C.POINTER(_Inputs), C.POINTER(_Outputs), C.c_int32, P],
+                       "couple_part_comm_matrix": [P, P], "couple_part_free": [P]}.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = I
+    L.couple_part_last_error.argtypes = [P]
+    L.couple_part_last_error.restype = C.c_char_p
     L.couple_remap_last_error.argtypes = [P]
     L.couple_remap_last_error.restype = C.c_char_p
     L.couple_mlp_last_error.argtypes = [P]
@@ -163,7 +172,7 @@ class Config:
     eps_min: float = 0.3
     phi_fp64: float = 0.5
     deposit: int = COUPLE_CIC
-    precision: int = COUPLE_FP32_KAHAN
+    precision: int = COUPLE_FP32_WIDE
     vel_source: int = COUPLE_VEL_FINE
     advect: int = 0
     dt: float = 0.0
@@ -624,7 +633,7 @@ class Remap:
     same box.  ``src_nodes`` / ``dst_nodes``: three 1-D arrays of node
     coordinates (x, y, z) of rectilinear cell-centred grids."""
 
-    def __init__(self, src_nodes, dst_nodes, precision=COUPLE_FP32_KAHAN):
+    def __init__(self, src_nodes, dst_nodes, precision=COUPLE_FP32_WIDE):
         import numpy as np
         self.ns = [len(a) - 1 for a in src_nodes]
         self.nd = [len(a) - 1 for a in dst_nodes]
@@ -682,7 +691,7 @@ class BoxMap:
     [n, 6] array of axis-aligned cells (x0, x1, y0, y1, z0, z1), through a CSR
     overlap map built once (host, FP64) and applied on the device."""
 
-    def __init__(self, sender_boxes, receiver_boxes, precision=COUPLE_FP32_KAHAN):
+    def __init__(self, sender_boxes, receiver_boxes, precision=COUPLE_FP32_WIDE):
         import numpy as np
         sb, psb = _host(np.asarray(sender_boxes, np.float64).reshape(-1, 6), "float64")
         rb, prb = _host(np.asarray(receiver_boxes, np.float64).reshape(-1, 6), "float64")
@@ -724,6 +733,73 @@ class BoxMap:
         if getattr(self, "m", None) is not None:
             _lib.couple_boxmap_free(self.m)
             self.m = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---- partitioned step (couple_part_* of include/couple.h) ----------------------
+
+class Part:
+    """The coupling step on ``nparts`` co-located z-slabs of one device, with the
+    halos exchanged through the static neighbour-to-neighbour communication
+    matrix, directly (``exchange=COUPLE_EXCHANGE_DISTRIBUTED``) or through a root
+    buffer (``COUPLE_EXCHANGE_GATHER_SCATTER``).  ``step`` takes and returns what
+    ``Coupler.step`` does."""
+
+    def __init__(self, cfg: Config, nparts: int):
+        self.cfg = cfg
+        self.nparts = int(nparts)
+        c = cfg.to_c()
+        p = C.c_void_p()
+        code = _lib.couple_part_init(C.byref(c), self.nparts, C.byref(p))
+        if code != COUPLE_OK:
+            s = _lib.couple_part_last_error(None)
+            raise CoupleError(code, s.decode() if s else "")
+        self.p = p
+        self.out = None
+
+    def step(self, pos, vel, diam, fine, out=None, exchange=COUPLE_EXCHANGE_DISTRIBUTED, stream=None, step=0,
+             beta=True, uf=False):
+        n = pos.shape[0]
+        if out is None:
+            if self.out is None or self.out["drag"].shape[0] != n or (uf and self.out["uf"] is None):
+                self.out = alloc_outputs(self.cfg, n, device=pos.device, beta=beta, uf=uf)
+            out = self.out
+        inputs = {"n": n, "pos": pos, "vel": vel, "diam": diam, "fine_u": fine[0], "fine_v": fine[1],
+                  "fine_w": fine[2], "fine_p": fine[3], "step": step}
+        validate_step(self.cfg, inputs, out)
+        i = _Inputs()
+        i.n = int(n)
+        i.step = int(step)
+        for k in ("pos", "vel", "diam", "fine_u", "fine_v", "fine_w", "fine_p"):
+            setattr(i, k, _ptr(inputs.get(k)))
+        o = _Outputs()
+        for k, _ in _Outputs._fields_:
+            setattr(o, k, _ptr(out.get(k)))
+        code = _lib.couple_part_step(self.p, C.byref(i), C.byref(o), int(exchange), _stream(stream))
+        if code != COUPLE_OK:
+            s = _lib.couple_part_last_error(self.p)
+            raise CoupleError(code, s.decode() if s else "")
+        return out
+
+    def comm_matrix(self):
+        """[nparts, nparts] int64 array: entry (i, j) is the bytes slab j sends to
+        slab i in one step."""
+        import numpy as np
+        m = np.zeros((self.nparts, self.nparts), np.int64)
+        code = _lib.couple_part_comm_matrix(self.p, m.ctypes.data_as(C.c_void_p))
+        if code != COUPLE_OK:
+            raise CoupleError(code, "couple_part_comm_matrix failed")
+        return m
+
+    def close(self):
+        if getattr(self, "p", None) is not None:
+            _lib.couple_part_free(self.p)
+            self.p = None
 
     def __del__(self):
         try:

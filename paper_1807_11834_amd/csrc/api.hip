@@ -8,27 +8,11 @@
 
 #include "couple.h"
 #include "couple_mlp.h"
+#include "handle.hpp"
 #include "launch.hpp"
 #include "mlp_state.hpp"
 
 using namespace cpl;
-
-struct couple_handle {
-    couple_config cfg;
-    std::string err;
-    int64_t ncell = 0, nfine = 0;
-    int64_t part_stride = 0;
-    SortScratch sort{};
-    void *sp = nullptr, *uf4 = nullptr, *plo = nullptr, *dep = nullptr;
-    void *alpha8 = nullptr;         // vof: packed stencil records of the bulk alpha
-    float4 *fgrid = nullptr;        // VEL_MLP: packed bulk features
-    const couple_mlp *mlp = nullptr;
-    double *part = nullptr;
-    // per-kernel timing
-    Marker mk;
-    std::vector<hipEvent_t> events;
-    std::vector<const char *> names;
-};
 
 // Text of the last error reported without a handle (couple_init, the no-alloc
 // step): a fixed per-thread buffer, so that reporting allocates nothing.
@@ -82,7 +66,8 @@ static const char *validate(const couple_config *c) {
     if (!(std::isfinite(c->eps_min) && c->eps_min >= 0.0 && c->eps_min < 1.0)) return "eps_min must be in [0, 1)";
     if (!std::isfinite(c->phi_fp64)) return "phi_fp64 must be finite";
     if (!(c->deposit == COUPLE_NGP || c->deposit == COUPLE_CIC)) return "deposit must be COUPLE_NGP or COUPLE_CIC";
-    if (!(c->precision == COUPLE_FP64 || c->precision == COUPLE_FP32_KAHAN || c->precision == COUPLE_FP32_NAIVE))
+    if (!(c->precision == COUPLE_FP64 || c->precision == COUPLE_FP32_WIDE || c->precision == COUPLE_FP32_NAIVE ||
+          c->precision == COUPLE_FP32_KAHAN))
         return "unknown precision";
     if (!(c->vel_source == COUPLE_VEL_FINE || c->vel_source == COUPLE_VEL_BULK || c->vel_source == COUPLE_VEL_GIVEN ||
           c->vel_source == COUPLE_VEL_MLP))
@@ -187,6 +172,7 @@ extern "C" int couple_init(const couple_config *cfg, couple_handle **out) {
     bool ok = true;
     for (int b = 0; b < B_COUNT && ok; ++b)
         if (plan.bytes[b] > 0 || b < B_FGRID) ok = dev_alloc(buf_slot(h, b), plan.bytes[b]);
+
     if (!ok) {
         release(h);
         delete h;
@@ -207,38 +193,21 @@ extern "C" const char *couple_last_error(const couple_handle *h) {
     return h ? h->err.c_str() : g_err;
 }
 
-template <typename T> static Geo<T> make_geo(const couple_config &c) {
-    Geo<T> g;
-    for (int a = 0; a < 3; ++a) {
-        g.nb[a] = c.nb[a];
-        g.nf[a] = c.nb[a] * c.ratio;
-        g.L[a] = (T)c.box[a];
-        g.sb[a] = (T)((double)c.nb[a] / c.box[a]);
-        g.sf[a] = (T)((double)g.nf[a] / c.box[a]);
-        g.hb[a] = (T)(c.box[a] / (double)c.nb[a]);
-    }
-    g.ncell = (int64_t)c.nb[0] * c.nb[1] * c.nb[2];
-    g.nfine = g.ncell * c.ratio * c.ratio * c.ratio;
-    g.vb = (c.box[0] / c.nb[0]) * (c.box[1] / c.nb[1]) * (c.box[2] / c.nb[2]);
-    g.vf = g.vb / ((double)c.ratio * c.ratio * c.ratio);
-    g.inv_vb = (T)(1.0 / g.vb);
-    return g;
-}
-
 // Enqueue the step's kernels with the scratch of `h` (a handle of couple_init, or
 // the stack-built view of the static scratch of couple_step_noalloc).  On a launch
 // failure returns COUPLE_EHIP with a static description in *what and the HIP
 // error in *herr; allocates nothing.
 template <typename T>
 static int step_impl(couple_handle *h, const couple_inputs *in, couple_outputs *out, hipStream_t st,
-                     const char **what, hipError_t *herr) {
+                     const char **what, hipError_t *herr, int phases = kPhaseAll, int64_t own_c0 = 0,
+                     int64_t own_c1 = -1) {
     const couple_config &c = h->cfg;
     StepArgs<T> a;
     a.g = make_geo<T>(c);
     a.n = in->n;
     a.ratio = c.ratio;
     a.cic = c.deposit == COUPLE_CIC;
-    a.kahan = c.precision == COUPLE_FP32_KAHAN;
+    a.sum_mode = c.precision == COUPLE_FP32_KAHAN ? kSumKahan : (c.precision == COUPLE_FP32_WIDE ? kSumWide : kSumPlain);
     a.vel_source = c.vel_source;
     a.advect = c.advect;
     a.semi = c.semi_implicit;
@@ -298,24 +267,36 @@ static int step_impl(couple_handle *h, const couple_inputs *in, couple_outputs *
     a.mlp_period = c.mlp_period > 0 ? c.mlp_period : 1;
     a.mlp_tol = (float)c.mlp_tol;
     a.n_bricks = bricks_of(c.nb);
+    a.own_c0 = own_c0;
+    a.own_c1 = own_c1 < 0 ? a.g.ncell : own_c1;
 
     (void)hipGetLastError();  // clear a stale error so that it is not reported as ours
-    const uint32_t *skeys = nullptr;
-    hipError_t e = launch_bin_sort<T>(a.pos, a.diam, a.n, a.g, out->cell, a.uf4, out->perm, out->start,
-                                      out->count, h->sort, h->part + SL_NOUT * h->part_stride, &skeys, &h->mk, st);
-    if (e != hipSuccess) {
-        *what = "sort launch failed: ";
-        *herr = e;
-        return COUPLE_EHIP;
+    hipError_t e = hipSuccess;
+    if (phases & kPhaseDeposit) {
+        const uint32_t *skeys = nullptr;
+        e = launch_bin_sort<T>(a.pos, a.diam, a.n, a.g, out->cell, a.uf4, out->perm, out->start, out->count, h->sort,
+                               h->part + SL_NOUT * h->part_stride, &skeys, &h->mk, st);
+        if (e != hipSuccess) {
+            *what = "sort launch failed: ";
+            *herr = e;
+            return COUPLE_EHIP;
+        }
+        h->skeys = skeys;
     }
-    a.keys = skeys;
-    e = launch_stages<T>(a, st);
+    a.keys = h->skeys;
+    e = launch_stages<T>(a, st, phases);
     if (e != hipSuccess) {
         *what = "stage launch failed: ";
         *herr = e;
         return COUPLE_EHIP;
     }
     return COUPLE_OK;
+}
+
+int cpl::step_phases(couple_handle *h, const couple_inputs *in, couple_outputs *out, hipStream_t st, int phases,
+                     int64_t own_c0, int64_t own_c1, const char **what, hipError_t *herr) {
+    return h->cfg.precision == COUPLE_FP64 ? step_impl<double>(h, in, out, st, what, herr, phases, own_c0, own_c1)
+                                           : step_impl<float>(h, in, out, st, what, herr, phases, own_c0, own_c1);
 }
 
 // Argument checks of a step (no allocation); nullptr when the call is valid.

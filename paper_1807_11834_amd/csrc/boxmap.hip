@@ -18,31 +18,29 @@
 
 namespace cpl {
 
-template <typename T, bool WIDE> using MapSum = typename std::conditional<WIDE, double, T>::type;
-
-template <typename T, bool WIDE, int NF>
+// One thread per receiver row: sum_j w_j src[col_j] for up to NF fields at a
+// time, under the map's sum mode (SumMode).
+template <typename T, int SM, int NF>
 __global__ __launch_bounds__(kBlock) void k_boxmap(const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
                                                    const T *__restrict__ w, int64_t nr, int64_t ns,
                                                    const T *__restrict__ src, T *__restrict__ dst, int nfields) {
-    using S = MapSum<T, WIDE>;
+    using S = typename FmaSum<T, SM>::W;
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t r = tile * kBlock + threadIdx.x;
     if (r >= nr) return;
     const int64_t b = rowptr[r], e = rowptr[r + 1];
     for (int f0 = 0; f0 < nfields; f0 += NF) {
-        S acc[NF];
-#pragma unroll
-        for (int k = 0; k < NF; ++k) acc[k] = S(0);
+        FmaSum<T, SM> acc[NF];
         for (int64_t j = b; j < e; ++j) {
             const int64_t c = col[j];
             const S wj = S(w[j]);
 #pragma unroll
             for (int k = 0; k < NF; ++k)
-                if (f0 + k < nfields) acc[k] += wj * S(src[(int64_t)(f0 + k) * ns + c]);
+                if (f0 + k < nfields) acc[k].add(wj, S(src[(int64_t)(f0 + k) * ns + c]));
         }
 #pragma unroll
         for (int k = 0; k < NF; ++k)
-            if (f0 + k < nfields) dst[(int64_t)(f0 + k) * nr + r] = T(acc[k]);
+            if (f0 + k < nfields) dst[(int64_t)(f0 + k) * nr + r] = acc[k].value();
     }
 }
 
@@ -214,7 +212,8 @@ extern "C" int couple_boxmap_init(int64_t ns, const double *sender_boxes, int64_
     const int64_t lim = (int64_t(1) << 31) - 1;
     if (ns < 1 || nr < 1 || ns >= lim || nr >= lim)
         return bfail(nullptr, COUPLE_EINVAL, "couple_boxmap_init: cell counts must be in [1, 2^31 - 1)");
-    if (!(precision == COUPLE_FP64 || precision == COUPLE_FP32_KAHAN || precision == COUPLE_FP32_NAIVE))
+    if (!(precision == COUPLE_FP64 || precision == COUPLE_FP32_WIDE || precision == COUPLE_FP32_NAIVE ||
+          precision == COUPLE_FP32_KAHAN))
         return bfail(nullptr, COUPLE_EINVAL, "couple_boxmap_init: unknown precision");
     if (const char *w = check_boxes(ns, sender_boxes))
         return bfail(nullptr, COUPLE_EINVAL, std::string("couple_boxmap_init: sender ") + w);
@@ -261,10 +260,10 @@ extern "C" int couple_boxmap_init(int64_t ns, const double *sender_boxes, int64_
     return COUPLE_OK;
 }
 
-template <typename T, bool WIDE>
+template <typename T, int SM>
 static void launch_boxmap(const couple_boxmap *m, const void *src, void *dst, int nf, hipStream_t st) {
     const int64_t blocks = (m->nr + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL((k_boxmap<T, WIDE, 4>), dim3((unsigned)blocks), dim3(kBlock), 0, st, m->rowptr, m->col,
+    hipLaunchKernelGGL((k_boxmap<T, SM, 4>), dim3((unsigned)blocks), dim3(kBlock), 0, st, m->rowptr, m->col,
                        (const T *)m->w, m->nr, m->ns, (const T *)src, (T *)dst, nf);
 }
 
@@ -274,9 +273,10 @@ extern "C" int couple_boxmap_apply(couple_boxmap *m, const void *src, void *dst,
     if (nfields < 1 || nfields > 64) return bfail(m, COUPLE_EINVAL, "couple_boxmap_apply: nfields must be in [1, 64]");
     hipStream_t st = static_cast<hipStream_t>(stream);
     (void)hipGetLastError();
-    if (m->precision == COUPLE_FP64) launch_boxmap<double, false>(m, src, dst, nfields, st);
-    else if (m->precision == COUPLE_FP32_KAHAN) launch_boxmap<float, true>(m, src, dst, nfields, st);
-    else launch_boxmap<float, false>(m, src, dst, nfields, st);
+    if (m->precision == COUPLE_FP64) launch_boxmap<double, kSumPlain>(m, src, dst, nfields, st);
+    else if (m->precision == COUPLE_FP32_WIDE) launch_boxmap<float, kSumWide>(m, src, dst, nfields, st);
+    else if (m->precision == COUPLE_FP32_KAHAN) launch_boxmap<float, kSumKahan>(m, src, dst, nfields, st);
+    else launch_boxmap<float, kSumPlain>(m, src, dst, nfields, st);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return bfail(m, COUPLE_EHIP, std::string("couple_boxmap_apply: launch failed: ") + hipGetErrorString(e));
     return COUPLE_OK;

@@ -1,5 +1,6 @@
 // common.hpp -- device helpers shared by the coupling kernels (gfx950, wave64).
 #pragma once
+#include <type_traits>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -38,6 +39,12 @@ template <typename T> struct Geo {
     double vb, vf;      // cell volumes (FP64, for the diagnostics)
 };
 
+// How the per-cell sums of a step accumulate (the FP32 precision modes):
+// plainly in the storage type, with Kahan compensation in the storage type, or
+// plainly in FP64 registers (rounded to the storage type once per cell).  The
+// FP64 mode sums plainly in FP64.
+enum SumMode : int { kSumPlain = 0, kSumKahan = 1, kSumWide = 2 };
+
 // Compensated (Kahan) or plain running sum.
 template <typename T, bool KAHAN> struct Acc {
     T s = T(0), c = T(0);
@@ -51,6 +58,35 @@ template <typename T, bool KAHAN> struct Acc {
             s += v;
         }
     }
+};
+
+// A per-cell sum of values of type T under mode SM.
+template <typename T, int SM> struct CellSum {
+    using W = typename std::conditional<SM == kSumWide, double, T>::type;
+    Acc<W, SM == kSumKahan> acc;
+    __device__ __forceinline__ void add(T v) { acc.add(W(v)); }
+    __device__ __forceinline__ T value() const { return T(acc.s); }
+};
+
+// A running sum of products w v under mode SM: Kahan in T with the product
+// formed by an FMA against the running compensation (each term rounded once),
+// plain FMAs in T, or plain FMAs in FP64 registers (rounded to T once, by
+// value()).
+template <typename T, int SM> struct FmaSum {
+    using W = typename std::conditional<SM == kSumWide, double, T>::type;
+    W s = W(0);
+    W c = W(0);   // Kahan compensation (SM == kSumKahan only)
+    __device__ __forceinline__ void add(W w, W v) {
+        if constexpr (SM == kSumKahan) {
+            const W y = fma(w, v, -c);
+            const W t = s + y;
+            c = (t - s) - y;
+            s = t;
+        } else {
+            s = fma(w, v, s);
+        }
+    }
+    __device__ __forceinline__ T value() const { return T(s); }
 };
 
 template <typename T> __device__ __forceinline__ T tmin(T a, T b) { return a < b ? a : b; }

@@ -42,7 +42,7 @@ __device__ __forceinline__ void write_gradient(int64_t c, int cx, int cy, int cz
 // ---------------------------------------------------------------------------
 // NGP (containing cell)
 // ---------------------------------------------------------------------------
-template <typename T, bool KAHAN, int MODE>
+template <typename T, int SM, int MODE>
 __global__ __launch_bounds__(kBlock) void k_deposit_ngp(const int32_t *__restrict__ start,
                                                         const vec4<T> *__restrict__ sp,
                                                         const int32_t *__restrict__ perm,
@@ -57,7 +57,7 @@ __global__ __launch_bounds__(kBlock) void k_deposit_ngp(const int32_t *__restric
     if (c < g.ncell) {
         const int32_t s = seg_clamp(start[c], n), e = seg_clamp(start[c + 1], n);
         if constexpr (MODE == kSemi) {
-            Acc<T, KAHAN> acc[4];
+            CellSum<T, SM> acc[4];
             for (int32_t p = s; p < e; ++p) {
                 int64_t id = perm[p];
                 if (id < 0 || id >= n) id = 0;
@@ -67,16 +67,16 @@ __global__ __launch_bounds__(kBlock) void k_deposit_ngp(const int32_t *__restric
                 acc[2].add(b.z);
                 acc[3].add(b.w);
             }
-            out[c] = acc[0].s * g.inv_vb;
-            for (int k = 0; k < 3; ++k) out2[k * g.ncell + c] = acc[k + 1].s * g.inv_vb;
-            for (int k = 0; k < 4; ++k) v[k] = (double)(acc[k].s * g.inv_vb);
+            out[c] = acc[0].value() * g.inv_vb;
+            for (int k = 0; k < 3; ++k) out2[k * g.ncell + c] = acc[k + 1].value() * g.inv_vb;
+            for (int k = 0; k < 4; ++k) v[k] = (double)(acc[k].value() * g.inv_vb);
         } else if constexpr (MODE == kPhi) {
-            Acc<T, KAHAN> acc;
+            CellSum<T, SM> acc;
             for (int32_t p = s; p < e; ++p) acc.add(vol_over_vb(sp[p].w, g.inv_vb));
-            out[c] = acc.s;
-            v[0] = (double)acc.s;
+            out[c] = acc.value();
+            v[0] = (double)acc.value();
         } else {
-            Acc<T, KAHAN> ax, ay, az;
+            CellSum<T, SM> ax, ay, az;
             for (int32_t p = s; p < e; ++p) {
                 int64_t id = perm[p];
                 if (id < 0 || id >= n) id = 0;
@@ -84,7 +84,7 @@ __global__ __launch_bounds__(kBlock) void k_deposit_ngp(const int32_t *__restric
                 ay.add(drag[3 * id + 1]);
                 az.add(drag[3 * id + 2]);
             }
-            const T fx = -ax.s * g.inv_vb, fy = -ay.s * g.inv_vb, fz = -az.s * g.inv_vb;
+            const T fx = -ax.value() * g.inv_vb, fy = -ay.value() * g.inv_vb, fz = -az.value() * g.inv_vb;
             out[c] = fx;
             out[g.ncell + c] = fy;
             out[2 * g.ncell + c] = fz;
@@ -139,19 +139,14 @@ template <typename T, int MODE> struct RowStage {
     T val[DepNc<MODE>::value][kWavesPerBlock][kChunk]; // V_p / V_b, F_p, or (beta_p, beta_p u_p)
 };
 
-// Row-pass sums s += w v.  Where the mode compensates its sums, the weights and
-// values are widened to FP64 and summed there with one FMA per term.  In the
-// FP32 mode both products are exact in FP64, so every term is rounded once at
-// FP64 precision: at least as accurate as a Kahan-compensated FP32 sum, for one
-// instruction per term instead of five (FP64 FMAs issue at the rate of unpacked
-// FP32 ones on this chip).  The FP64 mode sums with plain FP64 FMAs (the at most
-// ~100 terms of a partial sum carry an error below 1e-14 of their magnitudes),
-// the naive FP32 mode with plain FP32 FMAs.
-template <typename T, bool KAHAN> struct RowSum {
-    using W = typename std::conditional<KAHAN, double, T>::type;
-    W s = W(0);
-    __device__ __forceinline__ void add(W w, W v) { s = fma(w, v, s); }
-};
+// Row-pass sums s += w v under the step's sum mode: FP32 with Kahan
+// compensation (the product w v formed by an FMA against the running
+// compensation, so the term is rounded once), FP32 plainly, or widened to FP64
+// registers with one FMA per term (both products exact in FP64: every term is
+// rounded once at FP64 precision; FP64 FMAs issue at the rate of unpacked FP32
+// ones on this chip).  The FP64 mode sums with plain FP64 FMAs (the at most ~100
+// terms of a partial sum carry an error below 1e-14 of their magnitudes).
+template <typename T, int SM> using RowSum = FmaSum<T, SM>;
 
 template <typename T>
 __device__ __forceinline__ void row_weights(const Axis<T> &a, int c, T w[3]) {
@@ -169,14 +164,14 @@ __device__ __forceinline__ int group_lo(int t) { return ((t + 1) >> 1) - 1; }
 
 // One source row (ys, zs) of the wave's group: row JY, layer KZ of the group.
 // Its contributions go to the accumulators [KZ + 0..2][JY + 0..2].
-template <typename T, bool KAHAN, int MODE, int JY, int KZ>
-__device__ __forceinline__ void deposit_source_row(RowSum<T, KAHAN> (&acc)[4][4][DepNc<MODE>::value],
+template <typename T, int SM, int MODE, int JY, int KZ>
+__device__ __forceinline__ void deposit_source_row(RowSum<T, SM> (&acc)[4][4][DepNc<MODE>::value],
                                                    RowStage<T, MODE> &st, int w, int lane, int x0, int ys, int zs,
                                                    const int32_t *__restrict__ start, const vec4<T> *__restrict__ sp,
                                                    const int32_t *__restrict__ perm, const T *__restrict__ drag,
                                                    const vec4<T> *__restrict__ src4, int64_t n, const Geo<T> &g) {
     constexpr int NC = DepNc<MODE>::value;
-    using W = typename RowSum<T, KAHAN>::W;
+    using W = typename RowSum<T, SM>::W;
     const int nbx = g.nb[0], nby = g.nb[1], nbz = g.nb[2];
     const int x = x0 + lane;
     const int64_t srow = ((int64_t)zs * nby + ys) * nbx;
@@ -279,7 +274,7 @@ __device__ __forceinline__ void deposit_source_row(RowSum<T, KAHAN> (&acc)[4][4]
     }
 }
 
-template <typename T, bool KAHAN, int MODE>
+template <typename T, int SM, int MODE>
 __global__ __launch_bounds__(kBlock) void k_deposit_rows(const int32_t *__restrict__ start,
                                                          const vec4<T> *__restrict__ sp,
                                                          const int32_t *__restrict__ perm,
@@ -301,14 +296,14 @@ __global__ __launch_bounds__(kBlock) void k_deposit_rows(const int32_t *__restri
     const int gy = (int)(grp % ngy), gz = (int)(grp / ngy);
     const int x = x0 + lane;
     const int y0 = 2 * gy, z0 = 2 * gz;
-    RowSum<T, KAHAN> acc[4][4][NC];   // [target z - (z0 - 1)][target y - (y0 - 1)][component]
-    deposit_source_row<T, KAHAN, MODE, 0, 0>(acc, st, w, lane, x0, y0, z0, start, sp, perm, drag, src4, n, g);
+    RowSum<T, SM> acc[4][4][NC];   // [target z - (z0 - 1)][target y - (y0 - 1)][component]
+    deposit_source_row<T, SM, MODE, 0, 0>(acc, st, w, lane, x0, y0, z0, start, sp, perm, drag, src4, n, g);
     if (y0 + 1 < nby)
-        deposit_source_row<T, KAHAN, MODE, 1, 0>(acc, st, w, lane, x0, y0 + 1, z0, start, sp, perm, drag, src4, n, g);
+        deposit_source_row<T, SM, MODE, 1, 0>(acc, st, w, lane, x0, y0 + 1, z0, start, sp, perm, drag, src4, n, g);
     if (z0 + 1 < nbz) {
-        deposit_source_row<T, KAHAN, MODE, 0, 1>(acc, st, w, lane, x0, y0, z0 + 1, start, sp, perm, drag, src4, n, g);
+        deposit_source_row<T, SM, MODE, 0, 1>(acc, st, w, lane, x0, y0, z0 + 1, start, sp, perm, drag, src4, n, g);
         if (y0 + 1 < nby)
-            deposit_source_row<T, KAHAN, MODE, 1, 1>(acc, st, w, lane, x0, y0 + 1, z0 + 1, start, sp, perm, drag,
+            deposit_source_row<T, SM, MODE, 1, 1>(acc, st, w, lane, x0, y0 + 1, z0 + 1, start, sp, perm, drag,
                                                      src4, n, g);
     }
     if (x >= nbx) return;
@@ -329,7 +324,7 @@ __global__ __launch_bounds__(kBlock) void k_deposit_rows(const int32_t *__restri
     }
 }
 
-template <typename T, bool KAHAN, int MODE>
+template <typename T, int SM, int MODE>
 __global__ __launch_bounds__(kBlock) void k_deposit_sum(const T *__restrict__ partial, Geo<T> g,
                                                         const T *__restrict__ P, const T *__restrict__ Plo,
                                                         T *__restrict__ out, T *__restrict__ out2, T *__restrict__ G,
@@ -341,7 +336,7 @@ __global__ __launch_bounds__(kBlock) void k_deposit_sum(const T *__restrict__ pa
     if (c < g.ncell) {
         int cx, cy, cz;
         decode_cell(c, g.nb, cx, cy, cz);
-        Acc<T, KAHAN> acc[NC];
+        CellSum<T, SM> acc[NC];
         const int gzl = group_lo(cz), gyl = group_lo(cy);
         const int ngy = (g.nb[1] + 1) >> 1, ngz = (g.nb[2] + 1) >> 1;
         for (int sz = 0; sz < 2; ++sz) {
@@ -353,19 +348,19 @@ __global__ __launch_bounds__(kBlock) void k_deposit_sum(const T *__restrict__ pa
             }
         }
         if constexpr (MODE == kForce) {
-            const T fx = -acc[0].s * g.inv_vb, fy = -acc[1].s * g.inv_vb, fz = -acc[2].s * g.inv_vb;
+            const T fx = -acc[0].value() * g.inv_vb, fy = -acc[1].value() * g.inv_vb, fz = -acc[2].value() * g.inv_vb;
             out[c] = fx;
             out[g.ncell + c] = fy;
             out[2 * g.ncell + c] = fz;
             v[0] = fx; v[1] = fy; v[2] = fz;
             write_gradient(c, cx, cy, cz, g, P, Plo, G);
         } else if constexpr (MODE == kSemi) {
-            out[c] = acc[0].s * g.inv_vb;
-            for (int k = 0; k < 3; ++k) out2[k * g.ncell + c] = acc[k + 1].s * g.inv_vb;
-            for (int k = 0; k < 4; ++k) v[k] = (double)(acc[k].s * g.inv_vb);
+            out[c] = acc[0].value() * g.inv_vb;
+            for (int k = 0; k < 3; ++k) out2[k * g.ncell + c] = acc[k + 1].value() * g.inv_vb;
+            for (int k = 0; k < 4; ++k) v[k] = (double)(acc[k].value() * g.inv_vb);
         } else {
-            out[c] = acc[0].s;
-            v[0] = (double)acc[0].s;
+            out[c] = acc[0].value();
+            v[0] = (double)acc[0].value();
         }
     }
     if constexpr (MODE == kPhi) {
@@ -404,46 +399,46 @@ static int row_blocks(const int nb[3]) {
     return (int)((nwave + kWavesPerBlock - 1) / kWavesPerBlock);
 }
 
-template <typename T, bool KAHAN, int MODE>
+template <typename T, int SM, int MODE>
 static int launch_deposit(const StepArgs<T> &a, T *out, T *out2, hipStream_t st, const char *sum_mark) {
     const int nblk = deposit_blocks(a.g.nb, a.g.ncell, a.cic);
     const vec4<T> *src4 = a.uf4;   // (beta, beta u_p) per particle once the drag has run
     if (a.cic) {
-        hipLaunchKernelGGL((k_deposit_rows<T, KAHAN, MODE>), dim3(row_blocks(a.g.nb)), dim3(kBlock), 0, st, a.start,
+        hipLaunchKernelGGL((k_deposit_rows<T, SM, MODE>), dim3(row_blocks(a.g.nb)), dim3(kBlock), 0, st, a.start,
                            a.sp, a.perm, a.drag, src4, a.n, a.g, a.dep_partial);
         a.mk->mark(sum_mark, st);
-        hipLaunchKernelGGL((k_deposit_sum<T, KAHAN, MODE>), dim3(nblk), dim3(kBlock), 0, st, a.dep_partial, a.g, a.P,
+        hipLaunchKernelGGL((k_deposit_sum<T, SM, MODE>), dim3(nblk), dim3(kBlock), 0, st, a.dep_partial, a.g, a.P,
                            a.Plo, out, out2, a.G, a.part, a.part_stride);
     } else {
-        hipLaunchKernelGGL((k_deposit_ngp<T, KAHAN, MODE>), dim3(nblk), dim3(kBlock), 0, st, a.start, a.sp, a.perm,
+        hipLaunchKernelGGL((k_deposit_ngp<T, SM, MODE>), dim3(nblk), dim3(kBlock), 0, st, a.start, a.sp, a.perm,
                            a.drag, src4, a.n, a.g, a.P, a.Plo, out, out2, a.G, a.part, a.part_stride);
     }
     return nblk;
 }
 
-template <typename T, bool KAHAN> int launch_deposit_phi(const StepArgs<T> &a, hipStream_t st) {
-    return launch_deposit<T, KAHAN, kPhi>(a, a.phi, nullptr, st, "deposit_phi_sum");
+template <typename T, int SM> int launch_deposit_phi(const StepArgs<T> &a, hipStream_t st) {
+    return launch_deposit<T, SM, kPhi>(a, a.phi, nullptr, st, "deposit_phi_sum");
 }
 
-template <typename T, bool KAHAN> int launch_deposit_force(const StepArgs<T> &a, hipStream_t st) {
-    return launch_deposit<T, KAHAN, kForce>(a, a.F, nullptr, st, "deposit_force_sum");
+template <typename T, int SM> int launch_deposit_force(const StepArgs<T> &a, hipStream_t st) {
+    return launch_deposit<T, SM, kForce>(a, a.F, nullptr, st, "deposit_force_sum");
 }
 
-template <typename T, bool KAHAN> int launch_deposit_semi(const StepArgs<T> &a, hipStream_t st) {
-    return launch_deposit<T, KAHAN, kSemi>(a, a.K, a.KU, st, "deposit_semi_sum");
+template <typename T, int SM> int launch_deposit_semi(const StepArgs<T> &a, hipStream_t st) {
+    return launch_deposit<T, SM, kSemi>(a, a.K, a.KU, st, "deposit_semi_sum");
 }
 
-template int launch_deposit_phi<float, true>(const StepArgs<float> &, hipStream_t);
-template int launch_deposit_phi<float, false>(const StepArgs<float> &, hipStream_t);
-template int launch_deposit_phi<double, true>(const StepArgs<double> &, hipStream_t);
-template int launch_deposit_phi<double, false>(const StepArgs<double> &, hipStream_t);
-template int launch_deposit_force<float, true>(const StepArgs<float> &, hipStream_t);
-template int launch_deposit_force<float, false>(const StepArgs<float> &, hipStream_t);
-template int launch_deposit_force<double, true>(const StepArgs<double> &, hipStream_t);
-template int launch_deposit_force<double, false>(const StepArgs<double> &, hipStream_t);
-template int launch_deposit_semi<float, true>(const StepArgs<float> &, hipStream_t);
-template int launch_deposit_semi<float, false>(const StepArgs<float> &, hipStream_t);
-template int launch_deposit_semi<double, true>(const StepArgs<double> &, hipStream_t);
-template int launch_deposit_semi<double, false>(const StepArgs<double> &, hipStream_t);
+template int launch_deposit_phi<float, kSumPlain>(const StepArgs<float> &, hipStream_t);
+template int launch_deposit_phi<float, kSumKahan>(const StepArgs<float> &, hipStream_t);
+template int launch_deposit_phi<float, kSumWide>(const StepArgs<float> &, hipStream_t);
+template int launch_deposit_phi<double, kSumPlain>(const StepArgs<double> &, hipStream_t);
+template int launch_deposit_force<float, kSumPlain>(const StepArgs<float> &, hipStream_t);
+template int launch_deposit_force<float, kSumKahan>(const StepArgs<float> &, hipStream_t);
+template int launch_deposit_force<float, kSumWide>(const StepArgs<float> &, hipStream_t);
+template int launch_deposit_force<double, kSumPlain>(const StepArgs<double> &, hipStream_t);
+template int launch_deposit_semi<float, kSumPlain>(const StepArgs<float> &, hipStream_t);
+template int launch_deposit_semi<float, kSumKahan>(const StepArgs<float> &, hipStream_t);
+template int launch_deposit_semi<float, kSumWide>(const StepArgs<float> &, hipStream_t);
+template int launch_deposit_semi<double, kSumPlain>(const StepArgs<double> &, hipStream_t);
 
 }  // namespace cpl

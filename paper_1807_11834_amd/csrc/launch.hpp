@@ -36,6 +36,12 @@ struct SortScratch {
 
 int sort_tiles(int64_t n);
 
+// One stable radix pass over keys < 2^bits (1 <= bits <= 8) from the identity
+// order: keys_out / ids_out in ascending key, ties by id; s.totals[d] receives
+// the number of keys equal to d.
+hipError_t launch_stable_partition(const uint32_t *keys, int64_t n, int bits, const SortScratch &s, uint32_t *keys_out,
+                                   uint32_t *ids_out, hipStream_t st);
+
 // Bin particles, sort (cell, id), and build start/count.
 template <typename T>
 hipError_t launch_bin_sort(const T *pos, const T *diam, int64_t n, const Geo<T> &g, int32_t *cell, vec4<T> *pk,
@@ -56,7 +62,7 @@ template <typename T> struct StepArgs {
     int64_t n;
     int ratio;
     int cic;           // deposition / gather weights: 1 = CIC, 0 = NGP
-    int kahan;         // compensated per-cell sums (FP32 modes)
+    int sum_mode;      // SumMode of the per-cell sums (FP32 modes)
     int vel_source;    // 0 fine, 1 bulk, 2 given, 3 learned surrogate (+ fine fallback)
     int advect;
     int semi;          // semi-implicit source fields K, KU
@@ -100,10 +106,17 @@ template <typename T> struct StepArgs {
     int mlp_period;              // one particle in mlp_period is checked (id mod period)
     float mlp_tol;               // brick falls back to the fine lookup above this error
     int64_t n_bricks;            // 8x8x8-cell bricks of the bulk grid
+    int64_t own_c0, own_c1;      // bulk cells whose fine cells enter the fine-grid sums (all, except in a
+                                 // partition of the partitioned step: its owned layers)
 };
 
-// Stage launchers (in order of the step).
-template <typename T> hipError_t launch_stages(const StepArgs<T> &a, hipStream_t st);
+// Stage launchers: the phases of a step after binning and sorting: the sorted
+// copy and the volume deposition; the velocity at the particles and the drag;
+// the momentum-source deposition (and K, KU); the prolongations; the FP64 sums.
+// A whole step runs them all (kPhaseAll); the partitioned step runs them one at
+// a time with halo exchanges in between.
+enum { kPhaseDeposit = 1, kPhaseVelocity = 2, kPhaseSource = 4, kPhaseProlong = 8, kPhaseDiag = 16, kPhaseAll = 31 };
+template <typename T> hipError_t launch_stages(const StepArgs<T> &a, hipStream_t st, int phases = kPhaseAll);
 
 // Learned-surrogate stages of the step (mlp.hip): packed features and pressure
 // gradient, inference, sampled check with fine fallback.  Each check workgroup
@@ -116,9 +129,9 @@ int64_t bricks_of(const int nb[3]);
 
 // Deposition (deposit.hip); each returns the number of workgroups launched
 // (one FP64 partial per workgroup and diagnostic slot).
-template <typename T, bool KAHAN> int launch_deposit_phi(const StepArgs<T> &a, hipStream_t st);
-template <typename T, bool KAHAN> int launch_deposit_force(const StepArgs<T> &a, hipStream_t st);
-template <typename T, bool KAHAN> int launch_deposit_semi(const StepArgs<T> &a, hipStream_t st);
+template <typename T, int SM> int launch_deposit_phi(const StepArgs<T> &a, hipStream_t st);
+template <typename T, int SM> int launch_deposit_force(const StepArgs<T> &a, hipStream_t st);
+template <typename T, int SM> int launch_deposit_semi(const StepArgs<T> &a, hipStream_t st);
 int deposit_blocks(const int nb[3], int64_t ncell, int cic);
 
 }  // namespace cpl

@@ -48,10 +48,11 @@ template <typename T> struct RemapArgs {
     int64_t nsrc, ndst;
 };
 
-// Accumulator type: FP64 in the compensated FP32 mode, T otherwise.
-template <typename T, bool KAHAN> using SumT = typename std::conditional<KAHAN, double, T>::type;
+// Sums of weight x value under the map's sum mode (SumMode): W is the type the
+// weights and values are widened to.
+template <typename T, int SM> using SumT = typename FmaSum<T, SM>::W;
 
-template <typename T, bool KAHAN>
+template <typename T, int SM>
 __global__ __launch_bounds__(kBlock) void k_remap(RemapArgs<T> r, const T *__restrict__ src, T *__restrict__ dst) {
     const int64_t nblk = gridDim.x;
     const int64_t c = xcd_tile(blockIdx.x, nblk) * kBlock + threadIdx.x;
@@ -63,17 +64,17 @@ __global__ __launch_bounds__(kBlock) void k_remap(RemapArgs<T> r, const T *__res
     const int fy = r.first[1][j], ny = r.cnt[1][j], oy = r.off[1][j];
     const int fz = r.first[2][k], nz = r.cnt[2][k], oz = r.off[2][k];
     const int64_t sx = r.ns[0], sxy = (int64_t)r.ns[0] * r.ns[1];
-    using W = SumT<T, KAHAN>;
-    W acc = W(0);
+    using W = SumT<T, SM>;
+    FmaSum<T, SM> acc;
     for (int kz = 0; kz < nz; ++kz) {
         const T wz = r.w[2][oz + kz];
         for (int ky = 0; ky < ny; ++ky) {
             const T wyz = wz * r.w[1][oy + ky];
             const T *__restrict__ row = s + (int64_t)(fz + kz) * sxy + (int64_t)(fy + ky) * sx + fx;
-            for (int kx = 0; kx < nx; ++kx) acc = fma(W(wyz * r.w[0][ox + kx]), W(row[kx]), acc);
+            for (int kx = 0; kx < nx; ++kx) acc.add(W(wyz * r.w[0][ox + kx]), W(row[kx]));
         }
     }
-    dst[(int64_t)blockIdx.y * r.ndst + c] = T(acc);
+    dst[(int64_t)blockIdx.y * r.ndst + c] = acc.value();
 }
 
 // Receiver rows (y, z) of one field per workgroup, grid-strided over the rows.
@@ -85,7 +86,7 @@ __global__ __launch_bounds__(kBlock) void k_remap(RemapArgs<T> r, const T *__res
 // order: (z, y) in raster order, then x.
 constexpr int kMaxQ = 16;
 
-template <typename T, bool KAHAN>
+template <typename T, int SM>
 __global__ __launch_bounds__(kBlock) void k_remap_rows(RemapArgs<T> r, const T *__restrict__ src,
                                                        T *__restrict__ dst) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -114,21 +115,23 @@ __global__ __launch_bounds__(kBlock) void k_remap_rows(RemapArgs<T> r, const T *
                 T v[kMaxQ];
 #pragma unroll
                 for (int q = 0; q < kMaxQ; ++q) v[q] = q < mq ? s[qoff[q] + xs] : T(0);
-                Acc<T, KAHAN> acc;
-                if (q0 > 0) acc.s = row[xs];   // continue the partial sum of earlier rows
+                using W = SumT<T, SM>;
+                FmaSum<T, SM> acc;
+                if (q0 > 0) acc.s = W(row[xs]);   // continue the partial sum of earlier rows
 #pragma unroll
                 for (int q = 0; q < kMaxQ; ++q)
-                    if (q < mq) acc.add(qw[q] * v[q]);
-                row[xs] = acc.s;
+                    if (q < mq) acc.add(W(qw[q]), W(v[q]));
+                row[xs] = acc.value();
             }
             __syncthreads();
         }
         T *__restrict__ out = dst + (int64_t)blockIdx.y * r.ndst + rr * r.nd[0];
         for (int xd = threadIdx.x; xd < r.nd[0]; xd += kBlock) {
             const int fx = r.first[0][xd], nx = r.cnt[0][xd], ox = r.off[0][xd];
-            Acc<T, KAHAN> acc;
-            for (int kx = 0; kx < nx; ++kx) acc.add(r.w[0][ox + kx] * row[fx + kx]);
-            out[xd] = acc.s;
+            using W = SumT<T, SM>;
+            FmaSum<T, SM> acc;
+            for (int kx = 0; kx < nx; ++kx) acc.add(W(r.w[0][ox + kx]), W(row[fx + kx]));
+            out[xd] = acc.value();
         }
         __syncthreads();   // the row buffer is reused by the next row
     }
@@ -152,10 +155,10 @@ constexpr int kMaxTerms = 4;   // (z, y) terms of a receiver row in the table: a
 
 template <typename T> using Vec4NT = T __attribute__((ext_vector_type(4)));
 
-template <typename T, bool KAHAN>
+template <typename T, int SM>
 __global__ __launch_bounds__(kBlock) void k_remap_tile(RemapArgs<T> r, const T *__restrict__ src,
                                                        T *__restrict__ dst, bool vec4) {
-    using W = SumT<T, KAHAN>;
+    using W = SumT<T, SM>;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     __shared__ int32_t toff[kTileRows][kMaxTerms];   // rx offset of each term of a receiver row
     __shared__ W tw[kTileRows][kMaxTerms];           // its weight wz * wy
@@ -226,15 +229,15 @@ __global__ __launch_bounds__(kBlock) void k_remap_tile(RemapArgs<T> r, const T *
         for (int q = 0; q < kMaxX; ++q) wx[q] = q < nx ? W(r.w[0][ox + q]) : W(0);
         for (int row = 0; row < nrows; ++row) {
             const T *sr = slab + (size_t)row * nsx + fx;
-            W acc = W(0);
+            FmaSum<T, SM> acc;
             if (nx <= kMaxX) {
 #pragma unroll
                 for (int q = 0; q < kMaxX; ++q)
-                    if (q < nx) acc = fma(wx[q], W(sr[q]), acc);
+                    if (q < nx) acc.add(wx[q], W(sr[q]));
             } else {
-                for (int kx = 0; kx < nx; ++kx) acc = fma(W(r.w[0][ox + kx]), W(sr[kx]), acc);
+                for (int kx = 0; kx < nx; ++kx) acc.add(W(r.w[0][ox + kx]), W(sr[kx]));
             }
-            rx[(size_t)row * ndx + xd] = T(acc);
+            rx[(size_t)row * ndx + xd] = acc.value();
         }
     }
     __syncthreads();
@@ -251,16 +254,16 @@ __global__ __launch_bounds__(kBlock) void k_remap_tile(RemapArgs<T> r, const T *
     while (tr < ntr) {
         const int xd = xw * Wd;
         const int n = tn[tr];
-        W acc[4] = {W(0), W(0), W(0), W(0)};
+        FmaSum<T, SM> acc[4];
         auto term = [&](W w, const T *p) {
             if (vec4) {
                 const Vec4NT<T> v = *reinterpret_cast<const Vec4NT<T> *>(p);
-                acc[0] = fma(w, W(v.x), acc[0]);
-                acc[1] = fma(w, W(v.y), acc[1]);
-                acc[2] = fma(w, W(v.z), acc[2]);
-                acc[3] = fma(w, W(v.w), acc[3]);
+                acc[0].add(w, W(v.x));
+                acc[1].add(w, W(v.y));
+                acc[2].add(w, W(v.z));
+                acc[3].add(w, W(v.w));
             } else {
-                acc[0] = fma(w, W(p[0]), acc[0]);
+                acc[0].add(w, W(p[0]));
             }
         };
         if (n <= kMaxTerms) {
@@ -275,10 +278,10 @@ __global__ __launch_bounds__(kBlock) void k_remap_tile(RemapArgs<T> r, const T *
         }
         T *o = out + orow[tr] + xd;
         if (vec4) {
-            const Vec4NT<T> v = {T(acc[0]), T(acc[1]), T(acc[2]), T(acc[3])};
+            const Vec4NT<T> v = {acc[0].value(), acc[1].value(), acc[2].value(), acc[3].value()};
             __builtin_nontemporal_store(v, reinterpret_cast<Vec4NT<T> *>(o));
         } else {
-            __builtin_nontemporal_store(T(acc[0]), o);
+            __builtin_nontemporal_store(acc[0].value(), o);
         }
         xw += dxw;
         int d = dtr;
@@ -391,7 +394,8 @@ extern "C" int couple_remap_init(const int32_t src_n[3], const double *src_nodes
     if (!out) return rfail(nullptr, COUPLE_EINVAL, "couple_remap_init: NULL output");
     *out = nullptr;
     if (!src_n || !src_nodes || !dst_n || !dst_nodes) return rfail(nullptr, COUPLE_EINVAL, "couple_remap_init: NULL grid");
-    if (!(precision == COUPLE_FP64 || precision == COUPLE_FP32_KAHAN || precision == COUPLE_FP32_NAIVE))
+    if (!(precision == COUPLE_FP64 || precision == COUPLE_FP32_WIDE || precision == COUPLE_FP32_NAIVE ||
+          precision == COUPLE_FP32_KAHAN))
         return rfail(nullptr, COUPLE_EINVAL, "couple_remap_init: unknown precision");
     std::string e = check_grid(src_n, src_nodes, "sender grid");
     if (e.empty()) e = check_grid(dst_n, dst_nodes, "receiver grid");
@@ -455,7 +459,7 @@ extern "C" int couple_remap_init(const int32_t src_n[3], const double *src_nodes
     return COUPLE_OK;
 }
 
-template <typename T, bool KAHAN>
+template <typename T, int SM>
 static hipError_t launch_remap(const couple_remap *r, const void *src, void *dst, int nfields, hipStream_t st) {
     RemapArgs<T> a;
     a.nsrc = a.ndst = 1;
@@ -475,27 +479,25 @@ static hipError_t launch_remap(const couple_remap *r, const void *src, void *dst
     bool tile_ok = r->tile_slab_rows > 0 && tile_lds <= kTileLdsBytes;
     if (tile_ok && tile_lds > 64 * 1024) {
         // more than 64 KB of dynamic LDS per workgroup must be allowed explicitly
-        tile_ok = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_remap_tile<T, KAHAN>),
+        tile_ok = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_remap_tile<T, SM>),
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)tile_lds) == hipSuccess;
         if (!tile_ok) (void)hipGetLastError();
     }
     if (tile_ok) {
         const int64_t ntile = (int64_t)((r->nd[1] + kTileJ - 1) / kTileJ) * ((r->nd[2] + kTileK - 1) / kTileK);
         const bool vec4 = r->nd[0] % 4 == 0 && reinterpret_cast<uintptr_t>(dst) % (4 * sizeof(T)) == 0;
-        hipLaunchKernelGGL((k_remap_tile<T, KAHAN>), dim3((unsigned)ntile, (unsigned)nfields), dim3(kBlock), tile_lds,
+        hipLaunchKernelGGL((k_remap_tile<T, SM>), dim3((unsigned)ntile, (unsigned)nfields), dim3(kBlock), tile_lds,
                            st, a, static_cast<const T *>(src), static_cast<T *>(dst), vec4);
     } else if (lds <= kRowLdsBytes) {
         // enough workgroups to fill the chip several times over, each looping
         // over rows (a row is a small amount of work when the receiver is finer)
-        // enough workgroups to fill the chip several times over, each looping
-        // over rows (a row is a small amount of work when the receiver is finer)
         const int64_t nrow = (int64_t)r->nd[1] * r->nd[2];
         const int64_t per_field = std::max<int64_t>(1, std::min<int64_t>(nrow, 8192 / nfields + 1));
-        hipLaunchKernelGGL((k_remap_rows<T, KAHAN>), dim3((unsigned)per_field, (unsigned)nfields), dim3(kBlock), lds,
+        hipLaunchKernelGGL((k_remap_rows<T, SM>), dim3((unsigned)per_field, (unsigned)nfields), dim3(kBlock), lds,
                            st, a, static_cast<const T *>(src), static_cast<T *>(dst));
     } else {
         const int64_t nblk = (a.ndst + kBlock - 1) / kBlock;
-        hipLaunchKernelGGL((k_remap<T, KAHAN>), dim3((unsigned)nblk, (unsigned)nfields), dim3(kBlock), 0, st, a,
+        hipLaunchKernelGGL((k_remap<T, SM>), dim3((unsigned)nblk, (unsigned)nfields), dim3(kBlock), 0, st, a,
                            static_cast<const T *>(src), static_cast<T *>(dst));
     }
     return hipGetLastError();
@@ -513,9 +515,10 @@ extern "C" int couple_remap_apply(couple_remap *r, const void *src, void *dst, i
     (void)hipGetLastError();
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipError_t e;
-    if (r->precision == COUPLE_FP64) e = launch_remap<double, false>(r, src, dst, nfields, st);
-    else if (r->precision == COUPLE_FP32_KAHAN) e = launch_remap<float, true>(r, src, dst, nfields, st);
-    else e = launch_remap<float, false>(r, src, dst, nfields, st);
+    if (r->precision == COUPLE_FP64) e = launch_remap<double, kSumPlain>(r, src, dst, nfields, st);
+    else if (r->precision == COUPLE_FP32_WIDE) e = launch_remap<float, kSumWide>(r, src, dst, nfields, st);
+    else if (r->precision == COUPLE_FP32_KAHAN) e = launch_remap<float, kSumKahan>(r, src, dst, nfields, st);
+    else e = launch_remap<float, kSumPlain>(r, src, dst, nfields, st);
     if (e != hipSuccess) return rfail(r, COUPLE_EHIP, std::string("couple_remap_apply: launch failed: ") + hipGetErrorString(e));
     return COUPLE_OK;
 }

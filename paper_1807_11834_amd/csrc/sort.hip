@@ -330,6 +330,17 @@ hipError_t launch_bin_sort(const T *pos, const T *diam, int64_t n, const Geo<T> 
     return hipGetLastError();
 }
 
+hipError_t launch_stable_partition(const uint32_t *keys, int64_t n, int bits, const SortScratch &s, uint32_t *keys_out,
+                                   uint32_t *ids_out, hipStream_t st) {
+    if (n <= 0) return hipGetLastError();
+    const int ntile = sort_tiles(n);
+    hipLaunchKernelGGL(k_radix_hist, dim3(ntile), dim3(kBlock), 0, st, keys, n, 0, bits, s.hist, ntile);
+    hipLaunchKernelGGL(k_radix_prefix, dim3(1 << bits), dim3(kBlock), 0, st, s.hist, ntile, s.totals);
+    hipLaunchKernelGGL(k_radix_scatter<true>, dim3(ntile), dim3(kBlock), 0, st, keys, (const uint32_t *)nullptr, n, 0,
+                       bits, s.hist, s.totals, ntile, keys_out, ids_out);
+    return hipGetLastError();
+}
+
 template hipError_t launch_bin_sort<float>(const float *, const float *, int64_t, const Geo<float> &, int32_t *,
                                            vec4<float> *, int32_t *, int32_t *, int32_t *, const SortScratch &,
                                            double *, const uint32_t **, Marker *, hipStream_t);

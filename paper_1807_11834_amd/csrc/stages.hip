@@ -132,17 +132,19 @@ __device__ __forceinline__ void sample_particles(const int64_t (&idx)[KB], const
 // Restriction fine -> bulk
 // ---------------------------------------------------------------------------
 // Sums of the r^3 fine children, per fine child plane and then the planes in
-// order.  The compensated FP32 mode widens the FP32 children to FP64 and sums
-// them there: with at most 64 terms the sum is within 64 FP64 roundings of
-// exact, so its FP32 rounding is the correctly rounded average in all but rare
-// ties, and the FP32 residue lo = S - hi carries the rest of the pressure for
-// the gradient (a per-plane Kahan sum recombined over the planes keeps only
-// part of it); one convert and one FP64 add per child instead of Kahan's four
-// instructions.  The FP64 and naive FP32 modes sum plainly in their own type.
-template <typename T, bool KAHAN> struct ChildSum {
-    static constexpr bool kWide = std::is_same<T, float>::value && KAHAN;
+// order, under the step's sum mode.  Kahan (FP32): each plane is a Kahan sum and
+// the planes are combined as s_0, -c_0, s_1, -c_1, ... in a Kahan sum; the
+// average's residue lo = -c / r^3 carries the rest of the pressure for the
+// gradient.  Wide (FP32 storage): the children are widened to FP64 and summed
+// there; with at most 64 terms the sum is within 64 FP64 roundings of exact, so
+// its FP32 rounding is the correctly rounded average in all but rare ties, and
+// the FP32 residue lo = S - hi carries the rest of the pressure; one convert and
+// one FP64 add per child instead of Kahan's four instructions.  Plain: the FP64
+// mode and naive FP32 sum in their own type.
+template <typename T, int SM> struct ChildSum {
+    static constexpr bool kWide = std::is_same<T, float>::value && SM == kSumWide;
     using W = typename std::conditional<kWide, double, T>::type;
-    static constexpr bool kComp = KAHAN && !kWide;   // Kahan in T
+    static constexpr bool kComp = SM == kSumKahan;   // Kahan in T
     Acc<W, kComp> acc;
     __device__ __forceinline__ void add(T v) { acc.add(W(v)); }
     // a plane's sum (s, with its compensation c) added to the cell's
@@ -159,7 +161,10 @@ template <typename T, bool KAHAN> struct ChildSum {
     }
 };
 
-template <typename T, int R, bool KAHAN>
+// Fields F0 .. F1 - 1 of (u, v, w, p): all four for the bulk, given and learned
+// velocity sources, the pressure alone beside the brick kernel (which restricts
+// u, v, w).
+template <typename T, int R, int SM, int F0, int F1>
 __global__ __launch_bounds__(kBlock) void k_restrict(StepArgs<T> a) {
     const Geo<T> &g = a.g;
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -171,7 +176,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict(StepArgs<T> a) {
         const int64_t base = (int64_t)R * cz * nfxy + (int64_t)R * cy * nfx + (int64_t)R * cx;
         const T inv = T(1) / T(R * R * R);
 #pragma unroll
-        for (int f = 0; f < 4; ++f) {
+        for (int f = F0; f < F1; ++f) {
             const T *__restrict__ q = a.fine[f] + base;
             Row<T, R> rows[R][R];
 #pragma unroll
@@ -180,10 +185,10 @@ __global__ __launch_bounds__(kBlock) void k_restrict(StepArgs<T> a) {
                 for (int ly = 0; ly < R; ++ly) rows[lz][ly] = load_row<T, R>(q + lz * nfxy + ly * nfx);
             // per fine child plane, then the planes in order (with a Kahan sum,
             // s_0, -c_0, s_1, ...): the same sums as the brick-tiled kernel
-            ChildSum<T, KAHAN> acc;
+            ChildSum<T, SM> acc;
 #pragma unroll
             for (int lz = 0; lz < R; ++lz) {
-                ChildSum<T, KAHAN> plane;
+                ChildSum<T, SM> plane;
 #pragma unroll
                 for (int ly = 0; ly < R; ++ly)
 #pragma unroll
@@ -206,7 +211,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict(StepArgs<T> a) {
 // Restriction of the liquid volume fraction (two-fluid drag): the bulk alpha is
 // the average of the r^3 fine children (the volume average that defines alpha),
 // summed per fine child plane and then the planes in order, as for U and P.
-template <typename T, int R, bool KAHAN>
+template <typename T, int R, int SM>
 __global__ __launch_bounds__(kBlock) void k_restrict_alpha(StepArgs<T> a) {
     const Geo<T> &g = a.g;
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -221,10 +226,10 @@ __global__ __launch_bounds__(kBlock) void k_restrict_alpha(StepArgs<T> a) {
     for (int lz = 0; lz < R; ++lz)
 #pragma unroll
         for (int ly = 0; ly < R; ++ly) rows[lz][ly] = load_row<T, R>(q + lz * nfxy + ly * nfx);
-    ChildSum<T, KAHAN> acc;
+    ChildSum<T, SM> acc;
 #pragma unroll
     for (int lz = 0; lz < R; ++lz) {
-        ChildSum<T, KAHAN> plane;
+        ChildSum<T, SM> plane;
 #pragma unroll
         for (int ly = 0; ly < R; ++ly)
 #pragma unroll
@@ -286,197 +291,214 @@ __device__ __forceinline__ T trilin_alpha8(const T *__restrict__ alpha8, const A
     return sz * c0 + az.t * c1;
 }
 
-// Restriction with the fine-grid lookup, tiled in bricks of 8 x 4 x 2 bulk
-// cells, one 256-thread workgroup per brick: four neighbouring threads share a
-// cell, one per fine child plane (z).  Each thread loads its plane's r x r rows
-// of u, v, w, p, keeps u, v, w in LDS and sums its plane (compensated); the
-// four plane sums are combined in order through cross-lane reads.  The brick's
-// particles (8 rows of up to 8 cells, contiguous in the sorted order, flattened
-// over the workgroup) take their trilinear fine velocity from LDS when all
-// eight fine nodes lie in the brick (from global memory when the stencil
-// crosses a brick face) and their void fraction from a haloed copy of phi in
-// LDS.  The brick is 8r fine cells wide along x (one 128-byte line per row for
-// r = 4 in FP32).
+// Restriction of the velocity with the fine-grid lookup, tiled in bricks of
+// 8 x 4 x 2 bulk cells.  Filling a brick: 256 threads, four per cell (one per
+// fine child plane z), each loads its plane's r x r rows of u, v, w, stores them
+// in LDS and sums its plane (compensated); the four plane sums are combined in
+// order through cross-lane reads (the pressure is restricted by k_restrict
+// before this kernel).  The brick's particles (8 rows of up to 8 cells,
+// contiguous in the sorted order, flattened over the threads) then take their
+// trilinear fine velocity from LDS when all eight fine nodes lie in the brick
+// (from global memory when the stencil crosses a brick face) and their void
+// fraction from a haloed copy of phi in LDS.  The brick is 8r fine cells wide
+// along x (one 128-byte line per row for r = 4 in FP32).
+// One workgroup per brick: fill, then the particles.
 constexpr int kBrickX = 8, kBrickY = 4, kBrickZ = 2;
 constexpr int kBrickThreads = 4 * kBrickX * kBrickY * kBrickZ;
+constexpr int kBrickRows = kBrickY * kBrickZ;                                     // particle rows of a brick
+constexpr int kBrickHalo = (kBrickX + 2) * (kBrickY + 2) * (kBrickZ + 2);         // phi with a one-cell halo
 
-template <typename T, int R, bool KAHAN>
-__global__ __launch_bounds__(kBrickThreads) void k_restrict_brick(StepArgs<T> a) {
-    constexpr int FX = kBrickX * R, FY = kBrickY * R, FZ = kBrickZ * R;
-    constexpr int HX = kBrickX + 2, HY = kBrickY + 2, HZ = kBrickZ + 2;   // bulk cells with a one-cell halo
-    constexpr int NROW = kBrickY * kBrickZ;
-    constexpr int NT = kBrickThreads;
-    static_assert(R <= 4, "one thread per fine child plane");
-    __shared__ T sv[3][FZ][FY][FX];
-    __shared__ T sphi[HZ][HY][HX];
-    __shared__ int32_t srow[NROW + 1];    // particle-segment prefix over the brick's rows
-    __shared__ int32_t sbeg[NROW];
+template <typename T, int R> struct BrickLds {
+    T sv[3][kBrickZ * R][kBrickY * R][kBrickX * R];
+    T sphi[kBrickZ + 2][kBrickY + 2][kBrickX + 2];
+    int32_t cnt[kBrickRows];   // particles of each row
+    int32_t beg[kBrickRows];   // first sorted position of each row
+};
+
+template <typename T> struct BrickGrid {
+    int bnx, bny;
+    __device__ __forceinline__ void origin(int64_t brick, int &ox, int &oy, int &oz) const {
+        ox = (int)(brick % bnx) * kBrickX;
+        oy = (int)((brick / bnx) % bny) * kBrickY;
+        oz = (int)(brick / ((int64_t)bnx * bny)) * kBrickZ;
+    }
+};
+
+// Fill the brick at (ox, oy, oz) into L and write its U; thread t in [0, 256).
+template <typename T, int R, int SM>
+__device__ __forceinline__ void brick_fill(const StepArgs<T> &a, BrickLds<T, R> &L, int t, int ox, int oy, int oz) {
+    constexpr int HX = kBrickX + 2, HY = kBrickY + 2;
     const Geo<T> &g = a.g;
-    const int bnx = (g.nb[0] + kBrickX - 1) / kBrickX, bny = (g.nb[1] + kBrickY - 1) / kBrickY;
-    const int64_t brick = xcd_tile(blockIdx.x, gridDim.x);
-    const int ox = (int)(brick % bnx) * kBrickX, oy = (int)((brick / bnx) % bny) * kBrickY,
-              oz = (int)(brick / ((int64_t)bnx * bny)) * kBrickZ;
-    const int tid = threadIdx.x, lane = tid % kWave;
-    const int cl = tid >> 2, rz = tid & 3;   // cell of the brick, fine child plane
+    const int lane = t % kWave;
+    const int cl = t >> 2, rz = t & 3;   // cell of the brick, fine child plane
     const int lx = cl % kBrickX, ly = (cl / kBrickX) % kBrickY, lz = cl / (kBrickX * kBrickY);
     const int cx = ox + lx, cy = oy + ly, cz = oz + lz;
     const bool inside = cx < g.nb[0] && cy < g.nb[1] && cz < g.nb[2];
     const int64_t nx = g.nb[0], nxy = (int64_t)g.nb[0] * g.nb[1];
     const int64_t nfx = g.nf[0], nfxy = (int64_t)g.nf[0] * g.nf[1];
     // the brick's particle rows and phi with its halo (indices clamped at the walls)
-    const int wx = (ox + kBrickX < g.nb[0]) ? kBrickX : g.nb[0] - ox;
-    if (tid < NROW) {
-        const int ry = oy + tid % kBrickY, rzz = oz + tid / kBrickY;
-        int32_t b0 = 0, cnt = 0;
+    if (t < kBrickRows) {
+        const int wx = (ox + kBrickX < g.nb[0]) ? kBrickX : g.nb[0] - ox;
+        const int ry = oy + t % kBrickY, rzz = oz + t / kBrickY;
+        int32_t b0 = 0, c = 0;
         if (ry < g.nb[1] && rzz < g.nb[2]) {
             const int64_t c0 = ox + nx * ry + nxy * rzz;
             b0 = seg_clamp(a.start[c0], a.n);
-            cnt = seg_clamp(a.start[c0 + wx], a.n) - b0;
+            c = seg_clamp(a.start[c0 + wx], a.n) - b0;
         }
-        sbeg[tid] = b0;
-        srow[tid + 1] = cnt;
+        L.beg[t] = b0;
+        L.cnt[t] = c;
     }
-    for (int e = tid; e < HX * HY * HZ; e += NT) {
-        const int hx = e % HX, hy = (e / HX) % HY, hz = e / (HX * HY);
+    if (t < kBrickHalo) {
+        const int hx = t % HX, hy = (t / HX) % HY, hz = t / (HX * HY);
         const int gx = clampi(ox - 1 + hx, g.nb[0]), gy = clampi(oy - 1 + hy, g.nb[1]), gz = clampi(oz - 1 + hz, g.nb[2]);
-        sphi[hz][hy][hx] = a.phi[gx + nx * gy + nxy * gz];
+        L.sphi[hz][hy][hx] = a.phi[gx + nx * gy + nxy * gz];
     }
     const bool work = inside && rz < R;
     const int64_t base = ((int64_t)R * cz + rz) * nfxy + (int64_t)R * cy * nfx + (int64_t)R * cx;
     const T inv = T(1) / T(R * R * R);
+    Row<T, R> rows[3][R];
+    if (work) {
 #pragma unroll
-    for (int f = 0; f < 4; ++f) {
-        ChildSum<T, KAHAN> plane;
+        for (int f = 0; f < 3; ++f)
+#pragma unroll
+            for (int ry = 0; ry < R; ++ry) rows[f][ry] = load_row<T, R>(a.fine[f] + base + ry * nfx);
+    }
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        ChildSum<T, SM> plane;
         if (work) {
-            const T *__restrict__ q = a.fine[f] + base;
-            Row<T, R> rows[R];
-#pragma unroll
-            for (int ry = 0; ry < R; ++ry) rows[ry] = load_row<T, R>(q + ry * nfx);
 #pragma unroll
             for (int ry = 0; ry < R; ++ry)
 #pragma unroll
-                for (int rx = 0; rx < R; ++rx) plane.add(rows[ry].v[rx]);
-            if (f < 3) {
+                for (int rx = 0; rx < R; ++rx) plane.add(rows[f][ry].v[rx]);
 #pragma unroll
-                for (int ry = 0; ry < R; ++ry)
+            for (int ry = 0; ry < R; ++ry)
 #pragma unroll
-                    for (int rx = 0; rx < R; ++rx) sv[f][lz * R + rz][ly * R + ry][lx * R + rx] = rows[ry].v[rx];
-            }
+                for (int rx = 0; rx < R; ++rx) L.sv[f][lz * R + rz][ly * R + ry][lx * R + rx] = rows[f][ry].v[rx];
         }
         // the planes of this cell in order (with a Kahan sum, s_0, -c_0, s_1,
         // ...), read from the cell's four lanes; the plane-0 lane writes the
         // average
-        ChildSum<T, KAHAN> acc;
+        ChildSum<T, SM> acc;
         const int l0 = lane & ~3;
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             const auto sk = __shfl(plane.acc.s, l0 + k, kWave);
-            const auto ck = ChildSum<T, KAHAN>::kComp ? __shfl(plane.acc.c, l0 + k, kWave) : plane.acc.c;
+            const auto ck = ChildSum<T, SM>::kComp ? __shfl(plane.acc.c, l0 + k, kWave) : plane.acc.c;
             acc.add_plane(sk, ck);
         }
-        if (inside && rz == 0) {
-            const int64_t c = cx + nx * cy + nxy * cz;
-            const T val = acc.hi(inv);
-            if (f < 3) {
-                a.U[f * g.ncell + c] = val;
-            } else {
-                a.P[c] = val;
-                // keep the rest of the average so that the pressure gradient can
-                // difference (hi + lo) instead of the rounded hi
-                a.Plo[c] = acc.lo(inv);
-            }
-        }
+        if (inside && rz == 0) a.U[f * g.ncell + (cx + nx * cy + nxy * cz)] = acc.hi(inv);
     }
-    __syncthreads();
-    if (tid == 0) {
-        srow[0] = 0;
-        for (int r = 0; r < NROW; ++r) srow[r + 1] += srow[r];
-    }
-    __syncthreads();
-    const int total = srow[NROW];
+}
+
+// The particles of the filled brick at (ox, oy, oz): thread t of nt.
+template <typename T, int R>
+__device__ __forceinline__ void brick_particles(const StepArgs<T> &a, const BrickLds<T, R> &L, int t, int nt, int ox,
+                                                int oy, int oz) {
+    constexpr int FX = kBrickX * R, FY = kBrickY * R, FZ = kBrickZ * R;
+    const Geo<T> &g = a.g;
+    int32_t pre[kBrickRows + 1];   // particles before each row
+    pre[0] = 0;
+#pragma unroll
+    for (int r = 0; r < kBrickRows; ++r) pre[r + 1] = pre[r] + L.cnt[r];
+    const int total = pre[kBrickRows];
     const int fx0 = ox * R, fy0 = oy * R, fz0 = oz * R;
     // up to kPB particles per thread at a time: their loads are issued together
     constexpr int kPB = 2;
-    for (int j0 = tid; j0 < total; j0 += kPB * NT) {
+    for (int j0 = t; j0 < total; j0 += kPB * nt) {
         vec4<T> qs[kPB];
         int64_t ps[kPB];
 #pragma unroll
         for (int k = 0; k < kPB; ++k) {
-            const int j = j0 + k * NT;
-            int64_t i = sbeg[0];
+            const int j = j0 + k * nt;
+            int64_t i = L.beg[0];
             if (j < total) {
                 int r = 0;
-                while (r + 1 < NROW && srow[r + 1] <= j) ++r;
-                i = sbeg[r] + (j - srow[r]);
+#pragma unroll
+                for (int q = 1; q < kBrickRows; ++q) r += (pre[q] <= j) ? 1 : 0;
+                i = L.beg[r] + (j - pre[r]);
             }
             qs[k] = a.sp[i];
             ps[k] = a.perm[i];
         }
 #pragma unroll
         for (int k = 0; k < kPB; ++k) {
-        if (j0 + k * NT >= total) break;
-        const vec4<T> q = qs[k];
-        int64_t p = ps[k];
-        if (p < 0 || p >= a.n) p = 0;   // perm is a permutation of [0, n)
-        vec4<T> s;
-        // fine trilinear velocity: from LDS when the eight nodes lie in the brick
-        const Axis<T> ax = cic_axis(q.x, g.sf[0], g.nf[0]);
-        const Axis<T> ay = cic_axis(q.y, g.sf[1], g.nf[1]);
-        const Axis<T> az = cic_axis(q.z, g.sf[2], g.nf[2]);
-        const int xl = ax.lo - fx0, xh = ax.hi - fx0, yl = ay.lo - fy0, yh = ay.hi - fy0, zl = az.lo - fz0,
-                  zh = az.hi - fz0;
-        if (xl >= 0 && xh < FX && yl >= 0 && yh < FY && zl >= 0 && zh < FZ) {
-            const T sx = T(1) - ax.t, sy = T(1) - ay.t, sz = T(1) - az.t;
-            T u[3];
+            if (j0 + k * nt >= total) break;
+            const vec4<T> q = qs[k];
+            int64_t p = ps[k];
+            if (p < 0 || p >= a.n) p = 0;   // perm is a permutation of [0, n)
+            vec4<T> s;
+            // fine trilinear velocity: from LDS when the eight nodes lie in the brick
+            const Axis<T> ax = cic_axis(q.x, g.sf[0], g.nf[0]);
+            const Axis<T> ay = cic_axis(q.y, g.sf[1], g.nf[1]);
+            const Axis<T> az = cic_axis(q.z, g.sf[2], g.nf[2]);
+            const int xl = ax.lo - fx0, xh = ax.hi - fx0, yl = ay.lo - fy0, yh = ay.hi - fy0, zl = az.lo - fz0,
+                      zh = az.hi - fz0;
+            if (xl >= 0 && xh < FX && yl >= 0 && yh < FY && zl >= 0 && zh < FZ) {
+                const T sx = T(1) - ax.t, sy = T(1) - ay.t, sz = T(1) - az.t;
+                T u[3];
 #pragma unroll
-            for (int f = 0; f < 3; ++f) {
-                const T e0 = sy * (sx * sv[f][zl][yl][xl] + ax.t * sv[f][zl][yl][xh]) +
-                             ay.t * (sx * sv[f][zl][yh][xl] + ax.t * sv[f][zl][yh][xh]);
-                const T e1 = sy * (sx * sv[f][zh][yl][xl] + ax.t * sv[f][zh][yl][xh]) +
-                             ay.t * (sx * sv[f][zh][yh][xl] + ax.t * sv[f][zh][yh][xh]);
-                u[f] = sz * e0 + az.t * e1;
-            }
-            s.x = u[0];
-            s.y = u[1];
-            s.z = u[2];
-        } else {
-            fine_velocity(q, a, s.x, s.y, s.z);
-        }
-        // void fraction at the particle from the haloed phi (its stencil is the
-        // containing cell and a neighbour, always inside the halo)
-        if (a.cic) {
-            const Axis<T> bx = cic_axis(q.x, g.sb[0], g.nb[0]);
-            const Axis<T> by = cic_axis(q.y, g.sb[1], g.nb[1]);
-            const Axis<T> bz = cic_axis(q.z, g.sb[2], g.nb[2]);
-            const int hxl = bx.lo - ox + 1, hxh = bx.hi - ox + 1, hyl = by.lo - oy + 1, hyh = by.hi - oy + 1,
-                      hzl = bz.lo - oz + 1, hzh = bz.hi - oz + 1;
-            const T f000 = sphi[hzl][hyl][hxl], f001 = sphi[hzl][hyl][hxh], f010 = sphi[hzl][hyh][hxl],
-                    f011 = sphi[hzl][hyh][hxh], f100 = sphi[hzh][hyl][hxl], f101 = sphi[hzh][hyl][hxh],
-                    f110 = sphi[hzh][hyh][hxl], f111 = sphi[hzh][hyh][hxh];
-            const T sx = T(1) - bx.t, sy = T(1) - by.t, sz = T(1) - bz.t;
-            const T phi_p = sz * (sy * (sx * f000 + bx.t * f001) + by.t * (sx * f010 + bx.t * f011)) +
-                            bz.t * (sy * (sx * f100 + bx.t * f101) + by.t * (sx * f110 + bx.t * f111));
-            if (std::is_same<T, float>::value && phi_p > (T)a.phi_fp64) {
-                // FP64 weights from the same positions; the cancellation in 1 - phi is exact
-                const double gx = (double)q.x * (double)g.sb[0] - 0.5, gy = (double)q.y * (double)g.sb[1] - 0.5,
-                             gz = (double)q.z * (double)g.sb[2] - 0.5;
-                const double tx = gx - floor(gx), ty = gy - floor(gy), tz = gz - floor(gz);
-                const double ux = 1.0 - tx, uy = 1.0 - ty, uz = 1.0 - tz;
-                const double ph =
-                    uz * (uy * (ux * (double)f000 + tx * (double)f001) + ty * (ux * (double)f010 + tx * (double)f011)) +
-                    tz * (uy * (ux * (double)f100 + tx * (double)f101) + ty * (ux * (double)f110 + tx * (double)f111));
-                s.w = (T)(1.0 - ph);
+                for (int f = 0; f < 3; ++f) {
+                    const T e0 = sy * (sx * L.sv[f][zl][yl][xl] + ax.t * L.sv[f][zl][yl][xh]) +
+                                 ay.t * (sx * L.sv[f][zl][yh][xl] + ax.t * L.sv[f][zl][yh][xh]);
+                    const T e1 = sy * (sx * L.sv[f][zh][yl][xl] + ax.t * L.sv[f][zh][yl][xh]) +
+                                 ay.t * (sx * L.sv[f][zh][yh][xl] + ax.t * L.sv[f][zh][yh][xh]);
+                    u[f] = sz * e0 + az.t * e1;
+                }
+                s.x = u[0];
+                s.y = u[1];
+                s.z = u[2];
             } else {
-                s.w = T(1) - phi_p;
+                fine_velocity(q, a, s.x, s.y, s.z);
             }
-        } else {
-            const int ix = cell_axis(q.x, g.sb[0], g.nb[0]), iy = cell_axis(q.y, g.sb[1], g.nb[1]),
-                      iz = cell_axis(q.z, g.sb[2], g.nb[2]);
-            s.w = T(1) - sphi[iz - oz + 1][iy - oy + 1][ix - ox + 1];
-        }
-        a.uf4[p] = s;
+            // void fraction at the particle from the haloed phi (its stencil is the
+            // containing cell and a neighbour, always inside the halo)
+            if (a.cic) {
+                const Axis<T> bx = cic_axis(q.x, g.sb[0], g.nb[0]);
+                const Axis<T> by = cic_axis(q.y, g.sb[1], g.nb[1]);
+                const Axis<T> bz = cic_axis(q.z, g.sb[2], g.nb[2]);
+                const int hxl = bx.lo - ox + 1, hxh = bx.hi - ox + 1, hyl = by.lo - oy + 1, hyh = by.hi - oy + 1,
+                          hzl = bz.lo - oz + 1, hzh = bz.hi - oz + 1;
+                const T f000 = L.sphi[hzl][hyl][hxl], f001 = L.sphi[hzl][hyl][hxh], f010 = L.sphi[hzl][hyh][hxl],
+                        f011 = L.sphi[hzl][hyh][hxh], f100 = L.sphi[hzh][hyl][hxl], f101 = L.sphi[hzh][hyl][hxh],
+                        f110 = L.sphi[hzh][hyh][hxl], f111 = L.sphi[hzh][hyh][hxh];
+                const T sx = T(1) - bx.t, sy = T(1) - by.t, sz = T(1) - bz.t;
+                const T phi_p = sz * (sy * (sx * f000 + bx.t * f001) + by.t * (sx * f010 + bx.t * f011)) +
+                                bz.t * (sy * (sx * f100 + bx.t * f101) + by.t * (sx * f110 + bx.t * f111));
+                if (std::is_same<T, float>::value && phi_p > (T)a.phi_fp64) {
+                    // FP64 weights from the same positions; the cancellation in 1 - phi is exact
+                    const double gx = (double)q.x * (double)g.sb[0] - 0.5, gy = (double)q.y * (double)g.sb[1] - 0.5,
+                                 gz = (double)q.z * (double)g.sb[2] - 0.5;
+                    const double tx = gx - floor(gx), ty = gy - floor(gy), tz = gz - floor(gz);
+                    const double ux = 1.0 - tx, uy = 1.0 - ty, uz = 1.0 - tz;
+                    const double ph =
+                        uz * (uy * (ux * (double)f000 + tx * (double)f001) + ty * (ux * (double)f010 + tx * (double)f011)) +
+                        tz * (uy * (ux * (double)f100 + tx * (double)f101) + ty * (ux * (double)f110 + tx * (double)f111));
+                    s.w = (T)(1.0 - ph);
+                } else {
+                    s.w = T(1) - phi_p;
+                }
+            } else {
+                const int ix = cell_axis(q.x, g.sb[0], g.nb[0]), iy = cell_axis(q.y, g.sb[1], g.nb[1]),
+                          iz = cell_axis(q.z, g.sb[2], g.nb[2]);
+                s.w = T(1) - L.sphi[iz - oz + 1][iy - oy + 1][ix - ox + 1];
+            }
+            a.uf4[p] = s;
         }
     }
+}
+
+template <typename T, int R, int SM>
+__global__ __launch_bounds__(kBrickThreads) void k_restrict_brick(StepArgs<T> a, BrickGrid<T> bg) {
+    static_assert(R <= 4, "one thread per fine child plane");
+    static_assert(kBrickHalo <= kBrickThreads, "one halo value per thread");
+    __shared__ BrickLds<T, R> L;
+    int ox, oy, oz;
+    bg.origin(xcd_tile(blockIdx.x, gridDim.x), ox, oy, oz);
+    brick_fill<T, R, SM>(a, L, threadIdx.x, ox, oy, oz);
+    __syncthreads();
+    brick_particles<T, R>(a, L, threadIdx.x, kBrickThreads, ox, oy, oz);
 }
 
 template <typename T, int R> int64_t brick_blocks(const Geo<T> &g) {
@@ -628,14 +650,15 @@ __device__ __forceinline__ T wsum3(int l, T a0, T a1, T a2) {
     return s;
 }
 
-// The four bulk fields a prolongation launch transfers, their fine outputs and
-// the diagnostic slots of their fine sums; field 0 is optionally complemented
-// (the solid fraction phi is prolonged as the porosity 1 - phi).
+// The bulk fields a prolongation launch transfers (nf <= 4), their fine outputs
+// and the diagnostic slots of their fine sums; field 0 is optionally
+// complemented (the solid fraction phi is prolonged as the porosity 1 - phi).
 template <typename T> struct ProlongSet {
     const T *B[4];
     T *out[4];
     int slot[4];
     int complement0;
+    int nf;
 };
 
 template <typename T, int R>
@@ -645,6 +668,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong(StepArgs<T> a, ProlongSet<T>
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t c = tile * kBlock + threadIdx.x;
     double sums[4] = {0.0, 0.0, 0.0, 0.0};
+    const bool counted = c >= a.own_c0 && c < a.own_c1;   // owned cells enter the fine-grid sums
     if (c < g.ncell) {
         int cx, cy, cz;
         decode_cell(c, g.nb, cx, cy, cz);
@@ -656,6 +680,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong(StepArgs<T> a, ProlongSet<T>
         const int64_t fbase = (int64_t)R * cz * nfxy + (int64_t)R * cy * nfx + (int64_t)R * cx;
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
+            if (f >= fs.nf) break;   // uniform over the launch
             const T *__restrict__ B = fs.B[f];
             T *__restrict__ out = fs.out[f];
             T b[3][3][3];
@@ -714,10 +739,11 @@ __global__ __launch_bounds__(kBlock) void k_prolong(StepArgs<T> a, ProlongSet<T>
                     }
                     store_row<T, R>(out + fbase + lz * nfxy + ly * nfx, o);
                 }
-            sums[f] = s;
+            sums[f] = counted ? s : 0.0;
         }
     }
     for (int k = 0; k < 4; ++k) {
+        if (k >= fs.nf) break;
         double t = block_sum(sums[k], red);
         if (threadIdx.x == 0) a.part[fs.slot[k] * a.part_stride + blockIdx.x] = t;
     }
@@ -765,18 +791,26 @@ __global__ __launch_bounds__(kWave) void k_diag2(const double *__restrict__ part
 // ---------------------------------------------------------------------------
 // Host dispatch
 // ---------------------------------------------------------------------------
-template <typename T, int R, bool KAHAN>
-static void launch_grid_stages(const StepArgs<T> &a, hipStream_t st) {
+template <typename T, int R, int SM>
+static void launch_grid_stages(const StepArgs<T> &a, hipStream_t st, int phases) {
     const int64_t cb = (a.g.ncell + kBlock - 1) / kBlock;
     const int64_t pb = (a.n + kBlock - 1) / kBlock;
+    const int64_t nc = a.g.ncell, nf = a.g.nfine;
+    const ProlongSet<T> eps{{a.phi, nullptr, nullptr, nullptr}, {a.fine_eps, nullptr, nullptr, nullptr},
+                            {SL_EPSF, 0, 0, 0}, 1, 1};
+    if (phases & kPhaseVelocity) {
     if (a.vel_source == 0) {
+        // the pressure (for the gradient only), then u, v, w with the lookup
+        a.mk->mark("restrict_p", st);
+        hipLaunchKernelGGL((k_restrict<T, R, SM, 3, 4>), dim3(cb), dim3(kBlock), 0, st, a);
         a.mk->mark("restrict_lookup", st);
-        hipLaunchKernelGGL((k_restrict_brick<T, R, KAHAN>), dim3((unsigned)brick_blocks<T, R>(a.g)),
-                           dim3(kBrickThreads), 0, st, a);
+        const int64_t nbk = brick_blocks<T, R>(a.g);
+        const BrickGrid<T> bg{(a.g.nb[0] + kBrickX - 1) / kBrickX, (a.g.nb[1] + kBrickY - 1) / kBrickY};
+        hipLaunchKernelGGL((k_restrict_brick<T, R, SM>), dim3((unsigned)nbk), dim3(kBrickThreads), 0, st, a, bg);
     } else if (a.vel_source == 3) {
         if constexpr (std::is_same<T, float>::value) {
             a.mk->mark("restrict", st);
-            hipLaunchKernelGGL((k_restrict<T, R, KAHAN>), dim3(cb), dim3(kBlock), 0, st, a);
+            hipLaunchKernelGGL((k_restrict<T, R, SM, 0, 4>), dim3(cb), dim3(kBlock), 0, st, a);
             a.mk->mark("mlp_pack", st);
             launch_mlp_pack(a, st);
             if (a.n > 0) {
@@ -788,53 +822,59 @@ static void launch_grid_stages(const StepArgs<T> &a, hipStream_t st) {
         }
     } else {
         a.mk->mark("restrict", st);
-        hipLaunchKernelGGL((k_restrict<T, R, KAHAN>), dim3(cb), dim3(kBlock), 0, st, a);
+        hipLaunchKernelGGL((k_restrict<T, R, SM, 0, 4>), dim3(cb), dim3(kBlock), 0, st, a);
         if (a.n > 0) a.mk->mark("sample", st);
         if (a.n > 0) hipLaunchKernelGGL(k_sample<T>, dim3(pb), dim3(kBlock), 0, st, a);
     }
     if (a.vof) {
         a.mk->mark("restrict_alpha", st);
-        hipLaunchKernelGGL((k_restrict_alpha<T, R, KAHAN>), dim3(cb), dim3(kBlock), 0, st, a);
+        hipLaunchKernelGGL((k_restrict_alpha<T, R, SM>), dim3(cb), dim3(kBlock), 0, st, a);
         if (a.n > 0) a.mk->mark("pack_alpha", st);
         if (a.n > 0) hipLaunchKernelGGL(k_pack_alpha8<T>, dim3(cb), dim3(kBlock), 0, st, a);
     }
     if (a.n > 0) a.mk->mark("drag", st);
     if (a.n > 0) hipLaunchKernelGGL(k_drag<T>, dim3(pb), dim3(kBlock), 0, st, a);
+    }
+    if (phases & kPhaseSource) {
     a.mk->mark("deposit_force", st);
-    launch_deposit_force<T, KAHAN>(a, st);
+    launch_deposit_force<T, SM>(a, st);
     if (a.semi) {
         a.mk->mark("deposit_semi", st);
-        launch_deposit_semi<T, KAHAN>(a, st);
+        launch_deposit_semi<T, SM>(a, st);
     }
-    const int64_t nc = a.g.ncell, nf = a.g.nfine;
-    const ProlongSet<T> src{{a.phi, a.F, a.F + nc, a.F + 2 * nc},
-                            {a.fine_eps, a.fine_F, a.fine_F + nf, a.fine_F + 2 * nf},
-                            {SL_EPSF, SL_FF, SL_FF + 1, SL_FF + 2},
-                            1};
+    }
+    if (phases & kPhaseProlong) {
+    a.mk->mark("prolong_eps", st);
+    hipLaunchKernelGGL((k_prolong<T, R>), dim3(cb), dim3(kBlock), 0, st, a, eps);
+    const ProlongSet<T> src{{a.F, a.F + nc, a.F + 2 * nc, nullptr},
+                            {a.fine_F, a.fine_F + nf, a.fine_F + 2 * nf, nullptr},
+                            {SL_FF, SL_FF + 1, SL_FF + 2, 0},
+                            0, 3};
     a.mk->mark("prolong", st);
     hipLaunchKernelGGL((k_prolong<T, R>), dim3(cb), dim3(kBlock), 0, st, a, src);
     if (a.semi) {
         const ProlongSet<T> semi{{a.K, a.KU, a.KU + nc, a.KU + 2 * nc},
                                  {a.fine_K, a.fine_KU, a.fine_KU + nf, a.fine_KU + 2 * nf},
                                  {SL_KF, SL_KUF, SL_KUF + 1, SL_KUF + 2},
-                                 0};
+                                 0, 4};
         a.mk->mark("prolong_semi", st);
         hipLaunchKernelGGL((k_prolong<T, R>), dim3(cb), dim3(kBlock), 0, st, a, semi);
     }
-}
-
-template <typename T, bool KAHAN> static void launch_by_ratio(const StepArgs<T> &a, hipStream_t st) {
-    switch (a.ratio) {
-    case 1: launch_grid_stages<T, 1, KAHAN>(a, st); break;
-    case 2: launch_grid_stages<T, 2, KAHAN>(a, st); break;
-    default: launch_grid_stages<T, 4, KAHAN>(a, st); break;
     }
 }
 
-template <typename T> hipError_t launch_stages(const StepArgs<T> &a, hipStream_t st) {
+template <typename T, int SM> static void launch_by_ratio(const StepArgs<T> &a, hipStream_t st, int phases) {
+    switch (a.ratio) {
+    case 1: launch_grid_stages<T, 1, SM>(a, st, phases); break;
+    case 2: launch_grid_stages<T, 2, SM>(a, st, phases); break;
+    default: launch_grid_stages<T, 4, SM>(a, st, phases); break;
+    }
+}
+
+template <typename T> hipError_t launch_stages(const StepArgs<T> &a, hipStream_t st, int phases) {
     const int64_t cb = (a.g.ncell + kBlock - 1) / kBlock;
     const int64_t pb = (a.n + kBlock - 1) / kBlock;
-    const bool kahan = std::is_same<T, float>::value && a.kahan;
+    const int sm = a.sum_mode;   // FP32 modes; the FP64 mode sums plainly
 
     // workgroups per diagnostic slot (each writes one partial per slot), checked
     // against the partials' stride before anything is launched
@@ -873,23 +913,40 @@ template <typename T> hipError_t launch_stages(const StepArgs<T> &a, hipStream_t
     for (int s = 0; s < SL_COUNT; ++s)
         if (spec.nblk[s] > a.part_stride) return hipErrorInvalidValue;   // partials would not fit
 
-    if (a.n > 0) a.mk->mark("gather", st);
-    if (a.n > 0)
-        hipLaunchKernelGGL(k_gather<T>, dim3(pb), dim3(kBlock), 0, st, a.perm, a.uf4, a.n, a.sp);
-    a.mk->mark("deposit_phi", st);
-    if (kahan) launch_deposit_phi<T, true>(a, st);
-    else launch_deposit_phi<T, false>(a, st);
-    if (kahan) launch_by_ratio<T, true>(a, st);
-    else launch_by_ratio<T, false>(a, st);
-    a.mk->mark("diag", st);
-    double *part2 = a.part + (int64_t)SL_COUNT * a.part_stride;
-    hipLaunchKernelGGL(k_diag1, dim3(SL_COUNT * kDiagChunks), dim3(kBlock), 0, st, a.part, a.part_stride, spec, part2);
-    hipLaunchKernelGGL(k_diag2, dim3(SL_COUNT), dim3(kWave), 0, st, part2, spec, a.diag);
-    a.mk->mark(nullptr, st);
+    if (phases & kPhaseDeposit) {
+        if (a.n > 0) a.mk->mark("gather", st);
+        if (a.n > 0)
+            hipLaunchKernelGGL(k_gather<T>, dim3(pb), dim3(kBlock), 0, st, a.perm, a.uf4, a.n, a.sp);
+        a.mk->mark("deposit_phi", st);
+        if constexpr (std::is_same<T, float>::value) {
+            if (sm == kSumKahan) launch_deposit_phi<T, kSumKahan>(a, st);
+            else if (sm == kSumWide) launch_deposit_phi<T, kSumWide>(a, st);
+            else launch_deposit_phi<T, kSumPlain>(a, st);
+        } else {
+            launch_deposit_phi<T, kSumPlain>(a, st);
+        }
+    }
+    if (phases & (kPhaseVelocity | kPhaseSource | kPhaseProlong)) {
+        if constexpr (std::is_same<T, float>::value) {
+            if (sm == kSumKahan) launch_by_ratio<T, kSumKahan>(a, st, phases);
+            else if (sm == kSumWide) launch_by_ratio<T, kSumWide>(a, st, phases);
+            else launch_by_ratio<T, kSumPlain>(a, st, phases);
+        } else {
+            launch_by_ratio<T, kSumPlain>(a, st, phases);
+        }
+    }
+    if (phases & kPhaseDiag) {
+        a.mk->mark("diag", st);
+        double *part2 = a.part + (int64_t)SL_COUNT * a.part_stride;
+        hipLaunchKernelGGL(k_diag1, dim3(SL_COUNT * kDiagChunks), dim3(kBlock), 0, st, a.part, a.part_stride, spec,
+                           part2);
+        hipLaunchKernelGGL(k_diag2, dim3(SL_COUNT), dim3(kWave), 0, st, part2, spec, a.diag);
+        a.mk->mark(nullptr, st);
+    }
     return hipGetLastError();
 }
 
-template hipError_t launch_stages<float>(const StepArgs<float> &, hipStream_t);
-template hipError_t launch_stages<double>(const StepArgs<double> &, hipStream_t);
+template hipError_t launch_stages<float>(const StepArgs<float> &, hipStream_t, int);
+template hipError_t launch_stages<double>(const StepArgs<double> &, hipStream_t, int);
 
 }  // namespace cpl

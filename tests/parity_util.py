@@ -85,7 +85,7 @@ def fine_scale_from_bulk(Mb, nb, r, fine_index=None):
 
 
 def cfg_for(cpl, w, n, precision=None, deposit=None, vel_source=None, advect=None, dt=None):
-    prec = precision if precision is not None else (cpl.COUPLE_FP64 if w.precision == "fp64" else cpl.COUPLE_FP32_KAHAN)
+    prec = precision if precision is not None else (cpl.COUPLE_FP64 if w.precision == "fp64" else cpl.COUPLE_FP32_WIDE)
     dep = deposit if deposit is not None else (cpl.COUPLE_CIC if w.deposit == "cic" else cpl.COUPLE_NGP)
     return cpl.Config(box=w.grid.box, nb=w.grid.nb, ratio=w.grid.ratio, rho_f=w.rho_f, mu_f=w.mu_f,
                       rho_p=w.rho_p, eps_min=w.eps_min, deposit=dep, precision=prec,

@@ -30,7 +30,9 @@ def test_header_declares_the_entry_points():
         "couple_mlp_features", "couple_set_mlp",
         "couple_remap_init", "couple_remap_apply", "couple_remap_info", "couple_remap_free", "couple_remap_last_error",
         "couple_boxmap_init", "couple_boxmap_apply", "couple_boxmap_info", "couple_boxmap_free",
-        "couple_boxmap_last_error"])
+        "couple_boxmap_last_error",
+        "couple_part_init", "couple_part_step", "couple_part_comm_matrix", "couple_part_free",
+        "couple_part_last_error"])
 
 
 def test_library_exports_every_declared_symbol():
@@ -155,7 +157,7 @@ def _nodes(n, box=(1.0, 1.0, 1.0)):
 def test_remap_init_rejects_invalid_grids(case):
     import numpy as np
     import paper_1807_11834_amd as cpl
-    src, dst, prec = _nodes((4, 3, 2)), _nodes((2, 2, 2)), cpl.COUPLE_FP32_KAHAN
+    src, dst, prec = _nodes((4, 3, 2)), _nodes((2, 2, 2)), cpl.COUPLE_FP32_WIDE
     if case == "zero_cells":
         dst[1] = np.array([0.0])
     elif case == "not_increasing":
@@ -185,7 +187,7 @@ def test_boxmap_init_rejects_invalid_grids(case):
     import numpy as np
     import paper_1807_11834_amd as cpl
     good = np.array([[0.0, 1.0, 0.0, 1.0, 0.0, 1.0]])
-    s, r, prec = good.copy(), good.copy(), cpl.COUPLE_FP32_KAHAN
+    s, r, prec = good.copy(), good.copy(), cpl.COUPLE_FP32_WIDE
     if case == "ns0":
         s = np.zeros((0, 6))
     elif case == "nan":
@@ -210,3 +212,32 @@ def test_boxmap_null_handles():
     L = cpl._lib
     assert L.couple_boxmap_free(None) == cpl.COUPLE_OK
     assert L.couple_boxmap_apply(None, None, None, 1, None) == cpl.COUPLE_EINVAL
+
+
+PART_BAD = [
+    (dict(), 0, "nparts"), (dict(nb=(4, 4, 4)), 5, "nparts"), (dict(), 65, "nparts"),
+    (dict(vel_source=2), 2, "vel_source"), (dict(vel_source=3, precision=1), 2, "vel_source"),
+    (dict(vof=1), 2, "two-fluid"), (dict(box=(1.0, 1.0, 3.0), nb=(4, 4, 4)), 2, "power of two"),
+]
+
+
+@pytest.mark.parametrize("kw,nparts,msg", PART_BAD)
+def test_part_init_rejects_unsupported_configs(kw, nparts, msg):
+    """The partitioned step refuses what it does not cover before allocating."""
+    import paper_1807_11834_amd as cpl
+    cfg = cpl.Config(**{"max_particles": 10, "nb": (8, 8, 8), "box": (1.0, 1.0, 1.0), **kw})
+    with pytest.raises(cpl.CoupleError) as ei:
+        cpl.Part(cfg, nparts)
+    assert ei.value.code == cpl.COUPLE_EINVAL
+    assert msg in str(ei.value)
+
+
+def test_part_null_arguments():
+    import ctypes as C
+    import paper_1807_11834_amd as cpl
+    L = cpl._lib
+    assert L.couple_part_step(None, None, None, 0, None) == cpl.COUPLE_EINVAL
+    assert L.couple_part_free(None) == cpl.COUPLE_OK
+    assert L.couple_part_comm_matrix(None, None) == cpl.COUPLE_EINVAL
+    c = cpl.Config().to_c()
+    assert L.couple_part_init(C.byref(c), 2, None) == cpl.COUPLE_EINVAL

@@ -26,7 +26,7 @@ def _args(cfg, n, dtype=None):
 
 
 def test_valid_arguments_pass():
-    for prec in (cpl.COUPLE_FP32_KAHAN, cpl.COUPLE_FP64):
+    for prec in (cpl.COUPLE_FP32_WIDE, cpl.COUPLE_FP64):
         cfg = _cfg(precision=prec)
         i, o = _args(cfg, 7)
         cpl.validate_step(cfg, i, o, require_gpu=False)

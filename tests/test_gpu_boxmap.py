@@ -57,7 +57,7 @@ def test_refined_pairs_all_precisions(env):
     box = (1.0, 1.0, 2.0)
     s = W.refined_box_grid(box, (6, 6, 12), (0.0, 1.0, 0.0, 1.0, 0.0, 0.5))
     r = W.refined_box_grid(box, (5, 4, 9), (0.3, 0.9, 0.1, 0.6, 0.4, 1.5), split=3)
-    for prec in (cpl.COUPLE_FP32_KAHAN, cpl.COUPLE_FP32_NAIVE, cpl.COUPLE_FP64):
+    for prec in (cpl.COUPLE_FP32_WIDE, cpl.COUPLE_FP32_KAHAN, cpl.COUPLE_FP32_NAIVE, cpl.COUPLE_FP64):
         _check(torch, cpl, oracle, s, r, prec, label="refined s->r")
         _check(torch, cpl, oracle, r, s, prec, seed=1, label="refined r->s")
 
@@ -68,8 +68,8 @@ def test_many_term_rows_and_single_cells(env):
     fine = W.refined_box_grid(box, (9, 8, 7), (0.0, 0.5, 0.0, 1.0, 0.0, 1.0), split=4)   # up to 64 children
     one = W.box_grid(box, (1, 1, 1))
     coarse = W.box_grid(box, (2, 3, 1))
-    _check(torch, cpl, oracle, fine, one, cpl.COUPLE_FP32_KAHAN, nf=5, label="fine->one cell")
-    _check(torch, cpl, oracle, fine, coarse, cpl.COUPLE_FP32_KAHAN, nf=5, label="fine->coarse")
+    _check(torch, cpl, oracle, fine, one, cpl.COUPLE_FP32_WIDE, nf=5, label="fine->one cell")
+    _check(torch, cpl, oracle, fine, coarse, cpl.COUPLE_FP32_WIDE, nf=5, label="fine->coarse")
     _check(torch, cpl, oracle, one, fine, cpl.COUPLE_FP64, nf=1, label="one cell->fine")
 
 
@@ -77,7 +77,7 @@ def test_twin_cells_and_outside_receiver(env):
     torch, cpl, oracle = env
     g = W.refined_box_grid((1.0, 0.5, 0.75), (5, 3, 4), (0.2, 0.7, 0.0, 0.5, 0.3, 0.8))
     src = _fields(2, g.shape[0], 3).astype(np.float32)
-    m = cpl.BoxMap(g, g, precision=cpl.COUPLE_FP32_KAHAN)
+    m = cpl.BoxMap(g, g, precision=cpl.COUPLE_FP32_WIDE)
     got = m.apply(torch.from_numpy(src).cuda()).cpu().numpy()
     m.close()
     np.testing.assert_allclose(got, src, rtol=2e-7)
@@ -104,7 +104,7 @@ def test_bed_sized_pair_sampled(env):
     for s, r, label in ((f, b, "refined fine -> bulk"), (b, f, "bulk -> refined fine")):
         print(f"case boxmap {label}: {s.shape[0]} -> {r.shape[0]} cells", flush=True)
         src = rng.normal(size=(4, s.shape[0])).astype(np.float32)
-        m = cpl.BoxMap(s, r, precision=cpl.COUPLE_FP32_KAHAN)
+        m = cpl.BoxMap(s, r, precision=cpl.COUPLE_FP32_WIDE)
         try:
             D = m.apply(torch.from_numpy(src).cuda())
             torch.cuda.synchronize()

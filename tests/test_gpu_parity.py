@@ -46,15 +46,20 @@ def test_cube8_ngp_fp64(env):
 
 SMALL = [
     # (nb, ratio, box, n, precision, deposit, vel_source)
-    ((5, 3, 4), 4, (1.0, 0.75, 1.25), 777, "fp32k", "cic", "fine"),
+    ((5, 3, 4), 4, (1.0, 0.75, 1.25), 777, "fp32w", "cic", "fine"),
     ((5, 3, 4), 4, (1.0, 0.75, 1.25), 777, "fp64", "cic", "bulk"),
     ((7, 6, 5), 2, (0.7, 0.6, 0.5), 5000, "fp32n", "cic", "fine"),
-    ((9, 4, 3), 1, (0.9, 0.4, 0.3), 4097, "fp32k", "ngp", "bulk"),
-    ((70, 3, 2), 4, (1.0, 0.05, 0.04), 9001, "fp32k", "cic", "fine"),
+    ((9, 4, 3), 1, (0.9, 0.4, 0.3), 4097, "fp32w", "ngp", "bulk"),
+    ((70, 3, 2), 4, (1.0, 0.05, 0.04), 9001, "fp32w", "cic", "fine"),
     ((1, 1, 1), 4, (1.0, 1.0, 1.0), 300, "fp64", "cic", "fine"),
-    ((1, 5, 1), 2, (0.3, 1.0, 0.2), 300, "fp32k", "cic", "bulk"),
-    ((130, 1, 3), 4, (2.0, 0.01, 0.05), 12345, "fp32k", "ngp", "fine"),
+    ((1, 5, 1), 2, (0.3, 1.0, 0.2), 300, "fp32w", "cic", "bulk"),
+    ((130, 1, 3), 4, (2.0, 0.01, 0.05), 12345, "fp32w", "ngp", "fine"),
+    ((33, 17, 9), 4, (1.0, 0.5, 0.25), 70000, "fp32w", "cic", "fine"),
+    # Kahan-compensated FP32 per-cell sums
+    ((5, 3, 4), 4, (1.0, 0.75, 1.25), 777, "fp32k", "cic", "fine"),
+    ((9, 4, 3), 1, (0.9, 0.4, 0.3), 4097, "fp32k", "ngp", "bulk"),
     ((33, 17, 9), 4, (1.0, 0.5, 0.25), 70000, "fp32k", "cic", "fine"),
+    ((70, 3, 2), 2, (1.0, 0.05, 0.04), 9001, "fp32k", "cic", "bulk"),
 ]
 
 
@@ -62,7 +67,7 @@ SMALL = [
 def test_small_random(env, case):
     torch, cpl, oracle = env
     nb, r, box, n, prec, dep, src = case
-    precision = {"fp32k": cpl.COUPLE_FP32_KAHAN, "fp32n": cpl.COUPLE_FP32_NAIVE, "fp64": cpl.COUPLE_FP64}[prec]
+    precision = {"fp32w": cpl.COUPLE_FP32_WIDE, "fp32k": cpl.COUPLE_FP32_KAHAN, "fp32n": cpl.COUPLE_FP32_NAIVE, "fp64": cpl.COUPLE_FP64}[prec]
     w = W.small_workload(nb=nb, ratio=r, box=box, n=n, seed=100 + SMALL.index(case),
                          precision="fp64" if prec == "fp64" else "fp32", deposit=dep)
     pos, d, vel = W.particles(w)

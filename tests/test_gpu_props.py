@@ -29,7 +29,7 @@ cases = st.fixed_dictionaries({
     "ratio": st.sampled_from([1, 2, 4]),
     "box": st.tuples(st.floats(0.1, 2.0), st.floats(0.1, 2.0), st.floats(0.1, 2.0)),
     "n": st.integers(0, 5000),
-    "prec": st.sampled_from(["fp64", "fp32k", "fp32n"]),
+    "prec": st.sampled_from(["fp64", "fp32w", "fp32k", "fp32n"]),
     "cic": st.booleans(),
     "src": st.sampled_from(["fine", "bulk"]),
     "semi": st.booleans(),
@@ -49,7 +49,7 @@ def test_random_tiny_configurations(env, c):
     pos, d, vel = W.particles(w)
     fine = W.fine_fields(w)
     alpha = W.fine_alpha(w) if c["vof"] else None
-    precision = {"fp32k": cpl.COUPLE_FP32_KAHAN, "fp32n": cpl.COUPLE_FP32_NAIVE, "fp64": cpl.COUPLE_FP64}[c["prec"]]
+    precision = {"fp32w": cpl.COUPLE_FP32_WIDE, "fp32k": cpl.COUPLE_FP32_KAHAN, "fp32n": cpl.COUPLE_FP32_NAIVE, "fp64": cpl.COUPLE_FP64}[c["prec"]]
     cfg = cfg_for(cpl, w, c["n"], precision=precision, vel_source={"fine": 0, "bulk": 1}[c["src"]])
     cfg.semi_implicit, cfg.vof = int(c["semi"]), int(c["vof"])
     print(f"case props {c}", flush=True)

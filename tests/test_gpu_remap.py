@@ -49,24 +49,28 @@ def volumes(nodes):
 
 CASES = [
     # (sender cells, receiver cells, box, spacing, precision, fields)
-    ((40, 36, 28), (15, 13, 11), (1.0, 0.9, 0.7), "uniform", "fp32k", 1),
-    ((7, 5, 6), (23, 19, 17), (1.0, 1.0, 1.2), "uniform", "fp32k", 3),
+    ((40, 36, 28), (15, 13, 11), (1.0, 0.9, 0.7), "uniform", "fp32w", 1),
+    ((7, 5, 6), (23, 19, 17), (1.0, 1.0, 1.2), "uniform", "fp32w", 3),
     ((17, 13, 11), (9, 14, 6), (0.8, 1.3, 0.6), "random", "fp64", 2),
     ((32, 24, 20), (8, 6, 5), (1.0, 0.75, 0.625), "uniform", "fp32n", 1),
-    ((1, 30, 2), (1, 7, 5), (0.1, 1.0, 0.3), "random", "fp32k", 1),
-    ((61, 3, 47), (29, 5, 13), (1.0, 0.1, 0.8), "random", "fp32k", 1),
+    ((1, 30, 2), (1, 7, 5), (0.1, 1.0, 0.3), "random", "fp32w", 1),
+    ((61, 3, 47), (29, 5, 13), (1.0, 0.1, 0.8), "random", "fp32w", 1),
     # receiver finer in y and z with rows a multiple of 4 long: the tile kernel's
     # four-cell stores; with random spacing some receiver rows overlap more
     # than 2 x 2 sender rows (the table's overflow path)
-    ((6, 9, 8), (16, 11, 10), (1.0, 0.8, 0.6), "random", "fp32k", 2),
+    ((6, 9, 8), (16, 11, 10), (1.0, 0.8, 0.6), "random", "fp32w", 2),
     ((5, 4, 3), (12, 8, 8), (1.0, 1.0, 1.0), "uniform", "fp64", 1),
     # single cells
-    ((1, 1, 1), (1, 1, 1), (0.5, 0.25, 2.0), "uniform", "fp32k", 2),
+    ((1, 1, 1), (1, 1, 1), (0.5, 0.25, 2.0), "uniform", "fp32w", 2),
     ((1, 1, 1), (3, 2, 5), (0.5, 0.25, 2.0), "random", "fp64", 1),
-    ((4, 7, 3), (1, 1, 1), (0.5, 0.25, 2.0), "random", "fp32k", 1),
+    ((4, 7, 3), (1, 1, 1), (0.5, 0.25, 2.0), "random", "fp32w", 1),
     # sender rows longer than the LDS row buffer: the per-cell kernel
-    ((20000, 2, 1), (7, 3, 2), (1.0, 0.2, 0.1), "random", "fp32k", 1),
+    ((20000, 2, 1), (7, 3, 2), (1.0, 0.2, 0.1), "random", "fp32w", 1),
     ((9000, 1, 2), (13, 1, 1), (1.0, 0.1, 0.1), "uniform", "fp64", 1),
+    # Kahan-compensated FP32 sums in each kernel: rows, tile, per-cell
+    ((40, 36, 28), (15, 13, 11), (1.0, 0.9, 0.7), "random", "fp32k", 2),
+    ((6, 9, 8), (16, 11, 10), (1.0, 0.8, 0.6), "random", "fp32k", 2),
+    ((20000, 2, 1), (7, 3, 2), (1.0, 0.2, 0.1), "random", "fp32k", 1),
 ]
 
 
@@ -77,7 +81,7 @@ def test_remap_parity(env, case):
     rng = np.random.default_rng(500 + CASES.index(case))
     S = uniform_nodes(ns, box) if spacing == "uniform" else random_nodes(rng, ns, box)
     D = uniform_nodes(nd, box) if spacing == "uniform" else random_nodes(rng, nd, box)
-    precision = {"fp32k": cpl.COUPLE_FP32_KAHAN, "fp32n": cpl.COUPLE_FP32_NAIVE, "fp64": cpl.COUPLE_FP64}[prec]
+    precision = {"fp32w": cpl.COUPLE_FP32_WIDE, "fp32k": cpl.COUPLE_FP32_KAHAN, "fp32n": cpl.COUPLE_FP32_NAIVE, "fp64": cpl.COUPLE_FP64}[prec]
     src = rng.normal(1.0, 2.0, (nf, ns[2], ns[1], ns[0]))
     print(f"case remap {case}", flush=True)
     r = cpl.Remap(S, D, precision=precision)

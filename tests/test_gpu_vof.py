@@ -27,10 +27,11 @@ def env():
 
 CASES = [
     # (nb, ratio, box, n, precision, deposit, vel_source, semi)
-    ((5, 3, 4), 4, (1.0, 0.75, 1.25), 777, "fp32k", "cic", "fine", 0),
+    ((5, 3, 4), 4, (1.0, 0.75, 1.25), 777, "fp32w", "cic", "fine", 0),
     ((6, 5, 8), 4, (1.0, 1.0, 1.6), 6000, "fp64", "ngp", "bulk", 0),
     ((7, 6, 5), 2, (0.7, 0.6, 0.5), 5000, "fp32n", "cic", "fine", 0),
-    ((33, 17, 9), 4, (1.0, 0.5, 0.25), 70000, "fp32k", "cic", "fine", 1),
+    ((33, 17, 9), 4, (1.0, 0.5, 0.25), 70000, "fp32w", "cic", "fine", 1),
+    ((12, 10, 8), 4, (1.2, 1.0, 0.8), 20000, "fp32k", "cic", "fine", 0),
 ]
 
 
@@ -38,7 +39,7 @@ CASES = [
 def test_vof_parity(env, case):
     torch, cpl, oracle = env
     nb, r, box, n, prec, dep, src, semi = case
-    precision = {"fp32k": cpl.COUPLE_FP32_KAHAN, "fp32n": cpl.COUPLE_FP32_NAIVE, "fp64": cpl.COUPLE_FP64}[prec]
+    precision = {"fp32w": cpl.COUPLE_FP32_WIDE, "fp32k": cpl.COUPLE_FP32_KAHAN, "fp32n": cpl.COUPLE_FP32_NAIVE, "fp64": cpl.COUPLE_FP64}[prec]
     w = W.small_workload(nb=nb, ratio=r, box=box, n=n, seed=400 + CASES.index(case),
                          precision="fp64" if prec == "fp64" else "fp32", deposit=dep)
     pos, d, vel = W.particles(w)
