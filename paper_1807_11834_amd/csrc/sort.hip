@@ -13,12 +13,16 @@
 //   k_radix_scatter stable ranking inside a tile (wave ballots, LDS staging) and
 //                  coalesced scatter to the digit's output run;
 //   k_segment_starts  start[c] = first sorted position with cell >= c, set by
-//                  the sorted positions where the key changes;
-//   k_segment_counts  count[c] = start[c+1] - start[c].
+//                  the sorted positions where the key changes (long runs of
+//                  empty cells are left to the next kernel);
+//   k_segment_counts  the starts left unset (binary search of the sorted keys)
+//                  and count[c] = start[c+1] - start[c].
 //
 // Keys are cell indices < ncell; ids are the input order, so a stable LSD sort
 // starting from the identity order gives ascending (cell, id).  Integer atomics
 // are used only on LDS histogram bins (exact counts); no float atomics anywhere.
+#include <algorithm>
+
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -29,13 +33,24 @@ constexpr int kTile = kBlock * kItems;             // 4096 keys per tile
 constexpr int kWaveSpan = kWave * kItems;          // keys handled by one wave
 constexpr int kMaxDigits = 256;                    // radix <= 8 bits per pass
 
+// A start entry not yet known: k_bin marks every entry so, k_segment_starts sets
+// all but those inside long runs of empty cells, k_segment_counts the rest.
+constexpr int32_t kUnset = -1;
+
+// Workgroups [0, ntile) bin the particles of their tile; every workgroup of the
+// grid (which may be larger, to cover the cells) also marks a share of
+// start[0 .. nstart) unset.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_bin(const T *__restrict__ pos, const T *__restrict__ diam, int64_t n,
                                                 Geo<T> g, int32_t *__restrict__ cell, vec4<T> *__restrict__ pk,
                                                 uint32_t *__restrict__ hist,
-                                                int ntile, int bits0, double *__restrict__ part_nout) {
+                                                int ntile, int bits0, double *__restrict__ part_nout,
+                                                int32_t *__restrict__ start, int64_t nstart) {
     __shared__ uint32_t h[kMaxDigits];
     __shared__ double red[kWavesPerBlock];
+    for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < nstart; c += (int64_t)gridDim.x * kBlock)
+        start[c] = kUnset;
+    if ((int)blockIdx.x >= ntile) return;   // uniform over the workgroup, before any barrier
     const int ndig = 1 << bits0;
     for (int d = threadIdx.x; d < ndig; d += kBlock) h[d] = 0;
     __syncthreads();
@@ -235,10 +250,13 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t *__rest
 // start[c] = first sorted position with key >= c, for c in [0, ncell].  Every
 // sorted position i whose key differs from its predecessor's (with key[-1] = -1
 // and key[n] = ncell) sets start[c] = i for the cells c in (key[i-1], key[i]],
-// so every entry is written exactly once and the keys are read once, coalesced,
+// so every entry is written at most once and the keys are read once, coalesced,
 // without searches.  A gap of more than kGapLane cells (a run of empty cells)
-// is filled by the whole wave together.
+// is filled by the whole wave together; one of more than kGapWave cells is left
+// unset for k_segment_counts, which spreads it over the grid (a single wave
+// filling millions of empty cells would serialise the step).
 constexpr int kGapLane = 32;
+constexpr int64_t kGapWave = 4096;
 
 __global__ __launch_bounds__(kBlock) void k_segment_starts(const uint32_t *__restrict__ skeys, int64_t n,
                                                            int64_t ncell, int32_t *__restrict__ start) {
@@ -259,14 +277,40 @@ __global__ __launch_bounds__(kBlock) void k_segment_starts(const uint32_t *__res
         const int l = __ffsll((unsigned long long)m) - 1;
         m &= m - 1;
         const int32_t glo = __shfl(lo, l, kWave), ghi = __shfl(hi, l, kWave), gi = __shfl((int32_t)i, l, kWave);
+        if ((int64_t)ghi - glo + 1 > kGapWave) continue;   // left unset (wave-uniform)
         for (int64_t c = (int64_t)glo + lane; c <= ghi; c += kWave) start[c] = gi;   // 64-bit: no wrap near 2^31
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_segment_counts(const int32_t *__restrict__ start, int64_t ncell,
+// First sorted position i in [0, n] with key[i] >= c (binary search).
+__device__ __forceinline__ int32_t first_at_least(const uint32_t *__restrict__ skeys, int64_t n, int64_t c) {
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((int64_t)skeys[mid] < c) lo = mid + 1;
+        else hi = mid;
+    }
+    return (int32_t)lo;
+}
+
+// Thread c in [0, ncell]: resolves start[c] if it is unset, and count[c] =
+// start[c+1] - start[c] (an unset start[c+1] is resolved here too; its own
+// thread stores the same value).
+__global__ __launch_bounds__(kBlock) void k_segment_counts(int32_t *start, int64_t ncell,
+                                                           const uint32_t *__restrict__ skeys, int64_t n,
                                                            int32_t *__restrict__ count) {
     const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (c < ncell) count[c] = start[c + 1] - start[c];
+    if (c > ncell) return;
+    int32_t v = start[c];
+    if (v == kUnset) {
+        v = first_at_least(skeys, n, c);
+        start[c] = v;
+    }
+    if (c < ncell) {
+        int32_t w = start[c + 1];
+        if (w == kUnset) w = first_at_least(skeys, n, c + 1);
+        count[c] = w - v;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -290,11 +334,14 @@ hipError_t launch_bin_sort(const T *pos, const T *diam, int64_t n, const Geo<T> 
                            const uint32_t **sorted_keys, Marker *mk, hipStream_t st) {
     int npass, widths[4];
     sort_plan(g.ncell, &npass, widths);
-    const int ntile = sort_tiles(n);
+    const int ntile = n > 0 ? sort_tiles(n) : 0;
+    // the binning grid also covers start[0 .. ncell] (marked unset)
+    const int64_t nstart = g.ncell + 1;
+    const int bin_blocks = std::max<int64_t>(ntile, (nstart + kTile - 1) / kTile);
+    mk->mark("bin", st);
+    hipLaunchKernelGGL(k_bin<T>, dim3(bin_blocks), dim3(kBlock), 0, st, pos, diam, n, g, cell, pk, s.hist, ntile,
+                       widths[0], part_nout, start, nstart);
     if (n > 0) {
-        mk->mark("bin", st);
-        hipLaunchKernelGGL(k_bin<T>, dim3(ntile), dim3(kBlock), 0, st, pos, diam, n, g, cell, pk, s.hist, ntile,
-                           widths[0], part_nout);
         int shift = 0;
         const uint32_t *kin = (const uint32_t *)cell;
         const uint32_t *vin = nullptr;
@@ -323,10 +370,10 @@ hipError_t launch_bin_sort(const T *pos, const T *diam, int64_t n, const Geo<T> 
     } else {
         *sorted_keys = s.keys_a;
     }
-    const int sblk = (int)((n + 1 + kBlock - 1) / kBlock), cblk = (int)((g.ncell + kBlock - 1) / kBlock);
+    const int sblk = (int)((n + 1 + kBlock - 1) / kBlock), cblk = (int)((g.ncell + 1 + kBlock - 1) / kBlock);
     mk->mark("segments", st);
     hipLaunchKernelGGL(k_segment_starts, dim3(sblk), dim3(kBlock), 0, st, *sorted_keys, n, g.ncell, start);
-    hipLaunchKernelGGL(k_segment_counts, dim3(cblk), dim3(kBlock), 0, st, start, g.ncell, count);
+    hipLaunchKernelGGL(k_segment_counts, dim3(cblk), dim3(kBlock), 0, st, start, g.ncell, *sorted_keys, n, count);
     return hipGetLastError();
 }
 

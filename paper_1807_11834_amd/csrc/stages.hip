@@ -349,8 +349,8 @@ __device__ __forceinline__ void brick_fill(const StepArgs<T> &a, BrickLds<T, R> 
         L.beg[t] = b0;
         L.cnt[t] = c;
     }
-    if (t < kBrickHalo) {
-        const int hx = t % HX, hy = (t / HX) % HY, hz = t / (HX * HY);
+    for (int h = t; h < kBrickHalo; h += kBrickThreads) {
+        const int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
         const int gx = clampi(ox - 1 + hx, g.nb[0]), gy = clampi(oy - 1 + hy, g.nb[1]), gz = clampi(oz - 1 + hz, g.nb[2]);
         L.sphi[hz][hy][hx] = a.phi[gx + nx * gy + nxy * gz];
     }
@@ -492,7 +492,7 @@ __device__ __forceinline__ void brick_particles(const StepArgs<T> &a, const Bric
 template <typename T, int R, int SM>
 __global__ __launch_bounds__(kBrickThreads) void k_restrict_brick(StepArgs<T> a, BrickGrid<T> bg) {
     static_assert(R <= 4, "one thread per fine child plane");
-    static_assert(kBrickHalo <= kBrickThreads, "one halo value per thread");
+    static_assert(kBrickRows <= kBrickThreads, "one particle row per thread");
     __shared__ BrickLds<T, R> L;
     int ox, oy, oz;
     bg.origin(xcd_tile(blockIdx.x, gridDim.x), ox, oy, oz);

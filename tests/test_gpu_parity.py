@@ -120,6 +120,31 @@ def test_all_particles_in_one_cell_and_empty_cells(env):
     compare_step(g, o, pos.shape[0], w.grid.nb, w.grid.ratio, box=w.grid.box, fp64=False, label="one-cell")
 
 
+@pytest.mark.parametrize("n", [0, 1, 2000])
+def test_long_runs_of_empty_cells(env, n):
+    """Particles only in the lowest 30 % of a 32 x 32 x 32 grid (one particle in
+    the last cell; none at all): runs of tens of thousands of empty cells, whose
+    starts are resolved by binary search rather than filled by one wave; count
+    and start bit-exact.  Box 2 x 2 x 2: cells of 1/16 (larger than the
+    particles; a power-of-two scale, so the FP32 CIC weights carry no rounding of
+    x / h); the single particle in FP64 (one FP32 drag alone cannot meet the
+    1e-6 bound on the FP64 sum of the drags)."""
+    torch, cpl, oracle = env
+    prec = "fp64" if n == 1 else "fp32"
+    w = W.small_workload(nb=(32, 32, 32), ratio=2, box=(2.0, 2.0, 2.0), n=max(n, 1), seed=8, precision=prec)
+    pos, d, vel = W.particles(w)
+    pos, d, vel = pos[:n].copy(), d[:n].copy(), vel[:n].copy()
+    pos[:, 2] *= 0.3
+    if n == 1:
+        pos[0] = [1.99, 1.99, 1.99]   # the last cell: one run of 32,767 empty cells before it
+    cfg = cfg_for(cpl, w, n)
+    print(f"case long empty runs n={n}", flush=True)
+    g = run_gpu(cpl, torch, cfg, pos, vel, d, W.fine_fields(w))
+    o = _oracle(oracle, cpl, w, cfg, pos, vel, d, W.fine_fields(w))
+    compare_step(g, o, n, w.grid.nb, w.grid.ratio, box=w.grid.box, fp64=prec == "fp64", label=f"empty runs n={n}")
+    assert int(g["count"].sum()) == n and g["start"][-1] == n
+
+
 def test_zero_particles(env):
     torch, cpl, oracle = env
     w = W.small_workload(nb=(6, 5, 4), ratio=4, n=0, seed=3, precision="fp32")
