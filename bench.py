@@ -67,8 +67,9 @@ def step_alg_bytes(n, ncell, nfine, fsz, sort_passes):
 
 # Marks of the library's kernel timing -> the kernel names rocprofv3 reports.
 PROFILE_NAMES = {
-    "restrict_lookup": "cpl::k_restrict_brick<float, 4, true>",
-    "restrict": "cpl::k_restrict<float, 4, true>",
+    "restrict_lookup": "cpl::k_restrict_brick<float, 4, 2>",
+    "restrict_p": "cpl::k_restrict<float, 4, 2, 3, 4>",
+    "restrict": "cpl::k_restrict<float, 4, 2, 0, 4>",
     "prolong": "cpl::k_prolong<float, 4>",
     "mlp_infer": "cpl::mlp::k_infer",
 }
@@ -127,6 +128,8 @@ def _pmc_means(path):
         with open(fn) as f:
             for r in csv.DictReader(f):
                 k = re.sub(r"\(.*", "", r["Kernel_Name"]).replace("void ", "").strip()
+                if "k_boxmap" in k:   # two directions, told apart by their grids
+                    k = f"{k}@{r.get('Grid_Size', '')}"
                 vals.setdefault(k, []).append(float(r["Counter_Value"]))
     return {k: (sum(v) / len(v), len(v)) for k, v in vals.items()}
 
@@ -564,6 +567,49 @@ def part_leg(args, cfg, pos, vel, diam, fine, plain_ms, n, dev):
     return res
 
 
+def boxmap_leg(args, fsz, dev):
+    """Transfer through the CSR overlap map between a locally refined grid over
+    the bed's box (96 x 96 x 192 base cells, the bottom quarter split 2:1 per
+    axis: 4.9M cells) and the bulk grid (128 x 128 x 256): four fields each way.
+    Algorithmic bytes per transfer: the map once (8 B column + weight per
+    nonzero, 8 B row offset per receiver), the sender fields once and the
+    receiver fields written once."""
+    import torch
+    import paper_1807_11834_amd as cpl
+    import workload as W
+    box = (1.0, 1.0, 2.0)
+    f = W.refined_box_grid_fast(box, (96, 96, 192), (0.0, 1.0, 0.0, 1.0, 0.0, 0.5))
+    b = W.box_grid(box, (128, 128, 256))
+    prec = cpl.COUPLE_FP64 if fsz == 8 else cpl.COUPLE_FP32_WIDE
+    res = {"grids": {"refined_cells": int(f.shape[0]), "bulk_cells": int(b.shape[0])}}
+    stream = torch.cuda.current_stream()
+    for name, s_, r_ in (("refined_to_bulk", f, b), ("bulk_to_refined", b, f)):
+        t0 = time.time()
+        m = cpl.BoxMap(s_, r_, precision=prec)
+        build_s = time.time() - t0
+        try:
+            src = torch.rand((4, s_.shape[0]), dtype=m.dtype, device=dev)
+            dst = torch.empty((4, r_.shape[0]), dtype=m.dtype, device=dev)
+            for _ in range(3):
+                m.apply(src, dst)
+            k = max(args.steps, 20)
+            total, per = timed_steps(lambda i: m.apply(src, dst), k, stream)
+            nnz, mr = m.info()
+        finally:
+            m.close()
+        ms = total / k
+        ab = nnz * (4 + fsz) + 8 * (r_.shape[0] + 1) + 4 * fsz * (s_.shape[0] + r_.shape[0])
+        res[name] = {"ms_per_transfer": ms, "nnz": int(nnz), "longest_row": int(mr), "alg_bytes": int(ab),
+                     "GBps": round(ab / (ms * 1e-3) / 1e9, 1),
+                     "frac_hbm": round(ab / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                     "map_build_s": round(build_s, 2),
+                     "traffic": profiled_traffic(f"cpl::k_boxmap<float, 2, 4>@{(r_.shape[0] + 255) // 256 * 256}")}
+        print(f"# box map {name}: {ms:.3f} ms per four fields", file=sys.stderr, flush=True)
+        del src, dst
+    torch.cuda.empty_cache()
+    return res
+
+
 def remap_leg(args, g, fine, fsz, dev):
     """Grid-to-grid transfer between non-nested grids at the bed's size: the four
     fine fields (u, v, w, p; 512 x 512 x 1024 over 1 x 1 x 2) to a 192 x 192 x 384
@@ -762,6 +808,8 @@ def main():
         rec["two_fluid_drag"] = vof_leg(args, w, cfg, pos, vel, diam, fine, ms_step, n, g, fsz, dev)
     if not args.no_remap:
         rec["nonnested_transfer"] = remap_leg(args, g, fine, fsz, dev)
+    if not args.no_boxmap:
+        rec["refined_grid_transfer"] = boxmap_leg(args, fsz, dev)
     if not args.no_mlp:
         print("# surrogate: pairs, training, timing ...", file=sys.stderr, flush=True)
         rec["mlp_path"] = mlp_leg(args, w, cfg, pos, vel, diam, fine, ms_step, kernels, dev)
