@@ -76,9 +76,19 @@ PROFILE_NAMES = {
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_bed128.json")
 
 
-# Sources of kernels that never run in the profiled coupling commands (the
-# non-nested grid transfer): they do not change the counters.
-UNPROFILED_SOURCES = ("remap.hip",)
+# The sources each group of profiled kernels is built from: a group's counter
+# figures hold only while these hash as they did when the counters were taken.
+SOURCE_GROUPS = {
+    "step": ["csrc/common.hpp", "csrc/launch.hpp", "csrc/sample.hpp", "csrc/handle.hpp", "csrc/api.hip",
+             "csrc/sort.hip", "csrc/deposit.hip", "csrc/stages.hip", "include/couple.h"],
+    "mlp": ["csrc/common.hpp", "csrc/launch.hpp", "csrc/sample.hpp", "csrc/mlp.hpp", "csrc/mlp_state.hpp",
+            "csrc/mlp.hip", "csrc/mlp_api.hip", "include/couple.h", "include/couple_mlp.h"],
+    "boxmap": ["csrc/common.hpp", "csrc/boxmap.hip", "include/couple.h", "include/couple_boxmap.h"],
+}
+
+
+def kernel_group(name):
+    return "mlp" if "mlp::" in name else ("boxmap" if "k_boxmap" in name else "step")
 
 
 def _code_only(text):
@@ -90,18 +100,19 @@ def _code_only(text):
     return "\n".join(l.rstrip() for l in text.splitlines() if l.strip())
 
 
-def csrc_sha256():
-    """Hash of the HIP sources (code only) of the coupling step and the
-    surrogate: profiled counters apply only to this build."""
+def source_hashes():
+    """Hash per source group (code only) of the files its kernels are built from."""
     import hashlib
-    h = hashlib.sha256()
-    d = os.path.join(ROOT, "paper_1807_11834_amd", "csrc")
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".hpp")) and f not in UNPROFILED_SOURCES:
+    out = {}
+    for grp, files in SOURCE_GROUPS.items():
+        h = hashlib.sha256()
+        for f in files:
+            path = os.path.join(ROOT, "paper_1807_11834_amd", f) if f.startswith("csrc/") else os.path.join(ROOT, f)
             h.update(f.encode())
-            with open(os.path.join(d, f), encoding="utf-8") as fh:
+            with open(path, encoding="utf-8") as fh:
                 h.update(_code_only(fh.read()).encode())
-    return h.hexdigest()
+        out[grp] = h.hexdigest()
+    return out
 
 
 def profiled_traffic(mark):
@@ -112,9 +123,11 @@ def profiled_traffic(mark):
             prof = json.load(f)
     except (OSError, ValueError):
         return None
-    if prof.get("csrc_sha256") != csrc_sha256():
+    name = PROFILE_NAMES.get(mark, mark)
+    grp = kernel_group(name)
+    if prof.get("source_hashes", {}).get(grp) != source_hashes()[grp]:
         return None
-    k = prof.get("kernels", {}).get(PROFILE_NAMES.get(mark, mark))
+    k = prof.get("kernels", {}).get(name)
     return None if k is None else k["traffic_bytes_per_launch"]
 
 
@@ -161,7 +174,7 @@ def traffic_summary(d):
                       "traffic_bytes_per_launch": int(round((fk * f_fetch + wk * f_write) * 1024))}
     return {
         "workload": "bed128_cic: 10,000,000 particles, bulk 128x128x256, fine 512x512x1024, FP32",
-        "csrc_sha256": csrc_sha256(),
+        "source_hashes": source_hashes(),
         "calibration": {"kernel": copy[0], "bytes_read": 1 << 30, "bytes_written": 1 << 30,
                         "fetch_kib": cf[copy[0]][0], "write_kib": cw[copy[0]][0],
                         "fetch_factor": round(f_fetch, 4), "write_factor": round(f_write, 4)},
@@ -672,6 +685,7 @@ def main():
     ap.add_argument("--no-semi", action="store_true", help="skip the semi-implicit split variant")
     ap.add_argument("--no-vof", action="store_true", help="skip the two-fluid drag variant")
     ap.add_argument("--no-remap", action="store_true", help="skip the non-nested grid transfer")
+    ap.add_argument("--no-boxmap", action="store_true", help="skip the transfer through the CSR overlap map")
     ap.add_argument("--no-advected", action="store_true", help="skip the 100-step advected 64^3 cube")
     ap.add_argument("--no-part", action="store_true", help="skip the partitioned (z-slab) step")
     ap.add_argument("--no-precision", action="store_true", help="skip the Kahan and naive FP32 variants")

@@ -71,22 +71,29 @@ template <typename T, int SM> struct CellSum {
 // A running sum of products w v under mode SM: Kahan in T with the product
 // formed by an FMA against the running compensation (each term rounded once),
 // plain FMAs in T, or plain FMAs in FP64 registers (rounded to T once, by
-// value()).
-template <typename T, int SM> struct FmaSum {
-    using W = typename std::conditional<SM == kSumWide, double, T>::type;
+// value()).  Only the Kahan mode carries the compensation word (arrays of these
+// accumulators must stay in registers).
+template <typename W, bool KAHAN> struct FmaState {
     W s = W(0);
-    W c = W(0);   // Kahan compensation (SM == kSumKahan only)
+};
+template <typename W> struct FmaState<W, true> {
+    W s = W(0);
+    W c = W(0);
+};
+template <typename T, int SM>
+struct FmaSum : FmaState<typename std::conditional<SM == kSumWide, double, T>::type, SM == kSumKahan> {
+    using W = typename std::conditional<SM == kSumWide, double, T>::type;
     __device__ __forceinline__ void add(W w, W v) {
         if constexpr (SM == kSumKahan) {
-            const W y = fma(w, v, -c);
-            const W t = s + y;
-            c = (t - s) - y;
-            s = t;
+            const W y = fma(w, v, -this->c);
+            const W t = this->s + y;
+            this->c = (t - this->s) - y;
+            this->s = t;
         } else {
-            s = fma(w, v, s);
+            this->s = fma(w, v, this->s);
         }
     }
-    __device__ __forceinline__ T value() const { return T(s); }
+    __device__ __forceinline__ T value() const { return T(this->s); }
 };
 
 template <typename T> __device__ __forceinline__ T tmin(T a, T b) { return a < b ? a : b; }

@@ -89,6 +89,9 @@ constexpr int kMaxQ = 16;
 template <typename T, int SM>
 __global__ __launch_bounds__(kBlock) void k_remap_rows(RemapArgs<T> r, const T *__restrict__ src,
                                                        T *__restrict__ dst) {
+    // both compensated modes run Kahan in T here: FP64 sums of the sixteen
+    // rows in flight per thread ran three times slower
+    constexpr int SMR = SM == kSumWide ? (int)kSumKahan : SM;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     T *row = reinterpret_cast<T *>(lds_raw);
     __shared__ int64_t qoff[kMaxQ];
@@ -115,8 +118,8 @@ __global__ __launch_bounds__(kBlock) void k_remap_rows(RemapArgs<T> r, const T *
                 T v[kMaxQ];
 #pragma unroll
                 for (int q = 0; q < kMaxQ; ++q) v[q] = q < mq ? s[qoff[q] + xs] : T(0);
-                using W = SumT<T, SM>;
-                FmaSum<T, SM> acc;
+                using W = SumT<T, SMR>;
+                FmaSum<T, SMR> acc;
                 if (q0 > 0) acc.s = W(row[xs]);   // continue the partial sum of earlier rows
 #pragma unroll
                 for (int q = 0; q < kMaxQ; ++q)
@@ -128,8 +131,8 @@ __global__ __launch_bounds__(kBlock) void k_remap_rows(RemapArgs<T> r, const T *
         T *__restrict__ out = dst + (int64_t)blockIdx.y * r.ndst + rr * r.nd[0];
         for (int xd = threadIdx.x; xd < r.nd[0]; xd += kBlock) {
             const int fx = r.first[0][xd], nx = r.cnt[0][xd], ox = r.off[0][xd];
-            using W = SumT<T, SM>;
-            FmaSum<T, SM> acc;
+            using W = SumT<T, SMR>;
+            FmaSum<T, SMR> acc;
             for (int kx = 0; kx < nx; ++kx) acc.add(W(r.w[0][ox + kx]), W(row[fx + kx]));
             out[xd] = acc.value();
         }
