@@ -132,24 +132,57 @@ __global__ __launch_bounds__(kBlock) void k_adam(const float *__restrict__ grads
 // Batch kernels (training and inference on given features)
 // ---------------------------------------------------------------------------
 // X0[b][k] = bf16((feat[row][k] - mean[k]) / std[k]) for k < 193, 0 up to 224;
-// row = idx[b] (or b).  T[b] = resid[row] / scale (optional).
+// row = idx[b] (or b).  T[b] = resid[row] / scale (optional).  X0T (optional):
+// the same values transposed, [224][B], for the first layer's weight-gradient
+// products.  A workgroup takes 64 rows: their features are read row by row
+// (consecutive threads, consecutive features) and standardised into an LDS
+// tile, from which the rows leave as 16-byte stores and the transposed copy
+// as 2-byte stores of consecutive rows.
+constexpr int kStdRows = 64;
+constexpr int kStdPitch = kK1 + 2;   // BF16 elements per LDS row (odd word count: no bank conflicts by column)
 __global__ __launch_bounds__(kBlock) void k_standardise(const float *__restrict__ feat, const float *__restrict__ resid,
                                                         const int32_t *__restrict__ idx, int64_t nrows, int64_t B,
                                                         const float *__restrict__ mean_inv, float is0, float is1,
-                                                        float is2, uint16_t *__restrict__ x0, float *__restrict__ T) {
-    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (e >= B * kK1) return;
-    const int64_t b = e / kK1;
-    const int k = (int)(e % kK1);
-    int64_t row = idx ? (int64_t)idx[b] : b;
-    if (row < 0 || row >= nrows) row = 0;   // documented: indices must be in range; keeps loads in bounds
-    float v = 0.f;
-    if (k < kFeat) v = (feat[row * kFeat + k] - mean_inv[k]) * mean_inv[kK1 + k];
-    x0[e] = (uint16_t)bf16_bits(v);
-    if (T && k < 4) {
-        const float is[3] = {is0, is1, is2};
-        T[b * 4 + k] = (k < 3) ? resid[row * 3 + k] * is[k] : 0.f;
+                                                        float is2, uint16_t *__restrict__ x0, uint16_t *__restrict__ x0t,
+                                                        float *__restrict__ T) {
+    __shared__ uint16_t tile[kStdRows * kStdPitch];
+    __shared__ int64_t rows[kStdRows];
+    const int64_t b0 = (int64_t)blockIdx.x * kStdRows;
+    const int nr = (int)(B - b0 < kStdRows ? B - b0 : kStdRows);
+    if (threadIdx.x < kStdRows) {
+        int64_t row = 0;
+        if ((int)threadIdx.x < nr) {
+            row = idx ? (int64_t)idx[b0 + threadIdx.x] : b0 + threadIdx.x;
+            if (row < 0 || row >= nrows) row = 0;   // documented: indices must be in range; keeps loads in bounds
+        }
+        rows[threadIdx.x] = row;
     }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nr * kK1; e += kBlock) {
+        const int r = e / kK1, k = e % kK1;
+        float v = 0.f;
+        if (k < kFeat) v = (feat[rows[r] * kFeat + k] - mean_inv[k]) * mean_inv[kK1 + k];
+        tile[r * kStdPitch + k] = (uint16_t)bf16_bits(v);
+    }
+    if (T)
+        for (int e = threadIdx.x; e < nr * 4; e += kBlock) {
+            const int r = e / 4, j = e % 4;
+            const float is = j == 0 ? is0 : (j == 1 ? is1 : is2);
+            T[(b0 + r) * 4 + j] = j < 3 ? resid[rows[r] * 3 + j] * is : 0.f;
+        }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nr * (kK1 / 8); e += kBlock) {
+        const int r = e / (kK1 / 8), k0 = 8 * (e % (kK1 / 8));
+        const uint16_t *t = tile + r * kStdPitch + k0;
+        const uint4 pk = make_uint4(t[0] | ((uint32_t)t[1] << 16), t[2] | ((uint32_t)t[3] << 16),
+                                    t[4] | ((uint32_t)t[5] << 16), t[6] | ((uint32_t)t[7] << 16));
+        *reinterpret_cast<uint4 *>(x0 + (b0 + r) * kK1 + k0) = pk;
+    }
+    if (x0t)
+        for (int e = threadIdx.x; e < kK1 * kStdRows; e += kBlock) {
+            const int k = e / kStdRows, r = e % kStdRows;
+            if (r < nr) x0t[(int64_t)k * B + b0 + r] = tile[r * kStdPitch + k];
+        }
 }
 
 // One dense layer for 16-row tiles, one wave per tile:
@@ -270,22 +303,6 @@ __global__ __launch_bounds__(kBlock) void k_dense_bwd(const uint16_t *__restrict
     }
 }
 
-// BF16 transpose src [R][C] -> dst [C][R] through LDS (64 x 64 tiles).
-__global__ __launch_bounds__(kBlock) void k_transpose(const uint16_t *__restrict__ src, int64_t R, int64_t C,
-                                                      uint16_t *__restrict__ dst) {
-    __shared__ uint16_t t[64][66];
-    const int64_t r0 = (int64_t)blockIdx.x * 64, c0 = (int64_t)blockIdx.y * 64;
-    for (int i = threadIdx.x; i < 64 * 64; i += kBlock) {
-        const int rr = i / 64, cc = i % 64;
-        t[rr][cc] = (r0 + rr < R && c0 + cc < C) ? src[(r0 + rr) * C + c0 + cc] : (uint16_t)0;
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < 64 * 64; i += kBlock) {
-        const int cc = i / 64, rr = i % 64;
-        if (c0 + cc < C && r0 + rr < R) dst[(c0 + cc) * R + r0 + rr] = t[rr][cc];
-    }
-}
-
 // Weight and bias gradients of one layer over a chunk of rows:
 //   part_w[c][m][k] = sum_{b in chunk} dZ[b][m] H[b][k]   (BF16 x BF16, FP32 accumulate)
 //   part_b[c][m]    = sum_{b in chunk} dZf[b][m]          (FP32 values, FP64 sum)
@@ -308,13 +325,25 @@ __global__ __launch_bounds__(kBlock) void k_wgrad(const uint16_t *__restrict__ d
         for (int mt = 0; mt < MT; ++mt) acc[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
         const uint16_t *pb = HT + (int64_t)(16 * kt + n) * B + 8 * g;
         const uint16_t *pa = dZT + (int64_t)n * B + 8 * g;
-        for (int64_t bb = b0; bb < b1; bb += 32) {
-            const bf16x8 bv = load8(pb + bb);
-            bf16x8 av[MT];
+        // kU groups of 32 rows per round, all their loads issued before the
+        // products (the rows are still summed in order)
+        constexpr int kU = MT > 4 ? 4 : 8;
+        for (int64_t bb = b0; bb < b1; bb += 32 * kU) {
+            bf16x8 bv[kU];
+            bf16x8 av[kU][MT];
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt) av[mt] = load8(pa + (int64_t)16 * mt * B + bb);
+            for (int u = 0; u < kU; ++u) {
+                const int64_t r = bb + 32 * u < b1 ? bb + 32 * u : b1 - 32;
+                bv[u] = load8(pb + r);
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt) acc[mt] = mma(av[mt], bv, acc[mt]);
+                for (int mt = 0; mt < MT; ++mt) av[u][mt] = load8(pa + (int64_t)16 * mt * B + r);
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                if (bb + 32 * u >= b1) break;
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) acc[mt] = mma(av[u][mt], bv[u], acc[mt]);
+            }
         }
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
@@ -325,9 +354,12 @@ __global__ __launch_bounds__(kBlock) void k_wgrad(const uint16_t *__restrict__ d
     }
     for (int m = threadIdx.x; m < MP; m += kBlock) {
         double s[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int64_t b = b0; b < b1; b += 4) {   // chunks are multiples of 32 rows
+        for (int64_t b = b0; b < b1; b += 32) {   // chunks are multiples of 32 rows
+            float v[32];   // 32 loads in flight, then the sums in row order
 #pragma unroll
-            for (int q = 0; q < 4; ++q) s[q] += (double)dzf[(b + q) * MP + m];
+            for (int q = 0; q < 32; ++q) v[q] = dzf[(b + q) * MP + m];
+#pragma unroll
+            for (int q = 0; q < 32; ++q) s[q & 3] += (double)v[q];
         }
         part_b[c * MP + m] = (s[0] + s[1]) + (s[2] + s[3]);
     }
@@ -924,11 +956,11 @@ hipError_t launch_adam(const NetBufs &net, const float *grads, float lr, float b
 }
 
 hipError_t launch_standardise(const float *feat, const float *resid, const int32_t *idx, int64_t nrows, int64_t B,
-                              const float *mean_inv, const float inv_scale[3], uint16_t *x0, float *t,
+                              const float *mean_inv, const float inv_scale[3], uint16_t *x0, uint16_t *x0t, float *t,
                               hipStream_t st) {
     if (B <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_standardise, dim3(blocks(B * kK1)), dim3(kBlock), 0, st, feat, resid, idx, nrows, B, mean_inv,
-                       inv_scale[0], inv_scale[1], inv_scale[2], x0, t);
+    hipLaunchKernelGGL(k_standardise, dim3((unsigned)((B + kStdRows - 1) / kStdRows)), dim3(kBlock), 0, st, feat, resid,
+                       idx, nrows, B, mean_inv, inv_scale[0], inv_scale[1], inv_scale[2], x0, x0t, t);
     return hipGetLastError();
 }
 
@@ -953,11 +985,6 @@ hipError_t launch_forward(const NetBufs &net, const TrainBufs &tb, int64_t B, bo
     return hipGetLastError();
 }
 
-static void transpose(const uint16_t *src, int64_t R, int64_t C, uint16_t *dst, hipStream_t st) {
-    hipLaunchKernelGGL(k_transpose, dim3((unsigned)((R + 63) / 64), (unsigned)((C + 63) / 64)), dim3(kBlock), 0, st, src,
-                       R, C, dst);
-}
-
 hipError_t launch_backward(const NetBufs &net, const TrainBufs &tb, int64_t B, float *grads, float *loss,
                            hipStream_t st) {
     const dim3 gr(tile_blocks(B)), bl(kBlock);
@@ -968,9 +995,8 @@ hipError_t launch_backward(const NetBufs &net, const TrainBufs &tb, int64_t B, f
                        tb.dzt[1]);
     hipLaunchKernelGGL((k_dense_bwd<4, 8>), gr, bl, 0, st, tb.dz[1], net.wn[1], tb.z[0], B, tb.dzf[0], tb.dz[0],
                        tb.dzt[0]);
-    // the transposed layer input for the first layer's products over the batch
-    // (the other transposed copies were written by their producing kernels)
-    transpose(tb.x0, B, kK1, tb.x0t, st);
+    // (the transposed layer input of the first layer was written with it by
+    // k_standardise, the other transposed copies by their producing kernels)
     const unsigned nc = (unsigned)n_chunks(B);
     hipLaunchKernelGGL((k_wgrad<8, 14>), dim3(nc), bl, 0, st, tb.dzt[0], tb.x0t, tb.dzf[0], B, tb.part_w[0], tb.part_b[0]);
     hipLaunchKernelGGL((k_wgrad<8, 8>), dim3(nc), bl, 0, st, tb.dzt[1], tb.ht[0], tb.dzf[1], B, tb.part_w[1], tb.part_b[1]);

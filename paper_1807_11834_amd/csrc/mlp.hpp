@@ -62,7 +62,7 @@ struct NetBufs {
 // Kernel launchers (mlp.hip).  All enqueue on `st` and return the launch status.
 hipError_t launch_cast(const NetBufs &net, hipStream_t st);
 hipError_t launch_standardise(const float *feat, const float *resid, const int32_t *idx, int64_t nrows, int64_t B,
-                              const float *mean_inv, const float inv_scale[3], uint16_t *x0, float *t,
+                              const float *mean_inv, const float inv_scale[3], uint16_t *x0, uint16_t *x0t, float *t,
                               hipStream_t st);
 hipError_t launch_forward(const NetBufs &net, const TrainBufs &tb, int64_t B, bool with_loss, hipStream_t st);
 hipError_t launch_backward(const NetBufs &net, const TrainBufs &tb, int64_t B, float *grads, float *loss,

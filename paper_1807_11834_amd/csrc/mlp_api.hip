@@ -287,7 +287,8 @@ extern "C" int couple_mlp_forward(couple_mlp *m, const float *feat, int64_t n, f
     float is[3];
     inv_scale(m, is);
     (void)hipGetLastError();
-    if (launch_standardise(feat, nullptr, nullptr, n, n, m->net.mean_inv, is, m->tb.x0, nullptr, st) != hipSuccess ||
+    if (launch_standardise(feat, nullptr, nullptr, n, n, m->net.mean_inv, is, m->tb.x0, nullptr, nullptr, st) !=
+            hipSuccess ||
         launch_forward(m->net, m->tb, n, false, st) != hipSuccess || launch_output(m->tb, n, y, st) != hipSuccess)
         return mfail(m, COUPLE_EHIP, "couple_mlp_forward: launch failed");
     return COUPLE_OK;
@@ -302,7 +303,8 @@ static int grads_impl(couple_mlp *m, const char *who, const float *feat, const f
     float is[3];
     inv_scale(m, is);
     (void)hipGetLastError();
-    if (launch_standardise(feat, resid, idx, nrows, B, m->net.mean_inv, is, m->tb.x0, m->tb.t, st) != hipSuccess ||
+    if (launch_standardise(feat, resid, idx, nrows, B, m->net.mean_inv, is, m->tb.x0, m->tb.x0t, m->tb.t, st) !=
+            hipSuccess ||
         launch_forward(m->net, m->tb, B, true, st) != hipSuccess ||
         launch_backward(m->net, m->tb, B, grads, loss, st) != hipSuccess)
         return mfail(m, COUPLE_EHIP, std::string(who) + ": launch failed");

@@ -82,19 +82,22 @@ def collect(pool: PairPool, cfg: Config, pos, vel, diam, fine, steps, per_step, 
 
 def train(mlp: Mlp, feat, resid, steps, batch, seed, log_every=0, log=None):
     """``steps`` Adam steps on batches drawn without replacement from a fresh
-    permutation of the pairs each epoch (PCG64, seed).  Returns the losses read
+    permutation of the pairs each epoch, drawn on the device (torch's generator
+    seeded with ``seed``: a permutation of millions of pairs drawn on the host
+    would cost more than the epoch's training steps).  Returns the losses read
     back every ``log_every`` steps (none when 0)."""
     n = feat.shape[0]
     assert batch <= n and batch % 32 == 0
-    rng = np.random.default_rng(seed)
     dev = feat.device
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(int(seed))
     loss = torch.zeros(1, dtype=torch.float32, device=dev)
     perm, at = None, n
     hist = []
     t0 = time.perf_counter()
     for it in range(steps):
         if at + batch > n:
-            perm = torch.from_numpy(rng.permutation(n).astype(np.int32)).to(dev)
+            perm = torch.randperm(n, generator=gen, device=dev, dtype=torch.int32)
             at = 0
         want = log_every and (it % log_every == 0 or it == steps - 1)
         mlp.train_step(feat, resid, batch, idx=perm[at:at + batch], loss=loss if want else None)
