@@ -109,8 +109,9 @@ static ScratchPlan scratch_plan(const couple_config &c, int64_t nmax) {
     // grid of any kernel that writes partials
     const int64_t dblk = deposit_blocks(c.nb, ncell, c.deposit == COUPLE_CIC);
     const int64_t mblk = mlp_check_blocks(bricks_of(c.nb));
+    const int64_t prblk = prolong_tiles(c.nb);
     p.part_stride = 1;
-    for (int64_t b : {pblk, cblk, ntile, dblk, mblk})
+    for (int64_t b : {pblk, cblk, ntile, dblk, mblk, prblk})
         if (b > p.part_stride) p.part_stride = b;
     p.bytes[B_KEYS_A] = p.bytes[B_KEYS_B] = p.bytes[B_VALS_A] = p.bytes[B_VALS_B] = sizeof(uint32_t) * nmax;
     p.bytes[B_HIST] = sizeof(uint32_t) * 256 * ntile;

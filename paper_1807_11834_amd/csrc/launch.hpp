@@ -134,4 +134,8 @@ template <typename T, int SM> int launch_deposit_force(const StepArgs<T> &a, hip
 template <typename T, int SM> int launch_deposit_semi(const StepArgs<T> &a, hipStream_t st);
 int deposit_blocks(const int nb[3], int64_t ncell, int cic);
 
+// Workgroups of a prolongation launch (stages.hip), one FP64 partial each per
+// prolonged field.
+int64_t prolong_tiles(const int nb[3]);
+
 }  // namespace cpl

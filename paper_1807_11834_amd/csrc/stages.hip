@@ -40,20 +40,32 @@ namespace cpl {
 // ---------------------------------------------------------------------------
 template <typename T, int R> struct Row { T v[R]; };
 
-template <typename T, int R> __device__ __forceinline__ Row<T, R> load_row(const T *__restrict__ p) {
+template <typename T, int N> using NtVec = T __attribute__((ext_vector_type(N)));
+
+// STREAM: non-temporal loads, for fine rows that no later kernel of the step
+// reads again (k_restrict, k_restrict_alpha); the brick kernel's rows use
+// ordinary loads, since the stencils of its particles near a brick face read
+// the neighbouring bricks' rows from the cache.
+template <typename T, int N, bool STREAM> __device__ __forceinline__ NtVec<T, N> load_vec(const T *__restrict__ p) {
+    const NtVec<T, N> *q = reinterpret_cast<const NtVec<T, N> *>(p);
+    if constexpr (STREAM) return __builtin_nontemporal_load(q);
+    else return *q;
+}
+
+template <typename T, int R, bool STREAM = false>
+__device__ __forceinline__ Row<T, R> load_row(const T *__restrict__ p) {
     Row<T, R> r;
     if constexpr (std::is_same<T, float>::value && R == 4) {
-        float4 q = *reinterpret_cast<const float4 *>(p);
+        const NtVec<float, 4> q = load_vec<float, 4, STREAM>(p);
         r.v[0] = q.x; r.v[1] = q.y; r.v[2] = q.z; r.v[3] = q.w;
     } else if constexpr (std::is_same<T, float>::value && R == 2) {
-        float2 q = *reinterpret_cast<const float2 *>(p);
+        const NtVec<float, 2> q = load_vec<float, 2, STREAM>(p);
         r.v[0] = q.x; r.v[1] = q.y;
     } else if constexpr (std::is_same<T, double>::value && R == 4) {
-        double2 a = reinterpret_cast<const double2 *>(p)[0];
-        double2 b = reinterpret_cast<const double2 *>(p)[1];
+        const NtVec<double, 2> a = load_vec<double, 2, STREAM>(p), b = load_vec<double, 2, STREAM>(p + 2);
         r.v[0] = a.x; r.v[1] = a.y; r.v[2] = b.x; r.v[3] = b.y;
     } else if constexpr (std::is_same<T, double>::value && R == 2) {
-        double2 a = *reinterpret_cast<const double2 *>(p);
+        const NtVec<double, 2> a = load_vec<double, 2, STREAM>(p);
         r.v[0] = a.x; r.v[1] = a.y;
     } else {
         for (int k = 0; k < R; ++k) r.v[k] = p[k];
@@ -64,8 +76,6 @@ template <typename T, int R> __device__ __forceinline__ Row<T, R> load_row(const
 // Fine-grid rows written once and not read again in the step: non-temporal
 // stores, so that the 4 GB written per prolongation do not sit dirty in the
 // caches and slow the next kernels while they are written back.
-template <typename T, int N> using NtVec = T __attribute__((ext_vector_type(N)));
-
 template <typename T, int R> __device__ __forceinline__ void store_row(T *__restrict__ p, const T *v) {
     if constexpr (std::is_same<T, float>::value && R == 4) {
         const NtVec<float, 4> q = {v[0], v[1], v[2], v[3]};
@@ -182,7 +192,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict(StepArgs<T> a) {
 #pragma unroll
             for (int lz = 0; lz < R; ++lz)
 #pragma unroll
-                for (int ly = 0; ly < R; ++ly) rows[lz][ly] = load_row<T, R>(q + lz * nfxy + ly * nfx);
+                for (int ly = 0; ly < R; ++ly) rows[lz][ly] = load_row<T, R, true>(q + lz * nfxy + ly * nfx);
             // per fine child plane, then the planes in order (with a Kahan sum,
             // s_0, -c_0, s_1, ...): the same sums as the brick-tiled kernel
             ChildSum<T, SM> acc;
@@ -225,7 +235,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict_alpha(StepArgs<T> a) {
 #pragma unroll
     for (int lz = 0; lz < R; ++lz)
 #pragma unroll
-        for (int ly = 0; ly < R; ++ly) rows[lz][ly] = load_row<T, R>(q + lz * nfxy + ly * nfx);
+        for (int ly = 0; ly < R; ++ly) rows[lz][ly] = load_row<T, R, true>(q + lz * nfxy + ly * nfx);
     ChildSum<T, SM> acc;
 #pragma unroll
     for (int lz = 0; lz < R; ++lz) {
@@ -336,23 +346,26 @@ __device__ __forceinline__ void brick_fill(const StepArgs<T> &a, BrickLds<T, R> 
     const bool inside = cx < g.nb[0] && cy < g.nb[1] && cz < g.nb[2];
     const int64_t nx = g.nb[0], nxy = (int64_t)g.nb[0] * g.nb[1];
     const int64_t nfx = g.nf[0], nfxy = (int64_t)g.nf[0] * g.nf[1];
-    // the brick's particle rows and phi with its halo (indices clamped at the walls)
+    // Every load of the fill is issued before the first LDS write: the brick's
+    // particle rows (their first sorted position and count), phi with its halo
+    // (indices clamped at the walls) and the fine rows, so that a workgroup
+    // waits for one memory round trip instead of three.
+    static_assert(kBrickHalo <= kBrickThreads, "one halo value per thread");
+    int32_t seg0 = 0, seg1 = 0;
     if (t < kBrickRows) {
         const int wx = (ox + kBrickX < g.nb[0]) ? kBrickX : g.nb[0] - ox;
         const int ry = oy + t % kBrickY, rzz = oz + t / kBrickY;
-        int32_t b0 = 0, c = 0;
         if (ry < g.nb[1] && rzz < g.nb[2]) {
             const int64_t c0 = ox + nx * ry + nxy * rzz;
-            b0 = seg_clamp(a.start[c0], a.n);
-            c = seg_clamp(a.start[c0 + wx], a.n) - b0;
+            seg0 = a.start[c0];
+            seg1 = a.start[c0 + wx];
         }
-        L.beg[t] = b0;
-        L.cnt[t] = c;
     }
-    for (int h = t; h < kBrickHalo; h += kBrickThreads) {
-        const int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
+    const int hx = t % HX, hy = (t / HX) % HY, hz = t / (HX * HY);
+    T ph = T(0);
+    if (t < kBrickHalo) {
         const int gx = clampi(ox - 1 + hx, g.nb[0]), gy = clampi(oy - 1 + hy, g.nb[1]), gz = clampi(oz - 1 + hz, g.nb[2]);
-        L.sphi[hz][hy][hx] = a.phi[gx + nx * gy + nxy * gz];
+        ph = a.phi[gx + nx * gy + nxy * gz];
     }
     const bool work = inside && rz < R;
     const int64_t base = ((int64_t)R * cz + rz) * nfxy + (int64_t)R * cy * nfx + (int64_t)R * cx;
@@ -364,6 +377,12 @@ __device__ __forceinline__ void brick_fill(const StepArgs<T> &a, BrickLds<T, R> 
 #pragma unroll
             for (int ry = 0; ry < R; ++ry) rows[f][ry] = load_row<T, R>(a.fine[f] + base + ry * nfx);
     }
+    if (t < kBrickRows) {
+        const int32_t b0 = seg_clamp(seg0, a.n);
+        L.beg[t] = b0;
+        L.cnt[t] = seg_clamp(seg1, a.n) - b0;
+    }
+    if (t < kBrickHalo) L.sphi[hz][hy][hx] = ph;
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
         ChildSum<T, SM> plane;
@@ -661,27 +680,68 @@ template <typename T> struct ProlongSet {
     int nf;
 };
 
-template <typename T, int R>
+// One workgroup per tile of kPTX x kPTY bulk cells of one layer (a wave per
+// bulk row).  The bulk values of the tile's 3 x 3 x 3 neighbourhoods (the tile
+// with a one-cell halo, indices clamped at the walls) are staged in LDS for all
+// NF fields at once: one memory round trip per workgroup, and each cell reads
+// its 27 values at fixed offsets from one LDS address.  Each thread then
+// writes its cell's r^3 fine children of every field, one r-wide row at a
+// time (a wave's store covers kPTX cells' children on one fine row).
+constexpr int kPTX = kWave, kPTY = kBlock / kWave;
+constexpr int kPHX = kPTX + 2, kPHY = kPTY + 2, kPHalo = 3 * kPHY * kPHX;   // staged values per field
+
+int64_t prolong_tiles(const int nb[3]) {
+    return (int64_t)((nb[0] + kPTX - 1) / kPTX) * ((nb[1] + kPTY - 1) / kPTY) * nb[2];
+}
+
+template <typename T, int R, int NF>
 __global__ __launch_bounds__(kBlock) void k_prolong(StepArgs<T> a, ProlongSet<T> fs) {
+    __shared__ T sb[NF][3][kPHY][kPHX];
     __shared__ double red[kWavesPerBlock];
     const Geo<T> &g = a.g;
+    const int tnx = (g.nb[0] + kPTX - 1) / kPTX, tny = (g.nb[1] + kPTY - 1) / kPTY;
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int64_t c = tile * kBlock + threadIdx.x;
-    double sums[4] = {0.0, 0.0, 0.0, 0.0};
-    const bool counted = c >= a.own_c0 && c < a.own_c1;   // owned cells enter the fine-grid sums
-    if (c < g.ncell) {
-        int cx, cy, cz;
-        decode_cell(c, g.nb, cx, cy, cz);
-        const int64_t nx = g.nb[0], nxy = (int64_t)g.nb[0] * g.nb[1];
-        int64_t ox[3] = {(cx > 0 ? cx - 1 : 0), cx, (cx < g.nb[0] - 1 ? cx + 1 : cx)};
-        int64_t oy[3] = {(cy > 0 ? cy - 1 : 0) * nx, cy * nx, (cy < g.nb[1] - 1 ? cy + 1 : cy) * nx};
-        int64_t oz[3] = {(cz > 0 ? cz - 1 : 0) * nxy, cz * nxy, (cz < g.nb[2] - 1 ? cz + 1 : cz) * nxy};
+    const int cx0 = (int)(tile % tnx) * kPTX, cy0 = (int)((tile / tnx) % tny) * kPTY;
+    const int cz = (int)(tile / ((int64_t)tnx * tny));
+    const int64_t nx = g.nb[0], nxy = (int64_t)g.nb[0] * g.nb[1];
+    // staging: every load is issued before the first LDS write
+    constexpr int kIt = (kPHalo + kBlock - 1) / kBlock;
+    T v[NF][kIt];
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int it = 0; it < kIt; ++it) {
+            const int e = it * kBlock + (int)threadIdx.x;
+            v[f][it] = T(0);
+            if (e < kPHalo) {
+                const int i = e % kPHX, j = (e / kPHX) % kPHY, k = e / (kPHX * kPHY);
+                const int gx = clampi(cx0 - 1 + i, g.nb[0]), gy = clampi(cy0 - 1 + j, g.nb[1]),
+                          gz = clampi(cz - 1 + k, g.nb[2]);
+                v[f][it] = fs.B[f][gz * nxy + gy * nx + gx];
+            }
+        }
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int it = 0; it < kIt; ++it) {
+            const int e = it * kBlock + (int)threadIdx.x;
+            if (e < kPHalo) (&sb[f][0][0][0])[e] = (f == 0 && fs.complement0) ? T(1) - v[f][it] : v[f][it];
+        }
+    __syncthreads();
+
+    const int lane = (int)threadIdx.x % kWave, w = (int)threadIdx.x / kWave;
+    const int cx = cx0 + lane, cy = cy0 + w;
+    const bool inside = cx < g.nb[0] && cy < g.nb[1];
+    const int64_t c = cz * nxy + cy * nx + cx;
+    const bool counted = inside && c >= a.own_c0 && c < a.own_c1;   // owned cells enter the fine-grid sums
+    double sums[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) sums[f] = 0.0;
+    if (inside) {
         const int64_t nfx = g.nf[0], nfxy = (int64_t)g.nf[0] * g.nf[1];
         const int64_t fbase = (int64_t)R * cz * nfxy + (int64_t)R * cy * nfx + (int64_t)R * cx;
 #pragma unroll
-        for (int f = 0; f < 4; ++f) {
-            if (f >= fs.nf) break;   // uniform over the launch
-            const T *__restrict__ B = fs.B[f];
+        for (int f = 0; f < NF; ++f) {
             T *__restrict__ out = fs.out[f];
             T b[3][3][3];
 #pragma unroll
@@ -689,10 +749,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong(StepArgs<T> a, ProlongSet<T>
 #pragma unroll
                 for (int j = 0; j < 3; ++j)
 #pragma unroll
-                    for (int i = 0; i < 3; ++i) {
-                        T v = B[oz[k] + oy[j] + ox[i]];
-                        b[k][j][i] = (f == 0 && fs.complement0) ? T(1) - v : v;
-                    }
+                    for (int i = 0; i < 3; ++i) b[k][j][i] = sb[f][k][w + j][lane + i];
             // defect of the parent: B_c - (1/R^3) sum of the trilinear children
             T D = T(0);
             if constexpr (R > 1) {
@@ -719,32 +776,36 @@ __global__ __launch_bounds__(kBlock) void k_prolong(StepArgs<T> a, ProlongSet<T>
                 for (int j = 0; j < 3; ++j)
 #pragma unroll
                     for (int lx = 0; lx < R; ++lx) X[k][j][lx] = wsum3<T, R>(lx, b[k][j][0], b[k][j][1], b[k][j][2]);
-            T Y[3][R][R];
-#pragma unroll
-            for (int k = 0; k < 3; ++k)
-#pragma unroll
-                for (int ly = 0; ly < R; ++ly)
-#pragma unroll
-                    for (int lx = 0; lx < R; ++lx) Y[k][ly][lx] = wsum3<T, R>(ly, X[k][0][lx], X[k][1][lx], X[k][2][lx]);
+            // one child row y at a time (its y-interpolated values only are
+            // live), all its planes z
             double s = 0.0;
 #pragma unroll
-            for (int lz = 0; lz < R; ++lz)
+            for (int ly = 0; ly < R; ++ly) {
+                T Y[3][R];
 #pragma unroll
-                for (int ly = 0; ly < R; ++ly) {
+                for (int k = 0; k < 3; ++k)
+#pragma unroll
+                    for (int lx = 0; lx < R; ++lx) Y[k][lx] = wsum3<T, R>(ly, X[k][0][lx], X[k][1][lx], X[k][2][lx]);
+#pragma unroll
+                for (int lz = 0; lz < R; ++lz) {
                     T o[R];
 #pragma unroll
                     for (int lx = 0; lx < R; ++lx) {
-                        o[lx] = wsum3<T, R>(lz, Y[0][ly][lx], Y[1][ly][lx], Y[2][ly][lx]) + D;
+                        o[lx] = wsum3<T, R>(lz, Y[0][lx], Y[1][lx], Y[2][lx]) + D;
                         s += (double)o[lx];
                     }
                     store_row<T, R>(out + fbase + lz * nfxy + ly * nfx, o);
+                    // keeps the scheduler from computing every row before the
+                    // first store (all r^3 values live at once)
+                    __builtin_amdgcn_sched_barrier(0);
                 }
+            }
             sums[f] = counted ? s : 0.0;
         }
     }
-    for (int k = 0; k < 4; ++k) {
-        if (k >= fs.nf) break;
-        double t = block_sum(sums[k], red);
+#pragma unroll
+    for (int k = 0; k < NF; ++k) {
+        const double t = block_sum(sums[k], red);
         if (threadIdx.x == 0) a.part[fs.slot[k] * a.part_stride + blockIdx.x] = t;
     }
 }
@@ -844,21 +905,22 @@ static void launch_grid_stages(const StepArgs<T> &a, hipStream_t st, int phases)
     }
     }
     if (phases & kPhaseProlong) {
+    const int64_t ptiles = prolong_tiles(a.g.nb);
     a.mk->mark("prolong_eps", st);
-    hipLaunchKernelGGL((k_prolong<T, R>), dim3(cb), dim3(kBlock), 0, st, a, eps);
+    hipLaunchKernelGGL((k_prolong<T, R, 1>), dim3(ptiles), dim3(kBlock), 0, st, a, eps);
     const ProlongSet<T> src{{a.F, a.F + nc, a.F + 2 * nc, nullptr},
                             {a.fine_F, a.fine_F + nf, a.fine_F + 2 * nf, nullptr},
                             {SL_FF, SL_FF + 1, SL_FF + 2, 0},
                             0, 3};
     a.mk->mark("prolong", st);
-    hipLaunchKernelGGL((k_prolong<T, R>), dim3(cb), dim3(kBlock), 0, st, a, src);
+    hipLaunchKernelGGL((k_prolong<T, R, 3>), dim3(ptiles), dim3(kBlock), 0, st, a, src);
     if (a.semi) {
         const ProlongSet<T> semi{{a.K, a.KU, a.KU + nc, a.KU + 2 * nc},
                                  {a.fine_K, a.fine_KU, a.fine_KU + nf, a.fine_KU + 2 * nf},
                                  {SL_KF, SL_KUF, SL_KUF + 1, SL_KUF + 2},
                                  0, 4};
         a.mk->mark("prolong_semi", st);
-        hipLaunchKernelGGL((k_prolong<T, R>), dim3(cb), dim3(kBlock), 0, st, a, semi);
+        hipLaunchKernelGGL((k_prolong<T, R, 4>), dim3(ptiles), dim3(kBlock), 0, st, a, semi);
     }
     }
 }
@@ -897,10 +959,13 @@ template <typename T> hipError_t launch_stages(const StepArgs<T> &a, hipStream_t
     spec.nblk[SL_MLPERR] = nmlp;
     spec.nblk[SL_MLPREF] = nmlp;
     spec.nblk[SL_MLPSAMP] = nmlp;
+    const int ptiles = (int)prolong_tiles(a.g.nb);   // k_prolong
+    spec.nblk[SL_EPSF] = ptiles;
+    for (int k = 0; k < 3; ++k) spec.nblk[SL_FF + k] = ptiles;
     for (int k = 0; k < 4; ++k) {
         spec.nblk[SL_KP + k] = a.semi ? npart : 0;   // k_drag
         spec.nblk[SL_KB + k] = a.semi ? db : 0;      // deposition
-        spec.nblk[SL_KF + k] = a.semi ? (int)cb : 0; // prolongation
+        spec.nblk[SL_KF + k] = a.semi ? ptiles : 0;  // prolongation
         spec.scale[SL_KB + k] = a.g.vb;
         spec.scale[SL_KF + k] = a.g.vf;
     }
