@@ -36,6 +36,7 @@ COUPLE_NGP, COUPLE_CIC = 0, 1
 COUPLE_FP64, COUPLE_FP32_WIDE, COUPLE_FP32_NAIVE, COUPLE_FP32_KAHAN = 0, 1, 2, 3
 COUPLE_VEL_FINE, COUPLE_VEL_BULK, COUPLE_VEL_GIVEN, COUPLE_VEL_MLP = 0, 1, 2, 3
 COUPLE_EXCHANGE_DISTRIBUTED, COUPLE_EXCHANGE_GATHER_SCATTER = 0, 1
+COUPLE_HBMREF_READ, COUPLE_HBMREF_WRITE, COUPLE_HBMREF_COPY = 0, 1, 2
 DIAG = {"V_tot": 0, "V_dep": 1, "sum_Fp": 2, "S_b": 5, "S_f": 8, "E_f": 11, "n_clamped": 12,
         "n_outside": 13, "max_phi": 14, "n_fallback": 15, "mlp_err2": 16, "mlp_ref2": 17, "mlp_nsamp": 18,
         "K_p": 19, "KU_p": 20, "K_b": 23, "KU_b": 24, "K_f": 27, "KU_f": 28}
@@ -154,6 +155,8 @@ def _load():
     L.couple_remap_last_error.restype = C.c_char_p
     L.couple_mlp_last_error.argtypes = [P]
     L.couple_mlp_last_error.restype = C.c_char_p
+    L.couple_hbmref.argtypes = [I, P, P, I64, C.c_float, P]
+    L.couple_hbmref.restype = I
     return L
 
 
@@ -374,6 +377,28 @@ def _stream(stream):
     elif isinstance(stream, torch.cuda.Stream):
         stream = stream.cuda_stream
     return C.c_void_p(stream)
+
+
+def hbmref(kind, src, dst, value=0.0, stream=None):
+    """One pass of a streaming reference kernel (include/couple_hbmref.h) over
+    float32 device tensors: COUPLE_HBMREF_READ scans ``src`` (4 k floats) and
+    sets the one-element int32 ``dst`` to 1 if it holds a NaN or an infinity
+    (the caller clears it); COUPLE_HBMREF_WRITE fills ``dst`` with ``value``;
+    COUPLE_HBMREF_COPY copies ``src`` to ``dst``."""
+    if kind not in (COUPLE_HBMREF_READ, COUPLE_HBMREF_WRITE, COUPLE_HBMREF_COPY):
+        raise ArgumentError(f"kind: expected one of 0, 1, 2, got {kind!r}")
+    ref = dst if kind == COUPLE_HBMREF_WRITE else src
+    if not isinstance(ref, torch.Tensor) or ref.numel() % 4:
+        raise ArgumentError("the buffer must be a float32 tensor of a multiple of 4 elements")
+    n16 = ref.numel() // 4
+    dev = ref.device
+    if kind != COUPLE_HBMREF_WRITE:
+        check_tensor("src", src, torch.float32, 4 * n16, device=dev)
+    if kind == COUPLE_HBMREF_READ:
+        check_tensor("dst", dst, torch.int32, 1, device=dev, align=4)
+    else:
+        check_tensor("dst", dst, torch.float32, 4 * n16, device=dev)
+    _check(_lib.couple_hbmref(kind, _ptr(src), _ptr(dst), n16, float(value), _stream(stream)), None)
 
 
 def couple_timing_begin(h, max_steps):

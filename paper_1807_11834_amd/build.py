@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcouple.so")
-SOURCES = ["api.hip", "sort.hip", "deposit.hip", "stages.hip", "mlp.hip", "mlp_api.hip", "remap.hip", "boxmap.hip", "part.hip"]
+SOURCES = ["api.hip", "sort.hip", "deposit.hip", "stages.hip", "mlp.hip", "mlp_api.hip", "remap.hip", "boxmap.hip", "part.hip", "hbmref.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -1,5 +1,5 @@
 """CPU checks of the C ABI: the library loads, exports every entry point that
-include/couple.h, include/couple_mlp.h and include/couple_remap.h declare, its structs have the
+the headers under include/ declare, its structs have the
 headers' layout, and argument validation rejects bad calls before any device
 work."""
 import os
@@ -10,7 +10,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADERS = [os.path.join(ROOT, "include", h) for h in ("couple.h", "couple_mlp.h", "couple_remap.h",
-                                                       "couple_boxmap.h")]
+                                                       "couple_boxmap.h", "couple_hbmref.h")]
 LIB = os.path.join(ROOT, "paper_1807_11834_amd", "libcouple.so")
 
 
@@ -32,7 +32,7 @@ def test_header_declares_the_entry_points():
         "couple_boxmap_init", "couple_boxmap_apply", "couple_boxmap_info", "couple_boxmap_free",
         "couple_boxmap_last_error",
         "couple_part_init", "couple_part_step", "couple_part_comm_matrix", "couple_part_free",
-        "couple_part_last_error"])
+        "couple_part_last_error", "couple_hbmref"])
 
 
 def test_library_exports_every_declared_symbol():
@@ -241,3 +241,23 @@ def test_part_null_arguments():
     assert L.couple_part_comm_matrix(None, None) == cpl.COUPLE_EINVAL
     c = cpl.Config().to_c()
     assert L.couple_part_init(C.byref(c), 2, None) == cpl.COUPLE_EINVAL
+
+
+def test_hbmref_rejects_bad_calls_before_any_launch():
+    """The streaming reference kernels' argument checks (no device work)."""
+    import ctypes as C
+    import paper_1807_11834_amd as cpl
+    L = cpl._lib
+    buf = C.create_string_buffer(64)
+    p = C.cast(buf, C.c_void_p).value
+    p16 = (p + 15) & ~15
+    assert L.couple_hbmref(3, p16, p16, 1, 0.0, None) == cpl.COUPLE_EINVAL          # unknown kind
+    assert L.couple_hbmref(-1, p16, p16, 1, 0.0, None) == cpl.COUPLE_EINVAL
+    assert L.couple_hbmref(cpl.COUPLE_HBMREF_COPY, p16, p16, -1, 0.0, None) == cpl.COUPLE_EINVAL
+    assert L.couple_hbmref(cpl.COUPLE_HBMREF_COPY, None, p16, 1, 0.0, None) == cpl.COUPLE_EINVAL
+    assert L.couple_hbmref(cpl.COUPLE_HBMREF_READ, p16, None, 1, 0.0, None) == cpl.COUPLE_EINVAL
+    assert L.couple_hbmref(cpl.COUPLE_HBMREF_WRITE, None, p16 + 4, 1, 0.0, None) == cpl.COUPLE_EINVAL  # misaligned
+    assert L.couple_hbmref(cpl.COUPLE_HBMREF_COPY, p16 + 8, p16, 1, 0.0, None) == cpl.COUPLE_EINVAL
+    for k in (0, 1, 2):
+        assert L.couple_hbmref(k, None, None, 0, 0.0, None) == cpl.COUPLE_OK       # nothing to do
+    assert L.couple_hbmref(cpl.COUPLE_HBMREF_READ, p16, p16 + 2, 1, 0.0, None) == cpl.COUPLE_EINVAL  # flag alignment
