@@ -29,14 +29,51 @@ template <typename T> __device__ __forceinline__ T vol_over_vb(T d, T inv_vb) {
     return (T(kPi / 6.0) * d * d * d) * inv_vb;
 }
 
-// Bulk pressure gradient of cell c written to G ([3][ncell]).
+// Bulk pressure gradient of cell c written to G ([3][ncell]), in the arithmetic
+// of gradient_at(): the cell's and its six neighbours' (hi, lo) pressure are
+// loaded first, unconditionally (a neighbour beyond a wall is the cell itself),
+// so that a kernel can issue these loads with its others and wait once.
+template <typename T> struct GradLoads {
+    T hi[7], lo[7];   // centre, then (low, high) neighbour per axis
+};
+
 template <typename T>
-__device__ __forceinline__ void write_gradient(int64_t c, int cx, int cy, int cz, const Geo<T> &g,
-                                               const T *__restrict__ P, const T *__restrict__ Plo,
-                                               T *__restrict__ G) {
-    T gr[3];
-    gradient_at(c, cx, cy, cz, g.nb, g.hb, P, Plo, gr);
-    for (int a = 0; a < 3; ++a) G[a * g.ncell + c] = gr[a];
+__device__ __forceinline__ GradLoads<T> load_gradient(int64_t c, int cx, int cy, int cz, const Geo<T> &g,
+                                                      const T *__restrict__ P, const T *__restrict__ Plo) {
+    const int idx[3] = {cx, cy, cz};
+    const int64_t stride[3] = {1, g.nb[0], (int64_t)g.nb[0] * g.nb[1]};
+    GradLoads<T> r;
+    r.hi[0] = P[c];
+    r.lo[0] = Plo[c];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int64_t kl = idx[a] > 0 ? c - stride[a] : c, kh = idx[a] < g.nb[a] - 1 ? c + stride[a] : c;
+        r.hi[1 + 2 * a] = P[kl];
+        r.lo[1 + 2 * a] = Plo[kl];
+        r.hi[2 + 2 * a] = P[kh];
+        r.lo[2 + 2 * a] = Plo[kh];
+    }
+    return r;
+}
+
+template <typename T>
+__device__ __forceinline__ void write_gradient(const GradLoads<T> &v, int64_t c, int cx, int cy, int cz,
+                                               const Geo<T> &g, T *__restrict__ G) {
+    const int idx[3] = {cx, cy, cz};
+    const double p0 = (double)v.hi[0] + (double)v.lo[0];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double pl = (double)v.hi[1 + 2 * a] + (double)v.lo[1 + 2 * a];
+        const double ph = (double)v.hi[2 + 2 * a] + (double)v.lo[2 + 2 * a];
+        const int nax = g.nb[a];
+        const double h = (double)g.hb[a];
+        double gr;
+        if (nax == 1) gr = 0.0;
+        else if (idx[a] == 0) gr = (ph - p0) / h;
+        else if (idx[a] == nax - 1) gr = (p0 - pl) / h;
+        else gr = (ph - pl) / (2.0 * h);
+        G[a * g.ncell + c] = (T)gr;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -91,7 +128,7 @@ __global__ __launch_bounds__(kBlock) void k_deposit_ngp(const int32_t *__restric
             v[0] = fx; v[1] = fy; v[2] = fz;
             int cx, cy, cz;
             decode_cell(c, g.nb, cx, cy, cz);
-            write_gradient(c, cx, cy, cz, g, P, Plo, G);
+            write_gradient(load_gradient(c, cx, cy, cz, g, P, Plo), c, cx, cy, cz, g, G);
         }
     }
     if constexpr (MODE == kPhi) {
@@ -339,21 +376,31 @@ __global__ __launch_bounds__(kBlock) void k_deposit_sum(const T *__restrict__ pa
         CellSum<T, SM> acc[NC];
         const int gzl = group_lo(cz), gyl = group_lo(cy);
         const int ngy = (g.nb[1] + 1) >> 1, ngz = (g.nb[2] + 1) >> 1;
-        for (int sz = 0; sz < 2; ++sz) {
-            if (gzl + sz < 0 || gzl + sz >= ngz) continue;
+        GradLoads<T> gl;
+        if constexpr (MODE == kForce) gl = load_gradient(c, cx, cy, cz, g, P, Plo);
+        // all four slots loaded at once (in the partial buffer whether or not
+        // their source group exists), then the existing ones summed in order
+        T pv[4][NC];
+#pragma unroll
+        for (int slot = 0; slot < 4; ++slot)
+#pragma unroll
+            for (int k = 0; k < NC; ++k) pv[slot][k] = partial[((int64_t)slot * NC + k) * g.ncell + c];
+#pragma unroll
+        for (int sz = 0; sz < 2; ++sz)
+#pragma unroll
             for (int sy = 0; sy < 2; ++sy) {
-                if (gyl + sy < 0 || gyl + sy >= ngy) continue;
-                const int slot = sz * 2 + sy;
-                for (int k = 0; k < NC; ++k) acc[k].add(partial[((int64_t)slot * NC + k) * g.ncell + c]);
+                const bool has = gzl + sz >= 0 && gzl + sz < ngz && gyl + sy >= 0 && gyl + sy < ngy;
+                if (has)
+#pragma unroll
+                    for (int k = 0; k < NC; ++k) acc[k].add(pv[sz * 2 + sy][k]);
             }
-        }
         if constexpr (MODE == kForce) {
             const T fx = -acc[0].value() * g.inv_vb, fy = -acc[1].value() * g.inv_vb, fz = -acc[2].value() * g.inv_vb;
             out[c] = fx;
             out[g.ncell + c] = fy;
             out[2 * g.ncell + c] = fz;
             v[0] = fx; v[1] = fy; v[2] = fz;
-            write_gradient(c, cx, cy, cz, g, P, Plo, G);
+            write_gradient(gl, c, cx, cy, cz, g, G);
         } else if constexpr (MODE == kSemi) {
             out[c] = acc[0].value() * g.inv_vb;
             for (int k = 0; k < 3; ++k) out2[k * g.ncell + c] = acc[k + 1].value() * g.inv_vb;
