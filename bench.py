@@ -68,8 +68,8 @@ def step_alg_bytes(n, ncell, nfine, fsz, sort_passes):
 # Marks of the library's kernel timing -> the kernel names rocprofv3 reports.
 PROFILE_NAMES = {
     "restrict_lookup": "cpl::k_restrict_brick<float, 4, 2>",
-    "restrict_p": "cpl::k_restrict<float, 4, 2, 3, 4>",
-    "restrict": "cpl::k_restrict<float, 4, 2, 0, 4>",
+    "restrict_p": "cpl::k_restrict_planes<float, 2, 3, 4, false>",
+    "restrict": "cpl::k_restrict_planes<float, 2, 0, 4, false>",
     "prolong": "cpl::k_prolong<float, 4, 3>",
     "mlp_infer": "cpl::mlp::k_infer",
 }

@@ -218,6 +218,62 @@ __global__ __launch_bounds__(kBlock) void k_restrict(StepArgs<T> a) {
     }
 }
 
+// The same restrictions for r = 4 with four threads per bulk cell, one per fine
+// child plane (64 cells per workgroup): a thread loads its plane's 4 x 4 child
+// values of every field with streaming loads and sums them, and the cell's four
+// plane sums are combined in order through cross-lane reads, the sums of the
+// per-cell kernel above bit for bit.  A wave's row load covers 16 cells x 4
+// planes, whole 128-byte lines, and each thread keeps a quarter of the per-cell
+// kernel's loads in flight.  ALPHA: the liquid fraction instead of (u, v, w, p).
+constexpr int kPlaneCells = kBlock / 4;   // bulk cells per workgroup
+
+template <typename T, int SM, int F0, int F1, bool ALPHA>
+__global__ __launch_bounds__(kBlock) void k_restrict_planes(StepArgs<T> a) {
+    constexpr int R = 4, NF = ALPHA ? 1 : F1 - F0;
+    const Geo<T> &g = a.g;
+    const int t = (int)threadIdx.x, lane = t % kWave, rz = t & 3;
+    const int64_t c = xcd_tile(blockIdx.x, gridDim.x) * kPlaneCells + (t >> 2);
+    const bool inside = c < g.ncell;
+    int cx, cy, cz;
+    decode_cell(inside ? c : g.ncell - 1, g.nb, cx, cy, cz);   // every lane takes part in the cross-lane reads
+    const int64_t nfx = g.nf[0], nfxy = (int64_t)g.nf[0] * g.nf[1];
+    const int64_t base = ((int64_t)R * cz + rz) * nfxy + (int64_t)R * cy * nfx + (int64_t)R * cx;
+    Row<T, R> rows[NF][R];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        const T *__restrict__ q = (ALPHA ? a.fine_alpha : a.fine[F0 + f]) + base;
+#pragma unroll
+        for (int ry = 0; ry < R; ++ry) rows[f][ry] = load_row<T, R, true>(q + ry * nfx);
+    }
+    const T inv = T(1) / T(R * R * R);
+    const int l0 = lane & ~3;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        ChildSum<T, SM> plane;
+#pragma unroll
+        for (int ry = 0; ry < R; ++ry)
+#pragma unroll
+            for (int rx = 0; rx < R; ++rx) plane.add(rows[f][ry].v[rx]);
+        ChildSum<T, SM> acc;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const auto sk = __shfl(plane.acc.s, l0 + k, kWave);
+            const auto ck = ChildSum<T, SM>::kComp ? __shfl(plane.acc.c, l0 + k, kWave) : plane.acc.c;
+            acc.add_plane(sk, ck);
+        }
+        if (inside && rz == 0) {
+            if constexpr (ALPHA) {
+                a.alpha[c] = acc.hi(inv);
+            } else if (F0 + f < 3) {
+                a.U[(F0 + f) * g.ncell + c] = acc.hi(inv);
+            } else {
+                a.P[c] = acc.hi(inv);
+                a.Plo[c] = acc.lo(inv);
+            }
+        }
+    }
+}
+
 // Restriction of the liquid volume fraction (two-fluid drag): the bulk alpha is
 // the average of the r^3 fine children (the volume average that defines alpha),
 // summed per fine child plane and then the planes in order, as for U and P.
@@ -852,6 +908,17 @@ __global__ __launch_bounds__(kWave) void k_diag2(const double *__restrict__ part
 // ---------------------------------------------------------------------------
 // Host dispatch
 // ---------------------------------------------------------------------------
+// Restriction of fields F0 .. F1 - 1: four threads per cell for r = 4, one
+// otherwise.
+template <typename T, int R, int SM, int F0, int F1> static void restrict_fields(const StepArgs<T> &a, hipStream_t st) {
+    if constexpr (R == 4)
+        hipLaunchKernelGGL((k_restrict_planes<T, SM, F0, F1, false>),
+                           dim3((unsigned)((a.g.ncell + kPlaneCells - 1) / kPlaneCells)), dim3(kBlock), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_restrict<T, R, SM, F0, F1>), dim3((unsigned)((a.g.ncell + kBlock - 1) / kBlock)),
+                           dim3(kBlock), 0, st, a);
+}
+
 template <typename T, int R, int SM>
 static void launch_grid_stages(const StepArgs<T> &a, hipStream_t st, int phases) {
     const int64_t cb = (a.g.ncell + kBlock - 1) / kBlock;
@@ -863,7 +930,7 @@ static void launch_grid_stages(const StepArgs<T> &a, hipStream_t st, int phases)
     if (a.vel_source == 0) {
         // the pressure (for the gradient only), then u, v, w with the lookup
         a.mk->mark("restrict_p", st);
-        hipLaunchKernelGGL((k_restrict<T, R, SM, 3, 4>), dim3(cb), dim3(kBlock), 0, st, a);
+        restrict_fields<T, R, SM, 3, 4>(a, st);
         a.mk->mark("restrict_lookup", st);
         const int64_t nbk = brick_blocks<T, R>(a.g);
         const BrickGrid<T> bg{(a.g.nb[0] + kBrickX - 1) / kBrickX, (a.g.nb[1] + kBrickY - 1) / kBrickY};
@@ -871,7 +938,7 @@ static void launch_grid_stages(const StepArgs<T> &a, hipStream_t st, int phases)
     } else if (a.vel_source == 3) {
         if constexpr (std::is_same<T, float>::value) {
             a.mk->mark("restrict", st);
-            hipLaunchKernelGGL((k_restrict<T, R, SM, 0, 4>), dim3(cb), dim3(kBlock), 0, st, a);
+            restrict_fields<T, R, SM, 0, 4>(a, st);
             a.mk->mark("mlp_pack", st);
             launch_mlp_pack(a, st);
             if (a.n > 0) {
@@ -883,13 +950,17 @@ static void launch_grid_stages(const StepArgs<T> &a, hipStream_t st, int phases)
         }
     } else {
         a.mk->mark("restrict", st);
-        hipLaunchKernelGGL((k_restrict<T, R, SM, 0, 4>), dim3(cb), dim3(kBlock), 0, st, a);
+        restrict_fields<T, R, SM, 0, 4>(a, st);
         if (a.n > 0) a.mk->mark("sample", st);
         if (a.n > 0) hipLaunchKernelGGL(k_sample<T>, dim3(pb), dim3(kBlock), 0, st, a);
     }
     if (a.vof) {
         a.mk->mark("restrict_alpha", st);
-        hipLaunchKernelGGL((k_restrict_alpha<T, R, SM>), dim3(cb), dim3(kBlock), 0, st, a);
+        if constexpr (R == 4)
+            hipLaunchKernelGGL((k_restrict_planes<T, SM, 0, 1, true>), dim3((unsigned)((nc + kPlaneCells - 1) / kPlaneCells)),
+                               dim3(kBlock), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_restrict_alpha<T, R, SM>), dim3(cb), dim3(kBlock), 0, st, a);
         if (a.n > 0) a.mk->mark("pack_alpha", st);
         if (a.n > 0) hipLaunchKernelGGL(k_pack_alpha8<T>, dim3(cb), dim3(kBlock), 0, st, a);
     }
