@@ -118,7 +118,8 @@ static ScratchPlan scratch_plan(const couple_config &c, int64_t nmax) {
     p.bytes[B_TOTALS] = sizeof(uint32_t) * 256;
     p.bytes[B_SP] = p.bytes[B_UF4] = 4 * fsz * nmax;
     p.bytes[B_PLO] = fsz * ncell;
-    p.bytes[B_DEP] = (c.deposit == COUPLE_CIC ? (c.semi_implicit ? 16 : 12) : 1) * fsz * ncell;
+    const int dep_slots = deposit_group(c.nb) == 1 ? 9 : 4;   // CIC partial slots per cell and component
+    p.bytes[B_DEP] = (c.deposit == COUPLE_CIC ? dep_slots * (c.semi_implicit ? 4 : 3) : 1) * fsz * ncell;
     p.bytes[B_PART] = sizeof(double) * (SL_COUNT * p.part_stride + SL_COUNT * 64);
     p.bytes[B_FGRID] = c.vel_source == COUPLE_VEL_MLP ? sizeof(float4) * 2 * ncell : 0;
     p.bytes[B_ALPHA8] = c.vof ? 8 * fsz * ncell : 0;

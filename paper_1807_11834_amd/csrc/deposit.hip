@@ -196,13 +196,20 @@ __device__ __forceinline__ void row_weights(const Axis<T> &a, int c, T w[3]) {
     }
 }
 
-// Lowest source group (of 2 rows) that reaches target row t: floor((t - 1) / 2).
-__device__ __forceinline__ int group_lo(int t) { return ((t + 1) >> 1) - 1; }
+// Lowest source group (of G rows) that reaches target row t: floor((t - 1) / G)
+// (-1 for t = 0).
+template <int G> __device__ __forceinline__ int group_lo(int t) {
+    if constexpr (G == 2) return ((t + 1) >> 1) - 1;
+    else return t - 1;
+}
+// Source groups a target row receives from, per axis.
+template <int G> struct GroupSlots { static constexpr int value = G == 1 ? 3 : 2; };
 
 // One source row (ys, zs) of the wave's group: row JY, layer KZ of the group.
-// Its contributions go to the accumulators [KZ + 0..2][JY + 0..2].
-template <typename T, int SM, int MODE, int JY, int KZ>
-__device__ __forceinline__ void deposit_source_row(RowSum<T, SM> (&acc)[4][4][DepNc<MODE>::value],
+// Its contributions go to the accumulators [KZ + 0..2][JY + 0..2] (A = G + 2
+// target rows per axis).
+template <typename T, int SM, int MODE, int JY, int KZ, int A>
+__device__ __forceinline__ void deposit_source_row(RowSum<T, SM> (&acc)[A][A][DepNc<MODE>::value],
                                                    RowStage<T, MODE> &st, int w, int lane, int x0, int ys, int zs,
                                                    const int32_t *__restrict__ start, const vec4<T> *__restrict__ sp,
                                                    const int32_t *__restrict__ perm, const T *__restrict__ drag,
@@ -311,19 +318,19 @@ __device__ __forceinline__ void deposit_source_row(RowSum<T, SM> (&acc)[4][4][De
     }
 }
 
-template <typename T, int SM, int MODE>
+template <typename T, int SM, int MODE, int GS>
 __global__ __launch_bounds__(kBlock) void k_deposit_rows(const int32_t *__restrict__ start,
                                                          const vec4<T> *__restrict__ sp,
                                                          const int32_t *__restrict__ perm,
                                                          const T *__restrict__ drag,
                                                          const vec4<T> *__restrict__ src4, int64_t n, Geo<T> g,
                                                          T *__restrict__ partial) {
-    constexpr int NC = DepNc<MODE>::value;
+    constexpr int NC = DepNc<MODE>::value, A = GS + 2, S = GroupSlots<GS>::value;
     __shared__ RowStage<T, MODE> st;
     const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int nbx = g.nb[0], nby = g.nb[1], nbz = g.nb[2];
     const int nseg = (nbx + kWave - 1) / kWave;
-    const int ngy = (nby + 1) >> 1, ngz = (nbz + 1) >> 1;
+    const int ngy = (nby + GS - 1) / GS, ngz = (nbz + GS - 1) / GS;
     const int64_t nwave = (int64_t)ngy * ngz * nseg;
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t gw = tile * kWavesPerBlock + w;        // (source group, segment)
@@ -332,28 +339,32 @@ __global__ __launch_bounds__(kBlock) void k_deposit_rows(const int32_t *__restri
     const int x0 = (int)(gw % nseg) * kWave;
     const int gy = (int)(grp % ngy), gz = (int)(grp / ngy);
     const int x = x0 + lane;
-    const int y0 = 2 * gy, z0 = 2 * gz;
-    RowSum<T, SM> acc[4][4][NC];   // [target z - (z0 - 1)][target y - (y0 - 1)][component]
-    deposit_source_row<T, SM, MODE, 0, 0>(acc, st, w, lane, x0, y0, z0, start, sp, perm, drag, src4, n, g);
-    if (y0 + 1 < nby)
-        deposit_source_row<T, SM, MODE, 1, 0>(acc, st, w, lane, x0, y0 + 1, z0, start, sp, perm, drag, src4, n, g);
-    if (z0 + 1 < nbz) {
-        deposit_source_row<T, SM, MODE, 0, 1>(acc, st, w, lane, x0, y0, z0 + 1, start, sp, perm, drag, src4, n, g);
+    const int y0 = GS * gy, z0 = GS * gz;
+    RowSum<T, SM> acc[A][A][NC];   // [target z - (z0 - 1)][target y - (y0 - 1)][component]
+    deposit_source_row<T, SM, MODE, 0, 0, A>(acc, st, w, lane, x0, y0, z0, start, sp, perm, drag, src4, n, g);
+    if constexpr (GS == 2) {
         if (y0 + 1 < nby)
-            deposit_source_row<T, SM, MODE, 1, 1>(acc, st, w, lane, x0, y0 + 1, z0 + 1, start, sp, perm, drag,
-                                                     src4, n, g);
+            deposit_source_row<T, SM, MODE, 1, 0, A>(acc, st, w, lane, x0, y0 + 1, z0, start, sp, perm, drag, src4, n,
+                                                     g);
+        if (z0 + 1 < nbz) {
+            deposit_source_row<T, SM, MODE, 0, 1, A>(acc, st, w, lane, x0, y0, z0 + 1, start, sp, perm, drag, src4, n,
+                                                     g);
+            if (y0 + 1 < nby)
+                deposit_source_row<T, SM, MODE, 1, 1, A>(acc, st, w, lane, x0, y0 + 1, z0 + 1, start, sp, perm, drag,
+                                                         src4, n, g);
+        }
     }
     if (x >= nbx) return;
 #pragma unroll
-    for (int kz = 0; kz < 4; ++kz) {
+    for (int kz = 0; kz < A; ++kz) {
         const int tz = z0 - 1 + kz;
         if (tz < 0 || tz >= nbz) continue;
-        const int sz = gz - group_lo(tz);                // 0 or 1
+        const int sz = gz - group_lo<GS>(tz);             // 0 .. S - 1
 #pragma unroll
-        for (int jy = 0; jy < 4; ++jy) {
+        for (int jy = 0; jy < A; ++jy) {
             const int ty = y0 - 1 + jy;
             if (ty < 0 || ty >= nby) continue;
-            const int slot = sz * 2 + (gy - group_lo(ty));
+            const int slot = sz * S + (gy - group_lo<GS>(ty));
             const int64_t tc = ((int64_t)tz * nby + ty) * nbx + x;
 #pragma unroll
             for (int c = 0; c < NC; ++c) partial[((int64_t)slot * NC + c) * g.ncell + tc] = T(acc[kz][jy][c].s);
@@ -361,12 +372,12 @@ __global__ __launch_bounds__(kBlock) void k_deposit_rows(const int32_t *__restri
     }
 }
 
-template <typename T, int SM, int MODE>
+template <typename T, int SM, int MODE, int GS>
 __global__ __launch_bounds__(kBlock) void k_deposit_sum(const T *__restrict__ partial, Geo<T> g,
                                                         const T *__restrict__ P, const T *__restrict__ Plo,
                                                         T *__restrict__ out, T *__restrict__ out2, T *__restrict__ G,
                                                         double *__restrict__ part, int64_t ps) {
-    constexpr int NC = DepNc<MODE>::value;
+    constexpr int NC = DepNc<MODE>::value, S = GroupSlots<GS>::value;
     __shared__ double red[kWavesPerBlock];
     const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     double v[4] = {0.0, 0.0, 0.0, 0.0};
@@ -374,25 +385,25 @@ __global__ __launch_bounds__(kBlock) void k_deposit_sum(const T *__restrict__ pa
         int cx, cy, cz;
         decode_cell(c, g.nb, cx, cy, cz);
         CellSum<T, SM> acc[NC];
-        const int gzl = group_lo(cz), gyl = group_lo(cy);
-        const int ngy = (g.nb[1] + 1) >> 1, ngz = (g.nb[2] + 1) >> 1;
+        const int gzl = group_lo<GS>(cz), gyl = group_lo<GS>(cy);
+        const int ngy = (g.nb[1] + GS - 1) / GS, ngz = (g.nb[2] + GS - 1) / GS;
         GradLoads<T> gl;
         if constexpr (MODE == kForce) gl = load_gradient(c, cx, cy, cz, g, P, Plo);
-        // all four slots loaded at once (in the partial buffer whether or not
+        // all S x S slots loaded at once (in the partial buffer whether or not
         // their source group exists), then the existing ones summed in order
-        T pv[4][NC];
+        T pv[S * S][NC];
 #pragma unroll
-        for (int slot = 0; slot < 4; ++slot)
+        for (int slot = 0; slot < S * S; ++slot)
 #pragma unroll
             for (int k = 0; k < NC; ++k) pv[slot][k] = partial[((int64_t)slot * NC + k) * g.ncell + c];
 #pragma unroll
-        for (int sz = 0; sz < 2; ++sz)
+        for (int sz = 0; sz < S; ++sz)
 #pragma unroll
-            for (int sy = 0; sy < 2; ++sy) {
+            for (int sy = 0; sy < S; ++sy) {
                 const bool has = gzl + sz >= 0 && gzl + sz < ngz && gyl + sy >= 0 && gyl + sy < ngy;
                 if (has)
 #pragma unroll
-                    for (int k = 0; k < NC; ++k) acc[k].add(pv[sz * 2 + sy][k]);
+                    for (int k = 0; k < NC; ++k) acc[k].add(pv[sz * S + sy][k]);
             }
         if constexpr (MODE == kForce) {
             const T fx = -acc[0].value() * g.inv_vb, fy = -acc[1].value() * g.inv_vb, fz = -acc[2].value() * g.inv_vb;
@@ -440,10 +451,18 @@ int deposit_blocks(const int nb[3], int64_t ncell, int cic) {
     return (int)((ncell + kBlock - 1) / kBlock);   // NGP kernel and CIC pass 2
 }
 
-static int row_blocks(const int nb[3]) {
+static int64_t row_waves(const int nb[3], int G) {
     const int64_t nseg = (nb[0] + kWave - 1) / kWave;
-    const int64_t nwave = (int64_t)((nb[1] + 1) / 2) * ((nb[2] + 1) / 2) * nseg;
-    return (int)((nwave + kWavesPerBlock - 1) / kWavesPerBlock);
+    return (int64_t)((nb[1] + G - 1) / G) * ((nb[2] + G - 1) / G) * nseg;
+}
+
+// Source rows per group of the CIC row pass: 2 x 2 (each target row receives 4
+// partials) unless that leaves fewer than 4096 waves (four per SIMD of the
+// chip), then single rows (9 partials per target, four times the waves).
+int deposit_group(const int nb[3]) { return row_waves(nb, 2) < 4096 ? 1 : 2; }
+
+static int row_blocks(const int nb[3], int G) {
+    return (int)((row_waves(nb, G) + kWavesPerBlock - 1) / kWavesPerBlock);
 }
 
 template <typename T, int SM, int MODE>
@@ -451,11 +470,16 @@ static int launch_deposit(const StepArgs<T> &a, T *out, T *out2, hipStream_t st,
     const int nblk = deposit_blocks(a.g.nb, a.g.ncell, a.cic);
     const vec4<T> *src4 = a.uf4;   // (beta, beta u_p) per particle once the drag has run
     if (a.cic) {
-        hipLaunchKernelGGL((k_deposit_rows<T, SM, MODE>), dim3(row_blocks(a.g.nb)), dim3(kBlock), 0, st, a.start,
-                           a.sp, a.perm, a.drag, src4, a.n, a.g, a.dep_partial);
-        a.mk->mark(sum_mark, st);
-        hipLaunchKernelGGL((k_deposit_sum<T, SM, MODE>), dim3(nblk), dim3(kBlock), 0, st, a.dep_partial, a.g, a.P,
-                           a.Plo, out, out2, a.G, a.part, a.part_stride);
+        auto rows_and_sums = [&](auto gc) {
+            constexpr int GS = decltype(gc)::value;
+            hipLaunchKernelGGL((k_deposit_rows<T, SM, MODE, GS>), dim3(row_blocks(a.g.nb, GS)), dim3(kBlock), 0, st,
+                               a.start, a.sp, a.perm, a.drag, src4, a.n, a.g, a.dep_partial);
+            a.mk->mark(sum_mark, st);
+            hipLaunchKernelGGL((k_deposit_sum<T, SM, MODE, GS>), dim3(nblk), dim3(kBlock), 0, st, a.dep_partial, a.g,
+                               a.P, a.Plo, out, out2, a.G, a.part, a.part_stride);
+        };
+        if (deposit_group(a.g.nb) == 1) rows_and_sums(std::integral_constant<int, 1>{});
+        else rows_and_sums(std::integral_constant<int, 2>{});
     } else {
         hipLaunchKernelGGL((k_deposit_ngp<T, SM, MODE>), dim3(nblk), dim3(kBlock), 0, st, a.start, a.sp, a.perm,
                            a.drag, src4, a.n, a.g, a.P, a.Plo, out, out2, a.G, a.part, a.part_stride);

@@ -133,6 +133,9 @@ template <typename T, int SM> int launch_deposit_phi(const StepArgs<T> &a, hipSt
 template <typename T, int SM> int launch_deposit_force(const StepArgs<T> &a, hipStream_t st);
 template <typename T, int SM> int launch_deposit_semi(const StepArgs<T> &a, hipStream_t st);
 int deposit_blocks(const int nb[3], int64_t ncell, int cic);
+// Source rows per group of the CIC row pass (1 or 2 in y and z): the partial
+// buffer holds (G == 1 ? 9 : 4) slots per cell and component.
+int deposit_group(const int nb[3]);
 
 // Workgroups of a prolongation launch (stages.hip), one FP64 partial each per
 // prolonged field.
