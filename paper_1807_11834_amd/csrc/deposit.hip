@@ -155,19 +155,22 @@ __global__ __launch_bounds__(kBlock) void k_deposit_ngp(const int32_t *__restric
 // ---------------------------------------------------------------------------
 // CIC (trilinear to the 8 nearest bulk cell centres, folded at the walls)
 // ---------------------------------------------------------------------------
-// Pass 1, k_deposit_rows: one wave per (2 x 2 group of source rows in y and z,
-// 64-cell x segment).  For each source row of its group the wave stages the
-// particles of the source cells x0-1 .. x0+64 once (in chunks), with their
-// x-stencil, their weights on the three target y-rows and z-rows around the
-// source row and the deposited value(s).  Lane x then accumulates, over the
-// particles of source cells x-1, x, x+1 in canonical order, the contributions to
-// target cell x of the 4 x 4 target rows the group reaches (y-rows 2gy-1 ..
-// 2gy+2, z-layers 2gz-1 .. 2gz+2), and writes each to the partial slot of its
+// Pass 1, k_deposit_rows: one wave per (GS x GS group of source rows in y and
+// z, 64-cell x segment), GS = 2 (or 1 on small grids, see deposit_group()).  For
+// each source row of its group the wave stages the particles of the source
+// cells x0-1 .. x0+64 once (in chunks), with their x-stencil, their weights on
+// the three target y-rows and z-rows around the source row and the deposited
+// value(s).  Lane x then accumulates, over the particles of source cells x-1,
+// x, x+1 in canonical order, the contributions to target cell x of the
+// (GS + 2) x (GS + 2) target rows the group reaches (y-rows GS gy - 1 ..
+// GS gy + GS, likewise in z), and writes each to the partial slot of its
 // (z-group, y-group) offset from the target.
-// Pass 2, k_deposit_sum: per target cell, the <= 4 partials of the source groups
-// it receives from, in ascending (z-group, y-group) order.
-// A target row receives from 2 x 2 groups rather than from 3 x 3 source rows:
-// the partial sums written and read back are 4/9 of one slot per source row.
+// Pass 2, k_deposit_sum: per target cell, the <= 4 (GS = 2) or <= 9 (GS = 1)
+// partials of the source groups it receives from, in ascending (z-group,
+// y-group) order.
+// With GS = 2 a target row receives from 2 x 2 groups rather than from 3 x 3
+// source rows: the partial sums written and read back are 4/9 of one slot per
+// source row; GS = 1 trades that for four times the waves.
 template <typename T, int MODE> struct RowStage {
     int node[kWavesPerBlock][kChunk];                  // x-stencil nodes lo | hi << 16
     T tx[kWavesPerBlock][kChunk];                      // weight of hi
