@@ -21,9 +21,12 @@
 // 32q+16+4g+j.  The in-step inference kernel chains the four layers this way in
 // registers, with the weights pre-permuted into that slot order in LDS.
 //
-// Training runs layer by layer over a batch in HBM (natural slot order, rows
-// k = 32q + 8g + i) with transposed copies for the weight-gradient products,
-// whose contraction runs over the batch.  Every reduction has a fixed order.
+// The training pass chains forward and backward the same way, one 16-row tile
+// per wave, and writes transposed copies of the layer inputs and output
+// gradients for the weight-gradient products, whose contraction runs over the
+// batch.  Batch inference on given features runs layer by layer over HBM in
+// the natural slot order (rows k = 32q + 8g + i).  Every reduction has a fixed
+// order.
 #include <type_traits>
 
 #include "common.hpp"
@@ -129,47 +132,25 @@ __global__ __launch_bounds__(kBlock) void k_adam(const float *__restrict__ grads
 }
 
 // ---------------------------------------------------------------------------
-// Batch kernels (training and inference on given features)
+// Batch inference on given features
 // ---------------------------------------------------------------------------
-// X0[b][k] = bf16((feat[row][k] - mean[k]) / std[k]) for k < 193, 0 up to 224;
-// row = idx[b] (or b).  T[b] = resid[row] / scale (optional).  X0T (optional):
-// the same values transposed, [224][B], for the first layer's weight-gradient
-// products.  A workgroup takes 64 rows: their features are read row by row
-// (consecutive threads, consecutive features) and standardised into an LDS
-// tile, from which the rows leave as 16-byte stores and the transposed copy
-// as 2-byte stores of consecutive rows.
+// X0[b][k] = bf16((feat[b][k] - mean[k]) / std[k]) for k < 193, 0 up to 224.
+// A workgroup takes 64 rows: their features are read row by row (consecutive
+// threads, consecutive features) and standardised into an LDS tile, from which
+// the rows leave as 16-byte stores.
 constexpr int kStdRows = 64;
-constexpr int kStdPitch = kK1 + 2;   // BF16 elements per LDS row (odd word count: no bank conflicts by column)
-__global__ __launch_bounds__(kBlock) void k_standardise(const float *__restrict__ feat, const float *__restrict__ resid,
-                                                        const int32_t *__restrict__ idx, int64_t nrows, int64_t B,
-                                                        const float *__restrict__ mean_inv, float is0, float is1,
-                                                        float is2, uint16_t *__restrict__ x0, uint16_t *__restrict__ x0t,
-                                                        float *__restrict__ T) {
+constexpr int kStdPitch = kK1 + 2;   // BF16 elements per LDS row
+__global__ __launch_bounds__(kBlock) void k_standardise(const float *__restrict__ feat, int64_t B,
+                                                        const float *__restrict__ mean_inv, uint16_t *__restrict__ x0) {
     __shared__ uint16_t tile[kStdRows * kStdPitch];
-    __shared__ int64_t rows[kStdRows];
     const int64_t b0 = (int64_t)blockIdx.x * kStdRows;
     const int nr = (int)(B - b0 < kStdRows ? B - b0 : kStdRows);
-    if (threadIdx.x < kStdRows) {
-        int64_t row = 0;
-        if ((int)threadIdx.x < nr) {
-            row = idx ? (int64_t)idx[b0 + threadIdx.x] : b0 + threadIdx.x;
-            if (row < 0 || row >= nrows) row = 0;   // documented: indices must be in range; keeps loads in bounds
-        }
-        rows[threadIdx.x] = row;
-    }
-    __syncthreads();
     for (int e = threadIdx.x; e < nr * kK1; e += kBlock) {
         const int r = e / kK1, k = e % kK1;
         float v = 0.f;
-        if (k < kFeat) v = (feat[rows[r] * kFeat + k] - mean_inv[k]) * mean_inv[kK1 + k];
+        if (k < kFeat) v = (feat[(b0 + r) * kFeat + k] - mean_inv[k]) * mean_inv[kK1 + k];
         tile[r * kStdPitch + k] = (uint16_t)bf16_bits(v);
     }
-    if (T)
-        for (int e = threadIdx.x; e < nr * 4; e += kBlock) {
-            const int r = e / 4, j = e % 4;
-            const float is = j == 0 ? is0 : (j == 1 ? is1 : is2);
-            T[(b0 + r) * 4 + j] = j < 3 ? resid[rows[r] * 3 + j] * is : 0.f;
-        }
     __syncthreads();
     for (int e = threadIdx.x; e < nr * (kK1 / 8); e += kBlock) {
         const int r = e / (kK1 / 8), k0 = 8 * (e % (kK1 / 8));
@@ -178,27 +159,15 @@ __global__ __launch_bounds__(kBlock) void k_standardise(const float *__restrict_
                                     t[4] | ((uint32_t)t[5] << 16), t[6] | ((uint32_t)t[7] << 16));
         *reinterpret_cast<uint4 *>(x0 + (b0 + r) * kK1 + k0) = pk;
     }
-    if (x0t)
-        for (int e = threadIdx.x; e < kK1 * kStdRows; e += kBlock) {
-            const int k = e / kStdRows, r = e % kStdRows;
-            if (r < nr) x0t[(int64_t)k * B + b0 + r] = tile[r * kStdPitch + k];
-        }
 }
 
-// One dense layer for 16-row tiles, one wave per tile:
+// One dense layer of the batch forward pass for 16-row tiles, one wave per tile:
 //   Z = X W + b (X [B][32 KB] BF16, W^T [16 MB][32 KB] BF16), then
-//   hidden: Z -> z (FP32), gelu(Z) -> h (BF16), both [B][16 MB];
-//   output (MB = 1): Z -> y [B][16]; with targets T [B][4] also the loss partial
-//   of the tile and dY = (Y - T) / B as FP32 [B][16] and BF16 [B][32].
-// HT (may be NULL): the BF16 result (h, or dY for the output layer) also
-// written transposed, [16 MB][B], for the weight-gradient products.
+//   hidden: gelu(Z) -> H (BF16 [B][16 MB]); output (MB = 1): Z -> Y [B][16].
 template <int KB, int MB, bool OUT>
 __global__ __launch_bounds__(kBlock) void k_dense(const uint16_t *__restrict__ X, const uint16_t *__restrict__ WT,
                                                   const float *__restrict__ bias, int M, int64_t B,
-                                                  float *__restrict__ Z, uint16_t *__restrict__ H,
-                                                  const float *__restrict__ T, float inv_b, float *__restrict__ dzf,
-                                                  uint16_t *__restrict__ dz, double *__restrict__ loss_part,
-                                                  uint16_t *__restrict__ HT) {
+                                                  float *__restrict__ Y, uint16_t *__restrict__ H) {
     constexpr int KP = 32 * KB, MP = 16 * MB;
     const int lane = lane_id(), n = lane & 15, g = lane >> 4;
     const int64_t ntile = (B + 15) / 16;
@@ -209,7 +178,6 @@ __global__ __launch_bounds__(kBlock) void k_dense(const uint16_t *__restrict__ X
     bf16x8 xb[KB];
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) xb[kb] = valid ? load8(X + b * KP + 32 * kb + 8 * g) : zero8();
-    double lp = 0.0;
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) {
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
@@ -219,102 +187,353 @@ __global__ __launch_bounds__(kBlock) void k_dense(const uint16_t *__restrict__ X
         float z[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) z[j] = acc[j] + ((m0 + j < M) ? bias[m0 + j] : 0.f);
-        if constexpr (!OUT) {
-            if (valid) {
-                *reinterpret_cast<float4 *>(Z + b * MP + m0) = make_float4(z[0], z[1], z[2], z[3]);
-                const uint2 hv = make_uint2(pack2(gelu(z[0]), gelu(z[1])), pack2(gelu(z[2]), gelu(z[3])));
-                *reinterpret_cast<uint2 *>(H + b * MP + m0) = hv;
-                if (HT) {
-                    HT[(int64_t)(m0 + 0) * B + b] = (uint16_t)(hv.x & 0xffffu);
-                    HT[(int64_t)(m0 + 1) * B + b] = (uint16_t)(hv.x >> 16);
-                    HT[(int64_t)(m0 + 2) * B + b] = (uint16_t)(hv.y & 0xffffu);
-                    HT[(int64_t)(m0 + 3) * B + b] = (uint16_t)(hv.y >> 16);
-                }
-            }
+        if (!valid) continue;
+        if constexpr (OUT) {
+            *reinterpret_cast<float4 *>(Y + b * MP + m0) = make_float4(z[0], z[1], z[2], z[3]);
         } else {
-            if (valid) *reinterpret_cast<float4 *>(Z + b * MP + m0) = make_float4(z[0], z[1], z[2], z[3]);
-            if (T) {
-                float d[4];
+            *reinterpret_cast<uint2 *>(H + b * MP + m0) =
+                make_uint2(pack2(gelu(z[0]), gelu(z[1])), pack2(gelu(z[2]), gelu(z[3])));
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Training pass: standardisation, forward, loss and backward of one 16-row
+// tile per wave, in registers
+// ---------------------------------------------------------------------------
+// Batch rows are the product columns (lane n holds row 16 tile + n) and neurons
+// the product rows, as in the in-step inference.  Between layers the result
+// stays in registers as the next B operand in the permuted slot order (slots
+// 4s + j of group g <- neuron 32q + 16s + 4g + j); the weight fragments are read
+// in the same order, as two 8-byte halves.  The backward products take the
+// output gradients in the same layout, so the whole chain needs no data
+// movement between lanes.  gelu'(Z) of the hidden layers is formed in the
+// forward pass (it shares the exponential with gelu) and kept in registers.
+//
+// For the weight-gradient products over the batch the pass writes the BF16
+// layer inputs and the BF16 output gradients transposed, as the rows of one
+// [1008][B] matrix (x0 224, h 3 x 128, dZ 3 x 128 + 16).  These are staged in
+// LDS, [row][64 batch rows of the workgroup], and leave at the end as whole
+// 128-byte row segments: a wave's stores and loads share one in-order completion counter,
+// so a store issued between the weight loads of two layers would make the
+// second layer wait for it.  The bias gradients are the column sums of the
+// FP32 output gradients: summed in FP64 over the 16 rows of a wave (a fixed
+// butterfly), then over the four waves of a workgroup in wave order, into
+// part_b[l][workgroup][MP].  The loss partial of a tile is
+// sum 0.5 (y - t)^2 / B.  Rows b >= B do not occur (B is a multiple of 16).
+static_assert(kTrainGroupRows == 16 * kWavesPerBlock, "one 16-row tile per wave");
+constexpr int kBiasCols = 3 * kHid + 16;   // bias-gradient columns, layers 1-4
+// Staged transposed rows: x0t (224), ht[0..2] (3 x 128), dzt[0..2] (3 x 128),
+// dzt[3] (16).  68 BF16 per staged row: the four rows that one store
+// instruction writes per lane group (4 apart) then fall 8 banks apart.
+constexpr int kStagePitch = 68;
+constexpr int kStageHt = kTrHt, kStageDz = kTrDz, kStageRows = kTrRows;
+static_assert(kStageRows % 16 == 0, "the output pass takes 16 rows per round");
+
+struct TrainArgs {
+    const float *feat, *resid;
+    const int32_t *idx;
+    int64_t nrows, B;
+    const float *mean_inv;
+    float is[3], inv_b;
+    const float *params;
+    const uint16_t *wt[4], *wn[4];
+    uint16_t *tr;   // transposed rows [kTrRows][B]
+    double *part_b[4];
+    double *loss_part;
+};
+
+// Row r of a BF16 matrix, contraction block q, in the permuted slot order.
+__device__ __forceinline__ bf16x8 load_perm(const uint16_t *r, int q, int g) {
+    const uint2 lo = *reinterpret_cast<const uint2 *>(r + 32 * q + 4 * g);
+    const uint2 hi = *reinterpret_cast<const uint2 *>(r + 32 * q + 16 + 4 * g);
+    return as_bf16x8(make_uint4(lo.x, lo.y, hi.x, hi.y));
+}
+
+// Four BF16 values (two packed words) of column col staged to rows r0 .. r0+3.
+__device__ __forceinline__ void stage_t4(uint16_t *S, int r0, int col, uint32_t w0, uint32_t w1) {
+    S[r0 * kStagePitch + col] = (uint16_t)(w0 & 0xffffu);
+    S[(r0 + 1) * kStagePitch + col] = (uint16_t)(w0 >> 16);
+    S[(r0 + 2) * kStagePitch + col] = (uint16_t)(w1 & 0xffffu);
+    S[(r0 + 3) * kStagePitch + col] = (uint16_t)(w1 >> 16);
+}
+
+// Sum over the 16 lanes of a lane group (lanes with equal g), FP64.
+__device__ __forceinline__ double sum16(double v) {
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const float dd = (valid && m0 + j < M) ? z[j] - T[b * 4 + m0 + j] : 0.f;
-                    lp += 0.5 * (double)dd * (double)dd;
-                    d[j] = dd * inv_b;
+    for (int o = 1; o < 16; o <<= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// Column sums over the 16 lanes of a lane group of the 32 values v = 4 kb + j
+// of a lane (FP32 in, FP64 sums): a reduce-scatter butterfly over lane bits 3,
+// 2, 1, 0.  Each stage keeps half of the values (the upper half where the lane
+// bit is set), adds the partner's copy of that half and sends the other half;
+// lane n ends with the sums of values 2n and 2n + 1.  The adding order of every
+// column is a fixed tree (a + b = b + a exactly, so partners agree).
+__device__ __forceinline__ void colsum16(const f32x4 (&d)[8], int n, double out[2]) {
+    double s16[16];
+    const bool u3 = (n & 8) != 0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const float lo = d[i >> 2][i & 3], hi = d[(i + 16) >> 2][(i + 16) & 3];
+        const float recv = __shfl_xor(u3 ? lo : hi, 8, kWave);
+        s16[i] = (double)(u3 ? hi : lo) + (double)recv;
+    }
+    double s8[8];
+    const bool u2 = (n & 4) != 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) s8[i] = (u2 ? s16[i + 8] : s16[i]) + __shfl_xor(u2 ? s16[i] : s16[i + 8], 4, kWave);
+    double s4[4];
+    const bool u1 = (n & 2) != 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) s4[i] = (u1 ? s8[i + 4] : s8[i]) + __shfl_xor(u1 ? s8[i] : s8[i + 4], 2, kWave);
+    const bool u0 = (n & 1) != 0;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) out[i] = (u0 ? s4[i + 2] : s4[i]) + __shfl_xor(u0 ? s4[i] : s4[i + 2], 1, kWave);
+}
+
+// A layer's output gradient (FP32, result layout, 8 blocks): bias column sums
+// into bs[16 kb + 4 g + j], the BF16 values staged transposed (S, column col),
+// and (if nb) the BF16 values as the B operand of the next backward product.
+__device__ __forceinline__ void emit_grad(const f32x4 (&d)[8], int n, int g, uint16_t *S, int col, double *bs,
+                                          bf16x8 *nb) {
+    uint32_t w[8][2];
+#pragma unroll
+    for (int kb = 0; kb < 8; ++kb) {
+        w[kb][0] = pack2(d[kb][0], d[kb][1]);
+        w[kb][1] = pack2(d[kb][2], d[kb][3]);
+        stage_t4(S, 16 * kb + 4 * g, col, w[kb][0], w[kb][1]);
+    }
+    if (nb)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            nb[q] = as_bf16x8(make_uint4(w[2 * q][0], w[2 * q][1], w[2 * q + 1][0], w[2 * q + 1][1]));
+    double cs[2];
+    colsum16(d, n, cs);   // values 2n, 2n + 1: block n / 2, rows 2 (n % 2) + 0, 1
+    const int c = 16 * (n >> 1) + 4 * g + 2 * (n & 1);
+    bs[c] = cs[0];
+    bs[c + 1] = cs[1];
+}
+
+// Hidden layer result: Z = acc + b, H = gelu(Z) as BF16 (staged transposed and
+// as the next B operand), gelu'(Z) kept.
+__device__ __forceinline__ void finish_hidden(f32x4 (&acc)[8], const float *bias, int g, uint16_t *S, int col,
+                                              f32x4 (&gp)[8], bf16x8 (&hb)[4]) {
+    uint32_t w[8][2];
+    float4 bv[8];
+#pragma unroll
+    for (int mb = 0; mb < 8; ++mb) bv[mb] = *reinterpret_cast<const float4 *>(bias + 16 * mb + 4 * g);
+#pragma unroll
+    for (int mb = 0; mb < 8; ++mb) {
+        float h[4];
+        const float bj[4] = {bv[mb].x, bv[mb].y, bv[mb].z, bv[mb].w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const float z = acc[mb][j] + bj[j];
+            const float s = sig2u(z);
+            h[j] = z * s;   // gelu(z)
+            gp[mb][j] = s + 2.f * z * s * (1.f - s) * (kGc * fmaf(3.f * kGa, z * z, 1.f));   // gelu'(z)
+        }
+        w[mb][0] = pack2(h[0], h[1]);
+        w[mb][1] = pack2(h[2], h[3]);
+        stage_t4(S, 16 * mb + 4 * g, col, w[mb][0], w[mb][1]);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) hb[q] = as_bf16x8(make_uint4(w[2 * q][0], w[2 * q][1], w[2 * q + 1][0], w[2 * q + 1][1]));
+}
+
+// The 32 weight fragments of a 128 x 128 product in the permuted order:
+// f[r][q] = row 16 r + n of M (pitch P), contraction block q.  A layer's
+// fragments are loaded as one batch, ahead of the work before the product, so
+// that their latency overlaps it; the product then runs on registers.
+template <int P>
+__device__ __forceinline__ void load_frags(const uint16_t *__restrict__ M, int n, int g, bf16x8 (&f)[8][4]) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) f[r][q] = load_perm(M + (16 * r + n) * P, q, g);
+}
+__device__ __forceinline__ void product(const bf16x8 (&f)[8][4], const bf16x8 (&x)[4], f32x4 (&acc)[8]) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        acc[r] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[r] = mma(f[r][q], x[q], acc[r]);
+    }
+}
+// Keeps the loads above it from sinking towards their first use.
+__device__ __forceinline__ void issue_fence() { __builtin_amdgcn_sched_barrier(0); }
+
+__global__ __launch_bounds__(kBlock) void k_train_tile(TrainArgs a) {
+    __shared__ __align__(16) uint16_t stage[kStageRows * kStagePitch];
+    __shared__ float norm[2 * kK1];
+    __shared__ __align__(16) float sbias[3 * kHid + 4];
+    __shared__ double bsum[kWavesPerBlock][kBiasCols];
+    for (int i = threadIdx.x; i < 2 * kK1; i += kBlock) norm[i] = a.mean_inv[i];
+    for (int i = threadIdx.x; i < 3 * kHid + kOut; i += kBlock) {
+        constexpr int64_t o0 = off_b(0), o1 = off_b(1), o2 = off_b(2), o3 = off_b(3);
+        const int l = i < 3 * kHid ? i / kHid : 3;
+        const int64_t o = l == 0 ? o0 : (l == 1 ? o1 : (l == 2 ? o2 : o3));
+        sbias[i] = a.params[o + i - l * kHid];
+    }
+    __syncthreads();
+    const int lane = lane_id(), n = lane & 15, g = lane >> 4, w = threadIdx.x >> 6;
+    const int64_t B = a.B;
+    const int64_t tile = (int64_t)blockIdx.x * kWavesPerBlock + w;
+    const int col = 16 * w + n;   // staged column of this lane's row
+    double *bs = bsum[w];
+    double lp = 0.0;
+    if (tile * 16 < B) {
+        const int64_t b = tile * 16 + n;
+        int64_t row = a.idx ? (int64_t)a.idx[b] : b;
+        if (row < 0 || row >= a.nrows) row = 0;   // documented: indices must be in range; keeps loads in bounds
+        const float *fr = a.feat + row * kFeat;
+        float t[4] = {0.f, 0.f, 0.f, 0.f};
+        if (g == 0)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) t[j] = a.resid[row * 3 + j] * a.is[j];
+
+        // layer 1 from the standardised features, natural slot order (k = 32 kb + 8 g + i)
+        f32x4 acc[8];
+        {
+            float fv[7][8];
+#pragma unroll
+            for (int kb = 0; kb < 7; ++kb)
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int k = 32 * kb + 8 * g + i;
+                    fv[kb][i] = k < kFeat ? fr[k] : 0.f;
                 }
-                if (valid) {
-                    *reinterpret_cast<float4 *>(dzf + b * MP + m0) = make_float4(d[0], d[1], d[2], d[3]);
-                    const uint2 dv = make_uint2(pack2(d[0], d[1]), pack2(d[2], d[3]));
-                    *reinterpret_cast<uint2 *>(dz + b * 32 + m0) = dv;
-                    if (HT) {
-                        HT[(int64_t)(m0 + 0) * B + b] = (uint16_t)(dv.x & 0xffffu);
-                        HT[(int64_t)(m0 + 1) * B + b] = (uint16_t)(dv.x >> 16);
-                        HT[(int64_t)(m0 + 2) * B + b] = (uint16_t)(dv.y & 0xffffu);
-                        HT[(int64_t)(m0 + 3) * B + b] = (uint16_t)(dv.y >> 16);
-                    }
+            bf16x8 f1[8][7];
+#pragma unroll
+            for (int mb = 0; mb < 8; ++mb)
+#pragma unroll
+                for (int kb = 0; kb < 7; ++kb) f1[mb][kb] = load8(a.wt[0] + (16 * mb + n) * kK1 + 32 * kb + 8 * g);
+            issue_fence();
+            bf16x8 xb[7];
+#pragma unroll
+            for (int kb = 0; kb < 7; ++kb) {
+                float v[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int k = 32 * kb + 8 * g + i;
+                    v[i] = k < kFeat ? (fv[kb][i] - norm[k]) * norm[kK1 + k] : 0.f;
                 }
+                const uint4 u = make_uint4(pack2(v[0], v[1]), pack2(v[2], v[3]), pack2(v[4], v[5]), pack2(v[6], v[7]));
+                xb[kb] = as_bf16x8(u);
+                stage_t4(stage, 32 * kb + 8 * g, col, u.x, u.y);
+                stage_t4(stage, 32 * kb + 8 * g + 4, col, u.z, u.w);
+            }
+#pragma unroll
+            for (int mb = 0; mb < 8; ++mb) {
+                acc[mb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int kb = 0; kb < 7; ++kb) acc[mb] = mma(f1[mb][kb], xb[kb], acc[mb]);
             }
         }
+        f32x4 gp[3][8];
+        bf16x8 hb[4], f[8][4];
+        uint16_t *sh = stage + kStageHt * kStagePitch, *sd = stage + kStageDz * kStagePitch;
+        load_frags<kHid>(a.wt[1], n, g, f);
+        issue_fence();
+        finish_hidden(acc, sbias, g, sh, col, gp[0], hb);
+        product(f, hb, acc);
+        load_frags<kHid>(a.wt[2], n, g, f);
+        issue_fence();
+        finish_hidden(acc, sbias + kHid, g, sh + kHid * kStagePitch, col, gp[1], hb);
+        product(f, hb, acc);
+        bf16x8 fo[4], f4[8];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) fo[q] = load_perm(a.wt[3] + n * kHid, q, g);
+#pragma unroll
+        for (int kb = 0; kb < 8; ++kb) f4[kb] = load_perm(a.wn[3] + (16 * kb + n) * 32, 0, g);
+        issue_fence();
+        finish_hidden(acc, sbias + 2 * kHid, g, sh + 2 * kHid * kStagePitch, col, gp[2], hb);
+
+        // output layer (rows m = 4 g + j, three of them real), loss and dY
+        bf16x8 db[4];
+        {
+            f32x4 y = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) y = mma(fo[q], hb[q], y);
+            float d[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int m = 4 * g + j;
+                const float dd = m < kOut ? (y[j] + sbias[3 * kHid + m]) - t[j] : 0.f;
+                lp += 0.5 * (double)dd * (double)dd;
+                d[j] = dd * a.inv_b;
+            }
+            const uint32_t w0 = pack2(d[0], d[1]), w1 = pack2(d[2], d[3]);
+            stage_t4(sd + 3 * kHid * kStagePitch, 4 * g, col, w0, w1);
+            db[0] = as_bf16x8(make_uint4(w0, w1, 0u, 0u));
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const double s = sum16((double)d[j]);
+                if (n == 0) bs[3 * kHid + 4 * g + j] = s;
+            }
+        }
+
+        // backward: dZ_l = (dZ_{l+1} W_{l+1}^T) .* gelu'(Z_l), l = 3, 2, 1
+#pragma unroll
+        for (int kb = 0; kb < 8; ++kb) {
+            acc[kb] = mma(f4[kb], db[0], f32x4{0.f, 0.f, 0.f, 0.f});
+            acc[kb] *= gp[2][kb];
+        }
+        load_frags<kHid>(a.wn[2], n, g, f);
+        issue_fence();
+        emit_grad(acc, n, g, sd + 2 * kHid * kStagePitch, col, bs + 2 * kHid, db);
+        product(f, db, acc);
+#pragma unroll
+        for (int kb = 0; kb < 8; ++kb) acc[kb] *= gp[1][kb];
+        load_frags<kHid>(a.wn[1], n, g, f);
+        issue_fence();
+        emit_grad(acc, n, g, sd + kHid * kStagePitch, col, bs + kHid, db);
+        product(f, db, acc);
+#pragma unroll
+        for (int kb = 0; kb < 8; ++kb) acc[kb] *= gp[0][kb];
+        emit_grad(acc, n, g, sd, col, bs, nullptr);
+    } else {
+        for (int c = lane; c < kBiasCols; c += kWave) bs[c] = 0.0;
     }
-    if constexpr (OUT) {
-        if (T) {
-            lp = wave_sum(lp);
-            if (lane == 0) loss_part[tile] = lp * (double)inv_b;
+    lp = wave_sum(lp);
+    if (lane == 0 && tile * 16 < B) a.loss_part[tile] = lp * (double)a.inv_b;
+    __syncthreads();
+    for (int c = threadIdx.x; c < kBiasCols; c += kBlock) {
+        const double s = ((bsum[0][c] + bsum[1][c]) + bsum[2][c]) + bsum[3][c];
+        const int l = c < 3 * kHid ? c / kHid : 3, m = c - l * kHid, MP = mpad(l);
+        a.part_b[l][(int64_t)blockIdx.x * MP + m] = s;
+    }
+    // staged rows out: 16 threads per row, 4 batch rows (8 bytes) each, rows
+    // r0 + 16 i; chunks past B (a multiple of 16) belong to absent tiles
+    const int64_t b0 = (int64_t)blockIdx.x * kTrainGroupRows;
+    const int c = threadIdx.x & 15, r0 = threadIdx.x >> 4;
+    if (b0 + 4 * c < B) {
+        uint16_t *dst = a.tr + b0 + 4 * c;
+        const uint16_t *src = stage + 4 * c;
+        constexpr int kU = 9, kIter = kStageRows / 16;
+        static_assert(kIter % kU == 0, "whole rounds");
+        for (int i0 = 0; i0 < kIter; i0 += kU) {
+            uint2 v[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u)
+                v[u] = *reinterpret_cast<const uint2 *>(src + (r0 + 16 * (i0 + u)) * kStagePitch);
+#pragma unroll
+            for (int u = 0; u < kU; ++u) *reinterpret_cast<uint2 *>(dst + (int64_t)(r0 + 16 * (i0 + u)) * B) = v[u];
         }
     }
 }
 
-// Input gradient of a layer times gelu' of the previous pre-activation:
-//   dZp = (dZ W^T) .* gelu'(Zp),  dZ [B][32 KC] BF16, W [16 NB][32 KC] BF16,
-//   Zp [B][16 NB] FP32 -> dZp as FP32 and BF16 [B][16 NB], and the BF16 values
-//   transposed, dzpT [16 NB][B], for the weight-gradient products.
-template <int KC, int NB>
-__global__ __launch_bounds__(kBlock) void k_dense_bwd(const uint16_t *__restrict__ dZ, const uint16_t *__restrict__ W,
-                                                      const float *__restrict__ Zp, int64_t B,
-                                                      float *__restrict__ dzpf, uint16_t *__restrict__ dzp,
-                                                      uint16_t *__restrict__ dzpT) {
-    constexpr int MC = 32 * KC, KI = 16 * NB;
-    const int lane = lane_id(), n = lane & 15, g = lane >> 4;
-    const int64_t ntile = (B + 15) / 16;
-    const int64_t tile = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    if (tile >= ntile) return;
-    const int64_t b = tile * 16 + n;
-    const bool valid = b < B;
-    bf16x8 db[KC];
-#pragma unroll
-    for (int kc = 0; kc < KC; ++kc) db[kc] = valid ? load8(dZ + b * MC + 32 * kc + 8 * g) : zero8();
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int kc = 0; kc < KC; ++kc) acc = mma(load8(W + (int64_t)(16 * nb + n) * MC + 32 * kc + 8 * g), db[kc], acc);
-        const int k0 = 16 * nb + 4 * g;
-        if (valid) {
-            const float4 zp = *reinterpret_cast<const float4 *>(Zp + b * KI + k0);
-            const float d0 = acc[0] * gelu_grad(zp.x), d1 = acc[1] * gelu_grad(zp.y);
-            const float d2 = acc[2] * gelu_grad(zp.z), d3 = acc[3] * gelu_grad(zp.w);
-            *reinterpret_cast<float4 *>(dzpf + b * KI + k0) = make_float4(d0, d1, d2, d3);
-            const uint2 dv = make_uint2(pack2(d0, d1), pack2(d2, d3));
-            *reinterpret_cast<uint2 *>(dzp + b * KI + k0) = dv;
-            dzpT[(int64_t)(k0 + 0) * B + b] = (uint16_t)(dv.x & 0xffffu);
-            dzpT[(int64_t)(k0 + 1) * B + b] = (uint16_t)(dv.x >> 16);
-            dzpT[(int64_t)(k0 + 2) * B + b] = (uint16_t)(dv.y & 0xffffu);
-            dzpT[(int64_t)(k0 + 3) * B + b] = (uint16_t)(dv.y >> 16);
-        }
-    }
-}
-
-// Weight and bias gradients of one layer over a chunk of rows:
+// Weight gradients of one layer over a chunk of rows:
 //   part_w[c][m][k] = sum_{b in chunk} dZ[b][m] H[b][k]   (BF16 x BF16, FP32 accumulate)
-//   part_b[c][m]    = sum_{b in chunk} dZf[b][m]          (FP32 values, FP64 sum)
 // from the transposed copies dZT [16 MT][B] and HT [16 KT][B].  Rows in chunks
 // of kChunk; B is a multiple of 32.  Each wave owns output column blocks kt and
 // keeps all MT row blocks in registers: per 32 rows it loads one HT fragment and
-// the MT dZT fragments and issues MT independent products.  The bias sums run
-// four interleaved FP64 partial sums (rows b mod 4) combined in a fixed order.
+// the MT dZT fragments and issues MT independent products.
 template <int MT, int KT>
 __global__ __launch_bounds__(kBlock) void k_wgrad(const uint16_t *__restrict__ dZT, const uint16_t *__restrict__ HT,
-                                                  const float *__restrict__ dzf, int64_t B,
-                                                  float *__restrict__ part_w, double *__restrict__ part_b) {
+                                                  int64_t B, float *__restrict__ part_w) {
     constexpr int MP = 16 * MT, KP = 16 * KT;
     const int lane = lane_id(), n = lane & 15, g = lane >> 4, wave = threadIdx.x >> 6;
     const int64_t c = blockIdx.x;
@@ -352,17 +571,6 @@ __global__ __launch_bounds__(kBlock) void k_wgrad(const uint16_t *__restrict__ d
             for (int j = 0; j < 4; ++j) o[(int64_t)j * KP] = acc[mt][j];
         }
     }
-    for (int m = threadIdx.x; m < MP; m += kBlock) {
-        double s[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int64_t b = b0; b < b1; b += 32) {   // chunks are multiples of 32 rows
-            float v[32];   // 32 loads in flight, then the sums in row order
-#pragma unroll
-            for (int q = 0; q < 32; ++q) v[q] = dzf[(b + q) * MP + m];
-#pragma unroll
-            for (int q = 0; q < 32; ++q) s[q & 3] += (double)v[q];
-        }
-        part_b[c * MP + m] = (s[0] + s[1]) + (s[2] + s[3]);
-    }
 }
 
 struct GradParts {
@@ -370,11 +578,13 @@ struct GradParts {
     const double *b[4];
 };
 
-// Flat gradient vector from the per-chunk partials.  Work entries follow the
-// partials' layout (per layer the padded [m][k] weight slots, k fastest, then
-// the m bias slots), so that the loads of a wave are contiguous; each entry is
-// summed by kRedGroups threads over interleaved chunks (c mod kRedGroups, two
-// partial sums each) whose results are combined in a fixed order.
+// Flat gradient vector from the partials: nchunk row chunks of the weight
+// gradients, nchunk_b workgroups of the training pass for the bias gradients.
+// Work entries follow the partials' layout (per layer the padded [m][k] weight
+// slots, k fastest, then the m bias slots), so that the loads of a wave are
+// contiguous; each entry is summed by kRedGroups threads over interleaved
+// chunks (c mod kRedGroups, two partial sums each) whose results are combined
+// in a fixed order.
 constexpr int kRedGroups = 8;
 constexpr int kRedEntries = kBlock / kRedGroups;   // entries per workgroup
 
@@ -383,7 +593,8 @@ __host__ __device__ constexpr int64_t red_w_begin(int l) {
 }
 constexpr int64_t kRedTotal = red_w_begin(3) + (int64_t)mpad(3) * kpad(3) + mpad(3);
 
-__global__ __launch_bounds__(kBlock) void k_reduce_grads(GradParts parts, int64_t nchunk, float *__restrict__ grads) {
+__global__ __launch_bounds__(kBlock) void k_reduce_grads(GradParts parts, int64_t nchunk, int64_t nchunk_b,
+                                                         float *__restrict__ grads) {
     __shared__ double red[kRedGroups][kRedEntries];
     const int le = threadIdx.x % kRedEntries, grp = threadIdx.x / kRedEntries;
     const int64_t e = (int64_t)blockIdx.x * kRedEntries + le;
@@ -406,11 +617,11 @@ __global__ __launch_bounds__(kBlock) void k_reduce_grads(GradParts parts, int64_
             if (c < nchunk) s0 += (double)w[c * stride];
         } else {
             int64_t c = grp;
-            for (; c + kRedGroups < nchunk; c += 2 * kRedGroups) {
+            for (; c + kRedGroups < nchunk_b; c += 2 * kRedGroups) {
                 s0 += parts.b[l][c * MP + m];
                 s1 += parts.b[l][(c + kRedGroups) * MP + m];
             }
-            if (c < nchunk) s0 += parts.b[l][c * MP + m];
+            if (c < nchunk_b) s0 += parts.b[l][c * MP + m];
         }
     }
     red[grp][le] = s0 + s1;
@@ -955,61 +1166,62 @@ hipError_t launch_adam(const NetBufs &net, const float *grads, float lr, float b
     return hipGetLastError();
 }
 
-hipError_t launch_standardise(const float *feat, const float *resid, const int32_t *idx, int64_t nrows, int64_t B,
-                              const float *mean_inv, const float inv_scale[3], uint16_t *x0, uint16_t *x0t, float *t,
-                              hipStream_t st) {
+hipError_t launch_standardise(const float *feat, int64_t B, const float *mean_inv, uint16_t *x0, hipStream_t st) {
     if (B <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_standardise, dim3((unsigned)((B + kStdRows - 1) / kStdRows)), dim3(kBlock), 0, st, feat, resid,
-                       idx, nrows, B, mean_inv, inv_scale[0], inv_scale[1], inv_scale[2], x0, x0t, t);
+    hipLaunchKernelGGL(k_standardise, dim3((unsigned)((B + kStdRows - 1) / kStdRows)), dim3(kBlock), 0, st, feat, B,
+                       mean_inv, x0);
     return hipGetLastError();
 }
 
 static unsigned tile_blocks(int64_t B) { return (unsigned)(((B + 15) / 16 + kWavesPerBlock - 1) / kWavesPerBlock); }
 
-hipError_t launch_forward(const NetBufs &net, const TrainBufs &tb, int64_t B, bool with_loss, hipStream_t st) {
+hipError_t launch_forward(const NetBufs &net, const TrainBufs &tb, int64_t B, hipStream_t st) {
     if (B <= 0) return hipSuccess;
     const dim3 gr(tile_blocks(B)), bl(kBlock);
     const float *p = net.params;
-    // a training pass (with_loss) also writes the transposed copies that the
-    // weight-gradient products read
-    auto T = [&](uint16_t *q) { return with_loss ? q : nullptr; };
-    hipLaunchKernelGGL((k_dense<7, 8, false>), gr, bl, 0, st, tb.x0, net.wt[0], p + off_b(0), kHid, B, tb.z[0], tb.h[0],
-                       nullptr, 0.f, nullptr, nullptr, nullptr, T(tb.ht[0]));
-    hipLaunchKernelGGL((k_dense<4, 8, false>), gr, bl, 0, st, tb.h[0], net.wt[1], p + off_b(1), kHid, B, tb.z[1], tb.h[1],
-                       nullptr, 0.f, nullptr, nullptr, nullptr, T(tb.ht[1]));
-    hipLaunchKernelGGL((k_dense<4, 8, false>), gr, bl, 0, st, tb.h[1], net.wt[2], p + off_b(2), kHid, B, tb.z[2], tb.h[2],
-                       nullptr, 0.f, nullptr, nullptr, nullptr, T(tb.ht[2]));
-    hipLaunchKernelGGL((k_dense<4, 1, true>), gr, bl, 0, st, tb.h[2], net.wt[3], p + off_b(3), kOut, B, tb.y, nullptr,
-                       with_loss ? tb.t : nullptr, (float)(1.0 / (double)B), tb.dzf[3], tb.dz[3], tb.loss_part,
-                       T(tb.dzt[3]));
+    hipLaunchKernelGGL((k_dense<7, 8, false>), gr, bl, 0, st, tb.x0, net.wt[0], p + off_b(0), kHid, B, nullptr, tb.h[0]);
+    hipLaunchKernelGGL((k_dense<4, 8, false>), gr, bl, 0, st, tb.h[0], net.wt[1], p + off_b(1), kHid, B, nullptr, tb.h[1]);
+    hipLaunchKernelGGL((k_dense<4, 8, false>), gr, bl, 0, st, tb.h[1], net.wt[2], p + off_b(2), kHid, B, nullptr, tb.h[2]);
+    hipLaunchKernelGGL((k_dense<4, 1, true>), gr, bl, 0, st, tb.h[2], net.wt[3], p + off_b(3), kOut, B, tb.y, nullptr);
     return hipGetLastError();
 }
 
-hipError_t launch_backward(const NetBufs &net, const TrainBufs &tb, int64_t B, float *grads, float *loss,
-                           hipStream_t st) {
-    const dim3 gr(tile_blocks(B)), bl(kBlock);
-    // input gradients of layers 4, 3, 2 (each times gelu' of the layer below)
-    hipLaunchKernelGGL((k_dense_bwd<1, 8>), gr, bl, 0, st, tb.dz[3], net.wn[3], tb.z[2], B, tb.dzf[2], tb.dz[2],
-                       tb.dzt[2]);
-    hipLaunchKernelGGL((k_dense_bwd<4, 8>), gr, bl, 0, st, tb.dz[2], net.wn[2], tb.z[1], B, tb.dzf[1], tb.dz[1],
-                       tb.dzt[1]);
-    hipLaunchKernelGGL((k_dense_bwd<4, 8>), gr, bl, 0, st, tb.dz[1], net.wn[1], tb.z[0], B, tb.dzf[0], tb.dz[0],
-                       tb.dzt[0]);
-    // (the transposed layer input of the first layer was written with it by
-    // k_standardise, the other transposed copies by their producing kernels)
+hipError_t launch_gradients(const NetBufs &net, const TrainBufs &tb, const float *feat, const float *resid,
+                            const int32_t *idx, int64_t nrows, int64_t B, const float inv_scale[3], float *grads,
+                            float *loss, hipStream_t st) {
+    const dim3 bl(kBlock);
+    TrainArgs a;
+    a.feat = feat;
+    a.resid = resid;
+    a.idx = idx;
+    a.nrows = nrows;
+    a.B = B;
+    a.mean_inv = net.mean_inv;
+    for (int j = 0; j < 3; ++j) a.is[j] = inv_scale[j];
+    a.inv_b = (float)(1.0 / (double)B);
+    a.params = net.params;
+    for (int l = 0; l < 4; ++l) {
+        a.wt[l] = net.wt[l];
+        a.wn[l] = net.wn[l];
+        a.part_b[l] = tb.part_b[l];
+    }
+    a.tr = tb.tr;
+    a.loss_part = tb.loss_part;
+    const unsigned nt = (unsigned)n_train_groups(B);
+    hipLaunchKernelGGL(k_train_tile, dim3(nt), bl, 0, st, a);
     const unsigned nc = (unsigned)n_chunks(B);
-    hipLaunchKernelGGL((k_wgrad<8, 14>), dim3(nc), bl, 0, st, tb.dzt[0], tb.x0t, tb.dzf[0], B, tb.part_w[0], tb.part_b[0]);
-    hipLaunchKernelGGL((k_wgrad<8, 8>), dim3(nc), bl, 0, st, tb.dzt[1], tb.ht[0], tb.dzf[1], B, tb.part_w[1], tb.part_b[1]);
-    hipLaunchKernelGGL((k_wgrad<8, 8>), dim3(nc), bl, 0, st, tb.dzt[2], tb.ht[1], tb.dzf[2], B, tb.part_w[2], tb.part_b[2]);
-    hipLaunchKernelGGL((k_wgrad<1, 8>), dim3(nc), bl, 0, st, tb.dzt[3], tb.ht[2], tb.dzf[3], B, tb.part_w[3], tb.part_b[3]);
+    hipLaunchKernelGGL((k_wgrad<8, 14>), dim3(nc), bl, 0, st, tr_dz(tb, 0, B), tr_x0(tb), B, tb.part_w[0]);
+    hipLaunchKernelGGL((k_wgrad<8, 8>), dim3(nc), bl, 0, st, tr_dz(tb, 1, B), tr_h(tb, 0, B), B, tb.part_w[1]);
+    hipLaunchKernelGGL((k_wgrad<8, 8>), dim3(nc), bl, 0, st, tr_dz(tb, 2, B), tr_h(tb, 1, B), B, tb.part_w[2]);
+    hipLaunchKernelGGL((k_wgrad<1, 8>), dim3(nc), bl, 0, st, tr_dz(tb, 3, B), tr_h(tb, 2, B), B, tb.part_w[3]);
     GradParts parts;
     for (int l = 0; l < 4; ++l) {
         parts.w[l] = tb.part_w[l];
         parts.b[l] = tb.part_b[l];
     }
     hipLaunchKernelGGL(k_reduce_grads, dim3((unsigned)((kRedTotal + kRedEntries - 1) / kRedEntries)), bl, 0, st, parts,
-                       (int64_t)nc, grads);
-    if (loss) hipLaunchKernelGGL(k_sum_loss, dim3(1), bl, 0, st, tb.loss_part, (B + 15) / 16, loss);
+                       (int64_t)nc, (int64_t)nt, grads);
+    if (loss) hipLaunchKernelGGL(k_sum_loss, dim3(1), bl, 0, st, tb.loss_part, B / 16, loss);
     return hipGetLastError();
 }
 

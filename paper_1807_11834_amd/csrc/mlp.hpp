@@ -36,21 +36,28 @@ constexpr int kK1 = 224;     // padded layer-1 fan-in (and the length of mean/1/
 // Training and batch-inference buffers, sized for max_batch rows.
 struct TrainBufs {
     int64_t max_batch = 0;
-    uint16_t *x0 = nullptr, *x0t = nullptr;        // standardised input [B][224], [224][B]
-    uint16_t *h[3] = {}, *ht[3] = {};              // hidden activations [B][128], [128][B]
-    float *z[3] = {};                              // hidden pre-activations [B][128]
-    float *y = nullptr;                            // output [B][16]
-    float *t = nullptr;                            // scaled target [B][4]
-    uint16_t *dz[4] = {}, *dzt[4] = {};            // BF16 output gradients: [B][CP], [CP][B]
-    float *dzf[4] = {};                            // FP32 output gradients [B][MP]
+    uint16_t *x0 = nullptr;                        // standardised input [B][224] (batch inference)
+    uint16_t *h[3] = {};                           // hidden activations [B][128] (batch inference)
+    float *y = nullptr;                            // output [B][16] (batch inference)
+    uint16_t *tr = nullptr;                        // training: BF16 transposed rows [kTrRows][B] (below)
     float *part_w[4] = {};                         // per-chunk weight gradients [nchunk][MP][KP]
-    double *part_b[4] = {};                        // per-chunk bias gradients [nchunk][MP]
+    double *part_b[4] = {};                        // per-workgroup bias gradients [ngroup][MP]
     double *loss_part = nullptr;                   // per-16-row tile [B/16]
     float *grads = nullptr;                        // [kNParam]
 };
 
+// Rows of the training pass's transposed output, each B long: the layer-1
+// input (224 rows), the hidden activations of layers 1-3 (3 x 128), the output
+// gradients of layers 1-3 (3 x 128) and of layer 4 (16).
+constexpr int kTrHt = kK1, kTrDz = kK1 + 3 * kHid, kTrRows = kTrDz + 3 * kHid + 16;
+inline uint16_t *tr_x0(const TrainBufs &tb) { return tb.tr; }
+inline uint16_t *tr_h(const TrainBufs &tb, int l, int64_t B) { return tb.tr + (int64_t)(kTrHt + kHid * l) * B; }
+inline uint16_t *tr_dz(const TrainBufs &tb, int l, int64_t B) { return tb.tr + (int64_t)(kTrDz + kHid * l) * B; }
+
 constexpr int64_t kChunk = 256;   // rows per workgroup in the weight-gradient products
 inline int64_t n_chunks(int64_t B) { return (B + kChunk - 1) / kChunk; }
+constexpr int64_t kTrainGroupRows = 64;   // rows per workgroup of the training pass
+inline int64_t n_train_groups(int64_t B) { return (B + kTrainGroupRows - 1) / kTrainGroupRows; }
 
 // Device state of one network (owned by the couple_mlp handle).
 struct NetBufs {
@@ -61,12 +68,15 @@ struct NetBufs {
 
 // Kernel launchers (mlp.hip).  All enqueue on `st` and return the launch status.
 hipError_t launch_cast(const NetBufs &net, hipStream_t st);
-hipError_t launch_standardise(const float *feat, const float *resid, const int32_t *idx, int64_t nrows, int64_t B,
-                              const float *mean_inv, const float inv_scale[3], uint16_t *x0, uint16_t *x0t, float *t,
-                              hipStream_t st);
-hipError_t launch_forward(const NetBufs &net, const TrainBufs &tb, int64_t B, bool with_loss, hipStream_t st);
-hipError_t launch_backward(const NetBufs &net, const TrainBufs &tb, int64_t B, float *grads, float *loss,
-                           hipStream_t st);
+// Batch inference: standardise B rows of feat into x0, then the four layers into y.
+hipError_t launch_standardise(const float *feat, int64_t B, const float *mean_inv, uint16_t *x0, hipStream_t st);
+hipError_t launch_forward(const NetBufs &net, const TrainBufs &tb, int64_t B, hipStream_t st);
+// Gradient of the mean loss over a batch of B rows (a multiple of 32): rows
+// idx[b] (or b) of feat [nrows][193] and resid [nrows][3]; grads [kNParam] and
+// (if loss) the loss.
+hipError_t launch_gradients(const NetBufs &net, const TrainBufs &tb, const float *feat, const float *resid,
+                            const int32_t *idx, int64_t nrows, int64_t B, const float inv_scale[3], float *grads,
+                            float *loss, hipStream_t st);
 // b1, b2 and their complements 1 - b1, 1 - b2 are rounded separately from
 // double (0.999f alone would leave 1 - b2 off by 1e-5 relative).
 hipError_t launch_adam(const NetBufs &net, const float *grads, float lr, float b1, float omb1, float b2, float omb2,

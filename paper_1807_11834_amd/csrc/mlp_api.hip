@@ -35,21 +35,16 @@ template <typename X> static bool alloc0(X **p, size_t bytes) {
 }
 
 static void mlp_release(couple_mlp *m) {
-    std::vector<void *> ptrs = {m->net.params, m->net.m, m->net.v, m->net.mean_inv, m->tb.x0, m->tb.x0t,
-                                m->tb.y, m->tb.t, m->tb.loss_part, m->tb.grads, m->stats};
+    std::vector<void *> ptrs = {m->net.params, m->net.m, m->net.v, m->net.mean_inv, m->tb.x0, m->tb.tr,
+                                m->tb.y, m->tb.loss_part, m->tb.grads, m->stats};
     for (int l = 0; l < 4; ++l) {
         ptrs.push_back(m->net.wt[l]);
         ptrs.push_back(m->net.wn[l]);
-        ptrs.push_back(m->tb.dz[l]);
-        ptrs.push_back(m->tb.dzt[l]);
-        ptrs.push_back(m->tb.dzf[l]);
         ptrs.push_back(m->tb.part_w[l]);
         ptrs.push_back(m->tb.part_b[l]);
     }
     for (int l = 0; l < 3; ++l) {
         ptrs.push_back(m->tb.h[l]);
-        ptrs.push_back(m->tb.ht[l]);
-        ptrs.push_back(m->tb.z[l]);
     }
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -90,7 +85,7 @@ extern "C" int couple_mlp_init(const couple_mlp_config *cfg, couple_mlp **out) {
     }
     for (int a = 0; a < 3; ++a) m->scale[a] = 1.0;
     const int64_t B = (cfg->max_batch + 31) / 32 * 32;
-    const int64_t nc = n_chunks(B);
+    const int64_t nc = n_chunks(B), ng = n_train_groups(B);
     TrainBufs &tb = m->tb;
     tb.max_batch = cfg->max_batch;
     bool ok = alloc0(&m->net.params, sizeof(float) * kNParam) && alloc0(&m->net.m, sizeof(float) * kNParam) &&
@@ -98,17 +93,14 @@ extern "C" int couple_mlp_init(const couple_mlp_config *cfg, couple_mlp **out) {
     for (int l = 0; l < 4 && ok; ++l) {
         ok = alloc0(&m->net.wt[l], sizeof(uint16_t) * mpad(l) * kpad(l)) &&
              (l == 0 || alloc0(&m->net.wn[l], sizeof(uint16_t) * kpad(l) * cpad(l))) &&
-             alloc0(&tb.dz[l], sizeof(uint16_t) * B * cpad(l)) && alloc0(&tb.dzt[l], sizeof(uint16_t) * B * cpad(l)) &&
-             alloc0(&tb.dzf[l], sizeof(float) * B * mpad(l)) &&
              alloc0(&tb.part_w[l], sizeof(float) * nc * mpad(l) * kpad(l)) &&
-             alloc0(&tb.part_b[l], sizeof(double) * nc * mpad(l));
+             alloc0(&tb.part_b[l], sizeof(double) * ng * mpad(l));
     }
     for (int l = 0; l < 3 && ok; ++l)
-        ok = alloc0(&tb.h[l], sizeof(uint16_t) * B * kHid) && alloc0(&tb.ht[l], sizeof(uint16_t) * B * kHid) &&
-             alloc0(&tb.z[l], sizeof(float) * B * kHid);
+        ok = alloc0(&tb.h[l], sizeof(uint16_t) * B * kHid);
     m->stats_chunks = 256;
-    ok = ok && alloc0(&tb.x0, sizeof(uint16_t) * B * kK1) && alloc0(&tb.x0t, sizeof(uint16_t) * B * kK1) &&
-         alloc0(&tb.y, sizeof(float) * B * 16) && alloc0(&tb.t, sizeof(float) * B * 4) &&
+    ok = ok && alloc0(&tb.x0, sizeof(uint16_t) * B * kK1) && alloc0(&tb.tr, sizeof(uint16_t) * B * kTrRows) &&
+         alloc0(&tb.y, sizeof(float) * B * 16) &&
          alloc0(&tb.loss_part, sizeof(double) * ((B + 15) / 16)) && alloc0(&tb.grads, sizeof(float) * kNParam) &&
          alloc0(&m->stats, sizeof(double) * (m->stats_chunks * 256 + 4 * 256));
     if (!ok) {
@@ -284,12 +276,9 @@ extern "C" int couple_mlp_forward(couple_mlp *m, const float *feat, int64_t n, f
     if (n > 0 && (!feat || !y)) return mfail(m, COUPLE_EINVAL, "couple_mlp_forward: NULL argument");
     if (n == 0) return COUPLE_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    float is[3];
-    inv_scale(m, is);
     (void)hipGetLastError();
-    if (launch_standardise(feat, nullptr, nullptr, n, n, m->net.mean_inv, is, m->tb.x0, nullptr, nullptr, st) !=
-            hipSuccess ||
-        launch_forward(m->net, m->tb, n, false, st) != hipSuccess || launch_output(m->tb, n, y, st) != hipSuccess)
+    if (launch_standardise(feat, n, m->net.mean_inv, m->tb.x0, st) != hipSuccess ||
+        launch_forward(m->net, m->tb, n, st) != hipSuccess || launch_output(m->tb, n, y, st) != hipSuccess)
         return mfail(m, COUPLE_EHIP, "couple_mlp_forward: launch failed");
     return COUPLE_OK;
 }
@@ -303,10 +292,7 @@ static int grads_impl(couple_mlp *m, const char *who, const float *feat, const f
     float is[3];
     inv_scale(m, is);
     (void)hipGetLastError();
-    if (launch_standardise(feat, resid, idx, nrows, B, m->net.mean_inv, is, m->tb.x0, m->tb.x0t, m->tb.t, st) !=
-            hipSuccess ||
-        launch_forward(m->net, m->tb, B, true, st) != hipSuccess ||
-        launch_backward(m->net, m->tb, B, grads, loss, st) != hipSuccess)
+    if (launch_gradients(m->net, m->tb, feat, resid, idx, nrows, B, is, grads, loss, st) != hipSuccess)
         return mfail(m, COUPLE_EHIP, std::string(who) + ": launch failed");
     return COUPLE_OK;
 }
