@@ -528,17 +528,20 @@ __global__ __launch_bounds__(kBlock) void k_train_tile(TrainArgs a) {
 // Weight gradients of one layer over a chunk of rows:
 //   part_w[c][m][k] = sum_{b in chunk} dZ[b][m] H[b][k]   (BF16 x BF16, FP32 accumulate)
 // from the transposed copies dZT [16 MT][B] and HT [16 KT][B].  Rows in chunks
-// of kChunk; B is a multiple of 32.  Each wave owns output column blocks kt and
-// keeps all MT row blocks in registers: per 32 rows it loads one HT fragment and
-// the MT dZT fragments and issues MT independent products.
+// of kChunk; B is a multiple of 32.  Each of the kWgradWaves waves of a
+// workgroup owns output column blocks kt and keeps all MT row blocks in
+// registers: per 32 rows it loads one HT fragment and the MT dZT fragments and
+// issues MT independent products.
+constexpr int kWgradWaves = 8;
 template <int MT, int KT>
-__global__ __launch_bounds__(kBlock) void k_wgrad(const uint16_t *__restrict__ dZT, const uint16_t *__restrict__ HT,
-                                                  int64_t B, float *__restrict__ part_w) {
+__global__ __launch_bounds__(kWgradWaves * kWave) void k_wgrad(const uint16_t *__restrict__ dZT,
+                                                               const uint16_t *__restrict__ HT, int64_t B,
+                                                               float *__restrict__ part_w) {
     constexpr int MP = 16 * MT, KP = 16 * KT;
     const int lane = lane_id(), n = lane & 15, g = lane >> 4, wave = threadIdx.x >> 6;
     const int64_t c = blockIdx.x;
     const int64_t b0 = c * kChunk, b1 = (b0 + kChunk < B) ? b0 + kChunk : B;
-    for (int kt = wave; kt < KT; kt += kWavesPerBlock) {
+    for (int kt = wave; kt < KT; kt += kWgradWaves) {
         f32x4 acc[MT];
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) acc[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -578,51 +581,38 @@ struct GradParts {
     const double *b[4];
 };
 
-// Flat gradient vector from the partials: nchunk row chunks of the weight
-// gradients, nchunk_b workgroups of the training pass for the bias gradients.
-// Work entries follow the partials' layout (per layer the padded [m][k] weight
-// slots, k fastest, then the m bias slots), so that the loads of a wave are
-// contiguous; each entry is summed by kRedGroups threads over interleaved
-// chunks (c mod kRedGroups, two partial sums each) whose results are combined
-// in a fixed order.
+// Flat gradient vector from the partials.  Weight entries follow the
+// partials' layout (per layer the padded [m][k] slots, k fastest), so that the
+// loads of a wave are contiguous; each is summed by kRedGroups threads over
+// interleaved chunks (c mod kRedGroups, two partial sums each) whose results
+// are combined in a fixed order.  Each bias entry is summed by one wave over
+// the nchunk_b workgroup partials of the training pass (lane c mod 64, then a
+// fixed butterfly).
 constexpr int kRedGroups = 8;
 constexpr int kRedEntries = kBlock / kRedGroups;   // entries per workgroup
+constexpr int64_t kRedW1 = (int64_t)mpad(0) * kpad(0), kRedW2 = kRedW1 + (int64_t)mpad(1) * kpad(1),
+                  kRedW3 = kRedW2 + (int64_t)mpad(2) * kpad(2), kRedTotal = kRedW3 + (int64_t)mpad(3) * kpad(3);
+constexpr int kRedBias = 3 * kHid + kOut;          // bias entries (real ones)
 
-__host__ __device__ constexpr int64_t red_w_begin(int l) {
-    return l == 0 ? 0 : red_w_begin(l - 1) + (int64_t)mpad(l - 1) * kpad(l - 1) + mpad(l - 1);
-}
-constexpr int64_t kRedTotal = red_w_begin(3) + (int64_t)mpad(3) * kpad(3) + mpad(3);
-
-__global__ __launch_bounds__(kBlock) void k_reduce_grads(GradParts parts, int64_t nchunk, int64_t nchunk_b,
-                                                         float *__restrict__ grads) {
+__global__ __launch_bounds__(kBlock) void k_reduce_w(GradParts parts, int64_t nchunk, float *__restrict__ grads) {
+    constexpr int64_t kOffW[4] = {off_w(0), off_w(1), off_w(2), off_w(3)};
     __shared__ double red[kRedGroups][kRedEntries];
     const int le = threadIdx.x % kRedEntries, grp = threadIdx.x / kRedEntries;
     const int64_t e = (int64_t)blockIdx.x * kRedEntries + le;
-    int l = 0;
-    while (l < 3 && e >= red_w_begin(l + 1)) ++l;
-    const int64_t r = e - red_w_begin(l);
-    const int MP = mpad(l), KP = kpad(l);
-    const bool isw = r < (int64_t)MP * KP;
-    const int m = isw ? (int)(r / KP) : (int)(r - (int64_t)MP * KP), k = isw ? (int)(r % KP) : 0;
+    const int l = e < kRedW1 ? 0 : (e < kRedW2 ? 1 : (e < kRedW3 ? 2 : 3));
+    const int64_t r = e - (l == 0 ? 0 : (l == 1 ? kRedW1 : (l == 2 ? kRedW2 : kRedW3)));
+    const int MP = l == 3 ? mpad(3) : kHid, KP = l == 0 ? kpad(0) : kHid;
+    const int m = (int)(r / KP), k = (int)(r % KP);
     double s0 = 0.0, s1 = 0.0;
     if (e < kRedTotal) {
-        if (isw) {
-            const float *w = parts.w[l] + (int64_t)m * KP + k;
-            const int64_t stride = (int64_t)MP * KP;
-            int64_t c = grp;
-            for (; c + kRedGroups < nchunk; c += 2 * kRedGroups) {
-                s0 += (double)w[c * stride];
-                s1 += (double)w[(c + kRedGroups) * stride];
-            }
-            if (c < nchunk) s0 += (double)w[c * stride];
-        } else {
-            int64_t c = grp;
-            for (; c + kRedGroups < nchunk_b; c += 2 * kRedGroups) {
-                s0 += parts.b[l][c * MP + m];
-                s1 += parts.b[l][(c + kRedGroups) * MP + m];
-            }
-            if (c < nchunk_b) s0 += parts.b[l][c * MP + m];
+        const float *w = parts.w[l] + r;
+        const int64_t stride = (int64_t)MP * KP;
+        int64_t c = grp;
+        for (; c + kRedGroups < nchunk; c += 2 * kRedGroups) {
+            s0 += (double)w[c * stride];
+            s1 += (double)w[(c + kRedGroups) * stride];
         }
+        if (c < nchunk) s0 += (double)w[c * stride];
     }
     red[grp][le] = s0 + s1;
     __syncthreads();
@@ -630,12 +620,21 @@ __global__ __launch_bounds__(kBlock) void k_reduce_grads(GradParts parts, int64_
         double t = 0.0;
 #pragma unroll
         for (int q = 0; q < kRedGroups; ++q) t += red[q][le];
-        if (isw) {
-            if (k < fan_in(l) && m < fan_out(l)) grads[off_w(l) + (int64_t)k * fan_out(l) + m] = (float)t;
-        } else if (m < fan_out(l)) {
-            grads[off_b(l) + m] = (float)t;
-        }
+        const int fi = l == 0 ? kFeat : kHid, fo = l == 3 ? kOut : kHid;
+        if (k < fi && m < fo) grads[kOffW[l] + (int64_t)k * fo + m] = (float)t;
     }
+}
+
+__global__ __launch_bounds__(kBlock) void k_reduce_b(GradParts parts, int64_t nchunk_b, float *__restrict__ grads) {
+    constexpr int64_t kOffB[4] = {off_b(0), off_b(1), off_b(2), off_b(3)};
+    const int e = (int)(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6)), lane = lane_id();
+    if (e >= kRedBias) return;   // whole wave
+    const int l = e < 3 * kHid ? e / kHid : 3, m = e - l * kHid, MP = mpad(l);
+    const double *p = parts.b[l] + m;
+    double s = 0.0;
+    for (int64_t c = lane; c < nchunk_b; c += kWave) s += p[c * MP];
+    s = wave_sum(s);
+    if (lane == 0) grads[kOffB[l] + m] = (float)s;
 }
 
 __global__ __launch_bounds__(kBlock) void k_sum_loss(const double *__restrict__ part, int64_t n, float *__restrict__ out) {
@@ -1210,17 +1209,20 @@ hipError_t launch_gradients(const NetBufs &net, const TrainBufs &tb, const float
     const unsigned nt = (unsigned)n_train_groups(B);
     hipLaunchKernelGGL(k_train_tile, dim3(nt), bl, 0, st, a);
     const unsigned nc = (unsigned)n_chunks(B);
-    hipLaunchKernelGGL((k_wgrad<8, 14>), dim3(nc), bl, 0, st, tr_dz(tb, 0, B), tr_x0(tb), B, tb.part_w[0]);
-    hipLaunchKernelGGL((k_wgrad<8, 8>), dim3(nc), bl, 0, st, tr_dz(tb, 1, B), tr_h(tb, 0, B), B, tb.part_w[1]);
-    hipLaunchKernelGGL((k_wgrad<8, 8>), dim3(nc), bl, 0, st, tr_dz(tb, 2, B), tr_h(tb, 1, B), B, tb.part_w[2]);
-    hipLaunchKernelGGL((k_wgrad<1, 8>), dim3(nc), bl, 0, st, tr_dz(tb, 3, B), tr_h(tb, 2, B), B, tb.part_w[3]);
+    const dim3 bw(kWgradWaves * kWave);
+    hipLaunchKernelGGL((k_wgrad<8, 14>), dim3(nc), bw, 0, st, tr_dz(tb, 0, B), tr_x0(tb), B, tb.part_w[0]);
+    hipLaunchKernelGGL((k_wgrad<8, 8>), dim3(nc), bw, 0, st, tr_dz(tb, 1, B), tr_h(tb, 0, B), B, tb.part_w[1]);
+    hipLaunchKernelGGL((k_wgrad<8, 8>), dim3(nc), bw, 0, st, tr_dz(tb, 2, B), tr_h(tb, 1, B), B, tb.part_w[2]);
+    hipLaunchKernelGGL((k_wgrad<1, 8>), dim3(nc), bw, 0, st, tr_dz(tb, 3, B), tr_h(tb, 2, B), B, tb.part_w[3]);
     GradParts parts;
     for (int l = 0; l < 4; ++l) {
         parts.w[l] = tb.part_w[l];
         parts.b[l] = tb.part_b[l];
     }
-    hipLaunchKernelGGL(k_reduce_grads, dim3((unsigned)((kRedTotal + kRedEntries - 1) / kRedEntries)), bl, 0, st, parts,
-                       (int64_t)nc, (int64_t)nt, grads);
+    hipLaunchKernelGGL(k_reduce_w, dim3((unsigned)((kRedTotal + kRedEntries - 1) / kRedEntries)), bl, 0, st, parts,
+                       (int64_t)nc, grads);
+    hipLaunchKernelGGL(k_reduce_b, dim3((unsigned)((kRedBias + kWavesPerBlock - 1) / kWavesPerBlock)), bl, 0, st, parts,
+                       (int64_t)nt, grads);
     if (loss) hipLaunchKernelGGL(k_sum_loss, dim3(1), bl, 0, st, tb.loss_part, B / 16, loss);
     return hipGetLastError();
 }
