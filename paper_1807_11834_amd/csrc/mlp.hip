@@ -198,37 +198,44 @@ __global__ __launch_bounds__(kBlock) void k_dense(const uint16_t *__restrict__ X
 }
 
 // ---------------------------------------------------------------------------
-// Training pass: standardisation, forward, loss and backward of one 16-row
-// tile per wave, in registers
+// Training pass: standardisation, forward, loss and backward of a 16-row tile
+// by a pair of waves
 // ---------------------------------------------------------------------------
 // Batch rows are the product columns (lane n holds row 16 tile + n) and neurons
-// the product rows, as in the in-step inference.  Between layers the result
-// stays in registers as the next B operand in the permuted slot order (slots
-// 4s + j of group g <- neuron 32q + 16s + 4g + j); the weight fragments are read
-// in the same order, as two 8-byte halves.  The backward products take the
-// output gradients in the same layout, so the whole chain needs no data
-// movement between lanes.  gelu'(Z) of the hidden layers is formed in the
-// forward pass (it shares the exponential with gelu) and kept in registers.
+// the product rows, as in the in-step inference.  A layer's result is the next
+// B operand in the permuted slot order (slots 4s + j of group g <- neuron
+// 32q + 16s + 4g + j); the weight fragments are read in the same order, as two
+// 8-byte halves, and the backward products take the output gradients in the
+// same layout.  The two waves of a tile split every 128-neuron layer: wave h
+// computes neuron blocks 4h .. 4h+3 (64 neurons) and keeps their gelu'(Z),
+// formed in the forward pass with gelu (one exponential); the other half of
+// the next B operand is read back from the LDS stage below after a workgroup
+// barrier.  A workgroup takes two tiles (32 rows): with the halved registers
+// per wave and an 80 KB stage, two workgroups share a compute unit and hide
+// each other's load latency across the barriers.
 //
 // For the weight-gradient products over the batch the pass writes the BF16
 // layer inputs and the BF16 output gradients transposed, as the rows of one
-// [1008][B] matrix (x0 224, h 3 x 128, dZ 3 x 128 + 16).  These are staged in
-// LDS, [row][64 batch rows of the workgroup], and leave at the end as whole
-// 128-byte row segments: a wave's stores and loads share one in-order completion counter,
-// so a store issued between the weight loads of two layers would make the
-// second layer wait for it.  The bias gradients are the column sums of the
-// FP32 output gradients: summed in FP64 over the 16 rows of a wave (a fixed
-// butterfly), then over the four waves of a workgroup in wave order, into
-// part_b[l][workgroup][MP].  The loss partial of a tile is
+// 1008-row matrix (x0 224, h 3 x 128, dZ 3 x 128 + 16) in blocks of 32 batch
+// rows.  These are staged in LDS, [row][32 batch rows of the workgroup], and
+// leave at the end as the workgroup's contiguous block: a wave's stores and
+// loads share one in-order completion counter, so a store issued between the
+// weight loads of two layers would make the second layer wait for it.  The bias gradients are the
+// column sums of the FP32 output gradients: summed in FP64 over the 16 rows of
+// a tile (a fixed butterfly), then over the two tiles of a workgroup in tile
+// order, into part_b[l][workgroup][MP].  The loss partial of a tile is
 // sum 0.5 (y - t)^2 / B.  Rows b >= B do not occur (B is a multiple of 16).
-static_assert(kTrainGroupRows == 16 * kWavesPerBlock, "one 16-row tile per wave");
-constexpr int kBiasCols = 3 * kHid + 16;   // bias-gradient columns, layers 1-4
+constexpr int kTrainTiles = 2;                    // 16-row tiles per workgroup
+static_assert(kTrainGroupRows == 16 * kTrainTiles, "two 16-row tiles per workgroup");
+constexpr int kTrainWaves = 2 * kTrainTiles;      // two waves per tile
+constexpr int kTrainThreads = kTrainWaves * kWave;
+constexpr int kBiasCols = 3 * kHid + 16;          // bias-gradient columns, layers 1-4
 // Staged transposed rows: x0t (224), ht[0..2] (3 x 128), dzt[0..2] (3 x 128),
-// dzt[3] (16).  68 BF16 per staged row: the four rows that one store
-// instruction writes per lane group (4 apart) then fall 8 banks apart.
-constexpr int kStagePitch = 68;
+// dzt[3] (16).  36 BF16 per staged row: the four rows that one access
+// instruction touches per lane group (4 apart) then fall 8 banks apart.
+constexpr int kStagePitch = kTrainGroupRows + 4;
 constexpr int kStageHt = kTrHt, kStageDz = kTrDz, kStageRows = kTrRows;
-static_assert(kStageRows % 16 == 0, "the output pass takes 16 rows per round");
+static_assert(kStageRows % 16 == 0, "the output pass takes whole rows");
 
 struct TrainArgs {
     const float *feat, *resid;
@@ -238,7 +245,7 @@ struct TrainArgs {
     float is[3], inv_b;
     const float *params;
     const uint16_t *wt[4], *wn[4];
-    uint16_t *tr;   // transposed rows [kTrRows][B]
+    uint16_t *tr;   // transposed rows, blocks of kTrBlock batch rows
     double *part_b[4];
     double *loss_part;
 };
@@ -257,6 +264,11 @@ __device__ __forceinline__ void stage_t4(uint16_t *S, int r0, int col, uint32_t 
     S[(r0 + 2) * kStagePitch + col] = (uint16_t)(w1 & 0xffffu);
     S[(r0 + 3) * kStagePitch + col] = (uint16_t)(w1 >> 16);
 }
+// The same four values read back as two packed words.
+__device__ __forceinline__ void unstage_t4(const uint16_t *S, int r0, int col, uint32_t &w0, uint32_t &w1) {
+    w0 = (uint32_t)S[r0 * kStagePitch + col] | ((uint32_t)S[(r0 + 1) * kStagePitch + col] << 16);
+    w1 = (uint32_t)S[(r0 + 2) * kStagePitch + col] | ((uint32_t)S[(r0 + 3) * kStagePitch + col] << 16);
+}
 
 // Sum over the 16 lanes of a lane group (lanes with equal g), FP64.
 __device__ __forceinline__ double sum16(double v) {
@@ -265,98 +277,107 @@ __device__ __forceinline__ double sum16(double v) {
     return v;
 }
 
-// Column sums over the 16 lanes of a lane group of the 32 values v = 4 kb + j
+// Column sums over the 16 lanes of a lane group of the 16 values v = 4 kb + j
 // of a lane (FP32 in, FP64 sums): a reduce-scatter butterfly over lane bits 3,
 // 2, 1, 0.  Each stage keeps half of the values (the upper half where the lane
 // bit is set), adds the partner's copy of that half and sends the other half;
-// lane n ends with the sums of values 2n and 2n + 1.  The adding order of every
-// column is a fixed tree (a + b = b + a exactly, so partners agree).
-__device__ __forceinline__ void colsum16(const f32x4 (&d)[8], int n, double out[2]) {
-    double s16[16];
+// lane n ends with the sum of value n.  The adding order of every column is a
+// fixed tree (a + b = b + a exactly, so partners agree).
+__device__ __forceinline__ double colsum16(const f32x4 (&d)[4], int n) {
+    double s8[8];
     const bool u3 = (n & 8) != 0;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const float lo = d[i >> 2][i & 3], hi = d[(i + 16) >> 2][(i + 16) & 3];
+    for (int i = 0; i < 8; ++i) {
+        const float lo = d[i >> 2][i & 3], hi = d[(i + 8) >> 2][(i + 8) & 3];
         const float recv = __shfl_xor(u3 ? lo : hi, 8, kWave);
-        s16[i] = (double)(u3 ? hi : lo) + (double)recv;
+        s8[i] = (double)(u3 ? hi : lo) + (double)recv;
     }
-    double s8[8];
+    double s4[4];
     const bool u2 = (n & 4) != 0;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) s8[i] = (u2 ? s16[i + 8] : s16[i]) + __shfl_xor(u2 ? s16[i] : s16[i + 8], 4, kWave);
-    double s4[4];
+    for (int i = 0; i < 4; ++i) s4[i] = (u2 ? s8[i + 4] : s8[i]) + __shfl_xor(u2 ? s8[i] : s8[i + 4], 4, kWave);
+    double s2[2];
     const bool u1 = (n & 2) != 0;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) s4[i] = (u1 ? s8[i + 4] : s8[i]) + __shfl_xor(u1 ? s8[i] : s8[i + 4], 2, kWave);
+    for (int i = 0; i < 2; ++i) s2[i] = (u1 ? s4[i + 2] : s4[i]) + __shfl_xor(u1 ? s4[i] : s4[i + 2], 2, kWave);
     const bool u0 = (n & 1) != 0;
-#pragma unroll
-    for (int i = 0; i < 2; ++i) out[i] = (u0 ? s4[i + 2] : s4[i]) + __shfl_xor(u0 ? s4[i] : s4[i + 2], 1, kWave);
+    return (u0 ? s2[1] : s2[0]) + __shfl_xor(u0 ? s2[0] : s2[1], 1, kWave);
 }
 
-// A layer's output gradient (FP32, result layout, 8 blocks): bias column sums
-// into bs[16 kb + 4 g + j], the BF16 values staged transposed (S, column col),
-// and (if nb) the BF16 values as the B operand of the next backward product.
-__device__ __forceinline__ void emit_grad(const f32x4 (&d)[8], int n, int g, uint16_t *S, int col, double *bs,
-                                          bf16x8 *nb) {
-    uint32_t w[8][2];
+// Half a layer's output gradient (FP32, result layout, blocks 4h .. 4h+3):
+// the BF16 values staged transposed (S, column col) and kept as packed words,
+// the bias column sums into bs[16 (4h + kb) + 4 g + j].
+__device__ __forceinline__ void emit_grad(const f32x4 (&d)[4], int h, int n, int g, uint16_t *S, int col, double *bs,
+                                          uint32_t (&w)[4][2]) {
 #pragma unroll
-    for (int kb = 0; kb < 8; ++kb) {
+    for (int kb = 0; kb < 4; ++kb) {
         w[kb][0] = pack2(d[kb][0], d[kb][1]);
         w[kb][1] = pack2(d[kb][2], d[kb][3]);
-        stage_t4(S, 16 * kb + 4 * g, col, w[kb][0], w[kb][1]);
+        stage_t4(S, 16 * (4 * h + kb) + 4 * g, col, w[kb][0], w[kb][1]);
     }
-    if (nb)
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            nb[q] = as_bf16x8(make_uint4(w[2 * q][0], w[2 * q][1], w[2 * q + 1][0], w[2 * q + 1][1]));
-    double cs[2];
-    colsum16(d, n, cs);   // values 2n, 2n + 1: block n / 2, rows 2 (n % 2) + 0, 1
-    const int c = 16 * (n >> 1) + 4 * g + 2 * (n & 1);
-    bs[c] = cs[0];
-    bs[c + 1] = cs[1];
+    const double cs = colsum16(d, n);   // value n: block n / 4, row n % 4
+    bs[16 * (4 * h + (n >> 2)) + 4 * g + (n & 3)] = cs;
 }
 
-// Hidden layer result: Z = acc + b, H = gelu(Z) as BF16 (staged transposed and
-// as the next B operand), gelu'(Z) kept.
-__device__ __forceinline__ void finish_hidden(f32x4 (&acc)[8], const float *bias, int g, uint16_t *S, int col,
-                                              f32x4 (&gp)[8], bf16x8 (&hb)[4]) {
-    uint32_t w[8][2];
-    float4 bv[8];
+// Half a hidden layer's result (blocks 4h .. 4h+3): Z = acc + b (bv: the bias
+// values of the lane's rows), H = gelu(Z) as BF16 (staged transposed and kept
+// as packed words), gelu'(Z) kept.
+__device__ __forceinline__ void finish_hidden(const f32x4 (&acc)[4], const float4 (&bv)[4], int h, int g, uint16_t *S,
+                                              int col, f32x4 (&gp)[4], uint32_t (&w)[4][2]) {
 #pragma unroll
-    for (int mb = 0; mb < 8; ++mb) bv[mb] = *reinterpret_cast<const float4 *>(bias + 16 * mb + 4 * g);
-#pragma unroll
-    for (int mb = 0; mb < 8; ++mb) {
-        float h[4];
+    for (int mb = 0; mb < 4; ++mb) {
+        float hv[4];
         const float bj[4] = {bv[mb].x, bv[mb].y, bv[mb].z, bv[mb].w};
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const float z = acc[mb][j] + bj[j];
             const float s = sig2u(z);
-            h[j] = z * s;   // gelu(z)
+            hv[j] = z * s;   // gelu(z)
             gp[mb][j] = s + 2.f * z * s * (1.f - s) * (kGc * fmaf(3.f * kGa, z * z, 1.f));   // gelu'(z)
         }
-        w[mb][0] = pack2(h[0], h[1]);
-        w[mb][1] = pack2(h[2], h[3]);
-        stage_t4(S, 16 * mb + 4 * g, col, w[mb][0], w[mb][1]);
+        w[mb][0] = pack2(hv[0], hv[1]);
+        w[mb][1] = pack2(hv[2], hv[3]);
+        stage_t4(S, 16 * (4 * h + mb) + 4 * g, col, w[mb][0], w[mb][1]);
     }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) hb[q] = as_bf16x8(make_uint4(w[2 * q][0], w[2 * q][1], w[2 * q + 1][0], w[2 * q + 1][1]));
 }
 
-// The 32 weight fragments of a 128 x 128 product in the permuted order:
-// f[r][q] = row 16 r + n of M (pitch P), contraction block q.  A layer's
-// fragments are loaded as one batch, ahead of the work before the product, so
-// that their latency overlaps it; the product then runs on registers.
-template <int P>
-__device__ __forceinline__ void load_frags(const uint16_t *__restrict__ M, int n, int g, bf16x8 (&f)[8][4]) {
+// The full B operand (four contraction blocks) of a 128-neuron result split
+// over the two waves of a tile: the own blocks 4h .. 4h+3 from their packed
+// words, the partner's read back from its staged rows (S, column col).
+__device__ __forceinline__ void gather_operand(const uint32_t (&w)[4][2], const uint16_t *S, int h, int g, int col,
+                                               bf16x8 (&x)[4]) {
+    uint32_t p[4][2];   // partner's blocks 4(1-h) .. 4(1-h)+3
 #pragma unroll
-    for (int r = 0; r < 8; ++r)
+    for (int mb = 0; mb < 4; ++mb) unstage_t4(S, 16 * (4 * (1 - h) + mb) + 4 * g, col, p[mb][0], p[mb][1]);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) f[r][q] = load_perm(M + (16 * r + n) * P, q, g);
+    for (int q = 0; q < 2; ++q) {
+        // block pair (2q, 2q+1) of the own half and of the partner's half
+        const bf16x8 own = as_bf16x8(make_uint4(w[2 * q][0], w[2 * q][1], w[2 * q + 1][0], w[2 * q + 1][1]));
+        const bf16x8 oth = as_bf16x8(make_uint4(p[2 * q][0], p[2 * q][1], p[2 * q + 1][0], p[2 * q + 1][1]));
+        x[q] = h == 0 ? own : oth;
+        x[2 + q] = h == 0 ? oth : own;
+    }
 }
-__device__ __forceinline__ void product(const bf16x8 (&f)[8][4], const bf16x8 (&x)[4], f32x4 (&acc)[8]) {
+
+// Half of a 128 x 128 product in the permuted order: f[r][q] = row 16 (4h + r)
+// + n of M (pitch P), contraction block q.  A layer's fragments are loaded as
+// one batch, ahead of the work before the product, so that their latency
+// overlaps it; the product then runs on registers.
+template <int P>
+__device__ __forceinline__ void load_frags(const uint16_t *__restrict__ M, int h, int n, int g, bf16x8 (&f)[4][4]) {
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) f[r][q] = load_perm(M + (16 * (4 * h + r) + n) * P, q, g);
+}
+// The bias values of a hidden layer for the lane's rows of blocks 4h .. 4h+3.
+__device__ __forceinline__ void load_bias(const float *__restrict__ bias, int h, int g, float4 (&bv)[4]) {
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) bv[mb] = *reinterpret_cast<const float4 *>(bias + 16 * (4 * h + mb) + 4 * g);
+}
+__device__ __forceinline__ void product(const bf16x8 (&f)[4][4], const bf16x8 (&x)[4], f32x4 (&acc)[4]) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
         acc[r] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int q = 0; q < 4; ++q) acc[r] = mma(f[r][q], x[q], acc[r]);
@@ -365,179 +386,208 @@ __device__ __forceinline__ void product(const bf16x8 (&f)[8][4], const bf16x8 (&
 // Keeps the loads above it from sinking towards their first use.
 __device__ __forceinline__ void issue_fence() { __builtin_amdgcn_sched_barrier(0); }
 
-__global__ __launch_bounds__(kBlock) void k_train_tile(TrainArgs a) {
+__global__ __launch_bounds__(kTrainThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_train_tile(TrainArgs a) {
     __shared__ __align__(16) uint16_t stage[kStageRows * kStagePitch];
     __shared__ float norm[2 * kK1];
-    __shared__ __align__(16) float sbias[3 * kHid + 4];
-    __shared__ double bsum[kWavesPerBlock][kBiasCols];
-    for (int i = threadIdx.x; i < 2 * kK1; i += kBlock) norm[i] = a.mean_inv[i];
-    for (int i = threadIdx.x; i < 3 * kHid + kOut; i += kBlock) {
-        constexpr int64_t o0 = off_b(0), o1 = off_b(1), o2 = off_b(2), o3 = off_b(3);
-        const int l = i < 3 * kHid ? i / kHid : 3;
-        const int64_t o = l == 0 ? o0 : (l == 1 ? o1 : (l == 2 ? o2 : o3));
-        sbias[i] = a.params[o + i - l * kHid];
-    }
+    __shared__ double bsum[kTrainTiles][kBiasCols];
+    for (int i = threadIdx.x; i < 2 * kK1; i += kTrainThreads) norm[i] = a.mean_inv[i];
     __syncthreads();
-    const int lane = lane_id(), n = lane & 15, g = lane >> 4, w = threadIdx.x >> 6;
+    constexpr int64_t kOffB0 = off_b(0), kOffB1 = off_b(1), kOffB2 = off_b(2), kOffB3 = off_b(3);
+    const int lane = lane_id(), n = lane & 15, g = lane >> 4, w = threadIdx.x >> 6, tw = w >> 1, h = w & 1;
     const int64_t B = a.B;
-    const int64_t tile = (int64_t)blockIdx.x * kWavesPerBlock + w;
-    const int col = 16 * w + n;   // staged column of this lane's row
-    double *bs = bsum[w];
-    double lp = 0.0;
-    if (tile * 16 < B) {
+    const int64_t tile = (int64_t)blockIdx.x * kTrainTiles + tw;
+    const bool active = tile * 16 < B;   // the same for both waves of a tile
+    const int col = 16 * tw + n;         // staged column of this lane's row
+    double *bs = bsum[tw];
+    uint16_t *sh = stage + kStageHt * kStagePitch, *sd = stage + kStageDz * kStagePitch;
+    f32x4 acc[4], gp[3][4];
+    uint32_t wv[4][2];
+    bf16x8 x[4], f[4][4];
+    float4 bv[4];
+    float t[4] = {0.f, 0.f, 0.f, 0.f};
+    if (active) {
         const int64_t b = tile * 16 + n;
         int64_t row = a.idx ? (int64_t)a.idx[b] : b;
         if (row < 0 || row >= a.nrows) row = 0;   // documented: indices must be in range; keeps loads in bounds
         const float *fr = a.feat + row * kFeat;
-        float t[4] = {0.f, 0.f, 0.f, 0.f};
         if (g == 0)
 #pragma unroll
             for (int j = 0; j < 3; ++j) t[j] = a.resid[row * 3 + j] * a.is[j];
-
         // layer 1 from the standardised features, natural slot order (k = 32 kb + 8 g + i)
-        f32x4 acc[8];
-        {
-            float fv[7][8];
+        float fv[7][8];
+#pragma unroll
+        for (int kb = 0; kb < 7; ++kb)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int k = 32 * kb + 8 * g + i;
+                fv[kb][i] = k < kFeat ? fr[k] : 0.f;
+            }
+        bf16x8 f1[4][7];
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
             for (int kb = 0; kb < 7; ++kb)
+                f1[mb][kb] = load8(a.wt[0] + (16 * (4 * h + mb) + n) * kK1 + 32 * kb + 8 * g);
+        issue_fence();
+        bf16x8 xb[7];
 #pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    const int k = 32 * kb + 8 * g + i;
-                    fv[kb][i] = k < kFeat ? fr[k] : 0.f;
-                }
-            bf16x8 f1[8][7];
+        for (int kb = 0; kb < 7; ++kb) {
+            float v[8];
 #pragma unroll
-            for (int mb = 0; mb < 8; ++mb)
-#pragma unroll
-                for (int kb = 0; kb < 7; ++kb) f1[mb][kb] = load8(a.wt[0] + (16 * mb + n) * kK1 + 32 * kb + 8 * g);
-            issue_fence();
-            bf16x8 xb[7];
-#pragma unroll
-            for (int kb = 0; kb < 7; ++kb) {
-                float v[8];
-#pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    const int k = 32 * kb + 8 * g + i;
-                    v[i] = k < kFeat ? (fv[kb][i] - norm[k]) * norm[kK1 + k] : 0.f;
-                }
-                const uint4 u = make_uint4(pack2(v[0], v[1]), pack2(v[2], v[3]), pack2(v[4], v[5]), pack2(v[6], v[7]));
-                xb[kb] = as_bf16x8(u);
+            for (int i = 0; i < 8; ++i) {
+                const int k = 32 * kb + 8 * g + i;
+                v[i] = k < kFeat ? (fv[kb][i] - norm[k]) * norm[kK1 + k] : 0.f;
+            }
+            const uint4 u = make_uint4(pack2(v[0], v[1]), pack2(v[2], v[3]), pack2(v[4], v[5]), pack2(v[6], v[7]));
+            xb[kb] = as_bf16x8(u);
+            if ((kb < 4) == (h == 0)) {   // the input rows are staged by halves
                 stage_t4(stage, 32 * kb + 8 * g, col, u.x, u.y);
                 stage_t4(stage, 32 * kb + 8 * g + 4, col, u.z, u.w);
             }
-#pragma unroll
-            for (int mb = 0; mb < 8; ++mb) {
-                acc[mb] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int kb = 0; kb < 7; ++kb) acc[mb] = mma(f1[mb][kb], xb[kb], acc[mb]);
-            }
         }
-        f32x4 gp[3][8];
-        bf16x8 hb[4], f[8][4];
-        uint16_t *sh = stage + kStageHt * kStagePitch, *sd = stage + kStageDz * kStagePitch;
-        load_frags<kHid>(a.wt[1], n, g, f);
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb) {
+            acc[mb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kb = 0; kb < 7; ++kb) acc[mb] = mma(f1[mb][kb], xb[kb], acc[mb]);
+        }
+        load_frags<kHid>(a.wt[1], h, n, g, f);
+        load_bias(a.params + kOffB0, h, g, bv);
         issue_fence();
-        finish_hidden(acc, sbias, g, sh, col, gp[0], hb);
-        product(f, hb, acc);
-        load_frags<kHid>(a.wt[2], n, g, f);
+        finish_hidden(acc, bv, h, g, sh, col, gp[0], wv);
+    }
+    __syncthreads();   // layer 1 staged by both halves
+    if (active) {
+        gather_operand(wv, sh, h, g, col, x);
+        product(f, x, acc);
+        load_frags<kHid>(a.wt[2], h, n, g, f);
+        load_bias(a.params + kOffB1, h, g, bv);
         issue_fence();
-        finish_hidden(acc, sbias + kHid, g, sh + kHid * kStagePitch, col, gp[1], hb);
-        product(f, hb, acc);
-        bf16x8 fo[4], f4[8];
+        finish_hidden(acc, bv, h, g, sh + kHid * kStagePitch, col, gp[1], wv);
+    }
+    __syncthreads();   // layer 2 staged
+    bf16x8 f4[4];
+    float yb[4] = {0.f, 0.f, 0.f, 0.f};   // output bias of the lane's rows m = 4 g + j
+    if (active) {
+        gather_operand(wv, sh + kHid * kStagePitch, h, g, col, x);
+        product(f, x, acc);
+        bf16x8 fo[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) fo[q] = load_perm(a.wt[3] + n * kHid, q, g);
 #pragma unroll
-        for (int kb = 0; kb < 8; ++kb) f4[kb] = load_perm(a.wn[3] + (16 * kb + n) * 32, 0, g);
+        for (int kb = 0; kb < 4; ++kb) f4[kb] = load_perm(a.wn[3] + (16 * (4 * h + kb) + n) * 32, 0, g);
+        load_bias(a.params + kOffB2, h, g, bv);
+        if (g == 0)
+#pragma unroll
+            for (int j = 0; j < kOut; ++j) yb[j] = a.params[kOffB3 + j];
         issue_fence();
-        finish_hidden(acc, sbias + 2 * kHid, g, sh + 2 * kHid * kStagePitch, col, gp[2], hb);
-
-        // output layer (rows m = 4 g + j, three of them real), loss and dY
-        bf16x8 db[4];
-        {
-            f32x4 y = {0.f, 0.f, 0.f, 0.f};
+        finish_hidden(acc, bv, h, g, sh + 2 * kHid * kStagePitch, col, gp[2], wv);
+        f[0][0] = fo[0];
+        f[0][1] = fo[1];
+        f[0][2] = fo[2];
+        f[0][3] = fo[3];
+    }
+    __syncthreads();   // layer 3 staged
+    double lp = 0.0;
+    if (active) {
+        gather_operand(wv, sh + 2 * kHid * kStagePitch, h, g, col, x);
+        // output layer (rows m = 4 g + j, three of them real) in both waves;
+        // the loss, dY's staged rows and its bias sums from wave 0
+        f32x4 y = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int q = 0; q < 4; ++q) y = mma(fo[q], hb[q], y);
-            float d[4];
+        for (int q = 0; q < 4; ++q) y = mma(f[0][q], x[q], y);
+        float d[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int m = 4 * g + j;
-                const float dd = m < kOut ? (y[j] + sbias[3 * kHid + m]) - t[j] : 0.f;
-                lp += 0.5 * (double)dd * (double)dd;
-                d[j] = dd * a.inv_b;
-            }
-            const uint32_t w0 = pack2(d[0], d[1]), w1 = pack2(d[2], d[3]);
+        for (int j = 0; j < 4; ++j) {
+            const int m = 4 * g + j;
+            const float dd = m < kOut ? (y[j] + yb[j]) - t[j] : 0.f;
+            lp += 0.5 * (double)dd * (double)dd;
+            d[j] = dd * a.inv_b;
+        }
+        const uint32_t w0 = pack2(d[0], d[1]), w1 = pack2(d[2], d[3]);
+        const bf16x8 dy = as_bf16x8(make_uint4(w0, w1, 0u, 0u));
+        if (h == 0) {
             stage_t4(sd + 3 * kHid * kStagePitch, 4 * g, col, w0, w1);
-            db[0] = as_bf16x8(make_uint4(w0, w1, 0u, 0u));
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const double s = sum16((double)d[j]);
                 if (n == 0) bs[3 * kHid + 4 * g + j] = s;
             }
         }
-
         // backward: dZ_l = (dZ_{l+1} W_{l+1}^T) .* gelu'(Z_l), l = 3, 2, 1
 #pragma unroll
-        for (int kb = 0; kb < 8; ++kb) {
-            acc[kb] = mma(f4[kb], db[0], f32x4{0.f, 0.f, 0.f, 0.f});
+        for (int kb = 0; kb < 4; ++kb) {
+            acc[kb] = mma(f4[kb], dy, f32x4{0.f, 0.f, 0.f, 0.f});
             acc[kb] *= gp[2][kb];
         }
-        load_frags<kHid>(a.wn[2], n, g, f);
+        load_frags<kHid>(a.wn[2], h, n, g, f);
         issue_fence();
-        emit_grad(acc, n, g, sd + 2 * kHid * kStagePitch, col, bs + 2 * kHid, db);
-        product(f, db, acc);
+        emit_grad(acc, h, n, g, sd + 2 * kHid * kStagePitch, col, bs + 2 * kHid, wv);
+    }
+    __syncthreads();   // dZ3 staged
+    if (active) {
+        gather_operand(wv, sd + 2 * kHid * kStagePitch, h, g, col, x);
+        product(f, x, acc);
 #pragma unroll
-        for (int kb = 0; kb < 8; ++kb) acc[kb] *= gp[1][kb];
-        load_frags<kHid>(a.wn[1], n, g, f);
+        for (int kb = 0; kb < 4; ++kb) acc[kb] *= gp[1][kb];
+        load_frags<kHid>(a.wn[1], h, n, g, f);
         issue_fence();
-        emit_grad(acc, n, g, sd + kHid * kStagePitch, col, bs + kHid, db);
-        product(f, db, acc);
+        emit_grad(acc, h, n, g, sd + kHid * kStagePitch, col, bs + kHid, wv);
+    }
+    __syncthreads();   // dZ2 staged
+    if (active) {
+        gather_operand(wv, sd + kHid * kStagePitch, h, g, col, x);
+        product(f, x, acc);
 #pragma unroll
-        for (int kb = 0; kb < 8; ++kb) acc[kb] *= gp[0][kb];
-        emit_grad(acc, n, g, sd, col, bs, nullptr);
+        for (int kb = 0; kb < 4; ++kb) acc[kb] *= gp[0][kb];
+        emit_grad(acc, h, n, g, sd, col, bs, wv);
     } else {
-        for (int c = lane; c < kBiasCols; c += kWave) bs[c] = 0.0;
+        for (int c = h * kWave + lane; c < kBiasCols; c += 2 * kWave) bs[c] = 0.0;
     }
     lp = wave_sum(lp);
-    if (lane == 0 && tile * 16 < B) a.loss_part[tile] = lp * (double)a.inv_b;
-    __syncthreads();
-    for (int c = threadIdx.x; c < kBiasCols; c += kBlock) {
-        const double s = ((bsum[0][c] + bsum[1][c]) + bsum[2][c]) + bsum[3][c];
+    if (lane == 0 && h == 0 && active) a.loss_part[tile] = lp * (double)a.inv_b;
+    __syncthreads();   // the group is staged
+    for (int c = threadIdx.x; c < kBiasCols; c += kTrainThreads) {
+        const double s = bsum[0][c] + bsum[1][c];
         const int l = c < 3 * kHid ? c / kHid : 3, m = c - l * kHid, MP = mpad(l);
         a.part_b[l][(int64_t)blockIdx.x * MP + m] = s;
     }
-    // staged rows out: 16 threads per row, 4 batch rows (8 bytes) each, rows
-    // r0 + 16 i; chunks past B (a multiple of 16) belong to absent tiles
-    const int64_t b0 = (int64_t)blockIdx.x * kTrainGroupRows;
-    const int c = threadIdx.x & 15, r0 = threadIdx.x >> 4;
-    if (b0 + 4 * c < B) {
-        uint16_t *dst = a.tr + b0 + 4 * c;
-        const uint16_t *src = stage + 4 * c;
-        constexpr int kU = 9, kIter = kStageRows / 16;
-        static_assert(kIter % kU == 0, "whole rounds");
-        for (int i0 = 0; i0 < kIter; i0 += kU) {
-            uint2 v[kU];
+    // the staged block out: kTrRows rows of 32 batch rows, 8 threads per row
+    // with 4 batch rows (8 bytes) each; B is a multiple of 32, so a present
+    // group is whole
+    uint16_t *dst = a.tr + (int64_t)blockIdx.x * kStageRows * kTrBlock;
+    constexpr int kChunks = kStageRows * kTrBlock / 4, kU = 8;
+    constexpr int kIter = (kChunks + kTrainThreads - 1) / kTrainThreads;
+    for (int i0 = 0; i0 < kIter; i0 += kU) {
+        uint2 v[kU];
 #pragma unroll
-            for (int u = 0; u < kU; ++u)
-                v[u] = *reinterpret_cast<const uint2 *>(src + (r0 + 16 * (i0 + u)) * kStagePitch);
+        for (int u = 0; u < kU; ++u) {
+            const int e = threadIdx.x + kTrainThreads * (i0 + u);
+            if (e < kChunks) v[u] = *reinterpret_cast<const uint2 *>(stage + (e >> 3) * kStagePitch + 4 * (e & 7));
+        }
 #pragma unroll
-            for (int u = 0; u < kU; ++u) *reinterpret_cast<uint2 *>(dst + (int64_t)(r0 + 16 * (i0 + u)) * B) = v[u];
+        for (int u = 0; u < kU; ++u) {
+            const int e = threadIdx.x + kTrainThreads * (i0 + u);
+            if (e < kChunks) *reinterpret_cast<uint2 *>(dst + 4 * e) = v[u];
         }
     }
 }
 
 // Weight gradients of one layer over a chunk of rows:
 //   part_w[c][m][k] = sum_{b in chunk} dZ[b][m] H[b][k]   (BF16 x BF16, FP32 accumulate)
-// from the transposed copies dZT [16 MT][B] and HT [16 KT][B].  Rows in chunks
-// of kChunk; B is a multiple of 32.  Each of the kWgradWaves waves of a
-// workgroup owns output column blocks kt and keeps all MT row blocks in
-// registers: per 32 rows it loads one HT fragment and the MT dZT fragments and
-// issues MT independent products.
+// from the training pass's transposed rows (dZ rows dz_row + 16 MT, H rows
+// h_row + 16 KT, blocks of kTrBlock batch rows).  Rows in chunks of kChunk; B
+// is a multiple of 32.  Each of the kWgradWaves waves of a workgroup owns
+// output column blocks kt and keeps all MT row blocks in registers: per 32 rows
+// it loads one H fragment and the MT dZ fragments and issues MT independent
+// products.
 constexpr int kWgradWaves = 8;
 template <int MT, int KT>
-__global__ __launch_bounds__(kWgradWaves * kWave) void k_wgrad(const uint16_t *__restrict__ dZT,
-                                                               const uint16_t *__restrict__ HT, int64_t B,
-                                                               float *__restrict__ part_w) {
+__global__ __launch_bounds__(kWgradWaves * kWave) void k_wgrad(const uint16_t *__restrict__ tr, int dz_row, int h_row,
+                                                               int64_t B, float *__restrict__ part_w) {
     constexpr int MP = 16 * MT, KP = 16 * KT;
+    constexpr int64_t kBlk = (int64_t)kTrRows * kTrBlock;   // elements per block of batch rows
+    static_assert(kTrBlock == 32, "one block per 32-row product");
     const int lane = lane_id(), n = lane & 15, g = lane >> 4, wave = threadIdx.x >> 6;
     const int64_t c = blockIdx.x;
     const int64_t b0 = c * kChunk, b1 = (b0 + kChunk < B) ? b0 + kChunk : B;
@@ -545,8 +595,8 @@ __global__ __launch_bounds__(kWgradWaves * kWave) void k_wgrad(const uint16_t *_
         f32x4 acc[MT];
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) acc[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
-        const uint16_t *pb = HT + (int64_t)(16 * kt + n) * B + 8 * g;
-        const uint16_t *pa = dZT + (int64_t)n * B + 8 * g;
+        const uint16_t *pb = tr + (int64_t)(h_row + 16 * kt + n) * kTrBlock + 8 * g;
+        const uint16_t *pa = tr + (int64_t)(dz_row + n) * kTrBlock + 8 * g;
         // kU groups of 32 rows per round, all their loads issued before the
         // products (the rows are still summed in order)
         constexpr int kU = MT > 4 ? 4 : 8;
@@ -556,9 +606,10 @@ __global__ __launch_bounds__(kWgradWaves * kWave) void k_wgrad(const uint16_t *_
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
                 const int64_t r = bb + 32 * u < b1 ? bb + 32 * u : b1 - 32;
-                bv[u] = load8(pb + r);
+                const int64_t o = (r / kTrBlock) * kBlk;
+                bv[u] = load8(pb + o);
 #pragma unroll
-                for (int mt = 0; mt < MT; ++mt) av[u][mt] = load8(pa + (int64_t)16 * mt * B + r);
+                for (int mt = 0; mt < MT; ++mt) av[u][mt] = load8(pa + 16 * mt * kTrBlock + o);
             }
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
@@ -1207,13 +1258,13 @@ hipError_t launch_gradients(const NetBufs &net, const TrainBufs &tb, const float
     a.tr = tb.tr;
     a.loss_part = tb.loss_part;
     const unsigned nt = (unsigned)n_train_groups(B);
-    hipLaunchKernelGGL(k_train_tile, dim3(nt), bl, 0, st, a);
+    hipLaunchKernelGGL(k_train_tile, dim3(nt), dim3(kTrainThreads), 0, st, a);
     const unsigned nc = (unsigned)n_chunks(B);
     const dim3 bw(kWgradWaves * kWave);
-    hipLaunchKernelGGL((k_wgrad<8, 14>), dim3(nc), bw, 0, st, tr_dz(tb, 0, B), tr_x0(tb), B, tb.part_w[0]);
-    hipLaunchKernelGGL((k_wgrad<8, 8>), dim3(nc), bw, 0, st, tr_dz(tb, 1, B), tr_h(tb, 0, B), B, tb.part_w[1]);
-    hipLaunchKernelGGL((k_wgrad<8, 8>), dim3(nc), bw, 0, st, tr_dz(tb, 2, B), tr_h(tb, 1, B), B, tb.part_w[2]);
-    hipLaunchKernelGGL((k_wgrad<1, 8>), dim3(nc), bw, 0, st, tr_dz(tb, 3, B), tr_h(tb, 2, B), B, tb.part_w[3]);
+    hipLaunchKernelGGL((k_wgrad<8, 14>), dim3(nc), bw, 0, st, tb.tr, kTrDz, 0, B, tb.part_w[0]);
+    hipLaunchKernelGGL((k_wgrad<8, 8>), dim3(nc), bw, 0, st, tb.tr, kTrDz + kHid, kTrHt, B, tb.part_w[1]);
+    hipLaunchKernelGGL((k_wgrad<8, 8>), dim3(nc), bw, 0, st, tb.tr, kTrDz + 2 * kHid, kTrHt + kHid, B, tb.part_w[2]);
+    hipLaunchKernelGGL((k_wgrad<1, 8>), dim3(nc), bw, 0, st, tb.tr, kTrDz + 3 * kHid, kTrHt + 2 * kHid, B, tb.part_w[3]);
     GradParts parts;
     for (int l = 0; l < 4; ++l) {
         parts.w[l] = tb.part_w[l];

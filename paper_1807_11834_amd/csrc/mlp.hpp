@@ -39,24 +39,25 @@ struct TrainBufs {
     uint16_t *x0 = nullptr;                        // standardised input [B][224] (batch inference)
     uint16_t *h[3] = {};                           // hidden activations [B][128] (batch inference)
     float *y = nullptr;                            // output [B][16] (batch inference)
-    uint16_t *tr = nullptr;                        // training: BF16 transposed rows [kTrRows][B] (below)
+    uint16_t *tr = nullptr;                        // training: BF16 transposed rows, blocked (below)
     float *part_w[4] = {};                         // per-chunk weight gradients [nchunk][MP][KP]
     double *part_b[4] = {};                        // per-workgroup bias gradients [ngroup][MP]
     double *loss_part = nullptr;                   // per-16-row tile [B/16]
     float *grads = nullptr;                        // [kNParam]
 };
 
-// Rows of the training pass's transposed output, each B long: the layer-1
-// input (224 rows), the hidden activations of layers 1-3 (3 x 128), the output
-// gradients of layers 1-3 (3 x 128) and of layer 4 (16).
+// Rows of the training pass's transposed output: the layer-1 input (224
+// rows), the hidden activations of layers 1-3 (3 x 128), the output gradients
+// of layers 1-3 (3 x 128) and of layer 4 (16).  Stored in blocks of kTrBlock
+// batch rows, element (row r, batch row b) at
+// tr[(b / kTrBlock) kTrRows kTrBlock + r kTrBlock + b % kTrBlock], so that a
+// workgroup of the pass writes one contiguous block.
 constexpr int kTrHt = kK1, kTrDz = kK1 + 3 * kHid, kTrRows = kTrDz + 3 * kHid + 16;
-inline uint16_t *tr_x0(const TrainBufs &tb) { return tb.tr; }
-inline uint16_t *tr_h(const TrainBufs &tb, int l, int64_t B) { return tb.tr + (int64_t)(kTrHt + kHid * l) * B; }
-inline uint16_t *tr_dz(const TrainBufs &tb, int l, int64_t B) { return tb.tr + (int64_t)(kTrDz + kHid * l) * B; }
+constexpr int kTrBlock = 32;
 
 constexpr int64_t kChunk = 256;   // rows per workgroup in the weight-gradient products
 inline int64_t n_chunks(int64_t B) { return (B + kChunk - 1) / kChunk; }
-constexpr int64_t kTrainGroupRows = 64;   // rows per workgroup of the training pass
+constexpr int64_t kTrainGroupRows = kTrBlock;   // rows per workgroup of the training pass
 inline int64_t n_train_groups(int64_t B) { return (B + kTrainGroupRows - 1) / kTrainGroupRows; }
 
 // Device state of one network (owned by the couple_mlp handle).
