@@ -93,13 +93,17 @@ __device__ __forceinline__ void decode_param(int64_t i, int &l, bool &w, int &k,
 }
 
 struct WPtrs {
-    uint16_t *wt[4], *wn[4];
+    uint16_t *wt[4], *wn[4], *wtp[4], *wnp[4];
 };
 
 __device__ __forceinline__ void write_bf16_copies(const WPtrs &w, int l, int k, int m, float p) {
     const uint16_t b = (uint16_t)bf16_bits(p);
     w.wt[l][(int64_t)m * kpad(l) + k] = b;
-    if (l > 0) w.wn[l][(int64_t)k * cpad(l) + m] = b;
+    if (l > 0) {
+        w.wn[l][(int64_t)k * cpad(l) + m] = b;
+        w.wtp[l][(int64_t)m * kpad(l) + perm_col(k)] = b;
+        w.wnp[l][(int64_t)k * cpad(l) + perm_col(m)] = b;
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_cast(const float *__restrict__ params, WPtrs w) {
@@ -244,18 +248,12 @@ struct TrainArgs {
     const float *mean_inv;
     float is[3], inv_b;
     const float *params;
-    const uint16_t *wt[4], *wn[4];
+    const uint16_t *wt0;              // layer-1 W^T, natural order
+    const uint16_t *wtp[4], *wnp[4];  // layers 2-4, permuted order
     uint16_t *tr;   // transposed rows, blocks of kTrBlock batch rows
     double *part_b[4];
     double *loss_part;
 };
-
-// Row r of a BF16 matrix, contraction block q, in the permuted slot order.
-__device__ __forceinline__ bf16x8 load_perm(const uint16_t *r, int q, int g) {
-    const uint2 lo = *reinterpret_cast<const uint2 *>(r + 32 * q + 4 * g);
-    const uint2 hi = *reinterpret_cast<const uint2 *>(r + 32 * q + 16 + 4 * g);
-    return as_bf16x8(make_uint4(lo.x, lo.y, hi.x, hi.y));
-}
 
 // Four BF16 values (two packed words) of column col staged to rows r0 .. r0+3.
 __device__ __forceinline__ void stage_t4(uint16_t *S, int r0, int col, uint32_t w0, uint32_t w1) {
@@ -360,15 +358,16 @@ __device__ __forceinline__ void gather_operand(const uint32_t (&w)[4][2], const 
 }
 
 // Half of a 128 x 128 product in the permuted order: f[r][q] = row 16 (4h + r)
-// + n of M (pitch P), contraction block q.  A layer's fragments are loaded as
-// one batch, ahead of the work before the product, so that their latency
-// overlaps it; the product then runs on registers.
+// + n of Mp (a permuted copy, pitch P), contraction block q, one 16-byte load.
+// A layer's fragments are loaded as one batch, ahead of the work before the
+// product, so that their latency overlaps it; the product then runs on
+// registers.
 template <int P>
-__device__ __forceinline__ void load_frags(const uint16_t *__restrict__ M, int h, int n, int g, bf16x8 (&f)[4][4]) {
+__device__ __forceinline__ void load_frags(const uint16_t *__restrict__ Mp, int h, int n, int g, bf16x8 (&f)[4][4]) {
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) f[r][q] = load_perm(M + (16 * (4 * h + r) + n) * P, q, g);
+        for (int q = 0; q < 4; ++q) f[r][q] = load8(Mp + (16 * (4 * h + r) + n) * P + 32 * q + 8 * g);
 }
 // The bias values of a hidden layer for the lane's rows of blocks 4h .. 4h+3.
 __device__ __forceinline__ void load_bias(const float *__restrict__ bias, int h, int g, float4 (&bv)[4]) {
@@ -427,7 +426,7 @@ __global__ __launch_bounds__(kTrainThreads) __attribute__((amdgpu_waves_per_eu(2
         for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
             for (int kb = 0; kb < 7; ++kb)
-                f1[mb][kb] = load8(a.wt[0] + (16 * (4 * h + mb) + n) * kK1 + 32 * kb + 8 * g);
+                f1[mb][kb] = load8(a.wt0 + (16 * (4 * h + mb) + n) * kK1 + 32 * kb + 8 * g);
         issue_fence();
         bf16x8 xb[7];
 #pragma unroll
@@ -451,7 +450,7 @@ __global__ __launch_bounds__(kTrainThreads) __attribute__((amdgpu_waves_per_eu(2
 #pragma unroll
             for (int kb = 0; kb < 7; ++kb) acc[mb] = mma(f1[mb][kb], xb[kb], acc[mb]);
         }
-        load_frags<kHid>(a.wt[1], h, n, g, f);
+        load_frags<kHid>(a.wtp[1], h, n, g, f);
         load_bias(a.params + kOffB0, h, g, bv);
         issue_fence();
         finish_hidden(acc, bv, h, g, sh, col, gp[0], wv);
@@ -460,7 +459,7 @@ __global__ __launch_bounds__(kTrainThreads) __attribute__((amdgpu_waves_per_eu(2
     if (active) {
         gather_operand(wv, sh, h, g, col, x);
         product(f, x, acc);
-        load_frags<kHid>(a.wt[2], h, n, g, f);
+        load_frags<kHid>(a.wtp[2], h, n, g, f);
         load_bias(a.params + kOffB1, h, g, bv);
         issue_fence();
         finish_hidden(acc, bv, h, g, sh + kHid * kStagePitch, col, gp[1], wv);
@@ -473,9 +472,9 @@ __global__ __launch_bounds__(kTrainThreads) __attribute__((amdgpu_waves_per_eu(2
         product(f, x, acc);
         bf16x8 fo[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) fo[q] = load_perm(a.wt[3] + n * kHid, q, g);
+        for (int q = 0; q < 4; ++q) fo[q] = load8(a.wtp[3] + n * kHid + 32 * q + 8 * g);
 #pragma unroll
-        for (int kb = 0; kb < 4; ++kb) f4[kb] = load_perm(a.wn[3] + (16 * (4 * h + kb) + n) * 32, 0, g);
+        for (int kb = 0; kb < 4; ++kb) f4[kb] = load8(a.wnp[3] + (16 * (4 * h + kb) + n) * 32 + 8 * g);
         load_bias(a.params + kOffB2, h, g, bv);
         if (g == 0)
 #pragma unroll
@@ -520,7 +519,7 @@ __global__ __launch_bounds__(kTrainThreads) __attribute__((amdgpu_waves_per_eu(2
             acc[kb] = mma(f4[kb], dy, f32x4{0.f, 0.f, 0.f, 0.f});
             acc[kb] *= gp[2][kb];
         }
-        load_frags<kHid>(a.wn[2], h, n, g, f);
+        load_frags<kHid>(a.wnp[2], h, n, g, f);
         issue_fence();
         emit_grad(acc, h, n, g, sd + 2 * kHid * kStagePitch, col, bs + 2 * kHid, wv);
     }
@@ -530,7 +529,7 @@ __global__ __launch_bounds__(kTrainThreads) __attribute__((amdgpu_waves_per_eu(2
         product(f, x, acc);
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb) acc[kb] *= gp[1][kb];
-        load_frags<kHid>(a.wn[1], h, n, g, f);
+        load_frags<kHid>(a.wnp[1], h, n, g, f);
         issue_fence();
         emit_grad(acc, h, n, g, sd + kHid * kStagePitch, col, bs + kHid, wv);
     }
@@ -1198,6 +1197,8 @@ static WPtrs wptrs(const NetBufs &net) {
     for (int l = 0; l < 4; ++l) {
         w.wt[l] = net.wt[l];
         w.wn[l] = net.wn[l];
+        w.wtp[l] = net.wtp[l];
+        w.wnp[l] = net.wnp[l];
     }
     return w;
 }
@@ -1250,9 +1251,10 @@ hipError_t launch_gradients(const NetBufs &net, const TrainBufs &tb, const float
     for (int j = 0; j < 3; ++j) a.is[j] = inv_scale[j];
     a.inv_b = (float)(1.0 / (double)B);
     a.params = net.params;
+    a.wt0 = net.wt[0];
     for (int l = 0; l < 4; ++l) {
-        a.wt[l] = net.wt[l];
-        a.wn[l] = net.wn[l];
+        a.wtp[l] = net.wtp[l];
+        a.wnp[l] = net.wnp[l];
         a.part_b[l] = tb.part_b[l];
     }
     a.tr = tb.tr;

@@ -7,6 +7,10 @@
 //   wt[l]  W_l^T as [MP_l][KP_l]  (fan-out rows padded to 16, fan-in to 32)
 //   wn[l]  W_l   as [KP_l][CP_l]  (fan-out padded to a 32-wide contraction),
 //          layers 2-4 only (the backward product needs no input gradient of layer 1).
+//   wtp[l], wnp[l]  the same as wt[l], wn[l] for layers 2-4 with each row in the
+//          permuted slot order of the training pass (column 32q + 16s + 4g + j
+//          stored at 32q + 8g + 4s + j), so that a product fragment is one
+//          16-byte load.
 // Padding entries are zero.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -31,6 +35,10 @@ __host__ __device__ constexpr int64_t off_w(int l) {
 __host__ __device__ constexpr int64_t off_b(int l) { return off_w(l) + (int64_t)fan_in(l) * fan_out(l); }
 constexpr int64_t kNParam = off_b(3) + kOut;
 static_assert(kNParam == 58243, "parameter count");
+// Position of column c of a row in the permuted slot order.
+__host__ __device__ constexpr int perm_col(int c) {
+    return (c & ~31) | (((c >> 2) & 3) << 3) | (((c >> 4) & 1) << 2) | (c & 3);
+}
 constexpr int kK1 = 224;     // padded layer-1 fan-in (and the length of mean/1/std)
 
 // Training and batch-inference buffers, sized for max_batch rows.
@@ -64,6 +72,7 @@ inline int64_t n_train_groups(int64_t B) { return (B + kTrainGroupRows - 1) / kT
 struct NetBufs {
     float *params = nullptr, *m = nullptr, *v = nullptr;   // FP32 master and Adam moments [kNParam]
     uint16_t *wt[4] = {}, *wn[4] = {};
+    uint16_t *wtp[4] = {}, *wnp[4] = {};                    // permuted copies, layers 2-4
     float *mean_inv = nullptr;                              // [2][224]
 };
 

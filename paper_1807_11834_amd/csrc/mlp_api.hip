@@ -40,6 +40,8 @@ static void mlp_release(couple_mlp *m) {
     for (int l = 0; l < 4; ++l) {
         ptrs.push_back(m->net.wt[l]);
         ptrs.push_back(m->net.wn[l]);
+        ptrs.push_back(m->net.wtp[l]);
+        ptrs.push_back(m->net.wnp[l]);
         ptrs.push_back(m->tb.part_w[l]);
         ptrs.push_back(m->tb.part_b[l]);
     }
@@ -92,7 +94,9 @@ extern "C" int couple_mlp_init(const couple_mlp_config *cfg, couple_mlp **out) {
               alloc0(&m->net.v, sizeof(float) * kNParam) && alloc0(&m->net.mean_inv, sizeof(float) * 2 * kK1);
     for (int l = 0; l < 4 && ok; ++l) {
         ok = alloc0(&m->net.wt[l], sizeof(uint16_t) * mpad(l) * kpad(l)) &&
-             (l == 0 || alloc0(&m->net.wn[l], sizeof(uint16_t) * kpad(l) * cpad(l))) &&
+             (l == 0 || (alloc0(&m->net.wn[l], sizeof(uint16_t) * kpad(l) * cpad(l)) &&
+                         alloc0(&m->net.wtp[l], sizeof(uint16_t) * mpad(l) * kpad(l)) &&
+                         alloc0(&m->net.wnp[l], sizeof(uint16_t) * kpad(l) * cpad(l)))) &&
              alloc0(&tb.part_w[l], sizeof(float) * nc * mpad(l) * kpad(l)) &&
              alloc0(&tb.part_b[l], sizeof(double) * ng * mpad(l));
     }
