@@ -582,8 +582,8 @@ __global__ __launch_bounds__(kTrainThreads) __attribute__((amdgpu_waves_per_eu(2
 // products.
 constexpr int kWgradWaves = 8;
 template <int MT, int KT>
-__global__ __launch_bounds__(kWgradWaves * kWave) void k_wgrad(const uint16_t *__restrict__ tr, int dz_row, int h_row,
-                                                               int64_t B, float *__restrict__ part_w) {
+__device__ __forceinline__ void wgrad_chunk(const uint16_t *__restrict__ tr, int dz_row, int h_row, int64_t B,
+                                            float *__restrict__ part_w) {
     constexpr int MP = 16 * MT, KP = 16 * KT;
     constexpr int64_t kBlk = (int64_t)kTrRows * kTrBlock;   // elements per block of batch rows
     static_assert(kTrBlock == 32, "one block per 32-row product");
@@ -626,6 +626,21 @@ __global__ __launch_bounds__(kWgradWaves * kWave) void k_wgrad(const uint16_t *_
     }
 }
 
+// The four layers' weight gradients in one launch (blockIdx.y = layer), so
+// that the short layers fill the tail of the long one.
+struct WgradParts {
+    float *w[4];
+};
+__global__ __launch_bounds__(kWgradWaves * kWave) void k_wgrad(const uint16_t *__restrict__ tr, int64_t B,
+                                                               WgradParts parts) {
+    switch (blockIdx.y) {
+    case 0: wgrad_chunk<8, 14>(tr, kTrDz, 0, B, parts.w[0]); break;
+    case 1: wgrad_chunk<8, 8>(tr, kTrDz + kHid, kTrHt, B, parts.w[1]); break;
+    case 2: wgrad_chunk<8, 8>(tr, kTrDz + 2 * kHid, kTrHt + kHid, B, parts.w[2]); break;
+    default: wgrad_chunk<1, 8>(tr, kTrDz + 3 * kHid, kTrHt + 2 * kHid, B, parts.w[3]); break;
+    }
+}
+
 struct GradParts {
     const float *w[4];
     const double *b[4];
@@ -635,9 +650,8 @@ struct GradParts {
 // partials' layout (per layer the padded [m][k] slots, k fastest), so that the
 // loads of a wave are contiguous; each is summed by kRedGroups threads over
 // interleaved chunks (c mod kRedGroups, two partial sums each) whose results
-// are combined in a fixed order.  Each bias entry is summed by one wave over
-// the nchunk_b workgroup partials of the training pass (lane c mod 64, then a
-// fixed butterfly).
+// are combined in a fixed order.  The bias entries are summed over the
+// nchunk_b workgroup partials of the training pass (below).
 constexpr int kRedGroups = 8;
 constexpr int kRedEntries = kBlock / kRedGroups;   // entries per workgroup
 constexpr int64_t kRedW1 = (int64_t)mpad(0) * kpad(0), kRedW2 = kRedW1 + (int64_t)mpad(1) * kpad(1),
@@ -675,16 +689,34 @@ __global__ __launch_bounds__(kBlock) void k_reduce_w(GradParts parts, int64_t nc
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_reduce_b(GradParts parts, int64_t nchunk_b, float *__restrict__ grads) {
+// kRedBEntries consecutive bias entries per workgroup, kRedBLanes threads per
+// entry over interleaved partials (c mod kRedBLanes; a wave reads 8 partials
+// of 8 consecutive entries), then one thread per entry adds the lanes' sums
+// in lane order.
+constexpr int kRedBEntries = 8, kRedBLanes = 128, kRedBThreads = kRedBEntries * kRedBLanes;
+__global__ __launch_bounds__(kRedBThreads) void k_reduce_b(GradParts parts, int64_t nchunk_b, float *__restrict__ grads) {
     constexpr int64_t kOffB[4] = {off_b(0), off_b(1), off_b(2), off_b(3)};
-    const int e = (int)(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6)), lane = lane_id();
-    if (e >= kRedBias) return;   // whole wave
+    __shared__ double red[kRedBLanes][kRedBEntries];
+    const int le = threadIdx.x % kRedBEntries, cl = threadIdx.x / kRedBEntries;
+    const int e = (int)blockIdx.x * kRedBEntries + le;
     const int l = e < 3 * kHid ? e / kHid : 3, m = e - l * kHid, MP = mpad(l);
-    const double *p = parts.b[l] + m;
-    double s = 0.0;
-    for (int64_t c = lane; c < nchunk_b; c += kWave) s += p[c * MP];
-    s = wave_sum(s);
-    if (lane == 0) grads[kOffB[l] + m] = (float)s;
+    double s0 = 0.0, s1 = 0.0;
+    if (e < kRedBias) {
+        const double *p = parts.b[l] + m;
+        int64_t c = cl;
+        for (; c + kRedBLanes < nchunk_b; c += 2 * kRedBLanes) {
+            s0 += p[c * MP];
+            s1 += p[(c + kRedBLanes) * MP];
+        }
+        if (c < nchunk_b) s0 += p[c * MP];
+    }
+    red[cl][le] = s0 + s1;
+    __syncthreads();
+    if (cl == 0 && e < kRedBias) {
+        double t = 0.0;
+        for (int q = 0; q < kRedBLanes; ++q) t += red[q][le];
+        grads[kOffB[l] + m] = (float)t;
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_sum_loss(const double *__restrict__ part, int64_t n, float *__restrict__ out) {
@@ -1263,10 +1295,9 @@ hipError_t launch_gradients(const NetBufs &net, const TrainBufs &tb, const float
     hipLaunchKernelGGL(k_train_tile, dim3(nt), dim3(kTrainThreads), 0, st, a);
     const unsigned nc = (unsigned)n_chunks(B);
     const dim3 bw(kWgradWaves * kWave);
-    hipLaunchKernelGGL((k_wgrad<8, 14>), dim3(nc), bw, 0, st, tb.tr, kTrDz, 0, B, tb.part_w[0]);
-    hipLaunchKernelGGL((k_wgrad<8, 8>), dim3(nc), bw, 0, st, tb.tr, kTrDz + kHid, kTrHt, B, tb.part_w[1]);
-    hipLaunchKernelGGL((k_wgrad<8, 8>), dim3(nc), bw, 0, st, tb.tr, kTrDz + 2 * kHid, kTrHt + kHid, B, tb.part_w[2]);
-    hipLaunchKernelGGL((k_wgrad<1, 8>), dim3(nc), bw, 0, st, tb.tr, kTrDz + 3 * kHid, kTrHt + 2 * kHid, B, tb.part_w[3]);
+    WgradParts wp;
+    for (int l = 0; l < 4; ++l) wp.w[l] = tb.part_w[l];
+    hipLaunchKernelGGL(k_wgrad, dim3(nc, 4), bw, 0, st, tb.tr, B, wp);
     GradParts parts;
     for (int l = 0; l < 4; ++l) {
         parts.w[l] = tb.part_w[l];
@@ -1274,8 +1305,8 @@ hipError_t launch_gradients(const NetBufs &net, const TrainBufs &tb, const float
     }
     hipLaunchKernelGGL(k_reduce_w, dim3((unsigned)((kRedTotal + kRedEntries - 1) / kRedEntries)), bl, 0, st, parts,
                        (int64_t)nc, grads);
-    hipLaunchKernelGGL(k_reduce_b, dim3((unsigned)((kRedBias + kWavesPerBlock - 1) / kWavesPerBlock)), bl, 0, st, parts,
-                       (int64_t)nt, grads);
+    hipLaunchKernelGGL(k_reduce_b, dim3((unsigned)((kRedBias + kRedBEntries - 1) / kRedBEntries)), dim3(kRedBThreads), 0,
+                       st, parts, (int64_t)nt, grads);
     if (loss) hipLaunchKernelGGL(k_sum_loss, dim3(1), bl, 0, st, tb.loss_part, B / 16, loss);
     return hipGetLastError();
 }
