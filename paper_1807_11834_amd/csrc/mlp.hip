@@ -21,10 +21,10 @@
 // 32q+16+4g+j.  The in-step inference kernel chains the four layers this way in
 // registers, with the weights pre-permuted into that slot order in LDS.
 //
-// The training pass chains forward and backward the same way, one 16-row tile
-// per wave, and writes transposed copies of the layer inputs and output
-// gradients for the weight-gradient products, whose contraction runs over the
-// batch.  Batch inference on given features runs layer by layer over HBM in
+// The training pass chains forward and backward the same way, a 16-row tile
+// per pair of waves, and writes transposed copies of the layer inputs and
+// output gradients for the weight-gradient products, whose contraction runs
+// over the batch.  Batch inference on given features runs layer by layer over HBM in
 // the natural slot order (rows k = 32q + 8g + i).  Every reduction has a fixed
 // order.
 #include <type_traits>
@@ -234,8 +234,8 @@ static_assert(kTrainGroupRows == 16 * kTrainTiles, "two 16-row tiles per workgro
 constexpr int kTrainWaves = 2 * kTrainTiles;      // two waves per tile
 constexpr int kTrainThreads = kTrainWaves * kWave;
 constexpr int kBiasCols = 3 * kHid + 16;          // bias-gradient columns, layers 1-4
-// Staged transposed rows: x0t (224), ht[0..2] (3 x 128), dzt[0..2] (3 x 128),
-// dzt[3] (16).  36 BF16 per staged row: the four rows that one access
+// Staged transposed rows: layer-1 input (224), hidden activations (3 x 128),
+// output gradients (3 x 128 + 16).  36 BF16 per staged row: the four rows that one access
 // instruction touches per lane group (4 apart) then fall 8 banks apart.
 constexpr int kStagePitch = kTrainGroupRows + 4;
 constexpr int kStageHt = kTrHt, kStageDz = kTrDz, kStageRows = kTrRows;
