@@ -188,6 +188,37 @@ def test_gradients_match_oracle(env):
     m.close()
 
 
+@pytest.mark.parametrize("B, use_idx", [(32, True), (96, False), (288, True), (4096, True)])
+def test_gradients_at_edge_batch_sizes(env, B, use_idx):
+    """Gradient parity where the batch leaves partial units: the training pass
+    takes 32 rows per workgroup and the weight-gradient products 256-row chunks
+    (one workgroup; a single partial chunk without an index; a whole chunk and
+    a partial one; the largest batch of the handle)."""
+    torch, cpl, oracle = env
+    case = _small_case(torch, cpl)
+    feat, ub, res = _features(torch, cpl, case)
+    X = feat.cpu().numpy().astype(np.float64)
+    R = res.cpu().numpy().astype(np.float64)
+    mean, std = M.norm_stats(X)
+    scale = M.target_scale(R)
+    params = _params(5)
+    m = _net(torch, cpl, params, mean, std, scale)
+    rows = (np.random.default_rng(B).choice(X.shape[0], B, replace=False).astype(np.int32) if use_idx
+            else np.arange(B, dtype=np.int32))
+    grads = torch.empty(M.NPARAM, dtype=torch.float32, device="cuda:0")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda:0")
+    m.grads(feat, res, B, grads, idx=torch.from_numpy(rows).cuda() if use_idx else None, loss=loss)
+    torch.cuda.synchronize()
+    lo, go = M.loss_and_grads(params, M.standardise(X[rows], mean, std), R[rows] / scale, emulate=True)
+    assert abs(float(loss.item()) - lo) <= 1e-4 * lo, (loss.item(), lo)
+    gg = M.unflatten(grads.cpu().numpy())
+    for l, ((gw, gb), (ow, ob)) in enumerate(zip(gg, go)):
+        ew, eb = _rel(gw, ow), _rel(gb, ob)
+        print(f"B {B} layer {l}: dW rel {ew:.2e}, db rel {eb:.2e}")
+        assert ew <= TOL_MLP and eb <= TOL_MLP, (B, l, ew, eb)
+    m.close()
+
+
 def test_adam_matches_oracle(env):
     torch, cpl, oracle = env
     params = _params(3)
