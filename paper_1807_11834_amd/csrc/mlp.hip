@@ -202,21 +202,24 @@ __global__ __launch_bounds__(kBlock) void k_dense(const uint16_t *__restrict__ X
 }
 
 // ---------------------------------------------------------------------------
-// Training pass: standardisation, forward, loss and backward of a 16-row tile
-// by a pair of waves
+// Training pass: standardisation, forward, loss and backward of 32 rows by a
+// workgroup of four waves
 // ---------------------------------------------------------------------------
-// Batch rows are the product columns (lane n holds row 16 tile + n) and neurons
-// the product rows, as in the in-step inference.  A layer's result is the next
-// B operand in the permuted slot order (slots 4s + j of group g <- neuron
-// 32q + 16s + 4g + j); the weight fragments are read in the same order, as two
-// 8-byte halves, and the backward products take the output gradients in the
-// same layout.  The two waves of a tile split every 128-neuron layer: wave h
-// computes neuron blocks 4h .. 4h+3 (64 neurons) and keeps their gelu'(Z),
-// formed in the forward pass with gelu (one exponential); the other half of
-// the next B operand is read back from the LDS stage below after a workgroup
-// barrier.  A workgroup takes two tiles (32 rows): with the halved registers
-// per wave and an 80 KB stage, two workgroups share a compute unit and hide
-// each other's load latency across the barriers.
+// Batch rows are the product columns (lane n holds row 16 t + n of tile t) and
+// neurons the product rows, as in the in-step inference.  A layer's result is
+// the next B operand in the permuted slot order (slots 4s + j of group g <-
+// neuron 32q + 16s + 4g + j); the weight fragments are read in the same order
+// from the permuted copies, and the backward products take the output
+// gradients in the same layout.  The four waves of a workgroup split every
+// 128-neuron layer: wave w computes neuron blocks 2w and 2w + 1 (one
+// contraction block q = w of the next product) for both 16-row tiles, so that
+// each weight fragment it loads feeds two products, and keeps their gelu'(Z),
+// formed in the forward pass with gelu (one exponential).  The other three
+// contraction blocks of the next B operand are read back from the LDS stage
+// below after a workgroup barrier; so is the layer-1 input, of which each wave
+// loads and standardises two of the seven 32-feature blocks.  With an 80 KB
+// stage and at most 256 registers per wave, two workgroups share a compute
+// unit.
 //
 // For the weight-gradient products over the batch the pass writes the BF16
 // layer inputs and the BF16 output gradients transposed, as the rows of one
@@ -224,19 +227,21 @@ __global__ __launch_bounds__(kBlock) void k_dense(const uint16_t *__restrict__ X
 // rows.  These are staged in LDS, [row][32 batch rows of the workgroup], and
 // leave at the end as the workgroup's contiguous block: a wave's stores and
 // loads share one in-order completion counter, so a store issued between the
-// weight loads of two layers would make the second layer wait for it.  The bias gradients are the
-// column sums of the FP32 output gradients: summed in FP64 over the 16 rows of
-// a tile (a fixed butterfly), then over the two tiles of a workgroup in tile
-// order, into part_b[l][workgroup][MP].  The loss partial of a tile is
-// sum 0.5 (y - t)^2 / B.  Rows b >= B do not occur (B is a multiple of 16).
+// weight loads of two layers would make the second layer wait for it.  The
+// bias gradients are the column sums of the FP32 output gradients: summed in
+// FP64 over the 16 rows of a tile (a fixed butterfly), then over the two tiles
+// of a workgroup in tile order, into part_b[l][workgroup][MP].  The loss
+// partial of a tile is sum 0.5 (y - t)^2 / B.  B is a multiple of 32: every
+// workgroup has both tiles.
 constexpr int kTrainTiles = 2;                    // 16-row tiles per workgroup
 static_assert(kTrainGroupRows == 16 * kTrainTiles, "two 16-row tiles per workgroup");
-constexpr int kTrainWaves = 2 * kTrainTiles;      // two waves per tile
+constexpr int kTrainWaves = 4;                    // a quarter of every layer's neurons each
 constexpr int kTrainThreads = kTrainWaves * kWave;
 constexpr int kBiasCols = 3 * kHid + 16;          // bias-gradient columns, layers 1-4
 // Staged transposed rows: layer-1 input (224), hidden activations (3 x 128),
-// output gradients (3 x 128 + 16).  36 BF16 per staged row: the four rows that one access
-// instruction touches per lane group (4 apart) then fall 8 banks apart.
+// output gradients (3 x 128 + 16).  36 BF16 per staged row: the four rows that
+// one access instruction touches per lane group (4 apart) then fall 8 banks
+// apart.
 constexpr int kStagePitch = kTrainGroupRows + 4;
 constexpr int kStageHt = kTrHt, kStageDz = kTrDz, kStageRows = kTrRows;
 static_assert(kStageRows % 16 == 0, "the output pass takes whole rows");
@@ -275,112 +280,125 @@ __device__ __forceinline__ double sum16(double v) {
     return v;
 }
 
-// Column sums over the 16 lanes of a lane group of the 16 values v = 4 kb + j
-// of a lane (FP32 in, FP64 sums): a reduce-scatter butterfly over lane bits 3,
-// 2, 1, 0.  Each stage keeps half of the values (the upper half where the lane
-// bit is set), adds the partner's copy of that half and sends the other half;
-// lane n ends with the sum of value n.  The adding order of every column is a
-// fixed tree (a + b = b + a exactly, so partners agree).
-__device__ __forceinline__ double colsum16(const f32x4 (&d)[4], int n) {
-    double s8[8];
+// Column sums over the 16 lanes of a lane group of the 8 values v = 4 b + j of
+// a lane (FP32 in, FP64 sums): a reduce-scatter butterfly over lane bits 3, 2,
+// 1 (each stage keeps half of the values, the upper half where the lane bit is
+// set, adds the partner's copy of that half and sends the other half), then
+// lanes n and n ^ 1 add their partial sums: both hold the sum of value n / 2.
+// The adding order of every column is a fixed tree (a + b = b + a exactly, so
+// partners agree).
+__device__ __forceinline__ double colsum8(const float (&v)[8], int n) {
+    double s4[4];
     const bool u3 = (n & 8) != 0;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const float lo = d[i >> 2][i & 3], hi = d[(i + 8) >> 2][(i + 8) & 3];
-        const float recv = __shfl_xor(u3 ? lo : hi, 8, kWave);
-        s8[i] = (double)(u3 ? hi : lo) + (double)recv;
+    for (int i = 0; i < 4; ++i) {
+        const float recv = __shfl_xor(u3 ? v[i] : v[i + 4], 8, kWave);
+        s4[i] = (double)(u3 ? v[i + 4] : v[i]) + (double)recv;
     }
-    double s4[4];
+    double s2[2];
     const bool u2 = (n & 4) != 0;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) s4[i] = (u2 ? s8[i + 4] : s8[i]) + __shfl_xor(u2 ? s8[i] : s8[i + 4], 4, kWave);
-    double s2[2];
+    for (int i = 0; i < 2; ++i) s2[i] = (u2 ? s4[i + 2] : s4[i]) + __shfl_xor(u2 ? s4[i] : s4[i + 2], 4, kWave);
     const bool u1 = (n & 2) != 0;
-#pragma unroll
-    for (int i = 0; i < 2; ++i) s2[i] = (u1 ? s4[i + 2] : s4[i]) + __shfl_xor(u1 ? s4[i] : s4[i + 2], 2, kWave);
-    const bool u0 = (n & 1) != 0;
-    return (u0 ? s2[1] : s2[0]) + __shfl_xor(u0 ? s2[0] : s2[1], 1, kWave);
+    const double s1 = (u1 ? s2[1] : s2[0]) + __shfl_xor(u1 ? s2[0] : s2[1], 2, kWave);
+    return s1 + __shfl_xor(s1, 1, kWave);
 }
 
-// Half a layer's output gradient (FP32, result layout, blocks 4h .. 4h+3):
-// the BF16 values staged transposed (S, column col) and kept as packed words,
-// the bias column sums into bs[16 (4h + kb) + 4 g + j].
-__device__ __forceinline__ void emit_grad(const f32x4 (&d)[4], int h, int n, int g, uint16_t *S, int col, double *bs,
-                                          uint32_t (&w)[4][2]) {
+// A quarter of a layer's output gradient (FP32, result layout; tiles t, blocks
+// 2w + b): the BF16 values staged transposed (S, columns 16 t + n) and kept as
+// packed words, the bias column sums of each tile into
+// bs[t][16 (2w + b) + 4 g + j].
+__device__ __forceinline__ void emit_grad(const f32x4 (&d)[2][2], int w, int n, int g, uint16_t *S,
+                                          double (*bs)[kBiasCols], int bcol, uint32_t (&wv)[2][2][2]) {
 #pragma unroll
-    for (int kb = 0; kb < 4; ++kb) {
-        w[kb][0] = pack2(d[kb][0], d[kb][1]);
-        w[kb][1] = pack2(d[kb][2], d[kb][3]);
-        stage_t4(S, 16 * (4 * h + kb) + 4 * g, col, w[kb][0], w[kb][1]);
-    }
-    const double cs = colsum16(d, n);   // value n: block n / 4, row n % 4
-    bs[16 * (4 * h + (n >> 2)) + 4 * g + (n & 3)] = cs;
-}
-
-// Half a hidden layer's result (blocks 4h .. 4h+3): Z = acc + b (bv: the bias
-// values of the lane's rows), H = gelu(Z) as BF16 (staged transposed and kept
-// as packed words), gelu'(Z) kept.
-__device__ __forceinline__ void finish_hidden(const f32x4 (&acc)[4], const float4 (&bv)[4], int h, int g, uint16_t *S,
-                                              int col, f32x4 (&gp)[4], uint32_t (&w)[4][2]) {
+    for (int t = 0; t < 2; ++t) {
+        float v[8];
 #pragma unroll
-    for (int mb = 0; mb < 4; ++mb) {
-        float hv[4];
-        const float bj[4] = {bv[mb].x, bv[mb].y, bv[mb].z, bv[mb].w};
+        for (int b = 0; b < 2; ++b) {
+            wv[t][b][0] = pack2(d[t][b][0], d[t][b][1]);
+            wv[t][b][1] = pack2(d[t][b][2], d[t][b][3]);
+            stage_t4(S, 16 * (2 * w + b) + 4 * g, 16 * t + n, wv[t][b][0], wv[t][b][1]);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const float z = acc[mb][j] + bj[j];
-            const float s = sig2u(z);
-            hv[j] = z * s;   // gelu(z)
-            gp[mb][j] = s + 2.f * z * s * (1.f - s) * (kGc * fmaf(3.f * kGa, z * z, 1.f));   // gelu'(z)
+            for (int j = 0; j < 4; ++j) v[4 * b + j] = d[t][b][j];
         }
-        w[mb][0] = pack2(hv[0], hv[1]);
-        w[mb][1] = pack2(hv[2], hv[3]);
-        stage_t4(S, 16 * (4 * h + mb) + 4 * g, col, w[mb][0], w[mb][1]);
+        const double cs = colsum8(v, n);   // value n / 2: block n / 8, row (n / 2) % 4
+        if ((n & 1) == 0) bs[t][bcol + 16 * (2 * w + (n >> 3)) + 4 * g + ((n >> 1) & 3)] = cs;
     }
 }
 
-// The full B operand (four contraction blocks) of a 128-neuron result split
-// over the two waves of a tile: the own blocks 4h .. 4h+3 from their packed
-// words, the partner's read back from its staged rows (S, column col).
-__device__ __forceinline__ void gather_operand(const uint32_t (&w)[4][2], const uint16_t *S, int h, int g, int col,
-                                               bf16x8 (&x)[4]) {
-    uint32_t p[4][2];   // partner's blocks 4(1-h) .. 4(1-h)+3
+// A quarter of a hidden layer's result (tiles t, blocks 2w + b): Z = acc + b
+// (bv: the bias values of the lane's rows), H = gelu(Z) as BF16 (staged
+// transposed and kept as packed words), gelu'(Z) kept.
+__device__ __forceinline__ void finish_hidden(const f32x4 (&acc)[2][2], const float4 (&bv)[2], int w, int n, int g,
+                                              uint16_t *S, f32x4 (&gp)[2][2], uint32_t (&wv)[2][2][2]) {
 #pragma unroll
-    for (int mb = 0; mb < 4; ++mb) unstage_t4(S, 16 * (4 * (1 - h) + mb) + 4 * g, col, p[mb][0], p[mb][1]);
+    for (int t = 0; t < 2; ++t)
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        // block pair (2q, 2q+1) of the own half and of the partner's half
-        const bf16x8 own = as_bf16x8(make_uint4(w[2 * q][0], w[2 * q][1], w[2 * q + 1][0], w[2 * q + 1][1]));
-        const bf16x8 oth = as_bf16x8(make_uint4(p[2 * q][0], p[2 * q][1], p[2 * q + 1][0], p[2 * q + 1][1]));
-        x[q] = h == 0 ? own : oth;
-        x[2 + q] = h == 0 ? oth : own;
-    }
+        for (int b = 0; b < 2; ++b) {
+            float hv[4];
+            const float bj[4] = {bv[b].x, bv[b].y, bv[b].z, bv[b].w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float z = acc[t][b][j] + bj[j];
+                const float s = sig2u(z);
+                hv[j] = z * s;   // gelu(z)
+                gp[t][b][j] = s + 2.f * z * s * (1.f - s) * (kGc * fmaf(3.f * kGa, z * z, 1.f));   // gelu'(z)
+            }
+            wv[t][b][0] = pack2(hv[0], hv[1]);
+            wv[t][b][1] = pack2(hv[2], hv[3]);
+            stage_t4(S, 16 * (2 * w + b) + 4 * g, 16 * t + n, wv[t][b][0], wv[t][b][1]);
+        }
 }
 
-// Half of a 128 x 128 product in the permuted order: f[r][q] = row 16 (4h + r)
-// + n of Mp (a permuted copy, pitch P), contraction block q, one 16-byte load.
-// A layer's fragments are loaded as one batch, ahead of the work before the
-// product, so that their latency overlaps it; the product then runs on
-// registers.
+// The full B operands (four contraction blocks, both tiles) of a 128-neuron
+// result split over the four waves: block q = w from the wave's own packed
+// words, the others read back from their staged rows (S).
+__device__ __forceinline__ void gather_operand(const uint32_t (&wv)[2][2][2], const uint16_t *S, int w, int n, int g,
+                                               bf16x8 (&x)[2][4]) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            uint32_t p[4];
+            if (q == w) {
+                p[0] = wv[t][0][0];
+                p[1] = wv[t][0][1];
+                p[2] = wv[t][1][0];
+                p[3] = wv[t][1][1];
+            } else {
+                unstage_t4(S, 16 * (2 * q) + 4 * g, 16 * t + n, p[0], p[1]);
+                unstage_t4(S, 16 * (2 * q + 1) + 4 * g, 16 * t + n, p[2], p[3]);
+            }
+            x[t][q] = as_bf16x8(make_uint4(p[0], p[1], p[2], p[3]));
+        }
+}
+
+// A quarter of a 128 x 128 product in the permuted order: f[b][q] = row
+// 16 (2w + b) + n of Mp (a permuted copy, pitch P), contraction block q, one
+// 16-byte load.  A layer's fragments are loaded as one batch, ahead of the
+// work before the product, so that their latency overlaps it; the product
+// then runs on registers, each fragment feeding both tiles.
 template <int P>
-__device__ __forceinline__ void load_frags(const uint16_t *__restrict__ Mp, int h, int n, int g, bf16x8 (&f)[4][4]) {
+__device__ __forceinline__ void load_frags(const uint16_t *__restrict__ Mp, int w, int n, int g, bf16x8 (&f)[2][4]) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int b = 0; b < 2; ++b)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) f[r][q] = load8(Mp + (16 * (4 * h + r) + n) * P + 32 * q + 8 * g);
+        for (int q = 0; q < 4; ++q) f[b][q] = load8(Mp + (16 * (2 * w + b) + n) * P + 32 * q + 8 * g);
 }
-// The bias values of a hidden layer for the lane's rows of blocks 4h .. 4h+3.
-__device__ __forceinline__ void load_bias(const float *__restrict__ bias, int h, int g, float4 (&bv)[4]) {
+// The bias values of a hidden layer for the lane's rows of blocks 2w, 2w + 1.
+__device__ __forceinline__ void load_bias(const float *__restrict__ bias, int w, int g, float4 (&bv)[2]) {
 #pragma unroll
-    for (int mb = 0; mb < 4; ++mb) bv[mb] = *reinterpret_cast<const float4 *>(bias + 16 * (4 * h + mb) + 4 * g);
+    for (int b = 0; b < 2; ++b) bv[b] = *reinterpret_cast<const float4 *>(bias + 16 * (2 * w + b) + 4 * g);
 }
-__device__ __forceinline__ void product(const bf16x8 (&f)[4][4], const bf16x8 (&x)[4], f32x4 (&acc)[4]) {
+__device__ __forceinline__ void product(const bf16x8 (&f)[2][4], const bf16x8 (&x)[2][4], f32x4 (&acc)[2][2]) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        acc[r] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < 2; ++t)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[r] = mma(f[r][q], x[q], acc[r]);
-    }
+        for (int b = 0; b < 2; ++b) {
+            acc[t][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[t][b] = mma(f[b][q], x[t][q], acc[t][b]);
+        }
 }
 // Keeps the loads above it from sinking towards their first use.
 __device__ __forceinline__ void issue_fence() { __builtin_amdgcn_sched_barrier(0); }
@@ -392,168 +410,177 @@ __global__ __launch_bounds__(kTrainThreads) __attribute__((amdgpu_waves_per_eu(2
     for (int i = threadIdx.x; i < 2 * kK1; i += kTrainThreads) norm[i] = a.mean_inv[i];
     __syncthreads();
     constexpr int64_t kOffB0 = off_b(0), kOffB1 = off_b(1), kOffB2 = off_b(2), kOffB3 = off_b(3);
-    const int lane = lane_id(), n = lane & 15, g = lane >> 4, w = threadIdx.x >> 6, tw = w >> 1, h = w & 1;
-    const int64_t B = a.B;
-    const int64_t tile = (int64_t)blockIdx.x * kTrainTiles + tw;
-    const bool active = tile * 16 < B;   // the same for both waves of a tile
-    const int col = 16 * tw + n;         // staged column of this lane's row
-    double *bs = bsum[tw];
+    const int lane = lane_id(), n = lane & 15, g = lane >> 4, w = threadIdx.x >> 6;
+    const int64_t tile0 = (int64_t)blockIdx.x * kTrainTiles;
     uint16_t *sh = stage + kStageHt * kStagePitch, *sd = stage + kStageDz * kStagePitch;
-    f32x4 acc[4], gp[3][4];
-    uint32_t wv[4][2];
-    bf16x8 x[4], f[4][4];
-    float4 bv[4];
-    float t[4] = {0.f, 0.f, 0.f, 0.f};
-    if (active) {
-        const int64_t b = tile * 16 + n;
-        int64_t row = a.idx ? (int64_t)a.idx[b] : b;
-        if (row < 0 || row >= a.nrows) row = 0;   // documented: indices must be in range; keeps loads in bounds
-        const float *fr = a.feat + row * kFeat;
-        if (g == 0)
+    f32x4 acc[2][2], gp[3][2][2];
+    uint32_t wv[2][2][2];
+    bf16x8 x[2][4], f[2][4];
+    float4 bv[2];
+
+    // the rows of both tiles; this wave's share of the layer-1 input, feature
+    // blocks kb = 2w, 2w + 1 (< 7), standardised and staged; the layer-1
+    // weight fragments of its neuron blocks
+    float t[2][4];
+    {
+        float fv[2][2][8];
 #pragma unroll
-            for (int j = 0; j < 3; ++j) t[j] = a.resid[row * 3 + j] * a.is[j];
-        // layer 1 from the standardised features, natural slot order (k = 32 kb + 8 g + i)
-        float fv[7][8];
+        for (int tt = 0; tt < 2; ++tt) {
+            const int64_t b = (tile0 + tt) * 16 + n;
+            int64_t row = a.idx ? (int64_t)a.idx[b] : b;
+            if (row < 0 || row >= a.nrows) row = 0;   // documented: indices must be in range; keeps loads in bounds
+            const float *fr = a.feat + row * kFeat;
 #pragma unroll
-        for (int kb = 0; kb < 7; ++kb)
+            for (int j = 0; j < 4; ++j) t[tt][j] = (g == 0 && j < kOut) ? a.resid[row * 3 + j] * a.is[j] : 0.f;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int k = 32 * kb + 8 * g + i;
-                fv[kb][i] = k < kFeat ? fr[k] : 0.f;
-            }
-        bf16x8 f1[4][7];
+            for (int kk = 0; kk < 2; ++kk)
 #pragma unroll
-        for (int mb = 0; mb < 4; ++mb)
+                for (int i = 0; i < 8; ++i) {
+                    const int k = 32 * (2 * w + kk) + 8 * g + i;
+                    fv[tt][kk][i] = k < kFeat ? fr[k] : 0.f;
+                }
+        }
+        bf16x8 f1[2][7];
 #pragma unroll
-            for (int kb = 0; kb < 7; ++kb)
-                f1[mb][kb] = load8(a.wt0 + (16 * (4 * h + mb) + n) * kK1 + 32 * kb + 8 * g);
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int kb = 0; kb < 7; ++kb) f1[b][kb] = load8(a.wt0 + (16 * (2 * w + b) + n) * kK1 + 32 * kb + 8 * g);
         issue_fence();
-        bf16x8 xb[7];
 #pragma unroll
-        for (int kb = 0; kb < 7; ++kb) {
-            float v[8];
+        for (int tt = 0; tt < 2; ++tt)
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int k = 32 * kb + 8 * g + i;
-                v[i] = k < kFeat ? (fv[kb][i] - norm[k]) * norm[kK1 + k] : 0.f;
+            for (int kk = 0; kk < 2; ++kk) {
+                const int kb = 2 * w + kk;
+                if (kb < 7) {
+                    float v[8];
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) {
+                        const int k = 32 * kb + 8 * g + i;
+                        v[i] = k < kFeat ? (fv[tt][kk][i] - norm[k]) * norm[kK1 + k] : 0.f;
+                    }
+                    stage_t4(stage, 32 * kb + 8 * g, 16 * tt + n, pack2(v[0], v[1]), pack2(v[2], v[3]));
+                    stage_t4(stage, 32 * kb + 8 * g + 4, 16 * tt + n, pack2(v[4], v[5]), pack2(v[6], v[7]));
+                }
             }
-            const uint4 u = make_uint4(pack2(v[0], v[1]), pack2(v[2], v[3]), pack2(v[4], v[5]), pack2(v[6], v[7]));
-            xb[kb] = as_bf16x8(u);
-            if ((kb < 4) == (h == 0)) {   // the input rows are staged by halves
-                stage_t4(stage, 32 * kb + 8 * g, col, u.x, u.y);
-                stage_t4(stage, 32 * kb + 8 * g + 4, col, u.z, u.w);
+        __syncthreads();   // the layer-1 input staged
+#pragma unroll
+        for (int tt = 0; tt < 2; ++tt) {
+            bf16x8 xb[7];
+#pragma unroll
+            for (int kb = 0; kb < 7; ++kb) {
+                uint32_t p[4];
+                unstage_t4(stage, 32 * kb + 8 * g, 16 * tt + n, p[0], p[1]);
+                unstage_t4(stage, 32 * kb + 8 * g + 4, 16 * tt + n, p[2], p[3]);
+                xb[kb] = as_bf16x8(make_uint4(p[0], p[1], p[2], p[3]));
+            }
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                acc[tt][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int kb = 0; kb < 7; ++kb) acc[tt][b] = mma(f1[b][kb], xb[kb], acc[tt][b]);
             }
         }
-#pragma unroll
-        for (int mb = 0; mb < 4; ++mb) {
-            acc[mb] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int kb = 0; kb < 7; ++kb) acc[mb] = mma(f1[mb][kb], xb[kb], acc[mb]);
-        }
-        load_frags<kHid>(a.wtp[1], h, n, g, f);
-        load_bias(a.params + kOffB0, h, g, bv);
-        issue_fence();
-        finish_hidden(acc, bv, h, g, sh, col, gp[0], wv);
     }
-    __syncthreads();   // layer 1 staged by both halves
-    if (active) {
-        gather_operand(wv, sh, h, g, col, x);
-        product(f, x, acc);
-        load_frags<kHid>(a.wtp[2], h, n, g, f);
-        load_bias(a.params + kOffB1, h, g, bv);
-        issue_fence();
-        finish_hidden(acc, bv, h, g, sh + kHid * kStagePitch, col, gp[1], wv);
-    }
+    load_frags<kHid>(a.wtp[1], w, n, g, f);
+    load_bias(a.params + kOffB0, w, g, bv);
+    issue_fence();
+    finish_hidden(acc, bv, w, n, g, sh, gp[0], wv);
+    __syncthreads();   // layer 1 staged
+    gather_operand(wv, sh, w, n, g, x);
+    product(f, x, acc);
+    load_frags<kHid>(a.wtp[2], w, n, g, f);
+    load_bias(a.params + kOffB1, w, g, bv);
+    issue_fence();
+    finish_hidden(acc, bv, w, n, g, sh + kHid * kStagePitch, gp[1], wv);
     __syncthreads();   // layer 2 staged
-    bf16x8 f4[4];
+    gather_operand(wv, sh + kHid * kStagePitch, w, n, g, x);
+    product(f, x, acc);
+    bf16x8 fo[4], f4[2];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) fo[q] = load8(a.wtp[3] + n * kHid + 32 * q + 8 * g);
+#pragma unroll
+    for (int b = 0; b < 2; ++b) f4[b] = load8(a.wnp[3] + (16 * (2 * w + b) + n) * 32 + 8 * g);
+    load_bias(a.params + kOffB2, w, g, bv);
     float yb[4] = {0.f, 0.f, 0.f, 0.f};   // output bias of the lane's rows m = 4 g + j
-    if (active) {
-        gather_operand(wv, sh + kHid * kStagePitch, h, g, col, x);
-        product(f, x, acc);
-        bf16x8 fo[4];
+    if (g == 0)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) fo[q] = load8(a.wtp[3] + n * kHid + 32 * q + 8 * g);
-#pragma unroll
-        for (int kb = 0; kb < 4; ++kb) f4[kb] = load8(a.wnp[3] + (16 * (4 * h + kb) + n) * 32 + 8 * g);
-        load_bias(a.params + kOffB2, h, g, bv);
-        if (g == 0)
-#pragma unroll
-            for (int j = 0; j < kOut; ++j) yb[j] = a.params[kOffB3 + j];
-        issue_fence();
-        finish_hidden(acc, bv, h, g, sh + 2 * kHid * kStagePitch, col, gp[2], wv);
-        f[0][0] = fo[0];
-        f[0][1] = fo[1];
-        f[0][2] = fo[2];
-        f[0][3] = fo[3];
-    }
+        for (int j = 0; j < kOut; ++j) yb[j] = a.params[kOffB3 + j];
+    issue_fence();
+    finish_hidden(acc, bv, w, n, g, sh + 2 * kHid * kStagePitch, gp[2], wv);
     __syncthreads();   // layer 3 staged
-    double lp = 0.0;
-    if (active) {
-        gather_operand(wv, sh + 2 * kHid * kStagePitch, h, g, col, x);
-        // output layer (rows m = 4 g + j, three of them real) in both waves;
-        // the loss, dY's staged rows and its bias sums from wave 0
+    gather_operand(wv, sh + 2 * kHid * kStagePitch, w, n, g, x);
+
+    // output layer (rows m = 4 g + j, three of them real) in every wave; the
+    // loss, dY's staged rows and its bias sums from wave 0
+    double lp[2];
+    bf16x8 dy[2];
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt) {
         f32x4 y = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int q = 0; q < 4; ++q) y = mma(f[0][q], x[q], y);
+        for (int q = 0; q < 4; ++q) y = mma(fo[q], x[tt][q], y);
         float d[4];
+        lp[tt] = 0.0;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int m = 4 * g + j;
-            const float dd = m < kOut ? (y[j] + yb[j]) - t[j] : 0.f;
-            lp += 0.5 * (double)dd * (double)dd;
+            const float dd = m < kOut ? (y[j] + yb[j]) - t[tt][j] : 0.f;
+            lp[tt] += 0.5 * (double)dd * (double)dd;
             d[j] = dd * a.inv_b;
         }
         const uint32_t w0 = pack2(d[0], d[1]), w1 = pack2(d[2], d[3]);
-        const bf16x8 dy = as_bf16x8(make_uint4(w0, w1, 0u, 0u));
-        if (h == 0) {
-            stage_t4(sd + 3 * kHid * kStagePitch, 4 * g, col, w0, w1);
+        dy[tt] = as_bf16x8(make_uint4(w0, w1, 0u, 0u));
+        if (w == 0) {
+            stage_t4(sd + 3 * kHid * kStagePitch, 4 * g, 16 * tt + n, w0, w1);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const double s = sum16((double)d[j]);
-                if (n == 0) bs[3 * kHid + 4 * g + j] = s;
+                if (n == 0) bsum[tt][3 * kHid + 4 * g + j] = s;
             }
         }
-        // backward: dZ_l = (dZ_{l+1} W_{l+1}^T) .* gelu'(Z_l), l = 3, 2, 1
+    }
+    // backward: dZ_l = (dZ_{l+1} W_{l+1}^T) .* gelu'(Z_l), l = 3, 2, 1
 #pragma unroll
-        for (int kb = 0; kb < 4; ++kb) {
-            acc[kb] = mma(f4[kb], dy, f32x4{0.f, 0.f, 0.f, 0.f});
-            acc[kb] *= gp[2][kb];
+    for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            acc[tt][b] = mma(f4[b], dy[tt], f32x4{0.f, 0.f, 0.f, 0.f});
+            acc[tt][b] *= gp[2][tt][b];
         }
-        load_frags<kHid>(a.wnp[2], h, n, g, f);
-        issue_fence();
-        emit_grad(acc, h, n, g, sd + 2 * kHid * kStagePitch, col, bs + 2 * kHid, wv);
-    }
+    load_frags<kHid>(a.wnp[2], w, n, g, f);
+    issue_fence();
+    emit_grad(acc, w, n, g, sd + 2 * kHid * kStagePitch, bsum, 2 * kHid, wv);
     __syncthreads();   // dZ3 staged
-    if (active) {
-        gather_operand(wv, sd + 2 * kHid * kStagePitch, h, g, col, x);
-        product(f, x, acc);
+    gather_operand(wv, sd + 2 * kHid * kStagePitch, w, n, g, x);
+    product(f, x, acc);
 #pragma unroll
-        for (int kb = 0; kb < 4; ++kb) acc[kb] *= gp[1][kb];
-        load_frags<kHid>(a.wnp[1], h, n, g, f);
-        issue_fence();
-        emit_grad(acc, h, n, g, sd + kHid * kStagePitch, col, bs + kHid, wv);
-    }
+    for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[tt][b] *= gp[1][tt][b];
+    load_frags<kHid>(a.wnp[1], w, n, g, f);
+    issue_fence();
+    emit_grad(acc, w, n, g, sd + kHid * kStagePitch, bsum, kHid, wv);
     __syncthreads();   // dZ2 staged
-    if (active) {
-        gather_operand(wv, sd + kHid * kStagePitch, h, g, col, x);
-        product(f, x, acc);
+    gather_operand(wv, sd + kHid * kStagePitch, w, n, g, x);
+    product(f, x, acc);
 #pragma unroll
-        for (int kb = 0; kb < 4; ++kb) acc[kb] *= gp[0][kb];
-        emit_grad(acc, h, n, g, sd, col, bs, wv);
-    } else {
-        for (int c = h * kWave + lane; c < kBiasCols; c += 2 * kWave) bs[c] = 0.0;
+    for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[tt][b] *= gp[0][tt][b];
+    emit_grad(acc, w, n, g, sd, bsum, 0, wv);
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt) {
+        const double l = wave_sum(lp[tt]);
+        if (lane == 0 && w == 0) a.loss_part[tile0 + tt] = l * (double)a.inv_b;
     }
-    lp = wave_sum(lp);
-    if (lane == 0 && h == 0 && active) a.loss_part[tile] = lp * (double)a.inv_b;
     __syncthreads();   // the group is staged
     for (int c = threadIdx.x; c < kBiasCols; c += kTrainThreads) {
-        const double s = bsum[0][c] + bsum[1][c];
+        const double sb = bsum[0][c] + bsum[1][c];
         const int l = c < 3 * kHid ? c / kHid : 3, m = c - l * kHid, MP = mpad(l);
-        a.part_b[l][(int64_t)blockIdx.x * MP + m] = s;
+        a.part_b[l][(int64_t)blockIdx.x * MP + m] = sb;
     }
     // the staged block out: kTrRows rows of 32 batch rows, 8 threads per row
-    // with 4 batch rows (8 bytes) each; B is a multiple of 32, so a present
-    // group is whole
+    // with 4 batch rows (8 bytes) each
     uint16_t *dst = a.tr + (int64_t)blockIdx.x * kStageRows * kTrBlock;
     constexpr int kChunks = kStageRows * kTrBlock / 4, kU = 8;
     constexpr int kIter = (kChunks + kTrainThreads - 1) / kTrainThreads;
@@ -1291,6 +1318,7 @@ hipError_t launch_gradients(const NetBufs &net, const TrainBufs &tb, const float
     }
     a.tr = tb.tr;
     a.loss_part = tb.loss_part;
+    if (B <= 0 || B % kTrainGroupRows != 0) return hipErrorInvalidValue;   // every workgroup has both tiles
     const unsigned nt = (unsigned)n_train_groups(B);
     hipLaunchKernelGGL(k_train_tile, dim3(nt), dim3(kTrainThreads), 0, st, a);
     const unsigned nc = (unsigned)n_chunks(B);
