@@ -39,7 +39,10 @@
  * pointers are host memory.  The handle owns its parameters, Adam moments and
  * batch buffers (sized by max_batch), allocated by couple_mlp_init().
  * Streams and errors follow couple.h: enqueue on the given stream, return a
- * couple_status, detect argument errors before any launch.
+ * couple_status, detect argument errors before any launch.  Forward, gradient
+ * and training calls on one handle share its batch buffers: such calls that
+ * overlap (different streams or threads) race; calls in order on one stream
+ * do not.
  */
 #ifndef COUPLE_MLP_H
 #define COUPLE_MLP_H
