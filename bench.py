@@ -25,6 +25,9 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E, vendor figure
 MFMA_BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix-core peak, vendor figure
 MLP_FLOP_PER_PARTICLE = 2 * (193 * 128 + 128 * 128 + 128 * 128 + 128 * 3)   # 115,712: one forward pass
+# a training row: the forward pass, the input gradients of layers 2-4 and the
+# weight gradients of all four (297,728)
+TRAIN_FLOP_PER_ROW = MLP_FLOP_PER_PARTICLE + 2 * (128 * 128 + 128 * 128 + 128 * 3) + MLP_FLOP_PER_PARTICLE
 METRIC = "coupling particle-steps/s, plain vs MLP path at 1e-3 rel err; % HBM peak"
 
 
@@ -360,6 +363,10 @@ def mlp_leg(args, w, cfg, pos, vel, diam, fine, plain_ms, plain_kernels, dev):
                      "traffic": profiled_traffic("mlp_infer"), "flop_per_launch": flop, "avg_ms": round(t_inf, 4)},
         "kernels_avg_ms": {k: round(v["avg_ms"], 4) for k, v in kern.items()},
         "train": {"steps": args.mlp_steps, "batch": 65536, "seconds": round(t_train, 1),
+                  "ms_per_step": round(t_train / max(args.mlp_steps, 1) * 1e3, 4),
+                  "tflops": round(TRAIN_FLOP_PER_ROW * 65536 * args.mlp_steps / max(t_train, 1e-9) / 1e12, 1),
+                  "frac_bf16_peak": round(TRAIN_FLOP_PER_ROW * 65536 * args.mlp_steps / max(t_train, 1e-9) / 1e12
+                                          / MFMA_BF16_PEAK_TFLOPS, 4),
                   "pairs_seconds": round(t_pairs, 1), "loss_first_last": [hist[0][1], hist[-1][1]],
                   "pairs": "20,000 per step x 100 advected steps of cube64_cic + 2,000,000 of this workload's "
                            "first step"},
