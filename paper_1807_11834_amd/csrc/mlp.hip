@@ -78,17 +78,19 @@ __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 // ---------------------------------------------------------------------------
 // Flat parameter index -> (layer, is_weight, k, m).
 __device__ __forceinline__ void decode_param(int64_t i, int &l, bool &w, int &k, int &m) {
-    l = 0;
-    while (l < 3 && i >= off_w(l + 1)) ++l;
-    const int64_t r = i - off_w(l);
-    const int64_t nw = (int64_t)fan_in(l) * fan_out(l);
-    w = r < nw;
+    constexpr int64_t kW1 = off_w(1), kW2 = off_w(2), kW3 = off_w(3);
+    constexpr int64_t kB0 = off_b(0), kB1 = off_b(1), kB2 = off_b(2), kB3 = off_b(3);
+    l = i < kW1 ? 0 : (i < kW2 ? 1 : (i < kW3 ? 2 : 3));
+    const int64_t w0 = l == 0 ? 0 : (l == 1 ? kW1 : (l == 2 ? kW2 : kW3));
+    const int64_t b0 = l == 0 ? kB0 : (l == 1 ? kB1 : (l == 2 ? kB2 : kB3));
+    const int fo = l == 3 ? kOut : kHid;
+    w = i < b0;
     if (w) {
-        k = (int)(r / fan_out(l));
-        m = (int)(r % fan_out(l));
+        k = (int)((i - w0) / fo);
+        m = (int)((i - w0) % fo);
     } else {
         k = 0;
-        m = (int)(r - nw);
+        m = (int)(i - b0);
     }
 }
 
@@ -1055,7 +1057,9 @@ __global__ __launch_bounds__(kInfWaves * kWave) void k_infer(StepArgs<float> a) 
     }
     for (int e = threadIdx.x; e < 3 * kHid + 16; e += kInfWaves * kWave) {
         const int l = e / kHid, m = e % kHid;
-        L.bias[e] = (l < 3) ? net.params[off_b(l) + m] : (m < kOut ? net.params[off_b(3) + m] : 0.f);
+        constexpr int64_t kB0 = off_b(0), kB1 = off_b(1), kB2 = off_b(2), kB3 = off_b(3);
+        const int64_t ob = l == 0 ? kB0 : (l == 1 ? kB1 : kB2);
+        L.bias[e] = (l < 3) ? net.params[ob + m] : (m < kOut ? net.params[kB3 + m] : 0.f);
     }
     for (int e = threadIdx.x; e < kK1; e += kInfWaves * kWave) {
         L.mean[e] = net.mean_inv[e];
