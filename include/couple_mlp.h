@@ -105,7 +105,8 @@ int couple_mlp_forward(couple_mlp *m, const float *feat, int64_t n, float *y, vo
 
 /* Loss and gradient of one batch: rows idx[0..B) (device int32, each in
  * [0, nrows); NULL = rows 0..B-1) of feat [nrows][193] and resid [nrows][3]
- * (device).  B is a multiple of 32, 32 <= B <= max_batch.  grads
+ * (device).  An index outside [0, nrows) is not detected (the indices stay on
+ * the device); the kernels read row 0 for it, so every access stays in bounds.  B is a multiple of 32, 32 <= B <= max_batch.  grads
  * [COUPLE_MLP_NPARAM] and loss [1] are device FP32 outputs (loss may be NULL).
  * The parameters are not changed. */
 int couple_mlp_grads(couple_mlp *m, const float *feat, const float *resid, int64_t nrows, const int32_t *idx,

@@ -219,6 +219,32 @@ def test_gradients_at_edge_batch_sizes(env, B, use_idx):
     m.close()
 
 
+def test_gradients_with_out_of_range_indices_read_row_zero(env):
+    """Batch indices outside [0, nrows) read row 0 (the documented guard that
+    keeps every load in bounds): the gradients equal those of the same batch
+    with such indices replaced by 0, bit for bit."""
+    torch, cpl, oracle = env
+    case = _small_case(torch, cpl)
+    feat, ub, res = _features(torch, cpl, case)
+    X = feat.cpu().numpy().astype(np.float64)
+    R = res.cpu().numpy().astype(np.float64)
+    m = _net(torch, cpl, _params(6), *M.norm_stats(X), M.target_scale(R))
+    B = 96
+    idx = np.random.default_rng(7).choice(X.shape[0], B, replace=False).astype(np.int32)
+    bad = idx.copy()
+    bad[[3, 40, 95]] = [-1, X.shape[0], 2 ** 31 - 1]
+    fixed = bad.copy()
+    fixed[(fixed < 0) | (fixed >= X.shape[0])] = 0
+    out = []
+    for ix in (bad, fixed):
+        g = torch.empty(M.NPARAM, dtype=torch.float32, device="cuda:0")
+        m.grads(feat, res, B, g, idx=torch.from_numpy(ix).cuda())
+        torch.cuda.synchronize()
+        out.append(g.cpu().numpy())
+    np.testing.assert_array_equal(out[0], out[1])
+    m.close()
+
+
 def test_adam_matches_oracle(env):
     torch, cpl, oracle = env
     params = _params(3)
