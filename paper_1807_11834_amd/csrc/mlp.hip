@@ -1185,18 +1185,31 @@ __global__ __launch_bounds__(kBlock) void k_check(StepArgs<float> a) {
             return row0[wave][lo] + (j - pre[wave][lo]);
         };
         const int64_t period = a.mlp_period, phase = ((a.step % period) + period) % period;
-        for (int32_t j = lane; j < total; j += kWave) {
-            const int64_t s = position(j);
-            int64_t p = a.perm[s];
-            if (p < 0 || p >= a.n) p = 0;
-            if (p % period != phase) continue;
-            float ux, uy, uz;
-            fine_velocity(a.sp[s], a, ux, uy, uz);
-            const float4 m = a.uf4[p];
-            const double ex = (double)m.x - ux, ey = (double)m.y - uy, ez = (double)m.z - uz;
-            err += ex * ex + ey * ey + ez * ez;
-            ref += (double)ux * ux + (double)uy * uy + (double)uz * uz;
-            ns += 1.0;
+        // kU particles of a lane per round: their ids are loaded together (one
+        // round trip instead of kU), then taken in the lane's order j
+        constexpr int kU = 4;
+        for (int32_t j0 = lane; j0 < total; j0 += kU * kWave) {
+            int64_t s[kU], p[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int32_t j = j0 + u * kWave;
+                s[u] = position(j < total ? j : j0);
+                p[u] = a.perm[s[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                if (j0 + u * kWave >= total) break;
+                int64_t pu = p[u];
+                if (pu < 0 || pu >= a.n) pu = 0;
+                if (pu % period != phase) continue;
+                float ux, uy, uz;
+                fine_velocity(a.sp[s[u]], a, ux, uy, uz);
+                const float4 m = a.uf4[pu];
+                const double ex = (double)m.x - ux, ey = (double)m.y - uy, ez = (double)m.z - uz;
+                err += ex * ex + ey * ey + ez * ez;
+                ref += (double)ux * ux + (double)uy * uy + (double)uz * uz;
+                ns += 1.0;
+            }
         }
         const double terr = wave_sum(err), tref = wave_sum(ref), tns = wave_sum(ns);
         const double tol = (double)a.mlp_tol;
